@@ -1,0 +1,195 @@
+/*
+ * h2sp — non-extensive sparsification A = U S V^T of an H^2 matrix on MI355X.
+ *
+ * C ABI of the library libh2sp.so.  Every function is extern "C", never throws
+ * and returns an int status (H2_OK = 0, negative on failure); the message of the
+ * last failure on the calling thread is h2_last_error().  Handles own all their
+ * memory (host and device) and release it in h2_*_destroy; callers own every
+ * buffer they pass in.  All device work is ordered on the stream given to
+ * h2_set_stream (default: the null stream of the current HIP device).
+ *
+ * Method (Sushnikova & Oseledets, "Simple non-extensive sparsification of the
+ * hierarchical matrices"):
+ *   - the H^2 matrix is Definition 4.8: close part + sum over the interaction
+ *     lists of R_t D_ts E_s^T with nested cluster bases (Section 4.1);
+ *   - Section 2 (eqs. usv, fin, main_fact) and Section 4 (4.2, 4.3) turn it into
+ *     A = U S V^T, S sparse of the same size, U and V orthogonal products of
+ *     block-diagonal and permutation matrices;
+ *   - A x = b is solved as S y = U^T b, x = V y (eq. sp0).
+ * The kernel is symmetric and rows and columns share one cluster tree, so
+ * U = V (Proposition 2.1) and S is stored as its upper block triangle.
+ */
+#ifndef H2SP_H
+#define H2SP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+enum {
+  H2_OK = 0,
+  H2_EINVAL = -1,       /* bad argument (sizes, NaN or duplicate points, ...)        */
+  H2_ENOMEM = -2,       /* host or device allocation failed                         */
+  H2_EDEVICE = -3,      /* a HIP call failed                                        */
+  H2_ESINGULAR = -4,    /* a pivot block of S is numerically singular               */
+  H2_ENOCONV = -5,      /* refinement stopped above the tolerance (x still written) */
+  H2_EUNSUPPORTED = -6  /* option outside what this build supports                  */
+};
+
+/* ---- options --------------------------------------------------------------- */
+enum { H2_KERNEL_INVDIST = 0 }; /* A_ij = scale / |x_i - x_j| (i != j), A_ii = diag */
+enum { H2_FP64 = 0,             /* every step in FP64                                */
+       H2_MIXED = 1 };          /* transforms, S and its factor in FP32 (MFMA), basis
+                                   QR, pivot-block inversion and residuals in FP64   */
+
+typedef struct {
+  int kind;      /* H2_KERNEL_INVDIST                                           */
+  double scale;  /* c in c / |x - y|                                            */
+  double diag;   /* value of A_ii                                               */
+} h2_kernel;
+
+typedef struct {
+  int leaf;              /* max points per leaf cluster, 2..128                 */
+  int cheb;              /* Chebyshev nodes per axis, 2..4 (p^dim <= 64)         */
+  double recompress_tol; /* 0: keep the Chebyshev bases; else relative SVD cut   */
+  int rank_cap;          /* upper bound of the recompressed ranks (<= p^dim)     */
+  double eta;            /* admissibility: dist >= eta * max diam; 0 = weak      */
+} h2_build_opts;
+
+typedef struct {
+  int precision;         /* H2_FP64 or H2_MIXED                                  */
+} h2_sparsify_opts;
+
+typedef struct {
+  double tol;            /* stop when max_col ||b - A x||_2 / ||b||_2 <= tol     */
+  int max_iter;          /* refinement steps (>= 1)                              */
+} h2_solve_opts;
+
+typedef struct {
+  int iters;                   /* refinement steps taken                         */
+  double max_rel_residual;     /* final max_col ||b - A_H2 x|| / ||b||            */
+  double seconds[3];           /* U^T / S-solve / V sweeps, matvec: not filled    */
+} h2_solve_info;
+
+typedef struct h2_matrix h2_matrix;   /* tree, block tree, H^2 coefficients       */
+typedef struct h2_sparse h2_sparse;   /* Q_t of every cluster, S, plan            */
+typedef struct h2_factor h2_factor;   /* block ILU(0) of S                         */
+
+/* ---- library state --------------------------------------------------------- */
+const char* h2_last_error(void);
+/* All later device work of this thread goes to `stream` (a hipStream_t). */
+int h2_set_stream(void* stream);
+
+/* ---- construction of the H^2 matrix (Section 4.1: the input of the method) -- */
+/*
+ * h2_build: points `pts` (HOST, row-major n x dim, dim 2 or 3, finite, pairwise
+ * distinct) -> kd cluster tree (longest axis of the tight box, median split,
+ * equal-depth leaves), block cluster tree (Definitions 4.2-4.4), tensor
+ * Chebyshev bases, transfers and couplings, optionally recompressed.  Host
+ * work only; the coefficients go to the current device on first device use
+ * (h2_matvec, h2_sparsify).  EINVAL on bad
+ * sizes, NaN / infinite or duplicate points; ENOMEM / EDEVICE on allocation.
+ */
+int h2_build(const double* pts, int64_t n, int dim, const h2_kernel* kernel,
+             const h2_build_opts* opts, h2_matrix** out);
+
+/*
+ * h2_import: same tree and block tree as h2_build (derived from the points),
+ * but the cluster-basis coefficients come from the caller (HOST arrays):
+ *   rank[ncl]            r_t per cluster in heap order (0 for clusters without
+ *                        a basis, i.e. without farfield of their own or of an
+ *                        ancestor; must match that set exactly)
+ *   nodes[ncl * P * dim] Chebyshev nodes of each cluster (rows of P x dim,
+ *                        row-major); read only for clusters with r_t > 0
+ *   proj                 concatenation over clusters with r_t > 0 (heap order)
+ *                        of P_t, r_t x P column-major: coupling D_ts =
+ *                        P_t K(nodes_t, nodes_s) P_s^T
+ *   leaf_basis           concatenation over leaves with r_t > 0 of R_t,
+ *                        |t| x r_t column-major, rows in tree order
+ *   transfer             concatenation over non-root clusters c whose father
+ *                        has r > 0 (heap order) of T_c, r_c x r_father
+ *                        column-major
+ * P = cheb^dim.  The opts fields recompress_tol and rank_cap are ignored.
+ */
+int h2_import(const double* pts, int64_t n, int dim, const h2_kernel* kernel,
+              const h2_build_opts* opts, const int32_t* rank, const double* nodes,
+              const double* proj, const double* leaf_basis, const double* transfer,
+              h2_matrix** out);
+
+/* Sizes of the tree: depth L (leaves on level 0), cluster count 2^(L+1)-1. */
+int h2_matrix_info(const h2_matrix* h, int* depth, int64_t* ncl, int* cheb_points);
+/* HOST copies: perm[n] (tree position -> original index), rank[ncl]. */
+int h2_matrix_export_tree(const h2_matrix* h, int64_t* perm, int32_t* rank);
+
+/*
+ * h2_matvec: y = A_H2 x in FP64 on the device (close part evaluated on the
+ * fly from the points, far part by the nested bases).  x, y: DEVICE pointers,
+ * column-major n x nrhs with leading dimension ld >= n, ORIGINAL point order.
+ */
+int h2_matvec(const h2_matrix* h, const double* x, double* y, int64_t nrhs, int64_t ld);
+
+/* ---- sparsification (Section 2, Algorithm 1 as realised in Section 4) ------- */
+/*
+ * h2_sparsify: level sweep from the leaves to the root: batched Householder QR
+ * completing every cluster basis to a square orthogonal Q_t (FP64), two-sided
+ * transforms of the close blocks, couplings moved into the father's close
+ * block, strips of finalised rows, S assembled as a block-sparse matrix of the
+ * size of A.  The handle keeps a reference to `h` (do not destroy h first).
+ */
+int h2_sparsify(h2_matrix* h, const h2_sparsify_opts* opts, h2_sparse** out);
+
+/* Sizes: blocks of the upper block triangle of S, its scalar entries. */
+int h2_sparse_info(const h2_sparse* sp, int64_t* nnz_blocks, int64_t* nnz_entries);
+/*
+ * HOST copies of the combinatorial output (bit-exact contract):
+ *   n_act, kept, nonbasis [ncl]: n_t, k_t, m_t;  soff[ncl]: first row of
+ *   cluster t in S;  rowptr[ncl+1], colidx[nnz_blocks]: upper block pattern,
+ *   block rows = clusters in S order (level 0 first, left to right), column
+ *   indices are cluster ids sorted by S order.
+ */
+int h2_sparse_export_plan(const h2_sparse* sp, int64_t* n_act, int64_t* kept,
+                          int64_t* nonbasis, int64_t* soff, int64_t* rowptr,
+                          int64_t* colidx);
+/* HOST copy of block (t, s) of S (m_t x m_s column-major, FP64), t <= s in S order. */
+int h2_sparse_export_block(const h2_sparse* sp, int64_t t, int64_t s, double* out);
+/* HOST copy of Q_t (n_t x n_t column-major, FP64). */
+int h2_sparse_export_q(const h2_sparse* sp, int64_t t, double* out);
+
+/* ---- factorisation of S (the sparse-solver step of Sections 5.3-5.5) -------- */
+/*
+ * h2_factor_S: block ILU(0) of S on its own pattern in S order, symmetric form
+ * S ~ L D L^T with L^T_kj = D_k^{-1} S_kj; pivot blocks D_k inverted in FP64 by
+ * Gauss-Jordan with partial pivoting.  Right-looking, one launch per level of
+ * the elimination DAG.  ESINGULAR if a pivot block is singular.
+ * The handle keeps a reference to `sp`.
+ */
+int h2_factor_S(h2_sparse* sp, h2_factor** out);
+
+/*
+ * h2_solve: x = A_H2^{-1} b by iterative refinement: x += V (L D L^T)^{-1} U^T r,
+ * r = b - A_H2 x with the FP64 H^2 matvec, until max_col ||r||/||b|| <= tol.
+ * b, x: DEVICE pointers, column-major n x nrhs, leading dimension ld >= n,
+ * ORIGINAL point order.  ENOCONV (x written, info filled) if max_iter is hit.
+ */
+int h2_solve(h2_factor* f, const double* b, double* x, int64_t nrhs, int64_t ld,
+             const h2_solve_opts* opts, h2_solve_info* info);
+
+/* One application of the preconditioner: x = V (L D L^T)^{-1} U^T b (device). */
+int h2_apply_inverse(h2_factor* f, const double* b, double* x, int64_t nrhs, int64_t ld);
+
+void h2_matrix_destroy(h2_matrix* h);
+void h2_sparse_destroy(h2_sparse* sp);
+void h2_factor_destroy(h2_factor* f);
+
+/* Device time (ms) of the last sparsify / factor call's kernels, by phase:
+ * [0] QR, [1] close transforms, [2] couplings, [3] strips, [4] factor pivots,
+ * [5] factor Schur updates, [6] total.  Measured with HIP events. */
+int h2_last_timings(double* ms, int count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2SP_H */

@@ -1,0 +1,290 @@
+"""Python binding of libh2sp (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/h2sp.h under the
+same name; all arithmetic runs in the library's HIP kernels.  Device arrays are
+torch tensors on the current HIP device (torch provides memory and streams, the
+library's work goes to torch's current stream).  The binding fails loudly when
+the library has not been built: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libh2sp.so")
+HEADER = os.path.join(HERE, "..", "include", "h2sp.h")
+
+H2_OK, H2_EINVAL, H2_ENOMEM, H2_EDEVICE, H2_ESINGULAR, H2_ENOCONV, H2_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+H2_KERNEL_INVDIST = 0
+H2_FP64, H2_MIXED = 0, 1
+
+_NAMES = {0: "H2_OK", -1: "H2_EINVAL", -2: "H2_ENOMEM", -3: "H2_EDEVICE", -4: "H2_ESINGULAR",
+          -5: "H2_ENOCONV", -6: "H2_EUNSUPPORTED"}
+
+
+class H2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class h2_kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("scale", ctypes.c_double), ("diag", ctypes.c_double)]
+
+
+class h2_build_opts(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int), ("cheb", ctypes.c_int), ("recompress_tol", ctypes.c_double),
+                ("rank_cap", ctypes.c_int), ("eta", ctypes.c_double)]
+
+
+class h2_sparsify_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int)]
+
+
+class h2_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
+
+
+class h2_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("max_rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double * 3)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_DP = ctypes.POINTER(ctypes.c_double)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+
+_SIGS = {
+    "h2_last_error": (ctypes.c_char_p, []),
+    "h2_set_stream": (ctypes.c_int, [_P]),
+    "h2_build": (ctypes.c_int, [_DP, _I64, ctypes.c_int, ctypes.POINTER(h2_kernel),
+                                ctypes.POINTER(h2_build_opts), ctypes.POINTER(_P)]),
+    "h2_import": (ctypes.c_int, [_DP, _I64, ctypes.c_int, ctypes.POINTER(h2_kernel),
+                                 ctypes.POINTER(h2_build_opts), _I32P, _DP, _DP, _DP, _DP,
+                                 ctypes.POINTER(_P)]),
+    "h2_matrix_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), _I64P, ctypes.POINTER(ctypes.c_int)]),
+    "h2_matrix_export_tree": (ctypes.c_int, [_P, _I64P, _I32P]),
+    "h2_matvec": (ctypes.c_int, [_P, _P, _P, _I64, _I64]),
+    "h2_sparsify": (ctypes.c_int, [_P, ctypes.POINTER(h2_sparsify_opts), ctypes.POINTER(_P)]),
+    "h2_sparse_info": (ctypes.c_int, [_P, _I64P, _I64P]),
+    "h2_sparse_export_plan": (ctypes.c_int, [_P, _I64P, _I64P, _I64P, _I64P, _I64P, _I64P]),
+    "h2_sparse_export_block": (ctypes.c_int, [_P, _I64, _I64, _DP]),
+    "h2_sparse_export_q": (ctypes.c_int, [_P, _I64, _DP]),
+    "h2_factor_S": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "h2_solve": (ctypes.c_int, [_P, _P, _P, _I64, _I64, ctypes.POINTER(h2_solve_opts),
+                                ctypes.POINTER(h2_solve_info)]),
+    "h2_apply_inverse": (ctypes.c_int, [_P, _P, _P, _I64, _I64]),
+    "h2_matrix_destroy": (None, [_P]),
+    "h2_sparse_destroy": (None, [_P]),
+    "h2_factor_destroy": (None, [_P]),
+    "h2_last_timings": (ctypes.c_int, [_DP, ctypes.c_int]),
+}
+
+
+def lib():
+    """The loaded libh2sp (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/h2sp.h."""
+    import re
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(h2_[A-Za-z_0-9]+)\s*\(", text)))
+
+
+def _check(code):
+    if code != H2_OK:
+        raise H2Error(code, lib().h2_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def _use_torch_stream():
+    """Points the library at torch's current stream (no-op without a GPU)."""
+    import torch
+    if torch.cuda.is_available():
+        lib().h2_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+class _Handle:
+    _destroy = None
+
+    def __init__(self, ptr, keep=None):
+        self.ptr = ptr
+        self.keep = keep          # keeps parents alive (sparse -> matrix, factor -> sparse)
+
+    def __del__(self):
+        if self.ptr and _lib is not None:
+            getattr(_lib, self._destroy)(self.ptr)
+            self.ptr = None
+
+
+class H2MatrixHandle(_Handle):
+    _destroy = "h2_matrix_destroy"
+
+
+class H2SparseHandle(_Handle):
+    _destroy = "h2_sparse_destroy"
+
+
+class H2FactorHandle(_Handle):
+    _destroy = "h2_factor_destroy"
+
+
+def _opts(leaf, cheb, tol, rank_cap, eta):
+    return h2_build_opts(int(leaf), int(cheb), float(tol), int(rank_cap), float(eta))
+
+
+def h2_build(points: np.ndarray, scale: float, diag: float = 1.0, leaf: int = 32, cheb: int = 4,
+             tol: float = 0.0, rank_cap: int = 0, eta: float = 1.0) -> H2MatrixHandle:
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    _use_torch_stream()
+    out = _P()
+    k = h2_kernel(H2_KERNEL_INVDIST, float(scale), float(diag))
+    o = _opts(leaf, cheb, tol, rank_cap, eta)
+    _check(lib().h2_build(_dptr(pts), pts.shape[0], pts.shape[1], ctypes.byref(k), ctypes.byref(o),
+                          ctypes.byref(out)))
+    return H2MatrixHandle(out.value)
+
+
+def h2_import(points: np.ndarray, scale: float, diag: float, leaf: int, cheb: int, eta: float,
+              rank: np.ndarray, nodes: np.ndarray, proj: np.ndarray, leaf_basis: np.ndarray,
+              transfer: np.ndarray) -> H2MatrixHandle:
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    rank = np.ascontiguousarray(rank, dtype=np.int32)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (nodes, proj, leaf_basis, transfer)]
+    arrs = [a if a.size else np.zeros(1) for a in arrs]
+    _use_torch_stream()
+    out = _P()
+    k = h2_kernel(H2_KERNEL_INVDIST, float(scale), float(diag))
+    o = _opts(leaf, cheb, 0.0, 0, eta)
+    _check(lib().h2_import(_dptr(pts), pts.shape[0], pts.shape[1], ctypes.byref(k), ctypes.byref(o),
+                           rank.ctypes.data_as(_I32P), *[_dptr(a) for a in arrs], ctypes.byref(out)))
+    return H2MatrixHandle(out.value)
+
+
+def h2_matrix_info(h: H2MatrixHandle):
+    depth, pts = ctypes.c_int(), ctypes.c_int()
+    ncl = ctypes.c_int64()
+    _check(lib().h2_matrix_info(h.ptr, ctypes.byref(depth), ctypes.byref(ncl), ctypes.byref(pts)))
+    return depth.value, ncl.value, pts.value
+
+
+def h2_matrix_export_tree(h: H2MatrixHandle, n: int):
+    depth, ncl, _ = h2_matrix_info(h)
+    perm = np.zeros(n, dtype=np.int64)
+    rank = np.zeros(ncl, dtype=np.int32)
+    _check(lib().h2_matrix_export_tree(h.ptr, perm.ctypes.data_as(_I64P), rank.ctypes.data_as(_I32P)))
+    return perm, rank
+
+
+def _dev(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def h2_matvec(h: H2MatrixHandle, x, y):
+    """y = A_H2 x; x, y: float64 CUDA tensors (n, nrhs) column-major, i.e. x.T contiguous."""
+    _use_torch_stream()
+    n, nrhs, ld = _colmajor(x)
+    _colmajor(y)
+    _check(lib().h2_matvec(h.ptr, _dev(x), _dev(y), nrhs, ld))
+
+
+def _colmajor(t):
+    if t.dim() == 1:
+        return t.shape[0], 1, t.shape[0]
+    n, nrhs = t.shape
+    if t.stride(0) != 1:
+        raise ValueError("device arrays must be column-major (use t.T.contiguous().T)")
+    return n, nrhs, t.stride(1) if nrhs > 1 else n
+
+
+def h2_sparsify(h: H2MatrixHandle, precision: int = H2_FP64) -> H2SparseHandle:
+    _use_torch_stream()
+    out = _P()
+    o = h2_sparsify_opts(int(precision))
+    _check(lib().h2_sparsify(h.ptr, ctypes.byref(o), ctypes.byref(out)))
+    return H2SparseHandle(out.value, keep=h)
+
+
+def h2_sparse_info(sp: H2SparseHandle):
+    b, e = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().h2_sparse_info(sp.ptr, ctypes.byref(b), ctypes.byref(e)))
+    return b.value, e.value
+
+
+def h2_sparse_export_plan(sp: H2SparseHandle):
+    _, ncl, _ = h2_matrix_info(sp.keep)
+    nb, _ = h2_sparse_info(sp)
+    arr = [np.zeros(ncl, dtype=np.int64) for _ in range(4)]
+    rowptr = np.zeros(ncl + 1, dtype=np.int64)
+    colidx = np.zeros(max(nb, 1), dtype=np.int64)
+    _check(lib().h2_sparse_export_plan(sp.ptr, *[a.ctypes.data_as(_I64P) for a in arr],
+                                       rowptr.ctypes.data_as(_I64P), colidx.ctypes.data_as(_I64P)))
+    return dict(n_act=arr[0], kept=arr[1], nonbasis=arr[2], soff=arr[3], rowptr=rowptr,
+                colidx=colidx[:nb])
+
+
+def h2_sparse_export_block(sp: H2SparseHandle, t: int, s: int, mt: int, ms: int) -> np.ndarray:
+    out = np.zeros(mt * ms)
+    _check(lib().h2_sparse_export_block(sp.ptr, int(t), int(s), _dptr(out)))
+    return out.reshape(ms, mt).T
+
+
+def h2_sparse_export_q(sp: H2SparseHandle, t: int, n: int) -> np.ndarray:
+    out = np.zeros(n * n)
+    _check(lib().h2_sparse_export_q(sp.ptr, int(t), _dptr(out)))
+    return out.reshape(n, n).T
+
+
+def h2_factor_S(sp: H2SparseHandle) -> H2FactorHandle:
+    _use_torch_stream()
+    out = _P()
+    _check(lib().h2_factor_S(sp.ptr, ctypes.byref(out)))
+    return H2FactorHandle(out.value, keep=sp)
+
+
+def h2_solve(f: H2FactorHandle, b, x, tol: float = 1e-10, max_iter: int = 30, check: bool = True):
+    """x = A_H2^{-1} b by refinement; b, x float64 CUDA tensors (n, nrhs), column-major."""
+    _use_torch_stream()
+    n, nrhs, ld = _colmajor(b)
+    o = h2_solve_opts(float(tol), int(max_iter))
+    info = h2_solve_info()
+    code = lib().h2_solve(f.ptr, _dev(b), _dev(x), nrhs, ld, ctypes.byref(o), ctypes.byref(info))
+    if check or code not in (H2_OK, H2_ENOCONV):
+        _check(code)
+    return dict(iters=info.iters, residual=info.max_rel_residual, code=code)
+
+
+def h2_apply_inverse(f: H2FactorHandle, b, x):
+    _use_torch_stream()
+    n, nrhs, ld = _colmajor(b)
+    _check(lib().h2_apply_inverse(f.ptr, _dev(b), _dev(x), nrhs, ld))
+
+
+def h2_last_timings():
+    out = np.zeros(8)
+    _check(lib().h2_last_timings(_dptr(out), 8))
+    return out

@@ -1,0 +1,33 @@
+// Block ILU(0) of S (symmetric form L D L^T) and the solve plan.
+#pragma once
+
+#include <memory>
+
+#include "sparse.h"
+
+namespace h2 {
+
+// Device work lists of one preconditioner application for a fixed number of
+// right-hand sides.
+struct SolvePlan {
+  i64 nrhs = 0;
+  DeviceBuffer zin, zbuf, y, w, rs, colscale;
+  std::vector<GemmBatch> up, down;       // U^T and V sweeps, per tree level
+  std::vector<GemmBatch> fwd, bwd;       // triangular solves, per DAG level
+  GemmBatch diag;                        // D^{-1}
+};
+
+}  // namespace h2
+
+struct h2_factor {
+  h2_sparse* sp = nullptr;
+  // active block rows (m > 0) by S position; DAG levels of the elimination
+  std::vector<h2::i64> rows;                 // S positions with m > 0
+  std::vector<int> flev, blev;               // forward / backward level per S position
+  int nflev = 0, nblev = 0;
+  std::vector<h2::i64> inv_off;              // per S position: offset of D_k^{-1}
+  h2::DeviceBuffer dInv, dZ, dFlag;
+  double flops_schur = 0, flops_inv = 0, flops_z = 0;
+  std::unique_ptr<h2::SolvePlan> solve;
+  ~h2_factor();
+};

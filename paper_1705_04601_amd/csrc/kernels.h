@@ -1,0 +1,107 @@
+// Device kernels of libh2sp and their work-item descriptors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace h2 {
+
+// One K-segment of a batched GEMM item: acc += op(A) (M x K) * op(B) (K x N).
+// opA = 0: A column-major M x K (element (i, k) at A[i + k lda]);
+// opA = 1: A stored K x M   (element (i, k) at A[k + i lda]).
+// opB = 0: B column-major K x N; opB = 1: B stored N x K.
+// gen = 1: A is generated, A(i, k) = scale / |pr_i - pc_k| with pr = (const
+// double*) A and pc the column points (dim-strided); diag = 1 puts the
+// diagonal value where i == k (a cluster against itself).
+struct GemmSeg {
+  const void* A;
+  const void* B;
+  const double* pc;
+  int32_t K, lda, ldb;
+  uint8_t opA, opB, gen, diag;
+};
+
+// Output of a batched GEMM item (M x N), split into quadrants at row rs and
+// column cs: q0 = [0,rs) x [0,cs), q1 = [0,rs) x [cs,N), q2 = [rs,M) x [0,cs),
+// q3 = [rs,M) x [cs,N).  Destination q (0..3) receives its quadrant with local
+// indices; destination 4 receives quadrant 0 again.  trans[q] = 1 stores the
+// transpose (element (i, j) at out[j + i ld]).  A null out drops the quadrant.
+struct GemmItem {
+  int32_t M, N, seg_begin, seg_end;
+  int32_t rs, cs;
+  void* out[5];
+  int32_t ld[5];
+  uint8_t trans[5];
+};
+
+enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1, GEMM_SUB = 2 };
+
+struct GemmLaunch {
+  const GemmItem* items;
+  const GemmSeg* segs;
+  const int32_t* tiles;   // per work-group: (item << 8) | (tile_row << 4) | tile_col
+  int32_t ntiles;
+  int mode;
+  int dim;
+  double scale, diag;
+};
+
+template <class T>
+void launch_gemm(const GemmLaunch& g, hipStream_t st);
+
+// Householder QR of one cluster basis B (n x r, column-major, ld n), n <= 128,
+// r <= 64.  Writes the explicit square Q (n x n, ld n) and R^ = rows 0..k-1 of
+// R (k x r, ld k).  k = 0: Q = I and nothing else.
+struct QrItem {
+  const double* B;
+  double* Q;
+  double* Rhat;
+  int32_t n, r, k, pad;
+};
+void launch_qr(const QrItem* items, int count, hipStream_t st);
+
+// Inverse of a pivot block (m x m, column-major, m <= 128) computed in FP64 by
+// Gauss-Jordan elimination with partial pivoting; a zero pivot sets *flag = 1.
+template <class T>
+struct InvItem {
+  const T* A;
+  T* Inv;
+  int32_t m, pad;
+};
+template <class T>
+void launch_inverse(const InvItem<T>* items, int count, int* flag, hipStream_t st);
+
+// dst[s.dst + e] = src[s.src + e] for e < s.len, for every segment s.
+struct CopySeg {
+  int64_t dst, src, len;
+};
+template <class T>
+void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st);
+
+// Small element-wise helpers.
+void launch_fill(double* p, int64_t n, double v, hipStream_t st);
+void launch_fill_f(float* p, int64_t n, float v, hipStream_t st);
+void launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t st);
+void launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t st);
+// out[i + j ldo] = in[idx[i] + j ldi]  (gather rows), i < n, j < nrhs
+template <class T>
+void launch_gather_rows(const T* in, int64_t ldi, const int64_t* idx, T* out, int64_t ldo,
+                        int64_t n, int64_t nrhs, hipStream_t st);
+// out[idx[i] + j ldo] = in[i + j ldi]  (scatter rows)
+void launch_scatter_rows(const double* in, int64_t ldi, const int64_t* idx, double* out,
+                         int64_t ldo, int64_t n, int64_t nrhs, hipStream_t st);
+// r = b - y (ld's), columnwise sum of squares of r and of b into nrm2[2*nrhs]
+void launch_residual(const double* b, int64_t ldb, const double* y, int64_t ldy, double* r,
+                     int64_t n, int64_t nrhs, double* nrm2, hipStream_t st);
+// float out = in * (1/colscale[j]);  double acc += float in * colscale[j]
+void launch_scale_to_f(const double* in, const double* colscale, float* out, int64_t n,
+                       int64_t nrhs, hipStream_t st);
+void launch_add_scaled_f(const float* in, const double* colscale, double* acc, int64_t ldacc,
+                         int64_t n, int64_t nrhs, hipStream_t st);
+void launch_add(const double* in, double* acc, int64_t ldacc, int64_t n, int64_t nrhs,
+                hipStream_t st);
+void launch_copy_cols(const double* in, int64_t ldi, double* out, int64_t ldo, int64_t n,
+                      int64_t nrhs, hipStream_t st);
+
+}  // namespace h2

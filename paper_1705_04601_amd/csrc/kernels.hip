@@ -1,0 +1,482 @@
+// HIP kernels of libh2sp for gfx950 (CDNA4, 64-wide wavefronts).
+//
+//  * gemm_kernel: batched, segmented small GEMM on MFMA (v_mfma_f64_16x16x4 /
+//    v_mfma_f32_16x16x4).  One wavefront per 32 x 32 output tile, K staged
+//    through LDS in chunks of 16; operand A can be generated on the fly from
+//    points (kernel evaluation, so close blocks never touch HBM); the epilogue
+//    scatters the four quadrants of the tile to separate destinations (the
+//    basis / non-basis split of Section 2).
+//  * qr_kernel: Householder QR of a cluster basis held in LDS, FP64, norms by
+//    wavefront reductions, explicit square Q (Section 4.2).
+//  * inverse_kernel: FP64 Gauss-Jordan inversion with partial pivoting of a
+//    pivot block of S, LDS resident.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace h2 {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <class T> struct Mfma;
+// Output layout of the 16x16x4 instructions (lane l, accumulator element v):
+// f64 holds D[l/16 + 4v][l%16], f32 holds D[4(l/16) + v][l%16] (measured on
+// gfx950).  `row` returns that D row.
+template <> struct Mfma<double> {
+  using V = d4;
+  static __device__ __forceinline__ V run(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return lane / 16 + 4 * v; }
+};
+template <> struct Mfma<float> {
+  using V = f4;
+  static __device__ __forceinline__ V run(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
+};
+
+constexpr int TM = 32, TN = 32, KC = 16;
+
+template <class T>
+__device__ __forceinline__ void store_out(const GemmItem& it, int q, int lr, int lc, T v, int mode) {
+  T* base = static_cast<T*>(it.out[q]);
+  if (!base) return;
+  const int64_t ld = it.ld[q];
+  T* p = it.trans[q] ? base + lc + lr * ld : base + lr + lc * ld;
+  if (mode == GEMM_STORE) *p = v;
+  else if (mode == GEMM_ADD) *p += v;
+  else *p -= v;
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void gemm_kernel(GemmLaunch g) {
+  using V = typename Mfma<T>::V;
+  __shared__ T As[KC][TM + 1];
+  __shared__ T Bs[KC][TN + 1];
+  const int lane = threadIdx.x;
+  const uint32_t code = static_cast<uint32_t>(g.tiles[blockIdx.x]);
+  const GemmItem it = g.items[code >> 8];
+  const int m0 = int((code >> 4) & 15) * TM, n0 = int(code & 15) * TN;
+  V acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
+  const int dim = g.dim;
+  for (int si = it.seg_begin; si < it.seg_end; ++si) {
+    const GemmSeg sg = g.segs[si];
+    for (int k0 = 0; k0 < sg.K; k0 += KC) {
+      // ---- A chunk (TM x KC) into As[k][m]
+      if (sg.gen) {
+        const double* pr = static_cast<const double*>(sg.A);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int idx = lane + 64 * e, i = idx % TM, k = idx / TM;
+          const int gi = m0 + i, gk = k0 + k;
+          T v = T(0);
+          if (gi < it.M && gk < sg.K) {
+            if (sg.diag && gi == gk) {
+              v = T(g.diag);
+            } else {
+              double d2 = 0.0;
+              for (int a = 0; a < dim; ++a) {
+                const double d = pr[gi * dim + a] - sg.pc[gk * dim + a];
+                d2 += d * d;
+              }
+              v = T(g.scale / sqrt(d2));
+            }
+          }
+          As[k][i] = v;
+        }
+      } else if (sg.opA == 0) {
+        const T* A = static_cast<const T*>(sg.A);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int idx = lane + 64 * e, i = idx % TM, k = idx / TM;
+          const int gi = m0 + i, gk = k0 + k;
+          As[k][i] = (gi < it.M && gk < sg.K) ? A[gi + int64_t(gk) * sg.lda] : T(0);
+        }
+      } else {
+        const T* A = static_cast<const T*>(sg.A);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int idx = lane + 64 * e, k = idx % KC, i = idx / KC;
+          const int gi = m0 + i, gk = k0 + k;
+          As[k][i] = (gi < it.M && gk < sg.K) ? A[gk + int64_t(gi) * sg.lda] : T(0);
+        }
+      }
+      // ---- B chunk (KC x TN) into Bs[k][n]
+      const T* B = static_cast<const T*>(sg.B);
+      if (sg.opB == 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int idx = lane + 64 * e, k = idx % KC, n = idx / KC;
+          const int gk = k0 + k, gn = n0 + n;
+          Bs[k][n] = (gk < sg.K && gn < it.N) ? B[gk + int64_t(gn) * sg.ldb] : T(0);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int idx = lane + 64 * e, n = idx % TN, k = idx / TN;
+          const int gk = k0 + k, gn = n0 + n;
+          Bs[k][n] = (gk < sg.K && gn < it.N) ? B[gn + int64_t(gk) * sg.ldb] : T(0);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int kr = kk + lane / 16, c = lane % 16;
+        const T a0 = As[kr][c], a1 = As[kr][16 + c];
+        const T b0 = Bs[kr][c], b1 = Bs[kr][16 + c];
+        // operands swapped (D = B^T A^T) so that consecutive lanes hold
+        // consecutive output rows: lane l has output row 16bm + l%16 and
+        // output column 16bn + Mfma<T>::row(l, v)
+        acc[0][0] = Mfma<T>::run(b0, a0, acc[0][0]);
+        acc[0][1] = Mfma<T>::run(b1, a0, acc[0][1]);
+        acc[1][0] = Mfma<T>::run(b0, a1, acc[1][0]);
+        acc[1][1] = Mfma<T>::run(b1, a1, acc[1][1]);
+      }
+      __syncthreads();
+    }
+  }
+  // ---- epilogue: quadrant scatter
+  for (int bm = 0; bm < 2; ++bm)
+    for (int bn = 0; bn < 2; ++bn)
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + 16 * bm + lane % 16;
+        const int col = n0 + 16 * bn + Mfma<T>::row(lane, v);
+        if (row >= it.M || col >= it.N) continue;
+        const int q = (row >= it.rs ? 2 : 0) + (col >= it.cs ? 1 : 0);
+        const int lr = row - (q >= 2 ? it.rs : 0), lc = col - ((q & 1) ? it.cs : 0);
+        const T val = acc[bm][bn][v];
+        store_out<T>(it, q, lr, lc, val, g.mode);
+        if (q == 0) store_out<T>(it, 4, lr, lc, val, g.mode);
+      }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void qr_kernel(const QrItem* items) {
+  __shared__ double Bs[128 * 64];
+  __shared__ double Qs[128 * 32];
+  __shared__ double tau[64];
+  __shared__ double scal[2];
+  const QrItem it = items[blockIdx.x];
+  const int n = it.n, r = it.r, kk = it.k, tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  if (kk == 0) {
+    for (int e = tid; e < n * n; e += 256) it.Q[e] = (e % n == e / n) ? 1.0 : 0.0;
+    return;
+  }
+  for (int e = tid; e < n * r; e += 256) Bs[e] = it.B[e];
+  __syncthreads();
+  const int q = n < r ? n : r;
+  for (int j = 0; j < q; ++j) {
+    if (wave == 0) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < n; i += 64) s += Bs[i + j * n] * Bs[i + j * n];
+      s = wave_sum(s);
+      if (lane == 0) {
+        const double alpha = Bs[j + j * n];
+        if (s == 0.0) {
+          tau[j] = 0.0;
+        } else {
+          const double nrm = sqrt(alpha * alpha + s);
+          const double beta = alpha >= 0.0 ? -nrm : nrm;
+          tau[j] = (beta - alpha) / beta;
+          scal[0] = 1.0 / (alpha - beta);
+          scal[1] = beta;
+        }
+      }
+    }
+    __syncthreads();
+    const double tj = tau[j];
+    if (tj != 0.0) {
+      const double sc = scal[0];
+      for (int i = j + 1 + tid; i < n; i += 256) Bs[i + j * n] *= sc;
+      if (tid == 0) Bs[j + j * n] = scal[1];
+      __syncthreads();
+      for (int c = j + 1 + wave; c < r; c += 4) {
+        double d = 0.0;
+        for (int i = j + 1 + lane; i < n; i += 64) d += Bs[i + j * n] * Bs[i + c * n];
+        d = wave_sum(d);
+        d = (d + Bs[j + c * n]) * tj;
+        for (int i = j + 1 + lane; i < n; i += 64) Bs[i + c * n] -= d * Bs[i + j * n];
+        if (lane == 0) Bs[j + c * n] -= d;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kk * r; e += 256) {
+    const int i = e % kk, j = e / kk;
+    it.Rhat[e] = (i <= j) ? Bs[i + j * n] : 0.0;
+  }
+  const int cc = tid / 8, sub = tid % 8;
+  for (int c0 = 0; c0 < n; c0 += 32) {
+    const int nc = (n - c0) < 32 ? (n - c0) : 32;
+    for (int e = tid; e < n * 32; e += 256) {
+      const int i = e % n, c = e / n;
+      Qs[e] = (c < nc && i == c0 + c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int jtop = (q - 1) < (c0 + 31) ? (q - 1) : (c0 + 31);
+    if (cc < nc) {
+      for (int j = jtop; j >= 0; --j) {
+        const double tj = tau[j];
+        if (tj == 0.0) continue;
+        double d = 0.0;
+        for (int i = j + 1 + sub; i < n; i += 8) d += Bs[i + j * n] * Qs[i + cc * n];
+        d += __shfl_xor(d, 4, 64);
+        d += __shfl_xor(d, 2, 64);
+        d += __shfl_xor(d, 1, 64);
+        d = (d + Qs[j + cc * n]) * tj;
+        for (int i = j + 1 + sub; i < n; i += 8) Qs[i + cc * n] -= d * Bs[i + j * n];
+        if (sub == 0) Qs[j + cc * n] -= d;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * nc; e += 256) it.Q[int64_t(c0) * n + e] = Qs[e];
+    __syncthreads();
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void inverse_kernel(const InvItem<T>* items, int* flag) {
+  __shared__ double a[128 * 128];
+  __shared__ double fcol[128];
+  __shared__ int perm[128];
+  const InvItem<T> it = items[blockIdx.x];
+  const int m = it.m, tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  for (int e = tid; e < m * m; e += 256) a[e] = double(it.A[e]);
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = j;
+      for (int i = j + lane; i < m; i += 64) {
+        const double v = fabs(a[i + j * m]);
+        if (v > best) { best = v; bi = i; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        perm[j] = bi;
+        if (!(best > 0.0)) atomicOr(flag, 1);
+      }
+    }
+    __syncthreads();
+    const int p = perm[j];
+    if (p != j)
+      for (int c = tid; c < m; c += 256) {
+        const double t = a[j + c * m];
+        a[j + c * m] = a[p + c * m];
+        a[p + c * m] = t;
+      }
+    __syncthreads();
+    const double piv = a[j + j * m];
+    for (int i = tid; i < m; i += 256) fcol[i] = a[i + j * m];
+    __syncthreads();
+    for (int c = tid; c < m; c += 256) a[j + c * m] = (c == j ? 1.0 : a[j + c * m]) / piv;
+    __syncthreads();
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = e % m, c = e / m;
+      if (i != j) a[e] = (c == j ? 0.0 : a[e]) - fcol[i] * a[j + c * m];
+    }
+    __syncthreads();
+  }
+  for (int j = m - 1; j >= 0; --j) {
+    const int p = perm[j];
+    if (p != j)
+      for (int i = tid; i < m; i += 256) {
+        const double t = a[i + j * m];
+        a[i + j * m] = a[i + p * m];
+        a[i + p * m] = t;
+      }
+    __syncthreads();
+  }
+  for (int e = tid; e < m * m; e += 256) it.Inv[e] = T(a[e]);
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+__global__ void fill_f_kernel(float* p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+__global__ void cast_d2f_kernel(const double* in, float* out, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) out[i] = float(in[i]);
+}
+__global__ void cast_f2d_kernel(const float* in, double* out, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) out[i] = double(in[i]);
+}
+template <class T>
+__global__ void gather_rows_kernel(const T* in, int64_t ldi, const int64_t* idx, T* out, int64_t ldo, int64_t n, int64_t nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = e % n, j = e / n;
+    out[i + j * ldo] = in[idx[i] + j * ldi];
+  }
+}
+__global__ void scatter_rows_kernel(const double* in, int64_t ldi, const int64_t* idx, double* out, int64_t ldo, int64_t n, int64_t nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = e % n, j = e / n;
+    out[idx[i] + j * ldo] = in[i + j * ldi];
+  }
+}
+// one block per column: r = b - y and the sums of squares of r and b
+__global__ __launch_bounds__(256) void residual_kernel(const double* b, int64_t ldb, const double* y, int64_t ldy, double* r,
+                                                       int64_t n, double* nrm2, int64_t nrhs) {
+  __shared__ double red[2][256];
+  const int64_t j = blockIdx.x;
+  double sr = 0.0, sb = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double bv = b[i + j * ldb];
+    const double rv = bv - y[i + j * ldy];
+    r[i + j * n] = rv;
+    sr += rv * rv;
+    sb += bv * bv;
+  }
+  red[0][threadIdx.x] = sr;
+  red[1][threadIdx.x] = sb;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    nrm2[j] = red[0][0];
+    nrm2[nrhs + j] = red[1][0];
+  }
+}
+__global__ void scale_to_f_kernel(const double* in, const double* cs, float* out, int64_t n, int64_t nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x)
+    out[e] = float(in[e] / cs[e / n]);
+}
+__global__ void add_scaled_f_kernel(const float* in, const double* cs, double* acc, int64_t ldacc, int64_t n, int64_t nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = e % n, j = e / n;
+    acc[i + j * ldacc] += double(in[e]) * cs[j];
+  }
+}
+__global__ void add_kernel(const double* in, double* acc, int64_t ldacc, int64_t n, int64_t nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = e % n, j = e / n;
+    acc[i + j * ldacc] += in[e];
+  }
+}
+__global__ void copy_cols_kernel(const double* in, int64_t ldi, double* out, int64_t ldo, int64_t n, int64_t nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = e % n, j = e / n;
+    out[i + j * ldo] = in[i + j * ldi];
+  }
+}
+
+template <class T>
+__global__ void copy_segments_kernel(const CopySeg* segs, const T* src, T* dst) {
+  const CopySeg s = segs[blockIdx.y];
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < s.len; e += int64_t(gridDim.x) * blockDim.x)
+    dst[s.dst + e] = src[s.src + e];
+}
+
+int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return int(g);
+}
+
+}  // namespace
+
+template <class T>
+void launch_gemm(const GemmLaunch& g, hipStream_t st) {
+  if (g.ntiles <= 0) return;
+  hipLaunchKernelGGL(gemm_kernel<T>, dim3(g.ntiles), dim3(64), 0, st, g);
+}
+template void launch_gemm<double>(const GemmLaunch&, hipStream_t);
+template void launch_gemm<float>(const GemmLaunch&, hipStream_t);
+
+void launch_qr(const QrItem* items, int count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(qr_kernel, dim3(count), dim3(256), 0, st, items);
+}
+
+template <class T>
+void launch_inverse(const InvItem<T>* items, int count, int* flag, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(inverse_kernel<T>, dim3(count), dim3(256), 0, st, items, flag);
+}
+template void launch_inverse<double>(const InvItem<double>*, int, int*, hipStream_t);
+template void launch_inverse<float>(const InvItem<float>*, int, int*, hipStream_t);
+
+template <class T>
+void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st) {
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int c = (count - c0) < 65535 ? (count - c0) : 65535;
+    hipLaunchKernelGGL(copy_segments_kernel<T>, dim3(64, c), dim3(256), 0, st, segs + c0, src, dst);
+  }
+}
+template void launch_copy_segments<double>(const CopySeg*, int, const double*, double*, hipStream_t);
+template void launch_copy_segments<float>(const CopySeg*, int, const float*, float*, hipStream_t);
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+}
+void launch_fill_f(float* p, int64_t n, float v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(fill_f_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+}
+void launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(cast_d2f_kernel, dim3(grid_for(n)), dim3(256), 0, st, in, out, n);
+}
+void launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(cast_f2d_kernel, dim3(grid_for(n)), dim3(256), 0, st, in, out, n);
+}
+template <class T>
+void launch_gather_rows(const T* in, int64_t ldi, const int64_t* idx, T* out, int64_t ldo, int64_t n, int64_t nrhs,
+                        hipStream_t st) {
+  if (n * nrhs > 0)
+    hipLaunchKernelGGL(gather_rows_kernel<T>, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, ldi, idx, out, ldo, n, nrhs);
+}
+template void launch_gather_rows<double>(const double*, int64_t, const int64_t*, double*, int64_t, int64_t, int64_t, hipStream_t);
+void launch_scatter_rows(const double* in, int64_t ldi, const int64_t* idx, double* out, int64_t ldo, int64_t n,
+                         int64_t nrhs, hipStream_t st) {
+  if (n * nrhs > 0)
+    hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, ldi, idx, out, ldo, n, nrhs);
+}
+void launch_residual(const double* b, int64_t ldb, const double* y, int64_t ldy, double* r, int64_t n, int64_t nrhs,
+                     double* nrm2, hipStream_t st) {
+  if (nrhs > 0) hipLaunchKernelGGL(residual_kernel, dim3(nrhs), dim3(256), 0, st, b, ldb, y, ldy, r, n, nrm2, nrhs);
+}
+void launch_scale_to_f(const double* in, const double* cs, float* out, int64_t n, int64_t nrhs, hipStream_t st) {
+  if (n * nrhs > 0) hipLaunchKernelGGL(scale_to_f_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, cs, out, n, nrhs);
+}
+void launch_add_scaled_f(const float* in, const double* cs, double* acc, int64_t ldacc, int64_t n, int64_t nrhs,
+                         hipStream_t st) {
+  if (n * nrhs > 0)
+    hipLaunchKernelGGL(add_scaled_f_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, cs, acc, ldacc, n, nrhs);
+}
+void launch_add(const double* in, double* acc, int64_t ldacc, int64_t n, int64_t nrhs, hipStream_t st) {
+  if (n * nrhs > 0) hipLaunchKernelGGL(add_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, acc, ldacc, n, nrhs);
+}
+void launch_copy_cols(const double* in, int64_t ldi, double* out, int64_t ldo, int64_t n, int64_t nrhs, hipStream_t st) {
+  if (n * nrhs > 0)
+    hipLaunchKernelGGL(copy_cols_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, ldi, out, ldo, n, nrhs);
+}
+
+}  // namespace h2

@@ -1,0 +1,356 @@
+// h2_matrix: construction, import, export and the FP64 H^2 matrix-vector
+// product (Definition 4.8): close part evaluated on the fly from the points,
+// far part by the nested bases (upward pass, couplings, downward pass).
+#include <cmath>
+#include <memory>
+#include <unordered_map>
+
+#include "batch.h"
+#include "h2_internal.h"
+
+namespace h2 {
+void fill_structure(h2_matrix& H, const double* pts, i64 n, int dim, const h2_kernel& kern,
+                    const h2_build_opts& o);
+void build_chebyshev(h2_matrix& H, double tol, int rank_cap);
+
+static void validate(const double* pts, i64 n, int dim, const h2_kernel* kernel,
+                     const h2_build_opts* o) {
+  if (!pts || !kernel || !o) fail(H2_EINVAL, "null argument");
+  if (n < 1) fail(H2_EINVAL, "n must be >= 1");
+  if (dim != 2 && dim != 3) fail(H2_EINVAL, "dim must be 2 or 3");
+  if (kernel->kind != H2_KERNEL_INVDIST) fail(H2_EUNSUPPORTED, "unknown kernel kind");
+  if (!std::isfinite(kernel->scale) || !std::isfinite(kernel->diag)) fail(H2_EINVAL, "kernel constants not finite");
+  if (o->leaf < 2 || o->leaf > 128) fail(H2_EINVAL, "leaf must be in [2, 128]");
+  if (o->cheb < 2 || o->cheb > 8) fail(H2_EINVAL, "cheb must be in [2, 8]");
+  int P = 1;
+  for (int a = 0; a < dim; ++a) P *= o->cheb;
+  if (P > 64) fail(H2_EUNSUPPORTED, "cheb^dim must be <= 64");
+  if (!(o->eta >= 0.0) || !std::isfinite(o->eta)) fail(H2_EINVAL, "eta must be >= 0");
+  if (!(o->recompress_tol >= 0.0)) fail(H2_EINVAL, "recompress_tol must be >= 0");
+  for (i64 i = 0; i < n * dim; ++i)
+    if (!std::isfinite(pts[i])) fail(H2_EINVAL, "point coordinates must be finite");
+}
+
+// Duplicate points give a zero distance in the kernel; detected on the sorted
+// leaves (equal points always share a leaf: the split order is total).
+static void check_duplicates(const h2_matrix& H) {
+  const Tree& tr = H.tree;
+  const int dim = tr.dim;
+  const i64 f = tr.first_at_level(0), cnt = tr.count_at_level(0);
+  for (i64 c = f; c < f + cnt; ++c)
+    for (i64 i = tr.start[c]; i < tr.start[c] + tr.size[c]; ++i)
+      for (i64 j = i + 1; j < tr.start[c] + tr.size[c]; ++j) {
+        bool same = true;
+        for (int a = 0; a < dim && same; ++a) same = H.x_tree[i * dim + a] == H.x_tree[j * dim + a];
+        if (same) fail(H2_EINVAL, "duplicate points");
+      }
+}
+
+}  // namespace h2
+
+using namespace h2;
+
+void h2_matrix::upload_all() {
+  if (on_device) return;
+  on_device = true;
+  d_x = upload(x_tree);
+  d_nodes = upload(nodes);
+  d_proj = upload(proj);
+  d_basis = upload(basis);
+  d_transfer = upload(transfer);
+  d_perm = upload(tree.perm);
+}
+
+// ---------------------------------------------------------------- matvec plan
+namespace h2 {
+
+struct MatvecPlan {
+  i64 nrhs = 0;
+  DeviceBuffer xt, yt, xhat, xtil, ytil, yhat;
+  GemmBatch close;
+  std::vector<GemmBatch> up;     // per level (0 = leaves)
+  GemmBatch xproj, coup, yproj;
+  std::vector<GemmBatch> down;   // per level, applied from the top
+  GemmBatch leafout;
+};
+
+static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
+  H.upload_all();
+  auto mp = std::make_unique<MatvecPlan>();
+  MatvecPlan& p = *mp;
+  const Tree& tr = H.tree;
+  const i64 n = tr.n, ncl = tr.ncl();
+  const int dim = tr.dim, P = H.P, L = tr.depth;
+  p.nrhs = nrhs;
+  p.xt.reset(sizeof(double) * n * nrhs);
+  p.yt.reset(sizeof(double) * n * nrhs);
+  std::vector<i64> hoff(ncl, -1), poff(ncl, -1);
+  i64 hs = 0, ps = 0;
+  for (i64 c = 0; c < ncl; ++c)
+    if (H.ff[c]) {
+      hoff[c] = hs;
+      hs += i64(H.rank[c]) * nrhs;
+      poff[c] = ps;
+      ps += i64(P) * nrhs;
+    }
+  p.xhat.reset(sizeof(double) * std::max<i64>(hs, 1));
+  p.yhat.reset(sizeof(double) * std::max<i64>(hs, 1));
+  p.xtil.reset(sizeof(double) * std::max<i64>(ps, 1));
+  p.ytil.reset(sizeof(double) * std::max<i64>(ps, 1));
+  const double* X = H.d_x.as<double>();
+  double* xt = p.xt.as<double>();
+  double* yt = p.yt.as<double>();
+  double* xhat = p.xhat.as<double>();
+  double* yhat = p.yhat.as<double>();
+  double* xtil = H.identity_proj ? xhat : p.xtil.as<double>();
+  double* ytil = H.identity_proj ? yhat : p.ytil.as<double>();
+  const i64* til_off = H.identity_proj ? hoff.data() : poff.data();
+  const double* basis = H.d_basis.as<double>();
+  const double* transfer = H.d_transfer.as<double>();
+  const double* proj = H.d_proj.as<double>();
+  const double* nodes = H.d_nodes.as<double>();
+
+  // close part: one item per leaf, one segment per near leaf
+  std::vector<std::vector<int32_t>> nearOf(ncl);
+  for (const Pair& pr : H.bt.near[0]) nearOf[pr.t].push_back(pr.s);
+  const i64 f0 = tr.first_at_level(0), c0 = tr.count_at_level(0);
+  for (i64 t = f0; t < f0 + c0; ++t) {
+    GemmItem& it = p.close.item(int(tr.size[t]), int(nrhs), int(tr.size[t]), int(nrhs));
+    GemmBatch::set_out(it, 0, yt + tr.start[t], n, false);
+    for (int32_t s : nearOf[t])
+      p.close.seg_gen(X + tr.start[t] * dim, X + tr.start[s] * dim, s == t, xt + tr.start[s], int(n),
+                      false, int(tr.size[s]));
+  }
+  p.close.finalize();
+  // upward pass
+  p.up.resize(L + 1);
+  for (int k = 0; k <= L; ++k) {
+    const i64 f = tr.first_at_level(k), cnt = tr.count_at_level(k);
+    for (i64 c = f; c < f + cnt; ++c) {
+      if (!H.ff[c]) continue;
+      const int r = H.rank[c];
+      GemmItem& it = p.up[k].item(r, int(nrhs), r, int(nrhs));
+      GemmBatch::set_out(it, 0, xhat + hoff[c], r, false);
+      if (k == 0) {
+        p.up[k].seg(basis + H.basis_off[c], int(tr.size[c]), true, xt + tr.start[c], int(n), false,
+                    int(tr.size[c]));
+      } else {
+        for (i64 s = 2 * c + 1; s <= 2 * c + 2; ++s)
+          p.up[k].seg(transfer + H.transfer_off[s], H.rank[s], true, xhat + hoff[s], H.rank[s], false,
+                      H.rank[s]);
+      }
+    }
+    p.up[k].finalize();
+  }
+  // couplings: xtil = P^T xhat; ytil_t = sum_s K(nodes_t, nodes_s) xtil_s; yhat = P ytil
+  std::vector<std::vector<int32_t>> farOf(ncl);
+  for (const auto& lev : H.bt.far)
+    for (const Pair& pr : lev) farOf[pr.t].push_back(pr.s);
+  for (i64 c = 0; c < ncl; ++c) {
+    if (!H.ff[c]) continue;
+    const int r = H.rank[c];
+    if (!H.identity_proj) {
+      GemmItem& a = p.xproj.item(P, int(nrhs), P, int(nrhs));
+      GemmBatch::set_out(a, 0, xtil + poff[c], P, false);
+      p.xproj.seg(proj + H.proj_off[c], r, true, xhat + hoff[c], r, false, r);
+    }
+    GemmItem& it = p.coup.item(P, int(nrhs), P, int(nrhs));
+    GemmBatch::set_out(it, 0, ytil + til_off[c], P, false);
+    for (int32_t s : farOf[c])
+      p.coup.seg_gen(nodes + c * i64(P) * dim, nodes + s * i64(P) * dim, false, xtil + til_off[s], P,
+                     false, P);
+    if (!H.identity_proj) {
+      GemmItem& b = p.yproj.item(r, int(nrhs), r, int(nrhs));
+      GemmBatch::set_out(b, 0, yhat + hoff[c], r, false);
+      p.yproj.seg(proj + H.proj_off[c], r, false, ytil + poff[c], P, false, P);
+    }
+  }
+  p.xproj.finalize();
+  p.coup.finalize();
+  p.yproj.finalize();
+  // downward pass: yhat_c += T_c yhat_father (levels L-1 .. 0)
+  p.down.resize(L + 1);
+  for (int k = L - 1; k >= 0; --k) {
+    p.down[k].mode = GEMM_ADD;
+    const i64 f = tr.first_at_level(k), cnt = tr.count_at_level(k);
+    for (i64 c = f; c < f + cnt; ++c) {
+      if (!H.ff[c] || !H.ff[(c - 1) / 2]) continue;
+      const int r = H.rank[c], rp = H.rank[(c - 1) / 2];
+      GemmItem& it = p.down[k].item(r, int(nrhs), r, int(nrhs));
+      GemmBatch::set_out(it, 0, yhat + hoff[c], r, false);
+      p.down[k].seg(transfer + H.transfer_off[c], r, false, yhat + hoff[(c - 1) / 2], rp, false, rp);
+    }
+    p.down[k].finalize();
+  }
+  p.leafout.mode = GEMM_ADD;
+  for (i64 t = f0; t < f0 + c0; ++t) {
+    if (!H.ff[t]) continue;
+    const int r = H.rank[t];
+    GemmItem& it = p.leafout.item(int(tr.size[t]), int(nrhs), int(tr.size[t]), int(nrhs));
+    GemmBatch::set_out(it, 0, yt + tr.start[t], n, false);
+    p.leafout.seg(basis + H.basis_off[t], int(tr.size[t]), false, yhat + hoff[t], r, false, r);
+  }
+  p.leafout.finalize();
+  return mp;
+}
+
+// y_tree = A_H2 x_tree on plan buffers (x in p.xt, result in p.yt).
+void run_matvec_tree(const h2_matrix& H, MatvecPlan& p, hipStream_t st) {
+  const int dim = H.tree.dim;
+  const double sc = H.scale, dg = H.diag;
+  p.close.launch<double>(st, dim, sc, dg);
+  for (int k = 0; k <= H.tree.depth; ++k) p.up[k].launch<double>(st, dim, sc, dg);
+  p.xproj.launch<double>(st, dim, sc, dg);
+  p.coup.launch<double>(st, dim, sc, dg);
+  p.yproj.launch<double>(st, dim, sc, dg);
+  for (int k = H.tree.depth - 1; k >= 0; --k) p.down[k].launch<double>(st, dim, sc, dg);
+  p.leafout.launch<double>(st, dim, sc, dg);
+}
+
+MatvecPlan& matvec_plan(const h2_matrix& H, i64 nrhs);
+
+}  // namespace h2
+
+// The plan cache lives beside the handle (one plan per right-hand-side count).
+static std::unordered_map<const h2_matrix*, std::unique_ptr<h2::MatvecPlan>> g_mv_plans;
+
+h2::MatvecPlan& h2::matvec_plan(const h2_matrix& H, i64 nrhs) {
+  auto& slot = g_mv_plans[&H];
+  if (!slot || slot->nrhs != nrhs) {
+    slot.reset();
+    slot = make_matvec_plan(const_cast<h2_matrix&>(H), nrhs);
+  }
+  return *slot;
+}
+
+void h2_matrix_release_plans(const h2_matrix* H) { g_mv_plans.erase(H); }
+
+// ---------------------------------------------------------------- C ABI
+namespace h2 {
+std::string& last_error();
+int status_of(const Error& e);
+}  // namespace h2
+
+#define H2_API_BEGIN try {
+#define H2_API_END                                             \
+  return H2_OK;                                                \
+  }                                                            \
+  catch (const h2::Error& e) {                                 \
+    h2::last_error() = e.msg;                                  \
+    return e.code;                                             \
+  }                                                            \
+  catch (const std::bad_alloc&) {                              \
+    h2::last_error() = "host allocation failed";               \
+    return H2_ENOMEM;                                          \
+  }                                                            \
+  catch (const std::exception& e) {                            \
+    h2::last_error() = e.what();                               \
+    return H2_EINVAL;                                          \
+  }
+
+extern "C" int h2_build(const double* pts, int64_t n, int dim, const h2_kernel* kernel,
+                        const h2_build_opts* opts, h2_matrix** out) {
+  H2_API_BEGIN
+  if (!out) fail(H2_EINVAL, "null output handle");
+  *out = nullptr;
+  validate(pts, n, dim, kernel, opts);
+  auto H = std::make_unique<h2_matrix>();
+  fill_structure(*H, pts, n, dim, *kernel, *opts);
+  check_duplicates(*H);
+  if (opts->recompress_tol > 0 && opts->rank_cap < 0) fail(H2_EINVAL, "rank_cap must be >= 0");
+  build_chebyshev(*H, opts->recompress_tol, opts->rank_cap);
+  *out = H.release();
+  H2_API_END
+}
+
+extern "C" int h2_import(const double* pts, int64_t n, int dim, const h2_kernel* kernel,
+                         const h2_build_opts* opts, const int32_t* rank, const double* nodes,
+                         const double* proj, const double* leaf_basis, const double* transfer,
+                         h2_matrix** out) {
+  H2_API_BEGIN
+  if (!out) fail(H2_EINVAL, "null output handle");
+  *out = nullptr;
+  validate(pts, n, dim, kernel, opts);
+  if (!rank || !nodes || !proj || !leaf_basis || !transfer) fail(H2_EINVAL, "null coefficient array");
+  auto H = std::make_unique<h2_matrix>();
+  fill_structure(*H, pts, n, dim, *kernel, *opts);
+  check_duplicates(*H);
+  const Tree& tr = H->tree;
+  const i64 ncl = tr.ncl();
+  const int P = H->P;
+  H->rank.assign(rank, rank + ncl);
+  for (i64 c = 0; c < ncl; ++c) {
+    if ((H->rank[c] > 0) != bool(H->ff[c])) fail(H2_EINVAL, "rank > 0 must hold exactly for clusters with farfield");
+    if (H->rank[c] > 64 || H->rank[c] < 0) fail(H2_EUNSUPPORTED, "rank must be in [0, 64]");
+  }
+  std::copy(nodes, nodes + size_t(ncl) * P * dim, H->nodes.begin());
+  H->proj_off.assign(ncl, -1);
+  H->basis_off.assign(ncl, -1);
+  H->transfer_off.assign(ncl, -1);
+  i64 po = 0, bo = 0, to = 0;
+  for (i64 c = 0; c < ncl; ++c) {
+    if (!H->ff[c]) continue;
+    H->proj_off[c] = po;
+    po += i64(H->rank[c]) * P;
+    if (tr.is_leaf(c)) {
+      H->basis_off[c] = bo;
+      bo += tr.size[c] * H->rank[c];
+    }
+    if (c > 0 && H->ff[(c - 1) / 2]) {
+      H->transfer_off[c] = to;
+      to += i64(H->rank[c]) * H->rank[(c - 1) / 2];
+    }
+  }
+  H->proj.assign(proj, proj + po);
+  H->basis.assign(leaf_basis, leaf_basis + bo);
+  H->transfer.assign(transfer, transfer + to);
+  H->identity_proj = false;
+  *out = H.release();
+  H2_API_END
+}
+
+extern "C" int h2_matrix_info(const h2_matrix* h, int* depth, int64_t* ncl, int* cheb_points) {
+  H2_API_BEGIN
+  if (!h) fail(H2_EINVAL, "null handle");
+  if (depth) *depth = h->tree.depth;
+  if (ncl) *ncl = h->tree.ncl();
+  if (cheb_points) *cheb_points = h->P;
+  H2_API_END
+}
+
+extern "C" int h2_matrix_export_tree(const h2_matrix* h, int64_t* perm, int32_t* rank) {
+  H2_API_BEGIN
+  if (!h) fail(H2_EINVAL, "null handle");
+  if (perm) std::copy(h->tree.perm.begin(), h->tree.perm.end(), perm);
+  if (rank) std::copy(h->rank.begin(), h->rank.end(), rank);
+  H2_API_END
+}
+
+extern "C" int h2_matvec(const h2_matrix* h, const double* x, double* y, int64_t nrhs, int64_t ld) {
+  H2_API_BEGIN
+  if (!h || !x || !y) fail(H2_EINVAL, "null argument");
+  if (nrhs < 1 || ld < h->tree.n) fail(H2_EINVAL, "bad nrhs / ld");
+  const i64 n = h->tree.n;
+  MatvecPlan& p = matvec_plan(*h, nrhs);
+  hipStream_t st = current_stream();
+  launch_gather_rows<double>(x, ld, h->d_perm.as<i64>(), p.xt.as<double>(), n, n, nrhs, st);
+  run_matvec_tree(*h, p, st);
+  launch_scatter_rows(p.yt.as<double>(), n, h->d_perm.as<i64>(), y, ld, n, nrhs, st);
+  HIPCHECK(hipGetLastError());
+  H2_API_END
+}
+
+extern "C" void h2_matrix_destroy(h2_matrix* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(current_stream());
+  h2_matrix_release_plans(h);
+  delete h;
+}
+
+namespace h2 {
+struct MatvecPlanView {
+  double* xt;
+  double* yt;
+};
+MatvecPlanView matvec_buffers(MatvecPlan& p) { return {p.xt.as<double>(), p.yt.as<double>()}; }
+}  // namespace h2

@@ -1,0 +1,282 @@
+// Solve of A x = b through S y = U^T b, x = V y (eq. sp0), with the block
+// ILU(0) of S as the S-solver and iterative refinement against the FP64 H^2
+// matrix-vector product:  x += V (L D L^T)^{-1} U^T r,  r = b - A_H2 x.
+//
+// U^T sweep (leaves -> root): w = Q_t^T z_t, rows k_t.. go to y (S order),
+// rows ..k_t to the father's z.  V sweep (root -> leaves): z_t = Q_t [z_t^b; y_t].
+// Triangular solves by the levels of the elimination DAG: forward
+// u_i = r_i - sum_k Z_ki^T u_k, diagonal v_i = D_i^{-1} u_i, backward
+// x_i = v_i - sum_j Z_ij x_j.
+#include <algorithm>
+#include <cmath>
+
+#include "factor.h"
+
+namespace h2 {
+
+struct MatvecPlan;
+MatvecPlan& matvec_plan(const h2_matrix& H, i64 nrhs);
+void run_matvec_tree(const h2_matrix& H, MatvecPlan& p, hipStream_t st);
+struct MatvecPlanView {
+  double* xt;
+  double* yt;
+};
+MatvecPlanView matvec_buffers(MatvecPlan& p);
+
+template <class T>
+static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
+  h2_sparse& sp = *f.sp;
+  h2_matrix& H = *sp.H;
+  const Tree& tr = H.tree;
+  const i64 n = tr.n, ncl = sp.ncl;
+  const int L = tr.depth;
+  auto p = std::make_unique<SolvePlan>();
+  p->nrhs = nrhs;
+  const auto& na = sp.n_act;
+  const auto& kp = sp.kept;
+  const auto& mb = sp.nonbasis;
+  // z slots for non-leaf clusters
+  std::vector<i64> zoff(ncl, -1);
+  i64 zs = 0;
+  for (i64 c = 0; c < tr.first_at_level(0); ++c)
+    if (na[c] > 0) {
+      zoff[c] = zs;
+      zs += na[c] * nrhs;
+    }
+  p->zin.reset(sizeof(T) * n * nrhs);       // right-hand side in tree order (leaf z)
+  p->zbuf.reset(sizeof(T) * std::max<i64>(zs, 1));
+  p->y.reset(sizeof(T) * n * nrhs);
+  p->w.reset(sizeof(T) * n * nrhs);
+  p->rs.reset(sizeof(double) * n * nrhs);
+  p->colscale.reset(sizeof(double) * nrhs);
+  T* zin = p->zin.as<T>();
+  T* zb = p->zbuf.as<T>();
+  T* y = p->y.as<T>();
+  T* w = p->w.as<T>();
+  const T* Q = (sp.precision == H2_MIXED) ? sp.dQt.as<T>() : reinterpret_cast<const T*>(sp.dQ.as<double>());
+  const T* S = sp.dS.as<T>();
+  const T* Inv = f.dInv.as<T>();
+  auto son_off = [&](i64 c) -> i64 { return (c % 2 == 1) ? 0 : kp[c - 1]; };
+  auto zslot = [&](i64 c, i64* ld) -> T* {
+    if (tr.is_leaf(c)) {
+      *ld = n;
+      return zin + tr.start[c];
+    }
+    *ld = na[c];
+    return zb + zoff[c];
+  };
+  const int N = int(nrhs);
+  // U^T sweep: per level
+  p->up.resize(L + 1);
+  for (int k = 0; k <= L; ++k) {
+    for (i64 c = tr.first_at_level(k); c < tr.first_at_level(k) + tr.count_at_level(k); ++c) {
+      if (na[c] == 0) continue;
+      GemmItem& it = p->up[k].item(int(na[c]), N, int(kp[c]), N);
+      if (kp[c] > 0) {
+        i64 ldf;
+        T* zf = zslot((c - 1) / 2, &ldf);
+        GemmBatch::set_out(it, 0, zf + son_off(c), ldf, false);
+      }
+      if (mb[c] > 0) GemmBatch::set_out(it, 2, y + sp.soff[c], n, false);
+      i64 ldz;
+      T* zc = zslot(c, &ldz);
+      p->up[k].seg(Q + sp.q_off[c], int(na[c]), true, zc, int(ldz), false, int(na[c]));
+    }
+    p->up[k].finalize();
+  }
+  // forward and backward triangular solves by DAG level
+  std::vector<std::vector<i64>> fl(f.nflev), bl(f.nblev);
+  for (i64 pos : f.rows) {
+    fl[f.flev[pos]].push_back(pos);
+    bl[f.blev[pos]].push_back(pos);
+  }
+  std::vector<std::vector<i64>> colblk(ncl);  // per S position: blocks (k, i) above the diagonal
+  for (i64 pos : f.rows)
+    for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) colblk[sp.spos[sp.colidx[b]]].push_back(b);
+  auto row_of_block = [&](i64 b) {
+    return i64(std::upper_bound(sp.rowptr.begin(), sp.rowptr.end(), b) - sp.rowptr.begin() - 1);
+  };
+  p->fwd.resize(f.nflev);
+  for (int lv = 0; lv < f.nflev; ++lv) {
+    GemmBatch& g = p->fwd[lv];
+    g.mode = GEMM_SUB;
+    for (i64 pos : fl[lv]) {
+      if (colblk[pos].empty()) continue;
+      const i64 ci = sp.order[pos];
+      GemmItem& it = g.item(int(mb[ci]), N, int(mb[ci]), N);
+      GemmBatch::set_out(it, 0, y + sp.soff[ci], n, false);
+      for (i64 b : colblk[pos]) {
+        const i64 ck = sp.order[row_of_block(b)];
+        g.seg(S + sp.blk_off[b], int(mb[ck]), true, y + sp.soff[ck], int(n), false, int(mb[ck]));
+      }
+    }
+    g.finalize();
+  }
+  for (i64 pos : f.rows) {
+    const i64 c = sp.order[pos];
+    GemmItem& it = p->diag.item(int(mb[c]), N, int(mb[c]), N);
+    GemmBatch::set_out(it, 0, w + sp.soff[c], n, false);
+    p->diag.seg(Inv + f.inv_off[pos], int(mb[c]), false, y + sp.soff[c], int(n), false, int(mb[c]));
+  }
+  p->diag.finalize();
+  p->bwd.resize(f.nblev);
+  for (int lv = 0; lv < f.nblev; ++lv) {
+    GemmBatch& g = p->bwd[lv];
+    g.mode = GEMM_SUB;
+    for (i64 pos : bl[lv]) {
+      const i64 ci = sp.order[pos];
+      if (sp.rowptr[pos] + 1 == sp.rowptr[pos + 1]) continue;
+      GemmItem& it = g.item(int(mb[ci]), N, int(mb[ci]), N);
+      GemmBatch::set_out(it, 0, w + sp.soff[ci], n, false);
+      for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) {
+        const i64 cj = sp.colidx[b];
+        g.seg(S + sp.blk_off[b], int(mb[ci]), false, w + sp.soff[cj], int(n), false, int(mb[cj]));
+      }
+    }
+    g.finalize();
+  }
+  // V sweep: per level from the root
+  p->down.resize(L + 1);
+  for (int k = L; k >= 0; --k) {
+    for (i64 c = tr.first_at_level(k); c < tr.first_at_level(k) + tr.count_at_level(k); ++c) {
+      if (na[c] == 0) continue;
+      i64 ldz;
+      T* zc = zslot(c, &ldz);
+      GemmItem& it = p->down[k].item(int(na[c]), N, int(na[c]), N);
+      GemmBatch::set_out(it, 0, zc, ldz, false);
+      if (kp[c] > 0) {
+        i64 ldf;
+        T* zf = zslot((c - 1) / 2, &ldf);
+        p->down[k].seg(Q + sp.q_off[c], int(na[c]), false, zf + son_off(c), int(ldf), false, int(kp[c]));
+      }
+      if (mb[c] > 0)
+        p->down[k].seg(Q + sp.q_off[c] + kp[c] * na[c], int(na[c]), false, w + sp.soff[c], int(n), false,
+                       int(mb[c]));
+    }
+    p->down[k].finalize();
+  }
+  for (auto& g : p->up) g.drop_host();
+  for (auto& g : p->down) g.drop_host();
+  for (auto& g : p->fwd) g.drop_host();
+  for (auto& g : p->bwd) g.drop_host();
+  p->diag.drop_host();
+  HIPCHECK(hipStreamSynchronize(current_stream()));
+  return p;
+}
+
+// zin (tree order, T) holds the right-hand side; on return zin holds
+// V (L D L^T)^{-1} U^T zin in tree order.
+template <class T>
+static void apply_tree(h2_factor& f, SolvePlan& p, hipStream_t st) {
+  const int L = f.sp->H->tree.depth, dim = f.sp->H->tree.dim;
+  for (int k = 0; k <= L; ++k) p.up[k].launch<T>(st, dim, 0, 0);
+  for (int lv = 0; lv < f.nflev; ++lv) p.fwd[lv].launch<T>(st, dim, 0, 0);
+  p.diag.launch<T>(st, dim, 0, 0);
+  for (int lv = 0; lv < f.nblev; ++lv) p.bwd[lv].launch<T>(st, dim, 0, 0);
+  for (int k = L; k >= 0; --k) p.down[k].launch<T>(st, dim, 0, 0);
+}
+
+SolvePlan& solve_plan(h2_factor& f, i64 nrhs) {
+  if (!f.solve || f.solve->nrhs != nrhs) {
+    f.solve.reset();
+    if (f.sp->precision == H2_MIXED) f.solve = make_solve_plan<float>(f, nrhs);
+    else f.solve = make_solve_plan<double>(f, nrhs);
+  }
+  return *f.solve;
+}
+
+// x_acc (original order, ld) += V (LDL^T)^{-1} U^T r, r in tree order (FP64, ld n)
+static void correction(h2_factor& f, SolvePlan& p, const double* r_tree, double* x, i64 ldx,
+                       const double* colscale_dev, hipStream_t st) {
+  h2_matrix& H = *f.sp->H;
+  const i64 n = H.tree.n, nrhs = p.nrhs;
+  if (f.sp->precision == H2_MIXED) {
+    launch_scale_to_f(r_tree, colscale_dev, p.zin.as<float>(), n, nrhs, st);
+    apply_tree<float>(f, p, st);
+    launch_add_scaled_f(p.zin.as<float>(), colscale_dev, p.rs.as<double>(), n, n, nrhs, st);
+  } else {
+    launch_copy_cols(r_tree, n, p.zin.as<double>(), n, n, nrhs, st);
+    apply_tree<double>(f, p, st);
+    launch_add(p.zin.as<double>(), p.rs.as<double>(), n, n, nrhs, st);
+  }
+  (void)x;
+  (void)ldx;
+}
+
+}  // namespace h2
+
+using namespace h2;
+
+// One preconditioner application in original order: x = V (LDL^T)^{-1} U^T b.
+int apply_inverse_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld) {
+  h2_matrix& H = *f->sp->H;
+  const i64 n = H.tree.n;
+  hipStream_t st = current_stream();
+  SolvePlan& p = solve_plan(*f, nrhs);
+  DeviceBuffer rt(sizeof(double) * n * nrhs), ones(sizeof(double) * nrhs);
+  launch_fill(ones.as<double>(), nrhs, 1.0, st);
+  launch_gather_rows<double>(b, ld, H.d_perm.as<i64>(), rt.as<double>(), n, n, nrhs, st);
+  launch_fill(p.rs.as<double>(), n * nrhs, 0.0, st);
+  correction(*f, p, rt.as<double>(), nullptr, 0, ones.as<double>(), st);
+  launch_scatter_rows(p.rs.as<double>(), n, H.d_perm.as<i64>(), x, ld, n, nrhs, st);
+  HIPCHECK(hipStreamSynchronize(st));
+  return H2_OK;
+}
+
+// Iterative refinement.  x accumulates in tree order (p.rs), r = b - A_H2 x.
+int solve_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld, const h2_solve_opts* o,
+               h2_solve_info* info) {
+  h2_matrix& H = *f->sp->H;
+  const i64 n = H.tree.n;
+  hipStream_t st = current_stream();
+  SolvePlan& p = solve_plan(*f, nrhs);
+  MatvecPlan& mv = matvec_plan(H, nrhs);
+  MatvecPlanView mvb = matvec_buffers(mv);
+  DeviceBuffer bt(sizeof(double) * n * nrhs), rt(sizeof(double) * n * nrhs), nrm(sizeof(double) * 2 * nrhs),
+      cs(sizeof(double) * nrhs);
+  launch_gather_rows<double>(b, ld, H.d_perm.as<i64>(), bt.as<double>(), n, n, nrhs, st);
+  launch_copy_cols(bt.as<double>(), n, rt.as<double>(), n, n, nrhs, st);
+  launch_fill(p.rs.as<double>(), n * nrhs, 0.0, st);
+  std::vector<double> h_nrm(2 * nrhs), h_cs(nrhs);
+  // column norms of b for the first scaling
+  launch_fill(mvb.yt, n * nrhs, 0.0, st);
+  launch_residual(bt.as<double>(), n, mvb.yt, n, rt.as<double>(), n, nrhs, nrm.as<double>(), st);
+  HIPCHECK(hipMemcpyAsync(h_nrm.data(), nrm.ptr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  std::vector<double> bnorm(nrhs);
+  for (i64 j = 0; j < nrhs; ++j) bnorm[j] = std::sqrt(h_nrm[nrhs + j]);
+  const double tol = o ? o->tol : 1e-10;
+  const int max_iter = o ? std::max(1, o->max_iter) : 30;
+  double res = 0;
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    for (i64 j = 0; j < nrhs; ++j) {
+      const double rn = std::sqrt(h_nrm[j]);
+      h_cs[j] = rn > 0 ? rn : 1.0;
+    }
+    HIPCHECK(hipMemcpyAsync(cs.ptr, h_cs.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    correction(*f, p, rt.as<double>(), nullptr, 0, cs.as<double>(), st);
+    // r = b - A x  (x = p.rs in tree order)
+    launch_copy_cols(p.rs.as<double>(), n, mvb.xt, n, n, nrhs, st);
+    run_matvec_tree(H, mv, st);
+    launch_residual(bt.as<double>(), n, mvb.yt, n, rt.as<double>(), n, nrhs, nrm.as<double>(), st);
+    HIPCHECK(hipMemcpyAsync(h_nrm.data(), nrm.ptr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    res = 0;
+    for (i64 j = 0; j < nrhs; ++j)
+      res = std::max(res, bnorm[j] > 0 ? std::sqrt(h_nrm[j]) / bnorm[j] : 0.0);
+    if (!std::isfinite(res)) break;
+    if (res <= tol) break;
+  }
+  if (it > max_iter) it = max_iter;
+  launch_scatter_rows(p.rs.as<double>(), n, H.d_perm.as<i64>(), x, ld, n, nrhs, st);
+  HIPCHECK(hipStreamSynchronize(st));
+  if (info) {
+    info->iters = it;
+    info->max_rel_residual = res;
+  }
+  if (!(res <= tol)) return H2_ENOCONV;
+  return H2_OK;
+}
+
+h2_factor::~h2_factor() = default;

@@ -1,0 +1,61 @@
+// Sparsified form A = U S U^T of an H^2 matrix (U = V: symmetric kernel).
+#pragma once
+
+#include <unordered_map>
+
+#include "batch.h"
+#include "h2_internal.h"
+
+namespace h2 {
+
+struct QrLevel {
+  DeviceBuffer d_items;
+  int count = 0;
+  i64 q_begin = 0, q_end = 0;      // range of the level's Q blocks in the Q arena
+  i64 w_begin = 0, w_end = 0;      // range of the level's W blocks (coupling factors)
+};
+
+struct SweepLevel {
+  QrLevel qr;
+  GemmBatch stack;                 // R^_c T_c -> B of the father (FP64)
+  GemmBatch wproj;                 // W_t = R^_t P_t (FP64)
+  GemmBatch strips;                // G Q_p -> S block and carry
+  std::vector<GemmBatch> close1, close2;  // chunks: C Q_s, then Q_t^T (.)
+  std::vector<GemmBatch> coup1, coup2;    // chunks: K W_b^T, then W_a (.)
+  i64 gnext_entries = 0;           // entries of the next level's strip arena to clear
+  int gnext_side = 0;              // which of the two strip arenas is "next"
+};
+
+struct PlanCounts {
+  double flops_qr = 0, flops_close = 0, flops_coup = 0, flops_strip = 0, flops_misc = 0;
+  double bytes_qr = 0;
+};
+
+}  // namespace h2
+
+struct h2_sparse {
+  h2_matrix* H = nullptr;
+  int precision = H2_FP64;
+  h2::i64 ncl = 0;
+  std::vector<h2::i64> n_act, kept, nonbasis, soff, spos, order;
+  // upper block pattern of S: block rows = clusters in S order
+  std::vector<h2::i64> rowptr;     // by S position
+  std::vector<h2::i64> colidx;     // cluster ids (sorted by S position)
+  std::vector<h2::i64> blk_off;    // entry offset of each stored block
+  std::unordered_map<h2::i64, h2::i64> blk_index;  // t * ncl + s -> block number
+  h2::i64 s_entries = 0;
+  // arenas
+  std::vector<h2::i64> q_off, b_off, rhat_off, w_off;
+  h2::DeviceBuffer dQ, dQt, dB, dRhat, dW, dWt, dS, dC[2], dG[2], dTmp;
+  std::vector<h2::SweepLevel> levels;
+  h2::PlanCounts counts;
+  size_t elem = 8;                 // bytes per S / transform element
+  h2::i64 block_of(h2::i64 t, h2::i64 s) const {
+    auto it = blk_index.find(t * ncl + s);
+    return it == blk_index.end() ? -1 : it->second;
+  }
+};
+
+namespace h2 {
+void run_sparsify(h2_sparse& sp, hipStream_t st, double* phase_ms);
+}

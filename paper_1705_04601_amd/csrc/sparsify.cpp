@@ -1,0 +1,449 @@
+// Sparsification sweep (Section 2 "Compression at all levels", Algorithm 1 as
+// built from H^2 coefficients in Section 4.2-4.3), planned on the host and run
+// level by level on the device.
+//
+// Level k, for every cluster t on it (n_t active rows, k_t kept, m_t = n_t - k_t):
+//  1. B_t = R_t (leaf) or [R^_c1 T_c1; R^_c2 T_c2]; Householder QR B_t = Q_t [R^_t; 0]
+//     with explicit square Q_t (FP64, batched);
+//  2. every close pair (t, s) in N_k, t <= s: X = Q_t^T C_k(t,s) Q_s with
+//     C_0 = kernel block (generated in registers), C_k = block assembled at level
+//     k-1; X's four quadrants go to S (non-basis x non-basis), to the father's
+//     close block (basis x basis), and to the row strips of the finalised rows;
+//  3. every interaction pair (a, b) in I_k: R^_a D_ab R^_b^T into the father's
+//     close block (D_ab = P_a K(nodes_a, nodes_b) P_b^T);
+//  4. every strip G(tau, p) of rows finalised below level k: Y = G Q_p; the
+//     non-basis columns are the off-level block S(tau, p) (Section 3), the basis
+//     columns travel on to p's father.
+// S keeps its upper block triangle (S symmetric, Proposition 2.1): lower-level
+// rows first, clusters left to right.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+
+#include "sparse.h"
+
+namespace h2 {
+
+namespace {
+
+constexpr i64 kTmpChunkEntries = i64(1) << 26;  // GEMM temporaries per chunk
+
+inline i64 key(i64 a, i64 b, i64 ncl) { return a * ncl + b; }
+
+struct SymStrip {
+  int32_t tau, p;
+  i64 slot;
+};
+
+}  // namespace
+
+static h2_sparse* plan(h2_matrix* H, int precision) {
+  H->upload_all();
+  auto spp = std::make_unique<h2_sparse>();
+  h2_sparse& sp = *spp;
+  const Tree& tr = H->tree;
+  const int L = tr.depth, dim = tr.dim, P = H->P;
+  const i64 ncl = tr.ncl();
+  sp.H = H;
+  sp.precision = precision;
+  sp.ncl = ncl;
+  sp.elem = precision == H2_MIXED ? sizeof(float) : sizeof(double);
+
+  // ---- sizes n_t, k_t, m_t
+  sp.n_act.assign(ncl, 0);
+  sp.kept.assign(ncl, 0);
+  for (int k = 0; k <= L; ++k) {
+    const i64 f = tr.first_at_level(k), cnt = tr.count_at_level(k);
+    for (i64 c = f; c < f + cnt; ++c) {
+      sp.n_act[c] = (k == 0) ? tr.size[c] : sp.kept[2 * c + 1] + sp.kept[2 * c + 2];
+      sp.kept[c] = H->ff[c] ? std::min<i64>(sp.n_act[c], H->rank[c]) : 0;
+      if (sp.n_act[c] > 128) fail(H2_EUNSUPPORTED, "active cluster size above 128");
+      if (H->ff[c] && H->rank[c] > 64) fail(H2_EUNSUPPORTED, "rank above 64");
+    }
+  }
+  sp.nonbasis.resize(ncl);
+  for (i64 c = 0; c < ncl; ++c) sp.nonbasis[c] = sp.n_act[c] - sp.kept[c];
+  // ---- S order (level 0 first, left to right)
+  sp.order.clear();
+  for (int k = 0; k <= L; ++k)
+    for (i64 c = tr.first_at_level(k); c < tr.first_at_level(k) + tr.count_at_level(k); ++c)
+      sp.order.push_back(c);
+  sp.spos.assign(ncl, 0);
+  sp.soff.assign(ncl, 0);
+  i64 pos = 0;
+  for (i64 i = 0; i < ncl; ++i) {
+    sp.spos[sp.order[i]] = i;
+    sp.soff[sp.order[i]] = pos;
+    pos += sp.nonbasis[sp.order[i]];
+  }
+  if (pos != tr.n) fail(H2_EINVAL, "internal: non-basis rows do not add up to n");
+  const auto& n_act = sp.n_act;
+  const auto& kept = sp.kept;
+  const auto& mb = sp.nonbasis;
+  auto son_off = [&](i64 c) -> i64 { return (c % 2 == 1) ? 0 : kept[c - 1]; };
+
+  // ---- symbolic sweep: strips, close/coupling lists, C slots, S blocks
+  std::vector<std::vector<Pair>> closeL(L + 1), coupL(L + 1);
+  std::vector<std::vector<SymStrip>> stripL(L + 2);
+  std::vector<std::unordered_map<i64, i64>> cslot(L + 2), gslot(L + 2);
+  std::vector<i64> csize(L + 2, 0), gsize(L + 2, 0);
+  std::vector<std::pair<i64, i64>> blocks;  // (t, s) with spos(t) <= spos(s)
+  for (int k = 0; k <= L; ++k) {
+    auto add_strip = [&](i64 tau, i64 p) {
+      const i64 kk = key(tau, p, ncl);
+      if (gslot[k + 1].count(kk)) return;
+      gslot[k + 1][kk] = gsize[k + 1];
+      stripL[k + 1].push_back({int32_t(tau), int32_t(p), gsize[k + 1]});
+      gsize[k + 1] += mb[tau] * n_act[p];
+    };
+    for (const SymStrip& g : stripL[k]) {
+      if (mb[g.p] > 0) blocks.push_back({g.tau, g.p});
+      if (kept[g.p] > 0 && g.p > 0) add_strip(g.tau, (g.p - 1) / 2);
+    }
+    for (const Pair& pr : H->bt.near[k]) {
+      const i64 t = pr.t, s = pr.s;
+      if (t > s || n_act[t] == 0 || n_act[s] == 0) continue;
+      closeL[k].push_back(pr);
+      if (mb[t] > 0 && mb[s] > 0) blocks.push_back({t, s});
+      if (k < L) {
+        if (mb[t] > 0 && kept[s] > 0) add_strip(t, (s - 1) / 2);
+        if (t != s && mb[s] > 0 && kept[t] > 0) add_strip(s, (t - 1) / 2);
+      }
+    }
+    for (const Pair& pr : H->bt.far[k])
+      if (pr.t < pr.s) coupL[k].push_back(pr);
+    if (k < L)
+      for (const Pair& pr : H->bt.near[k + 1]) {
+        if (pr.t > pr.s || n_act[pr.t] == 0 || n_act[pr.s] == 0) continue;
+        cslot[k + 1][key(pr.t, pr.s, ncl)] = csize[k + 1];
+        csize[k + 1] += n_act[pr.t] * n_act[pr.s];
+      }
+  }
+  // ---- upper block pattern in S order
+  std::sort(blocks.begin(), blocks.end(), [&](const auto& a, const auto& b) {
+    return sp.spos[a.first] < sp.spos[b.first] ||
+           (sp.spos[a.first] == sp.spos[b.first] && sp.spos[a.second] < sp.spos[b.second]);
+  });
+  if (std::adjacent_find(blocks.begin(), blocks.end()) != blocks.end())
+    fail(H2_EINVAL, "internal: duplicate S block");
+  sp.rowptr.assign(ncl + 1, 0);
+  sp.colidx.resize(blocks.size());
+  sp.blk_off.resize(blocks.size());
+  sp.blk_index.reserve(blocks.size() * 2);
+  i64 ent = 0;
+  for (size_t b = 0; b < blocks.size(); ++b) {
+    const i64 t = blocks[b].first, s = blocks[b].second;
+    sp.rowptr[sp.spos[t] + 1]++;
+    sp.colidx[b] = s;
+    sp.blk_off[b] = ent;
+    sp.blk_index[key(t, s, ncl)] = i64(b);
+    ent += mb[t] * mb[s];
+  }
+  for (i64 i = 0; i < ncl; ++i) sp.rowptr[i + 1] += sp.rowptr[i];
+  sp.s_entries = ent;
+
+  // ---- arenas (level-contiguous so that one cast covers a level)
+  sp.q_off.assign(ncl, -1);
+  sp.b_off.assign(ncl, -1);
+  sp.rhat_off.assign(ncl, -1);
+  sp.w_off.assign(ncl, -1);
+  std::vector<i64> qlev(L + 2, 0), wlev(L + 2, 0);
+  i64 qs = 0, bs = 0, rs = 0, ws = 0;
+  for (int k = 0; k <= L; ++k) {
+    qlev[k] = qs;
+    wlev[k] = H->identity_proj ? rs : ws;
+    for (i64 c = tr.first_at_level(k); c < tr.first_at_level(k) + tr.count_at_level(k); ++c) {
+      if (n_act[c] == 0) continue;
+      sp.q_off[c] = qs;
+      qs += n_act[c] * n_act[c];
+      if (kept[c] > 0) {
+        if (k > 0) {
+          sp.b_off[c] = bs;
+          bs += n_act[c] * H->rank[c];
+        }
+        sp.rhat_off[c] = rs;
+        rs += kept[c] * H->rank[c];
+        if (!H->identity_proj) {
+          sp.w_off[c] = ws;
+          ws += kept[c] * P;
+        }
+      }
+    }
+    qlev[k + 1] = qs;
+    wlev[k + 1] = H->identity_proj ? rs : ws;
+  }
+  const bool mixed = precision == H2_MIXED;
+  const size_t el = sp.elem;
+  sp.dQ.reset(8 * std::max<i64>(qs, 1));
+  sp.dB.reset(8 * std::max<i64>(bs, 1));
+  sp.dRhat.reset(8 * std::max<i64>(rs, 1));
+  if (!H->identity_proj) sp.dW.reset(8 * std::max<i64>(ws, 1));
+  if (mixed) {
+    sp.dQt.reset(4 * std::max<i64>(qs, 1));
+    sp.dWt.reset(4 * std::max<i64>(H->identity_proj ? rs : ws, 1));
+  }
+  sp.dS.reset(el * std::max<i64>(ent, 1));
+  i64 cmax[2] = {1, 1}, gmax[2] = {1, 1};
+  for (int k = 0; k <= L + 1; ++k) {
+    cmax[k % 2] = std::max(cmax[k % 2], csize[k]);
+    gmax[k % 2] = std::max(gmax[k % 2], gsize[k]);
+  }
+  for (int side = 0; side < 2; ++side) {
+    sp.dC[side].reset(el * cmax[side]);
+    sp.dG[side].reset(el * gmax[side]);
+  }
+  sp.dTmp.reset(el * kTmpChunkEntries);
+
+  // ---- per-level work lists with device pointers
+  const double* X = H->d_x.as<double>();
+  const double* nodes = H->d_nodes.as<double>();
+  char* S = static_cast<char*>(sp.dS.ptr);
+  char* Qt = mixed ? static_cast<char*>(sp.dQt.ptr) : static_cast<char*>(sp.dQ.ptr);
+  char* Wt = mixed ? static_cast<char*>(sp.dWt.ptr)
+                   : static_cast<char*>(H->identity_proj ? sp.dRhat.ptr : sp.dW.ptr);
+  const std::vector<i64>& wtoff = H->identity_proj ? sp.rhat_off : sp.w_off;
+  char* tmp = static_cast<char*>(sp.dTmp.ptr);
+  double* dQ = sp.dQ.as<double>();
+  double* dB = sp.dB.as<double>();
+  double* dR = sp.dRhat.as<double>();
+  double* dW = sp.dW.as<double>();
+  const double* basis = H->d_basis.as<double>();
+  const double* transfer = H->d_transfer.as<double>();
+  const double* proj = H->d_proj.as<double>();
+  PlanCounts& pc = sp.counts;
+  sp.levels.resize(L + 1);
+  auto blk_ptr = [&](i64 t, i64 s) -> void* {
+    const i64 b = sp.block_of(t, s);
+    if (b < 0) fail(H2_EINVAL, "internal: missing S block");
+    return S + el * sp.blk_off[b];
+  };
+  for (int k = 0; k <= L; ++k) {
+    SweepLevel& lv = sp.levels[k];
+    char* Ccur = static_cast<char*>(sp.dC[k % 2].ptr);
+    char* Cnext = static_cast<char*>(sp.dC[(k + 1) % 2].ptr);
+    char* Gcur = static_cast<char*>(sp.dG[k % 2].ptr);
+    char* Gnext = static_cast<char*>(sp.dG[(k + 1) % 2].ptr);
+    lv.gnext_side = (k + 1) % 2;
+    lv.gnext_entries = (k < L) ? gsize[k + 1] : 0;
+    // 1. QR items
+    std::vector<QrItem> qi;
+    for (i64 c = tr.first_at_level(k); c < tr.first_at_level(k) + tr.count_at_level(k); ++c) {
+      if (n_act[c] == 0) continue;
+      QrItem it{};
+      it.n = int32_t(n_act[c]);
+      it.k = int32_t(kept[c]);
+      it.r = kept[c] > 0 ? H->rank[c] : 0;
+      it.Q = dQ + sp.q_off[c];
+      if (kept[c] > 0) {
+        it.B = (k == 0) ? basis + H->basis_off[c] : dB + sp.b_off[c];
+        it.Rhat = dR + sp.rhat_off[c];
+        const double n = it.n, r = it.r, q = std::min(it.n, it.r);
+        pc.flops_qr += 2 * n * r * r - 2.0 / 3 * r * r * r + 4 * n * n * q - 4 * n * q * q + 4.0 / 3 * q * q * q;
+        pc.bytes_qr += 8 * (n * r + n * n + double(it.k) * r);
+      } else {
+        pc.bytes_qr += 8.0 * it.n * it.n;
+      }
+      qi.push_back(it);
+    }
+    lv.qr.count = int(qi.size());
+    lv.qr.d_items = upload(qi);
+    lv.qr.q_begin = qlev[k];
+    lv.qr.q_end = qlev[k + 1];
+    lv.qr.w_begin = wlev[k];
+    lv.qr.w_end = wlev[k + 1];
+    // 2. stack into the father's B, and W = R^ P
+    for (i64 c = tr.first_at_level(k); c < tr.first_at_level(k) + tr.count_at_level(k); ++c) {
+      if (kept[c] == 0) continue;
+      const int r = H->rank[c];
+      if (c > 0 && kept[(c - 1) / 2] > 0) {
+        const i64 f = (c - 1) / 2;
+        const int rf = H->rank[f];
+        GemmItem& it = lv.stack.item(int(kept[c]), rf, int(kept[c]), rf);
+        GemmBatch::set_out(it, 0, dB + sp.b_off[f] + son_off(c), n_act[f], false);
+        lv.stack.seg(dR + sp.rhat_off[c], int(kept[c]), false, transfer + H->transfer_off[c], r, false, r);
+      }
+      if (!H->identity_proj) {
+        GemmItem& it = lv.wproj.item(int(kept[c]), P, int(kept[c]), P);
+        GemmBatch::set_out(it, 0, dW + sp.w_off[c], kept[c], false);
+        lv.wproj.seg(dR + sp.rhat_off[c], int(kept[c]), false, proj + H->proj_off[c], r, false, r);
+      }
+    }
+    lv.stack.finalize();
+    lv.wproj.finalize();
+    pc.flops_misc += lv.stack.flops + lv.wproj.flops;
+    // 3. strips: G(tau, p) Q_p
+    for (const SymStrip& g : stripL[k]) {
+      const i64 tau = g.tau, p = g.p;
+      GemmItem& it = lv.strips.item(int(mb[tau]), int(n_act[p]), 0, int(kept[p]));
+      if (mb[p] > 0) GemmBatch::set_out(it, 3, blk_ptr(tau, p), mb[tau], false);
+      if (kept[p] > 0 && p > 0) {
+        const i64 f = (p - 1) / 2;
+        const i64 slot = gslot[k + 1].at(key(tau, f, ncl));
+        GemmBatch::set_out(it, 2, Gnext + el * (slot + son_off(p) * mb[tau]), mb[tau], false);
+      }
+      lv.strips.seg(Gcur + el * g.slot, int(mb[tau]), false, Qt + el * sp.q_off[p], int(n_act[p]), false,
+                    int(n_act[p]));
+    }
+    lv.strips.finalize();
+    pc.flops_strip += lv.strips.flops;
+    // 4. close pairs, chunked by temporary space
+    {
+      i64 used = kTmpChunkEntries;
+      for (const Pair& pr : closeL[k]) {
+        const i64 t = pr.t, s = pr.s, nt = n_act[t], ns = n_act[s];
+        if (used + nt * ns > kTmpChunkEntries) {
+          lv.close1.emplace_back();
+          lv.close2.emplace_back();
+          used = 0;
+        }
+        GemmBatch& g1 = lv.close1.back();
+        GemmBatch& g2 = lv.close2.back();
+        char* w = tmp + el * used;
+        used += nt * ns;
+        GemmItem& a = g1.item(int(nt), int(ns), int(nt), int(ns));
+        GemmBatch::set_out(a, 0, w, nt, false);
+        if (k == 0)
+          g1.seg_gen(X + tr.start[t] * dim, X + tr.start[s] * dim, t == s, Qt + el * sp.q_off[s], int(ns), false,
+                     int(ns));
+        else
+          g1.seg(Ccur + el * cslot[k].at(key(t, s, ncl)), int(nt), false, Qt + el * sp.q_off[s], int(ns), false,
+                 int(ns));
+        GemmItem& b = g2.item(int(nt), int(ns), int(kept[t]), int(kept[s]));
+        if (mb[t] > 0 && mb[s] > 0) GemmBatch::set_out(b, 3, blk_ptr(t, s), mb[t], false);
+        if (k < L) {
+          const i64 pt = (t - 1) / 2, ps = (s - 1) / 2;
+          if (kept[t] > 0 && kept[s] > 0) {
+            char* cs = Cnext + el * cslot[k + 1].at(key(pt, ps, ncl));
+            GemmBatch::set_out(b, 0, cs + el * (son_off(t) + son_off(s) * n_act[pt]), n_act[pt], false);
+            if (pt == ps && t != s)
+              GemmBatch::set_out(b, 4, cs + el * (son_off(s) + son_off(t) * n_act[pt]), n_act[pt], true);
+          }
+          if (mb[t] > 0 && kept[s] > 0) {
+            const i64 slot = gslot[k + 1].at(key(t, ps, ncl));
+            GemmBatch::set_out(b, 2, Gnext + el * (slot + son_off(s) * mb[t]), mb[t], false);
+          }
+          if (t != s && mb[s] > 0 && kept[t] > 0) {
+            const i64 slot = gslot[k + 1].at(key(s, pt, ncl));
+            GemmBatch::set_out(b, 1, Gnext + el * (slot + son_off(t) * mb[s]), mb[s], true);
+          }
+        }
+        g2.seg(Qt + el * sp.q_off[t], int(nt), true, w, int(nt), false, int(nt));
+      }
+      for (auto& g : lv.close1) { g.finalize(); pc.flops_close += g.flops; }
+      for (auto& g : lv.close2) { g.finalize(); pc.flops_close += g.flops; }
+    }
+    // 5. couplings R^_a D_ab R^_b^T into the father's close block
+    {
+      i64 used = kTmpChunkEntries;
+      for (const Pair& pr : coupL[k]) {
+        const i64 a = pr.t, b = pr.s;
+        const i64 ka = kept[a], kb = kept[b];
+        if (ka == 0 || kb == 0) fail(H2_EINVAL, "internal: coupling of a cluster without kept rows");
+        if (used + P * kb > kTmpChunkEntries) {
+          lv.coup1.emplace_back();
+          lv.coup2.emplace_back();
+          used = 0;
+        }
+        GemmBatch& g1 = lv.coup1.back();
+        GemmBatch& g2 = lv.coup2.back();
+        char* w = tmp + el * used;
+        used += P * kb;
+        GemmItem& i1 = g1.item(P, int(kb), P, int(kb));
+        GemmBatch::set_out(i1, 0, w, P, false);
+        g1.seg_gen(nodes + a * i64(P) * dim, nodes + b * i64(P) * dim, false, Wt + el * wtoff[b], int(kb), true, P);
+        const i64 pa = (a - 1) / 2, pb = (b - 1) / 2;
+        GemmItem& i2 = g2.item(int(ka), int(kb), int(ka), int(kb));
+        char* cs = Cnext + el * cslot[k + 1].at(key(pa, pb, ncl));
+        GemmBatch::set_out(i2, 0, cs + el * (son_off(a) + son_off(b) * n_act[pa]), n_act[pa], false);
+        if (pa == pb)
+          GemmBatch::set_out(i2, 4, cs + el * (son_off(b) + son_off(a) * n_act[pa]), n_act[pa], true);
+        g2.seg(Wt + el * wtoff[a], int(ka), false, w, P, false, P);
+      }
+      for (auto& g : lv.coup1) { g.finalize(); pc.flops_coup += g.flops; }
+      for (auto& g : lv.coup2) { g.finalize(); pc.flops_coup += g.flops; }
+    }
+    // release host copies of the work lists
+    lv.stack.drop_host();
+    lv.wproj.drop_host();
+    lv.strips.drop_host();
+    for (auto& g : lv.close1) g.drop_host();
+    for (auto& g : lv.close2) g.drop_host();
+    for (auto& g : lv.coup1) g.drop_host();
+    for (auto& g : lv.coup2) g.drop_host();
+  }
+  HIPCHECK(hipStreamSynchronize(current_stream()));
+  return spp.release();
+}
+
+template <class T>
+static void run_levels(h2_sparse& sp, hipStream_t st, double* phase_ms) {
+  h2_matrix& H = *sp.H;
+  const int L = H.tree.depth, dim = H.tree.dim;
+  const double sc = H.scale, dg = H.diag;
+  const bool mixed = sp.precision == H2_MIXED;
+  std::vector<hipEvent_t> ev;
+  auto mark = [&]() {
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    HIPCHECK(hipEventRecord(e, st));
+    ev.push_back(e);
+  };
+  mark();
+  for (int k = 0; k <= L; ++k) {
+    SweepLevel& lv = sp.levels[k];
+    launch_qr(lv.qr.d_items.as<QrItem>(), lv.qr.count, st);
+    lv.stack.launch<double>(st, dim, sc, dg);
+    lv.wproj.launch<double>(st, dim, sc, dg);
+    if (mixed) {
+      launch_cast_d2f(sp.dQ.as<double>() + lv.qr.q_begin, sp.dQt.as<float>() + lv.qr.q_begin,
+                      lv.qr.q_end - lv.qr.q_begin, st);
+      const double* wsrc = H.identity_proj ? sp.dRhat.as<double>() : sp.dW.as<double>();
+      launch_cast_d2f(wsrc + lv.qr.w_begin, sp.dWt.as<float>() + lv.qr.w_begin, lv.qr.w_end - lv.qr.w_begin, st);
+    }
+    mark();  // QR phase end
+    if (lv.gnext_entries > 0) {
+      if (mixed) launch_fill_f(sp.dG[lv.gnext_side].as<float>(), lv.gnext_entries, 0.0f, st);
+      else launch_fill(sp.dG[lv.gnext_side].as<double>(), lv.gnext_entries, 0.0, st);
+    }
+    lv.strips.launch<T>(st, dim, sc, dg);
+    mark();  // strips end
+    for (size_t c = 0; c < lv.close1.size(); ++c) {
+      lv.close1[c].launch<T>(st, dim, sc, dg);
+      lv.close2[c].launch<T>(st, dim, sc, dg);
+    }
+    mark();  // close end
+    for (size_t c = 0; c < lv.coup1.size(); ++c) {
+      lv.coup1[c].launch<T>(st, dim, sc, dg);
+      lv.coup2[c].launch<T>(st, dim, sc, dg);
+    }
+    mark();  // couplings end
+  }
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipEventSynchronize(ev.back()));
+  double acc[4] = {0, 0, 0, 0};  // QR, strips, close, couplings
+  for (int k = 0; k <= L; ++k)
+    for (int ph = 0; ph < 4; ++ph) {
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, ev[4 * k + ph], ev[4 * k + ph + 1]));
+      acc[ph] += ms;
+    }
+  float tot = 0;
+  HIPCHECK(hipEventElapsedTime(&tot, ev.front(), ev.back()));
+  for (auto e : ev) (void)hipEventDestroy(e);
+  if (phase_ms) {
+    phase_ms[0] = acc[0];
+    phase_ms[1] = acc[2];
+    phase_ms[2] = acc[3];
+    phase_ms[3] = acc[1];
+    phase_ms[6] = tot;
+  }
+}
+
+void run_sparsify(h2_sparse& sp, hipStream_t st, double* phase_ms) {
+  if (sp.precision == H2_MIXED) run_levels<float>(sp, st, phase_ms);
+  else run_levels<double>(sp, st, phase_ms);
+}
+
+h2_sparse* plan_sparsify(h2_matrix* H, int precision) { return plan(H, precision); }
+
+}  // namespace h2
