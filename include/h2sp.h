@@ -188,6 +188,10 @@ void h2_factor_destroy(h2_factor* f);
  * [0] QR, [1] close transforms, [2] couplings, [3] strips, [4] factor pivots,
  * [5] factor Schur updates, [6] total.  Measured with HIP events. */
 int h2_last_timings(double* ms, int count);
+/* Algorithmic work of the last sparsify / factor call on this thread, same
+ * phase order as h2_last_timings: flop counts of the GEMMs and QRs as planned
+ * (2 m n k per product), [6] = bytes the QR phase must move at least. */
+int h2_last_work(double* work, int count);
 
 #ifdef __cplusplus
 }

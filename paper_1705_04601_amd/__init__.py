@@ -85,6 +85,7 @@ _SIGS = {
     "h2_sparse_destroy": (None, [_P]),
     "h2_factor_destroy": (None, [_P]),
     "h2_last_timings": (ctypes.c_int, [_DP, ctypes.c_int]),
+    "h2_last_work": (ctypes.c_int, [_DP, ctypes.c_int]),
 }
 
 
@@ -287,4 +288,10 @@ def h2_apply_inverse(f: H2FactorHandle, b, x):
 def h2_last_timings():
     out = np.zeros(8)
     _check(lib().h2_last_timings(_dptr(out), 8))
+    return out
+
+
+def h2_last_work():
+    out = np.zeros(8)
+    _check(lib().h2_last_work(_dptr(out), 8))
     return out

@@ -13,6 +13,7 @@ std::string& last_error() {
   return msg;
 }
 static thread_local double g_timings[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+static thread_local double g_work[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 }  // namespace h2
 
 int apply_inverse_impl(h2_factor* f, const double* b, double* x, h2::i64 nrhs, h2::i64 ld);
@@ -56,6 +57,12 @@ extern "C" int h2_sparsify(h2_matrix* h, const h2_sparsify_opts* opts, h2_sparse
   std::unique_ptr<h2_sparse> sp(plan_sparsify(h, prec));
   std::fill(g_timings, g_timings + 8, 0.0);
   run_sparsify(*sp, current_stream(), g_timings);
+  const PlanCounts& pc = sp->counts;
+  g_work[0] = pc.flops_qr + pc.flops_misc;
+  g_work[1] = pc.flops_close;
+  g_work[2] = pc.flops_coup;
+  g_work[3] = pc.flops_strip;
+  g_work[6] = pc.bytes_qr;
   HIPCHECK(hipStreamSynchronize(current_stream()));
   *out = sp.release();
   H2_API_END
@@ -123,6 +130,8 @@ extern "C" int h2_factor_S(h2_sparse* sp, h2_factor** out) {
   g_timings[4] = ph[4];
   g_timings[5] = ph[5];
   g_timings[7] = ph[6];
+  g_work[4] = f->flops_inv + f->flops_z;
+  g_work[5] = f->flops_schur;
   *out = f.release();
   H2_API_END
 }
@@ -152,6 +161,13 @@ extern "C" int h2_last_timings(double* ms, int count) {
   double tmp[8];
   std::copy(g_timings, g_timings + 8, tmp);
   for (int i = 0; i < count && i < 8; ++i) ms[i] = tmp[i];
+  H2_API_END
+}
+
+extern "C" int h2_last_work(double* work, int count) {
+  H2_API_BEGIN
+  if (!work) fail(H2_EINVAL, "null argument");
+  for (int i = 0; i < count && i < 8; ++i) work[i] = g_work[i];
   H2_API_END
 }
 

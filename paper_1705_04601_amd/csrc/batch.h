@@ -16,6 +16,7 @@ struct GemmBatch {
   std::vector<int32_t> tiles;
   DeviceBuffer d_items, d_segs, d_tiles;
   int mode = GEMM_STORE;
+  int role = ROLE_TRANSFORM;
   double flops = 0.0;  // algorithmic flops of the batch
 
   bool empty() const { return items.empty(); }
@@ -103,6 +104,7 @@ struct GemmBatch {
     g.tiles = d_tiles.as<int32_t>();
     g.ntiles = int32_t(tiles.size());
     g.mode = mode;
+    g.role = role;
     g.dim = dim;
     g.scale = scale;
     g.diag = diag;

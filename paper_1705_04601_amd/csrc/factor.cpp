@@ -73,6 +73,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     GemmBatch& zb = keep_z[lv];
     GemmBatch& sb = keep_s[lv];
     sb.mode = GEMM_SUB;
+    sb.role = ROLE_FACTOR;
+    zb.role = ROLE_FACTOR;
     std::vector<SchurRec> recs;
     i64 zoff = 0;
     for (i64 pk : piv) {

@@ -36,6 +36,9 @@ struct GemmItem {
 };
 
 enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1, GEMM_SUB = 2 };
+// The same kernel is instantiated once per role so that profiles separate the
+// sparsification transforms, the factorisation, the solve sweeps and the matvec.
+enum GemmRole { ROLE_TRANSFORM = 0, ROLE_FACTOR = 1, ROLE_SOLVE = 2, ROLE_MATVEC = 3 };
 
 struct GemmLaunch {
   const GemmItem* items;
@@ -43,6 +46,7 @@ struct GemmLaunch {
   const int32_t* tiles;   // per work-group: (item << 8) | (tile_row << 4) | tile_col
   int32_t ntiles;
   int mode;
+  int role;
   int dim;
   double scale, diag;
 };

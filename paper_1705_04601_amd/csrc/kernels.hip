@@ -53,7 +53,7 @@ __device__ __forceinline__ void store_out(const GemmItem& it, int q, int lr, int
   else *p -= v;
 }
 
-template <class T>
+template <class T, int ROLE>
 __global__ __launch_bounds__(64) void gemm_kernel(GemmLaunch g) {
   using V = typename Mfma<T>::V;
   __shared__ T As[KC][TM + 1];
@@ -407,7 +407,12 @@ int grid_for(int64_t n) {
 template <class T>
 void launch_gemm(const GemmLaunch& g, hipStream_t st) {
   if (g.ntiles <= 0) return;
-  hipLaunchKernelGGL(gemm_kernel<T>, dim3(g.ntiles), dim3(64), 0, st, g);
+  switch (g.role) {
+    case ROLE_FACTOR: hipLaunchKernelGGL((gemm_kernel<T, ROLE_FACTOR>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+    case ROLE_SOLVE: hipLaunchKernelGGL((gemm_kernel<T, ROLE_SOLVE>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+    case ROLE_MATVEC: hipLaunchKernelGGL((gemm_kernel<T, ROLE_MATVEC>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+    default: hipLaunchKernelGGL((gemm_kernel<T, ROLE_TRANSFORM>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+  }
 }
 template void launch_gemm<double>(const GemmLaunch&, hipStream_t);
 template void launch_gemm<float>(const GemmLaunch&, hipStream_t);

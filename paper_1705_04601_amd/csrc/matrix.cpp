@@ -196,6 +196,11 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
 
 // y_tree = A_H2 x_tree on plan buffers (x in p.xt, result in p.yt).
 void run_matvec_tree(const h2_matrix& H, MatvecPlan& p, hipStream_t st) {
+  if (p.close.role != ROLE_MATVEC) {
+    p.close.role = p.xproj.role = p.coup.role = p.yproj.role = p.leafout.role = ROLE_MATVEC;
+    for (auto& g : p.up) g.role = ROLE_MATVEC;
+    for (auto& g : p.down) g.role = ROLE_MATVEC;
+  }
   const int dim = H.tree.dim;
   const double sc = H.scale, dg = H.diag;
   p.close.launch<double>(st, dim, sc, dg);

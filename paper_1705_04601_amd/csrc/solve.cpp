@@ -155,6 +155,11 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
     }
     p->down[k].finalize();
   }
+  for (auto& g : p->up) g.role = ROLE_SOLVE;
+  for (auto& g : p->down) g.role = ROLE_SOLVE;
+  for (auto& g : p->fwd) g.role = ROLE_SOLVE;
+  for (auto& g : p->bwd) g.role = ROLE_SOLVE;
+  p->diag.role = ROLE_SOLVE;
   for (auto& g : p->up) g.drop_host();
   for (auto& g : p->down) g.drop_host();
   for (auto& g : p->fwd) g.drop_host();
