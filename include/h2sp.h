@@ -146,14 +146,20 @@ int h2_sparse_info(const h2_sparse* sp, int64_t* nnz_blocks, int64_t* nnz_entrie
 /*
  * HOST copies of the combinatorial output (bit-exact contract):
  *   n_act, kept, nonbasis [ncl]: n_t, k_t, m_t;  soff[ncl]: first row of
- *   cluster t in S;  rowptr[ncl+1], colidx[nnz_blocks]: upper block pattern,
- *   block rows = clusters in S order (level 0 first, left to right), column
- *   indices are cluster ids sorted by S order.
+ *   cluster t in S (S order: level 0 first, clusters left to right, the
+ *   permutations P_rk of Section 2);  elim[ncl]: clusters in the elimination
+ *   order of the factorisation (levels from the leaves up; inside a level by
+ *   greedy colour of the close graph, then cluster index; clusters without
+ *   non-basis rows last on their level);  rowptr[ncl+1], colidx[nnz_blocks]:
+ *   the stored upper block triangle in that order (block rows by elimination
+ *   position, column cluster ids sorted by elimination position).
+ * Any pointer may be NULL.
  */
 int h2_sparse_export_plan(const h2_sparse* sp, int64_t* n_act, int64_t* kept,
-                          int64_t* nonbasis, int64_t* soff, int64_t* rowptr,
-                          int64_t* colidx);
-/* HOST copy of block (t, s) of S (m_t x m_s column-major, FP64), t <= s in S order. */
+                          int64_t* nonbasis, int64_t* soff, int64_t* elim,
+                          int64_t* rowptr, int64_t* colidx);
+/* HOST copy of block (t, s) of S (m_t x m_s column-major, FP64) for any (t, s)
+ * in the pattern (either orientation); EINVAL when (t, s) is not in it. */
 int h2_sparse_export_block(const h2_sparse* sp, int64_t t, int64_t s, double* out);
 /* HOST copy of Q_t (n_t x n_t column-major, FP64). */
 int h2_sparse_export_q(const h2_sparse* sp, int64_t t, double* out);

@@ -26,7 +26,7 @@ from .householder import householder_qr
 from .sparsify import (Sparsified, sparsify, apply_ut, apply_v, dense_s, dense_u,
                        pattern_predicate, cluster_sizes)
 from .solve import (BlockILU0, dense_lu_solver, refine, rel_residual,
-                    conjugate_gradient)
+                    conjugate_gradient, elimination_order, elimination_colours)
 
 __all__ = [
     "ClusterTree", "BlockTree", "build_cluster_tree", "build_block_tree",
@@ -34,5 +34,5 @@ __all__ = [
     "kernel_block", "close_block", "householder_qr", "Sparsified", "sparsify",
     "apply_ut", "apply_v", "dense_s", "dense_u", "pattern_predicate",
     "cluster_sizes", "BlockILU0", "dense_lu_solver", "refine", "rel_residual",
-    "conjugate_gradient",
+    "conjugate_gradient", "elimination_order", "elimination_colours",
 ]

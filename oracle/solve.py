@@ -7,11 +7,17 @@ replaced by S y = U^T b and x = V y, S being handled by sparse tools (a
 sparse direct factorisation in Section 5.3-5.4, an incomplete factorisation
 used as a preconditioner in Section 5.5).  Readings used here:
 
-* the sparse factorisation is a block LU of S in S order restricted to the
-  block pattern of S (block ILU(0)): for every block row i, for every k < i
-  in row i (ascending), S_ik <- S_ik S_kk^{-1}, then S_ij -= S_ik S_kj for
-  every j > k in both rows; pivot blocks are handled by LU with partial
-  pivoting inside the block;
+* the sparse factorisation is a block LU of S restricted to the block
+  pattern of S (block ILU(0)) in an elimination order: for every block row
+  i, for every k before i in row i (in that order), S_ik <- S_ik S_kk^{-1},
+  then S_ij -= S_ik S_kj for every j after k in both rows; pivot blocks are
+  handled by LU with partial pivoting inside the block;
+* the elimination order (a sparse solver's own choice, as CHOLMOD's
+  reordering is in Section 5.3) is S order by default, or the multicolour
+  order of ``elimination_order``: tree levels from the leaves up and, inside
+  a level, clusters sorted by (greedy colour, index) where the colour of a
+  cluster is the smallest one not taken by an earlier close neighbour on its
+  level (rows of one colour share no block of S);
 * the residual is max over columns of ||b - A_H2 x||_2 / ||b||_2 with the
   H^2 matrix-vector product, and iterative refinement repeats
   x += V (LU_S)^{-1} U^T r until it drops below the tolerance.
@@ -25,12 +31,43 @@ import scipy.linalg as sla
 from .sparsify import Sparsified, apply_ut, apply_v, dense_s
 
 
-class BlockILU0:
-    """Block ILU(0) of S in S order (IKJ form)."""
+def elimination_colours(sp: Sparsified):
+    """Greedy colour of every cluster with m > 0 among its close neighbours on its level."""
+    tr = sp.h2.tree
+    colour = {}
+    for lev in range(tr.depth + 1):
+        nbrs = {}
+        for t, s in sp.h2.bt.near[lev]:
+            t, s = int(t), int(s)
+            if t != s and sp.nonbasis[t] > 0 and sp.nonbasis[s] > 0:
+                nbrs.setdefault(t, []).append(s)
+        for t in tr.clusters_at_level(lev):
+            t = int(t)
+            if sp.nonbasis[t] == 0:
+                continue
+            taken = {colour[s] for s in nbrs.get(t, []) if s < t}
+            c = 0
+            while c in taken:
+                c += 1
+            colour[t] = c
+    return colour
 
-    def __init__(self, sp: Sparsified):
+
+def elimination_order(sp: Sparsified):
+    """Multicolour elimination order: level by level, (greedy colour, cluster)."""
+    tr = sp.h2.tree
+    colour = elimination_colours(sp)
+    return sorted(colour, key=lambda u: (tr.level(u), colour[u], u))
+
+
+class BlockILU0:
+    """Block ILU(0) of S (IKJ form) in S order or in a given elimination order."""
+
+    def __init__(self, sp: Sparsified, order=None):
         self.sp = sp
-        order = [int(c) for c in sp.order if sp.nonbasis[c] > 0]
+        if order is None:
+            order = sp.order
+        order = [int(c) for c in order if sp.nonbasis[c] > 0]
         self.order = order
         self.pos = {c: i for i, c in enumerate(order)}
         rows = {c: [] for c in order}

@@ -74,7 +74,7 @@ _SIGS = {
     "h2_matvec": (ctypes.c_int, [_P, _P, _P, _I64, _I64]),
     "h2_sparsify": (ctypes.c_int, [_P, ctypes.POINTER(h2_sparsify_opts), ctypes.POINTER(_P)]),
     "h2_sparse_info": (ctypes.c_int, [_P, _I64P, _I64P]),
-    "h2_sparse_export_plan": (ctypes.c_int, [_P, _I64P, _I64P, _I64P, _I64P, _I64P, _I64P]),
+    "h2_sparse_export_plan": (ctypes.c_int, [_P, _I64P, _I64P, _I64P, _I64P, _I64P, _I64P, _I64P]),
     "h2_sparse_export_block": (ctypes.c_int, [_P, _I64, _I64, _DP]),
     "h2_sparse_export_q": (ctypes.c_int, [_P, _I64, _DP]),
     "h2_factor_S": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
@@ -239,13 +239,13 @@ def h2_sparse_info(sp: H2SparseHandle):
 def h2_sparse_export_plan(sp: H2SparseHandle):
     _, ncl, _ = h2_matrix_info(sp.keep)
     nb, _ = h2_sparse_info(sp)
-    arr = [np.zeros(ncl, dtype=np.int64) for _ in range(4)]
+    arr = [np.zeros(ncl, dtype=np.int64) for _ in range(5)]
     rowptr = np.zeros(ncl + 1, dtype=np.int64)
     colidx = np.zeros(max(nb, 1), dtype=np.int64)
     _check(lib().h2_sparse_export_plan(sp.ptr, *[a.ctypes.data_as(_I64P) for a in arr],
                                        rowptr.ctypes.data_as(_I64P), colidx.ctypes.data_as(_I64P)))
-    return dict(n_act=arr[0], kept=arr[1], nonbasis=arr[2], soff=arr[3], rowptr=rowptr,
-                colidx=colidx[:nb])
+    return dict(n_act=arr[0], kept=arr[1], nonbasis=arr[2], soff=arr[3], elim=arr[4],
+                rowptr=rowptr, colidx=colidx[:nb])
 
 
 def h2_sparse_export_block(sp: H2SparseHandle, t: int, s: int, mt: int, ms: int) -> np.ndarray:

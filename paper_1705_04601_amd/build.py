@@ -31,10 +31,10 @@ SOURCES = {
     "runtime.cpp": [],
     "tree.cpp": ["-ffp-contract=off"],
     "h2build.cpp": ["-fopenmp"],
-    "matrix.cpp": [],
-    "sparsify.cpp": [],
-    "factor.cpp": [],
-    "solve.cpp": [],
+    "matrix.cpp": ["-fopenmp"],
+    "sparsify.cpp": ["-fopenmp"],
+    "factor.cpp": ["-fopenmp"],
+    "solve.cpp": ["-fopenmp"],
     "api.cpp": [],
 }
 

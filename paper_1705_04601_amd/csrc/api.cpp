@@ -77,7 +77,7 @@ extern "C" int h2_sparse_info(const h2_sparse* sp, int64_t* nnz_blocks, int64_t*
 }
 
 extern "C" int h2_sparse_export_plan(const h2_sparse* sp, int64_t* n_act, int64_t* kept, int64_t* nonbasis,
-                                     int64_t* soff, int64_t* rowptr, int64_t* colidx) {
+                                     int64_t* soff, int64_t* elim, int64_t* rowptr, int64_t* colidx) {
   H2_API_BEGIN
   if (!sp) fail(H2_EINVAL, "null handle");
   auto cp = [](const std::vector<i64>& v, int64_t* dst) {
@@ -87,6 +87,7 @@ extern "C" int h2_sparse_export_plan(const h2_sparse* sp, int64_t* n_act, int64_
   cp(sp->kept, kept);
   cp(sp->nonbasis, nonbasis);
   cp(sp->soff, soff);
+  cp(sp->eorder, elim);
   cp(sp->rowptr, rowptr);
   cp(sp->colidx, colidx);
   H2_API_END
@@ -96,17 +97,23 @@ extern "C" int h2_sparse_export_block(const h2_sparse* sp, int64_t t, int64_t s,
   H2_API_BEGIN
   if (!sp || !out) fail(H2_EINVAL, "null argument");
   if (t < 0 || s < 0 || t >= sp->ncl || s >= sp->ncl) fail(H2_EINVAL, "cluster out of range");
-  const i64 b = sp->block_of(t, s);
-  if (b < 0) fail(H2_EINVAL, "block not stored (S keeps t <= s in S order)");
-  const i64 cnt = sp->nonbasis[t] * sp->nonbasis[s];
+  i64 b = sp->block_of(t, s);
+  const bool transposed = b < 0;
+  if (transposed) b = sp->block_of(s, t);
+  if (b < 0) fail(H2_EINVAL, "no such block in the pattern of S");
+  const i64 mt = sp->nonbasis[t], ms = sp->nonbasis[s], cnt = mt * ms;
   HIPCHECK(hipStreamSynchronize(current_stream()));
+  std::vector<double> tmp(cnt);
   if (sp->precision == H2_MIXED) {
-    std::vector<float> tmp(cnt);
-    HIPCHECK(hipMemcpy(tmp.data(), sp->dS.as<float>() + sp->blk_off[b], sizeof(float) * cnt, hipMemcpyDeviceToHost));
-    for (i64 i = 0; i < cnt; ++i) out[i] = tmp[i];
+    std::vector<float> tf(cnt);
+    HIPCHECK(hipMemcpy(tf.data(), sp->dS.as<float>() + sp->blk_off[b], sizeof(float) * cnt, hipMemcpyDeviceToHost));
+    for (i64 i = 0; i < cnt; ++i) tmp[i] = tf[i];
   } else {
-    HIPCHECK(hipMemcpy(out, sp->dS.as<double>() + sp->blk_off[b], sizeof(double) * cnt, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(tmp.data(), sp->dS.as<double>() + sp->blk_off[b], sizeof(double) * cnt, hipMemcpyDeviceToHost));
   }
+  // stored block is m_t x m_s (or m_s x m_t when transposed), column-major
+  for (i64 j = 0; j < ms; ++j)
+    for (i64 i = 0; i < mt; ++i) out[i + j * mt] = transposed ? tmp[j + i * ms] : tmp[i + j * mt];
   H2_API_END
 }
 

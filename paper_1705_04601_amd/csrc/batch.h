@@ -2,6 +2,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "h2_internal.h"
@@ -9,12 +10,17 @@
 
 namespace h2 {
 
-// Work list of one batched GEMM launch, kept on the device for replay.
+// Work list of one batched GEMM launch.  Built on the host, copied to the
+// device by upload_batches (one allocation for a whole plan), replayed as often
+// as the plan is run.
 struct GemmBatch {
   std::vector<GemmItem> items;
   std::vector<GemmSeg> segs;
   std::vector<int32_t> tiles;
-  DeviceBuffer d_items, d_segs, d_tiles;
+  const GemmItem* d_items = nullptr;
+  const GemmSeg* d_segs = nullptr;
+  const int32_t* d_tiles = nullptr;
+  int32_t ntiles = 0;
   int mode = GEMM_STORE;
   int role = ROLE_TRANSFORM;
   double flops = 0.0;  // algorithmic flops of the batch
@@ -75,8 +81,9 @@ struct GemmBatch {
     it.seg_end = int32_t(segs.size());
     flops += 2.0 * it.M * double(it.N) * s.K;
   }
-  // Builds the tile list and copies everything to the device.
-  void finalize() {
+  // Tile list: one 32 x 32 tile per work-group.  Items without segments are
+  // kept only when they store (they then write zeros).
+  void build_tiles() {
     tiles.clear();
     if (items.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "GEMM batch above 2^24 items");
     for (size_t i = 0; i < items.size(); ++i) {
@@ -86,23 +93,21 @@ struct GemmBatch {
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b) tiles.push_back(int32_t((uint32_t(i) << 8) | (a << 4) | b));
     }
-    d_items = upload(items);
-    d_segs = upload(segs);
-    d_tiles = upload(tiles);
+    ntiles = int32_t(tiles.size());
   }
-  // Releases the host copies once on the device.
   void drop_host() {
     std::vector<GemmItem>().swap(items);
     std::vector<GemmSeg>().swap(segs);
+    std::vector<int32_t>().swap(tiles);
   }
   template <class T>
   void launch(hipStream_t st, int dim, double scale, double diag) const {
-    if (tiles.empty()) return;
+    if (ntiles <= 0) return;
     GemmLaunch g{};
-    g.items = d_items.as<GemmItem>();
-    g.segs = d_segs.as<GemmSeg>();
-    g.tiles = d_tiles.as<int32_t>();
-    g.ntiles = int32_t(tiles.size());
+    g.items = d_items;
+    g.segs = d_segs;
+    g.tiles = d_tiles;
+    g.ntiles = ntiles;
     g.mode = mode;
     g.role = role;
     g.dim = dim;
@@ -111,5 +116,57 @@ struct GemmBatch {
     launch_gemm<T>(g, st);
   }
 };
+
+// Raw host arrays to place in the same device allocation as the batches.
+struct RawBlob {
+  const void* host;
+  size_t bytes;
+  const void** dev;   // receives the device address
+};
+
+// Builds the tile lists, copies every batch's items, segments and tiles (and the
+// extra blobs) into one device buffer `store`, and points the batches at it.
+// Synchronous: the host arrays may be released afterwards.
+inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& store,
+                           const std::vector<RawBlob>& extra = {}) {
+  auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t total = 0;
+  std::vector<size_t> off(bs.size() * 3);
+  for (size_t i = 0; i < bs.size(); ++i) {
+    bs[i]->build_tiles();
+    off[3 * i] = total;
+    total = align(total + bs[i]->items.size() * sizeof(GemmItem));
+    off[3 * i + 1] = total;
+    total = align(total + bs[i]->segs.size() * sizeof(GemmSeg));
+    off[3 * i + 2] = total;
+    total = align(total + bs[i]->tiles.size() * sizeof(int32_t));
+  }
+  std::vector<size_t> xoff(extra.size());
+  for (size_t i = 0; i < extra.size(); ++i) {
+    xoff[i] = total;
+    total = align(total + extra[i].bytes);
+  }
+  if (total == 0) return;
+  std::vector<char> staging(total);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long i = 0; i < long(bs.size()); ++i) {
+    GemmBatch& b = *bs[i];
+    if (!b.items.empty()) std::memcpy(&staging[off[3 * i]], b.items.data(), b.items.size() * sizeof(GemmItem));
+    if (!b.segs.empty()) std::memcpy(&staging[off[3 * i + 1]], b.segs.data(), b.segs.size() * sizeof(GemmSeg));
+    if (!b.tiles.empty()) std::memcpy(&staging[off[3 * i + 2]], b.tiles.data(), b.tiles.size() * sizeof(int32_t));
+  }
+  for (size_t i = 0; i < extra.size(); ++i)
+    if (extra[i].bytes) std::memcpy(&staging[xoff[i]], extra[i].host, extra[i].bytes);
+  store.reset(total);
+  HIPCHECK(hipMemcpy(store.ptr, staging.data(), total, hipMemcpyHostToDevice));
+  char* base = static_cast<char*>(store.ptr);
+  for (size_t i = 0; i < bs.size(); ++i) {
+    bs[i]->d_items = reinterpret_cast<const GemmItem*>(base + off[3 * i]);
+    bs[i]->d_segs = reinterpret_cast<const GemmSeg*>(base + off[3 * i + 1]);
+    bs[i]->d_tiles = reinterpret_cast<const int32_t*>(base + off[3 * i + 2]);
+    bs[i]->drop_host();
+  }
+  for (size_t i = 0; i < extra.size(); ++i) *extra[i].dev = base + xoff[i];
+}
 
 }  // namespace h2

@@ -1,16 +1,20 @@
 // Block ILU(0) of S restricted to its own block pattern (the sparse
 // factorisation step: a direct factorisation in Sections 5.3-5.4, an incomplete
 // one as preconditioner in Section 5.5), in the symmetric form
-// S ~ L D L^T, L^T_kj = Z_kj = D_k^{-1} S_kj (S is symmetric, Proposition 2.1).
+// S ~ L D L^T, L^T_kj = Z_kj = D_k^{-1} S_kj (S is symmetric, Proposition 2.1),
+// in the elimination order chosen at planning time (levels from the leaves up,
+// greedy colours inside a level, so that rows of one colour are independent).
 //
 // Right-looking, scheduled by the levels of the elimination DAG (pivot k waits
-// for every k' < k with S_k'k stored).  Per DAG level, on the device:
+// for every earlier k' with S_k'k stored).  Per DAG level, on the device:
 //   1. D_k^{-1} for every pivot of the level (FP64 Gauss-Jordan, pivoting);
 //   2. Z_kj = D_k^{-1} S_kj for the pivot rows (batched GEMM);
 //   3. S_ij -= S_ki^T Z_kj for every stored target (i <= j) reached from a
 //      pivot of the level, one work item per target, the pivots as K-segments
-//      in ascending order (no atomics: the result is deterministic);
+//      in elimination order (no atomics: the result is deterministic);
 //   4. Z replaces the pivot rows of S.
+// All levels are planned on the host first (in parallel), their work lists
+// copied to the device in one piece, then launched back to back.
 #include <algorithm>
 #include <cstring>
 
@@ -22,10 +26,19 @@ namespace {
 
 struct SchurRec {
   int64_t target;  // block number of (i, j)
-  int64_t kpos;    // S position of the pivot
+  int64_t kpos;    // elimination position of the pivot
   int64_t a_blk;   // block number of (k, i)
-  int64_t z_off;   // offset of Z_kj in the level's Z buffer
+  int64_t z_off;   // offset of Z_kj in the Z buffer
   int32_t mk;
+};
+
+template <class T>
+struct FactorLevel {
+  std::vector<InvItem<T>> inv;
+  std::vector<CopySeg> cps;
+  const InvItem<T>* d_inv = nullptr;
+  const CopySeg* d_cps = nullptr;
+  GemmBatch zb, sb;
 };
 
 }  // namespace
@@ -38,8 +51,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   T* S = sp.dS.as<T>();
   T* Inv = f.dInv.as<T>();
   const int dim = sp.H->tree.dim;
-  // per-position helpers
-  auto cl = [&](i64 pos) { return sp.order[pos]; };
+  auto cl = [&](i64 pos) { return sp.eorder[pos]; };
   std::vector<std::vector<i64>> by_level(f.nflev);
   for (i64 pos : f.rows) by_level[f.flev[pos]].push_back(pos);
   // Z buffer: largest level
@@ -54,7 +66,90 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   }
   f.dZ.reset(sizeof(T) * zmax);
   T* Z = f.dZ.as<T>();
-  std::vector<i64> mark(ncl, -1);
+  // block number -> elimination position of its row
+  std::vector<i64> row_of(sp.colidx.size());
+  for (i64 pos = 0; pos < ncl; ++pos)
+    for (i64 b = sp.rowptr[pos]; b < sp.rowptr[pos + 1]; ++b) row_of[b] = pos;
+
+  std::vector<FactorLevel<T>> lvls(f.nflev);
+  double fl_inv = 0, fl_z = 0, fl_s = 0;
+#pragma omp parallel reduction(+ : fl_inv, fl_z, fl_s)
+  {
+    std::vector<i64> mark(ncl, -1);
+    std::vector<SchurRec> recs;
+#pragma omp for schedule(dynamic, 1)
+    for (int lv = 0; lv < f.nflev; ++lv) {
+      FactorLevel<T>& L = lvls[lv];
+      L.zb.role = ROLE_FACTOR;
+      L.sb.role = ROLE_FACTOR;
+      L.sb.mode = GEMM_SUB;
+      recs.clear();
+      i64 zoff = 0;
+      for (i64 pk : by_level[lv]) {
+        const i64 ck = cl(pk);
+        const i64 mk = mb[ck];
+        const i64 dblk = sp.rowptr[pk];
+        L.inv.push_back({S + sp.blk_off[dblk], Inv + f.inv_off[pk], int32_t(mk), 0});
+        fl_inv += 2.0 * mk * mk * mk;
+        const i64 b0 = dblk + 1, b1 = sp.rowptr[pk + 1];
+        if (b0 == b1) continue;
+        const i64 row_start = sp.blk_off[b0];
+        i64 width = 0;
+        std::vector<i64> colpos(b1 - b0);
+        for (i64 b = b0; b < b1; ++b) {
+          colpos[b - b0] = width;
+          width += mb[sp.colidx[b]];
+        }
+        for (i64 c0 = 0; c0 < width; c0 += 512) {
+          const int w = int(std::min<i64>(512, width - c0));
+          GemmItem& it = L.zb.item(int(mk), w, int(mk), w);
+          GemmBatch::set_out(it, 0, Z + zoff + c0 * mk, mk, false);
+          L.zb.seg(Inv + f.inv_off[pk], int(mk), false, S + row_start + c0 * mk, int(mk), false, int(mk));
+        }
+        L.cps.push_back({row_start, zoff, mk * width});
+        // Schur targets (i, j), i before or equal to j, both in row k
+        for (i64 a = b0; a < b1; ++a) {
+          const i64 pi = sp.epos[sp.colidx[a]];
+          for (i64 b = sp.rowptr[pi]; b < sp.rowptr[pi + 1]; ++b) mark[sp.colidx[b]] = b;
+          for (i64 a2 = a; a2 < b1; ++a2) {
+            const i64 tb = mark[sp.colidx[a2]];
+            if (tb < 0) continue;
+            recs.push_back({tb, pk, a, zoff + colpos[a2 - b0] * mk, int32_t(mk)});
+          }
+          for (i64 b = sp.rowptr[pi]; b < sp.rowptr[pi + 1]; ++b) mark[sp.colidx[b]] = -1;
+        }
+        zoff += mk * width;
+      }
+      fl_z += L.zb.flops;
+      std::sort(recs.begin(), recs.end(), [](const SchurRec& x, const SchurRec& y) {
+        return x.target < y.target || (x.target == y.target && x.kpos < y.kpos);
+      });
+      for (size_t r = 0; r < recs.size();) {
+        const i64 tb = recs[r].target;
+        const i64 mi = mb[cl(row_of[tb])], mj = mb[sp.colidx[tb]];
+        GemmItem& it = L.sb.item(int(mi), int(mj), int(mi), int(mj));
+        GemmBatch::set_out(it, 0, S + sp.blk_off[tb], mi, false);
+        for (; r < recs.size() && recs[r].target == tb; ++r)
+          L.sb.seg(S + sp.blk_off[recs[r].a_blk], recs[r].mk, true, Z + recs[r].z_off, recs[r].mk, false,
+                   recs[r].mk);
+      }
+      fl_s += L.sb.flops;
+    }
+  }
+  f.flops_inv += fl_inv;
+  f.flops_z += fl_z;
+  f.flops_schur += fl_s;
+  {
+    std::vector<GemmBatch*> all;
+    std::vector<RawBlob> blobs;
+    for (auto& L : lvls) {
+      all.push_back(&L.zb);
+      all.push_back(&L.sb);
+      blobs.push_back({L.inv.data(), L.inv.size() * sizeof(InvItem<T>), reinterpret_cast<const void**>(&L.d_inv)});
+      blobs.push_back({L.cps.data(), L.cps.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_cps)});
+    }
+    upload_batches(all, f.dDesc, blobs);
+  }
   std::vector<hipEvent_t> ev;
   auto mark_ev = [&]() {
     hipEvent_t e;
@@ -62,83 +157,15 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     HIPCHECK(hipEventRecord(e, st));
     ev.push_back(e);
   };
-  // keep every level's work lists alive until the device is done with them
-  std::vector<DeviceBuffer> keep_inv, keep_cp;
-  std::vector<GemmBatch> keep_z(f.nflev), keep_s(f.nflev);
   mark_ev();
   for (int lv = 0; lv < f.nflev; ++lv) {
-    const auto& piv = by_level[lv];
-    std::vector<InvItem<T>> inv;
-    std::vector<CopySeg> cps;
-    GemmBatch& zb = keep_z[lv];
-    GemmBatch& sb = keep_s[lv];
-    sb.mode = GEMM_SUB;
-    sb.role = ROLE_FACTOR;
-    zb.role = ROLE_FACTOR;
-    std::vector<SchurRec> recs;
-    i64 zoff = 0;
-    for (i64 pk : piv) {
-      const i64 ck = cl(pk);
-      const i64 mk = mb[ck];
-      const i64 dblk = sp.rowptr[pk];
-      inv.push_back({S + sp.blk_off[dblk], Inv + f.inv_off[pk], int32_t(mk), 0});
-      f.flops_inv += 2.0 * mk * mk * mk;
-      const i64 b0 = dblk + 1, b1 = sp.rowptr[pk + 1];
-      if (b0 == b1) continue;
-      const i64 row_start = sp.blk_off[b0];
-      i64 width = 0;
-      std::vector<i64> colpos(b1 - b0);
-      for (i64 b = b0; b < b1; ++b) {
-        colpos[b - b0] = width;
-        width += mb[sp.colidx[b]];
-      }
-      for (i64 c0 = 0; c0 < width; c0 += 512) {
-        const int w = int(std::min<i64>(512, width - c0));
-        GemmItem& it = zb.item(int(mk), w, int(mk), w);
-        GemmBatch::set_out(it, 0, Z + zoff + c0 * mk, mk, false);
-        zb.seg(Inv + f.inv_off[pk], int(mk), false, S + row_start + c0 * mk, int(mk), false, int(mk));
-      }
-      cps.push_back({row_start, zoff, mk * width});
-      // Schur targets (i, j), i <= j, both in row k
-      for (i64 a = b0; a < b1; ++a) {
-        const i64 ci = sp.colidx[a];
-        const i64 pi = sp.spos[ci];
-        for (i64 b = sp.rowptr[pi]; b < sp.rowptr[pi + 1]; ++b) mark[sp.colidx[b]] = b;
-        for (i64 a2 = a; a2 < b1; ++a2) {
-          const i64 tb = mark[sp.colidx[a2]];
-          if (tb < 0) continue;
-          recs.push_back({tb, pk, a, zoff + colpos[a2 - b0] * mk, int32_t(mk)});
-        }
-        for (i64 b = sp.rowptr[pi]; b < sp.rowptr[pi + 1]; ++b) mark[sp.colidx[b]] = -1;
-      }
-      zoff += mk * width;
-    }
-    zb.finalize();
-    f.flops_z += zb.flops;
-    std::sort(recs.begin(), recs.end(), [](const SchurRec& x, const SchurRec& y) {
-      return x.target < y.target || (x.target == y.target && x.kpos < y.kpos);
-    });
-    // target block number -> (i, j) through the row of i: find by binary search
-    for (size_t r = 0; r < recs.size();) {
-      const i64 tb = recs[r].target;
-      const i64 pi = std::upper_bound(sp.rowptr.begin(), sp.rowptr.end(), tb) - sp.rowptr.begin() - 1;
-      const i64 mi = mb[cl(pi)], mj = mb[sp.colidx[tb]];
-      GemmItem& it = sb.item(int(mi), int(mj), int(mi), int(mj));
-      GemmBatch::set_out(it, 0, S + sp.blk_off[tb], mi, false);
-      for (; r < recs.size() && recs[r].target == tb; ++r)
-        sb.seg(S + sp.blk_off[recs[r].a_blk], recs[r].mk, true, Z + recs[r].z_off, recs[r].mk, false,
-               recs[r].mk);
-    }
-    sb.finalize();
-    f.flops_schur += sb.flops;
-    keep_inv.push_back(upload(inv));
-    keep_cp.push_back(upload(cps));
-    launch_inverse<T>(keep_inv.back().as<InvItem<T>>(), int(inv.size()), f.dFlag.as<int>(), st);
-    zb.launch<T>(st, dim, 0.0, 0.0);
+    FactorLevel<T>& L = lvls[lv];
+    launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
+    L.zb.template launch<T>(st, dim, 0.0, 0.0);
     mark_ev();
-    sb.launch<T>(st, dim, 0.0, 0.0);
+    L.sb.template launch<T>(st, dim, 0.0, 0.0);
     mark_ev();
-    launch_copy_segments<T>(keep_cp.back().as<CopySeg>(), int(cps.size()), Z, S, st);
+    launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
   }
   HIPCHECK(hipGetLastError());
   mark_ev();
@@ -173,14 +200,14 @@ h2_factor* factor(h2_sparse* sp, hipStream_t st, double* phase_ms) {
   std::vector<std::vector<i64>> col(ncl);
   i64 io = 0;
   for (i64 pos = 0; pos < ncl; ++pos) {
-    const i64 c = sp->order[pos];
+    const i64 c = sp->eorder[pos];
     if (mb[c] == 0) continue;
     f.rows.push_back(pos);
     if (sp->rowptr[pos] == sp->rowptr[pos + 1] || sp->colidx[sp->rowptr[pos]] != c)
       fail(H2_EINVAL, "internal: missing diagonal block of S");
     f.inv_off[pos] = io;
     io += mb[c] * mb[c];
-    for (i64 b = sp->rowptr[pos] + 1; b < sp->rowptr[pos + 1]; ++b) col[sp->spos[sp->colidx[b]]].push_back(pos);
+    for (i64 b = sp->rowptr[pos] + 1; b < sp->rowptr[pos + 1]; ++b) col[sp->epos[sp->colidx[b]]].push_back(pos);
   }
   for (i64 pos : f.rows) {
     int l = 0;
@@ -192,13 +219,13 @@ h2_factor* factor(h2_sparse* sp, hipStream_t st, double* phase_ms) {
     const i64 pos = *it;
     int l = 0;
     for (i64 b = sp->rowptr[pos] + 1; b < sp->rowptr[pos + 1]; ++b)
-      l = std::max(l, f.blev[sp->spos[sp->colidx[b]]] + 1);
+      l = std::max(l, f.blev[sp->epos[sp->colidx[b]]] + 1);
     f.blev[pos] = l;
     f.nblev = std::max(f.nblev, l + 1);
   }
   f.dInv.reset(sp->elem * std::max<i64>(io, 1));
   f.dFlag.reset(sizeof(int));
-  HIPCHECK(hipMemsetAsync(f.dFlag.ptr, 0, sizeof(int), st));
+  launch_fill_i(f.dFlag.as<int>(), 1, 0, st);
   if (sp->precision == H2_MIXED) factor_levels<float>(f, st, phase_ms);
   else factor_levels<double>(f, st, phase_ms);
   int flag = 0;

@@ -11,7 +11,7 @@ namespace h2 {
 // right-hand sides.
 struct SolvePlan {
   i64 nrhs = 0;
-  DeviceBuffer zin, zbuf, y, w, rs, colscale;
+  DeviceBuffer zin, zbuf, y, w, rs, colscale, desc;
   std::vector<GemmBatch> up, down;       // U^T and V sweeps, per tree level
   std::vector<GemmBatch> fwd, bwd;       // triangular solves, per DAG level
   GemmBatch diag;                        // D^{-1}
@@ -26,7 +26,7 @@ struct h2_factor {
   std::vector<int> flev, blev;               // forward / backward level per S position
   int nflev = 0, nblev = 0;
   std::vector<h2::i64> inv_off;              // per S position: offset of D_k^{-1}
-  h2::DeviceBuffer dInv, dZ, dFlag;
+  h2::DeviceBuffer dInv, dZ, dFlag, dDesc;
   double flops_schur = 0, flops_inv = 0, flops_z = 0;
   std::unique_ptr<h2::SolvePlan> solve;
   ~h2_factor();

@@ -86,6 +86,7 @@ void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, 
 // Small element-wise helpers.
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_f(float* p, int64_t n, float v, hipStream_t st);
+void launch_fill_i(int* p, int64_t n, int v, hipStream_t st);
 void launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t st);
 void launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t st);
 // out[i + j ldo] = in[idx[i] + j ldi]  (gather rows), i < n, j < nrhs

@@ -312,6 +312,9 @@ __global__ void fill_kernel(double* p, int64_t n, double v) {
 __global__ void fill_f_kernel(float* p, int64_t n, float v) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
 }
+__global__ void fill_i_kernel(int* p, int64_t n, int v) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
 __global__ void cast_d2f_kernel(const double* in, float* out, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) out[i] = float(in[i]);
 }
@@ -445,6 +448,9 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
 }
 void launch_fill_f(float* p, int64_t n, float v, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(fill_f_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+}
+void launch_fill_i(int* p, int64_t n, int v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(fill_i_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
 }
 void launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(cast_d2f_kernel, dim3(grid_for(n)), dim3(256), 0, st, in, out, n);

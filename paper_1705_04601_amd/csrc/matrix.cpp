@@ -66,7 +66,7 @@ namespace h2 {
 
 struct MatvecPlan {
   i64 nrhs = 0;
-  DeviceBuffer xt, yt, xhat, xtil, ytil, yhat;
+  DeviceBuffer xt, yt, xhat, xtil, ytil, yhat, desc;
   GemmBatch close;
   std::vector<GemmBatch> up;     // per level (0 = leaves)
   GemmBatch xproj, coup, yproj;
@@ -121,7 +121,6 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
       p.close.seg_gen(X + tr.start[t] * dim, X + tr.start[s] * dim, s == t, xt + tr.start[s], int(n),
                       false, int(tr.size[s]));
   }
-  p.close.finalize();
   // upward pass
   p.up.resize(L + 1);
   for (int k = 0; k <= L; ++k) {
@@ -140,7 +139,6 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
                       H.rank[s]);
       }
     }
-    p.up[k].finalize();
   }
   // couplings: xtil = P^T xhat; ytil_t = sum_s K(nodes_t, nodes_s) xtil_s; yhat = P ytil
   std::vector<std::vector<int32_t>> farOf(ncl);
@@ -165,9 +163,6 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
       p.yproj.seg(proj + H.proj_off[c], r, false, ytil + poff[c], P, false, P);
     }
   }
-  p.xproj.finalize();
-  p.coup.finalize();
-  p.yproj.finalize();
   // downward pass: yhat_c += T_c yhat_father (levels L-1 .. 0)
   p.down.resize(L + 1);
   for (int k = L - 1; k >= 0; --k) {
@@ -180,7 +175,6 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
       GemmBatch::set_out(it, 0, yhat + hoff[c], r, false);
       p.down[k].seg(transfer + H.transfer_off[c], r, false, yhat + hoff[(c - 1) / 2], rp, false, rp);
     }
-    p.down[k].finalize();
   }
   p.leafout.mode = GEMM_ADD;
   for (i64 t = f0; t < f0 + c0; ++t) {
@@ -190,17 +184,16 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
     GemmBatch::set_out(it, 0, yt + tr.start[t], n, false);
     p.leafout.seg(basis + H.basis_off[t], int(tr.size[t]), false, yhat + hoff[t], r, false, r);
   }
-  p.leafout.finalize();
+  std::vector<GemmBatch*> all{&p.close, &p.xproj, &p.coup, &p.yproj, &p.leafout};
+  for (auto& g : p.up) all.push_back(&g);
+  for (auto& g : p.down) all.push_back(&g);
+  for (GemmBatch* g : all) g->role = ROLE_MATVEC;
+  upload_batches(all, p.desc);
   return mp;
 }
 
 // y_tree = A_H2 x_tree on plan buffers (x in p.xt, result in p.yt).
 void run_matvec_tree(const h2_matrix& H, MatvecPlan& p, hipStream_t st) {
-  if (p.close.role != ROLE_MATVEC) {
-    p.close.role = p.xproj.role = p.coup.role = p.yproj.role = p.leafout.role = ROLE_MATVEC;
-    for (auto& g : p.up) g.role = ROLE_MATVEC;
-    for (auto& g : p.down) g.role = ROLE_MATVEC;
-  }
   const int dim = H.tree.dim;
   const double sc = H.scale, dg = H.diag;
   p.close.launch<double>(st, dim, sc, dg);

@@ -55,6 +55,7 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
   T* w = p->w.as<T>();
   const T* Q = (sp.precision == H2_MIXED) ? sp.dQt.as<T>() : reinterpret_cast<const T*>(sp.dQ.as<double>());
   const T* S = sp.dS.as<T>();
+  (void)0;
   const T* Inv = f.dInv.as<T>();
   auto son_off = [&](i64 c) -> i64 { return (c % 2 == 1) ? 0 : kp[c - 1]; };
   auto zslot = [&](i64 c, i64* ld) -> T* {
@@ -82,58 +83,71 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
       T* zc = zslot(c, &ldz);
       p->up[k].seg(Q + sp.q_off[c], int(na[c]), true, zc, int(ldz), false, int(na[c]));
     }
-    p->up[k].finalize();
+
   }
-  // forward and backward triangular solves by DAG level
+  // forward and backward triangular solves, right-looking by DAG level: once
+  // the rows of a level are final they update every row they reach; each work
+  // item owns one target row and takes the level's contributions in
+  // elimination order (short chains, many items per launch)
   std::vector<std::vector<i64>> fl(f.nflev), bl(f.nblev);
   for (i64 pos : f.rows) {
     fl[f.flev[pos]].push_back(pos);
     bl[f.blev[pos]].push_back(pos);
   }
-  std::vector<std::vector<i64>> colblk(ncl);  // per S position: blocks (k, i) above the diagonal
+  std::vector<i64> row_of(sp.colidx.size());
+  for (i64 pos = 0; pos < ncl; ++pos)
+    for (i64 b = sp.rowptr[pos]; b < sp.rowptr[pos + 1]; ++b) row_of[b] = pos;
+  std::vector<std::vector<i64>> colblk(ncl);  // per elimination position: blocks (k, i), k before i
   for (i64 pos : f.rows)
-    for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) colblk[sp.spos[sp.colidx[b]]].push_back(b);
-  auto row_of_block = [&](i64 b) {
-    return i64(std::upper_bound(sp.rowptr.begin(), sp.rowptr.end(), b) - sp.rowptr.begin() - 1);
+    for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) colblk[sp.epos[sp.colidx[b]]].push_back(b);
+  struct Rec {
+    i64 target, src, blk;
   };
   p->fwd.resize(f.nflev);
   for (int lv = 0; lv < f.nflev; ++lv) {
+    std::vector<Rec> recs;
+    for (i64 pk : fl[lv])
+      for (i64 b = sp.rowptr[pk] + 1; b < sp.rowptr[pk + 1]; ++b) recs.push_back({sp.epos[sp.colidx[b]], pk, b});
+    std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
+      return a.target < b.target || (a.target == b.target && a.src < b.src);
+    });
     GemmBatch& g = p->fwd[lv];
     g.mode = GEMM_SUB;
-    for (i64 pos : fl[lv]) {
-      if (colblk[pos].empty()) continue;
-      const i64 ci = sp.order[pos];
+    for (size_t r = 0; r < recs.size();) {
+      const i64 ci = sp.eorder[recs[r].target];
       GemmItem& it = g.item(int(mb[ci]), N, int(mb[ci]), N);
       GemmBatch::set_out(it, 0, y + sp.soff[ci], n, false);
-      for (i64 b : colblk[pos]) {
-        const i64 ck = sp.order[row_of_block(b)];
-        g.seg(S + sp.blk_off[b], int(mb[ck]), true, y + sp.soff[ck], int(n), false, int(mb[ck]));
+      for (; r < recs.size() && sp.eorder[recs[r].target] == ci; ++r) {
+        const i64 ck = sp.eorder[recs[r].src];
+        g.seg(S + sp.blk_off[recs[r].blk], int(mb[ck]), true, y + sp.soff[ck], int(n), false, int(mb[ck]));
       }
     }
-    g.finalize();
   }
   for (i64 pos : f.rows) {
-    const i64 c = sp.order[pos];
+    const i64 c = sp.eorder[pos];
     GemmItem& it = p->diag.item(int(mb[c]), N, int(mb[c]), N);
     GemmBatch::set_out(it, 0, w + sp.soff[c], n, false);
     p->diag.seg(Inv + f.inv_off[pos], int(mb[c]), false, y + sp.soff[c], int(n), false, int(mb[c]));
   }
-  p->diag.finalize();
   p->bwd.resize(f.nblev);
   for (int lv = 0; lv < f.nblev; ++lv) {
+    std::vector<Rec> recs;
+    for (i64 pj : bl[lv])
+      for (i64 b : colblk[pj]) recs.push_back({row_of[b], pj, b});
+    std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
+      return a.target < b.target || (a.target == b.target && a.src < b.src);
+    });
     GemmBatch& g = p->bwd[lv];
     g.mode = GEMM_SUB;
-    for (i64 pos : bl[lv]) {
-      const i64 ci = sp.order[pos];
-      if (sp.rowptr[pos] + 1 == sp.rowptr[pos + 1]) continue;
-      GemmItem& it = g.item(int(mb[ci]), N, int(mb[ci]), N);
-      GemmBatch::set_out(it, 0, w + sp.soff[ci], n, false);
-      for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) {
-        const i64 cj = sp.colidx[b];
-        g.seg(S + sp.blk_off[b], int(mb[ci]), false, w + sp.soff[cj], int(n), false, int(mb[cj]));
+    for (size_t r = 0; r < recs.size();) {
+      const i64 ck = sp.eorder[recs[r].target];
+      GemmItem& it = g.item(int(mb[ck]), N, int(mb[ck]), N);
+      GemmBatch::set_out(it, 0, w + sp.soff[ck], n, false);
+      for (; r < recs.size() && sp.eorder[recs[r].target] == ck; ++r) {
+        const i64 cj = sp.eorder[recs[r].src];
+        g.seg(S + sp.blk_off[recs[r].blk], int(mb[ck]), false, w + sp.soff[cj], int(n), false, int(mb[cj]));
       }
     }
-    g.finalize();
   }
   // V sweep: per level from the root
   p->down.resize(L + 1);
@@ -153,19 +167,17 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
         p->down[k].seg(Q + sp.q_off[c] + kp[c] * na[c], int(na[c]), false, w + sp.soff[c], int(n), false,
                        int(mb[c]));
     }
-    p->down[k].finalize();
+
   }
-  for (auto& g : p->up) g.role = ROLE_SOLVE;
-  for (auto& g : p->down) g.role = ROLE_SOLVE;
-  for (auto& g : p->fwd) g.role = ROLE_SOLVE;
-  for (auto& g : p->bwd) g.role = ROLE_SOLVE;
-  p->diag.role = ROLE_SOLVE;
-  for (auto& g : p->up) g.drop_host();
-  for (auto& g : p->down) g.drop_host();
-  for (auto& g : p->fwd) g.drop_host();
-  for (auto& g : p->bwd) g.drop_host();
-  p->diag.drop_host();
+  std::vector<GemmBatch*> all;
+  for (auto& g : p->up) all.push_back(&g);
+  for (auto& g : p->down) all.push_back(&g);
+  for (auto& g : p->fwd) all.push_back(&g);
+  for (auto& g : p->bwd) all.push_back(&g);
+  all.push_back(&p->diag);
+  for (GemmBatch* g : all) g->role = ROLE_SOLVE;
   HIPCHECK(hipStreamSynchronize(current_stream()));
+  upload_batches(all, p->desc);
   return p;
 }
 

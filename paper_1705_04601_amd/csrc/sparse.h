@@ -9,7 +9,8 @@
 namespace h2 {
 
 struct QrLevel {
-  DeviceBuffer d_items;
+  std::vector<QrItem> items;       // host copy until uploaded
+  const QrItem* d_items = nullptr;
   int count = 0;
   i64 q_begin = 0, q_end = 0;      // range of the level's Q blocks in the Q arena
   i64 w_begin = 0, w_end = 0;      // range of the level's W blocks (coupling factors)
@@ -38,15 +39,19 @@ struct h2_sparse {
   int precision = H2_FP64;
   h2::i64 ncl = 0;
   std::vector<h2::i64> n_act, kept, nonbasis, soff, spos, order;
-  // upper block pattern of S: block rows = clusters in S order
-  std::vector<h2::i64> rowptr;     // by S position
-  std::vector<h2::i64> colidx;     // cluster ids (sorted by S position)
+  // elimination order of the factorisation: levels from the leaves up, inside
+  // a level (greedy colour, cluster); S is stored as its upper block triangle
+  // in this order (block (t, s) kept with epos(t) <= epos(s))
+  std::vector<h2::i64> eorder, epos;
+  std::vector<int> colour;
+  std::vector<h2::i64> rowptr;     // by elimination position
+  std::vector<h2::i64> colidx;     // cluster ids (sorted by elimination position)
   std::vector<h2::i64> blk_off;    // entry offset of each stored block
   std::unordered_map<h2::i64, h2::i64> blk_index;  // t * ncl + s -> block number
   h2::i64 s_entries = 0;
   // arenas
   std::vector<h2::i64> q_off, b_off, rhat_off, w_off;
-  h2::DeviceBuffer dQ, dQt, dB, dRhat, dW, dWt, dS, dC[2], dG[2], dTmp;
+  h2::DeviceBuffer dQ, dQt, dB, dRhat, dW, dWt, dS, dC[2], dG[2], dTmp, dDesc;
   std::vector<h2::SweepLevel> levels;
   h2::PlanCounts counts;
   size_t elem = 8;                 // bytes per S / transform element

@@ -82,12 +82,43 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
   const auto& mb = sp.nonbasis;
   auto son_off = [&](i64 c) -> i64 { return (c % 2 == 1) ? 0 : kept[c - 1]; };
 
+  // ---- elimination order: per level, greedy colouring of the close graph
+  // among clusters with non-basis rows, then (colour, cluster)
+  sp.colour.assign(ncl, -1);
+  sp.eorder.clear();
+  sp.epos.assign(ncl, 0);
+  for (int k = 0; k <= L; ++k) {
+    const i64 f = tr.first_at_level(k), cnt = tr.count_at_level(k);
+    std::vector<std::vector<i64>> earlier(cnt);
+    for (const Pair& pr : H->bt.near[k])
+      if (pr.s < pr.t && mb[pr.t] > 0 && mb[pr.s] > 0) earlier[pr.t - f].push_back(pr.s);
+    std::vector<char> taken;
+    for (i64 c = f; c < f + cnt; ++c) {
+      if (mb[c] == 0) continue;
+      taken.assign(earlier[c - f].size() + 1, 0);
+      for (i64 s : earlier[c - f])
+        if (sp.colour[s] < int(taken.size())) taken[sp.colour[s]] = 1;
+      int col = 0;
+      while (taken[col]) ++col;
+      sp.colour[c] = col;
+    }
+    std::vector<i64> lv;
+    for (i64 c = f; c < f + cnt; ++c)
+      if (mb[c] > 0) lv.push_back(c);
+    std::stable_sort(lv.begin(), lv.end(), [&](i64 a, i64 b) { return sp.colour[a] < sp.colour[b]; });
+    for (i64 c = f; c < f + cnt; ++c)
+      if (mb[c] == 0) lv.push_back(c);
+    sp.eorder.insert(sp.eorder.end(), lv.begin(), lv.end());
+  }
+  for (i64 i = 0; i < ncl; ++i) sp.epos[sp.eorder[i]] = i;
+  const auto& epos = sp.epos;
+
   // ---- symbolic sweep: strips, close/coupling lists, C slots, S blocks
   std::vector<std::vector<Pair>> closeL(L + 1), coupL(L + 1);
   std::vector<std::vector<SymStrip>> stripL(L + 2);
   std::vector<std::unordered_map<i64, i64>> cslot(L + 2), gslot(L + 2);
   std::vector<i64> csize(L + 2, 0), gsize(L + 2, 0);
-  std::vector<std::pair<i64, i64>> blocks;  // (t, s) with spos(t) <= spos(s)
+  std::vector<std::pair<i64, i64>> blocks;  // (t, s) with epos(t) <= epos(s)
   for (int k = 0; k <= L; ++k) {
     auto add_strip = [&](i64 tau, i64 p) {
       const i64 kk = key(tau, p, ncl);
@@ -104,7 +135,7 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
       const i64 t = pr.t, s = pr.s;
       if (t > s || n_act[t] == 0 || n_act[s] == 0) continue;
       closeL[k].push_back(pr);
-      if (mb[t] > 0 && mb[s] > 0) blocks.push_back({t, s});
+      if (mb[t] > 0 && mb[s] > 0) blocks.push_back(epos[t] <= epos[s] ? std::make_pair(t, s) : std::make_pair(s, t));
       if (k < L) {
         if (mb[t] > 0 && kept[s] > 0) add_strip(t, (s - 1) / 2);
         if (t != s && mb[s] > 0 && kept[t] > 0) add_strip(s, (t - 1) / 2);
@@ -119,10 +150,10 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
         csize[k + 1] += n_act[pr.t] * n_act[pr.s];
       }
   }
-  // ---- upper block pattern in S order
+  // ---- upper block pattern in the elimination order
   std::sort(blocks.begin(), blocks.end(), [&](const auto& a, const auto& b) {
-    return sp.spos[a.first] < sp.spos[b.first] ||
-           (sp.spos[a.first] == sp.spos[b.first] && sp.spos[a.second] < sp.spos[b.second]);
+    return epos[a.first] < epos[b.first] ||
+           (epos[a.first] == epos[b.first] && epos[a.second] < epos[b.second]);
   });
   if (std::adjacent_find(blocks.begin(), blocks.end()) != blocks.end())
     fail(H2_EINVAL, "internal: duplicate S block");
@@ -133,7 +164,7 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
   i64 ent = 0;
   for (size_t b = 0; b < blocks.size(); ++b) {
     const i64 t = blocks[b].first, s = blocks[b].second;
-    sp.rowptr[sp.spos[t] + 1]++;
+    sp.rowptr[epos[t] + 1]++;
     sp.colidx[b] = s;
     sp.blk_off[b] = ent;
     sp.blk_index[key(t, s, ncl)] = i64(b);
@@ -217,6 +248,12 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
     if (b < 0) fail(H2_EINVAL, "internal: missing S block");
     return S + el * sp.blk_off[b];
   };
+  // destination of S(t, s) as seen from the pair's orientation: stored as is,
+  // or as the transposed block (s, t) when s comes first in elimination order
+  auto set_s_out = [&](GemmItem& it, int q, i64 t, i64 s) {
+    if (epos[t] <= epos[s]) GemmBatch::set_out(it, q, blk_ptr(t, s), mb[t], false);
+    else GemmBatch::set_out(it, q, blk_ptr(s, t), mb[s], true);
+  };
   for (int k = 0; k <= L; ++k) {
     SweepLevel& lv = sp.levels[k];
     char* Ccur = static_cast<char*>(sp.dC[k % 2].ptr);
@@ -246,7 +283,7 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
       qi.push_back(it);
     }
     lv.qr.count = int(qi.size());
-    lv.qr.d_items = upload(qi);
+    lv.qr.items = std::move(qi);
     lv.qr.q_begin = qlev[k];
     lv.qr.q_end = qlev[k + 1];
     lv.qr.w_begin = wlev[k];
@@ -268,8 +305,6 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
         lv.wproj.seg(dR + sp.rhat_off[c], int(kept[c]), false, proj + H->proj_off[c], r, false, r);
       }
     }
-    lv.stack.finalize();
-    lv.wproj.finalize();
     pc.flops_misc += lv.stack.flops + lv.wproj.flops;
     // 3. strips: G(tau, p) Q_p
     for (const SymStrip& g : stripL[k]) {
@@ -284,7 +319,6 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
       lv.strips.seg(Gcur + el * g.slot, int(mb[tau]), false, Qt + el * sp.q_off[p], int(n_act[p]), false,
                     int(n_act[p]));
     }
-    lv.strips.finalize();
     pc.flops_strip += lv.strips.flops;
     // 4. close pairs, chunked by temporary space
     {
@@ -309,7 +343,7 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
           g1.seg(Ccur + el * cslot[k].at(key(t, s, ncl)), int(nt), false, Qt + el * sp.q_off[s], int(ns), false,
                  int(ns));
         GemmItem& b = g2.item(int(nt), int(ns), int(kept[t]), int(kept[s]));
-        if (mb[t] > 0 && mb[s] > 0) GemmBatch::set_out(b, 3, blk_ptr(t, s), mb[t], false);
+        if (mb[t] > 0 && mb[s] > 0) set_s_out(b, 3, t, s);
         if (k < L) {
           const i64 pt = (t - 1) / 2, ps = (s - 1) / 2;
           if (kept[t] > 0 && kept[s] > 0) {
@@ -329,8 +363,8 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
         }
         g2.seg(Qt + el * sp.q_off[t], int(nt), true, w, int(nt), false, int(nt));
       }
-      for (auto& g : lv.close1) { g.finalize(); pc.flops_close += g.flops; }
-      for (auto& g : lv.close2) { g.finalize(); pc.flops_close += g.flops; }
+      for (auto& g : lv.close1) pc.flops_close += g.flops;
+      for (auto& g : lv.close2) pc.flops_close += g.flops;
     }
     // 5. couplings R^_a D_ab R^_b^T into the father's close block
     {
@@ -359,19 +393,27 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
           GemmBatch::set_out(i2, 4, cs + el * (son_off(b) + son_off(a) * n_act[pa]), n_act[pa], true);
         g2.seg(Wt + el * wtoff[a], int(ka), false, w, P, false, P);
       }
-      for (auto& g : lv.coup1) { g.finalize(); pc.flops_coup += g.flops; }
-      for (auto& g : lv.coup2) { g.finalize(); pc.flops_coup += g.flops; }
+      for (auto& g : lv.coup1) pc.flops_coup += g.flops;
+      for (auto& g : lv.coup2) pc.flops_coup += g.flops;
     }
-    // release host copies of the work lists
-    lv.stack.drop_host();
-    lv.wproj.drop_host();
-    lv.strips.drop_host();
-    for (auto& g : lv.close1) g.drop_host();
-    for (auto& g : lv.close2) g.drop_host();
-    for (auto& g : lv.coup1) g.drop_host();
-    for (auto& g : lv.coup2) g.drop_host();
+  }
+  // ---- one device allocation for every work list of the sweep
+  std::vector<GemmBatch*> all;
+  std::vector<RawBlob> blobs;
+  for (auto& lv : sp.levels) {
+    all.push_back(&lv.stack);
+    all.push_back(&lv.wproj);
+    all.push_back(&lv.strips);
+    for (auto& g : lv.close1) all.push_back(&g);
+    for (auto& g : lv.close2) all.push_back(&g);
+    for (auto& g : lv.coup1) all.push_back(&g);
+    for (auto& g : lv.coup2) all.push_back(&g);
+    blobs.push_back({lv.qr.items.data(), lv.qr.items.size() * sizeof(QrItem),
+                     reinterpret_cast<const void**>(&lv.qr.d_items)});
   }
   HIPCHECK(hipStreamSynchronize(current_stream()));
+  upload_batches(all, sp.dDesc, blobs);
+  for (auto& lv : sp.levels) std::vector<QrItem>().swap(lv.qr.items);
   return spp.release();
 }
 
@@ -391,7 +433,7 @@ static void run_levels(h2_sparse& sp, hipStream_t st, double* phase_ms) {
   mark();
   for (int k = 0; k <= L; ++k) {
     SweepLevel& lv = sp.levels[k];
-    launch_qr(lv.qr.d_items.as<QrItem>(), lv.qr.count, st);
+    launch_qr(lv.qr.d_items, lv.qr.count, st);
     lv.stack.launch<double>(st, dim, sc, dg);
     lv.wproj.launch<double>(st, dim, sc, dg);
     if (mixed) {

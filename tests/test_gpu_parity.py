@@ -107,15 +107,17 @@ def test_matvec_own_build(name):
 
 
 def _check_plan(sph, sp):
+    """Sizes, S offsets, elimination order and the stored pattern: bit-exact."""
     plan = P.h2_sparse_export_plan(sph)
     assert np.array_equal(plan["n_act"], sp.n_act)
     assert np.array_equal(plan["kept"], sp.kept)
     assert np.array_equal(plan["nonbasis"], sp.nonbasis)
     assert np.array_equal(plan["soff"], sp.soff)
-    pos = np.empty(len(sp.order), dtype=np.int64)
-    pos[sp.order] = np.arange(len(sp.order))
+    elim = [int(c) for c in plan["elim"] if sp.nonbasis[c] > 0]
+    assert elim == oracle.elimination_order(sp)
+    pos = {int(c): i for i, c in enumerate(plan["elim"])}
     got = set()
-    for i, t in enumerate(sp.order):
+    for i, t in enumerate(plan["elim"]):
         for b in range(plan["rowptr"][i], plan["rowptr"][i + 1]):
             got.add((int(t), int(plan["colidx"][b])))
     want = {(t, s) for (t, s) in sp.s_blocks if pos[t] <= pos[s]}
@@ -134,11 +136,8 @@ def test_sparsify_fp64_parity(name):
     for t, q in sp.q.items():
         got = P.h2_sparse_export_q(sph, t, q.shape[0])
         assert np.abs(got - q).max() <= 1e-12, f"Q of cluster {t}"
-    pos = {int(c): i for i, c in enumerate(sp.order)}
     worst = 0.0
     for (t, s), blk in sp.s_blocks.items():
-        if pos[t] > pos[s]:
-            continue
         got = P.h2_sparse_export_block(sph, t, s, *blk.shape)
         worst = max(worst, np.abs(got - blk).max())
     assert worst <= 1e-12 * amax
@@ -152,11 +151,8 @@ def test_sparsify_mixed_parity(name):
     sph = P.h2_sparsify(h, P.H2_MIXED)
     _check_plan(sph, sp)
     amax = np.abs(a).max()
-    pos = {int(c): i for i, c in enumerate(sp.order)}
     worst = 0.0
     for (t, s), blk in sp.s_blocks.items():
-        if pos[t] > pos[s]:
-            continue
         got = P.h2_sparse_export_block(sph, t, s, *blk.shape)
         worst = max(worst, np.abs(got - blk).max())
     assert worst <= 5e-6 * amax
@@ -171,7 +167,7 @@ def test_preconditioner_matches_oracle_ilu0(name):
     b = np.random.default_rng(3).standard_normal((x.shape[0], 2))
     out = dev(np.zeros_like(b))
     P.h2_apply_inverse(f, dev(b), out)
-    ilu = oracle.BlockILU0(sp)
+    ilu = oracle.BlockILU0(sp, oracle.elimination_order(sp))
     bt = to_tree(b, h2.tree.perm)
     want_t = oracle.apply_v(sp, ilu.solve(oracle.apply_ut(sp, bt)))
     want = from_tree(want_t, h2.tree.perm)
@@ -227,7 +223,7 @@ def test_fp64_sparsify_is_deterministic():
     s1 = P.h2_sparsify(h, P.H2_FP64)
     s2 = P.h2_sparsify(h, P.H2_FP64)
     plan = P.h2_sparse_export_plan(s1)
-    for i, t in enumerate(sp.order[:200]):
+    for i, t in enumerate(plan["elim"][:200]):
         for b in range(plan["rowptr"][i], plan["rowptr"][i + 1]):
             s = int(plan["colidx"][b])
             m1, m2 = sp.nonbasis[t], sp.nonbasis[s]

@@ -298,6 +298,38 @@ def test_refinement_with_ilu0(case):
     assert np.abs(x - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+def test_elimination_order_colouring(case):
+    """Greedy colouring: valid (no block of S joins one colour on one level) and minimal."""
+    h2, sp, a, u, s = case
+    tr = h2.tree
+    col = oracle.elimination_colours(sp)
+    order = oracle.elimination_order(sp)
+    assert sorted(order) == sorted(c for c in range(tr.ncl) if sp.nonbasis[c] > 0)
+    keys = [(tr.level(c), col[c], c) for c in order]
+    assert keys == sorted(keys)
+    nbrs = {}
+    for (t, v) in sp.s_blocks:
+        if t != v and tr.level(t) == tr.level(v):
+            assert col[t] != col[v]
+            nbrs.setdefault(t, set()).add(v)
+    for t, c in col.items():
+        earlier = {col[v] for v in nbrs.get(t, ()) if v < t}
+        assert all(k in earlier for k in range(c))        # smallest free colour
+    b = np.random.default_rng(9).standard_normal((tr.n, 1))
+    x, hist = oracle.refine(sp, oracle.BlockILU0(sp, order).solve, b, 1e-12)
+    ref = np.linalg.solve(a, b)
+    assert hist[-1] <= 1e-12 and np.abs(x - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_ilu0_full_pattern_is_lu_in_any_order():
+    h2 = _h2("square", 60, 4, 32, 4)
+    sp = oracle.sparsify(h2)
+    b = np.random.default_rng(3).standard_normal((60, 1))
+    ref = np.linalg.solve(oracle.dense_s(sp), b)
+    for order in (list(sp.order)[::-1], oracle.elimination_order(sp)):
+        assert np.abs(oracle.BlockILU0(sp, order).solve(b) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def test_cg_reference(case):
     h2, sp, a, u, s = case
     b = np.random.default_rng(5).standard_normal((h2.tree.n, 1))
