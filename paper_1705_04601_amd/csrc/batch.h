@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "h2_internal.h"
@@ -21,6 +22,7 @@ struct GemmBatch {
   const GemmSeg* d_segs = nullptr;
   const int32_t* d_tiles = nullptr;
   int32_t ntiles = 0;
+  bool kc = false;     // every segment K-contiguous (A stored K x M, B K x N)
   int mode = GEMM_STORE;
   int role = ROLE_TRANSFORM;
   double flops = 0.0;  // algorithmic flops of the batch
@@ -81,15 +83,23 @@ struct GemmBatch {
     it.seg_end = int32_t(segs.size());
     flops += 2.0 * it.M * double(it.N) * s.K;
   }
-  // Tile list: one 32 x 32 tile per work-group.  Items without segments are
-  // kept only when they store (they then write zeros).
+  // Tile list: one tile per work-group (64 x 64 for the K-contiguous kernel,
+  // 32 x 32 otherwise).  Items without segments are kept only when they store
+  // (they then write zeros).
   void build_tiles() {
     tiles.clear();
+    kc = !segs.empty();
+    for (const GemmSeg& s : segs)
+      if (s.gen || s.opA != 1 || s.opB != 0) {
+        kc = false;
+        break;
+      }
     if (items.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "GEMM batch above 2^24 items");
     for (size_t i = 0; i < items.size(); ++i) {
       const GemmItem& it = items[i];
       if (it.seg_end == it.seg_begin && mode != GEMM_STORE) continue;
-      const int tm = (it.M + 31) / 32, tn = (it.N + 31) / 32;
+      const int edge = kc ? 64 : 32;  // tile edge of the kernel that will run it
+      const int tm = (it.M + edge - 1) / edge, tn = (it.N + edge - 1) / edge;
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b) tiles.push_back(int32_t((uint32_t(i) << 8) | (a << 4) | b));
     }
@@ -104,6 +114,7 @@ struct GemmBatch {
   void launch(hipStream_t st, int dim, double scale, double diag) const {
     if (ntiles <= 0) return;
     GemmLaunch g{};
+    g.kc = kc ? 1 : 0;
     g.items = d_items;
     g.segs = d_segs;
     g.tiles = d_tiles;
@@ -147,7 +158,8 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
     total = align(total + extra[i].bytes);
   }
   if (total == 0) return;
-  std::vector<char> staging(total);
+  std::unique_ptr<char[]> staging_buf(new char[total]);  // no zero fill
+  char* staging = staging_buf.get();
 #pragma omp parallel for schedule(dynamic, 16)
   for (long i = 0; i < long(bs.size()); ++i) {
     GemmBatch& b = *bs[i];
@@ -155,10 +167,11 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
     if (!b.segs.empty()) std::memcpy(&staging[off[3 * i + 1]], b.segs.data(), b.segs.size() * sizeof(GemmSeg));
     if (!b.tiles.empty()) std::memcpy(&staging[off[3 * i + 2]], b.tiles.data(), b.tiles.size() * sizeof(int32_t));
   }
-  for (size_t i = 0; i < extra.size(); ++i)
+#pragma omp parallel for schedule(dynamic, 4)
+  for (long i = 0; i < long(extra.size()); ++i)
     if (extra[i].bytes) std::memcpy(&staging[xoff[i]], extra[i].host, extra[i].bytes);
   store.reset(total);
-  HIPCHECK(hipMemcpy(store.ptr, staging.data(), total, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(store.ptr, staging, total, hipMemcpyHostToDevice));
   char* base = static_cast<char*>(store.ptr);
   for (size_t i = 0; i < bs.size(); ++i) {
     bs[i]->d_items = reinterpret_cast<const GemmItem*>(base + off[3 * i]);

@@ -36,15 +36,22 @@ template <class T>
 struct FactorLevel {
   std::vector<InvItem<T>> inv;
   std::vector<CopySeg> cps;
+  std::vector<SchurItem> sitems;
+  std::vector<SchurSeg> ssegs;
+  std::vector<int32_t> stiles;
   const InvItem<T>* d_inv = nullptr;
   const CopySeg* d_cps = nullptr;
-  GemmBatch zb, sb;
+  const SchurItem* d_sitems = nullptr;
+  const SchurSeg* d_ssegs = nullptr;
+  const int32_t* d_stiles = nullptr;
+  GemmBatch zb;
 };
 
 }  // namespace
 
 template <class T>
 static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
+  TraceTimer tt("factor");
   h2_sparse& sp = *f.sp;
   const i64 ncl = sp.ncl;
   const auto& mb = sp.nonbasis;
@@ -64,6 +71,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     }
     zmax = std::max(zmax, z);
   }
+  if (zmax >= (i64(1) << 31)) fail(H2_EUNSUPPORTED, "factor level too wide for 32-bit Z offsets");
   f.dZ.reset(sizeof(T) * zmax);
   T* Z = f.dZ.as<T>();
   // block number -> elimination position of its row
@@ -81,8 +89,6 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     for (int lv = 0; lv < f.nflev; ++lv) {
       FactorLevel<T>& L = lvls[lv];
       L.zb.role = ROLE_FACTOR;
-      L.sb.role = ROLE_FACTOR;
-      L.sb.mode = GEMM_SUB;
       recs.clear();
       i64 zoff = 0;
       for (i64 pk : by_level[lv]) {
@@ -104,7 +110,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
           const int w = int(std::min<i64>(512, width - c0));
           GemmItem& it = L.zb.item(int(mk), w, int(mk), w);
           GemmBatch::set_out(it, 0, Z + zoff + c0 * mk, mk, false);
-          L.zb.seg(Inv + f.inv_off[pk], int(mk), false, S + row_start + c0 * mk, int(mk), false, int(mk));
+          // D_k^{-1} is symmetric (D_k is): read it through its transpose so that
+          // both operands run along K in memory
+          L.zb.seg(Inv + f.inv_off[pk], int(mk), true, S + row_start + c0 * mk, int(mk), false, int(mk));
         }
         L.cps.push_back({row_start, zoff, mk * width});
         // Schur targets (i, j), i before or equal to j, both in row k
@@ -124,32 +132,44 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       std::sort(recs.begin(), recs.end(), [](const SchurRec& x, const SchurRec& y) {
         return x.target < y.target || (x.target == y.target && x.kpos < y.kpos);
       });
+      L.ssegs.reserve(recs.size());
       for (size_t r = 0; r < recs.size();) {
         const i64 tb = recs[r].target;
         const i64 mi = mb[cl(row_of[tb])], mj = mb[sp.colidx[tb]];
-        GemmItem& it = L.sb.item(int(mi), int(mj), int(mi), int(mj));
-        GemmBatch::set_out(it, 0, S + sp.blk_off[tb], mi, false);
-        for (; r < recs.size() && recs[r].target == tb; ++r)
-          L.sb.seg(S + sp.blk_off[recs[r].a_blk], recs[r].mk, true, Z + recs[r].z_off, recs[r].mk, false,
-                   recs[r].mk);
+        SchurItem si{sp.blk_off[tb], int32_t(mi), int32_t(mj), int32_t(L.ssegs.size()), 0};
+        for (; r < recs.size() && recs[r].target == tb; ++r) {
+          L.ssegs.push_back({sp.blk_off[recs[r].a_blk], int32_t(recs[r].z_off), recs[r].mk});
+          fl_s += 2.0 * mi * mj * recs[r].mk;
+        }
+        si.seg_end = int32_t(L.ssegs.size());
+        const uint32_t item = uint32_t(L.sitems.size());
+        for (int a = 0; a < (mi + 63) / 64; ++a)
+          for (int b = 0; b < (mj + 63) / 64; ++b) L.stiles.push_back(int32_t((item << 8) | (a << 4) | b));
+        L.sitems.push_back(si);
       }
-      fl_s += L.sb.flops;
+      if (L.sitems.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "Schur level above 2^24 targets");
     }
   }
   f.flops_inv += fl_inv;
   f.flops_z += fl_z;
   f.flops_schur += fl_s;
+  tt.lap("plan-levels");
   {
     std::vector<GemmBatch*> all;
     std::vector<RawBlob> blobs;
     for (auto& L : lvls) {
       all.push_back(&L.zb);
-      all.push_back(&L.sb);
       blobs.push_back({L.inv.data(), L.inv.size() * sizeof(InvItem<T>), reinterpret_cast<const void**>(&L.d_inv)});
       blobs.push_back({L.cps.data(), L.cps.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_cps)});
+      blobs.push_back({L.sitems.data(), L.sitems.size() * sizeof(SchurItem),
+                       reinterpret_cast<const void**>(&L.d_sitems)});
+      blobs.push_back({L.ssegs.data(), L.ssegs.size() * sizeof(SchurSeg), reinterpret_cast<const void**>(&L.d_ssegs)});
+      blobs.push_back({L.stiles.data(), L.stiles.size() * sizeof(int32_t),
+                       reinterpret_cast<const void**>(&L.d_stiles)});
     }
     upload_batches(all, f.dDesc, blobs);
   }
+  tt.lap("upload");
   std::vector<hipEvent_t> ev;
   auto mark_ev = [&]() {
     hipEvent_t e;
@@ -163,13 +183,20 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
     L.zb.template launch<T>(st, dim, 0.0, 0.0);
     mark_ev();
-    L.sb.template launch<T>(st, dim, 0.0, 0.0);
+    SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z};
+    launch_schur<T>(sl, st);
     mark_ev();
     launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
   }
   HIPCHECK(hipGetLastError());
   mark_ev();
+  tt.lap("enqueue");
   HIPCHECK(hipEventSynchronize(ev.back()));
+  tt.lap("device");
+  for (auto& L : lvls) {
+    std::vector<SchurItem>().swap(L.sitems);
+    std::vector<SchurSeg>().swap(L.ssegs);
+  }
   double piv_ms = 0, schur_ms = 0;
   for (int lv = 0; lv < f.nflev; ++lv) {
     float a = 0, b = 0;

@@ -24,6 +24,17 @@ void check_hip(hipError_t e, const char* what);
 
 hipStream_t current_stream();
 
+// Host-side phase timer: with H2SP_TRACE=1 in the environment each phase's
+// wall time is printed to stderr as "[h2sp] <name> <ms> ms".
+struct TraceTimer {
+  const char* name;
+  double t0;
+  explicit TraceTimer(const char* n);
+  void lap(const char* what);
+  ~TraceTimer();
+};
+bool trace_enabled();
+
 // ---------------------------------------------------------------- cluster tree
 // Heap numbering: root 0, sons of c are 2c+1 and 2c+2; every leaf at depth L.
 struct Tree {

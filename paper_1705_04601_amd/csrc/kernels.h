@@ -41,6 +41,7 @@ enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1, GEMM_SUB = 2 };
 enum GemmRole { ROLE_TRANSFORM = 0, ROLE_FACTOR = 1, ROLE_SOLVE = 2, ROLE_MATVEC = 3 };
 
 struct GemmLaunch {
+  int kc;                 // 1: every segment has opA = 1, opB = 0 and no generated A
   const GemmItem* items;
   const GemmSeg* segs;
   const int32_t* tiles;   // per work-group: (item << 8) | (tile_row << 4) | tile_col
@@ -53,6 +54,29 @@ struct GemmLaunch {
 
 template <class T>
 void launch_gemm(const GemmLaunch& g, hipStream_t st);
+
+// Compact work list of the Schur update S_ij -= S_ki^T Z_kj (offsets in
+// elements into S and into the Z buffer; every operand has leading dimension
+// equal to its row count).  Tiles: (item << 8) | (tile_row << 4) | tile_col,
+// 64 x 64 tiles.
+struct SchurItem {
+  int64_t out_off;
+  int32_t M, N, seg_begin, seg_end;
+};
+struct SchurSeg {
+  int64_t a_off;
+  int32_t z_off, K;
+};
+struct SchurLaunch {
+  const SchurItem* items;
+  const SchurSeg* segs;
+  const int32_t* tiles;
+  int32_t ntiles;
+  void* S;
+  const void* Z;
+};
+template <class T>
+void launch_schur(const SchurLaunch& g, hipStream_t st);
 
 // Householder QR of one cluster basis B (n x r, column-major, ld n), n <= 128,
 // r <= 64.  Writes the explicit square Q (n x n, ld n) and R^ = rows 0..k-1 of

@@ -157,6 +157,142 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmLaunch g) {
       }
 }
 
+// K-contiguous variant: A stored K x M (op(A) = A^T) and B stored K x N, so
+// both operands run along K in memory.  No LDS: lane l loads 4 consecutive k
+// (k0 + 4(l/16) .. +3) of its row of A and of its column of B and feeds them
+// to 4 consecutive MFMAs.  Inside one instruction the four lane groups then
+// carry k = k0 + 4g + s (g = 0..3) for step s: A and B agree on that
+// permutation of K, and the four steps cover all 16 values of k.  A wave owns
+// a tile of up to 4 x 4 MFMA blocks (64 x 64), sized to the item so that
+// blocks of 48 or 16 rows waste no lanes.
+template <class T> struct Vec4;
+template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4), aligned(4))); };
+template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4), aligned(8))); };
+
+template <class T>
+__device__ __forceinline__ void load4(const T* p, int k, int K, bool ok, T* v) {
+  if (ok && k + 3 < K) {
+    const typename Vec4<T>::type x = *reinterpret_cast<const typename Vec4<T>::type*>(p + k);
+    v[0] = x[0];
+    v[1] = x[1];
+    v[2] = x[2];
+    v[3] = x[3];
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = (ok && k + s < K) ? p[k + s] : T(0);
+  }
+}
+
+constexpr int KT = 64;  // tile edge of the K-contiguous kernels
+
+// acc[bm][bn] += A^T(rows m0 + 16 bm ..) B(cols n0 + 16 bn ..) over one segment.
+template <class T>
+__device__ __forceinline__ void kc_segment(typename Mfma<T>::V (&acc)[4][4], int nbm, int nbn, const T* A,
+                                           int lda, const T* B, int ldb, int K, int m0, int n0, int M, int N,
+                                           int lane) {
+  const int r = lane % 16, kq = 4 * (lane / 16);
+  const T* pa[4];
+  const T* pb[4];
+  bool oa[4], ob[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int ra = m0 + 16 * b + r, cb = n0 + 16 * b + r;
+    oa[b] = b < nbm && ra < M;
+    ob[b] = b < nbn && cb < N;
+    pa[b] = A + int64_t(oa[b] ? ra : 0) * lda;
+    pb[b] = B + int64_t(ob[b] ? cb : 0) * ldb;
+  }
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const int k = k0 + kq;
+    T a[4][4], bv[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b < nbm) load4<T>(pa[b], k, K, oa[b], a[b]);
+      if (b < nbn) load4<T>(pb[b], k, K, ob[b], bv[b]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 4; ++bn)
+          if (bm < nbm && bn < nbn) acc[bm][bn] = Mfma<T>::run(bv[bn][s], a[bm][s], acc[bm][bn]);
+  }
+}
+
+template <class T, int ROLE>
+__global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
+  using V = typename Mfma<T>::V;
+  const int lane = threadIdx.x;
+  const uint32_t code = static_cast<uint32_t>(g.tiles[blockIdx.x]);
+  const GemmItem it = g.items[code >> 8];
+  const int m0 = int((code >> 4) & 15) * KT, n0 = int(code & 15) * KT;
+  const int nbm = min(4, (it.M - m0 + 15) / 16), nbn = min(4, (it.N - n0 + 15) / 16);
+  V acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = V{0, 0, 0, 0};
+  for (int si = it.seg_begin; si < it.seg_end; ++si) {
+    const GemmSeg sg = g.segs[si];
+    kc_segment<T>(acc, nbm, nbn, static_cast<const T*>(sg.A), sg.lda, static_cast<const T*>(sg.B), sg.ldb, sg.K, m0,
+                  n0, it.M, it.N, lane);
+  }
+#pragma unroll
+  for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 4; ++bn) {
+      if (bm >= nbm || bn >= nbn) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + 16 * bm + lane % 16;
+        const int col = n0 + 16 * bn + Mfma<T>::row(lane, v);
+        if (row >= it.M || col >= it.N) continue;
+        const int q = (row >= it.rs ? 2 : 0) + (col >= it.cs ? 1 : 0);
+        const int lr = row - (q >= 2 ? it.rs : 0), lc = col - ((q & 1) ? it.cs : 0);
+        const T val = acc[bm][bn][v];
+        store_out<T>(it, q, lr, lc, val, g.mode);
+        if (q == 0) store_out<T>(it, 4, lr, lc, val, g.mode);
+      }
+    }
+}
+
+// Schur update of the block factorisation with compact descriptors:
+// S[out] (M x N, ld M) -= sum_seg S[a]^T (K x M, ld K) Z[z] (K x N, ld K).
+template <class T>
+__global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
+  using V = typename Mfma<T>::V;
+  const int lane = threadIdx.x;
+  const uint32_t code = static_cast<uint32_t>(g.tiles[blockIdx.x]);
+  const SchurItem it = g.items[code >> 8];
+  const int m0 = int((code >> 4) & 15) * KT, n0 = int(code & 15) * KT;
+  const int nbm = min(4, (it.M - m0 + 15) / 16), nbn = min(4, (it.N - n0 + 15) / 16);
+  T* S = static_cast<T*>(g.S);
+  const T* Z = static_cast<const T*>(g.Z);
+  V acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = V{0, 0, 0, 0};
+  for (int si = it.seg_begin; si < it.seg_end; ++si) {
+    const SchurSeg sg = g.segs[si];
+    kc_segment<T>(acc, nbm, nbn, S + sg.a_off, sg.K, Z + sg.z_off, sg.K, sg.K, m0, n0, it.M, it.N, lane);
+  }
+  T* out = S + it.out_off;
+#pragma unroll
+  for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 4; ++bn) {
+      if (bm >= nbm || bn >= nbn) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + 16 * bm + lane % 16;
+        const int col = n0 + 16 * bn + Mfma<T>::row(lane, v);
+        if (row < it.M && col < it.N) out[row + int64_t(col) * it.M] -= acc[bm][bn][v];
+      }
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -410,6 +546,15 @@ int grid_for(int64_t n) {
 template <class T>
 void launch_gemm(const GemmLaunch& g, hipStream_t st) {
   if (g.ntiles <= 0) return;
+  if (g.kc) {
+    switch (g.role) {
+      case ROLE_FACTOR: hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE_FACTOR>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+      case ROLE_SOLVE: hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE_SOLVE>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+      case ROLE_MATVEC: hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE_MATVEC>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+      default: hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE_TRANSFORM>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+    }
+    return;
+  }
   switch (g.role) {
     case ROLE_FACTOR: hipLaunchKernelGGL((gemm_kernel<T, ROLE_FACTOR>), dim3(g.ntiles), dim3(64), 0, st, g); break;
     case ROLE_SOLVE: hipLaunchKernelGGL((gemm_kernel<T, ROLE_SOLVE>), dim3(g.ntiles), dim3(64), 0, st, g); break;
@@ -419,6 +564,14 @@ void launch_gemm(const GemmLaunch& g, hipStream_t st) {
 }
 template void launch_gemm<double>(const GemmLaunch&, hipStream_t);
 template void launch_gemm<float>(const GemmLaunch&, hipStream_t);
+
+template <class T>
+void launch_schur(const SchurLaunch& g, hipStream_t st) {
+  if (g.ntiles <= 0) return;
+  hipLaunchKernelGGL(schur_kernel<T>, dim3(g.ntiles), dim3(64), 0, st, g);
+}
+template void launch_schur<double>(const SchurLaunch&, hipStream_t);
+template void launch_schur<float>(const SchurLaunch&, hipStream_t);
 
 void launch_qr(const QrItem* items, int count, hipStream_t st) {
   if (count <= 0) return;

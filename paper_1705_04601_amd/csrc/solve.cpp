@@ -25,6 +25,7 @@ MatvecPlanView matvec_buffers(MatvecPlan& p);
 
 template <class T>
 static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
+  TraceTimer tt("solve-plan");
   h2_sparse& sp = *f.sp;
   h2_matrix& H = *sp.H;
   const Tree& tr = H.tree;
@@ -127,7 +128,7 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
     const i64 c = sp.eorder[pos];
     GemmItem& it = p->diag.item(int(mb[c]), N, int(mb[c]), N);
     GemmBatch::set_out(it, 0, w + sp.soff[c], n, false);
-    p->diag.seg(Inv + f.inv_off[pos], int(mb[c]), false, y + sp.soff[c], int(n), false, int(mb[c]));
+    p->diag.seg(Inv + f.inv_off[pos], int(mb[c]), true, y + sp.soff[c], int(n), false, int(mb[c]));
   }
   p->bwd.resize(f.nblev);
   for (int lv = 0; lv < f.nblev; ++lv) {

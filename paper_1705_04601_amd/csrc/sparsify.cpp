@@ -38,6 +38,7 @@ struct SymStrip {
 }  // namespace
 
 static h2_sparse* plan(h2_matrix* H, int precision) {
+  TraceTimer tt("sparsify-plan");
   H->upload_all();
   auto spp = std::make_unique<h2_sparse>();
   h2_sparse& sp = *spp;
@@ -150,6 +151,7 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
         csize[k + 1] += n_act[pr.t] * n_act[pr.s];
       }
   }
+  tt.lap("symbolic");
   // ---- upper block pattern in the elimination order
   std::sort(blocks.begin(), blocks.end(), [&](const auto& a, const auto& b) {
     return epos[a.first] < epos[b.first] ||
@@ -225,6 +227,7 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
   }
   sp.dTmp.reset(el * kTmpChunkEntries);
 
+  tt.lap("pattern+arenas");
   // ---- per-level work lists with device pointers
   const double* X = H->d_x.as<double>();
   const double* nodes = H->d_nodes.as<double>();
@@ -411,8 +414,10 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
     blobs.push_back({lv.qr.items.data(), lv.qr.items.size() * sizeof(QrItem),
                      reinterpret_cast<const void**>(&lv.qr.d_items)});
   }
+  tt.lap("work-lists");
   HIPCHECK(hipStreamSynchronize(current_stream()));
   upload_batches(all, sp.dDesc, blobs);
+  tt.lap("upload");
   for (auto& lv : sp.levels) std::vector<QrItem>().swap(lv.qr.items);
   return spp.release();
 }
