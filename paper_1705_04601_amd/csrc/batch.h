@@ -22,7 +22,7 @@ struct GemmBatch {
   const GemmSeg* d_segs = nullptr;
   const int32_t* d_tiles = nullptr;
   int32_t ntiles = 0;
-  bool kc = false;     // every segment K-contiguous (A stored K x M, B K x N)
+  bool kc = true;      // direct kernel (64 x 64 tiles, no LDS); false: LDS-staged kernel
   int mode = GEMM_STORE;
   int role = ROLE_TRANSFORM;
   double flops = 0.0;  // algorithmic flops of the batch
@@ -88,12 +88,7 @@ struct GemmBatch {
   // (they then write zeros).
   void build_tiles() {
     tiles.clear();
-    kc = !segs.empty();
-    for (const GemmSeg& s : segs)
-      if (s.gen || s.opA != 1 || s.opB != 0) {
-        kc = false;
-        break;
-      }
+    kc = true;  // the direct (no-LDS) kernel serves every operand layout
     if (items.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "GEMM batch above 2^24 items");
     for (size_t i = 0; i < items.size(); ++i) {
       const GemmItem& it = items[i];

@@ -42,12 +42,23 @@ template <> struct Mfma<float> {
 
 constexpr int TM = 32, TN = 32, KC = 16;
 
+// Destination q of an item, selected with constant indices only (a dynamic
+// index into the item's arrays would move the item to scratch memory).
 template <class T>
 __device__ __forceinline__ void store_out(const GemmItem& it, int q, int lr, int lc, T v, int mode) {
-  T* base = static_cast<T*>(it.out[q]);
+  void* b;
+  int64_t ld;
+  bool tr;
+  switch (q) {
+    case 0: b = it.out[0]; ld = it.ld[0]; tr = it.trans[0]; break;
+    case 1: b = it.out[1]; ld = it.ld[1]; tr = it.trans[1]; break;
+    case 2: b = it.out[2]; ld = it.ld[2]; tr = it.trans[2]; break;
+    case 3: b = it.out[3]; ld = it.ld[3]; tr = it.trans[3]; break;
+    default: b = it.out[4]; ld = it.ld[4]; tr = it.trans[4]; break;
+  }
+  T* base = static_cast<T*>(b);
   if (!base) return;
-  const int64_t ld = it.ld[q];
-  T* p = it.trans[q] ? base + lc + lr * ld : base + lr + lc * ld;
+  T* p = tr ? base + lc + lr * ld : base + lr + lc * ld;
   if (mode == GEMM_STORE) *p = v;
   else if (mode == GEMM_ADD) *p += v;
   else *p -= v;
@@ -220,6 +231,81 @@ __device__ __forceinline__ void kc_segment(typename Mfma<T>::V (&acc)[4][4], int
   }
 }
 
+// Operand fetch of the direct kernel for one 16-row (or 16-column) block and
+// the four k of this lane: K-contiguous rows (vector load), M-contiguous
+// columns (one load per k, coalesced across the 16 lanes of a group) or
+// generated kernel values.
+template <class T, int MODE>
+__device__ __forceinline__ void fetch4(const T* p, int64_t ld, int row, int k, int K, bool ok, T* v,
+                                       const double* pr, const double* pc, int dim, double scale, double dg,
+                                       bool diag) {
+  if (MODE == 0) {          // element (row, k) at p[k + row ld]
+    load4<T>(p, k, K, ok, v);
+  } else if (MODE == 1) {   // element (row, k) at p[row + k ld]
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = (ok && k + s < K) ? p[row + int64_t(k + s) * ld] : T(0);
+  } else {                  // generated: scale / |pr_row - pc_k|, dg on the diagonal
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      T val = T(0);
+      if (ok && k + s < K) {
+        if (diag && row == k + s) {
+          val = T(dg);
+        } else {
+          double d2 = 0.0;
+          for (int a = 0; a < dim; ++a) {
+            const double d = pr[row * dim + a] - pc[(k + s) * dim + a];
+            d2 += d * d;
+          }
+          val = T(scale / sqrt(d2));
+        }
+      }
+      v[s] = val;
+    }
+  }
+}
+
+// acc += op(A) op(B) for one segment; AM / BM select the fetch of each operand.
+template <class T, int AM, int BM>
+__device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[4][4], int nbm, int nbn,
+                                               const GemmSeg& sg, int m0, int n0, int M, int N, int lane,
+                                               int dim, double scale, double dg) {
+  const int r = lane % 16, kq = 4 * (lane / 16);
+  const T* A = static_cast<const T*>(sg.A);
+  const T* B = static_cast<const T*>(sg.B);
+  const double* pr = static_cast<const double*>(sg.A);
+  const int K = sg.K;
+  const T* pa[4];
+  const T* pb[4];
+  int ra[4], cb[4];
+  bool oa[4], ob[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    ra[b] = m0 + 16 * b + r;
+    cb[b] = n0 + 16 * b + r;
+    oa[b] = b < nbm && ra[b] < M;
+    ob[b] = b < nbn && cb[b] < N;
+    pa[b] = (AM == 0) ? A + int64_t(oa[b] ? ra[b] : 0) * sg.lda : A;
+    pb[b] = (BM == 0) ? B + int64_t(ob[b] ? cb[b] : 0) * sg.ldb : B;
+  }
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const int k = k0 + kq;
+    T a[4][4], bv[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b < nbm) fetch4<T, AM>(pa[b], sg.lda, ra[b], k, K, oa[b], a[b], pr, sg.pc, dim, scale, dg, sg.diag);
+      if (b < nbn) fetch4<T, BM>(pb[b], sg.ldb, cb[b], k, K, ob[b], bv[b], nullptr, nullptr, 0, 0.0, 0.0, false);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 4; ++bn)
+          if (bm < nbm && bn < nbn) acc[bm][bn] = Mfma<T>::run(bv[bn][s], a[bm][s], acc[bm][bn]);
+  }
+}
+
 template <class T, int ROLE>
 __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
   using V = typename Mfma<T>::V;
@@ -235,8 +321,22 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
     for (int b = 0; b < 4; ++b) acc[a][b] = V{0, 0, 0, 0};
   for (int si = it.seg_begin; si < it.seg_end; ++si) {
     const GemmSeg sg = g.segs[si];
-    kc_segment<T>(acc, nbm, nbn, static_cast<const T*>(sg.A), sg.lda, static_cast<const T*>(sg.B), sg.ldb, sg.K, m0,
-                  n0, it.M, it.N, lane);
+    // operand layouts: A K-contiguous (opA = 1), M-contiguous (opA = 0) or
+    // generated; B K-contiguous (opB = 0) or N-contiguous (opB = 1)
+    const int am = sg.gen ? 2 : (sg.opA ? 0 : 1);
+    const int bmode = sg.opB ? 1 : 0;
+    if (am == 0 && bmode == 0)
+      direct_segment<T, 0, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+    else if (am == 1 && bmode == 0)
+      direct_segment<T, 1, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+    else if (am == 2 && bmode == 0)
+      direct_segment<T, 2, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+    else if (am == 0)
+      direct_segment<T, 0, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+    else if (am == 1)
+      direct_segment<T, 1, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+    else
+      direct_segment<T, 2, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
   }
 #pragma unroll
   for (int bm = 0; bm < 4; ++bm)
