@@ -30,6 +30,9 @@ import h2inputs  # noqa: E402
 
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense MFMA (FP32 / FP64)
 PHASES = ["qr", "close", "couplings", "strips", "factor_pivots_z", "factor_schur"]
+KERNELS = {"qr": "qr_kernel", "close": "gemm_kc_kernel<float, 0>", "couplings": "gemm_kc_kernel<float, 0>",
+           "strips": "gemm_kc_kernel<float, 0>", "factor_pivots_z": "inverse_kernel<float> + gemm_kc_kernel<float, 1>",
+           "factor_schur": "schur_kernel<float>"}
 
 
 def log(msg):
@@ -165,7 +168,7 @@ def main():
     achieved = fl[dom] / (ms[dom] * 1e-3) / 1e12
     peak = PEAK_TFLOPS["f64"] if PHASES[dom] == "qr" else PEAK_TFLOPS["f32"]
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": f"{PHASES[dom]} (gemm_kernel)",
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": f"{PHASES[dom]}: {KERNELS[PHASES[dom]]}",
                 "phase_ms": {p: round(float(v), 3) for p, v in zip(PHASES, ms)},
                 "phase_tflops": {p: round(float(f / (m * 1e-3) / 1e12), 3) if m > 0 else None
                                  for p, f, m in zip(PHASES, fl, ms)}}
@@ -190,6 +193,8 @@ def main():
         "mixed": {"t_sparsify": last["t_sparsify"], "t_factor_S": last["t_factor"],
                   "t_solve": last["t_solve"], "factor_plus_solve_s": sec,
                   "iters": last["info"]["iters"], "rel_residual": last["info"]["residual"],
+                  "solve_device_s": {"precond": last["info"]["t_precond"], "matvec": last["info"]["t_matvec"],
+                                     "plan_host": last["info"]["t_plan"]},
                   "rhs_n_per_s_solve": nrhs * n / last["t_solve"]},
         "s_blocks": last["s_blocks"], "s_entries": last["s_entries"],
         "h2_build_s": t_build,

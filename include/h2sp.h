@@ -71,7 +71,9 @@ typedef struct {
 typedef struct {
   int iters;                   /* refinement steps taken                         */
   double max_rel_residual;     /* final max_col ||b - A_H2 x|| / ||b||            */
-  double seconds[3];           /* U^T / S-solve / V sweeps, matvec: not filled    */
+  double seconds[3];           /* device s of the preconditioner applications
+                                  (U^T, triangular solves, V), of the FP64 H^2
+                                  matvecs, and host s building the plans       */
 } h2_solve_info;
 
 typedef struct h2_matrix h2_matrix;   /* tree, block tree, H^2 coefficients       */

@@ -276,7 +276,8 @@ def h2_solve(f: H2FactorHandle, b, x, tol: float = 1e-10, max_iter: int = 30, ch
     code = lib().h2_solve(f.ptr, _dev(b), _dev(x), nrhs, ld, ctypes.byref(o), ctypes.byref(info))
     if check or code not in (H2_OK, H2_ENOCONV):
         _check(code)
-    return dict(iters=info.iters, residual=info.max_rel_residual, code=code)
+    return dict(iters=info.iters, residual=info.max_rel_residual, code=code,
+                t_precond=info.seconds[0], t_matvec=info.seconds[1], t_plan=info.seconds[2])
 
 
 def h2_apply_inverse(f: H2FactorHandle, b, x):

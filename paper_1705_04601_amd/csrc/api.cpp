@@ -57,6 +57,19 @@ extern "C" int h2_sparsify(h2_matrix* h, const h2_sparsify_opts* opts, h2_sparse
   std::unique_ptr<h2_sparse> sp(plan_sparsify(h, prec));
   std::fill(g_timings, g_timings + 8, 0.0);
   run_sparsify(*sp, current_stream(), g_timings);
+  HIPCHECK(hipStreamSynchronize(current_stream()));
+  // only Q_t (for U and V) and S outlive the sweep
+  for (int side = 0; side < 2; ++side) {
+    sp->dC[side].reset(0);
+    sp->dG[side].reset(0);
+  }
+  sp->dTmp.reset(0);
+  sp->dB.reset(0);
+  sp->dW.reset(0);
+  sp->dWt.reset(0);
+  sp->dRhat.reset(0);
+  sp->dDesc.reset(0);
+  sp->levels.clear();
   const PlanCounts& pc = sp->counts;
   g_work[0] = pc.flops_qr + pc.flops_misc;
   g_work[1] = pc.flops_close;

@@ -132,9 +132,12 @@ struct RawBlob {
 
 // Builds the tile lists, copies every batch's items, segments and tiles (and the
 // extra blobs) into one device buffer `store`, and points the batches at it.
-// Synchronous: the host arrays may be released afterwards.
+// The host arrays may be released on return.  With a copy stream the transfer
+// runs there and `wait` (the compute stream) is made to wait for it, so that
+// kernels already queued on `wait` keep running during the copy.
 inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& store,
-                           const std::vector<RawBlob>& extra = {}) {
+                           const std::vector<RawBlob>& extra = {}, hipStream_t copy = nullptr,
+                           hipStream_t wait = nullptr, bool parallel_pack = true) {
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   size_t total = 0;
   std::vector<size_t> off(bs.size() * 3);
@@ -155,18 +158,28 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
   if (total == 0) return;
   std::unique_ptr<char[]> staging_buf(new char[total]);  // no zero fill
   char* staging = staging_buf.get();
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) if (parallel_pack)
   for (long i = 0; i < long(bs.size()); ++i) {
     GemmBatch& b = *bs[i];
     if (!b.items.empty()) std::memcpy(&staging[off[3 * i]], b.items.data(), b.items.size() * sizeof(GemmItem));
     if (!b.segs.empty()) std::memcpy(&staging[off[3 * i + 1]], b.segs.data(), b.segs.size() * sizeof(GemmSeg));
     if (!b.tiles.empty()) std::memcpy(&staging[off[3 * i + 2]], b.tiles.data(), b.tiles.size() * sizeof(int32_t));
   }
-#pragma omp parallel for schedule(dynamic, 4)
+#pragma omp parallel for schedule(dynamic, 4) if (parallel_pack)
   for (long i = 0; i < long(extra.size()); ++i)
     if (extra[i].bytes) std::memcpy(&staging[xoff[i]], extra[i].host, extra[i].bytes);
   store.reset(total);
-  HIPCHECK(hipMemcpy(store.ptr, staging, total, hipMemcpyHostToDevice));
+  if (copy) {
+    HIPCHECK(hipMemcpyAsync(store.ptr, staging, total, hipMemcpyHostToDevice, copy));
+    hipEvent_t done;
+    HIPCHECK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(done, copy));
+    HIPCHECK(hipStreamWaitEvent(wait, done, 0));
+    HIPCHECK(hipStreamSynchronize(copy));  // the staging buffer is released below
+    HIPCHECK(hipEventDestroy(done));
+  } else {
+    HIPCHECK(hipMemcpy(store.ptr, staging, total, hipMemcpyHostToDevice));
+  }
   char* base = static_cast<char*>(store.ptr);
   for (size_t i = 0; i < bs.size(); ++i) {
     bs[i]->d_items = reinterpret_cast<const GemmItem*>(base + off[3 * i]);

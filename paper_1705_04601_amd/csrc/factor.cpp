@@ -13,10 +13,17 @@
 //      pivot of the level, one work item per target, the pivots as K-segments
 //      in elimination order (no atomics: the result is deterministic);
 //   4. Z replaces the pivot rows of S.
-// All levels are planned on the host first (in parallel), their work lists
-// copied to the device in one piece, then launched back to back.
+// The levels are planned on the host in chunks by a producer thread (each
+// chunk in parallel over its levels); the calling thread uploads every planned
+// chunk on a copy stream and queues its launches, so host planning overlaps the
+// device work of the chunks before it.
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstring>
+#include <exception>
+#include <mutex>
+#include <thread>
 
 #include "factor.h"
 
@@ -81,6 +88,14 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
 
   std::vector<FactorLevel<T>> lvls(f.nflev);
   double fl_inv = 0, fl_z = 0, fl_s = 0;
+  int too_wide = 0;
+  // per-level completion flags of the planning, read by the uploading thread
+  std::unique_ptr<std::atomic<int>[]> ready(new std::atomic<int>[f.nflev]);
+  for (int lv = 0; lv < f.nflev; ++lv) ready[lv] = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  // plans every level, dynamically scheduled in level order (parallel)
+  auto plan_all = [&]() {
 #pragma omp parallel reduction(+ : fl_inv, fl_z, fl_s)
   {
     std::vector<i64> mark(ncl, -1);
@@ -147,29 +162,16 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
           for (int b = 0; b < (mj + 63) / 64; ++b) L.stiles.push_back(int32_t((item << 8) | (a << 4) | b));
         L.sitems.push_back(si);
       }
-      if (L.sitems.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "Schur level above 2^24 targets");
+      if (L.sitems.size() >= (size_t(1) << 24)) too_wide = 1;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        ready[lv] = 1;
+      }
+      cv.notify_one();
     }
   }
-  f.flops_inv += fl_inv;
-  f.flops_z += fl_z;
-  f.flops_schur += fl_s;
-  tt.lap("plan-levels");
-  {
-    std::vector<GemmBatch*> all;
-    std::vector<RawBlob> blobs;
-    for (auto& L : lvls) {
-      all.push_back(&L.zb);
-      blobs.push_back({L.inv.data(), L.inv.size() * sizeof(InvItem<T>), reinterpret_cast<const void**>(&L.d_inv)});
-      blobs.push_back({L.cps.data(), L.cps.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_cps)});
-      blobs.push_back({L.sitems.data(), L.sitems.size() * sizeof(SchurItem),
-                       reinterpret_cast<const void**>(&L.d_sitems)});
-      blobs.push_back({L.ssegs.data(), L.ssegs.size() * sizeof(SchurSeg), reinterpret_cast<const void**>(&L.d_ssegs)});
-      blobs.push_back({L.stiles.data(), L.stiles.size() * sizeof(int32_t),
-                       reinterpret_cast<const void**>(&L.d_stiles)});
-    }
-    upload_batches(all, f.dDesc, blobs);
-  }
-  tt.lap("upload");
+  if (too_wide) fail(H2_EUNSUPPORTED, "Schur level above 2^24 targets");
+  };
   std::vector<hipEvent_t> ev;
   auto mark_ev = [&]() {
     hipEvent_t e;
@@ -177,26 +179,84 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     HIPCHECK(hipEventRecord(e, st));
     ev.push_back(e);
   };
+  // upload in runs of planned levels: as soon as the next level is ready,
+  // every ready level after it (up to kMaxRun) goes in one copy
+  constexpr int kMaxRun = 32;
+  std::vector<DeviceBuffer> chunk_desc;
+  chunk_desc.reserve(f.nflev);
+  std::exception_ptr perr;
+  bool done_planning = false;
+  std::thread producer([&] {
+    try {
+      plan_all();
+    } catch (...) {
+      perr = std::current_exception();
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    done_planning = true;
+    cv.notify_one();
+  });
+  hipStream_t cstream = nullptr;
+  HIPCHECK(hipStreamCreateWithFlags(&cstream, hipStreamNonBlocking));  // no implicit sync with the null stream
   mark_ev();
-  for (int lv = 0; lv < f.nflev; ++lv) {
-    FactorLevel<T>& L = lvls[lv];
-    launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
-    L.zb.template launch<T>(st, dim, 0.0, 0.0);
-    mark_ev();
-    SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z};
-    launch_schur<T>(sl, st);
-    mark_ev();
-    launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
+  try {
+    int next = 0;
+    while (next < f.nflev) {
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return ready[next] != 0 || done_planning; });
+        if (!ready[next]) break;  // planning stopped early (error)
+      }
+      int end = next + 1;
+      while (end < f.nflev && end - next < kMaxRun && ready[end]) ++end;
+      std::vector<GemmBatch*> all;
+      std::vector<RawBlob> blobs;
+      for (int lv = next; lv < end; ++lv) {
+        FactorLevel<T>& L = lvls[lv];
+        all.push_back(&L.zb);
+        blobs.push_back({L.inv.data(), L.inv.size() * sizeof(InvItem<T>), reinterpret_cast<const void**>(&L.d_inv)});
+        blobs.push_back({L.cps.data(), L.cps.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_cps)});
+        blobs.push_back({L.sitems.data(), L.sitems.size() * sizeof(SchurItem),
+                         reinterpret_cast<const void**>(&L.d_sitems)});
+        blobs.push_back({L.ssegs.data(), L.ssegs.size() * sizeof(SchurSeg),
+                         reinterpret_cast<const void**>(&L.d_ssegs)});
+        blobs.push_back({L.stiles.data(), L.stiles.size() * sizeof(int32_t),
+                         reinterpret_cast<const void**>(&L.d_stiles)});
+      }
+      chunk_desc.emplace_back();
+      upload_batches(all, chunk_desc.back(), blobs, cstream, st, /*parallel_pack=*/false);
+      for (int lv = next; lv < end; ++lv) {
+        FactorLevel<T>& L = lvls[lv];
+        launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
+        L.zb.template launch<T>(st, dim, 0.0, 0.0);
+        mark_ev();
+        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z};
+        launch_schur<T>(sl, st);
+        mark_ev();
+        launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
+        std::vector<SchurItem>().swap(L.sitems);
+        std::vector<SchurSeg>().swap(L.ssegs);
+        std::vector<int32_t>().swap(L.stiles);
+      }
+      next = end;
+    }
+  } catch (...) {
+    producer.join();
+    (void)hipStreamDestroy(cstream);
+    throw;
   }
+  producer.join();
+  HIPCHECK(hipStreamDestroy(cstream));
+  if (perr) std::rethrow_exception(perr);
+  if (int(ev.size()) != 2 * f.nflev + 1) fail(H2_EINVAL, "internal: factorisation stopped early");
+  f.flops_inv += fl_inv;
+  f.flops_z += fl_z;
+  f.flops_schur += fl_s;
+  tt.lap("plan+upload+enqueue");
   HIPCHECK(hipGetLastError());
   mark_ev();
-  tt.lap("enqueue");
   HIPCHECK(hipEventSynchronize(ev.back()));
-  tt.lap("device");
-  for (auto& L : lvls) {
-    std::vector<SchurItem>().swap(L.sitems);
-    std::vector<SchurSeg>().swap(L.ssegs);
-  }
+  tt.lap("device-drain");
   double piv_ms = 0, schur_ms = 0;
   for (int lv = 0; lv < f.nflev; ++lv) {
     float a = 0, b = 0;

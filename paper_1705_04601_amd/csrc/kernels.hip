@@ -196,41 +196,6 @@ __device__ __forceinline__ void load4(const T* p, int k, int K, bool ok, T* v) {
 
 constexpr int KT = 64;  // tile edge of the K-contiguous kernels
 
-// acc[bm][bn] += A^T(rows m0 + 16 bm ..) B(cols n0 + 16 bn ..) over one segment.
-template <class T>
-__device__ __forceinline__ void kc_segment(typename Mfma<T>::V (&acc)[4][4], int nbm, int nbn, const T* A,
-                                           int lda, const T* B, int ldb, int K, int m0, int n0, int M, int N,
-                                           int lane) {
-  const int r = lane % 16, kq = 4 * (lane / 16);
-  const T* pa[4];
-  const T* pb[4];
-  bool oa[4], ob[4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int ra = m0 + 16 * b + r, cb = n0 + 16 * b + r;
-    oa[b] = b < nbm && ra < M;
-    ob[b] = b < nbn && cb < N;
-    pa[b] = A + int64_t(oa[b] ? ra : 0) * lda;
-    pb[b] = B + int64_t(ob[b] ? cb : 0) * ldb;
-  }
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const int k = k0 + kq;
-    T a[4][4], bv[4][4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      if (b < nbm) load4<T>(pa[b], k, K, oa[b], a[b]);
-      if (b < nbn) load4<T>(pb[b], k, K, ob[b], bv[b]);
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int bm = 0; bm < 4; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 4; ++bn)
-          if (bm < nbm && bn < nbn) acc[bm][bn] = Mfma<T>::run(bv[bn][s], a[bm][s], acc[bm][bn]);
-  }
-}
-
 // Operand fetch of the direct kernel for one 16-row (or 16-column) block and
 // the four k of this lane: K-contiguous rows (vector load), M-contiguous
 // columns (one load per k, coalesced across the 16 lanes of a group) or
@@ -359,6 +324,21 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
 
 // Schur update of the block factorisation with compact descriptors:
 // S[out] (M x N, ld M) -= sum_seg S[a]^T (K x M, ld K) Z[z] (K x N, ld K).
+// The (segment, 16-wide k step) pairs form one chunk stream; the operands of
+// chunk c + 1 are loaded into a second register set while the MFMAs of chunk c
+// issue, so a wave keeps its loads in flight behind its own math.
+template <class T>
+__device__ __forceinline__ void schur_load(const T* S, const T* Z, const SchurSeg& sg, int k, int nbm, int nbn,
+                                           int m0, int n0, int M, int N, int r, T (&a)[4][4], T (&b)[4][4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int ra = m0 + 16 * q + r, cb = n0 + 16 * q + r;
+    const bool oa = q < nbm && ra < M, ob = q < nbn && cb < N;
+    if (q < nbm) load4<T>(S + sg.a_off + int64_t(oa ? ra : 0) * sg.K, k, sg.K, oa, a[q]);
+    if (q < nbn) load4<T>(Z + sg.z_off + int64_t(ob ? cb : 0) * sg.K, k, sg.K, ob, b[q]);
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
   using V = typename Mfma<T>::V;
@@ -367,6 +347,7 @@ __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
   const SchurItem it = g.items[code >> 8];
   const int m0 = int((code >> 4) & 15) * KT, n0 = int(code & 15) * KT;
   const int nbm = min(4, (it.M - m0 + 15) / 16), nbn = min(4, (it.N - n0 + 15) / 16);
+  const int r = lane % 16, kq = 4 * (lane / 16);
   T* S = static_cast<T*>(g.S);
   const T* Z = static_cast<const T*>(g.Z);
   V acc[4][4];
@@ -374,9 +355,44 @@ __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = V{0, 0, 0, 0};
-  for (int si = it.seg_begin; si < it.seg_end; ++si) {
-    const SchurSeg sg = g.segs[si];
-    kc_segment<T>(acc, nbm, nbn, S + sg.a_off, sg.K, Z + sg.z_off, sg.K, sg.K, m0, n0, it.M, it.N, lane);
+  int si = it.seg_begin, k0 = 0;
+  if (si < it.seg_end) {
+    SchurSeg sg = g.segs[si];
+    T a[4][4], b[4][4];
+    schur_load<T>(S, Z, sg, k0 + kq, nbm, nbn, m0, n0, it.M, it.N, r, a, b);
+    while (true) {
+      // position of the next chunk
+      int nsi = si, nk0 = k0 + 16;
+      if (nk0 >= sg.K) {
+        ++nsi;
+        nk0 = 0;
+      }
+      const bool more = nsi < it.seg_end;
+      SchurSeg nsg = sg;
+      T na[4][4], nb[4][4];
+      if (more) {
+        if (nsi != si) nsg = g.segs[nsi];
+        schur_load<T>(S, Z, nsg, nk0 + kq, nbm, nbn, m0, n0, it.M, it.N, r, na, nb);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < 4; ++bn)
+            if (bm < nbm && bn < nbn) acc[bm][bn] = Mfma<T>::run(b[bn][s], a[bm][s], acc[bm][bn]);
+      if (!more) break;
+      si = nsi;
+      k0 = nk0;
+      sg = nsg;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          a[q][s] = na[q][s];
+          b[q][s] = nb[q][s];
+        }
+    }
   }
   T* out = S + it.out_off;
 #pragma unroll

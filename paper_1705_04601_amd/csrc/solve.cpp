@@ -8,6 +8,7 @@
 // u_i = r_i - sum_k Z_ki^T u_k, diagonal v_i = D_i^{-1} u_i, backward
 // x_i = v_i - sum_j Z_ij x_j.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 
 #include "factor.h"
@@ -247,8 +248,18 @@ int solve_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld, const
   h2_matrix& H = *f->sp->H;
   const i64 n = H.tree.n;
   hipStream_t st = current_stream();
+  const auto t_plan0 = std::chrono::steady_clock::now();
   SolvePlan& p = solve_plan(*f, nrhs);
   MatvecPlan& mv = matvec_plan(H, nrhs);
+  const double plan_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_plan0).count();
+  // device time of the preconditioner applications and of the matvecs
+  std::vector<hipEvent_t> ev;
+  auto mark = [&]() {
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    HIPCHECK(hipEventRecord(e, st));
+    ev.push_back(e);
+  };
   MatvecPlanView mvb = matvec_buffers(mv);
   DeviceBuffer bt(sizeof(double) * n * nrhs), rt(sizeof(double) * n * nrhs), nrm(sizeof(double) * 2 * nrhs),
       cs(sizeof(double) * nrhs);
@@ -273,10 +284,13 @@ int solve_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld, const
       h_cs[j] = rn > 0 ? rn : 1.0;
     }
     HIPCHECK(hipMemcpyAsync(cs.ptr, h_cs.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    mark();
     correction(*f, p, rt.as<double>(), nullptr, 0, cs.as<double>(), st);
+    mark();
     // r = b - A x  (x = p.rs in tree order)
     launch_copy_cols(p.rs.as<double>(), n, mvb.xt, n, n, nrhs, st);
     run_matvec_tree(H, mv, st);
+    mark();
     launch_residual(bt.as<double>(), n, mvb.yt, n, rt.as<double>(), n, nrhs, nrm.as<double>(), st);
     HIPCHECK(hipMemcpyAsync(h_nrm.data(), nrm.ptr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
@@ -289,9 +303,21 @@ int solve_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld, const
   if (it > max_iter) it = max_iter;
   launch_scatter_rows(p.rs.as<double>(), n, H.d_perm.as<i64>(), x, ld, n, nrhs, st);
   HIPCHECK(hipStreamSynchronize(st));
+  double t_prec = 0, t_mv = 0;
+  for (size_t e = 0; e + 2 < ev.size(); e += 3) {
+    float a = 0, c = 0;
+    HIPCHECK(hipEventElapsedTime(&a, ev[e], ev[e + 1]));
+    HIPCHECK(hipEventElapsedTime(&c, ev[e + 1], ev[e + 2]));
+    t_prec += a * 1e-3;
+    t_mv += c * 1e-3;
+  }
+  for (auto e : ev) (void)hipEventDestroy(e);
   if (info) {
     info->iters = it;
     info->max_rel_residual = res;
+    info->seconds[0] = t_prec;
+    info->seconds[1] = t_mv;
+    info->seconds[2] = plan_s;
   }
   if (!(res <= tol)) return H2_ENOCONV;
   return H2_OK;

@@ -47,7 +47,6 @@ struct h2_sparse {
   std::vector<h2::i64> rowptr;     // by elimination position
   std::vector<h2::i64> colidx;     // cluster ids (sorted by elimination position)
   std::vector<h2::i64> blk_off;    // entry offset of each stored block
-  std::unordered_map<h2::i64, h2::i64> blk_index;  // t * ncl + s -> block number
   h2::i64 s_entries = 0;
   // arenas
   std::vector<h2::i64> q_off, b_off, rhat_off, w_off;
@@ -55,9 +54,17 @@ struct h2_sparse {
   std::vector<h2::SweepLevel> levels;
   h2::PlanCounts counts;
   size_t elem = 8;                 // bytes per S / transform element
+  // Block number of stored block (t, s), or -1: binary search in row epos[t]
+  // (columns sorted by elimination position).
   h2::i64 block_of(h2::i64 t, h2::i64 s) const {
-    auto it = blk_index.find(t * ncl + s);
-    return it == blk_index.end() ? -1 : it->second;
+    const h2::i64 ps = epos[s];
+    h2::i64 lo = rowptr[epos[t]], hi = rowptr[epos[t] + 1];
+    while (lo < hi) {
+      const h2::i64 mid = (lo + hi) / 2;
+      if (epos[colidx[mid]] < ps) lo = mid + 1;
+      else hi = mid;
+    }
+    return (lo < rowptr[epos[t] + 1] && colidx[lo] == s) ? lo : -1;
   }
 };
 

@@ -162,14 +162,12 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
   sp.rowptr.assign(ncl + 1, 0);
   sp.colidx.resize(blocks.size());
   sp.blk_off.resize(blocks.size());
-  sp.blk_index.reserve(blocks.size() * 2);
   i64 ent = 0;
   for (size_t b = 0; b < blocks.size(); ++b) {
     const i64 t = blocks[b].first, s = blocks[b].second;
     sp.rowptr[epos[t] + 1]++;
     sp.colidx[b] = s;
     sp.blk_off[b] = ent;
-    sp.blk_index[key(t, s, ncl)] = i64(b);
     ent += mb[t] * mb[s];
   }
   for (i64 i = 0; i < ncl; ++i) sp.rowptr[i + 1] += sp.rowptr[i];
@@ -244,7 +242,7 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
   const double* basis = H->d_basis.as<double>();
   const double* transfer = H->d_transfer.as<double>();
   const double* proj = H->d_proj.as<double>();
-  PlanCounts& pc = sp.counts;
+  std::vector<PlanCounts> lpc(L + 1);
   sp.levels.resize(L + 1);
   auto blk_ptr = [&](i64 t, i64 s) -> void* {
     const i64 b = sp.block_of(t, s);
@@ -257,7 +255,13 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
     if (epos[t] <= epos[s]) GemmBatch::set_out(it, q, blk_ptr(t, s), mb[t], false);
     else GemmBatch::set_out(it, q, blk_ptr(s, t), mb[s], true);
   };
+  // levels are independent once slots and offsets are fixed: build in parallel
+  std::string first_error;
+  int first_code = 0;
+#pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k <= L; ++k) {
+   try {
+    PlanCounts& pc = lpc[k];
     SweepLevel& lv = sp.levels[k];
     char* Ccur = static_cast<char*>(sp.dC[k % 2].ptr);
     char* Cnext = static_cast<char*>(sp.dC[(k + 1) % 2].ptr);
@@ -399,6 +403,22 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
       for (auto& g : lv.coup1) pc.flops_coup += g.flops;
       for (auto& g : lv.coup2) pc.flops_coup += g.flops;
     }
+   } catch (const Error& e) {
+#pragma omp critical
+    if (!first_code) { first_code = e.code; first_error = e.msg; }
+   } catch (const std::exception& e) {
+#pragma omp critical
+    if (!first_code) { first_code = H2_EINVAL; first_error = e.what(); }
+   }
+  }
+  if (first_code) fail(first_code, first_error);
+  for (const PlanCounts& c : lpc) {
+    sp.counts.flops_qr += c.flops_qr;
+    sp.counts.flops_close += c.flops_close;
+    sp.counts.flops_coup += c.flops_coup;
+    sp.counts.flops_strip += c.flops_strip;
+    sp.counts.flops_misc += c.flops_misc;
+    sp.counts.bytes_qr += c.bytes_qr;
   }
   // ---- one device allocation for every work list of the sweep
   std::vector<GemmBatch*> all;
