@@ -13,10 +13,10 @@
 //      pivot of the level, one work item per target, the pivots as K-segments
 //      in elimination order (no atomics: the result is deterministic);
 //   4. Z replaces the pivot rows of S.
-// The levels are planned on the host in chunks by a producer thread (each
-// chunk in parallel over its levels); the calling thread uploads every planned
-// chunk on a copy stream and queues its launches, so host planning overlaps the
-// device work of the chunks before it.
+// The levels are planned on the host, in order, by a producer thread (each level
+// in parallel over its pivots); the calling thread uploads runs of planned
+// levels on a copy stream and queues their launches, so host planning overlaps
+// the device work of the levels before it.
 #include <algorithm>
 #include <atomic>
 #include <condition_variable>
@@ -24,6 +24,8 @@
 #include <exception>
 #include <mutex>
 #include <thread>
+
+#include <omp.h>
 
 #include "factor.h"
 
@@ -33,9 +35,8 @@ namespace {
 
 struct SchurRec {
   int64_t target;  // block number of (i, j)
-  int64_t kpos;    // elimination position of the pivot
-  int64_t a_blk;   // block number of (k, i)
-  int64_t z_off;   // offset of Z_kj in the Z buffer
+  int64_t a_off;   // offset of S_ki in S
+  int32_t z_off;   // offset of Z_kj in the Z buffer
   int32_t mk;
 };
 
@@ -94,83 +95,171 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   for (int lv = 0; lv < f.nflev; ++lv) ready[lv] = 0;
   std::mutex mu;
   std::condition_variable cv;
-  // plans every level, dynamically scheduled in level order (parallel)
-  auto plan_all = [&]() {
-#pragma omp parallel reduction(+ : fl_inv, fl_z, fl_s)
-  {
-    std::vector<i64> mark(ncl, -1);
-    std::vector<SchurRec> recs;
-#pragma omp for schedule(dynamic, 1)
-    for (int lv = 0; lv < f.nflev; ++lv) {
-      FactorLevel<T>& L = lvls[lv];
-      L.zb.role = ROLE_FACTOR;
+  const int nthr = std::max(1, omp_get_max_threads());
+  std::vector<std::vector<i64>> marks(nthr);
+  std::vector<std::vector<SchurRec>> local(nthr);
+  std::vector<SchurRec> grouped;
+  // Plans one level.  The pivots' Schur records are produced in parallel
+  // (thread-local), spread over target buckets by sampled splitters, and each
+  // bucket is sorted by (target, Z offset): Z offsets grow with the pivot's
+  // elimination position, so every target's K-segments come in elimination
+  // order whatever thread produced them.
+  auto plan_level = [&](int lv) {
+    FactorLevel<T>& L = lvls[lv];
+    L.zb.role = ROLE_FACTOR;
+    const std::vector<i64>& piv = by_level[lv];
+    const long np = long(piv.size());
+    std::vector<i64> zoffs(np), colbase(np + 1, 0);
+    i64 zoff = 0;
+    for (long q = 0; q < np; ++q) {
+      const i64 pk = piv[q];
+      const i64 ck = cl(pk);
+      const i64 mk = mb[ck];
+      const i64 dblk = sp.rowptr[pk];
+      L.inv.push_back({S + sp.blk_off[dblk], Inv + f.inv_off[pk], int32_t(mk), 0});
+      fl_inv += 2.0 * mk * mk * mk;
+      zoffs[q] = zoff;
+      const i64 b0 = dblk + 1, b1 = sp.rowptr[pk + 1];
+      if (b0 == b1) continue;
+      const i64 row_start = sp.blk_off[b0];
+      i64 width = 0;
+      for (i64 b = b0; b < b1; ++b) width += mb[sp.colidx[b]];
+      for (i64 c0 = 0; c0 < width; c0 += 512) {
+        const int w = int(std::min<i64>(512, width - c0));
+        GemmItem& it = L.zb.item(int(mk), w, int(mk), w);
+        GemmBatch::set_out(it, 0, Z + zoff + c0 * mk, mk, false);
+        // D_k^{-1} is symmetric (D_k is): read it through its transpose so that
+        // both operands run along K in memory
+        L.zb.seg(Inv + f.inv_off[pk], int(mk), true, S + row_start + c0 * mk, int(mk), false, int(mk));
+      }
+      L.cps.push_back({row_start, zoff, mk * width});
+      zoff += mk * width;
+    }
+    fl_z += L.zb.flops;
+    // Schur targets (i, j), i before or equal to j, both in row k
+    const int nt = int(std::min<long>(nthr, std::max<long>(1, np / 4)));
+#pragma omp parallel num_threads(nt)
+    {
+      const int t = omp_get_thread_num();
+      std::vector<SchurRec>& recs = local[t];
       recs.clear();
-      i64 zoff = 0;
-      for (i64 pk : by_level[lv]) {
-        const i64 ck = cl(pk);
-        const i64 mk = mb[ck];
-        const i64 dblk = sp.rowptr[pk];
-        L.inv.push_back({S + sp.blk_off[dblk], Inv + f.inv_off[pk], int32_t(mk), 0});
-        fl_inv += 2.0 * mk * mk * mk;
-        const i64 b0 = dblk + 1, b1 = sp.rowptr[pk + 1];
-        if (b0 == b1) continue;
-        const i64 row_start = sp.blk_off[b0];
-        i64 width = 0;
-        std::vector<i64> colpos(b1 - b0);
-        for (i64 b = b0; b < b1; ++b) {
-          colpos[b - b0] = width;
-          width += mb[sp.colidx[b]];
-        }
-        for (i64 c0 = 0; c0 < width; c0 += 512) {
-          const int w = int(std::min<i64>(512, width - c0));
-          GemmItem& it = L.zb.item(int(mk), w, int(mk), w);
-          GemmBatch::set_out(it, 0, Z + zoff + c0 * mk, mk, false);
-          // D_k^{-1} is symmetric (D_k is): read it through its transpose so that
-          // both operands run along K in memory
-          L.zb.seg(Inv + f.inv_off[pk], int(mk), true, S + row_start + c0 * mk, int(mk), false, int(mk));
-        }
-        L.cps.push_back({row_start, zoff, mk * width});
-        // Schur targets (i, j), i before or equal to j, both in row k
+      std::vector<i64>& mark = marks[t];
+      if (mark.empty()) mark.assign(ncl, -1);
+#pragma omp for schedule(dynamic, 8)
+      for (long q = 0; q < np; ++q) {
+        const i64 pk = piv[q];
+        const i64 mk = mb[cl(pk)];
+        const i64 b0 = sp.rowptr[pk] + 1, b1 = sp.rowptr[pk + 1];
+        i64 col = 0;
         for (i64 a = b0; a < b1; ++a) {
           const i64 pi = sp.epos[sp.colidx[a]];
           for (i64 b = sp.rowptr[pi]; b < sp.rowptr[pi + 1]; ++b) mark[sp.colidx[b]] = b;
+          i64 col2 = col;
           for (i64 a2 = a; a2 < b1; ++a2) {
-            const i64 tb = mark[sp.colidx[a2]];
-            if (tb < 0) continue;
-            recs.push_back({tb, pk, a, zoff + colpos[a2 - b0] * mk, int32_t(mk)});
+            const i64 s2 = sp.colidx[a2];
+            const i64 tb = mark[s2];
+            if (tb >= 0) recs.push_back({tb, sp.blk_off[a], int32_t(zoffs[q] + col2 * mk), int32_t(mk)});
+            col2 += mb[s2];
           }
           for (i64 b = sp.rowptr[pi]; b < sp.rowptr[pi + 1]; ++b) mark[sp.colidx[b]] = -1;
+          col += mb[sp.colidx[a]];
         }
-        zoff += mk * width;
       }
-      fl_z += L.zb.flops;
-      std::sort(recs.begin(), recs.end(), [](const SchurRec& x, const SchurRec& y) {
-        return x.target < y.target || (x.target == y.target && x.kpos < y.kpos);
-      });
-      L.ssegs.reserve(recs.size());
-      for (size_t r = 0; r < recs.size();) {
-        const i64 tb = recs[r].target;
+    }
+    size_t total = 0;
+    for (int t = 0; t < nt; ++t) total += local[t].size();
+    auto by_target = [](const SchurRec& x, const SchurRec& y) {
+      return x.target < y.target || (x.target == y.target && x.z_off < y.z_off);
+    };
+    // buckets of targets: splitters sampled from the records
+    const int nbk = total < (size_t(1) << 15) ? 1 : 4 * nt;
+    std::vector<i64> split;
+    if (nbk > 1) {
+      std::vector<i64> sample;
+      const size_t stride = std::max<size_t>(1, total / (size_t(nbk) * 64));
+      for (int t = 0; t < nt; ++t)
+        for (size_t r = 0; r < local[t].size(); r += stride) sample.push_back(local[t][r].target);
+      std::sort(sample.begin(), sample.end());
+      for (int q = 1; q < nbk; ++q) split.push_back(sample[sample.size() * q / nbk]);
+    }
+    auto bucket_of = [&](i64 tb) { return int(std::upper_bound(split.begin(), split.end(), tb) - split.begin()); };
+    std::vector<size_t> cnt(size_t(nt) * nbk, 0);  // [t][q]
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+    for (int t = 0; t < nt; ++t)
+      for (const SchurRec& r : local[t]) ++cnt[size_t(t) * nbk + bucket_of(r.target)];
+    std::vector<size_t> bstart(nbk + 1, 0), woff(size_t(nt) * nbk);
+    {
+      size_t o = 0;
+      for (int q = 0; q < nbk; ++q) {
+        bstart[q] = o;
+        for (int t = 0; t < nt; ++t) {
+          woff[size_t(t) * nbk + q] = o;
+          o += cnt[size_t(t) * nbk + q];
+        }
+      }
+      bstart[nbk] = o;
+    }
+    grouped.resize(total);
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+    for (int t = 0; t < nt; ++t) {
+      size_t* w = &woff[size_t(t) * nbk];
+      for (const SchurRec& r : local[t]) grouped[w[bucket_of(r.target)]++] = r;
+    }
+    // per bucket: sort, then items (one per target), segments (one per record,
+    // written in place) and tiles
+    L.ssegs.resize(total);
+    std::vector<std::vector<SchurItem>> bitems(nbk);
+    std::vector<std::vector<int32_t>> btiles(nbk);
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1) reduction(+ : fl_s)
+    for (int q = 0; q < nbk; ++q) {
+      const size_t r0 = bstart[q], r1 = bstart[q + 1];
+      std::sort(grouped.begin() + r0, grouped.begin() + r1, by_target);
+      for (size_t r = r0; r < r1;) {
+        const i64 tb = grouped[r].target;
         const i64 mi = mb[cl(row_of[tb])], mj = mb[sp.colidx[tb]];
-        SchurItem si{sp.blk_off[tb], int32_t(mi), int32_t(mj), int32_t(L.ssegs.size()), 0};
-        for (; r < recs.size() && recs[r].target == tb; ++r) {
-          L.ssegs.push_back({sp.blk_off[recs[r].a_blk], int32_t(recs[r].z_off), recs[r].mk});
-          fl_s += 2.0 * mi * mj * recs[r].mk;
+        SchurItem si{sp.blk_off[tb], int32_t(mi), int32_t(mj), int32_t(r), 0};
+        for (; r < r1 && grouped[r].target == tb; ++r) {
+          L.ssegs[r] = {grouped[r].a_off, grouped[r].z_off, grouped[r].mk};
+          fl_s += 2.0 * mi * mj * grouped[r].mk;
         }
-        si.seg_end = int32_t(L.ssegs.size());
-        const uint32_t item = uint32_t(L.sitems.size());
+        si.seg_end = int32_t(r);
+        const uint32_t item = uint32_t(bitems[q].size());
         for (int a = 0; a < (mi + 63) / 64; ++a)
-          for (int b = 0; b < (mj + 63) / 64; ++b) L.stiles.push_back(int32_t((item << 8) | (a << 4) | b));
-        L.sitems.push_back(si);
+          for (int b = 0; b < (mj + 63) / 64; ++b) btiles[q].push_back(int32_t((item << 8) | (a << 4) | b));
+        bitems[q].push_back(si);
       }
-      if (L.sitems.size() >= (size_t(1) << 24)) too_wide = 1;
+    }
+    size_t nitems = 0, ntl = 0;
+    for (int q = 0; q < nbk; ++q) {
+      nitems += bitems[q].size();
+      ntl += btiles[q].size();
+    }
+    if (nitems >= (size_t(1) << 24) || total >= (size_t(1) << 31)) {
+      too_wide = 1;
+      return;
+    }
+    L.sitems.reserve(nitems);
+    L.stiles.reserve(ntl);
+    for (int q = 0; q < nbk; ++q) {
+      const uint32_t base = uint32_t(L.sitems.size());
+      L.sitems.insert(L.sitems.end(), bitems[q].begin(), bitems[q].end());
+      for (int32_t tcode : btiles[q]) L.stiles.push_back(int32_t(uint32_t(tcode) + (base << 8)));
+    }
+  };
+  // plans the levels in order, each in parallel
+  auto plan_all = [&]() {
+    for (int lv = 0; lv < f.nflev && !too_wide; ++lv) {
+      plan_level(lv);
       {
         std::lock_guard<std::mutex> lk(mu);
         ready[lv] = 1;
       }
       cv.notify_one();
     }
-  }
-  if (too_wide) fail(H2_EUNSUPPORTED, "Schur level above 2^24 targets");
+    std::vector<SchurRec>().swap(grouped);
+    for (auto& v : local) std::vector<SchurRec>().swap(v);
+    for (auto& v : marks) std::vector<i64>().swap(v);
+    if (too_wide) fail(H2_EUNSUPPORTED, "Schur level above 2^24 targets or 2^31 segments");
   };
   std::vector<hipEvent_t> ev;
   auto mark_ev = [&]() {
