@@ -198,7 +198,10 @@ void h2_factor_destroy(h2_factor* f);
 int h2_last_timings(double* ms, int count);
 /* Algorithmic work of the last sparsify / factor call on this thread, same
  * phase order as h2_last_timings: flop counts of the GEMMs and QRs as planned
- * (2 m n k per product), [6] = bytes the QR phase must move at least. */
+ * (2 m n k per product), [6] = bytes the QR phase must move at least,
+ * [7] = Schur targets of the factorisation whose sum over pivots was split
+ * into parts (long K; the environment variable H2SP_SCHUR_SPLIT_K sets the
+ * smallest K of a part, default 512). */
 int h2_last_work(double* work, int count);
 
 #ifdef __cplusplus

@@ -152,6 +152,7 @@ extern "C" int h2_factor_S(h2_sparse* sp, h2_factor** out) {
   g_timings[7] = ph[6];
   g_work[4] = f->flops_inv + f->flops_z;
   g_work[5] = f->flops_schur;
+  g_work[7] = double(f->split_targets);
   *out = f.release();
   H2_API_END
 }

@@ -5,20 +5,26 @@
 // in the elimination order chosen at planning time (levels from the leaves up,
 // greedy colours inside a level, so that rows of one colour are independent).
 //
-// Right-looking, scheduled by the levels of the elimination DAG (pivot k waits
-// for every earlier k' with S_k'k stored).  Per DAG level, on the device:
-//   1. D_k^{-1} for every pivot of the level (FP64 Gauss-Jordan, pivoting);
-//   2. Z_kj = D_k^{-1} S_kj for the pivot rows (batched GEMM);
-//   3. S_ij -= S_ki^T Z_kj for every stored target (i <= j) reached from a
-//      pivot of the level, one work item per target, the pivots as K-segments
-//      in elimination order (no atomics: the result is deterministic);
-//   4. Z replaces the pivot rows of S.
+// Left-looking (fan-in), scheduled by the levels of the elimination DAG (row i
+// waits for every earlier k with S_ki stored).  Per DAG level, on the device:
+//   1. Z_ki = D_k^{-1} S_ki for every stored S_ki above a row i of the level
+//      (batched GEMM; row k and D_k^{-1} are final by then);
+//   2. S_ij -= sum_k Z_ki^T S_kj for every stored target (i <= j) of the rows
+//      of the level, one work item per target carrying all of its pivots k as
+//      K-segments in elimination order, so each target is read and written
+//      once (no atomics: the result is deterministic);
+//   3. D_i^{-1} for every row of the level (FP64 Gauss-Jordan, pivoting);
+//   4. Z_ki replaces S_ki (no later level reads S_ki: a later target (i', i)
+//      would need S_i'i stored, which places i' before i in the DAG).
+// At the end every stored block above the diagonal holds Z_kj and D_k^{-1} is
+// in its own buffer, which is what the triangular solves read.
 // The levels are planned on the host, in order, by a producer thread (each level
-// in parallel over its pivots); the calling thread uploads runs of planned
-// levels on a copy stream and queues their launches, so host planning overlaps
-// the device work of the levels before it.
+// in parallel over its rows); the calling thread uploads runs of planned levels
+// on a copy stream and queues their launches, so host planning overlaps the
+// device work of the levels before it.
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <exception>
@@ -33,13 +39,6 @@ namespace h2 {
 
 namespace {
 
-struct SchurRec {
-  int64_t target;  // block number of (i, j)
-  int64_t a_off;   // offset of S_ki in S
-  int32_t z_off;   // offset of Z_kj in the Z buffer
-  int32_t mk;
-};
-
 template <class T>
 struct FactorLevel {
   std::vector<InvItem<T>> inv;
@@ -47,12 +46,21 @@ struct FactorLevel {
   std::vector<SchurItem> sitems;
   std::vector<SchurSeg> ssegs;
   std::vector<int32_t> stiles;
+  std::vector<SchurReduce> reds;
   const InvItem<T>* d_inv = nullptr;
   const CopySeg* d_cps = nullptr;
   const SchurItem* d_sitems = nullptr;
   const SchurSeg* d_ssegs = nullptr;
   const int32_t* d_stiles = nullptr;
+  const SchurReduce* d_reds = nullptr;
   GemmBatch zb;
+};
+
+// Output of one chunk of rows of a level (concatenated in row order).
+struct RowChunk {
+  std::vector<SchurItem> items;
+  std::vector<SchurSeg> segs;
+  double flops = 0;
 };
 
 }  // namespace
@@ -69,26 +77,42 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   auto cl = [&](i64 pos) { return sp.eorder[pos]; };
   std::vector<std::vector<i64>> by_level(f.nflev);
   for (i64 pos : f.rows) by_level[f.flev[pos]].push_back(pos);
-  // Z buffer: largest level
+  // column lists of the stored upper pattern: for S position i, the rows k
+  // (elimination order) with S_ki stored and the block number of S_ki
+  std::vector<i64> cptr(ncl + 1, 0), ck_pos, ck_blk;
+  for (i64 pos = 0; pos < ncl; ++pos)
+    for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) ++cptr[sp.epos[sp.colidx[b]] + 1];
+  for (i64 i = 0; i < ncl; ++i) cptr[i + 1] += cptr[i];
+  ck_pos.resize(cptr[ncl]);
+  ck_blk.resize(cptr[ncl]);
+  {
+    std::vector<i64> fillp(cptr.begin(), cptr.end() - 1);
+    for (i64 pos = 0; pos < ncl; ++pos)
+      for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) {
+        const i64 i = sp.epos[sp.colidx[b]];
+        ck_pos[fillp[i]] = pos;
+        ck_blk[fillp[i]++] = b;
+      }
+  }
+  // Z buffer: the Z_ki blocks of the largest level
   i64 zmax = 1;
   for (const auto& lv : by_level) {
     i64 z = 0;
-    for (i64 pk : lv) {
-      const i64 ck = cl(pk);
-      for (i64 b = sp.rowptr[pk] + 1; b < sp.rowptr[pk + 1]; ++b) z += mb[ck] * mb[sp.colidx[b]];
-    }
+    for (i64 pi : lv)
+      for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) z += mb[cl(ck_pos[c])] * mb[cl(pi)];
     zmax = std::max(zmax, z);
   }
   if (zmax >= (i64(1) << 31)) fail(H2_EUNSUPPORTED, "factor level too wide for 32-bit Z offsets");
   f.dZ.reset(sizeof(T) * zmax);
   T* Z = f.dZ.as<T>();
-  // block number -> elimination position of its row
-  std::vector<i64> row_of(sp.colidx.size());
-  for (i64 pos = 0; pos < ncl; ++pos)
-    for (i64 b = sp.rowptr[pos]; b < sp.rowptr[pos + 1]; ++b) row_of[b] = pos;
+  // partial sums of split targets (at most pcap elements per level)
+  f.pcap = std::min<i64>(i64(1) << 25, std::max<i64>(sp.s_entries, 1));
+  f.dP.reset(sizeof(T) * f.pcap);
+  T* Pbuf = f.dP.as<T>();
 
   std::vector<FactorLevel<T>> lvls(f.nflev);
   double fl_inv = 0, fl_z = 0, fl_s = 0;
+  i64 nsplit = 0;
   int too_wide = 0;
   // per-level completion flags of the planning, read by the uploading thread
   std::unique_ptr<std::atomic<int>[]> ready(new std::atomic<int>[f.nflev]);
@@ -96,155 +120,186 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   std::mutex mu;
   std::condition_variable cv;
   const int nthr = std::max(1, omp_get_max_threads());
-  std::vector<std::vector<i64>> marks(nthr);
-  std::vector<std::vector<SchurRec>> local(nthr);
-  std::vector<SchurRec> grouped;
-  // Plans one level.  The pivots' Schur records are produced in parallel
-  // (thread-local), spread over target buckets by sampled splitters, and each
-  // bucket is sorted by (target, Z offset): Z offsets grow with the pivot's
-  // elimination position, so every target's K-segments come in elimination
-  // order whatever thread produced them.
+  std::vector<std::vector<int32_t>> marks(nthr);
+  // Split-K of long targets.  A level's Schur work is spread over at least
+  // kUnits tile-sized units where it has that much: a target whose K exceeds
+  // 1.5 kt is cut at segment boundaries into parts of about kt, part 0
+  // subtracting from S, the others storing partial sums that a reduction item
+  // adds in part order (deterministic).  kt doubles until the partial sums of
+  // the level fit the partial buffer.
+  constexpr double kUnits = 8192;
+  i64 kMinK = 512;  // smallest K of a part; H2SP_SCHUR_SPLIT_K overrides it
+  if (const char* e = std::getenv("H2SP_SCHUR_SPLIT_K")) kMinK = std::max<i64>(1, std::atoll(e));
+  const i64 pcap = f.pcap;
+  auto split_targets = [&](const std::vector<SchurItem>& items, FactorLevel<T>& L) {
+    std::vector<i64> kitem(items.size());
+    double work = 0;
+    for (size_t t = 0; t < items.size(); ++t) {
+      const SchurItem& it = items[t];
+      i64 k = 0;
+      for (int32_t r = it.seg_begin; r < it.seg_end; ++r) k += L.ssegs[r].K;
+      kitem[t] = k;
+      work += double(k) * ((it.M + 63) / 64) * ((it.N + 63) / 64);
+    }
+    i64 kt = std::max<i64>(kMinK, i64(work / kUnits) + 1);
+    auto parts_of = [&](size_t t) -> i64 { return kitem[t] * 2 > 3 * kt ? (kitem[t] + kt - 1) / kt : 1; };
+    while (true) {
+      i64 need = 0;
+      for (size_t t = 0; t < items.size(); ++t) need += (parts_of(t) - 1) * i64(items[t].M) * items[t].N;
+      if (need <= pcap) break;
+      kt *= 2;
+    }
+    L.sitems.clear();
+    L.stiles.clear();
+    L.reds.clear();
+    i64 pbase = 0;
+    auto emit = [&](const SchurItem& si) {
+      const uint32_t item = uint32_t(L.sitems.size());
+      for (int a = 0; a < (si.M + 63) / 64; ++a)
+        for (int b = 0; b < (si.N + 63) / 64; ++b) L.stiles.push_back(int32_t((item << 8) | (a << 4) | b));
+      L.sitems.push_back(si);
+    };
+    for (size_t t = 0; t < items.size(); ++t) {
+      const SchurItem& it = items[t];
+      const i64 np = parts_of(t);
+      if (np == 1) {
+        emit(it);
+        continue;
+      }
+      const i64 len = i64(it.M) * it.N;
+      int32_t begin = it.seg_begin;
+      i64 acc = 0, part = 0;
+      for (int32_t r = it.seg_begin; r < it.seg_end; ++r) {
+        acc += L.ssegs[r].K;
+        const bool last = r + 1 == it.seg_end;
+        if (last || (part < np - 1 && acc * np >= (part + 1) * kitem[t])) {
+          SchurItem si = it;
+          si.seg_begin = begin;
+          si.seg_end = r + 1;
+          if (part > 0) {
+            si.partial = 1;
+            si.out_off = pbase + (part - 1) * len;
+          }
+          emit(si);
+          begin = r + 1;
+          ++part;
+        }
+      }
+      if (part > 1) {
+        L.reds.push_back({it.out_off, pbase, int32_t(len), int32_t(part - 1)});
+        pbase += (part - 1) * len;
+        ++nsplit;
+      }
+    }
+  };
+  // Plans one level: Z GEMMs, copies and inverses row by row (cheap), Schur
+  // targets in parallel over chunks of rows, concatenated in row order.
   auto plan_level = [&](int lv) {
     FactorLevel<T>& L = lvls[lv];
     L.zb.role = ROLE_FACTOR;
-    const std::vector<i64>& piv = by_level[lv];
-    const long np = long(piv.size());
-    std::vector<i64> zoffs(np), colbase(np + 1, 0);
-    i64 zoff = 0;
-    for (long q = 0; q < np; ++q) {
-      const i64 pk = piv[q];
-      const i64 ck = cl(pk);
-      const i64 mk = mb[ck];
-      const i64 dblk = sp.rowptr[pk];
-      L.inv.push_back({S + sp.blk_off[dblk], Inv + f.inv_off[pk], int32_t(mk), 0});
-      fl_inv += 2.0 * mk * mk * mk;
-      zoffs[q] = zoff;
-      const i64 b0 = dblk + 1, b1 = sp.rowptr[pk + 1];
-      if (b0 == b1) continue;
-      const i64 row_start = sp.blk_off[b0];
-      i64 width = 0;
-      for (i64 b = b0; b < b1; ++b) width += mb[sp.colidx[b]];
-      for (i64 c0 = 0; c0 < width; c0 += 512) {
-        const int w = int(std::min<i64>(512, width - c0));
-        GemmItem& it = L.zb.item(int(mk), w, int(mk), w);
-        GemmBatch::set_out(it, 0, Z + zoff + c0 * mk, mk, false);
+    const std::vector<i64>& rows = by_level[lv];
+    const long nr = long(rows.size());
+    std::vector<i64> zbase(nr + 1, 0);
+    for (long q = 0; q < nr; ++q) {
+      const i64 pi = rows[q];
+      const i64 mi = mb[cl(pi)];
+      L.inv.push_back({S + sp.blk_off[sp.rowptr[pi]], Inv + f.inv_off[pi], int32_t(mi), 0});
+      fl_inv += 2.0 * mi * mi * mi;
+      i64 z = zbase[q];
+      for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+        const i64 pk = ck_pos[c];
+        const i64 mk = mb[cl(pk)];
+        const i64 soff = sp.blk_off[ck_blk[c]];
+        GemmItem& it = L.zb.item(int(mk), int(mi), int(mk), int(mi));
+        GemmBatch::set_out(it, 0, Z + z, mk, false);
         // D_k^{-1} is symmetric (D_k is): read it through its transpose so that
         // both operands run along K in memory
-        L.zb.seg(Inv + f.inv_off[pk], int(mk), true, S + row_start + c0 * mk, int(mk), false, int(mk));
+        L.zb.seg(Inv + f.inv_off[pk], int(mk), true, S + soff, int(mk), false, int(mk));
+        L.cps.push_back({soff, z, mk * mi});
+        z += mk * mi;
       }
-      L.cps.push_back({row_start, zoff, mk * width});
-      zoff += mk * width;
+      zbase[q + 1] = z;
     }
     fl_z += L.zb.flops;
-    // Schur targets (i, j), i before or equal to j, both in row k
-    const int nt = int(std::min<long>(nthr, std::max<long>(1, np / 4)));
+    // Schur targets: every stored (i, j), j at or after i, of a row i of the level
+    const int nchunk = int(std::min<long>(nr, 8L * nthr));
+    std::vector<RowChunk> chunks(nchunk);
+    const int nt = int(std::min<long>(nthr, std::max<long>(1, nr / 2)));
 #pragma omp parallel num_threads(nt)
     {
-      const int t = omp_get_thread_num();
-      std::vector<SchurRec>& recs = local[t];
-      recs.clear();
-      std::vector<i64>& mark = marks[t];
+      std::vector<int32_t>& mark = marks[omp_get_thread_num()];
       if (mark.empty()) mark.assign(ncl, -1);
-#pragma omp for schedule(dynamic, 8)
-      for (long q = 0; q < np; ++q) {
-        const i64 pk = piv[q];
-        const i64 mk = mb[cl(pk)];
-        const i64 b0 = sp.rowptr[pk] + 1, b1 = sp.rowptr[pk + 1];
-        i64 col = 0;
-        for (i64 a = b0; a < b1; ++a) {
-          const i64 pi = sp.epos[sp.colidx[a]];
-          for (i64 b = sp.rowptr[pi]; b < sp.rowptr[pi + 1]; ++b) mark[sp.colidx[b]] = b;
-          i64 col2 = col;
-          for (i64 a2 = a; a2 < b1; ++a2) {
-            const i64 s2 = sp.colidx[a2];
-            const i64 tb = mark[s2];
-            if (tb >= 0) recs.push_back({tb, sp.blk_off[a], int32_t(zoffs[q] + col2 * mk), int32_t(mk)});
-            col2 += mb[s2];
+      std::vector<int32_t> cnt, fillp;
+#pragma omp for schedule(dynamic, 1)
+      for (int ch = 0; ch < nchunk; ++ch) {
+        RowChunk& out = chunks[ch];
+        const long q0 = nr * ch / nchunk, q1 = nr * (ch + 1) / nchunk;
+        for (long q = q0; q < q1; ++q) {
+          const i64 pi = rows[q];
+          const i64 mi = mb[cl(pi)];
+          const i64 t0 = sp.rowptr[pi], t1 = sp.rowptr[pi + 1];
+          const int nt_row = int(t1 - t0);
+          for (i64 b = t0; b < t1; ++b) mark[sp.colidx[b]] = int32_t(b - t0);
+          cnt.assign(nt_row + 1, 0);
+          for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+            const i64 pk = ck_pos[c];
+            for (i64 b = sp.rowptr[pk]; b < sp.rowptr[pk + 1]; ++b) {
+              const int32_t t = mark[sp.colidx[b]];
+              if (t >= 0) ++cnt[t + 1];
+            }
           }
-          for (i64 b = sp.rowptr[pi]; b < sp.rowptr[pi + 1]; ++b) mark[sp.colidx[b]] = -1;
-          col += mb[sp.colidx[a]];
+          for (int t = 0; t < nt_row; ++t) cnt[t + 1] += cnt[t];
+          const size_t sbase = out.segs.size();
+          out.segs.resize(sbase + cnt[nt_row]);
+          fillp.assign(cnt.begin(), cnt.end() - 1);
+          i64 zoff = zbase[q];
+          for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+            const i64 pk = ck_pos[c];
+            const i64 mk = mb[cl(pk)];
+            for (i64 b = sp.rowptr[pk]; b < sp.rowptr[pk + 1]; ++b) {
+              const int32_t t = mark[sp.colidx[b]];
+              if (t >= 0) out.segs[sbase + fillp[t]++] = {sp.blk_off[b], int32_t(zoff), int32_t(mk)};
+            }
+            zoff += mk * mi;
+          }
+          for (i64 b = t0; b < t1; ++b) mark[sp.colidx[b]] = -1;
+          for (int t = 0; t < nt_row; ++t) {
+            if (cnt[t + 1] == cnt[t]) continue;
+            const i64 mj = mb[sp.colidx[t0 + t]];
+            SchurItem si{sp.blk_off[t0 + t], int32_t(mi), int32_t(mj), int32_t(sbase + cnt[t]),
+                         int32_t(sbase + cnt[t + 1]), 0, 0};
+            for (int32_t r = si.seg_begin; r < si.seg_end; ++r) out.flops += 2.0 * mi * mj * out.segs[r].K;
+            out.items.push_back(si);
+          }
         }
       }
     }
-    size_t total = 0;
-    for (int t = 0; t < nt; ++t) total += local[t].size();
-    auto by_target = [](const SchurRec& x, const SchurRec& y) {
-      return x.target < y.target || (x.target == y.target && x.z_off < y.z_off);
-    };
-    // buckets of targets: splitters sampled from the records
-    const int nbk = total < (size_t(1) << 15) ? 1 : 4 * nt;
-    std::vector<i64> split;
-    if (nbk > 1) {
-      std::vector<i64> sample;
-      const size_t stride = std::max<size_t>(1, total / (size_t(nbk) * 64));
-      for (int t = 0; t < nt; ++t)
-        for (size_t r = 0; r < local[t].size(); r += stride) sample.push_back(local[t][r].target);
-      std::sort(sample.begin(), sample.end());
-      for (int q = 1; q < nbk; ++q) split.push_back(sample[sample.size() * q / nbk]);
+    size_t nitems = 0, nsegs = 0;
+    for (const RowChunk& c : chunks) {
+      nitems += c.items.size();
+      nsegs += c.segs.size();
+      fl_s += c.flops;
     }
-    auto bucket_of = [&](i64 tb) { return int(std::upper_bound(split.begin(), split.end(), tb) - split.begin()); };
-    std::vector<size_t> cnt(size_t(nt) * nbk, 0);  // [t][q]
-#pragma omp parallel for num_threads(nt) schedule(static, 1)
-    for (int t = 0; t < nt; ++t)
-      for (const SchurRec& r : local[t]) ++cnt[size_t(t) * nbk + bucket_of(r.target)];
-    std::vector<size_t> bstart(nbk + 1, 0), woff(size_t(nt) * nbk);
-    {
-      size_t o = 0;
-      for (int q = 0; q < nbk; ++q) {
-        bstart[q] = o;
-        for (int t = 0; t < nt; ++t) {
-          woff[size_t(t) * nbk + q] = o;
-          o += cnt[size_t(t) * nbk + q];
-        }
-      }
-      bstart[nbk] = o;
-    }
-    grouped.resize(total);
-#pragma omp parallel for num_threads(nt) schedule(static, 1)
-    for (int t = 0; t < nt; ++t) {
-      size_t* w = &woff[size_t(t) * nbk];
-      for (const SchurRec& r : local[t]) grouped[w[bucket_of(r.target)]++] = r;
-    }
-    // per bucket: sort, then items (one per target), segments (one per record,
-    // written in place) and tiles
-    L.ssegs.resize(total);
-    std::vector<std::vector<SchurItem>> bitems(nbk);
-    std::vector<std::vector<int32_t>> btiles(nbk);
-#pragma omp parallel for num_threads(nt) schedule(dynamic, 1) reduction(+ : fl_s)
-    for (int q = 0; q < nbk; ++q) {
-      const size_t r0 = bstart[q], r1 = bstart[q + 1];
-      std::sort(grouped.begin() + r0, grouped.begin() + r1, by_target);
-      for (size_t r = r0; r < r1;) {
-        const i64 tb = grouped[r].target;
-        const i64 mi = mb[cl(row_of[tb])], mj = mb[sp.colidx[tb]];
-        SchurItem si{sp.blk_off[tb], int32_t(mi), int32_t(mj), int32_t(r), 0};
-        for (; r < r1 && grouped[r].target == tb; ++r) {
-          L.ssegs[r] = {grouped[r].a_off, grouped[r].z_off, grouped[r].mk};
-          fl_s += 2.0 * mi * mj * grouped[r].mk;
-        }
-        si.seg_end = int32_t(r);
-        const uint32_t item = uint32_t(bitems[q].size());
-        for (int a = 0; a < (mi + 63) / 64; ++a)
-          for (int b = 0; b < (mj + 63) / 64; ++b) btiles[q].push_back(int32_t((item << 8) | (a << 4) | b));
-        bitems[q].push_back(si);
-      }
-    }
-    size_t nitems = 0, ntl = 0;
-    for (int q = 0; q < nbk; ++q) {
-      nitems += bitems[q].size();
-      ntl += btiles[q].size();
-    }
-    if (nitems >= (size_t(1) << 24) || total >= (size_t(1) << 31)) {
+    if (nsegs >= (size_t(1) << 31)) {
       too_wide = 1;
       return;
     }
-    L.sitems.reserve(nitems);
-    L.stiles.reserve(ntl);
-    for (int q = 0; q < nbk; ++q) {
-      const uint32_t base = uint32_t(L.sitems.size());
-      L.sitems.insert(L.sitems.end(), bitems[q].begin(), bitems[q].end());
-      for (int32_t tcode : btiles[q]) L.stiles.push_back(int32_t(uint32_t(tcode) + (base << 8)));
+    std::vector<SchurItem> items;
+    items.reserve(nitems);
+    L.ssegs.reserve(nsegs);
+    for (RowChunk& c : chunks) {
+      const int32_t sb = int32_t(L.ssegs.size());
+      for (SchurItem si : c.items) {
+        si.seg_begin += sb;
+        si.seg_end += sb;
+        items.push_back(si);
+      }
+      L.ssegs.insert(L.ssegs.end(), c.segs.begin(), c.segs.end());
+      std::vector<SchurItem>().swap(c.items);
+      std::vector<SchurSeg>().swap(c.segs);
     }
+    split_targets(items, L);
+    if (L.sitems.size() >= (size_t(1) << 24)) too_wide = 1;
   };
   // plans the levels in order, each in parallel
   auto plan_all = [&]() {
@@ -256,9 +311,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       }
       cv.notify_one();
     }
-    std::vector<SchurRec>().swap(grouped);
-    for (auto& v : local) std::vector<SchurRec>().swap(v);
-    for (auto& v : marks) std::vector<i64>().swap(v);
+    for (auto& v : marks) std::vector<int32_t>().swap(v);
     if (too_wide) fail(H2_EUNSUPPORTED, "Schur level above 2^24 targets or 2^31 segments");
   };
   std::vector<hipEvent_t> ev;
@@ -311,21 +364,26 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
                          reinterpret_cast<const void**>(&L.d_ssegs)});
         blobs.push_back({L.stiles.data(), L.stiles.size() * sizeof(int32_t),
                          reinterpret_cast<const void**>(&L.d_stiles)});
+        blobs.push_back({L.reds.data(), L.reds.size() * sizeof(SchurReduce),
+                         reinterpret_cast<const void**>(&L.d_reds)});
       }
       chunk_desc.emplace_back();
       upload_batches(all, chunk_desc.back(), blobs, cstream, st, /*parallel_pack=*/false);
       for (int lv = next; lv < end; ++lv) {
         FactorLevel<T>& L = lvls[lv];
-        launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
         L.zb.template launch<T>(st, dim, 0.0, 0.0);
         mark_ev();
-        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z};
+        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf};
         launch_schur<T>(sl, st);
+        launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
         mark_ev();
+        launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
         launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
+        mark_ev();
         std::vector<SchurItem>().swap(L.sitems);
         std::vector<SchurSeg>().swap(L.ssegs);
         std::vector<int32_t>().swap(L.stiles);
+        std::vector<SchurReduce>().swap(L.reds);
       }
       next = end;
     }
@@ -337,10 +395,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   producer.join();
   HIPCHECK(hipStreamDestroy(cstream));
   if (perr) std::rethrow_exception(perr);
-  if (int(ev.size()) != 2 * f.nflev + 1) fail(H2_EINVAL, "internal: factorisation stopped early");
+  if (int(ev.size()) != 3 * f.nflev + 1) fail(H2_EINVAL, "internal: factorisation stopped early");
   f.flops_inv += fl_inv;
   f.flops_z += fl_z;
   f.flops_schur += fl_s;
+  f.split_targets += nsplit;
   tt.lap("plan+upload+enqueue");
   HIPCHECK(hipGetLastError());
   mark_ev();
@@ -348,10 +407,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   tt.lap("device-drain");
   double piv_ms = 0, schur_ms = 0;
   for (int lv = 0; lv < f.nflev; ++lv) {
-    float a = 0, b = 0;
-    HIPCHECK(hipEventElapsedTime(&a, ev[2 * lv], ev[2 * lv + 1]));
-    HIPCHECK(hipEventElapsedTime(&b, ev[2 * lv + 1], ev[2 * lv + 2]));
-    piv_ms += a;
+    float a = 0, b = 0, c = 0;
+    HIPCHECK(hipEventElapsedTime(&a, ev[3 * lv], ev[3 * lv + 1]));
+    HIPCHECK(hipEventElapsedTime(&b, ev[3 * lv + 1], ev[3 * lv + 2]));
+    HIPCHECK(hipEventElapsedTime(&c, ev[3 * lv + 2], ev[3 * lv + 3]));
+    piv_ms += a + c;
     schur_ms += b;
   }
   float tot = 0;

@@ -26,8 +26,10 @@ struct h2_factor {
   std::vector<int> flev, blev;               // forward / backward level per S position
   int nflev = 0, nblev = 0;
   std::vector<h2::i64> inv_off;              // per S position: offset of D_k^{-1}
-  h2::DeviceBuffer dInv, dZ, dFlag, dDesc;
+  h2::DeviceBuffer dInv, dZ, dP, dFlag, dDesc;
+  h2::i64 pcap = 0;                          // elements of the partial-sum buffer dP
   double flops_schur = 0, flops_inv = 0, flops_z = 0;
+  h2::i64 split_targets = 0;                 // Schur targets summed in parts
   std::unique_ptr<h2::SolvePlan> solve;
   ~h2_factor();
 };

@@ -55,17 +55,25 @@ struct GemmLaunch {
 template <class T>
 void launch_gemm(const GemmLaunch& g, hipStream_t st);
 
-// Compact work list of the Schur update S_ij -= S_ki^T Z_kj (offsets in
-// elements into S and into the Z buffer; every operand has leading dimension
-// equal to its row count).  Tiles: (item << 8) | (tile_row << 4) | tile_col,
-// 64 x 64 tiles.
+// Compact work list of the Schur update S_ij -= Z_ki^T S_kj (offsets in
+// elements into S and into the buffer of Z_ki blocks; every operand has leading
+// dimension equal to its row count).  Tiles: (item << 8) | (tile_row << 4) |
+// tile_col, 64 x 64 tiles.
+// A target with a long K is split into parts: part 0 subtracts its sum from S
+// directly, every further part stores its sum (M x N, ld M) in the partial
+// buffer and a reduction item subtracts those sums, in a fixed order.
 struct SchurItem {
-  int64_t out_off;
+  int64_t out_off;   // into S (partial == 0) or the partial buffer (partial == 1)
   int32_t M, N, seg_begin, seg_end;
+  int32_t partial, pad;
 };
 struct SchurSeg {
-  int64_t a_off;
-  int32_t z_off, K;
+  int64_t b_off;     // S_kj in S (K x N)
+  int32_t a_off, K;  // Z_ki in the Z buffer (K x M)
+};
+struct SchurReduce {
+  int64_t s_off, p_off;  // target in S; first of `parts` consecutive M x N partial sums
+  int32_t len, parts;    // len = M N
 };
 struct SchurLaunch {
   const SchurItem* items;
@@ -74,9 +82,12 @@ struct SchurLaunch {
   int32_t ntiles;
   void* S;
   const void* Z;
+  void* P;               // partial buffer
 };
 template <class T>
 void launch_schur(const SchurLaunch& g, hipStream_t st);
+template <class T>
+void launch_schur_reduce(const SchurReduce* items, int count, const T* P, T* S, hipStream_t st);
 
 // Householder QR of one cluster basis B (n x r, column-major, ld n), n <= 128,
 // r <= 64.  Writes the explicit square Q (n x n, ld n) and R^ = rows 0..k-1 of

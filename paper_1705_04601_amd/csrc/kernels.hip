@@ -323,7 +323,7 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
 }
 
 // Schur update of the block factorisation with compact descriptors:
-// S[out] (M x N, ld M) -= sum_seg S[a]^T (K x M, ld K) Z[z] (K x N, ld K).
+// S[out] (M x N, ld M) -= sum_seg Z[a]^T (K x M, ld K) S[b] (K x N, ld K).
 // The (segment, 16-wide k step) pairs form one chunk stream; the operands of
 // chunk c + 1 are loaded into a second register set while the MFMAs of chunk c
 // issue, so a wave keeps its loads in flight behind its own math.
@@ -334,8 +334,8 @@ __device__ __forceinline__ void schur_load(const T* S, const T* Z, const SchurSe
   for (int q = 0; q < 4; ++q) {
     const int ra = m0 + 16 * q + r, cb = n0 + 16 * q + r;
     const bool oa = q < nbm && ra < M, ob = q < nbn && cb < N;
-    if (q < nbm) load4<T>(S + sg.a_off + int64_t(oa ? ra : 0) * sg.K, k, sg.K, oa, a[q]);
-    if (q < nbn) load4<T>(Z + sg.z_off + int64_t(ob ? cb : 0) * sg.K, k, sg.K, ob, b[q]);
+    if (q < nbm) load4<T>(Z + sg.a_off + int64_t(oa ? ra : 0) * sg.K, k, sg.K, oa, a[q]);
+    if (q < nbn) load4<T>(S + sg.b_off + int64_t(ob ? cb : 0) * sg.K, k, sg.K, ob, b[q]);
   }
 }
 
@@ -394,7 +394,8 @@ __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
         }
     }
   }
-  T* out = S + it.out_off;
+  const bool part = it.partial != 0;
+  T* out = (part ? static_cast<T*>(g.P) : S) + it.out_off;
 #pragma unroll
   for (int bm = 0; bm < 4; ++bm)
 #pragma unroll
@@ -404,9 +405,24 @@ __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + 16 * bm + lane % 16;
         const int col = n0 + 16 * bn + Mfma<T>::row(lane, v);
-        if (row < it.M && col < it.N) out[row + int64_t(col) * it.M] -= acc[bm][bn][v];
+        if (row < it.M && col < it.N) {
+          T* o = out + row + int64_t(col) * it.M;
+          if (part) *o = acc[bm][bn][v];
+          else *o -= acc[bm][bn][v];
+        }
       }
     }
+}
+
+// S[target] -= sum of the target's partial sums, in part order.
+template <class T>
+__global__ void schur_reduce_kernel(const SchurReduce* items, const T* P, T* S) {
+  const SchurReduce r = items[blockIdx.y];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < r.len; e += gridDim.x * blockDim.x) {
+    T acc = T(0);
+    for (int p = 0; p < r.parts; ++p) acc += P[r.p_off + int64_t(p) * r.len + e];
+    S[r.s_off + e] -= acc;
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -688,6 +704,16 @@ void launch_schur(const SchurLaunch& g, hipStream_t st) {
 }
 template void launch_schur<double>(const SchurLaunch&, hipStream_t);
 template void launch_schur<float>(const SchurLaunch&, hipStream_t);
+
+template <class T>
+void launch_schur_reduce(const SchurReduce* items, int count, const T* P, T* S, hipStream_t st) {
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int c = count - c0 < 65535 ? count - c0 : 65535;
+    hipLaunchKernelGGL(schur_reduce_kernel<T>, dim3(16, c), dim3(256), 0, st, items + c0, P, S);
+  }
+}
+template void launch_schur_reduce<double>(const SchurReduce*, int, const double*, double*, hipStream_t);
+template void launch_schur_reduce<float>(const SchurReduce*, int, const float*, float*, hipStream_t);
 
 void launch_qr(const QrItem* items, int count, hipStream_t st) {
   if (count <= 0) return;

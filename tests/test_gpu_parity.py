@@ -174,6 +174,40 @@ def test_preconditioner_matches_oracle_ilu0(name):
     assert np.abs(host(out) - want).max() <= 1e-10 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("name", ["cube2500r48", "sphere2k", "hodlr700"])
+def test_split_schur_targets_match_oracle_ilu0(name, monkeypatch):
+    """Long Schur sums cut into parts (forced with a tiny part size) still give
+    the oracle's block ILU(0)."""
+    x, sc, h2, sp, a, _ = case(name)
+    note(f"apply inverse fp64 split-K {name}")
+    monkeypatch.setenv("H2SP_SCHUR_SPLIT_K", "4")
+    h = imported(name)
+    f = P.h2_factor_S(P.h2_sparsify(h, P.H2_FP64))
+    assert P.h2_last_work()[7] > 0
+    b = np.random.default_rng(7).standard_normal((x.shape[0], 3))
+    out = dev(np.zeros_like(b))
+    P.h2_apply_inverse(f, dev(b), out)
+    ilu = oracle.BlockILU0(sp, oracle.elimination_order(sp))
+    bt = to_tree(b, h2.tree.perm)
+    want = from_tree(oracle.apply_v(sp, ilu.solve(oracle.apply_ut(sp, bt))), h2.tree.perm)
+    assert np.abs(host(out) - want).max() <= 1e-10 * np.abs(want).max()
+
+
+def test_split_schur_targets_mixed_solve(monkeypatch):
+    x, sc, h2, sp, a, (leaf, cheb, tol, cap, eta) = case("cube2500r48")
+    note("solve mixed split-K cube2500r48")
+    monkeypatch.setenv("H2SP_SCHUR_SPLIT_K", "4")
+    h = P.h2_build(x, sc, 1.0, leaf, cheb, tol, cap, eta)
+    f = P.h2_factor_S(P.h2_sparsify(h, P.H2_MIXED))
+    assert P.h2_last_work()[7] > 0
+    b = np.random.default_rng(8).standard_normal((x.shape[0], 4))
+    xs = dev(np.zeros_like(b))
+    info = P.h2_solve(f, dev(b), xs, tol=1e-10, max_iter=40)
+    assert info["residual"] <= 1e-10
+    ref = from_tree(np.linalg.solve(a, to_tree(b, h2.tree.perm)), h2.tree.perm)
+    assert np.abs(host(xs) - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("precision", [P.H2_FP64, P.H2_MIXED], ids=["fp64", "mixed"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_solve_refined(name, precision):
