@@ -24,12 +24,14 @@
 // device work of the levels before it.
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
 #include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <exception>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 
 #include <omp.h>
 
@@ -54,6 +56,7 @@ struct FactorLevel {
   const int32_t* d_stiles = nullptr;
   const SchurReduce* d_reds = nullptr;
   GemmBatch zb;
+  i64 zlen = 0;  // extent of the level's Z_ki blocks in the Z buffer
 };
 
 // Output of one chunk of rows of a level (concatenated in row order).
@@ -61,6 +64,7 @@ struct RowChunk {
   std::vector<SchurItem> items;
   std::vector<SchurSeg> segs;
   double flops = 0;
+  double dense_pairs = 0;  // sum over rows of (pivots above the row) x (targets of the row)
 };
 
 }  // namespace
@@ -94,16 +98,19 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         ck_blk[fillp[i]++] = b;
       }
   }
-  // Z buffer: the Z_ki blocks of the largest level
+  // Z buffer: the Z_ki blocks of the largest level, each stored with its
+  // row count rounded up to 16 (zero rows below m_k: the Schur kernel reads K
+  // in steps of 16)
+  auto kpad16 = [](i64 m) { return (m + 15) & ~i64(15); };
   i64 zmax = 1;
   for (const auto& lv : by_level) {
     i64 z = 0;
     for (i64 pi : lv)
-      for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) z += mb[cl(ck_pos[c])] * mb[cl(pi)];
+      for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) z += kpad16(mb[cl(ck_pos[c])]) * mb[cl(pi)];
     zmax = std::max(zmax, z);
   }
   if (zmax >= (i64(1) << 31)) fail(H2_EUNSUPPORTED, "factor level too wide for 32-bit Z offsets");
-  f.dZ.reset(sizeof(T) * zmax);
+  f.dZ.reset(sizeof(T) * (zmax + kOverread));
   T* Z = f.dZ.as<T>();
   // partial sums of split targets (at most pcap elements per level)
   f.pcap = std::min<i64>(i64(1) << 25, std::max<i64>(sp.s_entries, 1));
@@ -127,6 +134,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   // subtracting from S, the others storing partial sums that a reduction item
   // adds in part order (deterministic).  kt doubles until the partial sums of
   // the level fit the partial buffer.
+  double shape_fl[4] = {0, 0, 0, 0}, pad_fl = 0, kpad = 0, ksum = 0;  // statistics (H2SP_TRACE)
+  double st_pairs = 0, st_segs = 0, st_items = 0, st_rows = 0;
+  constexpr int edge = 64;  // Schur tile edge
+  int schur_waves = 0;      // H2SP_SCHUR_WAVES=3: Schur kernel built for 3 waves per SIMD
+  if (const char* e = std::getenv("H2SP_SCHUR_WAVES")) schur_waves = std::atoi(e);
   constexpr double kUnits = 8192;
   i64 kMinK = 512;  // smallest K of a part; H2SP_SCHUR_SPLIT_K overrides it
   if (const char* e = std::getenv("H2SP_SCHUR_SPLIT_K")) kMinK = std::max<i64>(1, std::atoll(e));
@@ -140,6 +152,13 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       for (int32_t r = it.seg_begin; r < it.seg_end; ++r) k += L.ssegs[r].K;
       kitem[t] = k;
       work += double(k) * ((it.M + 63) / 64) * ((it.N + 63) / 64);
+      if (trace_enabled()) {
+        const double fl = 2.0 * it.M * it.N * k;
+        shape_fl[(it.M > 64 ? 2 : 0) + (it.N > 64 ? 1 : 0)] += fl;
+        pad_fl += 2.0 * ((it.M + 15) / 16 * 16) * ((it.N + 15) / 16 * 16) * k;
+        for (int32_t r = it.seg_begin; r < it.seg_end; ++r) kpad += (L.ssegs[r].K + 15) / 16 * 16;
+        ksum += k;
+      }
     }
     i64 kt = std::max<i64>(kMinK, i64(work / kUnits) + 1);
     auto parts_of = [&](size_t t) -> i64 { return kitem[t] * 2 > 3 * kt ? (kitem[t] + kt - 1) / kt : 1; };
@@ -155,8 +174,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     i64 pbase = 0;
     auto emit = [&](const SchurItem& si) {
       const uint32_t item = uint32_t(L.sitems.size());
-      for (int a = 0; a < (si.M + 63) / 64; ++a)
-        for (int b = 0; b < (si.N + 63) / 64; ++b) L.stiles.push_back(int32_t((item << 8) | (a << 4) | b));
+      for (int a = 0; a < (si.M + edge - 1) / edge; ++a)
+        for (int b = 0; b < (si.N + edge - 1) / edge; ++b) L.stiles.push_back(int32_t((item << 8) | (a << 4) | b));
       L.sitems.push_back(si);
     };
     for (size_t t = 0; t < items.size(); ++t) {
@@ -211,15 +230,16 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         const i64 mk = mb[cl(pk)];
         const i64 soff = sp.blk_off[ck_blk[c]];
         GemmItem& it = L.zb.item(int(mk), int(mi), int(mk), int(mi));
-        GemmBatch::set_out(it, 0, Z + z, mk, false);
+        GemmBatch::set_out(it, 0, Z + z, kpad16(mk), false);
         // D_k^{-1} is symmetric (D_k is): read it through its transpose so that
         // both operands run along K in memory
         L.zb.seg(Inv + f.inv_off[pk], int(mk), true, S + soff, int(mk), false, int(mk));
-        L.cps.push_back({soff, z, mk * mi});
-        z += mk * mi;
+        L.cps.push_back({soff, z, int32_t(mk), int32_t(mi), int32_t(kpad16(mk)), 0});
+        z += kpad16(mk) * mi;
       }
       zbase[q + 1] = z;
     }
+    L.zlen = zbase[nr];
     fl_z += L.zb.flops;
     // Schur targets: every stored (i, j), j at or after i, of a row i of the level
     const int nchunk = int(std::min<long>(nr, 8L * nthr));
@@ -260,9 +280,10 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
               const int32_t t = mark[sp.colidx[b]];
               if (t >= 0) out.segs[sbase + fillp[t]++] = {sp.blk_off[b], int32_t(zoff), int32_t(mk)};
             }
-            zoff += mk * mi;
+            zoff += kpad16(mk) * mi;
           }
           for (i64 b = t0; b < t1; ++b) mark[sp.colidx[b]] = -1;
+          out.dense_pairs += double(cptr[pi + 1] - cptr[pi]) * nt_row;
           for (int t = 0; t < nt_row; ++t) {
             if (cnt[t + 1] == cnt[t]) continue;
             const i64 mj = mb[sp.colidx[t0 + t]];
@@ -279,7 +300,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       nitems += c.items.size();
       nsegs += c.segs.size();
       fl_s += c.flops;
+      st_pairs += c.dense_pairs;
     }
+    st_segs += double(nsegs);
+    st_items += double(nitems);
+    st_rows += double(nr);
     if (nsegs >= (size_t(1) << 31)) {
       too_wide = 1;
       return;
@@ -371,9 +396,16 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       upload_batches(all, chunk_desc.back(), blobs, cstream, st, /*parallel_pack=*/false);
       for (int lv = next; lv < end; ++lv) {
         FactorLevel<T>& L = lvls[lv];
+        // zero rows of the padded Z_ki blocks (the buffer holds the previous
+        // level's blocks in another layout)
+        if (L.zlen > 0) {
+          if constexpr (std::is_same<T, float>::value) launch_fill_f(Z, L.zlen, 0.0f, st);
+          else launch_fill(Z, L.zlen, 0.0, st);
+        }
         L.zb.template launch<T>(st, dim, 0.0, 0.0);
         mark_ev();
-        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf};
+        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf, S + sp.s_entries,
+                       schur_waves};
         launch_schur<T>(sl, st);
         launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
         mark_ev();
@@ -401,6 +433,19 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   f.flops_schur += fl_s;
   f.split_targets += nsplit;
   tt.lap("plan+upload+enqueue");
+  if (trace_enabled()) {
+    const double tot = std::max(1.0, shape_fl[0] + shape_fl[1] + shape_fl[2] + shape_fl[3]);
+    std::fprintf(stderr,
+                 "[h2sp] schur flops by target shape (M<=64,N<=64 | M<=64,N>64 | M>64,N<=64 | M>64,N>64): "
+                 "%.3f %.3f %.3f %.3f; 16-padded M N / exact %.3f; 16-padded K / exact %.3f; splits %lld\n",
+                 shape_fl[0] / tot, shape_fl[1] / tot, shape_fl[2] / tot, shape_fl[3] / tot, pad_fl / tot,
+                 kpad / std::max(1.0, ksum), (long long)nsplit);
+    std::fprintf(stderr,
+                 "[h2sp] schur pattern: rows %.0f targets %.0f segments %.0f (%.1f per target, mean K %.1f); "
+                 "segments / (pivots x targets per row) %.3f\n",
+                 st_rows, st_items, st_segs, st_segs / std::max(1.0, st_items), ksum / std::max(1.0, st_segs),
+                 st_segs / std::max(1.0, st_pairs));
+  }
   HIPCHECK(hipGetLastError());
   mark_ev();
   HIPCHECK(hipEventSynchronize(ev.back()));

@@ -62,14 +62,19 @@ void launch_gemm(const GemmLaunch& g, hipStream_t st);
 // A target with a long K is split into parts: part 0 subtracts its sum from S
 // directly, every further part stores its sum (M x N, ld M) in the partial
 // buffer and a reduction item subtracts those sums, in a fixed order.
+// Spare elements allocated past the end of S and of the Z buffer.  The Schur
+// kernel's operand loads are 4 elements wide and unconditional, so they may
+// run past a block's end; the spare elements of S are kept zero and also serve
+// as the zeros read past an item's last chunk.
+constexpr int64_t kOverread = 64;
 struct SchurItem {
   int64_t out_off;   // into S (partial == 0) or the partial buffer (partial == 1)
   int32_t M, N, seg_begin, seg_end;
   int32_t partial, pad;
 };
 struct SchurSeg {
-  int64_t b_off;     // S_kj in S (K x N)
-  int32_t a_off, K;  // Z_ki in the Z buffer (K x M)
+  int64_t b_off;     // S_kj in S (K x N, ld K)
+  int32_t a_off, K;  // Z_ki in the Z buffer (K x M, ld K rounded up to 16, zero rows below K)
 };
 struct SchurReduce {
   int64_t s_off, p_off;  // target in S; first of `parts` consecutive M x N partial sums
@@ -83,6 +88,8 @@ struct SchurLaunch {
   void* S;
   const void* Z;
   void* P;               // partial buffer
+  const void* zeros;     // 4 or more zero elements (read past an item's last chunk)
+  int32_t waves;         // 3: FP32 kernel built for 3 waves per SIMD (may spill); else the compiler's choice
 };
 template <class T>
 void launch_schur(const SchurLaunch& g, hipStream_t st);
@@ -111,9 +118,11 @@ struct InvItem {
 template <class T>
 void launch_inverse(const InvItem<T>* items, int count, int* flag, hipStream_t st);
 
-// dst[s.dst + e] = src[s.src + e] for e < s.len, for every segment s.
+// Copies a rows x cols block from src (leading dimension src_ld) to a
+// contiguous block of dst (leading dimension rows), for every segment.
 struct CopySeg {
-  int64_t dst, src, len;
+  int64_t dst, src;          // dst: rows x cols, ld rows; src: ld src_ld
+  int32_t rows, cols, src_ld, pad;
 };
 template <class T>
 void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st);

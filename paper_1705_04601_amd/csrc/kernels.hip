@@ -196,6 +196,15 @@ __device__ __forceinline__ void load4(const T* p, int k, int K, bool ok, T* v) {
 
 constexpr int KT = 64;  // tile edge of the K-contiguous kernels
 
+// Work-groups are handed to the 8 XCDs round-robin by block index, and each
+// XCD has its own L2.  Tile lists put tiles that share operands next to each
+// other; this mapping gives XCD x the x-th contiguous eighth of the list, so
+// neighbouring tiles meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int x = b % 8, q = b / 8, base = n / 8, rem = n % 8;
+  return x * base + min(x, rem) + q;
+}
+
 // Operand fetch of the direct kernel for one 16-row (or 16-column) block and
 // the four k of this lane: K-contiguous rows (vector load), M-contiguous
 // columns (one load per k, coalesced across the 16 lanes of a group) or
@@ -275,7 +284,10 @@ template <class T, int ROLE>
 __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
   using V = typename Mfma<T>::V;
   const int lane = threadIdx.x;
-  const uint32_t code = static_cast<uint32_t>(g.tiles[blockIdx.x]);
+  // the solve and matvec lists interleave heavy and light items: keep their
+  // round-robin spread over the XCDs
+  const int tb = (ROLE == ROLE_TRANSFORM || ROLE == ROLE_FACTOR) ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);
+  const uint32_t code = static_cast<uint32_t>(g.tiles[tb]);
   const GemmItem it = g.items[code >> 8];
   const int m0 = int((code >> 4) & 15) * KT, n0 = int(code & 15) * KT;
   const int nbm = min(4, (it.M - m0 + 15) / 16), nbn = min(4, (it.N - n0 + 15) / 16);
@@ -324,86 +336,113 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
 
 // Schur update of the block factorisation with compact descriptors:
 // S[out] (M x N, ld M) -= sum_seg Z[a]^T (K x M, ld K) S[b] (K x N, ld K).
-// The (segment, 16-wide k step) pairs form one chunk stream; the operands of
-// chunk c + 1 are loaded into a second register set while the MFMAs of chunk c
-// issue, so a wave keeps its loads in flight behind its own math.
-template <class T>
-__device__ __forceinline__ void schur_load(const T* S, const T* Z, const SchurSeg& sg, int k, int nbm, int nbn,
-                                           int m0, int n0, int M, int N, int r, T (&a)[4][4], T (&b)[4][4]) {
+// One wave per 64 x 64 tile.  The (segment, 16-wide k step) pairs form one
+// chunk stream, consumed with two register sets in ping-pong: the loads of
+// chunk c + 1 are in flight while the MFMAs of chunk c issue.  The number of
+// 16 x 16 blocks of the tile (NBM x NBN) is a template parameter and every
+// load is issued unconditionally, so the count of loads in flight is static
+// and the compiler waits only for the older set.  Z_ki is stored with its K
+// rounded up to 16 and zero rows below K, so a chunk may run past the end of
+// a segment: the extra k multiply zeros of Z by finite entries of S (the
+// over-read stays inside S, which is allocated with kOverread zeroed spare
+// elements at its end).
+template <class T, int NBM, int NBN>
+__device__ __forceinline__ void schur_fetch(const T* S, const T* Z, const SchurSeg& sg, int k0, bool valid,
+                                            const T* zeros, int m0, int n0, int M, int N, int r, int kq,
+                                            T (&a)[4][4], T (&b)[4][4]) {
+  // no arithmetic on the loaded values (it would make the wave wait for them
+  // at once): rows past the tile read a valid row and land in discarded
+  // outputs; k past the segment meets the zero rows of the padded Z_ki; a
+  // chunk past the item's end reads zeros
+  const int k = k0 + kq, lda = (sg.K + 15) & ~15;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int ra = m0 + 16 * q + r, cb = n0 + 16 * q + r;
-    const bool oa = q < nbm && ra < M, ob = q < nbn && cb < N;
-    if (q < nbm) load4<T>(Z + sg.a_off + int64_t(oa ? ra : 0) * sg.K, k, sg.K, oa, a[q]);
-    if (q < nbn) load4<T>(S + sg.b_off + int64_t(ob ? cb : 0) * sg.K, k, sg.K, ob, b[q]);
+  for (int q = 0; q < NBM; ++q) {
+    const int row = m0 + 16 * q + r;
+    const T* p = valid ? Z + sg.a_off + int64_t(row < M ? row : 0) * lda + k : zeros;
+    const typename Vec4<T>::type x = *reinterpret_cast<const typename Vec4<T>::type*>(p);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[q][s] = x[s];
+  }
+#pragma unroll
+  for (int q = 0; q < NBN; ++q) {
+    const int col = n0 + 16 * q + r;
+    const T* p = valid ? S + sg.b_off + int64_t(col < N ? col : 0) * sg.K + k : zeros;
+    const typename Vec4<T>::type x = *reinterpret_cast<const typename Vec4<T>::type*>(p);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) b[q][s] = x[s];
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
+template <class T, int NBM, int NBN>
+__device__ __forceinline__ void schur_mfma(typename Mfma<T>::V (&acc)[4][4], const T (&a)[4][4], const T (&b)[4][4]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int bm = 0; bm < NBM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < NBN; ++bn) acc[bm][bn] = Mfma<T>::run(b[bn][s], a[bm][s], acc[bm][bn]);
+}
+
+// Chunk cursor: segment index, first k of the chunk, the segment; valid is
+// false past the item's last segment (and stays false).
+struct SchurCursor {
+  int si, k0;
+  bool valid;
+  SchurSeg sg;
+};
+
+__device__ __forceinline__ SchurCursor schur_next(const SchurSeg* segs, int seg_end, SchurCursor c) {
+  if (!c.valid) return c;
+  c.k0 += 16;
+  if (c.k0 < c.sg.K) return c;
+  ++c.si;
+  c.k0 = 0;
+  if (c.si >= seg_end) {
+    c.valid = false;
+    return c;
+  }
+  c.sg = segs[c.si];
+  return c;
+}
+
+template <class T, int NBM, int NBN>
+__device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem& it, int m0, int n0, int lane) {
   using V = typename Mfma<T>::V;
-  const int lane = threadIdx.x;
-  const uint32_t code = static_cast<uint32_t>(g.tiles[blockIdx.x]);
-  const SchurItem it = g.items[code >> 8];
-  const int m0 = int((code >> 4) & 15) * KT, n0 = int(code & 15) * KT;
-  const int nbm = min(4, (it.M - m0 + 15) / 16), nbn = min(4, (it.N - n0 + 15) / 16);
   const int r = lane % 16, kq = 4 * (lane / 16);
   T* S = static_cast<T*>(g.S);
   const T* Z = static_cast<const T*>(g.Z);
+  const T* zeros = static_cast<const T*>(g.zeros);
   V acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = V{0, 0, 0, 0};
-  int si = it.seg_begin, k0 = 0;
-  if (si < it.seg_end) {
-    SchurSeg sg = g.segs[si];
-    T a[4][4], b[4][4];
-    schur_load<T>(S, Z, sg, k0 + kq, nbm, nbn, m0, n0, it.M, it.N, r, a, b);
+  if (it.seg_begin < it.seg_end) {
+    T a0[4][4], b0[4][4], a1[4][4], b1[4][4];
+    SchurCursor c{it.seg_begin, 0, true, g.segs[it.seg_begin]};
+    schur_fetch<T, NBM, NBN>(S, Z, c.sg, c.k0, true, zeros, m0, n0, it.M, it.N, r, kq, a0, b0);
+    // two chunks per pass, one exit: the second chunk of the last pass may
+    // be past the end and then contributes zeros
     while (true) {
-      // position of the next chunk
-      int nsi = si, nk0 = k0 + 16;
-      if (nk0 >= sg.K) {
-        ++nsi;
-        nk0 = 0;
-      }
-      const bool more = nsi < it.seg_end;
-      SchurSeg nsg = sg;
-      T na[4][4], nb[4][4];
-      if (more) {
-        if (nsi != si) nsg = g.segs[nsi];
-        schur_load<T>(S, Z, nsg, nk0 + kq, nbm, nbn, m0, n0, it.M, it.N, r, na, nb);
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int bm = 0; bm < 4; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < 4; ++bn)
-            if (bm < nbm && bn < nbn) acc[bm][bn] = Mfma<T>::run(b[bn][s], a[bm][s], acc[bm][bn]);
-      if (!more) break;
-      si = nsi;
-      k0 = nk0;
-      sg = nsg;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          a[q][s] = na[q][s];
-          b[q][s] = nb[q][s];
-        }
+      const SchurCursor c1 = schur_next(g.segs, it.seg_end, c);
+      schur_fetch<T, NBM, NBN>(S, Z, c1.sg, c1.k0, c1.valid, zeros, m0, n0, it.M, it.N, r, kq, a1, b1);
+      schur_mfma<T, NBM, NBN>(acc, a0, b0);
+      const SchurCursor c2 = schur_next(g.segs, it.seg_end, c1);
+      schur_fetch<T, NBM, NBN>(S, Z, c2.sg, c2.k0, c2.valid, zeros, m0, n0, it.M, it.N, r, kq, a0, b0);
+      schur_mfma<T, NBM, NBN>(acc, a1, b1);
+      if (!c2.valid) break;
+      c = c2;
     }
   }
   const bool part = it.partial != 0;
   T* out = (part ? static_cast<T*>(g.P) : S) + it.out_off;
 #pragma unroll
-  for (int bm = 0; bm < 4; ++bm)
+  for (int bm = 0; bm < NBM; ++bm)
 #pragma unroll
-    for (int bn = 0; bn < 4; ++bn) {
-      if (bm >= nbm || bn >= nbn) continue;
+    for (int bn = 0; bn < NBN; ++bn)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + 16 * bm + lane % 16;
+        const int row = m0 + 16 * bm + r;
         const int col = n0 + 16 * bn + Mfma<T>::row(lane, v);
         if (row < it.M && col < it.N) {
           T* o = out + row + int64_t(col) * it.M;
@@ -411,7 +450,27 @@ __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
           else *o -= acc[bm][bn][v];
         }
       }
-    }
+}
+
+// W: waves per SIMD the register budget is cut for (0: the compiler's choice)
+template <class T, int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1)))
+void schur_kernel(SchurLaunch g) {
+  const int lane = threadIdx.x;
+  const uint32_t code = static_cast<uint32_t>(g.tiles[xcd_tile(blockIdx.x, gridDim.x)]);
+  const SchurItem it = g.items[code >> 8];
+  const int m0 = int((code >> 4) & 15) * KT, n0 = int(code & 15) * KT;
+  const int nbm = min(4, (it.M - m0 + 15) / 16), nbn = min(4, (it.N - n0 + 15) / 16);
+  switch (nbm * 4 + nbn) {
+#define H2_SCHUR_CASE(I, J) \
+  case I * 4 + J: schur_tile<T, I, J>(g, it, m0, n0, lane); break;
+    H2_SCHUR_CASE(1, 1) H2_SCHUR_CASE(1, 2) H2_SCHUR_CASE(1, 3) H2_SCHUR_CASE(1, 4)
+    H2_SCHUR_CASE(2, 1) H2_SCHUR_CASE(2, 2) H2_SCHUR_CASE(2, 3) H2_SCHUR_CASE(2, 4)
+    H2_SCHUR_CASE(3, 1) H2_SCHUR_CASE(3, 2) H2_SCHUR_CASE(3, 3) H2_SCHUR_CASE(3, 4)
+    H2_SCHUR_CASE(4, 1) H2_SCHUR_CASE(4, 2) H2_SCHUR_CASE(4, 3) H2_SCHUR_CASE(4, 4)
+#undef H2_SCHUR_CASE
+    default: break;
+  }
 }
 
 // S[target] -= sum of the target's partial sums, in part order.
@@ -662,8 +721,11 @@ __global__ void copy_cols_kernel(const double* in, int64_t ldi, double* out, int
 template <class T>
 __global__ void copy_segments_kernel(const CopySeg* segs, const T* src, T* dst) {
   const CopySeg s = segs[blockIdx.y];
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < s.len; e += int64_t(gridDim.x) * blockDim.x)
-    dst[s.dst + e] = src[s.src + e];
+  const int len = s.rows * s.cols;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) {
+    const int c = e / s.rows, r = e - c * s.rows;
+    dst[s.dst + e] = src[s.src + int64_t(c) * s.src_ld + r];
+  }
 }
 
 int grid_for(int64_t n) {
@@ -700,7 +762,13 @@ template void launch_gemm<float>(const GemmLaunch&, hipStream_t);
 template <class T>
 void launch_schur(const SchurLaunch& g, hipStream_t st) {
   if (g.ntiles <= 0) return;
-  hipLaunchKernelGGL(schur_kernel<T>, dim3(g.ntiles), dim3(64), 0, st, g);
+  if constexpr (sizeof(T) == 4) {
+    if (g.waves == 3) {
+      hipLaunchKernelGGL((schur_kernel<T, 3>), dim3(g.ntiles), dim3(64), 0, st, g);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((schur_kernel<T, 0>), dim3(g.ntiles), dim3(64), 0, st, g);
 }
 template void launch_schur<double>(const SchurLaunch&, hipStream_t);
 template void launch_schur<float>(const SchurLaunch&, hipStream_t);
