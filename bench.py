@@ -31,13 +31,58 @@ import h2inputs  # noqa: E402
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense MFMA (FP32 / FP64)
 PHASES = ["qr", "close", "couplings", "strips", "factor_pivots_z", "factor_schur"]
 KERNELS = {"qr": "qr_kernel", "close": "gemm_kc_kernel<float, 0>", "couplings": "gemm_kc_kernel<float, 0>",
-           "strips": "gemm_kc_kernel<float, 0>", "factor_pivots_z": "inverse_kernel<float> + gemm_kc_kernel<float, 1>",
-           "factor_schur": "schur_kernel<float>"}
+           "strips": "gemm_kc_kernel<float, 0>",
+           "factor_pivots_z": "inverse_kernel<float> + gemm_kc_kernel<float, 1> + schur_reduce_kernel<float>",
+           "factor_schur": "schur_kernel<float, 0>"}
+# HBM traffic of the Schur kernel measured with rocprofv3 counters; used only
+# while the kernel and its planner are the sources the counters were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_kernel_cube1m_traffic.txt")
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1705_04601_amd", "csrc", f) for f in ("kernels.hip", "factor.cpp")]
 
 
 def log(msg):
     sys.stderr.write(msg + "\n")
     sys.stderr.flush()
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """Bytes per Schur launch from the committed counter summary, or None when
+    it was taken on another workload or on other kernel sources."""
+    if workload != "cube1m" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            k, sep, v = line.partition(":")
+            if sep:
+                vals[k.strip()] = v.strip()
+    if vals.get("sources_sha256") != source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib):
+    """A plain device copy of known size (counter calibration under rocprofv3)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 copies of {mib} MiB")
 
 
 def run_step(P, h, precision, b, x, tol, max_iter):
@@ -59,7 +104,8 @@ def run_step(P, h, precision, b, x, tol, max_iter):
     ms = np.concatenate([ms_sp[:4], ms_f[4:6]])
     work = np.concatenate([work_sp[:4], work_f[4:6]])
     return dict(t_sparsify=t1 - t0, t_factor=t2 - t1, t_solve=t3 - t2, info=info,
-                phase_ms=ms, phase_flops=work, qr_bytes=work_sp[6], s_blocks=nb, s_entries=ne)
+                phase_ms=ms, phase_flops=work, qr_bytes=work_sp[6], s_blocks=nb, s_entries=ne,
+                schur_launches=int(work_f[8]))
 
 
 def time_path(P, h, precision, b, x, steps, warmup, tol, max_iter):
@@ -123,7 +169,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube256k", choices=sorted(h2inputs.WORKLOADS))
+    ap.add_argument("--workload", default="cube1m", choices=sorted(h2inputs.WORKLOADS))
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device copy of this size (counter calibration)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=40)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
@@ -140,6 +188,8 @@ def main():
     wl = h2inputs.WORKLOADS[args.workload]
     n, nrhs = wl["n"], wl["nrhs"]
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        copy_probe(args.copy_probe_mib)
     log(f"workload {args.workload}: {wl}")
     x = h2inputs.points(wl["kind"], n, wl["seed"])
     sc = h2inputs.kernel_scale(wl["scale"], n)
@@ -167,8 +217,15 @@ def main():
     dom = int(np.argmax(ms))
     achieved = fl[dom] / (ms[dom] * 1e-3) / 1e12
     peak = PEAK_TFLOPS["f64"] if PHASES[dom] == "qr" else PEAK_TFLOPS["f32"]
+    launches = last["schur_launches"] if PHASES[dom] == "factor_schur" else None
+    traffic = measured_traffic(args.workload) if PHASES[dom] == "factor_schur" else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": f"{PHASES[dom]}: {KERNELS[PHASES[dom]]}",
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": f"{PHASES[dom]}: {KERNELS[PHASES[dom]]}",
+                "launches": launches,
+                "avg_launch_ms": round(float(ms[dom]) / launches, 4) if launches else None,
+                "flops_per_launch": float(fl[dom]) / launches if launches else None,
                 "phase_ms": {p: round(float(v), 3) for p, v in zip(PHASES, ms)},
                 "phase_tflops": {p: round(float(f / (m * 1e-3) / 1e12), 3) if m > 0 else None
                                  for p, f, m in zip(PHASES, fl, ms)}}

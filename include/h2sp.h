@@ -201,7 +201,8 @@ int h2_last_timings(double* ms, int count);
  * (2 m n k per product), [6] = bytes the QR phase must move at least,
  * [7] = Schur targets of the factorisation whose sum over pivots was split
  * into parts (long K; the environment variable H2SP_SCHUR_SPLIT_K sets the
- * smallest K of a part, default 512). */
+ * smallest K of a part, default 512), [8] = Schur kernel launches of the
+ * factorisation.  Entries past [8] are zero; count may be up to 16. */
 int h2_last_work(double* work, int count);
 
 #ifdef __cplusplus

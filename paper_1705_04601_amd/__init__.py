@@ -293,6 +293,6 @@ def h2_last_timings():
 
 
 def h2_last_work():
-    out = np.zeros(8)
-    _check(lib().h2_last_work(_dptr(out), 8))
+    out = np.zeros(16)
+    _check(lib().h2_last_work(_dptr(out), 16))
     return out

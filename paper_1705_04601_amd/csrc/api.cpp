@@ -13,7 +13,7 @@ std::string& last_error() {
   return msg;
 }
 static thread_local double g_timings[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-static thread_local double g_work[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+static thread_local double g_work[16] = {0};
 }  // namespace h2
 
 int apply_inverse_impl(h2_factor* f, const double* b, double* x, h2::i64 nrhs, h2::i64 ld);
@@ -153,6 +153,7 @@ extern "C" int h2_factor_S(h2_sparse* sp, h2_factor** out) {
   g_work[4] = f->flops_inv + f->flops_z;
   g_work[5] = f->flops_schur;
   g_work[7] = double(f->split_targets);
+  g_work[8] = double(f->schur_launches);
   *out = f.release();
   H2_API_END
 }
@@ -188,7 +189,7 @@ extern "C" int h2_last_timings(double* ms, int count) {
 extern "C" int h2_last_work(double* work, int count) {
   H2_API_BEGIN
   if (!work) fail(H2_EINVAL, "null argument");
-  for (int i = 0; i < count && i < 8; ++i) work[i] = g_work[i];
+  for (int i = 0; i < count && i < 16; ++i) work[i] = g_work[i];
   H2_API_END
 }
 

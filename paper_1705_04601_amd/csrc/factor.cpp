@@ -57,6 +57,7 @@ struct FactorLevel {
   const SchurReduce* d_reds = nullptr;
   GemmBatch zb;
   i64 zlen = 0;  // extent of the level's Z_ki blocks in the Z buffer
+  int32_t nschur_tiles = 0;
 };
 
 // Output of one chunk of rows of a level (concatenated in row order).
@@ -404,11 +405,12 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         }
         L.zb.template launch<T>(st, dim, 0.0, 0.0);
         mark_ev();
+        L.nschur_tiles = int32_t(L.stiles.size());
         SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf, S + sp.s_entries,
                        schur_waves};
         launch_schur<T>(sl, st);
-        launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
         mark_ev();
+        launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
         launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
         launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
         mark_ev();
@@ -432,6 +434,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   f.flops_z += fl_z;
   f.flops_schur += fl_s;
   f.split_targets += nsplit;
+  for (const auto& L : lvls) f.schur_launches += L.nschur_tiles > 0 ? 1 : 0;
   tt.lap("plan+upload+enqueue");
   if (trace_enabled()) {
     const double tot = std::max(1.0, shape_fl[0] + shape_fl[1] + shape_fl[2] + shape_fl[3]);

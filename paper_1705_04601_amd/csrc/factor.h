@@ -30,6 +30,7 @@ struct h2_factor {
   h2::i64 pcap = 0;                          // elements of the partial-sum buffer dP
   double flops_schur = 0, flops_inv = 0, flops_z = 0;
   h2::i64 split_targets = 0;                 // Schur targets summed in parts
+  h2::i64 schur_launches = 0;                // Schur kernel launches
   std::unique_ptr<h2::SolvePlan> solve;
   ~h2_factor();
 };
