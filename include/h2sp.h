@@ -63,6 +63,13 @@ typedef struct {
   int precision;         /* H2_FP64 or H2_MIXED                                  */
 } h2_sparsify_opts;
 
+enum { H2_FACTOR_EXACT = 0,     /* block LU of S with its fill (exact up to rounding) */
+       H2_FACTOR_ILU0 = 1 };    /* block ILU(0): S's own pattern, no fill (default)  */
+
+typedef struct {
+  int mode;              /* H2_FACTOR_EXACT or H2_FACTOR_ILU0                    */
+} h2_factor_opts;
+
 typedef struct {
   double tol;            /* stop when max_col ||b - A x||_2 / ||b||_2 <= tol     */
   int max_iter;          /* refinement steps (>= 1)                              */
@@ -78,7 +85,7 @@ typedef struct {
 
 typedef struct h2_matrix h2_matrix;   /* tree, block tree, H^2 coefficients       */
 typedef struct h2_sparse h2_sparse;   /* Q_t of every cluster, S, plan            */
-typedef struct h2_factor h2_factor;   /* block ILU(0) of S                         */
+typedef struct h2_factor h2_factor;   /* block L D L^T of S (exact or ILU(0))      */
 
 /* ---- library state --------------------------------------------------------- */
 const char* h2_last_error(void);
@@ -168,13 +175,20 @@ int h2_sparse_export_q(const h2_sparse* sp, int64_t t, double* out);
 
 /* ---- factorisation of S (the sparse-solver step of Sections 5.3-5.5) -------- */
 /*
- * h2_factor_S: block ILU(0) of S on its own pattern in S order, symmetric form
- * S ~ L D L^T with L^T_kj = D_k^{-1} S_kj; pivot blocks D_k inverted in FP64 by
- * Gauss-Jordan with partial pivoting.  Right-looking, one launch per level of
- * the elimination DAG.  ESINGULAR if a pivot block is singular.
- * The handle keeps a reference to `sp`.
+ * h2_factor_S: block factorisation of S in the elimination order, symmetric
+ * form S = L D L^T with L^T_kj = D_k^{-1} S_kj (S is symmetric, Proposition
+ * 2.1); the sparse direct factorisation of Sections 5.3-5.4 (H2_FACTOR_EXACT)
+ * or its incomplete form used as a preconditioner in Section 5.5
+ * (H2_FACTOR_ILU0).  EXACT first extends S's block pattern by its symbolic
+ * fill (new blocks start at zero) and so re-lays `sp`'s S; ENOMEM if the
+ * filled S does not fit in device memory.  Pivot blocks D_k are inverted in
+ * FP64 by Gauss-Jordan with partial pivoting; the Schur updates run in the
+ * precision of `sp`.  Left-looking, a few launches per level of the
+ * elimination DAG.  opts NULL = ILU(0).  The factors overwrite S: a sparse
+ * handle is factored once (EINVAL on a second call).  ESINGULAR if a pivot
+ * block is singular.  The handle keeps a reference to `sp`.
  */
-int h2_factor_S(h2_sparse* sp, h2_factor** out);
+int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor** out);
 
 /*
  * h2_solve: x = A_H2^{-1} b by iterative refinement: x += V (L D L^T)^{-1} U^T r,
@@ -202,7 +216,8 @@ int h2_last_timings(double* ms, int count);
  * [7] = Schur targets of the factorisation whose sum over pivots was split
  * into parts (long K; the environment variable H2SP_SCHUR_SPLIT_K sets the
  * smallest K of a part, default 512), [8] = Schur kernel launches of the
- * factorisation.  Entries past [8] are zero; count may be up to 16. */
+ * factorisation, [9] = stored S entries the factorisation worked on (after
+ * the fill in exact mode).  Entries past [9] are zero; count may be up to 16. */
 int h2_last_work(double* work, int count);
 
 #ifdef __cplusplus

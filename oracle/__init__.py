@@ -26,7 +26,8 @@ from .householder import householder_qr
 from .sparsify import (Sparsified, sparsify, apply_ut, apply_v, dense_s, dense_u,
                        pattern_predicate, cluster_sizes)
 from .solve import (BlockILU0, dense_lu_solver, refine, rel_residual,
-                    conjugate_gradient, elimination_order, elimination_colours)
+                    conjugate_gradient, elimination_order, elimination_colours,
+                    block_fill, filled)
 
 __all__ = [
     "ClusterTree", "BlockTree", "build_cluster_tree", "build_block_tree",
@@ -35,4 +36,5 @@ __all__ = [
     "apply_ut", "apply_v", "dense_s", "dense_u", "pattern_predicate",
     "cluster_sizes", "BlockILU0", "dense_lu_solver", "refine", "rel_residual",
     "conjugate_gradient", "elimination_order", "elimination_colours",
+    "block_fill", "filled",
 ]

@@ -60,6 +60,43 @@ def elimination_order(sp: Sparsified):
     return sorted(colour, key=lambda u: (tr.level(u), colour[u], u))
 
 
+def block_fill(sp: Sparsified, order):
+    """Block pattern of the exact factorisation of S in ``order``: graph
+    elimination on the symmetric block pattern (eliminating k joins every
+    pair of its later neighbours), the fill of a sparse direct factorisation
+    (Sections 5.3-5.4).  Returns the set of (t, s) blocks, both orientations."""
+    order = [int(c) for c in order if sp.nonbasis[c] > 0]
+    pos = {c: i for i, c in enumerate(order)}
+    nbr = {c: set() for c in order}
+    for (t, s) in sp.s_blocks:
+        if t != s:
+            nbr[t].add(s)
+    for k in order:
+        later = [j for j in nbr[k] if pos[j] > pos[k]]
+        for a in later:
+            for b in later:
+                if a != b:
+                    nbr[a].add(b)
+    out = {(c, c) for c in order}
+    for t, ns in nbr.items():
+        for s in ns:
+            out.add((t, s))
+    return out
+
+
+def filled(sp: Sparsified, order):
+    """A copy of ``sp`` whose S carries explicit zero blocks on the fill of
+    ``block_fill``; BlockILU0 on it is the exact block factorisation."""
+    import copy
+    out = copy.copy(sp)
+    blocks = dict(sp.s_blocks)
+    for (t, s) in block_fill(sp, order):
+        if (t, s) not in blocks:
+            blocks[(t, s)] = np.zeros((sp.nonbasis[t], sp.nonbasis[s]))
+    out.s_blocks = blocks
+    return out
+
+
 class BlockILU0:
     """Block ILU(0) of S (IKJ form) in S order or in a given elimination order."""
 

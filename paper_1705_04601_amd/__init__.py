@@ -21,6 +21,7 @@ HEADER = os.path.join(HERE, "..", "include", "h2sp.h")
 H2_OK, H2_EINVAL, H2_ENOMEM, H2_EDEVICE, H2_ESINGULAR, H2_ENOCONV, H2_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 H2_KERNEL_INVDIST = 0
 H2_FP64, H2_MIXED = 0, 1
+H2_FACTOR_EXACT, H2_FACTOR_ILU0 = 0, 1
 
 _NAMES = {0: "H2_OK", -1: "H2_EINVAL", -2: "H2_ENOMEM", -3: "H2_EDEVICE", -4: "H2_ESINGULAR",
           -5: "H2_ENOCONV", -6: "H2_EUNSUPPORTED"}
@@ -43,6 +44,10 @@ class h2_build_opts(ctypes.Structure):
 
 class h2_sparsify_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int)]
+
+
+class h2_factor_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int)]
 
 
 class h2_solve_opts(ctypes.Structure):
@@ -77,7 +82,7 @@ _SIGS = {
     "h2_sparse_export_plan": (ctypes.c_int, [_P, _I64P, _I64P, _I64P, _I64P, _I64P, _I64P, _I64P]),
     "h2_sparse_export_block": (ctypes.c_int, [_P, _I64, _I64, _DP]),
     "h2_sparse_export_q": (ctypes.c_int, [_P, _I64, _DP]),
-    "h2_factor_S": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "h2_factor_S": (ctypes.c_int, [_P, ctypes.POINTER(h2_factor_opts), ctypes.POINTER(_P)]),
     "h2_solve": (ctypes.c_int, [_P, _P, _P, _I64, _I64, ctypes.POINTER(h2_solve_opts),
                                 ctypes.POINTER(h2_solve_info)]),
     "h2_apply_inverse": (ctypes.c_int, [_P, _P, _P, _I64, _I64]),
@@ -260,10 +265,11 @@ def h2_sparse_export_q(sp: H2SparseHandle, t: int, n: int) -> np.ndarray:
     return out.reshape(n, n).T
 
 
-def h2_factor_S(sp: H2SparseHandle) -> H2FactorHandle:
+def h2_factor_S(sp: H2SparseHandle, mode: int = H2_FACTOR_ILU0) -> H2FactorHandle:
     _use_torch_stream()
     out = _P()
-    _check(lib().h2_factor_S(sp.ptr, ctypes.byref(out)))
+    o = h2_factor_opts(int(mode))
+    _check(lib().h2_factor_S(sp.ptr, ctypes.byref(o), ctypes.byref(out)))
     return H2FactorHandle(out.value, keep=sp)
 
 

@@ -6,7 +6,7 @@
 
 namespace h2 {
 h2_sparse* plan_sparsify(h2_matrix* H, int precision);
-h2_factor* factor(h2_sparse* sp, hipStream_t st, double* phase_ms);
+h2_factor* factor(h2_sparse* sp, bool exact, hipStream_t st, double* phase_ms);
 void set_stream(hipStream_t s);
 std::string& last_error() {
   static thread_local std::string msg;
@@ -140,13 +140,16 @@ extern "C" int h2_sparse_export_q(const h2_sparse* sp, int64_t t, double* out) {
   H2_API_END
 }
 
-extern "C" int h2_factor_S(h2_sparse* sp, h2_factor** out) {
+extern "C" int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor** out) {
   H2_API_BEGIN
   if (!sp || !out) fail(H2_EINVAL, "null argument");
   *out = nullptr;
+  const int mode = opts ? opts->mode : H2_FACTOR_ILU0;
+  if (mode != H2_FACTOR_EXACT && mode != H2_FACTOR_ILU0) fail(H2_EINVAL, "unknown factorisation mode");
+  if (sp->factored) fail(H2_EINVAL, "S of this sparse handle is already factored");
   for (int i = 4; i < 8; ++i) g_timings[i] = 0;
   double ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  std::unique_ptr<h2_factor> f(factor(sp, current_stream(), ph));
+  std::unique_ptr<h2_factor> f(factor(sp, mode == H2_FACTOR_EXACT, current_stream(), ph));
   g_timings[4] = ph[4];
   g_timings[5] = ph[5];
   g_timings[7] = ph[6];
@@ -154,6 +157,7 @@ extern "C" int h2_factor_S(h2_sparse* sp, h2_factor** out) {
   g_work[5] = f->flops_schur;
   g_work[7] = double(f->split_targets);
   g_work[8] = double(f->schur_launches);
+  g_work[9] = double(sp->s_entries);
   *out = f.release();
   H2_API_END
 }

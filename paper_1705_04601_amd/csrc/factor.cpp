@@ -29,6 +29,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <exception>
+#include <string>
 #include <mutex>
 #include <thread>
 #include <type_traits>
@@ -129,7 +130,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   std::condition_variable cv;
   const int nthr = std::max(1, omp_get_max_threads());
   std::vector<std::vector<int32_t>> marks(nthr);
-  // Split-K of long targets.  A level's Schur work is spread over at least
+  // Split-K of long targets.  A level's Schur work is spread over about
   // kUnits tile-sized units where it has that much: a target whose K exceeds
   // 1.5 kt is cut at segment boundaries into parts of about kt, part 0
   // subtracting from S, the others storing partial sums that a reduction item
@@ -138,9 +139,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   double shape_fl[4] = {0, 0, 0, 0}, pad_fl = 0, kpad = 0, ksum = 0;  // statistics (H2SP_TRACE)
   double st_pairs = 0, st_segs = 0, st_items = 0, st_rows = 0;
   constexpr int edge = 64;  // Schur tile edge
-  int schur_waves = 0;      // H2SP_SCHUR_WAVES=3: Schur kernel built for 3 waves per SIMD
-  if (const char* e = std::getenv("H2SP_SCHUR_WAVES")) schur_waves = std::atoi(e);
-  constexpr double kUnits = 8192;
+  double kUnits = 32768;  // H2SP_SCHUR_UNITS overrides
+  if (const char* e = std::getenv("H2SP_SCHUR_UNITS")) kUnits = std::max(1.0, std::atof(e));
+
   i64 kMinK = 512;  // smallest K of a part; H2SP_SCHUR_SPLIT_K overrides it
   if (const char* e = std::getenv("H2SP_SCHUR_SPLIT_K")) kMinK = std::max<i64>(1, std::atoll(e));
   const i64 pcap = f.pcap;
@@ -406,8 +407,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         L.zb.template launch<T>(st, dim, 0.0, 0.0);
         mark_ev();
         L.nschur_tiles = int32_t(L.stiles.size());
-        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf, S + sp.s_entries,
-                       schur_waves};
+        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf, S + sp.s_entries};
         launch_schur<T>(sl, st);
         mark_ev();
         launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
@@ -472,7 +472,104 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   }
 }
 
-h2_factor* factor(h2_sparse* sp, hipStream_t st, double* phase_ms) {
+// Exact mode: extends S's stored upper block pattern by the symbolic fill of
+// its elimination in the elimination order (row structures of the block
+// factor: a row's pattern is its own plus its children's in the elimination
+// tree, the parent of a row being its first off-diagonal block), and re-lays
+// S with the new blocks zero.  Block ILU(0) on the filled pattern is then the
+// exact block factorisation.
+template <class T>
+static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
+  TraceTimer tt("fill");
+  const i64 ncl = sp.ncl;
+  const auto& mb = sp.nonbasis;
+  std::vector<std::vector<i64>> R(ncl), kids(ncl);
+  std::vector<i64> mark(ncl, -1);
+  for (i64 pos = 0; pos < ncl; ++pos) {
+    if (mb[sp.eorder[pos]] == 0) {
+      if (sp.rowptr[pos] != sp.rowptr[pos + 1]) fail(H2_EINVAL, "internal: S row without rows");
+      continue;
+    }
+    std::vector<i64>& r = R[pos];
+    mark[pos] = pos;
+    for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) {
+      const i64 j = sp.epos[sp.colidx[b]];
+      if (mark[j] != pos) {
+        mark[j] = pos;
+        r.push_back(j);
+      }
+    }
+    for (i64 c : kids[pos])
+      for (i64 j : R[c])
+        if (mark[j] != pos) {
+          mark[j] = pos;
+          r.push_back(j);
+        }
+    std::vector<i64>().swap(kids[pos]);
+    std::sort(r.begin(), r.end());
+    if (!r.empty()) kids[r[0]].push_back(pos);
+  }
+  std::vector<i64> rowptr(ncl + 1, 0), colidx, blk_off;
+  i64 ent = 0;
+  for (i64 pos = 0; pos < ncl; ++pos) {
+    const i64 c = sp.eorder[pos];
+    if (mb[c] > 0) {
+      colidx.push_back(c);
+      blk_off.push_back(ent);
+      ent += mb[c] * mb[c];
+      for (i64 j : R[pos]) {
+        const i64 cj = sp.eorder[j];
+        colidx.push_back(cj);
+        blk_off.push_back(ent);
+        ent += mb[c] * mb[cj];
+      }
+    }
+    rowptr[pos + 1] = i64(colidx.size());
+    std::vector<i64>().swap(R[pos]);
+  }
+  tt.lap("symbolic");
+  const size_t el = sizeof(T);
+  size_t free_b = 0, total_b = 0;
+  HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+  const double need = double(el) * double(ent + kOverread);
+  if (need > 0.9 * double(free_b))
+    fail(H2_ENOMEM, "exact factorisation: the filled S needs " + std::to_string(need / 1e9) + " GB, " +
+                        std::to_string(double(free_b) / 1e9) + " GB of device memory free");
+  // old blocks -> their places in the filled layout
+  std::vector<CopySeg> cps;
+  cps.reserve(sp.colidx.size());
+  for (i64 pos = 0; pos < ncl; ++pos) {
+    const i64 mi = mb[sp.eorder[pos]];
+    i64 nb = rowptr[pos];
+    for (i64 b = sp.rowptr[pos]; b < sp.rowptr[pos + 1]; ++b) {
+      const i64 cj = sp.colidx[b];
+      while (nb < rowptr[pos + 1] && colidx[nb] != cj) ++nb;
+      if (nb == rowptr[pos + 1]) fail(H2_EINVAL, "internal: fill pattern misses a block of S");
+      cps.push_back({blk_off[nb], sp.blk_off[b], int32_t(mi), int32_t(mb[cj]), int32_t(mi), 0});
+    }
+  }
+  DeviceBuffer nS(el * size_t(ent + kOverread));
+  if constexpr (std::is_same<T, float>::value) launch_fill_f(nS.as<float>(), ent + kOverread, 0.0f, st);
+  else launch_fill(nS.as<double>(), ent + kOverread, 0.0, st);
+  DeviceBuffer dcps(sizeof(CopySeg) * std::max<size_t>(cps.size(), 1));
+  HIPCHECK(hipMemcpyAsync(dcps.ptr, cps.data(), sizeof(CopySeg) * cps.size(), hipMemcpyHostToDevice, st));
+  launch_copy_segments<T>(dcps.as<CopySeg>(), int(cps.size()), sp.dS.as<T>(), nS.as<T>(), st);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(st));
+  sp.dS = std::move(nS);
+  sp.rowptr.swap(rowptr);
+  sp.colidx.swap(colidx);
+  sp.blk_off.swap(blk_off);
+  sp.s_entries = ent;
+  tt.lap("relayout");
+}
+
+h2_factor* factor(h2_sparse* sp, bool exact, hipStream_t st, double* phase_ms) {
+  if (exact) {
+    if (sp->precision == H2_MIXED) extend_by_fill<float>(*sp, st);
+    else extend_by_fill<double>(*sp, st);
+  }
+  sp->factored = true;
   auto fp = std::make_unique<h2_factor>();
   h2_factor& f = *fp;
   f.sp = sp;

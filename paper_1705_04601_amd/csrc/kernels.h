@@ -89,7 +89,6 @@ struct SchurLaunch {
   const void* Z;
   void* P;               // partial buffer
   const void* zeros;     // 4 or more zero elements (read past an item's last chunk)
-  int32_t waves;         // 3: FP32 kernel built for 3 waves per SIMD (may spill); else the compiler's choice
 };
 template <class T>
 void launch_schur(const SchurLaunch& g, hipStream_t st);

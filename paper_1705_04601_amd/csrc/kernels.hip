@@ -452,10 +452,8 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
       }
 }
 
-// W: waves per SIMD the register budget is cut for (0: the compiler's choice)
-template <class T, int W>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1)))
-void schur_kernel(SchurLaunch g) {
+template <class T>
+__global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
   const int lane = threadIdx.x;
   const uint32_t code = static_cast<uint32_t>(g.tiles[xcd_tile(blockIdx.x, gridDim.x)]);
   const SchurItem it = g.items[code >> 8];
@@ -762,13 +760,7 @@ template void launch_gemm<float>(const GemmLaunch&, hipStream_t);
 template <class T>
 void launch_schur(const SchurLaunch& g, hipStream_t st) {
   if (g.ntiles <= 0) return;
-  if constexpr (sizeof(T) == 4) {
-    if (g.waves == 3) {
-      hipLaunchKernelGGL((schur_kernel<T, 3>), dim3(g.ntiles), dim3(64), 0, st, g);
-      return;
-    }
-  }
-  hipLaunchKernelGGL((schur_kernel<T, 0>), dim3(g.ntiles), dim3(64), 0, st, g);
+  hipLaunchKernelGGL(schur_kernel<T>, dim3(g.ntiles), dim3(64), 0, st, g);
 }
 template void launch_schur<double>(const SchurLaunch&, hipStream_t);
 template void launch_schur<float>(const SchurLaunch&, hipStream_t);

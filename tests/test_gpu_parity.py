@@ -208,6 +208,56 @@ def test_split_schur_targets_mixed_solve(monkeypatch):
     assert np.abs(host(xs) - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_exact_factor_fill_and_inverse(name):
+    """Exact mode: the filled pattern matches the oracle's graph elimination
+    bit for bit, and one application of V (L D L^T)^{-1} U^T is A_H2^{-1}."""
+    x, sc, h2, sp, a, _ = case(name)
+    note(f"exact factor fp64 {name}")
+    h = imported(name)
+    sph = P.h2_sparsify(h, P.H2_FP64)
+    f = P.h2_factor_S(sph, P.H2_FACTOR_EXACT)
+    plan = P.h2_sparse_export_plan(sph)
+    order = oracle.elimination_order(sp)
+    pos = {c: i for i, c in enumerate(order)}
+    got = set()
+    for i, t in enumerate(plan["elim"]):
+        for b in range(plan["rowptr"][i], plan["rowptr"][i + 1]):
+            got.add((int(t), int(plan["colidx"][b])))
+    want = {(t, s) for (t, s) in oracle.block_fill(sp, order) if pos[t] <= pos[s]}
+    assert got == want
+    assert P.h2_last_work()[9] == sum(sp.nonbasis[t] * sp.nonbasis[s] for (t, s) in want)
+    b = np.random.default_rng(10).standard_normal((x.shape[0], 3))
+    out = dev(np.zeros_like(b))
+    P.h2_apply_inverse(f, dev(b), out)
+    ref = from_tree(np.linalg.solve(a, to_tree(b, h2.tree.perm)), h2.tree.perm)
+    assert np.abs(host(out) - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["cube1536", "cube2500r48", "torus777"])
+def test_exact_factor_mixed_solve(name):
+    x, sc, h2, sp, a, (leaf, cheb, tol, cap, eta) = case(name)
+    note(f"exact factor mixed {name}")
+    h = P.h2_build(x, sc, 1.0, leaf, cheb, tol, cap, eta)
+    f = P.h2_factor_S(P.h2_sparsify(h, P.H2_MIXED), P.H2_FACTOR_EXACT)
+    b = np.random.default_rng(11).standard_normal((x.shape[0], 4))
+    xs = dev(np.zeros_like(b))
+    info = P.h2_solve(f, dev(b), xs, tol=1e-10, max_iter=10)
+    assert info["residual"] <= 1e-10 and info["iters"] <= 3
+    ref = from_tree(np.linalg.solve(a, to_tree(b, h2.tree.perm)), h2.tree.perm)
+    assert np.abs(host(xs) - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_factor_twice_is_rejected():
+    x, sc, h2, sp, a, _ = case("torus777")
+    note("factor twice")
+    sph = P.h2_sparsify(imported("torus777"), P.H2_FP64)
+    P.h2_factor_S(sph)
+    with pytest.raises(P.H2Error) as e:
+        P.h2_factor_S(sph, P.H2_FACTOR_EXACT)
+    assert e.value.code == P.H2_EINVAL
+
+
 @pytest.mark.parametrize("precision", [P.H2_FP64, P.H2_MIXED], ids=["fp64", "mixed"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_solve_refined(name, precision):

@@ -72,7 +72,7 @@ def test_null_handles_are_rejected():
     lib = P.lib()
     out = ctypes.c_void_p()
     assert lib.h2_sparsify(None, None, ctypes.byref(out)) == P.H2_EINVAL
-    assert lib.h2_factor_S(None, ctypes.byref(out)) == P.H2_EINVAL
+    assert lib.h2_factor_S(None, None, ctypes.byref(out)) == P.H2_EINVAL
     assert lib.h2_matvec(None, None, None, 1, 1) == P.H2_EINVAL
     lib.h2_matrix_destroy(None)
     lib.h2_sparse_destroy(None)

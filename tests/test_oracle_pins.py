@@ -330,6 +330,46 @@ def test_ilu0_full_pattern_is_lu_in_any_order():
         assert np.abs(oracle.BlockILU0(sp, order).solve(b) - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+def test_block_fill_gives_exact_factor(case):
+    """Block ILU(0) on the pattern closed under graph elimination is the exact
+    block factorisation: it reproduces the dense solve of S (Sections 5.3-5.4
+    use a sparse direct factorisation).  The fill is idempotent and the
+    unfilled ILU(0) is not exact, so the pin tells the two apart."""
+    h2, sp, a, u, s = case
+    order = oracle.elimination_order(sp)
+    fill = oracle.block_fill(sp, order)
+    assert set(sp.s_blocks) <= fill
+    assert oracle.block_fill(oracle.filled(sp, order), order) == fill
+    b = np.random.default_rng(6).standard_normal((h2.tree.n, 2))
+    ref = np.linalg.solve(s, b)
+    got = oracle.BlockILU0(oracle.filled(sp, order), order).solve(b)
+    err = np.abs(got - ref).max()
+    assert err <= 1e-11 * np.abs(ref).max()
+    if len(fill) > len(sp.s_blocks):
+        ilu = oracle.BlockILU0(sp, order).solve(b)
+        assert np.abs(ilu - ref).max() > 100 * max(err, 1e-15 * np.abs(ref).max())
+
+
+def test_block_fill_brute_force():
+    """Tiny pattern: fill against elimination of a dense boolean matrix."""
+    h2 = _h2("square", 400, 8, 16, 3)
+    sp = oracle.sparsify(h2)
+    order = oracle.elimination_order(sp)
+    fill = oracle.block_fill(sp, order)
+    idx = {c: i for i, c in enumerate(order)}
+    n = len(order)
+    g = np.zeros((n, n), dtype=bool)
+    for (t, v) in sp.s_blocks:
+        g[idx[t], idx[v]] = True
+    for k in range(n):                      # symbolic Gaussian elimination
+        later = [j for j in range(k + 1, n) if g[k, j]]
+        for i in later:
+            for j in later:
+                g[i, j] = True
+    want = {(order[i], order[j]) for i in range(n) for j in range(n) if g[i, j]}
+    assert fill == want
+
+
 def test_cg_reference(case):
     h2, sp, a, u, s = case
     b = np.random.default_rng(5).standard_normal((h2.tree.n, 1))
