@@ -85,14 +85,14 @@ def copy_probe(mib):
     log(f"copy probe: 3 copies of {mib} MiB")
 
 
-def run_step(P, h, precision, b, x, tol, max_iter):
+def run_step(P, h, precision, b, x, tol, max_iter, mode):
     import torch
     t0 = time.perf_counter()
     sp = P.h2_sparsify(h, precision)
     ms_sp = P.h2_last_timings().copy()
     work_sp = P.h2_last_work().copy()
     t1 = time.perf_counter()
-    f = P.h2_factor_S(sp)
+    f = P.h2_factor_S(sp, mode)
     ms_f = P.h2_last_timings().copy()
     work_f = P.h2_last_work().copy()
     t2 = time.perf_counter()
@@ -105,19 +105,19 @@ def run_step(P, h, precision, b, x, tol, max_iter):
     work = np.concatenate([work_sp[:4], work_f[4:6]])
     return dict(t_sparsify=t1 - t0, t_factor=t2 - t1, t_solve=t3 - t2, info=info,
                 phase_ms=ms, phase_flops=work, qr_bytes=work_sp[6], s_blocks=nb, s_entries=ne,
-                schur_launches=int(work_f[8]))
+                schur_launches=int(work_f[8]), factor_entries=int(work_f[9]))
 
 
-def time_path(P, h, precision, b, x, steps, warmup, tol, max_iter):
+def time_path(P, h, precision, b, x, steps, warmup, tol, max_iter, mode):
     import torch
     for w in range(warmup):
         log(f"warmup {w + 1}/{warmup} precision={precision}")
-        run_step(P, h, precision, b, x, tol, max_iter)
+        run_step(P, h, precision, b, x, tol, max_iter, mode)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
     for k in range(steps):
-        recs.append(run_step(P, h, precision, b, x, tol, max_iter))
+        recs.append(run_step(P, h, precision, b, x, tol, max_iter, mode))
         log(f"step {k + 1}/{steps} precision={precision}: sparsify {recs[-1]['t_sparsify']:.3f}s "
             f"factor {recs[-1]['t_factor']:.3f}s solve {recs[-1]['t_solve']:.3f}s "
             f"iters {recs[-1]['info']['iters']} res {recs[-1]['info']['residual']:.2e}")
@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=40)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--factor", default="ilu0", choices=["ilu0", "exact"],
+                    help="block ILU(0) of S (default) or the exact block factorisation with fill")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported in this build "
@@ -206,7 +208,8 @@ def main():
     res = {}
     paths = [("mixed", P.H2_MIXED)] + ([] if args.no_fp64 else [("fp64", P.H2_FP64)])
     for name, prec in paths:
-        sec, recs = time_path(P, h, prec, b, xs, args.steps, args.warmup, args.tol, args.max_iter)
+        mode = P.H2_FACTOR_EXACT if args.factor == "exact" else P.H2_FACTOR_ILU0
+        sec, recs = time_path(P, h, prec, b, xs, args.steps, args.warmup, args.tol, args.max_iter, mode)
         res[name] = (sec, recs)
 
     sec, recs = res["mixed"]
@@ -246,7 +249,8 @@ def main():
                    "leaf": wl["leaf"], "cheb": wl["cheb"], "recompress_tol": wl["tol"],
                    "rank_cap": wl["rank_cap"], "kernel": "1/(4 pi N |x-y|), A_ii = 1"
                    if wl["scale"] != "1/N" else "1/(N |x-y|), A_ii = 1",
-                   "factor": "block ILU(0) of S", "precision": "mixed"},
+                   "factor": "block ILU(0) of S" if args.factor == "ilu0" else "exact block LDL^T of S (with fill)",
+                   "precision": "mixed"},
         "mixed": {"t_sparsify": last["t_sparsify"], "t_factor_S": last["t_factor"],
                   "t_solve": last["t_solve"], "factor_plus_solve_s": sec,
                   "iters": last["info"]["iters"], "rel_residual": last["info"]["residual"],
@@ -254,6 +258,7 @@ def main():
                                      "plan_host": last["info"]["t_plan"]},
                   "rhs_n_per_s_solve": nrhs * n / last["t_solve"]},
         "s_blocks": last["s_blocks"], "s_entries": last["s_entries"],
+        "factor_entries": last["factor_entries"],
         "h2_build_s": t_build,
         "roofline": roofline,
     }

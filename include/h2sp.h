@@ -190,6 +190,11 @@ int h2_sparse_export_q(const h2_sparse* sp, int64_t t, double* out);
  */
 int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor** out);
 
+/* Host-only symbolic analysis of the exact mode, before factoring: entries of
+ * the filled upper block triangle of S and the flops of its Schur updates
+ * (2 m_i m_j m_k per update).  Either pointer may be NULL. */
+int h2_factor_analyze(const h2_sparse* sp, int64_t* filled_entries, double* exact_flops);
+
 /*
  * h2_solve: x = A_H2^{-1} b by iterative refinement: x += V (L D L^T)^{-1} U^T r,
  * r = b - A_H2 x with the FP64 H^2 matvec, until max_col ||r||/||b|| <= tol.

@@ -83,6 +83,7 @@ _SIGS = {
     "h2_sparse_export_block": (ctypes.c_int, [_P, _I64, _I64, _DP]),
     "h2_sparse_export_q": (ctypes.c_int, [_P, _I64, _DP]),
     "h2_factor_S": (ctypes.c_int, [_P, ctypes.POINTER(h2_factor_opts), ctypes.POINTER(_P)]),
+    "h2_factor_analyze": (ctypes.c_int, [_P, _I64P, _DP]),
     "h2_solve": (ctypes.c_int, [_P, _P, _P, _I64, _I64, ctypes.POINTER(h2_solve_opts),
                                 ctypes.POINTER(h2_solve_info)]),
     "h2_apply_inverse": (ctypes.c_int, [_P, _P, _P, _I64, _I64]),
@@ -271,6 +272,14 @@ def h2_factor_S(sp: H2SparseHandle, mode: int = H2_FACTOR_ILU0) -> H2FactorHandl
     o = h2_factor_opts(int(mode))
     _check(lib().h2_factor_S(sp.ptr, ctypes.byref(o), ctypes.byref(out)))
     return H2FactorHandle(out.value, keep=sp)
+
+
+def h2_factor_analyze(sp: H2SparseHandle):
+    """(filled entries, exact-mode Schur flops) of S's exact factorisation."""
+    e = ctypes.c_int64()
+    fl = ctypes.c_double()
+    _check(lib().h2_factor_analyze(sp.ptr, ctypes.byref(e), ctypes.byref(fl)))
+    return e.value, fl.value
 
 
 def h2_solve(f: H2FactorHandle, b, x, tol: float = 1e-10, max_iter: int = 30, check: bool = True):

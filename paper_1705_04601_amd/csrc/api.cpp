@@ -7,6 +7,7 @@
 namespace h2 {
 h2_sparse* plan_sparsify(h2_matrix* H, int precision);
 h2_factor* factor(h2_sparse* sp, bool exact, hipStream_t st, double* phase_ms);
+void analyze_fill(const h2_sparse& sp, double* entries, double* flops);
 void set_stream(hipStream_t s);
 std::string& last_error() {
   static thread_local std::string msg;
@@ -159,6 +160,17 @@ extern "C" int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor*
   g_work[8] = double(f->schur_launches);
   g_work[9] = double(sp->s_entries);
   *out = f.release();
+  H2_API_END
+}
+
+extern "C" int h2_factor_analyze(const h2_sparse* sp, int64_t* filled_entries, double* exact_flops) {
+  H2_API_BEGIN
+  if (!sp) fail(H2_EINVAL, "null argument");
+  if (sp->factored) fail(H2_EINVAL, "S of this sparse handle is already factored");
+  double e = 0, fl = 0;
+  analyze_fill(*sp, &e, &fl);
+  if (filled_entries) *filled_entries = int64_t(e);
+  if (exact_flops) *exact_flops = fl;
   H2_API_END
 }
 

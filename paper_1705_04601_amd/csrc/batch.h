@@ -4,12 +4,37 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <new>
+#include <utility>
 #include <vector>
 
 #include "h2_internal.h"
 #include "kernels.h"
 
 namespace h2 {
+
+// Allocator that leaves trivially constructible elements uninitialised on
+// resize (work lists are written in full right after they are sized).
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+template <class T>
+using PodVector = std::vector<T, NoInitAlloc<T>>;
 
 // Work list of one batched GEMM launch.  Built on the host, copied to the
 // device by upload_batches (one allocation for a whole plan), replayed as often
@@ -165,9 +190,18 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
     if (!b.segs.empty()) std::memcpy(&staging[off[3 * i + 1]], b.segs.data(), b.segs.size() * sizeof(GemmSeg));
     if (!b.tiles.empty()) std::memcpy(&staging[off[3 * i + 2]], b.tiles.data(), b.tiles.size() * sizeof(int32_t));
   }
-#pragma omp parallel for schedule(dynamic, 4) if (parallel_pack)
-  for (long i = 0; i < long(extra.size()); ++i)
-    if (extra[i].bytes) std::memcpy(&staging[xoff[i]], extra[i].host, extra[i].bytes);
+  // blobs in pieces of at most 32 MiB, so that one large blob is copied by
+  // many threads
+  constexpr size_t kPiece = size_t(32) << 20;
+  std::vector<std::pair<size_t, size_t>> pieces;  // (blob, first byte)
+  for (size_t i = 0; i < extra.size(); ++i)
+    for (size_t b = 0; b < extra[i].bytes; b += kPiece) pieces.emplace_back(i, b);
+#pragma omp parallel for schedule(dynamic, 1) if (parallel_pack || pieces.size() > 8)
+  for (long j = 0; j < long(pieces.size()); ++j) {
+    const size_t i = pieces[j].first, b = pieces[j].second;
+    const size_t n = std::min(kPiece, extra[i].bytes - b);
+    std::memcpy(&staging[xoff[i] + b], static_cast<const char*>(extra[i].host) + b, n);
+  }
   store.reset(total);
   if (copy) {
     HIPCHECK(hipMemcpyAsync(store.ptr, staging, total, hipMemcpyHostToDevice, copy));

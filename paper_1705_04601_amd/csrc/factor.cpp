@@ -47,7 +47,7 @@ struct FactorLevel {
   std::vector<InvItem<T>> inv;
   std::vector<CopySeg> cps;
   std::vector<SchurItem> sitems;
-  std::vector<SchurSeg> ssegs;
+  PodVector<SchurSeg> ssegs;
   std::vector<int32_t> stiles;
   std::vector<SchurReduce> reds;
   const InvItem<T>* d_inv = nullptr;
@@ -64,7 +64,7 @@ struct FactorLevel {
 // Output of one chunk of rows of a level (concatenated in row order).
 struct RowChunk {
   std::vector<SchurItem> items;
-  std::vector<SchurSeg> segs;
+  PodVector<SchurSeg> segs;
   double flops = 0;
   double dense_pairs = 0;  // sum over rows of (pivots above the row) x (targets of the row)
 };
@@ -146,70 +146,116 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   if (const char* e = std::getenv("H2SP_SCHUR_SPLIT_K")) kMinK = std::max<i64>(1, std::atoll(e));
   const i64 pcap = f.pcap;
   auto split_targets = [&](const std::vector<SchurItem>& items, FactorLevel<T>& L) {
-    std::vector<i64> kitem(items.size());
+    const long ni = long(items.size());
+    const bool par = ni > 16384;
+    auto tiles_of = [&](const SchurItem& it) { return i64((it.M + 63) / 64) * ((it.N + 63) / 64); };
     double work = 0;
-    for (size_t t = 0; t < items.size(); ++t) {
-      const SchurItem& it = items[t];
-      i64 k = 0;
-      for (int32_t r = it.seg_begin; r < it.seg_end; ++r) k += L.ssegs[r].K;
-      kitem[t] = k;
-      work += double(k) * ((it.M + 63) / 64) * ((it.N + 63) / 64);
-      if (trace_enabled()) {
-        const double fl = 2.0 * it.M * it.N * k;
-        shape_fl[(it.M > 64 ? 2 : 0) + (it.N > 64 ? 1 : 0)] += fl;
+#pragma omp parallel for reduction(+ : work) schedule(static) if (par)
+    for (long t = 0; t < ni; ++t) work += double(items[t].ksum) * double(tiles_of(items[t]));
+    if (trace_enabled()) {
+      for (long t = 0; t < ni; ++t) {
+        const SchurItem& it = items[t];
+        const double k = it.ksum;
+        shape_fl[(it.M > 64 ? 2 : 0) + (it.N > 64 ? 1 : 0)] += 2.0 * it.M * it.N * k;
         pad_fl += 2.0 * ((it.M + 15) / 16 * 16) * ((it.N + 15) / 16 * 16) * k;
         for (int32_t r = it.seg_begin; r < it.seg_end; ++r) kpad += (L.ssegs[r].K + 15) / 16 * 16;
         ksum += k;
       }
     }
     i64 kt = std::max<i64>(kMinK, i64(work / kUnits) + 1);
-    auto parts_of = [&](size_t t) -> i64 { return kitem[t] * 2 > 3 * kt ? (kitem[t] + kt - 1) / kt : 1; };
+    auto parts_of = [&](long t) -> i64 {
+      const i64 k = items[t].ksum;
+      return k * 2 > 3 * kt ? (k + kt - 1) / kt : 1;
+    };
     while (true) {
       i64 need = 0;
-      for (size_t t = 0; t < items.size(); ++t) need += (parts_of(t) - 1) * i64(items[t].M) * items[t].N;
+#pragma omp parallel for reduction(+ : need) schedule(static) if (par)
+      for (long t = 0; t < ni; ++t) need += (parts_of(t) - 1) * i64(items[t].M) * items[t].N;
       if (need <= pcap) break;
       kt *= 2;
     }
-    L.sitems.clear();
-    L.stiles.clear();
-    L.reds.clear();
-    i64 pbase = 0;
-    auto emit = [&](const SchurItem& si) {
-      const uint32_t item = uint32_t(L.sitems.size());
-      for (int a = 0; a < (si.M + edge - 1) / edge; ++a)
-        for (int b = 0; b < (si.N + edge - 1) / edge; ++b) L.stiles.push_back(int32_t((item << 8) | (a << 4) | b));
-      L.sitems.push_back(si);
+    // emission in contiguous ranges of items (in parallel), then merged in
+    // range order with item indices and partial offsets shifted
+    struct Out {
+      std::vector<SchurItem> items;
+      std::vector<int32_t> tiles;
+      std::vector<SchurReduce> reds;
+      i64 pbase = 0, nsplit = 0;
     };
-    for (size_t t = 0; t < items.size(); ++t) {
-      const SchurItem& it = items[t];
-      const i64 np = parts_of(t);
-      if (np == 1) {
-        emit(it);
-        continue;
-      }
-      const i64 len = i64(it.M) * it.N;
-      int32_t begin = it.seg_begin;
-      i64 acc = 0, part = 0;
-      for (int32_t r = it.seg_begin; r < it.seg_end; ++r) {
-        acc += L.ssegs[r].K;
-        const bool last = r + 1 == it.seg_end;
-        if (last || (part < np - 1 && acc * np >= (part + 1) * kitem[t])) {
-          SchurItem si = it;
-          si.seg_begin = begin;
-          si.seg_end = r + 1;
-          if (part > 0) {
-            si.partial = 1;
-            si.out_off = pbase + (part - 1) * len;
+    const int nparts = par ? 4 * nthr : 1;
+    std::vector<Out> outs(nparts);
+#pragma omp parallel for schedule(dynamic, 1) if (par)
+    for (int p = 0; p < nparts; ++p) {
+      Out& o = outs[p];
+      auto emit = [&](const SchurItem& si) {
+        const uint32_t item = uint32_t(o.items.size());
+        for (int a = 0; a < (si.M + edge - 1) / edge; ++a)
+          for (int b = 0; b < (si.N + edge - 1) / edge; ++b) o.tiles.push_back(int32_t((item << 8) | (a << 4) | b));
+        o.items.push_back(si);
+      };
+      for (long t = ni * p / nparts; t < ni * (p + 1) / nparts; ++t) {
+        const SchurItem& it = items[t];
+        const i64 np = parts_of(t);
+        if (np == 1) {
+          emit(it);
+          continue;
+        }
+        const i64 len = i64(it.M) * it.N;
+        int32_t begin = it.seg_begin;
+        i64 acc = 0, part = 0;
+        for (int32_t r = it.seg_begin; r < it.seg_end; ++r) {
+          acc += L.ssegs[r].K;
+          const bool last = r + 1 == it.seg_end;
+          if (last || (part < np - 1 && acc * np >= (part + 1) * i64(it.ksum))) {
+            SchurItem si = it;
+            si.seg_begin = begin;
+            si.seg_end = r + 1;
+            if (part > 0) {
+              si.partial = 1;
+              si.out_off = o.pbase + (part - 1) * len;  // shifted by the range's base below
+            }
+            emit(si);
+            begin = r + 1;
+            ++part;
           }
-          emit(si);
-          begin = r + 1;
-          ++part;
+        }
+        if (part > 1) {
+          o.reds.push_back({it.out_off, o.pbase, int32_t(len), int32_t(part - 1)});
+          o.pbase += (part - 1) * len;
+          ++o.nsplit;
         }
       }
-      if (part > 1) {
-        L.reds.push_back({it.out_off, pbase, int32_t(len), int32_t(part - 1)});
-        pbase += (part - 1) * len;
-        ++nsplit;
+    }
+    std::vector<size_t> io(nparts + 1, 0), to(nparts + 1, 0), ro(nparts + 1, 0);
+    std::vector<i64> po(nparts + 1, 0);
+    for (int p = 0; p < nparts; ++p) {
+      io[p + 1] = io[p] + outs[p].items.size();
+      to[p + 1] = to[p] + outs[p].tiles.size();
+      ro[p + 1] = ro[p] + outs[p].reds.size();
+      po[p + 1] = po[p] + outs[p].pbase;
+      nsplit += outs[p].nsplit;
+    }
+    if (io[nparts] >= (size_t(1) << 24)) {
+      too_wide = 1;
+      return;
+    }
+    L.sitems.resize(io[nparts]);
+    L.stiles.resize(to[nparts]);
+    L.reds.resize(ro[nparts]);
+#pragma omp parallel for schedule(dynamic, 1) if (par)
+    for (int p = 0; p < nparts; ++p) {
+      const Out& o = outs[p];
+      for (size_t i = 0; i < o.items.size(); ++i) {
+        SchurItem si = o.items[i];
+        if (si.partial) si.out_off += po[p];
+        L.sitems[io[p] + i] = si;
+      }
+      for (size_t i = 0; i < o.tiles.size(); ++i)
+        L.stiles[to[p] + i] = int32_t(uint32_t(o.tiles[i]) + (uint32_t(io[p]) << 8));
+      for (size_t i = 0; i < o.reds.size(); ++i) {
+        SchurReduce r = o.reds[i];
+        r.p_off += po[p];
+        L.reds[ro[p] + i] = r;
       }
     }
   };
@@ -291,7 +337,10 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
             const i64 mj = mb[sp.colidx[t0 + t]];
             SchurItem si{sp.blk_off[t0 + t], int32_t(mi), int32_t(mj), int32_t(sbase + cnt[t]),
                          int32_t(sbase + cnt[t + 1]), 0, 0};
-            for (int32_t r = si.seg_begin; r < si.seg_end; ++r) out.flops += 2.0 * mi * mj * out.segs[r].K;
+            i64 k = 0;
+            for (int32_t r = si.seg_begin; r < si.seg_end; ++r) k += out.segs[r].K;
+            si.ksum = int32_t(k);
+            out.flops += 2.0 * mi * mj * double(k);
             out.items.push_back(si);
           }
         }
@@ -311,19 +360,26 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       too_wide = 1;
       return;
     }
-    std::vector<SchurItem> items;
-    items.reserve(nitems);
-    L.ssegs.reserve(nsegs);
-    for (RowChunk& c : chunks) {
-      const int32_t sb = int32_t(L.ssegs.size());
-      for (SchurItem si : c.items) {
+    std::vector<size_t> io(nchunk + 1, 0), so(nchunk + 1, 0);
+    for (int ch = 0; ch < nchunk; ++ch) {
+      io[ch + 1] = io[ch] + chunks[ch].items.size();
+      so[ch + 1] = so[ch] + chunks[ch].segs.size();
+    }
+    std::vector<SchurItem> items(nitems);
+    L.ssegs.resize(nsegs);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+    for (int ch = 0; ch < nchunk; ++ch) {
+      RowChunk& c = chunks[ch];
+      const int32_t sb = int32_t(so[ch]);
+      for (size_t i = 0; i < c.items.size(); ++i) {
+        SchurItem si = c.items[i];
         si.seg_begin += sb;
         si.seg_end += sb;
-        items.push_back(si);
+        items[io[ch] + i] = si;
       }
-      L.ssegs.insert(L.ssegs.end(), c.segs.begin(), c.segs.end());
+      if (!c.segs.empty()) std::memcpy(&L.ssegs[so[ch]], c.segs.data(), c.segs.size() * sizeof(SchurSeg));
       std::vector<SchurItem>().swap(c.items);
-      std::vector<SchurSeg>().swap(c.segs);
+      PodVector<SchurSeg>().swap(c.segs);
     }
     split_targets(items, L);
     if (L.sitems.size() >= (size_t(1) << 24)) too_wide = 1;
@@ -415,7 +471,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
         mark_ev();
         std::vector<SchurItem>().swap(L.sitems);
-        std::vector<SchurSeg>().swap(L.ssegs);
+        PodVector<SchurSeg>().swap(L.ssegs);
         std::vector<int32_t>().swap(L.stiles);
         std::vector<SchurReduce>().swap(L.reds);
       }
@@ -478,11 +534,16 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
 // tree, the parent of a row being its first off-diagonal block), and re-lays
 // S with the new blocks zero.  Block ILU(0) on the filled pattern is then the
 // exact block factorisation.
-template <class T>
-static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
-  TraceTimer tt("fill");
+// Row structures (positions after the row) of the block factor of S's
+// pattern in elimination order.  Stops with ENOMEM once the entries counted
+// exceed `budget` (when budget > 0).  entries / flops: stored entries of the
+// filled upper triangle and 2 m_i m_j m_k summed over the Schur updates of
+// the exact factorisation (i <= j both after pivot k in its row).
+static std::vector<std::vector<i64>> symbolic_fill(const h2_sparse& sp, double budget, double elem_bytes,
+                                                   double* entries, double* flops) {
   const i64 ncl = sp.ncl;
   const auto& mb = sp.nonbasis;
+  double counted = 0, fl = 0;
   std::vector<std::vector<i64>> R(ncl), kids(ncl);
   std::vector<i64> mark(ncl, -1);
   for (i64 pos = 0; pos < ncl; ++pos) {
@@ -508,7 +569,36 @@ static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
     std::vector<i64>().swap(kids[pos]);
     std::sort(r.begin(), r.end());
     if (!r.empty()) kids[r[0]].push_back(pos);
+    const double mk = double(mb[sp.eorder[pos]]);
+    double sum = 0, sq = 0;
+    for (i64 j : r) {
+      const double mj = double(mb[sp.eorder[j]]);
+      sum += mj;
+      sq += mj * mj;
+    }
+    counted += mk * mk + mk * sum;
+    fl += mk * (sum * sum + sq);  // 2 m_i m_j m_k over i < j, plus 2 m_i^2 m_k over i = j
+    if (budget > 0 && counted > budget)
+      fail(H2_ENOMEM, "exact factorisation: the filled S needs more than " +
+                          std::to_string(counted * elem_bytes / 1e9) + " GB of device memory (" +
+                          std::to_string(budget * elem_bytes / 1e9) + " GB usable)");
   }
+  if (entries) *entries = counted;
+  if (flops) *flops = fl;
+  return R;
+}
+
+template <class T>
+static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
+  TraceTimer tt("fill");
+  const i64 ncl = sp.ncl;
+  const auto& mb = sp.nonbasis;
+  // device budget for the filled S: the symbolic pass stops as soon as the
+  // entries counted so far exceed it (3D fill grows much faster than S)
+  size_t free_b = 0, total_b = 0;
+  HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+  const double budget = std::max(1.0, 0.9 * double(free_b) / double(sizeof(T)) - double(kOverread));
+  std::vector<std::vector<i64>> R = symbolic_fill(sp, budget, double(sizeof(T)), nullptr, nullptr);
   std::vector<i64> rowptr(ncl + 1, 0), colidx, blk_off;
   i64 ent = 0;
   for (i64 pos = 0; pos < ncl; ++pos) {
@@ -529,12 +619,6 @@ static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
   }
   tt.lap("symbolic");
   const size_t el = sizeof(T);
-  size_t free_b = 0, total_b = 0;
-  HIPCHECK(hipMemGetInfo(&free_b, &total_b));
-  const double need = double(el) * double(ent + kOverread);
-  if (need > 0.9 * double(free_b))
-    fail(H2_ENOMEM, "exact factorisation: the filled S needs " + std::to_string(need / 1e9) + " GB, " +
-                        std::to_string(double(free_b) / 1e9) + " GB of device memory free");
   // old blocks -> their places in the filled layout
   std::vector<CopySeg> cps;
   cps.reserve(sp.colidx.size());
@@ -562,6 +646,10 @@ static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
   sp.blk_off.swap(blk_off);
   sp.s_entries = ent;
   tt.lap("relayout");
+}
+
+void analyze_fill(const h2_sparse& sp, double* entries, double* flops) {
+  (void)symbolic_fill(sp, 0.0, double(sp.elem), entries, flops);
 }
 
 h2_factor* factor(h2_sparse* sp, bool exact, hipStream_t st, double* phase_ms) {

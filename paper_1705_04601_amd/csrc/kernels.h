@@ -70,7 +70,7 @@ constexpr int64_t kOverread = 64;
 struct SchurItem {
   int64_t out_off;   // into S (partial == 0) or the partial buffer (partial == 1)
   int32_t M, N, seg_begin, seg_end;
-  int32_t partial, pad;
+  int32_t partial, ksum;  // ksum: K summed over the item's segments (planning)
 };
 struct SchurSeg {
   int64_t b_off;     // S_kj in S (K x N, ld K)

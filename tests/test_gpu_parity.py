@@ -216,7 +216,10 @@ def test_exact_factor_fill_and_inverse(name):
     note(f"exact factor fp64 {name}")
     h = imported(name)
     sph = P.h2_sparsify(h, P.H2_FP64)
+    entries, flops = P.h2_factor_analyze(sph)
     f = P.h2_factor_S(sph, P.H2_FACTOR_EXACT)
+    work = P.h2_last_work()
+    assert work[9] == entries and abs(work[5] - flops) <= 1e-9 * max(flops, 1.0)
     plan = P.h2_sparse_export_plan(sph)
     order = oracle.elimination_order(sp)
     pos = {c: i for i, c in enumerate(order)}
