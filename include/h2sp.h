@@ -167,6 +167,16 @@ int h2_sparse_info(const h2_sparse* sp, int64_t* nnz_blocks, int64_t* nnz_entrie
 int h2_sparse_export_plan(const h2_sparse* sp, int64_t* n_act, int64_t* kept,
                           int64_t* nonbasis, int64_t* soff, int64_t* elim,
                           int64_t* rowptr, int64_t* colidx);
+/*
+ * h2_sparsify_batch: sparsifies `count` independent H^2 matrices (uneven
+ * sizes, ranks and depths allowed; one precision for all) in one level sweep:
+ * level k of every instance (from the leaves up) runs in the same QR,
+ * transform and strip launches, their work lists concatenated.  outs[i]
+ * receives the handle of hs[i], as h2_sparsify would return it; on error no
+ * handle is returned.  h2_last_timings / h2_last_work report the whole batch.
+ */
+int h2_sparsify_batch(h2_matrix* const* hs, int count, const h2_sparsify_opts* opts, h2_sparse** outs);
+
 /* HOST copy of block (t, s) of S (m_t x m_s column-major, FP64) for any (t, s)
  * in the pattern (either orientation); EINVAL when (t, s) is not in it. */
 int h2_sparse_export_block(const h2_sparse* sp, int64_t t, int64_t s, double* out);
@@ -203,6 +213,19 @@ int h2_factor_analyze(const h2_sparse* sp, int64_t* filled_entries, double* exac
  */
 int h2_solve(h2_factor* f, const double* b, double* x, int64_t nrhs, int64_t ld,
              const h2_solve_opts* opts, h2_solve_info* info);
+
+/*
+ * Batched factorisation and solve of independent instances: each instance as
+ * h2_factor_S / h2_solve, run concurrently on a pool of streams that start
+ * after the work queued on the current stream and that the current stream
+ * waits for on return.  b[i], x[i]: device pointers of instance i (its own
+ * nrhs[i], ld[i]); infos may be NULL.  A handle may appear once per batch.
+ * Any instance failing fails the call (first error reported); ENOCONV after
+ * every instance ran if one of them stopped above the tolerance.
+ */
+int h2_factor_S_batch(h2_sparse* const* sps, int count, const h2_factor_opts* opts, h2_factor** outs);
+int h2_solve_batch(h2_factor* const* fs, int count, const double* const* b, double* const* x,
+                   const int64_t* nrhs, const int64_t* ld, const h2_solve_opts* opts, h2_solve_info* infos);
 
 /* One application of the preconditioner: x = V (L D L^T)^{-1} U^T b (device). */
 int h2_apply_inverse(h2_factor* f, const double* b, double* x, int64_t nrhs, int64_t ld);

@@ -84,6 +84,12 @@ _SIGS = {
     "h2_sparse_export_q": (ctypes.c_int, [_P, _I64, _DP]),
     "h2_factor_S": (ctypes.c_int, [_P, ctypes.POINTER(h2_factor_opts), ctypes.POINTER(_P)]),
     "h2_factor_analyze": (ctypes.c_int, [_P, _I64P, _DP]),
+    "h2_sparsify_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(h2_sparsify_opts),
+                                         ctypes.POINTER(_P)]),
+    "h2_factor_S_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(h2_factor_opts),
+                                         ctypes.POINTER(_P)]),
+    "h2_solve_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                      _I64P, _I64P, ctypes.POINTER(h2_solve_opts), ctypes.POINTER(h2_solve_info)]),
     "h2_solve": (ctypes.c_int, [_P, _P, _P, _I64, _I64, ctypes.POINTER(h2_solve_opts),
                                 ctypes.POINTER(h2_solve_info)]),
     "h2_apply_inverse": (ctypes.c_int, [_P, _P, _P, _I64, _I64]),
@@ -272,6 +278,51 @@ def h2_factor_S(sp: H2SparseHandle, mode: int = H2_FACTOR_ILU0) -> H2FactorHandl
     o = h2_factor_opts(int(mode))
     _check(lib().h2_factor_S(sp.ptr, ctypes.byref(o), ctypes.byref(out)))
     return H2FactorHandle(out.value, keep=sp)
+
+
+def _handles(hs):
+    arr = (_P * len(hs))(*[h.ptr for h in hs])
+    return arr
+
+
+def h2_sparsify_batch(hs, precision: int = H2_FP64):
+    """Sparsifies several H^2 matrices in one level sweep; a handle per matrix."""
+    _use_torch_stream()
+    outs = (_P * len(hs))()
+    o = h2_sparsify_opts(int(precision))
+    _check(lib().h2_sparsify_batch(_handles(hs), len(hs), ctypes.byref(o), outs))
+    return [H2SparseHandle(outs[i], keep=h) for i, h in enumerate(hs)]
+
+
+def h2_factor_S_batch(sps, mode: int = H2_FACTOR_ILU0):
+    _use_torch_stream()
+    outs = (_P * len(sps))()
+    o = h2_factor_opts(int(mode))
+    _check(lib().h2_factor_S_batch(_handles(sps), len(sps), ctypes.byref(o), outs))
+    return [H2FactorHandle(outs[i], keep=sp) for i, sp in enumerate(sps)]
+
+
+def h2_solve_batch(fs, bs, xs, tol: float = 1e-10, max_iter: int = 30, check: bool = True):
+    """Solves every instance (b[i], x[i]: float64 CUDA tensors, column-major)."""
+    _use_torch_stream()
+    cnt = len(fs)
+    shapes = [_colmajor(b) for b in bs]
+    for x in xs:
+        _colmajor(x)
+    barr = (_P * cnt)(*[b.data_ptr() for b in bs])
+    xarr = (_P * cnt)(*[x.data_ptr() for x in xs])
+    nrhs = np.array([sh[1] for sh in shapes], dtype=np.int64)
+    ld = np.array([sh[2] for sh in shapes], dtype=np.int64)
+    o = h2_solve_opts(float(tol), int(max_iter))
+    infos = (h2_solve_info * cnt)()
+    code = lib().h2_solve_batch(_handles(fs), cnt, barr, xarr, nrhs.ctypes.data_as(_I64P),
+                                ld.ctypes.data_as(_I64P), ctypes.byref(o), infos)
+    if check:
+        _check(code)
+    elif code not in (H2_OK, H2_ENOCONV):
+        _check(code)
+    return [dict(iters=i.iters, residual=i.max_rel_residual, code=code, t_precond=i.seconds[0],
+                 t_matvec=i.seconds[1], t_plan=i.seconds[2]) for i in infos]
 
 
 def h2_factor_analyze(sp: H2SparseHandle):

@@ -1,11 +1,17 @@
 // C ABI of libh2sp: sparsification, factorisation and solve entry points.
+#include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <functional>
 #include <memory>
+#include <mutex>
+#include <thread>
+
+#include <omp.h>
 
 #include "factor.h"
 
 namespace h2 {
-h2_sparse* plan_sparsify(h2_matrix* H, int precision);
 h2_factor* factor(h2_sparse* sp, bool exact, hipStream_t st, double* phase_ms);
 void analyze_fill(const h2_sparse& sp, double* entries, double* flops);
 void set_stream(hipStream_t s);
@@ -49,34 +55,86 @@ extern "C" int h2_set_stream(void* stream) {
   return H2_OK;
 }
 
+// After the sweep: only Q_t (for U and V) and S outlive it; the plan's work
+// counts go to h2_last_work (summed over a batch).
+static void finish_sparsify(h2_sparse& sp) {
+  for (int side = 0; side < 2; ++side) {
+    sp.dC[side].reset(0);
+    sp.dG[side].reset(0);
+  }
+  sp.dTmp.reset(0);
+  sp.dB.reset(0);
+  sp.dW.reset(0);
+  sp.dWt.reset(0);
+  sp.dRhat.reset(0);
+  sp.dDesc.reset(0);
+  sp.levels.clear();
+  const PlanCounts& pc = sp.counts;
+  g_work[0] += pc.flops_qr + pc.flops_misc;
+  g_work[1] += pc.flops_close;
+  g_work[2] += pc.flops_coup;
+  g_work[3] += pc.flops_strip;
+  g_work[6] += pc.bytes_qr;
+}
+
+// Runs job(i) for i < count on a pool of host threads, each with a stream of
+// its own (so that the instances' device work overlaps), then makes the
+// caller's stream wait for all of them.  The first error is rethrown.
+static void run_pooled(int count, const std::function<void(int)>& job) {
+  const hipStream_t caller = current_stream();
+  const int nthr = std::max(1, std::min(count, 8));
+  const int omp_share = std::max(1, omp_get_max_threads() / nthr);
+  std::vector<hipStream_t> streams(nthr, nullptr);
+  hipEvent_t ready;
+  HIPCHECK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  HIPCHECK(hipEventRecord(ready, caller));
+  for (auto& st : streams) {
+    HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    HIPCHECK(hipStreamWaitEvent(st, ready, 0));  // inputs written on the caller's stream
+  }
+  std::atomic<int> next{0};
+  std::mutex mu;
+  int code = 0;
+  std::string msg;
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthr; ++t)
+    pool.emplace_back([&, t] {
+      set_stream(streams[t]);
+      omp_set_num_threads(omp_share);
+      for (int i = next++; i < count; i = next++) {
+        try {
+          job(i);
+        } catch (const Error& e) {
+          std::lock_guard<std::mutex> lk(mu);
+          if (!code) code = e.code, msg = e.msg;
+        } catch (const std::bad_alloc&) {
+          std::lock_guard<std::mutex> lk(mu);
+          if (!code) code = H2_ENOMEM, msg = "host allocation failed";
+        } catch (const std::exception& e) {
+          std::lock_guard<std::mutex> lk(mu);
+          if (!code) code = H2_EINVAL, msg = e.what();
+        }
+      }
+      (void)hipStreamSynchronize(streams[t]);
+    });
+  for (auto& th : pool) th.join();
+  for (auto& st : streams) (void)hipStreamDestroy(st);
+  (void)hipEventDestroy(ready);
+  if (code) fail(code, msg);
+}
+
 extern "C" int h2_sparsify(h2_matrix* h, const h2_sparsify_opts* opts, h2_sparse** out) {
   H2_API_BEGIN
   if (!h || !out) fail(H2_EINVAL, "null argument");
   *out = nullptr;
   const int prec = opts ? opts->precision : H2_FP64;
   if (prec != H2_FP64 && prec != H2_MIXED) fail(H2_EINVAL, "unknown precision");
-  std::unique_ptr<h2_sparse> sp(plan_sparsify(h, prec));
+  std::unique_ptr<h2_sparse> sp(plan_sparsify(h, prec, true));
   std::fill(g_timings, g_timings + 8, 0.0);
+  std::fill(g_work, g_work + 16, 0.0);
   run_sparsify(*sp, current_stream(), g_timings);
   HIPCHECK(hipStreamSynchronize(current_stream()));
-  // only Q_t (for U and V) and S outlive the sweep
-  for (int side = 0; side < 2; ++side) {
-    sp->dC[side].reset(0);
-    sp->dG[side].reset(0);
-  }
-  sp->dTmp.reset(0);
-  sp->dB.reset(0);
-  sp->dW.reset(0);
-  sp->dWt.reset(0);
-  sp->dRhat.reset(0);
-  sp->dDesc.reset(0);
-  sp->levels.clear();
-  const PlanCounts& pc = sp->counts;
-  g_work[0] = pc.flops_qr + pc.flops_misc;
-  g_work[1] = pc.flops_close;
-  g_work[2] = pc.flops_coup;
-  g_work[3] = pc.flops_strip;
-  g_work[6] = pc.bytes_qr;
+  finish_sparsify(*sp);
   HIPCHECK(hipStreamSynchronize(current_stream()));
   *out = sp.release();
   H2_API_END
@@ -171,6 +229,84 @@ extern "C" int h2_factor_analyze(const h2_sparse* sp, int64_t* filled_entries, d
   analyze_fill(*sp, &e, &fl);
   if (filled_entries) *filled_entries = int64_t(e);
   if (exact_flops) *exact_flops = fl;
+  H2_API_END
+}
+
+extern "C" int h2_sparsify_batch(h2_matrix* const* hs, int count, const h2_sparsify_opts* opts, h2_sparse** outs) {
+  H2_API_BEGIN
+  if (!hs || !outs || count < 1) fail(H2_EINVAL, "null argument or empty batch");
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i]) fail(H2_EINVAL, "null matrix in the batch");
+    outs[i] = nullptr;
+  }
+  const int prec = opts ? opts->precision : H2_FP64;
+  if (prec != H2_FP64 && prec != H2_MIXED) fail(H2_EINVAL, "unknown precision");
+  std::vector<std::unique_ptr<h2_sparse>> own(count);
+  std::vector<h2_sparse*> sps(count);
+  for (int i = 0; i < count; ++i) {
+    own[i].reset(plan_sparsify(hs[i], prec, false));
+    sps[i] = own[i].get();
+  }
+  std::fill(g_timings, g_timings + 8, 0.0);
+  std::fill(g_work, g_work + 16, 0.0);
+  run_sparsify_batch(sps, current_stream(), g_timings);
+  HIPCHECK(hipStreamSynchronize(current_stream()));
+  for (int i = 0; i < count; ++i) {
+    finish_sparsify(*own[i]);
+    outs[i] = own[i].release();
+  }
+  H2_API_END
+}
+
+extern "C" int h2_factor_S_batch(h2_sparse* const* sps, int count, const h2_factor_opts* opts, h2_factor** outs) {
+  H2_API_BEGIN
+  if (!sps || !outs || count < 1) fail(H2_EINVAL, "null argument or empty batch");
+  const int mode = opts ? opts->mode : H2_FACTOR_ILU0;
+  if (mode != H2_FACTOR_EXACT && mode != H2_FACTOR_ILU0) fail(H2_EINVAL, "unknown factorisation mode");
+  for (int i = 0; i < count; ++i) {
+    if (!sps[i]) fail(H2_EINVAL, "null sparse handle in the batch");
+    if (sps[i]->factored) fail(H2_EINVAL, "S of a sparse handle in the batch is already factored");
+    for (int j = 0; j < i; ++j)
+      if (sps[j] == sps[i]) fail(H2_EINVAL, "the same sparse handle twice in the batch");
+    outs[i] = nullptr;
+  }
+  std::vector<std::unique_ptr<h2_factor>> fs(count);
+  std::vector<double> ph(size_t(count) * 8, 0.0);
+  run_pooled(count, [&](int i) {
+    fs[i].reset(factor(sps[i], mode == H2_FACTOR_EXACT, current_stream(), &ph[size_t(i) * 8]));
+  });
+  std::fill(g_timings + 4, g_timings + 8, 0.0);
+  std::fill(g_work + 4, g_work + 16, 0.0);
+  for (int i = 0; i < count; ++i) {
+    g_timings[4] += ph[size_t(i) * 8 + 4];
+    g_timings[5] += ph[size_t(i) * 8 + 5];
+    g_work[4] += fs[i]->flops_inv + fs[i]->flops_z;
+    g_work[5] += fs[i]->flops_schur;
+    g_work[7] += double(fs[i]->split_targets);
+    g_work[8] += double(fs[i]->schur_launches);
+    g_work[9] += double(sps[i]->s_entries);
+  }
+  for (int i = 0; i < count; ++i) outs[i] = fs[i].release();
+  H2_API_END
+}
+
+extern "C" int h2_solve_batch(h2_factor* const* fs, int count, const double* const* b, double* const* x,
+                              const int64_t* nrhs, const int64_t* ld, const h2_solve_opts* opts,
+                              h2_solve_info* infos) {
+  H2_API_BEGIN
+  if (!fs || !b || !x || !nrhs || !ld || count < 1) fail(H2_EINVAL, "null argument or empty batch");
+  for (int i = 0; i < count; ++i) {
+    if (!fs[i] || !b[i] || !x[i]) fail(H2_EINVAL, "null factor or vector in the batch");
+    if (nrhs[i] < 1 || nrhs[i] > 512 || ld[i] < fs[i]->sp->H->tree.n) fail(H2_EINVAL, "bad nrhs / ld in the batch");
+    for (int j = 0; j < i; ++j)
+      if (fs[j] == fs[i]) fail(H2_EINVAL, "the same factor twice in the batch");
+  }
+  std::vector<int> rc(count, H2_OK);
+  run_pooled(count, [&](int i) {
+    rc[i] = solve_impl(fs[i], b[i], x[i], nrhs[i], ld[i], opts, infos ? &infos[i] : nullptr);
+  });
+  for (int i = 0; i < count; ++i)
+    if (rc[i] == H2_ENOCONV) fail(H2_ENOCONV, "refinement stopped above the tolerance (instance " + std::to_string(i) + ")");
   H2_API_END
 }
 

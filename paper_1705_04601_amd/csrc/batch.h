@@ -130,8 +130,34 @@ struct GemmBatch {
     std::vector<GemmSeg>().swap(segs);
     std::vector<int32_t>().swap(tiles);
   }
+  // Parameters of generated operands (kernel c / |x - y|) for every item.
+  void set_generator(int dim, double scale, double diag) {
+    for (GemmItem& it : items) {
+      it.gdim = dim;
+      it.gscale = scale;
+      it.gdiag = diag;
+    }
+  }
+  // Appends another batch's items and segments (same mode and role).
+  void append(GemmBatch& o) {
+    if (o.items.empty()) return;
+    if (items.empty()) {
+      mode = o.mode;
+      role = o.role;
+    }
+    if (mode != o.mode || role != o.role) fail(H2_EINVAL, "internal: merging GEMM batches of another kind");
+    const int32_t off = int32_t(segs.size());
+    for (GemmItem it : o.items) {
+      it.seg_begin += off;
+      it.seg_end += off;
+      items.push_back(it);
+    }
+    segs.insert(segs.end(), o.segs.begin(), o.segs.end());
+    flops += o.flops;
+    o.drop_host();
+  }
   template <class T>
-  void launch(hipStream_t st, int dim, double scale, double diag) const {
+  void launch(hipStream_t st) const {
     if (ntiles <= 0) return;
     GemmLaunch g{};
     g.kc = kc ? 1 : 0;
@@ -141,9 +167,6 @@ struct GemmBatch {
     g.ntiles = ntiles;
     g.mode = mode;
     g.role = role;
-    g.dim = dim;
-    g.scale = scale;
-    g.diag = diag;
     launch_gemm<T>(g, st);
   }
 };

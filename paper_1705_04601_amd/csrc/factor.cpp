@@ -79,7 +79,6 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   const auto& mb = sp.nonbasis;
   T* S = sp.dS.as<T>();
   T* Inv = f.dInv.as<T>();
-  const int dim = sp.H->tree.dim;
   auto cl = [&](i64 pos) { return sp.eorder[pos]; };
   std::vector<std::vector<i64>> by_level(f.nflev);
   for (i64 pos : f.rows) by_level[f.flev[pos]].push_back(pos);
@@ -150,7 +149,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     const bool par = ni > 16384;
     auto tiles_of = [&](const SchurItem& it) { return i64((it.M + 63) / 64) * ((it.N + 63) / 64); };
     double work = 0;
-#pragma omp parallel for reduction(+ : work) schedule(static) if (par)
+#pragma omp parallel for reduction(+ : work) schedule(static) num_threads(nthr) if (par)
     for (long t = 0; t < ni; ++t) work += double(items[t].ksum) * double(tiles_of(items[t]));
     if (trace_enabled()) {
       for (long t = 0; t < ni; ++t) {
@@ -169,7 +168,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     };
     while (true) {
       i64 need = 0;
-#pragma omp parallel for reduction(+ : need) schedule(static) if (par)
+#pragma omp parallel for reduction(+ : need) schedule(static) num_threads(nthr) if (par)
       for (long t = 0; t < ni; ++t) need += (parts_of(t) - 1) * i64(items[t].M) * items[t].N;
       if (need <= pcap) break;
       kt *= 2;
@@ -184,7 +183,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     };
     const int nparts = par ? 4 * nthr : 1;
     std::vector<Out> outs(nparts);
-#pragma omp parallel for schedule(dynamic, 1) if (par)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr) if (par)
     for (int p = 0; p < nparts; ++p) {
       Out& o = outs[p];
       auto emit = [&](const SchurItem& si) {
@@ -242,7 +241,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     L.sitems.resize(io[nparts]);
     L.stiles.resize(to[nparts]);
     L.reds.resize(ro[nparts]);
-#pragma omp parallel for schedule(dynamic, 1) if (par)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthr) if (par)
     for (int p = 0; p < nparts; ++p) {
       const Out& o = outs[p];
       for (size_t i = 0; i < o.items.size(); ++i) {
@@ -460,7 +459,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
           if constexpr (std::is_same<T, float>::value) launch_fill_f(Z, L.zlen, 0.0f, st);
           else launch_fill(Z, L.zlen, 0.0, st);
         }
-        L.zb.template launch<T>(st, dim, 0.0, 0.0);
+        L.zb.template launch<T>(st);
         mark_ev();
         L.nschur_tiles = int32_t(L.stiles.size());
         SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf, S + sp.s_entries};

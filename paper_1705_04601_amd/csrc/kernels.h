@@ -13,7 +13,9 @@ namespace h2 {
 // opB = 0: B column-major K x N; opB = 1: B stored N x K.
 // gen = 1: A is generated, A(i, k) = scale / |pr_i - pc_k| with pr = (const
 // double*) A and pc the column points (dim-strided); diag = 1 puts the
-// diagonal value where i == k (a cluster against itself).
+// diagonal value where i == k (a cluster against itself).  scale, the
+// diagonal value and dim belong to the item (so that items of different
+// matrices can share a launch).
 struct GemmSeg {
   const void* A;
   const void* B;
@@ -33,6 +35,8 @@ struct GemmItem {
   void* out[5];
   int32_t ld[5];
   uint8_t trans[5];
+  int32_t gdim;            // generated operands: point dimension
+  double gscale, gdiag;    // generated operands: kernel scale, diagonal value
 };
 
 enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1, GEMM_SUB = 2 };
@@ -48,8 +52,6 @@ struct GemmLaunch {
   int32_t ntiles;
   int mode;
   int role;
-  int dim;
-  double scale, diag;
 };
 
 template <class T>

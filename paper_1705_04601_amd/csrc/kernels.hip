@@ -76,7 +76,7 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmLaunch g) {
   V acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
-  const int dim = g.dim;
+  const int dim = it.gdim;
   for (int si = it.seg_begin; si < it.seg_end; ++si) {
     const GemmSeg sg = g.segs[si];
     for (int k0 = 0; k0 < sg.K; k0 += KC) {
@@ -90,14 +90,14 @@ __global__ __launch_bounds__(64) void gemm_kernel(GemmLaunch g) {
           T v = T(0);
           if (gi < it.M && gk < sg.K) {
             if (sg.diag && gi == gk) {
-              v = T(g.diag);
+              v = T(it.gdiag);
             } else {
               double d2 = 0.0;
               for (int a = 0; a < dim; ++a) {
                 const double d = pr[gi * dim + a] - sg.pc[gk * dim + a];
                 d2 += d * d;
               }
-              v = T(g.scale / sqrt(d2));
+              v = T(it.gscale / sqrt(d2));
             }
           }
           As[k][i] = v;
@@ -303,17 +303,17 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
     const int am = sg.gen ? 2 : (sg.opA ? 0 : 1);
     const int bmode = sg.opB ? 1 : 0;
     if (am == 0 && bmode == 0)
-      direct_segment<T, 0, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+      direct_segment<T, 0, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
     else if (am == 1 && bmode == 0)
-      direct_segment<T, 1, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+      direct_segment<T, 1, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
     else if (am == 2 && bmode == 0)
-      direct_segment<T, 2, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+      direct_segment<T, 2, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
     else if (am == 0)
-      direct_segment<T, 0, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+      direct_segment<T, 0, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
     else if (am == 1)
-      direct_segment<T, 1, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+      direct_segment<T, 1, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
     else
-      direct_segment<T, 2, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, g.dim, g.scale, g.diag);
+      direct_segment<T, 2, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
   }
 #pragma unroll
   for (int bm = 0; bm < 4; ++bm)

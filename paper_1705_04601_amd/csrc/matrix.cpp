@@ -187,22 +187,23 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
   std::vector<GemmBatch*> all{&p.close, &p.xproj, &p.coup, &p.yproj, &p.leafout};
   for (auto& g : p.up) all.push_back(&g);
   for (auto& g : p.down) all.push_back(&g);
-  for (GemmBatch* g : all) g->role = ROLE_MATVEC;
+  for (GemmBatch* g : all) {
+    g->role = ROLE_MATVEC;
+    g->set_generator(dim, H.scale, H.diag);
+  }
   upload_batches(all, p.desc);
   return mp;
 }
 
 // y_tree = A_H2 x_tree on plan buffers (x in p.xt, result in p.yt).
 void run_matvec_tree(const h2_matrix& H, MatvecPlan& p, hipStream_t st) {
-  const int dim = H.tree.dim;
-  const double sc = H.scale, dg = H.diag;
-  p.close.launch<double>(st, dim, sc, dg);
-  for (int k = 0; k <= H.tree.depth; ++k) p.up[k].launch<double>(st, dim, sc, dg);
-  p.xproj.launch<double>(st, dim, sc, dg);
-  p.coup.launch<double>(st, dim, sc, dg);
-  p.yproj.launch<double>(st, dim, sc, dg);
-  for (int k = H.tree.depth - 1; k >= 0; --k) p.down[k].launch<double>(st, dim, sc, dg);
-  p.leafout.launch<double>(st, dim, sc, dg);
+  p.close.launch<double>(st);
+  for (int k = 0; k <= H.tree.depth; ++k) p.up[k].launch<double>(st);
+  p.xproj.launch<double>(st);
+  p.coup.launch<double>(st);
+  p.yproj.launch<double>(st);
+  for (int k = H.tree.depth - 1; k >= 0; --k) p.down[k].launch<double>(st);
+  p.leafout.launch<double>(st);
 }
 
 MatvecPlan& matvec_plan(const h2_matrix& H, i64 nrhs);

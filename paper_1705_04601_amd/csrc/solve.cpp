@@ -187,12 +187,12 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
 // V (L D L^T)^{-1} U^T zin in tree order.
 template <class T>
 static void apply_tree(h2_factor& f, SolvePlan& p, hipStream_t st) {
-  const int L = f.sp->H->tree.depth, dim = f.sp->H->tree.dim;
-  for (int k = 0; k <= L; ++k) p.up[k].launch<T>(st, dim, 0, 0);
-  for (int lv = 0; lv < f.nflev; ++lv) p.fwd[lv].launch<T>(st, dim, 0, 0);
-  p.diag.launch<T>(st, dim, 0, 0);
-  for (int lv = 0; lv < f.nblev; ++lv) p.bwd[lv].launch<T>(st, dim, 0, 0);
-  for (int k = L; k >= 0; --k) p.down[k].launch<T>(st, dim, 0, 0);
+  const int L = f.sp->H->tree.depth;
+  for (int k = 0; k <= L; ++k) p.up[k].launch<T>(st);
+  for (int lv = 0; lv < f.nflev; ++lv) p.fwd[lv].launch<T>(st);
+  p.diag.launch<T>(st);
+  for (int lv = 0; lv < f.nblev; ++lv) p.bwd[lv].launch<T>(st);
+  for (int k = L; k >= 0; --k) p.down[k].launch<T>(st);
 }
 
 SolvePlan& solve_plan(h2_factor& f, i64 nrhs) {

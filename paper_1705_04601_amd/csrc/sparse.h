@@ -71,4 +71,6 @@ struct h2_sparse {
 
 namespace h2 {
 void run_sparsify(h2_sparse& sp, hipStream_t st, double* phase_ms);
+h2_sparse* plan_sparsify(h2_matrix* H, int precision, bool upload);
+void run_sparsify_batch(std::vector<h2_sparse*>& sps, hipStream_t st, double* phase_ms);
 }

@@ -37,7 +37,7 @@ struct SymStrip {
 
 }  // namespace
 
-static h2_sparse* plan(h2_matrix* H, int precision) {
+static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
   TraceTimer tt("sparsify-plan");
   H->upload_all();
   auto spp = std::make_unique<h2_sparse>();
@@ -438,8 +438,10 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
     blobs.push_back({lv.qr.items.data(), lv.qr.items.size() * sizeof(QrItem),
                      reinterpret_cast<const void**>(&lv.qr.d_items)});
   }
+  for (GemmBatch* g : all) g->set_generator(dim, H->scale, H->diag);
   tt.lap("work-lists");
   HIPCHECK(hipStreamSynchronize(current_stream()));
+  if (!upload) return spp.release();  // a batched sweep merges and uploads the lists
   upload_batches(all, sp.dDesc, blobs);
   tt.lap("upload");
   for (auto& lv : sp.levels) std::vector<QrItem>().swap(lv.qr.items);
@@ -449,8 +451,7 @@ static h2_sparse* plan(h2_matrix* H, int precision) {
 template <class T>
 static void run_levels(h2_sparse& sp, hipStream_t st, double* phase_ms) {
   h2_matrix& H = *sp.H;
-  const int L = H.tree.depth, dim = H.tree.dim;
-  const double sc = H.scale, dg = H.diag;
+  const int L = H.tree.depth;
   const bool mixed = sp.precision == H2_MIXED;
   std::vector<hipEvent_t> ev;
   auto mark = [&]() {
@@ -463,8 +464,8 @@ static void run_levels(h2_sparse& sp, hipStream_t st, double* phase_ms) {
   for (int k = 0; k <= L; ++k) {
     SweepLevel& lv = sp.levels[k];
     launch_qr(lv.qr.d_items, lv.qr.count, st);
-    lv.stack.launch<double>(st, dim, sc, dg);
-    lv.wproj.launch<double>(st, dim, sc, dg);
+    lv.stack.launch<double>(st);
+    lv.wproj.launch<double>(st);
     if (mixed) {
       launch_cast_d2f(sp.dQ.as<double>() + lv.qr.q_begin, sp.dQt.as<float>() + lv.qr.q_begin,
                       lv.qr.q_end - lv.qr.q_begin, st);
@@ -476,16 +477,16 @@ static void run_levels(h2_sparse& sp, hipStream_t st, double* phase_ms) {
       if (mixed) launch_fill_f(sp.dG[lv.gnext_side].as<float>(), lv.gnext_entries, 0.0f, st);
       else launch_fill(sp.dG[lv.gnext_side].as<double>(), lv.gnext_entries, 0.0, st);
     }
-    lv.strips.launch<T>(st, dim, sc, dg);
+    lv.strips.launch<T>(st);
     mark();  // strips end
     for (size_t c = 0; c < lv.close1.size(); ++c) {
-      lv.close1[c].launch<T>(st, dim, sc, dg);
-      lv.close2[c].launch<T>(st, dim, sc, dg);
+      lv.close1[c].launch<T>(st);
+      lv.close2[c].launch<T>(st);
     }
     mark();  // close end
     for (size_t c = 0; c < lv.coup1.size(); ++c) {
-      lv.coup1[c].launch<T>(st, dim, sc, dg);
-      lv.coup2[c].launch<T>(st, dim, sc, dg);
+      lv.coup1[c].launch<T>(st);
+      lv.coup2[c].launch<T>(st);
     }
     mark();  // couplings end
   }
@@ -515,6 +516,133 @@ void run_sparsify(h2_sparse& sp, hipStream_t st, double* phase_ms) {
   else run_levels<double>(sp, st, phase_ms);
 }
 
-h2_sparse* plan_sparsify(h2_matrix* H, int precision) { return plan(H, precision); }
+h2_sparse* plan_sparsify(h2_matrix* H, int precision, bool upload) { return plan(H, precision, upload); }
+
+// Several sparsifications swept together (independent H^2 matrices of uneven
+// size): level k of every instance goes into the same launches.  Work items
+// carry absolute addresses and their own kernel constants, so the instances'
+// lists are concatenated per step and chunk and every instance keeps its own
+// arenas; only the per-instance casts and arena clears stay separate.
+struct MergedLevel {
+  std::vector<QrItem> qr;
+  const QrItem* d_qr = nullptr;
+  int nqr = 0;
+  GemmBatch stack, wproj, strips;
+  std::vector<GemmBatch> close1, close2, coup1, coup2;
+};
+
+template <class T>
+static void run_merged(std::vector<h2_sparse*>& sps, std::vector<MergedLevel>& M, hipStream_t st,
+                       double* phase_ms) {
+  const bool mixed = sps.front()->precision == H2_MIXED;
+  std::vector<hipEvent_t> ev;
+  auto mark = [&]() {
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    HIPCHECK(hipEventRecord(e, st));
+    ev.push_back(e);
+  };
+  mark();
+  const int nlev = int(M.size());
+  for (int k = 0; k < nlev; ++k) {
+    MergedLevel& m = M[k];
+    launch_qr(m.d_qr, m.nqr, st);
+    m.stack.launch<double>(st);
+    m.wproj.launch<double>(st);
+    for (h2_sparse* sp : sps) {
+      if (k > sp->H->tree.depth || !mixed) continue;
+      const SweepLevel& lv = sp->levels[k];
+      launch_cast_d2f(sp->dQ.as<double>() + lv.qr.q_begin, sp->dQt.as<float>() + lv.qr.q_begin,
+                      lv.qr.q_end - lv.qr.q_begin, st);
+      const double* wsrc = sp->H->identity_proj ? sp->dRhat.as<double>() : sp->dW.as<double>();
+      launch_cast_d2f(wsrc + lv.qr.w_begin, sp->dWt.as<float>() + lv.qr.w_begin, lv.qr.w_end - lv.qr.w_begin, st);
+    }
+    mark();
+    for (h2_sparse* sp : sps) {
+      if (k > sp->H->tree.depth) continue;
+      const SweepLevel& lv = sp->levels[k];
+      if (lv.gnext_entries <= 0) continue;
+      if (mixed) launch_fill_f(sp->dG[lv.gnext_side].as<float>(), lv.gnext_entries, 0.0f, st);
+      else launch_fill(sp->dG[lv.gnext_side].as<double>(), lv.gnext_entries, 0.0, st);
+    }
+    m.strips.launch<T>(st);
+    mark();
+    for (size_t c = 0; c < m.close1.size(); ++c) {
+      m.close1[c].launch<T>(st);
+      m.close2[c].launch<T>(st);
+    }
+    mark();
+    for (size_t c = 0; c < m.coup1.size(); ++c) {
+      m.coup1[c].launch<T>(st);
+      m.coup2[c].launch<T>(st);
+    }
+    mark();
+  }
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipEventSynchronize(ev.back()));
+  double acc[4] = {0, 0, 0, 0};
+  for (int k = 0; k < nlev; ++k)
+    for (int ph = 0; ph < 4; ++ph) {
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, ev[4 * k + ph], ev[4 * k + ph + 1]));
+      acc[ph] += ms;
+    }
+  float tot = 0;
+  HIPCHECK(hipEventElapsedTime(&tot, ev.front(), ev.back()));
+  for (auto e : ev) (void)hipEventDestroy(e);
+  if (phase_ms) {
+    phase_ms[0] = acc[0];
+    phase_ms[1] = acc[2];
+    phase_ms[2] = acc[3];
+    phase_ms[3] = acc[1];
+    phase_ms[6] = tot;
+  }
+}
+
+void run_sparsify_batch(std::vector<h2_sparse*>& sps, hipStream_t st, double* phase_ms) {
+  TraceTimer tt("sparsify-batch");
+  int nlev = 0;
+  for (h2_sparse* sp : sps) nlev = std::max(nlev, sp->H->tree.depth + 1);
+  std::vector<MergedLevel> M(nlev);
+  for (int k = 0; k < nlev; ++k) {
+    MergedLevel& m = M[k];
+    for (h2_sparse* sp : sps) {
+      if (k > sp->H->tree.depth) continue;
+      SweepLevel& lv = sp->levels[k];
+      m.qr.insert(m.qr.end(), lv.qr.items.begin(), lv.qr.items.end());
+      std::vector<QrItem>().swap(lv.qr.items);
+      m.stack.append(lv.stack);
+      m.wproj.append(lv.wproj);
+      m.strips.append(lv.strips);
+      auto merge_chunks = [](std::vector<GemmBatch>& dst, std::vector<GemmBatch>& src) {
+        if (dst.size() < src.size()) dst.resize(src.size());
+        for (size_t c = 0; c < src.size(); ++c) dst[c].append(src[c]);
+      };
+      merge_chunks(m.close1, lv.close1);
+      merge_chunks(m.close2, lv.close2);
+      merge_chunks(m.coup1, lv.coup1);
+      merge_chunks(m.coup2, lv.coup2);
+    }
+    m.nqr = int(m.qr.size());
+  }
+  std::vector<GemmBatch*> all;
+  std::vector<RawBlob> blobs;
+  for (MergedLevel& m : M) {
+    all.push_back(&m.stack);
+    all.push_back(&m.wproj);
+    all.push_back(&m.strips);
+    for (auto& g : m.close1) all.push_back(&g);
+    for (auto& g : m.close2) all.push_back(&g);
+    for (auto& g : m.coup1) all.push_back(&g);
+    for (auto& g : m.coup2) all.push_back(&g);
+    blobs.push_back({m.qr.data(), m.qr.size() * sizeof(QrItem), reinterpret_cast<const void**>(&m.d_qr)});
+  }
+  DeviceBuffer desc;
+  upload_batches(all, desc, blobs);
+  tt.lap("merge+upload");
+  if (sps.front()->precision == H2_MIXED) run_merged<float>(sps, M, st, phase_ms);
+  else run_merged<double>(sps, M, st, phase_ms);
+  tt.lap("run");
+}
 
 }  // namespace h2

@@ -316,3 +316,58 @@ def test_fp64_sparsify_is_deterministic():
             m1, m2 = sp.nonbasis[t], sp.nonbasis[s]
             assert np.array_equal(P.h2_sparse_export_block(s1, t, s, m1, m2),
                                   P.h2_sparse_export_block(s2, t, s, m1, m2))
+
+
+BATCH = ["cube1536", "sphere2k", "torus777", "cube2500r48", "hodlr700", "square1k"]
+
+
+@pytest.mark.parametrize("precision", [P.H2_FP64, P.H2_MIXED], ids=["fp64", "mixed"])
+def test_sparsify_batch_matches_single(precision):
+    """One merged level sweep over instances of different size, depth, rank,
+    admissibility and dimension gives every instance exactly its own result."""
+    note(f"sparsify batch precision={precision}")
+    hs = [imported(n) for n in BATCH]
+    batch = P.h2_sparsify_batch(hs, precision)
+    for name, h, spb in zip(BATCH, hs, batch):
+        sp = case(name)[3]
+        single = P.h2_sparsify(imported(name), precision)
+        _check_plan(spb, sp)
+        for t, q in sp.q.items():
+            assert np.array_equal(P.h2_sparse_export_q(spb, t, q.shape[0]),
+                                  P.h2_sparse_export_q(single, t, q.shape[0])), f"{name}: Q of {t}"
+        for (t, s), blk in sp.s_blocks.items():
+            got = P.h2_sparse_export_block(spb, t, s, *blk.shape)
+            assert np.array_equal(got, P.h2_sparse_export_block(single, t, s, *blk.shape)), f"{name}: S {t},{s}"
+
+
+def test_factor_solve_batch():
+    note("factor + solve batch mixed")
+    hs = [P.h2_build(case(n)[0], case(n)[1], 1.0, *case(n)[5]) for n in BATCH]
+    sps = P.h2_sparsify_batch(hs, P.H2_MIXED)
+    fs = P.h2_factor_S_batch(sps)
+    rng = np.random.default_rng(12)
+    bs, xs, refs = [], [], []
+    for i, name in enumerate(BATCH):
+        x, sc, h2, sp, a, _ = case(name)
+        b = rng.standard_normal((x.shape[0], 1 + i))
+        bs.append(dev(b))
+        xs.append(dev(np.zeros_like(b)))
+        refs.append(from_tree(np.linalg.solve(a, to_tree(b, h2.tree.perm)), h2.tree.perm))
+    infos = P.h2_solve_batch(fs, bs, xs, tol=1e-10, max_iter=40)
+    for name, info, xv, ref, b in zip(BATCH, infos, xs, refs, bs):
+        assert info["residual"] <= 1e-10, name
+        assert np.abs(host(xv) - ref).max() <= 1e-8 * np.abs(ref).max(), name
+    # the same instance alone gives the same bits
+    h0 = P.h2_build(case(BATCH[1])[0], case(BATCH[1])[1], 1.0, *case(BATCH[1])[5])
+    f0 = P.h2_factor_S(P.h2_sparsify(h0, P.H2_MIXED))
+    x0 = dev(np.zeros((case(BATCH[1])[0].shape[0], 2)))
+    P.h2_solve(f0, bs[1], x0, tol=1e-10, max_iter=40)
+    assert np.array_equal(host(x0), host(xs[1]))
+
+
+def test_batch_rejects_repeated_handles():
+    note("batch argument errors")
+    sp = P.h2_sparsify(imported("torus777"), P.H2_FP64)
+    with pytest.raises(P.H2Error) as e:
+        P.h2_factor_S_batch([sp, sp])
+    assert e.value.code == P.H2_EINVAL
