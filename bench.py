@@ -164,12 +164,80 @@ def cpu_baseline(wl, budget_s=20.0):
                       f"{best['iters']} steps): sparsify+ILU(0)+refine {best['seconds']:.2f}s on 1 thread"}
 
 
+BATCH_WORKLOAD = "batch64"
+
+
+def bench_batch(args, P, torch):
+    """64 independent instances (N log-uniform in [4096, 65536], cube / sphere /
+    torus, leaf 32..64, Chebyshev 3^3 recompressed to 1e-8, 16 RHS each): one
+    step = h2_sparsify_batch + h2_factor_S_batch + h2_solve_batch."""
+    inst = h2inputs.batch_instances(64, 4)
+    nrhs = 16
+    hs, bs, xs, ns = [], [], [], []
+    t0 = time.perf_counter()
+    for kind, n, leaf, seed in inst:
+        x = h2inputs.points(kind, n, seed)
+        sc = h2inputs.kernel_scale("1/(4piN)", n)
+        hs.append(P.h2_build(x, sc, 1.0, leaf, 3, 1e-8, 27))
+        bh = h2inputs.rhs(n, nrhs, seed)
+        b = torch.from_numpy(np.ascontiguousarray(bh.T)).cuda().T
+        bs.append(b)
+        xs.append(torch.zeros_like(b))
+        ns.append(n)
+    t_build = time.perf_counter() - t0
+    log(f"batch64: {len(hs)} instances, N {min(ns)}..{max(ns)} (total {sum(ns)}), built in {t_build:.1f}s")
+    total = nrhs * sum(ns)
+
+    def step(prec):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        sps = P.h2_sparsify_batch(hs, prec)
+        b_ = time.perf_counter()
+        fs = P.h2_factor_S_batch(sps)
+        c_ = time.perf_counter()
+        infos = P.h2_solve_batch(fs, bs, xs, tol=args.tol, max_iter=args.max_iter, check=False)
+        torch.cuda.synchronize()
+        d_ = time.perf_counter()
+        del fs, sps
+        return dict(t_sparsify=b_ - a, t_factor_S=c_ - b_, t_solve=d_ - c_,
+                    iters=max(i["iters"] for i in infos), rel_residual=max(i["residual"] for i in infos))
+
+    res = {}
+    for name, prec in [("mixed", P.H2_MIXED)] + ([] if args.no_fp64 else [("fp64", P.H2_FP64)]):
+        for w in range(args.warmup):
+            step(prec)
+        recs = []
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            recs.append(step(prec))
+            log(f"batch64 step {k + 1}/{args.steps} {name}: {recs[-1]}")
+        torch.cuda.synchronize()
+        res[name] = ((time.perf_counter() - t0) / args.steps, recs[-1])
+    sec, last = res["mixed"]
+    out = {
+        "metric": "factor+solve s and RHS*N/s, mixed vs FP64 plain, 1e-8 rel. residual",
+        "value": total / sec, "unit": "RHS*N/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": BATCH_WORKLOAD, "instances": len(hs), "N_total": sum(ns), "N_min": min(ns),
+                   "N_max": max(ns), "points": "cube/sphere/torus", "leaf": "32..64", "cheb": 3,
+                   "recompress_tol": 1e-8, "nrhs_each": nrhs, "factor": "block ILU(0) of S", "precision": "mixed"},
+        "mixed": dict(last, factor_plus_solve_s=sec),
+        "h2_build_s": t_build,
+    }
+    if "fp64" in res:
+        sec64, l64 = res["fp64"]
+        out["fp64_plain"] = dict(l64, factor_plus_solve_s=sec64, rhs_n_per_s=total / sec64)
+        out["mixed_speedup_vs_fp64"] = sec64 / sec
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube1m", choices=sorted(h2inputs.WORKLOADS))
+    ap.add_argument("--workload", default="cube1m", choices=sorted(h2inputs.WORKLOADS) + [BATCH_WORKLOAD])
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this size (counter calibration)")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -187,6 +255,10 @@ def main():
     import torch
     import paper_1705_04601_amd as P
 
+    if args.workload == BATCH_WORKLOAD:
+        torch.cuda.set_device(0)
+        bench_batch(args, P, torch)
+        return
     wl = h2inputs.WORKLOADS[args.workload]
     n, nrhs = wl["n"], wl["nrhs"]
     torch.cuda.set_device(0)

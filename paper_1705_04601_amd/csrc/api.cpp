@@ -243,10 +243,9 @@ extern "C" int h2_sparsify_batch(h2_matrix* const* hs, int count, const h2_spars
   if (prec != H2_FP64 && prec != H2_MIXED) fail(H2_EINVAL, "unknown precision");
   std::vector<std::unique_ptr<h2_sparse>> own(count);
   std::vector<h2_sparse*> sps(count);
-  for (int i = 0; i < count; ++i) {
-    own[i].reset(plan_sparsify(hs[i], prec, false));
-    sps[i] = own[i].get();
-  }
+  // the instances are planned concurrently (host work); their sweeps are merged below
+  run_pooled(count, [&](int i) { own[i].reset(plan_sparsify(hs[i], prec, false)); });
+  for (int i = 0; i < count; ++i) sps[i] = own[i].get();
   std::fill(g_timings, g_timings + 8, 0.0);
   std::fill(g_work, g_work + 16, 0.0);
   run_sparsify_batch(sps, current_stream(), g_timings);

@@ -225,7 +225,7 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
     const size_t n = std::min(kPiece, extra[i].bytes - b);
     std::memcpy(&staging[xoff[i] + b], static_cast<const char*>(extra[i].host) + b, n);
   }
-  store.reset(total);
+  store.reset(total, copy);
   if (copy) {
     HIPCHECK(hipMemcpyAsync(store.ptr, staging, total, hipMemcpyHostToDevice, copy));
     hipEvent_t done;
@@ -235,7 +235,9 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
     HIPCHECK(hipStreamSynchronize(copy));  // the staging buffer is released below
     HIPCHECK(hipEventDestroy(done));
   } else {
-    HIPCHECK(hipMemcpy(store.ptr, staging, total, hipMemcpyHostToDevice));
+    // on the current stream: a reused block may wait there for its last user
+    HIPCHECK(hipMemcpyAsync(store.ptr, staging, total, hipMemcpyHostToDevice, current_stream()));
+    HIPCHECK(hipStreamSynchronize(current_stream()));  // the staging buffer is released below
   }
   char* base = static_cast<char*>(store.ptr);
   for (size_t i = 0; i < bs.size(); ++i) {

@@ -596,6 +596,7 @@ static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
   // entries counted so far exceed it (3D fill grows much faster than S)
   size_t free_b = 0, total_b = 0;
   HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+  free_b += cached_device_bytes();
   const double budget = std::max(1.0, 0.9 * double(free_b) / double(sizeof(T)) - double(kOverread));
   std::vector<std::vector<i64>> R = symbolic_fill(sp, budget, double(sizeof(T)), nullptr, nullptr);
   std::vector<i64> rowptr(ncl + 1, 0), colidx, blk_off;

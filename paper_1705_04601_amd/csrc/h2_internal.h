@@ -66,19 +66,32 @@ BlockTree build_block_tree(const Tree& tr, double eta);
 std::vector<char> farfield_flags(const Tree& tr, const BlockTree& bt);
 
 // ---------------------------------------------------------------- device arena
+// Device memory block from the library's caching allocator (a freed block is
+// kept for reuse, ordered by an event on the freeing stream).
 struct DeviceBuffer {
   void* ptr = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // requested
+  size_t cap = 0;    // allocated
   DeviceBuffer() = default;
   explicit DeviceBuffer(size_t b);
   DeviceBuffer(const DeviceBuffer&) = delete;
   DeviceBuffer& operator=(const DeviceBuffer&) = delete;
-  DeviceBuffer(DeviceBuffer&& o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+  DeviceBuffer(DeviceBuffer&& o) noexcept : ptr(o.ptr), bytes(o.bytes), cap(o.cap) {
+    o.ptr = nullptr;
+    o.bytes = 0;
+    o.cap = 0;
+  }
   DeviceBuffer& operator=(DeviceBuffer&& o) noexcept;
   ~DeviceBuffer();
-  void reset(size_t b);
+  // frees the block (ordered after the work queued on the current stream) and
+  // allocates b bytes; a reused block is made safe for `first_use` (default:
+  // the current stream), the stream that touches it first
+  void reset(size_t b, hipStream_t first_use = nullptr);
   template <class T> T* as() const { return static_cast<T*>(ptr); }
 };
+
+// Bytes held by idle cached blocks (free for the library's own allocations).
+size_t cached_device_bytes();
 
 template <class T>
 DeviceBuffer upload(const std::vector<T>& v) {

@@ -1,5 +1,8 @@
 // Runtime pieces shared by every entry point: errors, stream, device memory.
 #include <chrono>
+#include <iterator>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -41,31 +44,135 @@ void check_hip(hipError_t e, const char* what) {
   fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// ---------------------------------------------------------------- device memory
+// Caching allocator.  hipFree waits for the whole device, which serialises
+// work queued on other streams (batched instances run on a stream pool), and
+// the same large buffers come back call after call.  A freed block is kept
+// with an event recorded on the freeing stream; a later request of about its
+// size takes it back after making its own stream wait for that event.  Idle
+// blocks are capped and are released first when hipMalloc runs out.
+namespace {
+struct CachedBlock {
+  void* p;
+  size_t cap;
+  hipEvent_t done;
+  int dev;
+};
+std::mutex g_cache_mu;
+std::multimap<size_t, CachedBlock> g_cache;  // by capacity
+size_t g_cached = 0;
+constexpr size_t kCacheLimit = size_t(64) << 30;
+
+size_t round_cap(size_t b) {
+  constexpr size_t g = size_t(2) << 20;
+  return b >= (size_t(1) << 20) ? (b + g - 1) & ~(g - 1) : (b + 255) & ~size_t(255);
+}
+
+// releases idle blocks (largest first) until at most `keep` bytes stay cached
+void trim_locked(size_t keep) {
+  while (g_cached > keep && !g_cache.empty()) {
+    auto it = std::prev(g_cache.end());
+    (void)hipEventSynchronize(it->second.done);
+    (void)hipEventDestroy(it->second.done);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (it->second.dev != cur) (void)hipSetDevice(it->second.dev);
+    (void)hipFree(it->second.p);
+    if (it->second.dev != cur) (void)hipSetDevice(cur);
+    g_cached -= it->second.cap;
+    g_cache.erase(it);
+  }
+}
+
+void* device_alloc(size_t bytes, size_t* cap, hipStream_t first_use) {
+  const size_t want = round_cap(bytes);
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  {
+    std::unique_lock<std::mutex> lk(g_cache_mu);
+    // a cached block at most a quarter (+ 64 MiB) larger than the request
+    const size_t limit = want + want / 4 + (size_t(64) << 20);
+    for (auto it = g_cache.lower_bound(want); it != g_cache.end() && it->first <= limit; ++it) {
+      if (it->second.dev != dev) continue;
+      const CachedBlock c = it->second;
+      g_cache.erase(it);
+      g_cached -= c.cap;
+      lk.unlock();
+      const hipError_t e = hipStreamWaitEvent(first_use, c.done, 0);
+      (void)hipEventDestroy(c.done);
+      if (e != hipSuccess) {
+        (void)hipDeviceSynchronize();  // cannot order the reuse: wait for everything instead
+        (void)hipGetLastError();
+      }
+      *cap = c.cap;
+      return c.p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      trim_locked(0);
+    }
+    e = hipMalloc(&p, want);
+  }
+  check_hip(e, "hipMalloc");
+  *cap = want;
+  return p;
+}
+
+void device_free(void* p, size_t cap) {
+  int dev = 0;
+  hipEvent_t ev = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ev, current_stream()) != hipSuccess) {
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.emplace(cap, CachedBlock{p, cap, ev, dev});
+  g_cached += cap;
+  trim_locked(kCacheLimit);
+}
+}  // namespace
+
+size_t cached_device_bytes() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  return g_cached;
+}
+
 DeviceBuffer::DeviceBuffer(size_t b) { reset(b); }
 
 DeviceBuffer& DeviceBuffer::operator=(DeviceBuffer&& o) noexcept {
   if (this != &o) {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) device_free(ptr, cap);
     ptr = o.ptr;
     bytes = o.bytes;
+    cap = o.cap;
     o.ptr = nullptr;
     o.bytes = 0;
+    o.cap = 0;
   }
   return *this;
 }
 
 DeviceBuffer::~DeviceBuffer() {
-  if (ptr) (void)hipFree(ptr);
+  if (ptr) device_free(ptr, cap);
 }
 
-void DeviceBuffer::reset(size_t b) {
+void DeviceBuffer::reset(size_t b, hipStream_t first_use) {
   if (ptr) {
-    HIPCHECK(hipStreamSynchronize(current_stream()));
-    HIPCHECK(hipFree(ptr));
+    device_free(ptr, cap);
     ptr = nullptr;
+    cap = 0;
   }
   bytes = b;
-  if (b) HIPCHECK(hipMalloc(&ptr, b));
+  if (b) ptr = device_alloc(b, &cap, first_use ? first_use : current_stream());
 }
 
 }  // namespace h2
