@@ -47,9 +47,9 @@ struct GemmBatch {
   const GemmSeg* d_segs = nullptr;
   const int32_t* d_tiles = nullptr;
   int32_t ntiles = 0;
-  bool kc = true;      // direct kernel (64 x 64 tiles, no LDS); false: LDS-staged kernel
   int mode = GEMM_STORE;
   int role = ROLE_TRANSFORM;
+  int amode = -1, bmode = -1;  // operand layouts shared by every segment (build_tiles)
   double flops = 0.0;  // algorithmic flops of the batch
 
   bool empty() const { return items.empty(); }
@@ -86,6 +86,22 @@ struct GemmBatch {
     s.diag = 0;
     push(s);
   }
+  // Generated B(k, j) = scale / |pr_j - pc_k| (diagonal value where j == k if
+  // diag) times a stored A (M x K).
+  void seg_genB(const void* A, int lda, bool tA, const double* pr, const double* pc, bool diag, int K) {
+    GemmSeg s{};
+    s.A = A;
+    s.B = pr;
+    s.pc = pc;
+    s.K = K;
+    s.lda = lda;
+    s.ldb = 0;
+    s.opA = tA;
+    s.opB = 0;
+    s.gen = 2;
+    s.diag = diag ? 1 : 0;
+    push(s);
+  }
   // Generated A(i, k) = scale / |pr_i - pc_k| (diagonal value where i == k if diag).
   void seg_gen(const double* pr, const double* pc, bool diag, const void* B, int ldb, bool tB, int K) {
     GemmSeg s{};
@@ -108,17 +124,28 @@ struct GemmBatch {
     it.seg_end = int32_t(segs.size());
     flops += 2.0 * it.M * double(it.N) * s.K;
   }
-  // Tile list: one tile per work-group (64 x 64 for the K-contiguous kernel,
-  // 32 x 32 otherwise).  Items without segments are kept only when they store
-  // (they then write zeros).
+  // Tile list: one 64 x 64 tile per work-group.  Items without segments are
+  // kept only when they store (they then write zeros).
   void build_tiles() {
     tiles.clear();
-    kc = true;  // the direct (no-LDS) kernel serves every operand layout
+    amode = bmode = -1;
+    for (const GemmSeg& sg : segs) {
+      const int am = sg.gen == 1 ? 2 : (sg.opA ? 0 : 1);
+      const int bm = sg.gen == 2 ? 2 : (sg.opB ? 1 : 0);
+      if (amode < 0) {
+        amode = am;
+        bmode = bm;
+      } else if (am != amode || bm != bmode) {
+        fail(H2_EINVAL, "internal: segments of one GEMM batch with different operand layouts");
+      }
+    }
+    if (amode >= 0 && !gemm_layout_supported(role, amode, bmode))
+      fail(H2_EINVAL, "internal: no GEMM kernel for this role and operand layout");
     if (items.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "GEMM batch above 2^24 items");
     for (size_t i = 0; i < items.size(); ++i) {
       const GemmItem& it = items[i];
       if (it.seg_end == it.seg_begin && mode != GEMM_STORE) continue;
-      const int edge = kc ? 64 : 32;  // tile edge of the kernel that will run it
+      constexpr int edge = 64;  // tile edge of the kernel
       const int tm = (it.M + edge - 1) / edge, tn = (it.N + edge - 1) / edge;
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b) tiles.push_back(int32_t((uint32_t(i) << 8) | (a << 4) | b));
@@ -160,7 +187,8 @@ struct GemmBatch {
   void launch(hipStream_t st) const {
     if (ntiles <= 0) return;
     GemmLaunch g{};
-    g.kc = kc ? 1 : 0;
+    g.amode = amode;
+    g.bmode = bmode;
     g.items = d_items;
     g.segs = d_segs;
     g.tiles = d_tiles;

@@ -12,10 +12,12 @@ namespace h2 {
 // opA = 1: A stored K x M   (element (i, k) at A[k + i lda]).
 // opB = 0: B column-major K x N; opB = 1: B stored N x K.
 // gen = 1: A is generated, A(i, k) = scale / |pr_i - pc_k| with pr = (const
-// double*) A and pc the column points (dim-strided); diag = 1 puts the
-// diagonal value where i == k (a cluster against itself).  scale, the
-// diagonal value and dim belong to the item (so that items of different
-// matrices can share a launch).
+// double*) A and pc the points along K (dim-strided); gen = 2: B is generated
+// the same way, B(k, j) = scale / |pr_j - pc_k| with pr = (const double*) B
+// (the kernel is symmetric).  diag = 1 puts the diagonal value where the two
+// indices are equal (a cluster against itself).  scale, the diagonal value
+// and dim belong to the item (so that items of different matrices can share
+// a launch).
 struct GemmSeg {
   const void* A;
   const void* B;
@@ -44,8 +46,12 @@ enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1, GEMM_SUB = 2 };
 // sparsification transforms, the factorisation, the solve sweeps and the matvec.
 enum GemmRole { ROLE_TRANSFORM = 0, ROLE_FACTOR = 1, ROLE_SOLVE = 2, ROLE_MATVEC = 3 };
 
+// Operand layout codes of a launch: amode 0 = A K-contiguous (opA = 1),
+// 1 = A M-contiguous (opA = 0), 2 = A generated; bmode 0 = B K-contiguous
+// (opB = 0), 1 = B N-contiguous (opB = 1), 2 = B generated.  All segments of
+// a launch share them.
 struct GemmLaunch {
-  int kc;                 // 1: every segment has opA = 1, opB = 0 and no generated A
+  int amode, bmode;
   const GemmItem* items;
   const GemmSeg* segs;
   const int32_t* tiles;   // per work-group: (item << 8) | (tile_row << 4) | tile_col
@@ -56,6 +62,8 @@ struct GemmLaunch {
 
 template <class T>
 void launch_gemm(const GemmLaunch& g, hipStream_t st);
+// whether a role's kernels are built for a layout pair
+bool gemm_layout_supported(int role, int amode, int bmode);
 
 // Compact work list of the Schur update S_ij -= Z_ki^T S_kj (offsets in
 // elements into S and into the buffer of Z_ki blocks; every operand has leading
@@ -133,25 +141,25 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_f(float* p, int64_t n, float v, hipStream_t st);
 void launch_fill_i(int* p, int64_t n, int v, hipStream_t st);
 void launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t st);
-void launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t st);
-// out[i + j ldo] = in[idx[i] + j ldi]  (gather rows), i < n, j < nrhs
-template <class T>
-void launch_gather_rows(const T* in, int64_t ldi, const int64_t* idx, T* out, int64_t ldo,
-                        int64_t n, int64_t nrhs, hipStream_t st);
-// out[idx[i] + j ldo] = in[i + j ldi]  (scatter rows)
-void launch_scatter_rows(const double* in, int64_t ldi, const int64_t* idx, double* out,
-                         int64_t ldo, int64_t n, int64_t nrhs, hipStream_t st);
-// r = b - y (ld's), columnwise sum of squares of r and of b into nrm2[2*nrhs]
-void launch_residual(const double* b, int64_t ldb, const double* y, int64_t ldy, double* r,
-                     int64_t n, int64_t nrhs, double* nrm2, hipStream_t st);
-// float out = in * (1/colscale[j]);  double acc += float in * colscale[j]
-void launch_scale_to_f(const double* in, const double* colscale, float* out, int64_t n,
-                       int64_t nrhs, hipStream_t st);
-void launch_add_scaled_f(const float* in, const double* colscale, double* acc, int64_t ldacc,
-                         int64_t n, int64_t nrhs, hipStream_t st);
 void launch_add(const double* in, double* acc, int64_t ldacc, int64_t n, int64_t nrhs,
                 hipStream_t st);
-void launch_copy_cols(const double* in, int64_t ldi, double* out, int64_t ldo, int64_t n,
-                      int64_t nrhs, hipStream_t st);
+
+// Right-hand-side blocks inside the solve and the matvec are stored
+// RHS-fastest: element (i, j) of an n x nrhs block at i nrhs + j.
+// out[i nrhs + j] = in[idx[i] + j ld]  (caller's column-major block, rows picked by idx)
+void launch_gather_rm(const double* in, int64_t ld, const int64_t* idx, double* out, int64_t n, int64_t nrhs,
+                      hipStream_t st);
+// out[idx[i] + j ld] = in[i nrhs + j]
+void launch_scatter_rm(const double* in, const int64_t* idx, double* out, int64_t ld, int64_t n, int64_t nrhs,
+                       hipStream_t st);
+// r = b - y, then nrm2[j] = sum_i r_ij^2 and nrm2[nrhs + j] = sum_i b_ij^2 in a
+// fixed order; part: scratch of residual_rm_blocks(n) * 2 * nrhs doubles;
+// nrhs <= 512
+int residual_rm_blocks(int64_t n);
+void launch_residual_rm(const double* b, const double* y, double* r, int64_t n, int64_t nrhs, double* part,
+                        double* nrm2, hipStream_t st);
+// float out = in / colscale[j];  double acc += float in * colscale[j]
+void launch_scale_to_f_rm(const double* in, const double* cs, float* out, int64_t n, int64_t nrhs, hipStream_t st);
+void launch_add_scaled_f_rm(const float* in, const double* cs, double* acc, int64_t n, int64_t nrhs, hipStream_t st);
 
 }  // namespace h2

@@ -1,11 +1,12 @@
 // HIP kernels of libh2sp for gfx950 (CDNA4, 64-wide wavefronts).
 //
-//  * gemm_kernel: batched, segmented small GEMM on MFMA (v_mfma_f64_16x16x4 /
-//    v_mfma_f32_16x16x4).  One wavefront per 32 x 32 output tile, K staged
-//    through LDS in chunks of 16; operand A can be generated on the fly from
-//    points (kernel evaluation, so close blocks never touch HBM); the epilogue
-//    scatters the four quadrants of the tile to separate destinations (the
-//    basis / non-basis split of Section 2).
+//  * gemm_kc_kernel: batched, segmented small GEMM on MFMA (v_mfma_f64_16x16x4
+//    / v_mfma_f32_16x16x4).  One wavefront per 64 x 64 output tile, operands
+//    straight from L2 without LDS; either operand can be generated on the fly
+//    from points (kernel evaluation, so close blocks never touch HBM); the
+//    epilogue scatters the four quadrants of the tile to separate
+//    destinations (the basis / non-basis split of Section 2).
+//  * schur_kernel: the Schur updates of the block factorisation.
 //  * qr_kernel: Householder QR of a cluster basis held in LDS, FP64, norms by
 //    wavefront reductions, explicit square Q (Section 4.2).
 //  * inverse_kernel: FP64 Gauss-Jordan inversion with partial pivoting of a
@@ -40,7 +41,6 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
 };
 
-constexpr int TM = 32, TN = 32, KC = 16;
 
 // Destination q of an item, selected with constant indices only (a dynamic
 // index into the item's arrays would move the item to scratch memory).
@@ -62,110 +62,6 @@ __device__ __forceinline__ void store_out(const GemmItem& it, int q, int lr, int
   if (mode == GEMM_STORE) *p = v;
   else if (mode == GEMM_ADD) *p += v;
   else *p -= v;
-}
-
-template <class T, int ROLE>
-__global__ __launch_bounds__(64) void gemm_kernel(GemmLaunch g) {
-  using V = typename Mfma<T>::V;
-  __shared__ T As[KC][TM + 1];
-  __shared__ T Bs[KC][TN + 1];
-  const int lane = threadIdx.x;
-  const uint32_t code = static_cast<uint32_t>(g.tiles[blockIdx.x]);
-  const GemmItem it = g.items[code >> 8];
-  const int m0 = int((code >> 4) & 15) * TM, n0 = int(code & 15) * TN;
-  V acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = V{0, 0, 0, 0};
-  const int dim = it.gdim;
-  for (int si = it.seg_begin; si < it.seg_end; ++si) {
-    const GemmSeg sg = g.segs[si];
-    for (int k0 = 0; k0 < sg.K; k0 += KC) {
-      // ---- A chunk (TM x KC) into As[k][m]
-      if (sg.gen) {
-        const double* pr = static_cast<const double*>(sg.A);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int idx = lane + 64 * e, i = idx % TM, k = idx / TM;
-          const int gi = m0 + i, gk = k0 + k;
-          T v = T(0);
-          if (gi < it.M && gk < sg.K) {
-            if (sg.diag && gi == gk) {
-              v = T(it.gdiag);
-            } else {
-              double d2 = 0.0;
-              for (int a = 0; a < dim; ++a) {
-                const double d = pr[gi * dim + a] - sg.pc[gk * dim + a];
-                d2 += d * d;
-              }
-              v = T(it.gscale / sqrt(d2));
-            }
-          }
-          As[k][i] = v;
-        }
-      } else if (sg.opA == 0) {
-        const T* A = static_cast<const T*>(sg.A);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int idx = lane + 64 * e, i = idx % TM, k = idx / TM;
-          const int gi = m0 + i, gk = k0 + k;
-          As[k][i] = (gi < it.M && gk < sg.K) ? A[gi + int64_t(gk) * sg.lda] : T(0);
-        }
-      } else {
-        const T* A = static_cast<const T*>(sg.A);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int idx = lane + 64 * e, k = idx % KC, i = idx / KC;
-          const int gi = m0 + i, gk = k0 + k;
-          As[k][i] = (gi < it.M && gk < sg.K) ? A[gk + int64_t(gi) * sg.lda] : T(0);
-        }
-      }
-      // ---- B chunk (KC x TN) into Bs[k][n]
-      const T* B = static_cast<const T*>(sg.B);
-      if (sg.opB == 0) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int idx = lane + 64 * e, k = idx % KC, n = idx / KC;
-          const int gk = k0 + k, gn = n0 + n;
-          Bs[k][n] = (gk < sg.K && gn < it.N) ? B[gk + int64_t(gn) * sg.ldb] : T(0);
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int idx = lane + 64 * e, n = idx % TN, k = idx / TN;
-          const int gk = k0 + k, gn = n0 + n;
-          Bs[k][n] = (gk < sg.K && gn < it.N) ? B[gn + int64_t(gk) * sg.ldb] : T(0);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < KC; kk += 4) {
-        const int kr = kk + lane / 16, c = lane % 16;
-        const T a0 = As[kr][c], a1 = As[kr][16 + c];
-        const T b0 = Bs[kr][c], b1 = Bs[kr][16 + c];
-        // operands swapped (D = B^T A^T) so that consecutive lanes hold
-        // consecutive output rows: lane l has output row 16bm + l%16 and
-        // output column 16bn + Mfma<T>::row(l, v)
-        acc[0][0] = Mfma<T>::run(b0, a0, acc[0][0]);
-        acc[0][1] = Mfma<T>::run(b1, a0, acc[0][1]);
-        acc[1][0] = Mfma<T>::run(b0, a1, acc[1][0]);
-        acc[1][1] = Mfma<T>::run(b1, a1, acc[1][1]);
-      }
-      __syncthreads();
-    }
-  }
-  // ---- epilogue: quadrant scatter
-  for (int bm = 0; bm < 2; ++bm)
-    for (int bn = 0; bn < 2; ++bn)
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + 16 * bm + lane % 16;
-        const int col = n0 + 16 * bn + Mfma<T>::row(lane, v);
-        if (row >= it.M || col >= it.N) continue;
-        const int q = (row >= it.rs ? 2 : 0) + (col >= it.cs ? 1 : 0);
-        const int lr = row - (q >= 2 ? it.rs : 0), lc = col - ((q & 1) ? it.cs : 0);
-        const T val = acc[bm][bn][v];
-        store_out<T>(it, q, lr, lc, val, g.mode);
-        if (q == 0) store_out<T>(it, 4, lr, lc, val, g.mode);
-      }
 }
 
 // K-contiguous variant: A stored K x M (op(A) = A^T) and B stored K x N, so
@@ -260,7 +156,7 @@ __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[4][4],
     oa[b] = b < nbm && ra[b] < M;
     ob[b] = b < nbn && cb[b] < N;
     pa[b] = (AM == 0) ? A + int64_t(oa[b] ? ra[b] : 0) * sg.lda : A;
-    pb[b] = (BM == 0) ? B + int64_t(ob[b] ? cb[b] : 0) * sg.ldb : B;
+    pb[b] = (BM == 0) ? B + int64_t(ob[b] ? cb[b] : 0) * sg.ldb : B;  // BM 1, 2: addressed per element
   }
   for (int k0 = 0; k0 < K; k0 += 16) {
     const int k = k0 + kq;
@@ -268,7 +164,9 @@ __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[4][4],
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       if (b < nbm) fetch4<T, AM>(pa[b], sg.lda, ra[b], k, K, oa[b], a[b], pr, sg.pc, dim, scale, dg, sg.diag);
-      if (b < nbn) fetch4<T, BM>(pb[b], sg.ldb, cb[b], k, K, ob[b], bv[b], nullptr, nullptr, 0, 0.0, 0.0, false);
+      if (b < nbn)
+        fetch4<T, BM>(pb[b], sg.ldb, cb[b], k, K, ob[b], bv[b], static_cast<const double*>(sg.B), sg.pc, dim,
+                      scale, dg, sg.diag);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -280,7 +178,8 @@ __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[4][4],
   }
 }
 
-template <class T, int ROLE>
+// AM / BM: operand layouts of every segment of the launch (see direct_segment)
+template <class T, int ROLE, int AM, int BM>
 __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
   using V = typename Mfma<T>::V;
   const int lane = threadIdx.x;
@@ -298,22 +197,7 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
     for (int b = 0; b < 4; ++b) acc[a][b] = V{0, 0, 0, 0};
   for (int si = it.seg_begin; si < it.seg_end; ++si) {
     const GemmSeg sg = g.segs[si];
-    // operand layouts: A K-contiguous (opA = 1), M-contiguous (opA = 0) or
-    // generated; B K-contiguous (opB = 0) or N-contiguous (opB = 1)
-    const int am = sg.gen ? 2 : (sg.opA ? 0 : 1);
-    const int bmode = sg.opB ? 1 : 0;
-    if (am == 0 && bmode == 0)
-      direct_segment<T, 0, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
-    else if (am == 1 && bmode == 0)
-      direct_segment<T, 1, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
-    else if (am == 2 && bmode == 0)
-      direct_segment<T, 2, 0>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
-    else if (am == 0)
-      direct_segment<T, 0, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
-    else if (am == 1)
-      direct_segment<T, 1, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
-    else
-      direct_segment<T, 2, 1>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
+    direct_segment<T, AM, BM>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
   }
 #pragma unroll
   for (int bm = 0; bm < 4; ++bm)
@@ -643,64 +527,6 @@ __global__ void fill_i_kernel(int* p, int64_t n, int v) {
 __global__ void cast_d2f_kernel(const double* in, float* out, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) out[i] = float(in[i]);
 }
-__global__ void cast_f2d_kernel(const float* in, double* out, int64_t n) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) out[i] = double(in[i]);
-}
-template <class T>
-__global__ void gather_rows_kernel(const T* in, int64_t ldi, const int64_t* idx, T* out, int64_t ldo, int64_t n, int64_t nrhs) {
-  const int64_t tot = n * nrhs;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t i = e % n, j = e / n;
-    out[i + j * ldo] = in[idx[i] + j * ldi];
-  }
-}
-__global__ void scatter_rows_kernel(const double* in, int64_t ldi, const int64_t* idx, double* out, int64_t ldo, int64_t n, int64_t nrhs) {
-  const int64_t tot = n * nrhs;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t i = e % n, j = e / n;
-    out[idx[i] + j * ldo] = in[i + j * ldi];
-  }
-}
-// one block per column: r = b - y and the sums of squares of r and b
-__global__ __launch_bounds__(256) void residual_kernel(const double* b, int64_t ldb, const double* y, int64_t ldy, double* r,
-                                                       int64_t n, double* nrm2, int64_t nrhs) {
-  __shared__ double red[2][256];
-  const int64_t j = blockIdx.x;
-  double sr = 0.0, sb = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const double bv = b[i + j * ldb];
-    const double rv = bv - y[i + j * ldy];
-    r[i + j * n] = rv;
-    sr += rv * rv;
-    sb += bv * bv;
-  }
-  red[0][threadIdx.x] = sr;
-  red[1][threadIdx.x] = sb;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + s];
-      red[1][threadIdx.x] += red[1][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    nrm2[j] = red[0][0];
-    nrm2[nrhs + j] = red[1][0];
-  }
-}
-__global__ void scale_to_f_kernel(const double* in, const double* cs, float* out, int64_t n, int64_t nrhs) {
-  const int64_t tot = n * nrhs;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x)
-    out[e] = float(in[e] / cs[e / n]);
-}
-__global__ void add_scaled_f_kernel(const float* in, const double* cs, double* acc, int64_t ldacc, int64_t n, int64_t nrhs) {
-  const int64_t tot = n * nrhs;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t i = e % n, j = e / n;
-    acc[i + j * ldacc] += double(in[e]) * cs[j];
-  }
-}
 __global__ void add_kernel(const double* in, double* acc, int64_t ldacc, int64_t n, int64_t nrhs) {
   const int64_t tot = n * nrhs;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
@@ -708,12 +534,74 @@ __global__ void add_kernel(const double* in, double* acc, int64_t ldacc, int64_t
     acc[i + j * ldacc] += in[e];
   }
 }
-__global__ void copy_cols_kernel(const double* in, int64_t ldi, double* out, int64_t ldo, int64_t n, int64_t nrhs) {
+
+// ---- right-hand-side blocks stored RHS-fastest: element (i, j) of an
+// n x nrhs block at i nrhs + j
+__global__ void gather_rm_kernel(const double* in, int64_t ld, const int64_t* idx, double* out, int64_t n,
+                                 int64_t nrhs) {
   const int64_t tot = n * nrhs;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t i = e % n, j = e / n;
-    out[i + j * ldo] = in[i + j * ldi];
+    const int64_t i = e / nrhs, j = e - i * nrhs;
+    out[e] = in[idx[i] + j * ld];
   }
+}
+__global__ void scatter_rm_kernel(const double* in, const int64_t* idx, double* out, int64_t ld, int64_t n,
+                                  int64_t nrhs) {
+  const int64_t tot = n * nrhs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = e / nrhs, j = e - i * nrhs;
+    out[idx[i] + j * ld] = in[e];
+  }
+}
+// r = b - y; per block and column the sums of squares of r and of b (lanes
+// run over the columns, 4 row groups per block, up to 512 columns)
+__global__ __launch_bounds__(256) void residual_rm_kernel(const double* b, const double* y, double* r, int64_t n,
+                                                          int64_t nrhs, int64_t rows, double* part) {
+  __shared__ double red[2][4][512];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t r0 = blockIdx.x * rows, r1 = min(n, r0 + rows);
+  double sr[8], sb[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) sr[q] = sb[q] = 0.0;
+  for (int64_t i = r0 + ty; i < r1; i += 4) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t j = tx + 64 * q;
+      if (j < nrhs) {
+        const double bv = b[i * nrhs + j];
+        const double rv = bv - y[i * nrhs + j];
+        r[i * nrhs + j] = rv;
+        sr[q] += rv * rv;
+        sb[q] += bv * bv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    red[0][ty][tx + 64 * q] = sr[q];
+    red[1][ty][tx + 64 * q] = sb[q];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nrhs; j += 256) {
+    part[blockIdx.x * 2 * nrhs + j] = red[0][0][j] + red[0][1][j] + red[0][2][j] + red[0][3][j];
+    part[blockIdx.x * 2 * nrhs + nrhs + j] = red[1][0][j] + red[1][1][j] + red[1][2][j] + red[1][3][j];
+  }
+}
+// nrm2[c] = sum over blocks of part[blk][c], in block order (deterministic)
+__global__ void sum_parts_kernel(const double* part, int nblk, int64_t width, double* nrm2) {
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < width; c += int64_t(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int bk = 0; bk < nblk; ++bk) s += part[bk * width + c];
+    nrm2[c] = s;
+  }
+}
+__global__ void scale_to_f_rm_kernel(const double* in, const double* cs, float* out, int64_t tot, int64_t nrhs) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x)
+    out[e] = float(in[e] / cs[e % nrhs]);
+}
+__global__ void add_scaled_f_rm_kernel(const float* in, const double* cs, double* acc, int64_t tot, int64_t nrhs) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x)
+    acc[e] += double(in[e]) * cs[e % nrhs];
 }
 
 template <class T>
@@ -735,23 +623,44 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
+// Operand layouts each role plans (the host checks every batch against them).
+template <class T, int ROLE, int AM, int BM>
+static void launch_kc(const GemmLaunch& g, hipStream_t st) {
+  hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM>), dim3(g.ntiles), dim3(64), 0, st, g);
+}
+
 template <class T>
 void launch_gemm(const GemmLaunch& g, hipStream_t st) {
   if (g.ntiles <= 0) return;
-  if (g.kc) {
-    switch (g.role) {
-      case ROLE_FACTOR: hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE_FACTOR>), dim3(g.ntiles), dim3(64), 0, st, g); break;
-      case ROLE_SOLVE: hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE_SOLVE>), dim3(g.ntiles), dim3(64), 0, st, g); break;
-      case ROLE_MATVEC: hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE_MATVEC>), dim3(g.ntiles), dim3(64), 0, st, g); break;
-      default: hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE_TRANSFORM>), dim3(g.ntiles), dim3(64), 0, st, g); break;
-    }
-    return;
-  }
+  const int m = g.amode * 3 + g.bmode;
   switch (g.role) {
-    case ROLE_FACTOR: hipLaunchKernelGGL((gemm_kernel<T, ROLE_FACTOR>), dim3(g.ntiles), dim3(64), 0, st, g); break;
-    case ROLE_SOLVE: hipLaunchKernelGGL((gemm_kernel<T, ROLE_SOLVE>), dim3(g.ntiles), dim3(64), 0, st, g); break;
-    case ROLE_MATVEC: hipLaunchKernelGGL((gemm_kernel<T, ROLE_MATVEC>), dim3(g.ntiles), dim3(64), 0, st, g); break;
-    default: hipLaunchKernelGGL((gemm_kernel<T, ROLE_TRANSFORM>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+    case ROLE_FACTOR:
+      if (m == 0) return launch_kc<T, ROLE_FACTOR, 0, 0>(g, st);
+      break;
+    case ROLE_SOLVE:
+      if (m == 3) return launch_kc<T, ROLE_SOLVE, 1, 0>(g, st);
+      if (m == 4) return launch_kc<T, ROLE_SOLVE, 1, 1>(g, st);
+      break;
+    case ROLE_MATVEC:
+      if (m == 3) return launch_kc<T, ROLE_MATVEC, 1, 0>(g, st);
+      if (m == 4) return launch_kc<T, ROLE_MATVEC, 1, 1>(g, st);
+      if (m == 5) return launch_kc<T, ROLE_MATVEC, 1, 2>(g, st);
+      break;
+    default:
+      if (m == 0) return launch_kc<T, ROLE_TRANSFORM, 0, 0>(g, st);
+      if (m == 3) return launch_kc<T, ROLE_TRANSFORM, 1, 0>(g, st);
+      if (m == 6) return launch_kc<T, ROLE_TRANSFORM, 2, 0>(g, st);
+      if (m == 7) return launch_kc<T, ROLE_TRANSFORM, 2, 1>(g, st);
+      break;
+  }
+}
+bool gemm_layout_supported(int role, int amode, int bmode) {
+  const int m = amode * 3 + bmode;
+  switch (role) {
+    case ROLE_FACTOR: return m == 0;
+    case ROLE_SOLVE: return m == 3 || m == 4;
+    case ROLE_MATVEC: return m == 3 || m == 4 || m == 5;
+    default: return m == 0 || m == 3 || m == 6 || m == 7;
   }
 }
 template void launch_gemm<double>(const GemmLaunch&, hipStream_t);
@@ -798,6 +707,34 @@ void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, 
 template void launch_copy_segments<double>(const CopySeg*, int, const double*, double*, hipStream_t);
 template void launch_copy_segments<float>(const CopySeg*, int, const float*, float*, hipStream_t);
 
+void launch_gather_rm(const double* in, int64_t ld, const int64_t* idx, double* out, int64_t n, int64_t nrhs,
+                      hipStream_t st) {
+  if (n * nrhs > 0) hipLaunchKernelGGL(gather_rm_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, ld, idx, out, n, nrhs);
+}
+void launch_scatter_rm(const double* in, const int64_t* idx, double* out, int64_t ld, int64_t n, int64_t nrhs,
+                       hipStream_t st) {
+  if (n * nrhs > 0) hipLaunchKernelGGL(scatter_rm_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, idx, out, ld, n, nrhs);
+}
+int residual_rm_blocks(int64_t n) {
+  int64_t b = (n + 63) / 64;
+  return int(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+void launch_residual_rm(const double* b, const double* y, double* r, int64_t n, int64_t nrhs, double* part,
+                        double* nrm2, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return;
+  const int nblk = residual_rm_blocks(n);
+  const int64_t rows = (n + nblk - 1) / nblk;
+  hipLaunchKernelGGL(residual_rm_kernel, dim3(nblk), dim3(256), 0, st, b, y, r, n, nrhs, rows, part);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(grid_for(2 * nrhs)), dim3(256), 0, st, part, nblk, 2 * nrhs, nrm2);
+}
+void launch_scale_to_f_rm(const double* in, const double* cs, float* out, int64_t n, int64_t nrhs, hipStream_t st) {
+  if (n * nrhs > 0) hipLaunchKernelGGL(scale_to_f_rm_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, cs, out, n * nrhs, nrhs);
+}
+void launch_add_scaled_f_rm(const float* in, const double* cs, double* acc, int64_t n, int64_t nrhs, hipStream_t st) {
+  if (n * nrhs > 0)
+    hipLaunchKernelGGL(add_scaled_f_rm_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, cs, acc, n * nrhs, nrhs);
+}
+
 void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
 }
@@ -810,39 +747,8 @@ void launch_fill_i(int* p, int64_t n, int v, hipStream_t st) {
 void launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(cast_d2f_kernel, dim3(grid_for(n)), dim3(256), 0, st, in, out, n);
 }
-void launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(cast_f2d_kernel, dim3(grid_for(n)), dim3(256), 0, st, in, out, n);
-}
-template <class T>
-void launch_gather_rows(const T* in, int64_t ldi, const int64_t* idx, T* out, int64_t ldo, int64_t n, int64_t nrhs,
-                        hipStream_t st) {
-  if (n * nrhs > 0)
-    hipLaunchKernelGGL(gather_rows_kernel<T>, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, ldi, idx, out, ldo, n, nrhs);
-}
-template void launch_gather_rows<double>(const double*, int64_t, const int64_t*, double*, int64_t, int64_t, int64_t, hipStream_t);
-void launch_scatter_rows(const double* in, int64_t ldi, const int64_t* idx, double* out, int64_t ldo, int64_t n,
-                         int64_t nrhs, hipStream_t st) {
-  if (n * nrhs > 0)
-    hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, ldi, idx, out, ldo, n, nrhs);
-}
-void launch_residual(const double* b, int64_t ldb, const double* y, int64_t ldy, double* r, int64_t n, int64_t nrhs,
-                     double* nrm2, hipStream_t st) {
-  if (nrhs > 0) hipLaunchKernelGGL(residual_kernel, dim3(nrhs), dim3(256), 0, st, b, ldb, y, ldy, r, n, nrm2, nrhs);
-}
-void launch_scale_to_f(const double* in, const double* cs, float* out, int64_t n, int64_t nrhs, hipStream_t st) {
-  if (n * nrhs > 0) hipLaunchKernelGGL(scale_to_f_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, cs, out, n, nrhs);
-}
-void launch_add_scaled_f(const float* in, const double* cs, double* acc, int64_t ldacc, int64_t n, int64_t nrhs,
-                         hipStream_t st) {
-  if (n * nrhs > 0)
-    hipLaunchKernelGGL(add_scaled_f_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, cs, acc, ldacc, n, nrhs);
-}
 void launch_add(const double* in, double* acc, int64_t ldacc, int64_t n, int64_t nrhs, hipStream_t st) {
   if (n * nrhs > 0) hipLaunchKernelGGL(add_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, acc, ldacc, n, nrhs);
-}
-void launch_copy_cols(const double* in, int64_t ldi, double* out, int64_t ldo, int64_t n, int64_t nrhs, hipStream_t st) {
-  if (n * nrhs > 0)
-    hipLaunchKernelGGL(copy_cols_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, ldi, out, ldo, n, nrhs);
 }
 
 }  // namespace h2

@@ -3,6 +3,7 @@
 // far part by the nested bases (upward pass, couplings, downward pass).
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <unordered_map>
 
 #include "batch.h"
@@ -110,33 +111,38 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
   const double* proj = H.d_proj.as<double>();
   const double* nodes = H.d_nodes.as<double>();
 
-  // close part: one item per leaf, one segment per near leaf
+  // Every block of right-hand sides is stored RHS-fastest (element (i, j) at
+  // i nrhs + j), and every product is formed transposed, C^T = B^T A^T: the
+  // right-hand sides are the rows of each output tile, so loads of them and
+  // stores run along contiguous memory.
+  const int N = int(nrhs);
+  // close part: one item per leaf, one segment per near leaf (kernel values
+  // generated from the points, the leaf's points along the output columns)
   std::vector<std::vector<int32_t>> nearOf(ncl);
   for (const Pair& pr : H.bt.near[0]) nearOf[pr.t].push_back(pr.s);
   const i64 f0 = tr.first_at_level(0), c0 = tr.count_at_level(0);
   for (i64 t = f0; t < f0 + c0; ++t) {
-    GemmItem& it = p.close.item(int(tr.size[t]), int(nrhs), int(tr.size[t]), int(nrhs));
-    GemmBatch::set_out(it, 0, yt + tr.start[t], n, false);
+    GemmItem& it = p.close.item(N, int(tr.size[t]), N, int(tr.size[t]));
+    GemmBatch::set_out(it, 0, yt + tr.start[t] * nrhs, nrhs, false);
     for (int32_t s : nearOf[t])
-      p.close.seg_gen(X + tr.start[t] * dim, X + tr.start[s] * dim, s == t, xt + tr.start[s], int(n),
-                      false, int(tr.size[s]));
+      p.close.seg_genB(xt + tr.start[s] * nrhs, N, false, X + tr.start[t] * dim, X + tr.start[s] * dim, s == t,
+                       int(tr.size[s]));
   }
-  // upward pass
+  // upward pass: xhat_t = R_t^T x_t at the leaves, sum of T_s^T xhat_s above
   p.up.resize(L + 1);
   for (int k = 0; k <= L; ++k) {
     const i64 f = tr.first_at_level(k), cnt = tr.count_at_level(k);
     for (i64 c = f; c < f + cnt; ++c) {
       if (!H.ff[c]) continue;
       const int r = H.rank[c];
-      GemmItem& it = p.up[k].item(r, int(nrhs), r, int(nrhs));
-      GemmBatch::set_out(it, 0, xhat + hoff[c], r, false);
+      GemmItem& it = p.up[k].item(N, r, N, r);
+      GemmBatch::set_out(it, 0, xhat + hoff[c], nrhs, false);
       if (k == 0) {
-        p.up[k].seg(basis + H.basis_off[c], int(tr.size[c]), true, xt + tr.start[c], int(n), false,
+        p.up[k].seg(xt + tr.start[c] * nrhs, N, false, basis + H.basis_off[c], int(tr.size[c]), false,
                     int(tr.size[c]));
       } else {
         for (i64 s = 2 * c + 1; s <= 2 * c + 2; ++s)
-          p.up[k].seg(transfer + H.transfer_off[s], H.rank[s], true, xhat + hoff[s], H.rank[s], false,
-                      H.rank[s]);
+          p.up[k].seg(xhat + hoff[s], N, false, transfer + H.transfer_off[s], H.rank[s], false, H.rank[s]);
       }
     }
   }
@@ -148,19 +154,18 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
     if (!H.ff[c]) continue;
     const int r = H.rank[c];
     if (!H.identity_proj) {
-      GemmItem& a = p.xproj.item(P, int(nrhs), P, int(nrhs));
-      GemmBatch::set_out(a, 0, xtil + poff[c], P, false);
-      p.xproj.seg(proj + H.proj_off[c], r, true, xhat + hoff[c], r, false, r);
+      GemmItem& a = p.xproj.item(N, P, N, P);
+      GemmBatch::set_out(a, 0, xtil + poff[c], nrhs, false);
+      p.xproj.seg(xhat + hoff[c], N, false, proj + H.proj_off[c], r, false, r);
     }
-    GemmItem& it = p.coup.item(P, int(nrhs), P, int(nrhs));
-    GemmBatch::set_out(it, 0, ytil + til_off[c], P, false);
+    GemmItem& it = p.coup.item(N, P, N, P);
+    GemmBatch::set_out(it, 0, ytil + til_off[c], nrhs, false);
     for (int32_t s : farOf[c])
-      p.coup.seg_gen(nodes + c * i64(P) * dim, nodes + s * i64(P) * dim, false, xtil + til_off[s], P,
-                     false, P);
+      p.coup.seg_genB(xtil + til_off[s], N, false, nodes + c * i64(P) * dim, nodes + s * i64(P) * dim, false, P);
     if (!H.identity_proj) {
-      GemmItem& b = p.yproj.item(r, int(nrhs), r, int(nrhs));
-      GemmBatch::set_out(b, 0, yhat + hoff[c], r, false);
-      p.yproj.seg(proj + H.proj_off[c], r, false, ytil + poff[c], P, false, P);
+      GemmItem& b = p.yproj.item(N, r, N, r);
+      GemmBatch::set_out(b, 0, yhat + hoff[c], nrhs, false);
+      p.yproj.seg(ytil + poff[c], N, false, proj + H.proj_off[c], r, true, P);
     }
   }
   // downward pass: yhat_c += T_c yhat_father (levels L-1 .. 0)
@@ -171,18 +176,18 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
     for (i64 c = f; c < f + cnt; ++c) {
       if (!H.ff[c] || !H.ff[(c - 1) / 2]) continue;
       const int r = H.rank[c], rp = H.rank[(c - 1) / 2];
-      GemmItem& it = p.down[k].item(r, int(nrhs), r, int(nrhs));
-      GemmBatch::set_out(it, 0, yhat + hoff[c], r, false);
-      p.down[k].seg(transfer + H.transfer_off[c], r, false, yhat + hoff[(c - 1) / 2], rp, false, rp);
+      GemmItem& it = p.down[k].item(N, r, N, r);
+      GemmBatch::set_out(it, 0, yhat + hoff[c], nrhs, false);
+      p.down[k].seg(yhat + hoff[(c - 1) / 2], N, false, transfer + H.transfer_off[c], r, true, rp);
     }
   }
   p.leafout.mode = GEMM_ADD;
   for (i64 t = f0; t < f0 + c0; ++t) {
     if (!H.ff[t]) continue;
     const int r = H.rank[t];
-    GemmItem& it = p.leafout.item(int(tr.size[t]), int(nrhs), int(tr.size[t]), int(nrhs));
-    GemmBatch::set_out(it, 0, yt + tr.start[t], n, false);
-    p.leafout.seg(basis + H.basis_off[t], int(tr.size[t]), false, yhat + hoff[t], r, false, r);
+    GemmItem& it = p.leafout.item(N, int(tr.size[t]), N, int(tr.size[t]));
+    GemmBatch::set_out(it, 0, yt + tr.start[t] * nrhs, nrhs, false);
+    p.leafout.seg(yhat + hoff[t], N, false, basis + H.basis_off[t], int(tr.size[t]), true, r);
   }
   std::vector<GemmBatch*> all{&p.close, &p.xproj, &p.coup, &p.yproj, &p.leafout};
   for (auto& g : p.up) all.push_back(&g);
@@ -211,18 +216,33 @@ MatvecPlan& matvec_plan(const h2_matrix& H, i64 nrhs);
 }  // namespace h2
 
 // The plan cache lives beside the handle (one plan per right-hand-side count).
+// A matrix is used by one thread at a time; the map itself is shared.
 static std::unordered_map<const h2_matrix*, std::unique_ptr<h2::MatvecPlan>> g_mv_plans;
+static std::mutex g_mv_mu;
 
 h2::MatvecPlan& h2::matvec_plan(const h2_matrix& H, i64 nrhs) {
-  auto& slot = g_mv_plans[&H];
-  if (!slot || slot->nrhs != nrhs) {
-    slot.reset();
-    slot = make_matvec_plan(const_cast<h2_matrix&>(H), nrhs);
+  std::unique_ptr<h2::MatvecPlan>* slot;
+  {
+    std::lock_guard<std::mutex> lk(g_mv_mu);
+    slot = &g_mv_plans[&H];  // node-based map: the slot stays valid
   }
-  return *slot;
+  if (!*slot || (*slot)->nrhs != nrhs) {
+    slot->reset();
+    *slot = make_matvec_plan(const_cast<h2_matrix&>(H), nrhs);
+  }
+  return **slot;
 }
 
-void h2_matrix_release_plans(const h2_matrix* H) { g_mv_plans.erase(H); }
+void h2_matrix_release_plans(const h2_matrix* H) {
+  std::unique_ptr<h2::MatvecPlan> dead;
+  {
+    std::lock_guard<std::mutex> lk(g_mv_mu);
+    auto it = g_mv_plans.find(H);
+    if (it == g_mv_plans.end()) return;
+    dead = std::move(it->second);
+    g_mv_plans.erase(it);
+  }
+}
 
 // ---------------------------------------------------------------- C ABI
 namespace h2 {
@@ -328,13 +348,13 @@ extern "C" int h2_matrix_export_tree(const h2_matrix* h, int64_t* perm, int32_t*
 extern "C" int h2_matvec(const h2_matrix* h, const double* x, double* y, int64_t nrhs, int64_t ld) {
   H2_API_BEGIN
   if (!h || !x || !y) fail(H2_EINVAL, "null argument");
-  if (nrhs < 1 || ld < h->tree.n) fail(H2_EINVAL, "bad nrhs / ld");
+  if (nrhs < 1 || nrhs > 512 || ld < h->tree.n) fail(H2_EINVAL, "bad nrhs / ld");
   const i64 n = h->tree.n;
   MatvecPlan& p = matvec_plan(*h, nrhs);
   hipStream_t st = current_stream();
-  launch_gather_rows<double>(x, ld, h->d_perm.as<i64>(), p.xt.as<double>(), n, n, nrhs, st);
+  launch_gather_rm(x, ld, h->d_perm.as<i64>(), p.xt.as<double>(), n, nrhs, st);
   run_matvec_tree(*h, p, st);
-  launch_scatter_rows(p.yt.as<double>(), n, h->d_perm.as<i64>(), y, ld, n, nrhs, st);
+  launch_scatter_rm(p.yt.as<double>(), h->d_perm.as<i64>(), y, ld, n, nrhs, st);
   HIPCHECK(hipGetLastError());
   H2_API_END
 }

@@ -7,6 +7,10 @@
 // Triangular solves by the levels of the elimination DAG: forward
 // u_i = r_i - sum_k Z_ki^T u_k, diagonal v_i = D_i^{-1} u_i, backward
 // x_i = v_i - sum_j Z_ij x_j.
+// Blocks of right-hand sides are stored RHS-fastest (element (i, j) at
+// i nrhs + j) and every product is formed transposed (C^T = B^T A^T), so that
+// the right-hand sides run along the rows of each output tile: loads of them
+// and stores are contiguous, and a block of rows is one contiguous piece.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -60,37 +64,24 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
   (void)0;
   const T* Inv = f.dInv.as<T>();
   auto son_off = [&](i64 c) -> i64 { return (c % 2 == 1) ? 0 : kp[c - 1]; };
-  auto zslot = [&](i64 c, i64* ld) -> T* {
-    if (tr.is_leaf(c)) {
-      *ld = n;
-      return zin + tr.start[c];
-    }
-    *ld = na[c];
-    return zb + zoff[c];
-  };
+  auto zslot = [&](i64 c) -> T* { return tr.is_leaf(c) ? zin + tr.start[c] * nrhs : zb + zoff[c]; };
   const int N = int(nrhs);
-  // U^T sweep: per level
+  // U^T sweep: w^T = z_t^T Q_t, columns ..k_t to the father's slot, the rest to y
   p->up.resize(L + 1);
   for (int k = 0; k <= L; ++k) {
     for (i64 c = tr.first_at_level(k); c < tr.first_at_level(k) + tr.count_at_level(k); ++c) {
       if (na[c] == 0) continue;
-      GemmItem& it = p->up[k].item(int(na[c]), N, int(kp[c]), N);
-      if (kp[c] > 0) {
-        i64 ldf;
-        T* zf = zslot((c - 1) / 2, &ldf);
-        GemmBatch::set_out(it, 0, zf + son_off(c), ldf, false);
-      }
-      if (mb[c] > 0) GemmBatch::set_out(it, 2, y + sp.soff[c], n, false);
-      i64 ldz;
-      T* zc = zslot(c, &ldz);
-      p->up[k].seg(Q + sp.q_off[c], int(na[c]), true, zc, int(ldz), false, int(na[c]));
+      GemmItem& it = p->up[k].item(N, int(na[c]), N, int(kp[c]));
+      if (kp[c] > 0) GemmBatch::set_out(it, 0, zslot((c - 1) / 2) + son_off(c) * nrhs, nrhs, false);
+      if (mb[c] > 0) GemmBatch::set_out(it, 1, y + sp.soff[c] * nrhs, nrhs, false);
+      p->up[k].seg(zslot(c), N, false, Q + sp.q_off[c], int(na[c]), false, int(na[c]));
     }
-
   }
   // forward and backward triangular solves, right-looking by DAG level: once
   // the rows of a level are final they update every row they reach; each work
   // item owns one target row and takes the level's contributions in
-  // elimination order (short chains, many items per launch)
+  // elimination order (short chains, many items per launch).  Levels are
+  // planned in parallel.
   std::vector<std::vector<i64>> fl(f.nflev), bl(f.nblev);
   for (i64 pos : f.rows) {
     fl[f.flev[pos]].push_back(pos);
@@ -105,71 +96,70 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
   struct Rec {
     i64 target, src, blk;
   };
+  auto by_target = [](const Rec& a, const Rec& b) {
+    return a.target < b.target || (a.target == b.target && a.src < b.src);
+  };
   p->fwd.resize(f.nflev);
+  p->bwd.resize(f.nblev);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int lv = 0; lv < f.nflev; ++lv) {
     std::vector<Rec> recs;
     for (i64 pk : fl[lv])
       for (i64 b = sp.rowptr[pk] + 1; b < sp.rowptr[pk + 1]; ++b) recs.push_back({sp.epos[sp.colidx[b]], pk, b});
-    std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
-      return a.target < b.target || (a.target == b.target && a.src < b.src);
-    });
+    std::sort(recs.begin(), recs.end(), by_target);
     GemmBatch& g = p->fwd[lv];
     g.mode = GEMM_SUB;
     for (size_t r = 0; r < recs.size();) {
       const i64 ci = sp.eorder[recs[r].target];
-      GemmItem& it = g.item(int(mb[ci]), N, int(mb[ci]), N);
-      GemmBatch::set_out(it, 0, y + sp.soff[ci], n, false);
+      // u_i^T -= u_k^T Z_ki  (Z_ki: m_k x m_i, ld m_k)
+      GemmItem& it = g.item(N, int(mb[ci]), N, int(mb[ci]));
+      GemmBatch::set_out(it, 0, y + sp.soff[ci] * nrhs, nrhs, false);
       for (; r < recs.size() && sp.eorder[recs[r].target] == ci; ++r) {
         const i64 ck = sp.eorder[recs[r].src];
-        g.seg(S + sp.blk_off[recs[r].blk], int(mb[ck]), true, y + sp.soff[ck], int(n), false, int(mb[ck]));
+        g.seg(y + sp.soff[ck] * nrhs, N, false, S + sp.blk_off[recs[r].blk], int(mb[ck]), false, int(mb[ck]));
       }
     }
   }
-  for (i64 pos : f.rows) {
-    const i64 c = sp.eorder[pos];
-    GemmItem& it = p->diag.item(int(mb[c]), N, int(mb[c]), N);
-    GemmBatch::set_out(it, 0, w + sp.soff[c], n, false);
-    p->diag.seg(Inv + f.inv_off[pos], int(mb[c]), true, y + sp.soff[c], int(n), false, int(mb[c]));
-  }
-  p->bwd.resize(f.nblev);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int lv = 0; lv < f.nblev; ++lv) {
     std::vector<Rec> recs;
     for (i64 pj : bl[lv])
       for (i64 b : colblk[pj]) recs.push_back({row_of[b], pj, b});
-    std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
-      return a.target < b.target || (a.target == b.target && a.src < b.src);
-    });
+    std::sort(recs.begin(), recs.end(), by_target);
     GemmBatch& g = p->bwd[lv];
     g.mode = GEMM_SUB;
     for (size_t r = 0; r < recs.size();) {
       const i64 ck = sp.eorder[recs[r].target];
-      GemmItem& it = g.item(int(mb[ck]), N, int(mb[ck]), N);
-      GemmBatch::set_out(it, 0, w + sp.soff[ck], n, false);
+      // x_k^T -= x_j^T Z_kj^T  (Z_kj: m_k x m_j, ld m_k)
+      GemmItem& it = g.item(N, int(mb[ck]), N, int(mb[ck]));
+      GemmBatch::set_out(it, 0, w + sp.soff[ck] * nrhs, nrhs, false);
       for (; r < recs.size() && sp.eorder[recs[r].target] == ck; ++r) {
         const i64 cj = sp.eorder[recs[r].src];
-        g.seg(S + sp.blk_off[recs[r].blk], int(mb[ck]), false, w + sp.soff[cj], int(n), false, int(mb[cj]));
+        g.seg(w + sp.soff[cj] * nrhs, N, false, S + sp.blk_off[recs[r].blk], int(mb[ck]), true, int(mb[cj]));
       }
     }
   }
-  // V sweep: per level from the root
+  // v_i^T = u_i^T D_i^{-1}: D_i^{-1} is symmetric (D_i is), read as stored
+  for (i64 pos : f.rows) {
+    const i64 c = sp.eorder[pos];
+    GemmItem& it = p->diag.item(N, int(mb[c]), N, int(mb[c]));
+    GemmBatch::set_out(it, 0, w + sp.soff[c] * nrhs, nrhs, false);
+    p->diag.seg(y + sp.soff[c] * nrhs, N, false, Inv + f.inv_off[pos], int(mb[c]), false, int(mb[c]));
+  }
+  // V sweep: z_t^T = [z_t^b; y_t]^T Q_t^T, per level from the root
   p->down.resize(L + 1);
   for (int k = L; k >= 0; --k) {
     for (i64 c = tr.first_at_level(k); c < tr.first_at_level(k) + tr.count_at_level(k); ++c) {
       if (na[c] == 0) continue;
-      i64 ldz;
-      T* zc = zslot(c, &ldz);
-      GemmItem& it = p->down[k].item(int(na[c]), N, int(na[c]), N);
-      GemmBatch::set_out(it, 0, zc, ldz, false);
-      if (kp[c] > 0) {
-        i64 ldf;
-        T* zf = zslot((c - 1) / 2, &ldf);
-        p->down[k].seg(Q + sp.q_off[c], int(na[c]), false, zf + son_off(c), int(ldf), false, int(kp[c]));
-      }
+      GemmItem& it = p->down[k].item(N, int(na[c]), N, int(na[c]));
+      GemmBatch::set_out(it, 0, zslot(c), nrhs, false);
+      if (kp[c] > 0)
+        p->down[k].seg(zslot((c - 1) / 2) + son_off(c) * nrhs, N, false, Q + sp.q_off[c], int(na[c]), true,
+                       int(kp[c]));
       if (mb[c] > 0)
-        p->down[k].seg(Q + sp.q_off[c] + kp[c] * na[c], int(na[c]), false, w + sp.soff[c], int(n), false,
+        p->down[k].seg(w + sp.soff[c] * nrhs, N, false, Q + sp.q_off[c] + kp[c] * na[c], int(na[c]), true,
                        int(mb[c]));
     }
-
   }
   std::vector<GemmBatch*> all;
   for (auto& g : p->up) all.push_back(&g);
@@ -204,22 +194,21 @@ SolvePlan& solve_plan(h2_factor& f, i64 nrhs) {
   return *f.solve;
 }
 
-// x_acc (original order, ld) += V (LDL^T)^{-1} U^T r, r in tree order (FP64, ld n)
-static void correction(h2_factor& f, SolvePlan& p, const double* r_tree, double* x, i64 ldx,
-                       const double* colscale_dev, hipStream_t st) {
-  h2_matrix& H = *f.sp->H;
-  const i64 n = H.tree.n, nrhs = p.nrhs;
+// acc += V (LDL^T)^{-1} U^T r: r, acc in tree order, FP64, RHS-fastest; in
+// mixed precision r is scaled column by column to unit norm for the FP32
+// application and scaled back into acc
+static void correction(h2_factor& f, SolvePlan& p, const double* r_tree, double* acc, const double* colscale_dev,
+                       hipStream_t st) {
+  const i64 n = f.sp->H->tree.n, nrhs = p.nrhs;
   if (f.sp->precision == H2_MIXED) {
-    launch_scale_to_f(r_tree, colscale_dev, p.zin.as<float>(), n, nrhs, st);
+    launch_scale_to_f_rm(r_tree, colscale_dev, p.zin.as<float>(), n, nrhs, st);
     apply_tree<float>(f, p, st);
-    launch_add_scaled_f(p.zin.as<float>(), colscale_dev, p.rs.as<double>(), n, n, nrhs, st);
+    launch_add_scaled_f_rm(p.zin.as<float>(), colscale_dev, acc, n, nrhs, st);
   } else {
-    launch_copy_cols(r_tree, n, p.zin.as<double>(), n, n, nrhs, st);
+    HIPCHECK(hipMemcpyAsync(p.zin.ptr, r_tree, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
     apply_tree<double>(f, p, st);
-    launch_add(p.zin.as<double>(), p.rs.as<double>(), n, n, nrhs, st);
+    launch_add(p.zin.as<double>(), acc, n * nrhs, n * nrhs, 1, st);
   }
-  (void)x;
-  (void)ldx;
 }
 
 }  // namespace h2
@@ -234,10 +223,10 @@ int apply_inverse_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 l
   SolvePlan& p = solve_plan(*f, nrhs);
   DeviceBuffer rt(sizeof(double) * n * nrhs), ones(sizeof(double) * nrhs);
   launch_fill(ones.as<double>(), nrhs, 1.0, st);
-  launch_gather_rows<double>(b, ld, H.d_perm.as<i64>(), rt.as<double>(), n, n, nrhs, st);
+  launch_gather_rm(b, ld, H.d_perm.as<i64>(), rt.as<double>(), n, nrhs, st);
   launch_fill(p.rs.as<double>(), n * nrhs, 0.0, st);
-  correction(*f, p, rt.as<double>(), nullptr, 0, ones.as<double>(), st);
-  launch_scatter_rows(p.rs.as<double>(), n, H.d_perm.as<i64>(), x, ld, n, nrhs, st);
+  correction(*f, p, rt.as<double>(), p.rs.as<double>(), ones.as<double>(), st);
+  launch_scatter_rm(p.rs.as<double>(), H.d_perm.as<i64>(), x, ld, n, nrhs, st);
   HIPCHECK(hipStreamSynchronize(st));
   return H2_OK;
 }
@@ -261,15 +250,15 @@ int solve_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld, const
     ev.push_back(e);
   };
   MatvecPlanView mvb = matvec_buffers(mv);
-  DeviceBuffer bt(sizeof(double) * n * nrhs), rt(sizeof(double) * n * nrhs), nrm(sizeof(double) * 2 * nrhs),
-      cs(sizeof(double) * nrhs);
-  launch_gather_rows<double>(b, ld, H.d_perm.as<i64>(), bt.as<double>(), n, n, nrhs, st);
-  launch_copy_cols(bt.as<double>(), n, rt.as<double>(), n, n, nrhs, st);
+  const size_t vec = sizeof(double) * n * nrhs;
+  DeviceBuffer bt(vec), rt(vec), nrm(sizeof(double) * 2 * nrhs), cs(sizeof(double) * nrhs),
+      part(sizeof(double) * 2 * nrhs * residual_rm_blocks(n));
+  launch_gather_rm(b, ld, H.d_perm.as<i64>(), bt.as<double>(), n, nrhs, st);
   launch_fill(p.rs.as<double>(), n * nrhs, 0.0, st);
   std::vector<double> h_nrm(2 * nrhs), h_cs(nrhs);
-  // column norms of b for the first scaling
+  // r = b (x = 0) and the column norms of b for the first scaling
   launch_fill(mvb.yt, n * nrhs, 0.0, st);
-  launch_residual(bt.as<double>(), n, mvb.yt, n, rt.as<double>(), n, nrhs, nrm.as<double>(), st);
+  launch_residual_rm(bt.as<double>(), mvb.yt, rt.as<double>(), n, nrhs, part.as<double>(), nrm.as<double>(), st);
   HIPCHECK(hipMemcpyAsync(h_nrm.data(), nrm.ptr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
   std::vector<double> bnorm(nrhs);
@@ -285,13 +274,13 @@ int solve_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld, const
     }
     HIPCHECK(hipMemcpyAsync(cs.ptr, h_cs.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
     mark();
-    correction(*f, p, rt.as<double>(), nullptr, 0, cs.as<double>(), st);
+    correction(*f, p, rt.as<double>(), p.rs.as<double>(), cs.as<double>(), st);
     mark();
     // r = b - A x  (x = p.rs in tree order)
-    launch_copy_cols(p.rs.as<double>(), n, mvb.xt, n, n, nrhs, st);
+    HIPCHECK(hipMemcpyAsync(mvb.xt, p.rs.ptr, vec, hipMemcpyDeviceToDevice, st));
     run_matvec_tree(H, mv, st);
     mark();
-    launch_residual(bt.as<double>(), n, mvb.yt, n, rt.as<double>(), n, nrhs, nrm.as<double>(), st);
+    launch_residual_rm(bt.as<double>(), mvb.yt, rt.as<double>(), n, nrhs, part.as<double>(), nrm.as<double>(), st);
     HIPCHECK(hipMemcpyAsync(h_nrm.data(), nrm.ptr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     res = 0;
@@ -301,7 +290,7 @@ int solve_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld, const
     if (res <= tol) break;
   }
   if (it > max_iter) it = max_iter;
-  launch_scatter_rows(p.rs.as<double>(), n, H.d_perm.as<i64>(), x, ld, n, nrhs, st);
+  launch_scatter_rm(p.rs.as<double>(), H.d_perm.as<i64>(), x, ld, n, nrhs, st);
   HIPCHECK(hipStreamSynchronize(st));
   double t_prec = 0, t_mv = 0;
   for (size_t e = 0; e + 2 < ev.size(); e += 3) {
