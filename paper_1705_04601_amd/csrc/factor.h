@@ -15,6 +15,7 @@ struct SolvePlan {
   std::vector<GemmBatch> up, down;       // U^T and V sweeps, per tree level
   std::vector<GemmBatch> fwd, bwd;       // triangular solves, per DAG level
   GemmBatch diag;                        // D^{-1}
+  LaunchGraph apply;                     // the whole application, captured once
 };
 
 }  // namespace h2

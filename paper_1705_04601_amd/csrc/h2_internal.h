@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -92,6 +93,28 @@ struct DeviceBuffer {
 
 // Bytes held by idle cached blocks (free for the library's own allocations).
 size_t cached_device_bytes();
+
+// A fixed sequence of kernel launches (a plan's sweep) captured once into a
+// HIP graph on a private stream and replayed on the caller's stream; the
+// sequence must only launch kernels.  H2SP_GRAPHS=0 runs it eagerly instead.
+bool graphs_enabled();
+struct LaunchGraph {
+  hipGraphExec_t exec = nullptr;
+  LaunchGraph() = default;
+  LaunchGraph(const LaunchGraph&) = delete;
+  LaunchGraph& operator=(const LaunchGraph&) = delete;
+  ~LaunchGraph();
+  void capture(const std::function<void(hipStream_t)>& record);
+  template <class F>
+  void run(hipStream_t st, F&& record) {
+    if (!graphs_enabled()) {
+      record(st);
+      return;
+    }
+    if (!exec) capture(record);
+    HIPCHECK(hipGraphLaunch(exec, st));
+  }
+};
 
 template <class T>
 DeviceBuffer upload(const std::vector<T>& v) {

@@ -73,6 +73,7 @@ struct MatvecPlan {
   GemmBatch xproj, coup, yproj;
   std::vector<GemmBatch> down;   // per level, applied from the top
   GemmBatch leafout;
+  LaunchGraph graph;             // the whole product, captured once
 };
 
 static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
@@ -202,13 +203,15 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
 
 // y_tree = A_H2 x_tree on plan buffers (x in p.xt, result in p.yt).
 void run_matvec_tree(const h2_matrix& H, MatvecPlan& p, hipStream_t st) {
-  p.close.launch<double>(st);
-  for (int k = 0; k <= H.tree.depth; ++k) p.up[k].launch<double>(st);
-  p.xproj.launch<double>(st);
-  p.coup.launch<double>(st);
-  p.yproj.launch<double>(st);
-  for (int k = H.tree.depth - 1; k >= 0; --k) p.down[k].launch<double>(st);
-  p.leafout.launch<double>(st);
+  p.graph.run(st, [&](hipStream_t s) {
+    p.close.launch<double>(s);
+    for (int k = 0; k <= H.tree.depth; ++k) p.up[k].launch<double>(s);
+    p.xproj.launch<double>(s);
+    p.coup.launch<double>(s);
+    p.yproj.launch<double>(s);
+    for (int k = H.tree.depth - 1; k >= 0; --k) p.down[k].launch<double>(s);
+    p.leafout.launch<double>(s);
+  });
 }
 
 MatvecPlan& matvec_plan(const h2_matrix& H, i64 nrhs);

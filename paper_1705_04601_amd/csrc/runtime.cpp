@@ -146,6 +146,34 @@ size_t cached_device_bytes() {
   return g_cached;
 }
 
+bool graphs_enabled() {
+  static const bool on = [] {
+    const char* v = std::getenv("H2SP_GRAPHS");
+    return !(v && v[0] == '0');
+  }();
+  return on;
+}
+
+LaunchGraph::~LaunchGraph() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+}
+
+void LaunchGraph::capture(const std::function<void(hipStream_t)>& record) {
+  hipStream_t cap = nullptr;
+  HIPCHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    record(cap);
+    e = hipStreamEndCapture(cap, &graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) exec = nullptr;
+  check_hip(e, "capturing a launch sequence");
+}
+
 DeviceBuffer::DeviceBuffer(size_t b) { reset(b); }
 
 DeviceBuffer& DeviceBuffer::operator=(DeviceBuffer&& o) noexcept {

@@ -178,11 +178,13 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
 template <class T>
 static void apply_tree(h2_factor& f, SolvePlan& p, hipStream_t st) {
   const int L = f.sp->H->tree.depth;
-  for (int k = 0; k <= L; ++k) p.up[k].launch<T>(st);
-  for (int lv = 0; lv < f.nflev; ++lv) p.fwd[lv].launch<T>(st);
-  p.diag.launch<T>(st);
-  for (int lv = 0; lv < f.nblev; ++lv) p.bwd[lv].launch<T>(st);
-  for (int k = L; k >= 0; --k) p.down[k].launch<T>(st);
+  p.apply.run(st, [&](hipStream_t s) {
+    for (int k = 0; k <= L; ++k) p.up[k].launch<T>(s);
+    for (int lv = 0; lv < f.nflev; ++lv) p.fwd[lv].launch<T>(s);
+    p.diag.launch<T>(s);
+    for (int lv = 0; lv < f.nblev; ++lv) p.bwd[lv].launch<T>(s);
+    for (int k = L; k >= 0; --k) p.down[k].launch<T>(s);
+  });
 }
 
 SolvePlan& solve_plan(h2_factor& f, i64 nrhs) {

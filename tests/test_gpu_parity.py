@@ -371,3 +371,28 @@ def test_batch_rejects_repeated_handles():
     with pytest.raises(P.H2Error) as e:
         P.h2_factor_S_batch([sp, sp])
     assert e.value.code == P.H2_EINVAL
+
+
+def test_graph_replays_match_eager(tmp_path):
+    """The captured preconditioner and matvec, replayed three times with other
+    work in between, give exactly what the eager launches give (a child
+    process with graphs off) and the oracle's results."""
+    import os
+    import subprocess
+    from graph_cases import run_sequence
+    note("graph replays vs eager")
+    got = run_sequence(P)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = tmp_path / "eager.npy"
+    env = dict(os.environ, H2SP_GRAPHS="0")
+    subprocess.run([sys.executable, os.path.join(root, "tests", "graph_child.py"), root, str(out)],
+                   env=env, check=True, timeout=300)
+    eager = np.load(out)
+    assert np.array_equal(got, eager)
+    # and against the oracle: the matvec replays are A_H2 b
+    x, sc, h2, sp, a, _ = case("cube1536")
+    rng = np.random.default_rng(21)
+    for rep in range(3):
+        b = rng.standard_normal((1536, 3))
+        want = from_tree(a @ to_tree(b, h2.tree.perm), h2.tree.perm)
+        assert np.abs(got[2 * rep + 1] - want).max() <= 1e-10 * np.abs(want).max()
