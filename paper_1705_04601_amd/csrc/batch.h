@@ -124,8 +124,8 @@ struct GemmBatch {
     it.seg_end = int32_t(segs.size());
     flops += 2.0 * it.M * double(it.N) * s.K;
   }
-  // Tile list: one 64 x 64 tile per work-group.  Items without segments are
-  // kept only when they store (they then write zeros).
+  // Tile list: one tile per work-group.  Items without segments are kept
+  // only when they store (they then write zeros).
   void build_tiles() {
     tiles.clear();
     amode = bmode = -1;
@@ -142,11 +142,14 @@ struct GemmBatch {
     if (amode >= 0 && !gemm_layout_supported(role, amode, bmode))
       fail(H2_EINVAL, "internal: no GEMM kernel for this role and operand layout");
     if (items.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "GEMM batch above 2^24 items");
+    // tile of the kernel that runs the batch: 128 x 32 for a generated B
+    // (right-hand sides along M), 64 x 64 otherwise
+    const int em = bmode == 2 ? 128 : 64, en = bmode == 2 ? 32 : 64;
     for (size_t i = 0; i < items.size(); ++i) {
       const GemmItem& it = items[i];
       if (it.seg_end == it.seg_begin && mode != GEMM_STORE) continue;
-      constexpr int edge = 64;  // tile edge of the kernel
-      const int tm = (it.M + edge - 1) / edge, tn = (it.N + edge - 1) / edge;
+      const int tm = (it.M + em - 1) / em, tn = (it.N + en - 1) / en;
+      if (tm > 16 || tn > 16) fail(H2_EUNSUPPORTED, "GEMM item above 16 tiles along an edge");
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b) tiles.push_back(int32_t((uint32_t(i) << 8) | (a << 4) | b));
     }
