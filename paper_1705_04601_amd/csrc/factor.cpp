@@ -111,7 +111,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     zmax = std::max(zmax, z);
   }
   if (zmax >= (i64(1) << 31)) fail(H2_EUNSUPPORTED, "factor level too wide for 32-bit Z offsets");
-  f.dZ.reset(sizeof(T) * (zmax + kOverread));
+  f.dZ.reset(sizeof(T) * zmax);
   T* Z = f.dZ.as<T>();
   // partial sums of split targets (at most pcap elements per level)
   f.pcap = std::min<i64>(i64(1) << 25, std::max<i64>(sp.s_entries, 1));
@@ -462,7 +462,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         L.zb.template launch<T>(st);
         mark_ev();
         L.nschur_tiles = int32_t(L.stiles.size());
-        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf, S + sp.s_entries};
+        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf};
         launch_schur<T>(sl, st);
         mark_ev();
         launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
@@ -597,7 +597,7 @@ static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
   size_t free_b = 0, total_b = 0;
   HIPCHECK(hipMemGetInfo(&free_b, &total_b));
   free_b += cached_device_bytes();
-  const double budget = std::max(1.0, 0.9 * double(free_b) / double(sizeof(T)) - double(kOverread));
+  const double budget = std::max(1.0, 0.9 * double(free_b) / double(sizeof(T)));
   std::vector<std::vector<i64>> R = symbolic_fill(sp, budget, double(sizeof(T)), nullptr, nullptr);
   std::vector<i64> rowptr(ncl + 1, 0), colidx, blk_off;
   i64 ent = 0;
@@ -632,9 +632,9 @@ static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
       cps.push_back({blk_off[nb], sp.blk_off[b], int32_t(mi), int32_t(mb[cj]), int32_t(mi), 0});
     }
   }
-  DeviceBuffer nS(el * size_t(ent + kOverread));
-  if constexpr (std::is_same<T, float>::value) launch_fill_f(nS.as<float>(), ent + kOverread, 0.0f, st);
-  else launch_fill(nS.as<double>(), ent + kOverread, 0.0, st);
+  DeviceBuffer nS(el * size_t(std::max<i64>(ent, 1)));
+  if constexpr (std::is_same<T, float>::value) launch_fill_f(nS.as<float>(), ent, 0.0f, st);
+  else launch_fill(nS.as<double>(), ent, 0.0, st);
   DeviceBuffer dcps(sizeof(CopySeg) * std::max<size_t>(cps.size(), 1));
   HIPCHECK(hipMemcpyAsync(dcps.ptr, cps.data(), sizeof(CopySeg) * cps.size(), hipMemcpyHostToDevice, st));
   launch_copy_segments<T>(dcps.as<CopySeg>(), int(cps.size()), sp.dS.as<T>(), nS.as<T>(), st);

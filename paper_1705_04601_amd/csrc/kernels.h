@@ -72,11 +72,8 @@ bool gemm_layout_supported(int role, int amode, int bmode);
 // A target with a long K is split into parts: part 0 subtracts its sum from S
 // directly, every further part stores its sum (M x N, ld M) in the partial
 // buffer and a reduction item subtracts those sums, in a fixed order.
-// Spare elements allocated past the end of S and of the Z buffer.  The Schur
-// kernel's operand loads are 4 elements wide and unconditional, so they may
-// run past a block's end; the spare elements of S are kept zero and also serve
-// as the zeros read past an item's last chunk.
-constexpr int64_t kOverread = 64;
+// The kernel reads every operand through a buffer resource of the block's own
+// size, so it reads nothing outside the blocks the descriptors name.
 struct SchurItem {
   int64_t out_off;   // into S (partial == 0) or the partial buffer (partial == 1)
   int32_t M, N, seg_begin, seg_end;
@@ -98,7 +95,6 @@ struct SchurLaunch {
   void* S;
   const void* Z;
   void* P;               // partial buffer
-  const void* zeros;     // 4 or more zero elements (read past an item's last chunk)
 };
 template <class T>
 void launch_schur(const SchurLaunch& g, hipStream_t st);

@@ -17,10 +17,18 @@
 
 namespace h2 {
 
-namespace {
-
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// Raw buffer loads, declared as the LLVM intrinsics they are (the clang
+// builtin of the 128-bit form returns a single dword with this compiler).
+__device__ f4 raw_buffer_load_f4(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux) __asm(
+    "llvm.amdgcn.raw.ptr.buffer.load.v4f32");
+__device__ d2 raw_buffer_load_d2(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux) __asm(
+    "llvm.amdgcn.raw.ptr.buffer.load.v2f64");
+
+namespace {
 
 template <class T> struct Mfma;
 // Output layout of the 16x16x4 instructions (lane l, accumulator element v):
@@ -235,46 +243,137 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
 }
 
 // Schur update of the block factorisation with compact descriptors:
-// S[out] (M x N, ld M) -= sum_seg Z[a]^T (K x M, ld K) S[b] (K x N, ld K).
-// One wave per 64 x 64 tile.  The (segment, 16-wide k step) pairs form one
-// chunk stream, consumed with two register sets in ping-pong: the loads of
-// chunk c + 1 are in flight while the MFMAs of chunk c issue.  The number of
-// 16 x 16 blocks of the tile (NBM x NBN) is a template parameter and every
-// load is issued unconditionally, so the count of loads in flight is static
-// and the compiler waits only for the older set.  Z_ki is stored with its K
-// rounded up to 16 and zero rows below K, so a chunk may run past the end of
-// a segment: the extra k multiply zeros of Z by finite entries of S (the
-// over-read stays inside S, which is allocated with kOverread zeroed spare
-// elements at its end).
-template <class T, int NBM, int NBN>
-__device__ __forceinline__ void schur_fetch(const T* S, const T* Z, const SchurSeg& sg, int k0, bool valid,
-                                            const T* zeros, int m0, int n0, int M, int N, int r, int kq,
-                                            T (&a)[4][4], T (&b)[4][4]) {
-  // no arithmetic on the loaded values (it would make the wave wait for them
-  // at once): rows past the tile read a valid row and land in discarded
-  // outputs; k past the segment meets the zero rows of the padded Z_ki; a
-  // chunk past the item's end reads zeros
-  const int k = k0 + kq, lda = (sg.K + 15) & ~15;
+// S[out] (M x N, ld M) -= sum_seg Z[a]^T (K x M, ld K16) S[b] (K x N, ld K),
+// K16 = K rounded up to 16.  One wave per 64 x 64 tile.  The (segment,
+// 16-wide k step) pairs form one chunk stream, consumed through a ring of NS
+// register sets: the loads of NS - 1 chunks are in flight while the MFMAs of
+// the oldest issue.  The number of 16 x 16 blocks of the tile (NBM x NBN) is a
+// template parameter and every load is issued unconditionally, so the count
+// of loads in flight is static and the compiler waits only for the oldest set.
+//
+// Operands are read with buffer loads: per segment, one resource (base and
+// size in bytes) for the Z_ki block and one for the S_kj block, and one 32-bit
+// offset per lane and 16 x 16 block that stays fixed for the whole segment; a
+// chunk only moves the two bases on by 16 k.  Reads outside a resource return
+// zero, which covers rows past M and columns past N, and a chunk past the
+// item's last segment (a resource of size zero).  Inside a segment, k past K
+// meets the zero rows of the padded Z_ki; the S_kj operand then reads the
+// next column of the block, or zero past the block's end.
+// Segment descriptors are loaded 64 at a time, one per lane, and taken out
+// with readlane, so that moving to the next segment waits for no memory.
+constexpr int kRsrcFlags = 0x00020000;  // raw 32-bit buffer, no swizzle (gfx9 family)
+
+// The base and the size are wave-uniform; readfirstlane keeps them in SGPRs
+// (a resource in VGPRs would make the compiler loop over the lanes).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a))));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a >> 32))));
+  const int n = __builtin_amdgcn_readfirstlane(int(bytes));
+  void* q = reinterpret_cast<void*>((uint64_t(hi) << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, 0, n, kRsrcFlags);
+}
+
+template <class T> struct BufLoad4;
+template <> struct BufLoad4<float> {
+  static __device__ __forceinline__ void run(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&v)[4]) {
+    const f4 x = raw_buffer_load_f4(rs, int(off), 0, 0);
 #pragma unroll
-  for (int q = 0; q < NBM; ++q) {
-    const int row = m0 + 16 * q + r;
-    const T* p = valid ? Z + sg.a_off + int64_t(row < M ? row : 0) * lda + k : zeros;
-    const typename Vec4<T>::type x = *reinterpret_cast<const typename Vec4<T>::type*>(p);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) a[q][s] = x[s];
+    for (int s = 0; s < 4; ++s) v[s] = x[s];
   }
+};
+template <> struct BufLoad4<double> {
+  static __device__ __forceinline__ void run(__amdgpu_buffer_rsrc_t rs, uint32_t off, double (&v)[4]) {
+    const d2 x = raw_buffer_load_d2(rs, int(off), 0, 0);
+    const d2 y = raw_buffer_load_d2(rs, int(off + 16), 0, 0);
+    v[0] = x[0];
+    v[1] = x[1];
+    v[2] = y[0];
+    v[3] = y[1];
+  }
+};
+
+// Chunk cursor of a tile (wave-uniform apart from the lane offsets and the
+// lane-held descriptors).
+template <class T, int NBM, int NBN>
+struct SchurCursor {
+  int si, se, k0, K;
+  bool valid;           // false past the item's last segment (and stays false)
+  int dbase;            // lane l holds the descriptor of segment dbase + l
+  uint32_t d[4];
+  const T* pa;          // Z_ki and S_kj of the current segment
+  const T* pb;
+  uint32_t na, nb;      // their sizes in bytes
+  uint32_t oa[NBM], ob[NBN];
+};
+
+template <class T, int NBM, int NBN>
+__device__ __forceinline__ void schur_load_desc(SchurCursor<T, NBM, NBN>& c, const SchurSeg* segs, int lane) {
+  const int i = c.dbase + lane < c.se ? c.dbase + lane : c.se - 1;
+  const uint4 x = *reinterpret_cast<const uint4*>(segs + i);
+  c.d[0] = x.x;
+  c.d[1] = x.y;
+  c.d[2] = x.z;
+  c.d[3] = x.w;
+}
+
+template <class T, int NBM, int NBN>
+__device__ __forceinline__ void schur_setup(SchurCursor<T, NBM, NBN>& c, const T* S, const T* Z, int m0, int n0,
+                                            int M, int N, int r, int kq) {
+  static_assert(sizeof(SchurSeg) == 16, "descriptor of four 32-bit words");
+  const int idx = c.si - c.dbase;
+  const uint64_t b_off = (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(c.d[1]), idx))) << 32) |
+                         uint32_t(__builtin_amdgcn_readlane(int(c.d[0]), idx));
+  const int a_off = __builtin_amdgcn_readlane(int(c.d[2]), idx);
+  const int K = __builtin_amdgcn_readlane(int(c.d[3]), idx);
+  const int lda = (K + 15) & ~15;
+  c.K = K;
+  c.pa = Z + a_off;
+  c.pb = S + int64_t(b_off);
+  c.na = uint32_t(lda * M) * uint32_t(sizeof(T));
+  c.nb = uint32_t(K * N) * uint32_t(sizeof(T));
 #pragma unroll
-  for (int q = 0; q < NBN; ++q) {
-    const int col = n0 + 16 * q + r;
-    const T* p = valid ? S + sg.b_off + int64_t(col < N ? col : 0) * sg.K + k : zeros;
-    const typename Vec4<T>::type x = *reinterpret_cast<const typename Vec4<T>::type*>(p);
+  for (int q = 0; q < NBM; ++q) c.oa[q] = uint32_t((m0 + 16 * q + r) * lda + kq) * uint32_t(sizeof(T));
 #pragma unroll
-    for (int s = 0; s < 4; ++s) b[q][s] = x[s];
+  for (int q = 0; q < NBN; ++q) c.ob[q] = uint32_t((n0 + 16 * q + r) * K + kq) * uint32_t(sizeof(T));
+}
+
+template <class T, int NBM, int NBN>
+__device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const SchurSeg* segs, const T* S,
+                                           const T* Z, int m0, int n0, int M, int N, int r, int kq, int lane) {
+  if (!c.valid) return;
+  c.k0 += 16;
+  if (c.k0 < c.K) return;
+  c.k0 = 0;
+  if (++c.si >= c.se) {
+    c.valid = false;
+    return;
+  }
+  // the descriptor reload waits for every load in flight: a path of its own,
+  // so that the common one does not inherit the wait
+  if (c.si - c.dbase >= 64) {
+    c.dbase += 64;
+    schur_load_desc(c, segs, lane);
+    schur_setup(c, S, Z, m0, n0, M, N, r, kq);
+  } else {
+    schur_setup(c, S, Z, m0, n0, M, N, r, kq);
   }
 }
 
 template <class T, int NBM, int NBN>
-__device__ __forceinline__ void schur_mfma(typename Mfma<T>::V (&acc)[4][4], const T (&a)[4][4], const T (&b)[4][4]) {
+__device__ __forceinline__ void schur_fetch(const SchurCursor<T, NBM, NBN>& c, T (&a)[NBM][4], T (&b)[NBN][4]) {
+  const uint32_t sh = uint32_t(c.k0) * uint32_t(sizeof(T));  // k0 < K <= K16: both sizes stay positive
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.pa + c.k0, c.valid ? c.na - sh : 0u);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.pb + c.k0, c.valid ? c.nb - sh : 0u);
+#pragma unroll
+  for (int q = 0; q < NBM; ++q) BufLoad4<T>::run(ra, c.oa[q], a[q]);
+#pragma unroll
+  for (int q = 0; q < NBN; ++q) BufLoad4<T>::run(rb, c.ob[q], b[q]);
+}
+
+template <class T, int NBM, int NBN>
+__device__ __forceinline__ void schur_mfma(typename Mfma<T>::V (&acc)[NBM][NBN], const T (&a)[NBM][4],
+                                           const T (&b)[NBN][4]) {
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -283,56 +382,47 @@ __device__ __forceinline__ void schur_mfma(typename Mfma<T>::V (&acc)[4][4], con
       for (int bn = 0; bn < NBN; ++bn) acc[bm][bn] = Mfma<T>::run(b[bn][s], a[bm][s], acc[bm][bn]);
 }
 
-// Chunk cursor: segment index, first k of the chunk, the segment; valid is
-// false past the item's last segment (and stays false).
-struct SchurCursor {
-  int si, k0;
-  bool valid;
-  SchurSeg sg;
-};
-
-__device__ __forceinline__ SchurCursor schur_next(const SchurSeg* segs, int seg_end, SchurCursor c) {
-  if (!c.valid) return c;
-  c.k0 += 16;
-  if (c.k0 < c.sg.K) return c;
-  ++c.si;
-  c.k0 = 0;
-  if (c.si >= seg_end) {
-    c.valid = false;
-    return c;
-  }
-  c.sg = segs[c.si];
-  return c;
-}
-
-template <class T, int NBM, int NBN>
+template <class T, int NBM, int NBN, int NS>
 __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem& it, int m0, int n0, int lane) {
   using V = typename Mfma<T>::V;
   const int r = lane % 16, kq = 4 * (lane / 16);
   T* S = static_cast<T*>(g.S);
   const T* Z = static_cast<const T*>(g.Z);
-  const T* zeros = static_cast<const T*>(g.zeros);
-  V acc[4][4];
+  V acc[NBM][NBN];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NBM; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = V{0, 0, 0, 0};
+    for (int b = 0; b < NBN; ++b) acc[a][b] = V{0, 0, 0, 0};
   if (it.seg_begin < it.seg_end) {
-    T a0[4][4], b0[4][4], a1[4][4], b1[4][4];
-    SchurCursor c{it.seg_begin, 0, true, g.segs[it.seg_begin]};
-    schur_fetch<T, NBM, NBN>(S, Z, c.sg, c.k0, true, zeros, m0, n0, it.M, it.N, r, kq, a0, b0);
-    // two chunks per pass, one exit: the second chunk of the last pass may
-    // be past the end and then contributes zeros
-    while (true) {
-      const SchurCursor c1 = schur_next(g.segs, it.seg_end, c);
-      schur_fetch<T, NBM, NBN>(S, Z, c1.sg, c1.k0, c1.valid, zeros, m0, n0, it.M, it.N, r, kq, a1, b1);
-      schur_mfma<T, NBM, NBN>(acc, a0, b0);
-      const SchurCursor c2 = schur_next(g.segs, it.seg_end, c1);
-      schur_fetch<T, NBM, NBN>(S, Z, c2.sg, c2.k0, c2.valid, zeros, m0, n0, it.M, it.N, r, kq, a0, b0);
-      schur_mfma<T, NBM, NBN>(acc, a1, b1);
-      if (!c2.valid) break;
-      c = c2;
+    SchurCursor<T, NBM, NBN> c;
+    c.si = c.dbase = it.seg_begin;
+    c.se = it.seg_end;
+    c.k0 = 0;
+    c.valid = true;
+    schur_load_desc(c, g.segs, lane);
+    schur_setup(c, S, Z, m0, n0, it.M, it.N, r, kq);
+    T a[NS][NBM][4], b[NS][NBN][4];
+    schur_fetch(c, a[0], b[0]);
+#pragma unroll
+    for (int i = 1; i < NS - 1; ++i) {
+      schur_next(c, g.segs, S, Z, m0, n0, it.M, it.N, r, kq, lane);
+      schur_fetch(c, a[i], b[i]);
     }
+    // one exit per NS chunks; chunks past the end read zeros
+    while (true) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        schur_next(c, g.segs, S, Z, m0, n0, it.M, it.N, r, kq, lane);
+        schur_fetch(c, a[(i + NS - 1) % NS], b[(i + NS - 1) % NS]);
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
+        schur_mfma<T, NBM, NBN>(acc, a[i], b[i]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (!c.valid) break;
+    }
+    // sets 0 .. NS - 2 hold chunks fetched but not yet multiplied
+#pragma unroll
+    for (int i = 0; i < NS - 1; ++i) schur_mfma<T, NBM, NBN>(acc, a[i], b[i]);
   }
   const bool part = it.partial != 0;
   T* out = (part ? static_cast<T*>(g.P) : S) + it.out_off;
@@ -352,8 +442,11 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
       }
 }
 
+// three register sets in FP32 (the occupancy of two waves per SIMD is set by
+// the accumulators either way), two in FP64
 template <class T>
 __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
+  constexpr int NS = sizeof(T) == 4 ? 3 : 2;
   const int lane = threadIdx.x;
   const uint32_t code = static_cast<uint32_t>(g.tiles[xcd_tile(blockIdx.x, gridDim.x)]);
   const SchurItem it = g.items[code >> 8];
@@ -361,7 +454,7 @@ __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
   const int nbm = min(4, (it.M - m0 + 15) / 16), nbn = min(4, (it.N - n0 + 15) / 16);
   switch (nbm * 4 + nbn) {
 #define H2_SCHUR_CASE(I, J) \
-  case I * 4 + J: schur_tile<T, I, J>(g, it, m0, n0, lane); break;
+  case I * 4 + J: schur_tile<T, I, J, NS>(g, it, m0, n0, lane); break;
     H2_SCHUR_CASE(1, 1) H2_SCHUR_CASE(1, 2) H2_SCHUR_CASE(1, 3) H2_SCHUR_CASE(1, 4)
     H2_SCHUR_CASE(2, 1) H2_SCHUR_CASE(2, 2) H2_SCHUR_CASE(2, 3) H2_SCHUR_CASE(2, 4)
     H2_SCHUR_CASE(3, 1) H2_SCHUR_CASE(3, 2) H2_SCHUR_CASE(3, 3) H2_SCHUR_CASE(3, 4)

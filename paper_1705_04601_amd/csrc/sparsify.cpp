@@ -213,11 +213,7 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
     sp.dQt.reset(4 * std::max<i64>(qs, 1));
     sp.dWt.reset(4 * std::max<i64>(H->identity_proj ? rs : ws, 1));
   }
-  sp.dS.reset(el * (std::max<i64>(ent, 1) + kOverread));
-  // the spare elements past the end of S are read (and multiplied by zeros)
-  // by the Schur kernel: keep them finite
-  if (mixed) launch_fill_f(sp.dS.as<float>() + ent, kOverread, 0.0f, current_stream());
-  else launch_fill(sp.dS.as<double>() + ent, kOverread, 0.0, current_stream());
+  sp.dS.reset(el * std::max<i64>(ent, 1));
   i64 cmax[2] = {1, 1}, gmax[2] = {1, 1};
   for (int k = 0; k <= L + 1; ++k) {
     cmax[k % 2] = std::max(cmax[k % 2], csize[k]);
