@@ -59,6 +59,9 @@ struct FactorLevel {
   GemmBatch zb;
   i64 zlen = 0;  // extent of the level's Z_ki blocks in the Z buffer
   int32_t nschur_tiles = 0;
+  double schur_flops = 0;
+  double xcd_imbalance = 1;  // largest over mean work of the XCDs' tile ranges (traced)
+  double col_share = 1, piv_share = 1;  // targets per distinct column, pivots per distinct pivot row (traced)
 };
 
 // Output of one chunk of rows of a level (concatenated in row order).
@@ -350,6 +353,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       nitems += c.items.size();
       nsegs += c.segs.size();
       fl_s += c.flops;
+      L.schur_flops += c.flops;
       st_pairs += c.dense_pairs;
     }
     st_segs += double(nsegs);
@@ -382,6 +386,37 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     }
     split_targets(items, L);
     if (L.sitems.size() >= (size_t(1) << 24)) too_wide = 1;
+    if (trace_level() >= 2 && !L.stiles.empty()) {
+      // the kernel gives XCD x the x-th contiguous eighth of the tile list
+      const i64 n = i64(L.stiles.size()), base = n / 8, rem = n % 8;
+      double w[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tot = 0;
+      for (int x = 0; x < 8; ++x)
+        for (i64 t = x * base + std::min<i64>(x, rem); t < (x + 1) * base + std::min<i64>(x + 1, rem); ++t) {
+          const uint32_t code = uint32_t(L.stiles[t]);
+          const SchurItem& it = L.sitems[code >> 8];
+          const int m0 = int((code >> 4) & 15) * edge, n0 = int(code & 15) * edge;
+          const double tm = std::min(edge, (it.M - m0 + 15) / 16 * 16), tn = std::min(edge, (it.N - n0 + 15) / 16 * 16);
+          w[x] += tm * tn * it.ksum;
+          tot += tm * tn * it.ksum;
+        }
+      L.xcd_imbalance = *std::max_element(w, w + 8) / std::max(1e-30, tot / 8);
+    }
+    if (trace_level() >= 2) {
+      std::vector<char> seen_j(ncl, 0), seen_k(ncl, 0);
+      double nt = 0, nj = 0, np = 0, nk = 0;
+      for (i64 pi : rows) {
+        for (i64 b = sp.rowptr[pi]; b < sp.rowptr[pi + 1]; ++b) {
+          ++nt;
+          if (!seen_j[sp.colidx[b]]) seen_j[sp.colidx[b]] = 1, ++nj;
+        }
+        for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+          ++np;
+          if (!seen_k[ck_pos[c]]) seen_k[ck_pos[c]] = 1, ++nk;
+        }
+      }
+      L.col_share = nt / std::max(1.0, nj);
+      L.piv_share = np / std::max(1.0, nk);
+    }
   };
   // plans the levels in order, each in parallel
   auto plan_all = [&]() {
@@ -516,6 +551,13 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     HIPCHECK(hipEventElapsedTime(&c, ev[3 * lv + 2], ev[3 * lv + 3]));
     piv_ms += a + c;
     schur_ms += b;
+    if (trace_level() >= 2)
+      std::fprintf(stderr,
+                   "[h2sp] factor level %d: %zu rows, %d Schur tiles, %.4g GFLOP, %.3f ms (%.1f TF), XCD imbalance %.3f, "
+                   "rows per target column %.2f, rows per pivot %.2f; pivots and Z %.3f ms\n",
+                   lv, by_level[lv].size(), lvls[lv].nschur_tiles, lvls[lv].schur_flops / 1e9, b,
+                   lvls[lv].schur_flops / std::max(1e-6, double(b)) / 1e9, lvls[lv].xcd_imbalance, lvls[lv].col_share,
+                   lvls[lv].piv_share, a + c);
   }
   float tot = 0;
   HIPCHECK(hipEventElapsedTime(&tot, ev.front(), ev.back()));

@@ -34,7 +34,8 @@ struct TraceTimer {
   void lap(const char* what);
   ~TraceTimer();
 };
-bool trace_enabled();
+bool trace_enabled();  // H2SP_TRACE >= 1: phase timings and statistics on stderr
+int trace_level();     // H2SP_TRACE >= 2 adds per-level lines
 
 // ---------------------------------------------------------------- cluster tree
 // Heap numbering: root 0, sons of c are 2c+1 and 2c+2; every leaf at depth L.

@@ -1,4 +1,5 @@
 // Runtime pieces shared by every entry point: errors, stream, device memory.
+#include <algorithm>
 #include <chrono>
 #include <iterator>
 #include <map>
@@ -21,13 +22,14 @@ void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 static double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
-bool trace_enabled() {
-  static const bool on = [] {
+int trace_level() {
+  static const int lv = [] {
     const char* v = std::getenv("H2SP_TRACE");
-    return v && v[0] && v[0] != '0';
+    return v ? std::max(0, std::atoi(v)) : 0;
   }();
-  return on;
+  return lv;
 }
+bool trace_enabled() { return trace_level() > 0; }
 TraceTimer::TraceTimer(const char* n) : name(n), t0(now_ms()) {}
 void TraceTimer::lap(const char* what) {
   const double t = now_ms();
