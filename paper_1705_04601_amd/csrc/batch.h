@@ -2,9 +2,11 @@
 #pragma once
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -218,10 +220,23 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
                            const std::vector<RawBlob>& extra = {}, hipStream_t copy = nullptr,
                            hipStream_t wait = nullptr, bool parallel_pack = true) {
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  {
+    int code = 0;
+    std::string msg;
+#pragma omp parallel for schedule(dynamic, 4) if (parallel_pack)
+    for (long i = 0; i < long(bs.size()); ++i) {
+      try {
+        bs[i]->build_tiles();
+      } catch (const Error& e) {
+#pragma omp critical(h2_upload_error)
+        if (!code) code = e.code, msg = e.msg;
+      }
+    }
+    if (code) fail(code, msg);
+  }
   size_t total = 0;
   std::vector<size_t> off(bs.size() * 3);
   for (size_t i = 0; i < bs.size(); ++i) {
-    bs[i]->build_tiles();
     off[3 * i] = total;
     total = align(total + bs[i]->items.size() * sizeof(GemmItem));
     off[3 * i + 1] = total;
@@ -235,8 +250,17 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
     total = align(total + extra[i].bytes);
   }
   if (total == 0) return;
-  std::unique_ptr<char[]> staging_buf(new char[total]);  // no zero fill
-  char* staging = staging_buf.get();
+  if (trace_level() >= 2) std::fprintf(stderr, "[h2sp] upload: %zu GEMM batches, %.1f MB\n", bs.size(), total / 1e6);
+  // page-locked staging, returned to the pool once the copy has completed
+  struct Staging {
+    PinnedBlock b;
+    hipStream_t used = nullptr;  // stream of the copy out of it (drained before reuse)
+    ~Staging() {
+      if (used) (void)hipStreamSynchronize(used);
+      pinned_release(b);
+    }
+  } stage{pinned_acquire(total)};
+  char* staging = stage.b.ptr;
 #pragma omp parallel for schedule(dynamic, 16) if (parallel_pack)
   for (long i = 0; i < long(bs.size()); ++i) {
     GemmBatch& b = *bs[i];
@@ -258,6 +282,7 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
   }
   store.reset(total, copy);
   if (copy) {
+    stage.used = copy;
     HIPCHECK(hipMemcpyAsync(store.ptr, staging, total, hipMemcpyHostToDevice, copy));
     hipEvent_t done;
     HIPCHECK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
@@ -267,11 +292,13 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
     HIPCHECK(hipEventDestroy(done));
   } else {
     // on the current stream: a reused block may wait there for its last user
+    stage.used = current_stream();
     HIPCHECK(hipMemcpyAsync(store.ptr, staging, total, hipMemcpyHostToDevice, current_stream()));
     HIPCHECK(hipStreamSynchronize(current_stream()));  // the staging buffer is released below
   }
   char* base = static_cast<char*>(store.ptr);
-  for (size_t i = 0; i < bs.size(); ++i) {
+#pragma omp parallel for schedule(dynamic, 16) if (parallel_pack)
+  for (long i = 0; i < long(bs.size()); ++i) {
     bs[i]->d_items = reinterpret_cast<const GemmItem*>(base + off[3 * i]);
     bs[i]->d_segs = reinterpret_cast<const GemmSeg*>(base + off[3 * i + 1]);
     bs[i]->d_tiles = reinterpret_cast<const int32_t*>(base + off[3 * i + 2]);

@@ -95,6 +95,16 @@ struct DeviceBuffer {
 // Bytes held by idle cached blocks (free for the library's own allocations).
 size_t cached_device_bytes();
 
+// Page-locked host staging memory for uploads (hipHostMalloc), kept in a pool
+// for reuse: a copy from it runs at the link's speed and without the
+// runtime's own staging.  The block is the caller's until released.
+struct PinnedBlock {
+  char* ptr = nullptr;
+  size_t cap = 0;
+};
+PinnedBlock pinned_acquire(size_t bytes);
+void pinned_release(PinnedBlock b);
+
 // A fixed sequence of kernel launches (a plan's sweep) captured once into a
 // HIP graph on a private stream and replayed on the caller's stream; the
 // sequence must only launch kernels.  H2SP_GRAPHS=0 runs it eagerly instead.

@@ -148,6 +148,50 @@ size_t cached_device_bytes() {
   return g_cached;
 }
 
+// ---------------------------------------------------------------- pinned pool
+namespace {
+std::mutex g_pin_mu;
+std::multimap<size_t, char*> g_pin_free;  // idle blocks by capacity
+size_t g_pin_idle = 0;
+constexpr size_t kPinIdleLimit = size_t(8) << 30;  // idle pinned bytes kept
+}  // namespace
+
+PinnedBlock pinned_acquire(size_t bytes) {
+  bytes = std::max<size_t>(bytes, 1);
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto it = g_pin_free.lower_bound(bytes);
+    if (it != g_pin_free.end() && it->first <= 2 * bytes + (size_t(64) << 20)) {
+      PinnedBlock b{it->second, it->first};
+      g_pin_idle -= it->first;
+      g_pin_free.erase(it);
+      return b;
+    }
+  }
+  // a quarter more than asked, so that a slightly larger plan reuses it
+  const size_t cap = ((bytes + bytes / 4) + 4095) & ~size_t(4095);
+  void* p = nullptr;
+  HIPCHECK(hipHostMalloc(&p, cap, hipHostMallocDefault));
+  return PinnedBlock{static_cast<char*>(p), cap};
+}
+
+void pinned_release(PinnedBlock b) {
+  if (!b.ptr) return;
+  std::vector<char*> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_free.emplace(b.cap, b.ptr);
+    g_pin_idle += b.cap;
+    while (g_pin_idle > kPinIdleLimit && !g_pin_free.empty()) {  // largest first
+      auto it = std::prev(g_pin_free.end());
+      g_pin_idle -= it->first;
+      drop.push_back(it->second);
+      g_pin_free.erase(it);
+    }
+  }
+  for (char* p : drop) (void)hipHostFree(p);
+}
+
 bool graphs_enabled() {
   static const bool on = [] {
     const char* v = std::getenv("H2SP_GRAPHS");

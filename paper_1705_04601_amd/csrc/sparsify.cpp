@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <parallel/algorithm>
 
 #include "sparse.h"
 
@@ -29,6 +30,66 @@ namespace {
 constexpr i64 kTmpChunkEntries = i64(1) << 26;  // GEMM temporaries per chunk
 
 inline i64 key(i64 a, i64 b, i64 ncl) { return a * ncl + b; }
+
+// Slot table of one level: open addressing with linear probing over
+// non-negative keys, power-of-two capacity, no deletion.  (A node-based map
+// of a few million entries costs more to fill, probe and free than the whole
+// sweep's planning otherwise.)
+class SlotMap {
+ public:
+  void reserve(size_t n) {
+    size_t cap = 16;
+    while (cap < 2 * n) cap <<= 1;
+    if (cap > keys_.size()) rehash(cap);
+  }
+  // inserts (k, v) unless k is present; returns whether it inserted
+  bool insert(i64 k, i64 v) {
+    if (2 * (size_ + 1) > keys_.size()) rehash(std::max<size_t>(16, 2 * keys_.size()));
+    size_t h = hash(k) & (keys_.size() - 1);
+    while (keys_[h] >= 0) {
+      if (keys_[h] == k) return false;
+      h = (h + 1) & (keys_.size() - 1);
+    }
+    keys_[h] = k;
+    vals_[h] = v;
+    ++size_;
+    return true;
+  }
+  i64 at(i64 k) const {
+    if (!keys_.empty()) {
+      size_t h = hash(k) & (keys_.size() - 1);
+      while (keys_[h] >= 0) {
+        if (keys_[h] == k) return vals_[h];
+        h = (h + 1) & (keys_.size() - 1);
+      }
+    }
+    fail(H2_EINVAL, "internal: missing slot");
+  }
+
+ private:
+  // 64-bit finaliser of MurmurHash3 (public domain)
+  static uint64_t hash(i64 k) {
+    uint64_t x = uint64_t(k);
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ULL;
+    x ^= x >> 33;
+    return x;
+  }
+  void rehash(size_t cap) {
+    std::vector<i64> ok, ov;
+    ok.swap(keys_);
+    ov.swap(vals_);
+    keys_.assign(cap, -1);
+    vals_.resize(cap);
+    size_ = 0;
+    for (size_t i = 0; i < ok.size(); ++i)
+      if (ok[i] >= 0) insert(ok[i], ov[i]);
+  }
+  std::vector<i64> keys_, vals_;
+  size_t size_ = 0;
+};
 
 struct SymStrip {
   int32_t tau, p;
@@ -117,14 +178,12 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
   // ---- symbolic sweep: strips, close/coupling lists, C slots, S blocks
   std::vector<std::vector<Pair>> closeL(L + 1), coupL(L + 1);
   std::vector<std::vector<SymStrip>> stripL(L + 2);
-  std::vector<std::unordered_map<i64, i64>> cslot(L + 2), gslot(L + 2);
+  std::vector<SlotMap> cslot(L + 2), gslot(L + 2);
   std::vector<i64> csize(L + 2, 0), gsize(L + 2, 0);
   std::vector<std::pair<i64, i64>> blocks;  // (t, s) with epos(t) <= epos(s)
   for (int k = 0; k <= L; ++k) {
     auto add_strip = [&](i64 tau, i64 p) {
-      const i64 kk = key(tau, p, ncl);
-      if (gslot[k + 1].count(kk)) return;
-      gslot[k + 1][kk] = gsize[k + 1];
+      if (!gslot[k + 1].insert(key(tau, p, ncl), gsize[k + 1])) return;
       stripL[k + 1].push_back({int32_t(tau), int32_t(p), gsize[k + 1]});
       gsize[k + 1] += mb[tau] * n_act[p];
     };
@@ -144,32 +203,38 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
     }
     for (const Pair& pr : H->bt.far[k])
       if (pr.t < pr.s) coupL[k].push_back(pr);
-    if (k < L)
+    if (k < L) {
+      cslot[k + 1].reserve(H->bt.near[k + 1].size());
       for (const Pair& pr : H->bt.near[k + 1]) {
         if (pr.t > pr.s || n_act[pr.t] == 0 || n_act[pr.s] == 0) continue;
-        cslot[k + 1][key(pr.t, pr.s, ncl)] = csize[k + 1];
+        cslot[k + 1].insert(key(pr.t, pr.s, ncl), csize[k + 1]);
         csize[k + 1] += n_act[pr.t] * n_act[pr.s];
       }
+    }
   }
   tt.lap("symbolic");
-  // ---- upper block pattern in the elimination order
-  std::sort(blocks.begin(), blocks.end(), [&](const auto& a, const auto& b) {
-    return epos[a.first] < epos[b.first] ||
-           (epos[a.first] == epos[b.first] && epos[a.second] < epos[b.second]);
-  });
-  if (std::adjacent_find(blocks.begin(), blocks.end()) != blocks.end())
+  // ---- upper block pattern in the elimination order: blocks as
+  // (row position, column position) keys, sorted in parallel
+  std::vector<uint64_t> bkeys(blocks.size());
+  for (size_t b = 0; b < blocks.size(); ++b)
+    bkeys[b] = (uint64_t(epos[blocks[b].first]) << 32) | uint64_t(epos[blocks[b].second]);
+  std::vector<std::pair<i64, i64>>().swap(blocks);
+  __gnu_parallel::sort(bkeys.begin(), bkeys.end());
+  if (std::adjacent_find(bkeys.begin(), bkeys.end()) != bkeys.end())
     fail(H2_EINVAL, "internal: duplicate S block");
   sp.rowptr.assign(ncl + 1, 0);
-  sp.colidx.resize(blocks.size());
-  sp.blk_off.resize(blocks.size());
+  sp.colidx.resize(bkeys.size());
+  sp.blk_off.resize(bkeys.size());
   i64 ent = 0;
-  for (size_t b = 0; b < blocks.size(); ++b) {
-    const i64 t = blocks[b].first, s = blocks[b].second;
+  for (size_t b = 0; b < bkeys.size(); ++b) {
+    const i64 t = sp.eorder[i64(bkeys[b] >> 32)], s = sp.eorder[i64(bkeys[b] & 0xffffffffu)];
     sp.rowptr[epos[t] + 1]++;
     sp.colidx[b] = s;
     sp.blk_off[b] = ent;
     ent += mb[t] * mb[s];
   }
+  std::vector<uint64_t>().swap(bkeys);
+  tt.lap("pattern");
   for (i64 i = 0; i < ncl; ++i) sp.rowptr[i + 1] += sp.rowptr[i];
   sp.s_entries = ent;
 
@@ -225,7 +290,7 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
   }
   sp.dTmp.reset(el * kTmpChunkEntries);
 
-  tt.lap("pattern+arenas");
+  tt.lap("arenas");
   // ---- per-level work lists with device pointers
   const double* X = H->d_x.as<double>();
   const double* nodes = H->d_nodes.as<double>();
