@@ -31,6 +31,7 @@
 #include <exception>
 #include <string>
 #include <mutex>
+#include <parallel/algorithm>
 #include <thread>
 #include <type_traits>
 
@@ -62,6 +63,7 @@ struct FactorLevel {
   double schur_flops = 0;
   double xcd_imbalance = 1;  // largest over mean work of the XCDs' tile ranges (traced)
   double col_share = 1, piv_share = 1;  // targets per distinct column, pivots per distinct pivot row (traced)
+  double once_bytes = 0, stream_bytes = 0;  // Schur operands read once per level / once per tile (traced)
 };
 
 // Output of one chunk of rows of a level (concatenated in row order).
@@ -416,6 +418,25 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       }
       L.col_share = nt / std::max(1.0, nj);
       L.piv_share = np / std::max(1.0, nk);
+      // operand bytes: every Z_ki and S_kj block once, targets read and
+      // written once; against every tile reading its own operands
+      std::vector<std::pair<i64, i64>> bb;
+      bb.reserve(L.ssegs.size());
+      double stream = 0;
+      for (const SchurItem& it : L.sitems)
+        for (int32_t r = it.seg_begin; r < it.seg_end; ++r) {
+          const SchurSeg& sg = L.ssegs[r];
+          bb.push_back({sg.b_off, i64(sg.K) * it.N});
+          stream += double(sizeof(T)) * (double(kpad16(sg.K)) * it.M + double(sg.K) * it.N);
+        }
+      __gnu_parallel::sort(bb.begin(), bb.end());
+      double once = double(sizeof(T)) * double(L.zlen);
+      for (size_t q = 0; q < bb.size(); ++q)
+        if (q == 0 || bb[q].first != bb[q - 1].first) once += double(sizeof(T)) * double(bb[q].second);
+      for (const SchurItem& it : L.sitems)
+        if (!it.partial) once += 2.0 * sizeof(T) * double(it.M) * it.N;
+      L.once_bytes = once;
+      L.stream_bytes = stream;
     }
   };
   // plans the levels in order, each in parallel
@@ -554,10 +575,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     if (trace_level() >= 2)
       std::fprintf(stderr,
                    "[h2sp] factor level %d: %zu rows, %d Schur tiles, %.4g GFLOP, %.3f ms (%.1f TF), XCD imbalance %.3f, "
-                   "rows per target column %.2f, rows per pivot %.2f; pivots and Z %.3f ms\n",
+                   "rows per target column %.2f, rows per pivot %.2f, operands once %.3f GB, per tile %.3f GB; "
+                   "pivots and Z %.3f ms\n",
                    lv, by_level[lv].size(), lvls[lv].nschur_tiles, lvls[lv].schur_flops / 1e9, b,
                    lvls[lv].schur_flops / std::max(1e-6, double(b)) / 1e9, lvls[lv].xcd_imbalance, lvls[lv].col_share,
-                   lvls[lv].piv_share, a + c);
+                   lvls[lv].piv_share, lvls[lv].once_bytes / 1e9, lvls[lv].stream_bytes / 1e9, a + c);
   }
   float tot = 0;
   HIPCHECK(hipEventElapsedTime(&tot, ev.front(), ev.back()));

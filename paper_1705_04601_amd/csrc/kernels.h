@@ -132,6 +132,19 @@ struct CopySeg {
 template <class T>
 void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st);
 
+// Kernel blocks written out: element (k, j) of block b, at out[b.off + k + j ns],
+// is scale / |x_{t0 + j} - x_{s0 + k}| (dim coordinates per point, points
+// consecutive in x), or diag where diag_blk is set and t0 + j == s0 + k.  The
+// values are bit for bit those the GEMM kernels generate for a B operand of
+// the same block (gen = 2).
+struct KernelBlock {
+  int64_t off;
+  int32_t t0, s0, nt, ns;
+  int32_t diag_blk, pad;
+};
+void launch_kernel_blocks(const KernelBlock* blocks, int count, const double* x, int dim, double scale,
+                          double diag, double* out, hipStream_t st);
+
 // Small element-wise helpers.
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_f(float* p, int64_t n, float v, hipStream_t st);

@@ -844,6 +844,37 @@ void launch_add_scaled_f_rm(const float* in, const double* cs, double* acc, int6
     hipLaunchKernelGGL(add_scaled_f_rm_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, cs, acc, n * nrhs, nrhs);
 }
 
+// One work-group per block, threads along the block's elements (k fastest).
+// The value is formed exactly as fetch4 forms a generated B element.
+__global__ __launch_bounds__(256) void kernel_blocks_kernel(const KernelBlock* blocks, const double* x, int dim,
+                                                          double scale, double diag, double* out) {
+  const KernelBlock b = blocks[blockIdx.x];
+  const int64_t len = int64_t(b.nt) * b.ns;
+  const double* pr = x + int64_t(b.t0) * dim;
+  const double* pc = x + int64_t(b.s0) * dim;
+  for (int64_t e = threadIdx.x; e < len; e += blockDim.x) {
+    const int k = int(e % b.ns), j = int(e / b.ns);
+    double val;
+    if (b.diag_blk && j == k) {
+      val = diag;
+    } else {
+      double d2 = 0.0;
+      for (int a = 0; a < dim; ++a) {
+        const double d = pr[j * dim + a] - pc[k * dim + a];
+        d2 += d * d;
+      }
+      val = double(scale * inv_sqrt(d2));
+    }
+    out[b.off + e] = val;
+  }
+}
+
+void launch_kernel_blocks(const KernelBlock* blocks, int count, const double* x, int dim, double scale,
+                          double diag, double* out, hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(kernel_blocks_kernel, dim3(count), dim3(256), 0, st, blocks, x, dim, scale, diag, out);
+}
+
 void launch_fill(double* p, int64_t n, double v, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
 }

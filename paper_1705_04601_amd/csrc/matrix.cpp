@@ -1,7 +1,9 @@
 // h2_matrix: construction, import, export and the FP64 H^2 matrix-vector
-// product (Definition 4.8): close part evaluated on the fly from the points,
-// far part by the nested bases (upward pass, couplings, downward pass).
+// product (Definition 4.8): close part from kernel blocks kept on the device
+// (or evaluated on the fly from the points when they do not fit), far part by
+// the nested bases (upward pass, couplings, downward pass).
 #include <cmath>
+#include <cstdlib>
 #include <memory>
 #include <mutex>
 #include <unordered_map>
@@ -68,6 +70,7 @@ namespace h2 {
 struct MatvecPlan {
   i64 nrhs = 0;
   DeviceBuffer xt, yt, xhat, xtil, ytil, yhat, desc;
+  DeviceBuffer close_blocks;     // kernel blocks of the close part, when resident
   GemmBatch close;
   std::vector<GemmBatch> up;     // per level (0 = leaves)
   GemmBatch xproj, coup, yproj;
@@ -75,6 +78,17 @@ struct MatvecPlan {
   GemmBatch leafout;
   LaunchGraph graph;             // the whole product, captured once
 };
+
+// Whether the close part's kernel blocks (FP64) are kept on the device: when
+// they take at most a quarter of the free device memory (idle cached blocks
+// count as free).  H2SP_CLOSE_RESIDENT=0 generates them inside every product.
+static bool close_blocks_fit(size_t bytes) {
+  if (const char* e = std::getenv("H2SP_CLOSE_RESIDENT"))
+    if (e[0] == '0') return false;
+  size_t free_b = 0, total_b = 0;
+  HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+  return bytes <= (free_b + cached_device_bytes()) / 4;
+}
 
 static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
   H.upload_all();
@@ -117,17 +131,45 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
   // right-hand sides are the rows of each output tile, so loads of them and
   // stores run along contiguous memory.
   const int N = int(nrhs);
-  // close part: one item per leaf, one segment per near leaf (kernel values
-  // generated from the points, the leaf's points along the output columns)
+  // close part: one item per leaf, one segment per near leaf, the leaf's
+  // points along the output columns.  The kernel blocks are written out once
+  // per plan and kept when they fit the budget (a stored operand runs at the
+  // GEMM's rate); otherwise they are generated from the points inside the GEMM
+  // for every product.
   std::vector<std::vector<int32_t>> nearOf(ncl);
   for (const Pair& pr : H.bt.near[0]) nearOf[pr.t].push_back(pr.s);
   const i64 f0 = tr.first_at_level(0), c0 = tr.count_at_level(0);
+  std::vector<KernelBlock> kb;
+  i64 kb_entries = 0;
+  for (i64 t = f0; t < f0 + c0; ++t)
+    for (int32_t s : nearOf[t]) {
+      kb.push_back({kb_entries, int32_t(tr.start[t]), int32_t(tr.start[s]), int32_t(tr.size[t]), int32_t(tr.size[s]),
+                    s == t ? 1 : 0, 0});
+      kb_entries += tr.size[t] * tr.size[s];
+    }
+  const bool resident = close_blocks_fit(size_t(kb_entries) * sizeof(double));
+  const double* blocks = nullptr;
+  if (resident) {
+    p.close_blocks.reset(sizeof(double) * std::max<i64>(kb_entries, 1));
+    DeviceBuffer dkb = upload(kb);
+    launch_kernel_blocks(dkb.as<KernelBlock>(), int(kb.size()), X, dim, H.scale, H.diag, p.close_blocks.as<double>(),
+                         current_stream());
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(current_stream()));
+    blocks = p.close_blocks.as<double>();
+  }
+  size_t b = 0;
   for (i64 t = f0; t < f0 + c0; ++t) {
     GemmItem& it = p.close.item(N, int(tr.size[t]), N, int(tr.size[t]));
     GemmBatch::set_out(it, 0, yt + tr.start[t] * nrhs, nrhs, false);
-    for (int32_t s : nearOf[t])
-      p.close.seg_genB(xt + tr.start[s] * nrhs, N, false, X + tr.start[t] * dim, X + tr.start[s] * dim, s == t,
-                       int(tr.size[s]));
+    for (int32_t s : nearOf[t]) {
+      if (resident)
+        p.close.seg(xt + tr.start[s] * nrhs, N, false, blocks + kb[b].off, int(tr.size[s]), false, int(tr.size[s]));
+      else
+        p.close.seg_genB(xt + tr.start[s] * nrhs, N, false, X + tr.start[t] * dim, X + tr.start[s] * dim, s == t,
+                         int(tr.size[s]));
+      ++b;
+    }
   }
   // upward pass: xhat_t = R_t^T x_t at the leaves, sum of T_s^T xhat_s above
   p.up.resize(L + 1);

@@ -106,6 +106,26 @@ def test_matvec_own_build(name):
     assert np.abs(host(y) - want).max() <= 1e-10 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("name", ["cube1536", "sphere2k", "torus777"])
+def test_matvec_close_generated_vs_resident(name, monkeypatch):
+    """The close part from kernel blocks written out once (the default) and
+    generated inside the GEMM for every product: both against the dense
+    product, and against each other (the same values in the same order)."""
+    x, sc, h2, sp, a, _ = case(name)
+    note(f"matvec close resident vs generated {name}")
+    v = np.random.default_rng(3).standard_normal((x.shape[0], 5))
+    want = from_tree(a @ to_tree(v, h2.tree.perm), h2.tree.perm)
+    got = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("H2SP_CLOSE_RESIDENT", flag)
+        h = imported(name)  # a fresh handle: the plan (and the choice) is per matrix
+        y = dev(np.zeros_like(v))
+        P.h2_matvec(h, dev(v), y)
+        got[flag] = host(y)
+        assert np.abs(got[flag] - want).max() <= 1e-13 * np.abs(want).max()
+    assert np.abs(got["0"] - got["1"]).max() <= 1e-15 * np.abs(want).max()
+
+
 def _check_plan(sph, sp):
     """Sizes, S offsets, elimination order and the stored pattern: bit-exact."""
     plan = P.h2_sparse_export_plan(sph)
