@@ -144,9 +144,9 @@ struct GemmBatch {
     if (amode >= 0 && !gemm_layout_supported(role, amode, bmode))
       fail(H2_EINVAL, "internal: no GEMM kernel for this role and operand layout");
     if (items.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "GEMM batch above 2^24 items");
-    // tile of the kernel that runs the batch: 128 x 32 for a generated B
+    // tile of the kernel that runs the batch: 64 x 32 for a generated B
     // (right-hand sides along M), 64 x 64 otherwise
-    const int em = bmode == 2 ? 128 : 64, en = bmode == 2 ? 32 : 64;
+    const int em = 64, en = bmode == 2 ? 32 : 64;
     for (size_t i = 0; i < items.size(); ++i) {
       const GemmItem& it = items[i];
       if (it.seg_end == it.seg_begin && mode != GEMM_STORE) continue;

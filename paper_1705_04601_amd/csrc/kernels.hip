@@ -121,36 +121,46 @@ __device__ __forceinline__ double inv_sqrt(double x) {
 }
 
 // Operand fetch of the direct kernel for one 16-row (or 16-column) block and
-// the four k of this lane: K-contiguous rows (vector load), M-contiguous
-// columns (one load per k, coalesced across the 16 lanes of a group) or
-// generated kernel values.
+// the four k of this lane: K-contiguous rows (vector load) or M-contiguous
+// columns (one load per k, coalesced across the 16 lanes of a group).
+// Generated operands go through gen4.
 template <class T, int MODE>
-__device__ __forceinline__ void fetch4(const T* p, int64_t ld, int row, int k, int K, bool ok, T* v,
-                                       const double* pr, const double* pc, int dim, double scale, double dg,
-                                       bool diag) {
+__device__ __forceinline__ void fetch4(const T* p, int64_t ld, int row, int k, int K, bool ok, T* v) {
   if (MODE == 0) {          // element (row, k) at p[k + row ld]
     load4<T>(p, k, K, ok, v);
-  } else if (MODE == 1) {   // element (row, k) at p[row + k ld]
+  } else {                  // element (row, k) at p[row + k ld]
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[s] = (ok && k + s < K) ? p[row + int64_t(k + s) * ld] : T(0);
-  } else {                  // generated: scale / |pr_row - pc_k|, dg on the diagonal
+  }
+}
+
+// Generated operand block for the four k of this lane: scale / |x_row - y_k|
+// (dg on the diagonal) from the row's point, held in registers for the whole
+// segment, and the chunk's four source points, loaded once per chunk and
+// shared by every block of the tile.  Coordinates past dim are zero on both
+// sides; the sum runs over a = 0 .. dim - 1 in order (kernel_blocks_kernel
+// forms the same values).
+template <class T>
+__device__ __forceinline__ void gen4(const double (&prow)[3], const double (&pcol)[4][3], int row, int k, int K,
+                                     bool ok, int dim, double scale, double dg, bool diag, T* v) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      T val = T(0);
-      if (ok && k + s < K) {
-        if (diag && row == k + s) {
-          val = T(dg);
-        } else {
-          double d2 = 0.0;
-          for (int a = 0; a < dim; ++a) {
-            const double d = pr[row * dim + a] - pc[(k + s) * dim + a];
+  for (int s = 0; s < 4; ++s) {
+    T val = T(0);
+    if (ok && k + s < K) {
+      if (diag && row == k + s) {
+        val = T(dg);
+      } else {
+        double d2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          if (a < dim) {
+            const double d = prow[a] - pcol[s][a];
             d2 += d * d;
           }
-          val = T(scale * inv_sqrt(d2));
-        }
+        val = T(scale * inv_sqrt(d2));
       }
-      v[s] = val;
     }
+    v[s] = val;
   }
 }
 
@@ -180,17 +190,44 @@ __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[MB][NB
     ob[b] = b < nbn && cb[b] < N;
     pb[b] = (BM == 0) ? B + int64_t(ob[b] ? cb[b] : 0) * sg.ldb : B;  // BM 1, 2: addressed per element
   }
+  // generated operands: the points of this lane's rows (A) or columns (B)
+  constexpr int GA = AM == 2 ? MB : 1, GB = BM == 2 ? NB : 1;
+  double prA[GA][3], prB[GB][3];
+  if (AM == 2) {
+#pragma unroll
+    for (int b = 0; b < GA; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) prA[b][a] = (oa[b] && a < dim) ? pr[ra[b] * dim + a] : 0.0;
+  }
+  if (BM == 2) {
+    const double* pcb = static_cast<const double*>(sg.B);
+#pragma unroll
+    for (int b = 0; b < GB; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) prB[b][a] = (ob[b] && a < dim) ? pcb[cb[b] * dim + a] : 0.0;
+  }
   for (int k0 = 0; k0 < K; k0 += 16) {
     const int k = k0 + kq;
     T a[MB][4], bv[NB][4];
+    double pcol[4][3];
+    if (AM == 2 || BM == 2) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) pcol[s][a] = (k + s < K && a < dim) ? sg.pc[(k + s) * dim + a] : 0.0;
+    }
 #pragma unroll
     for (int b = 0; b < MB; ++b)
-      if (b < nbm) fetch4<T, AM>(pa[b], sg.lda, ra[b], k, K, oa[b], a[b], pr, sg.pc, dim, scale, dg, sg.diag);
+      if (b < nbm) {
+        if constexpr (AM == 2) gen4<T>(prA[b], pcol, ra[b], k, K, oa[b], dim, scale, dg, sg.diag, a[b]);
+        else fetch4<T, AM>(pa[b], sg.lda, ra[b], k, K, oa[b], a[b]);
+      }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      if (b < nbn)
-        fetch4<T, BM>(pb[b], sg.ldb, cb[b], k, K, ob[b], bv[b], static_cast<const double*>(sg.B), sg.pc, dim,
-                      scale, dg, sg.diag);
+      if (b < nbn) {
+        if constexpr (BM == 2) gen4<T>(prB[b], pcol, cb[b], k, K, ob[b], dim, scale, dg, sg.diag, bv[b]);
+        else fetch4<T, BM>(pb[b], sg.ldb, cb[b], k, K, ob[b], bv[b]);
+      }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -753,7 +790,7 @@ void launch_gemm(const GemmLaunch& g, hipStream_t st) {
     case ROLE_MATVEC:
       if (m == 3) return launch_kc<T, ROLE_MATVEC, 1, 0>(g, st);
       if (m == 4) return launch_kc<T, ROLE_MATVEC, 1, 1>(g, st);
-      if (m == 5) return launch_kc<T, ROLE_MATVEC, 1, 2, 8, 2>(g, st);  // 128 x 32 tiles
+      if (m == 5) return launch_kc<T, ROLE_MATVEC, 1, 2, 4, 2>(g, st);  // 64 x 32 tiles
       break;
     default:
       if (m == 0) return launch_kc<T, ROLE_TRANSFORM, 0, 0>(g, st);
@@ -845,7 +882,7 @@ void launch_add_scaled_f_rm(const float* in, const double* cs, double* acc, int6
 }
 
 // One work-group per block, threads along the block's elements (k fastest).
-// The value is formed exactly as fetch4 forms a generated B element.
+// The value is formed exactly as gen4 forms a generated B element.
 __global__ __launch_bounds__(256) void kernel_blocks_kernel(const KernelBlock* blocks, const double* x, int dim,
                                                           double scale, double diag, double* out) {
   const KernelBlock b = blocks[blockIdx.x];
