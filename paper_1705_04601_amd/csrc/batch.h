@@ -144,9 +144,12 @@ struct GemmBatch {
     if (amode >= 0 && !gemm_layout_supported(role, amode, bmode))
       fail(H2_EINVAL, "internal: no GEMM kernel for this role and operand layout");
     if (items.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "GEMM batch above 2^24 items");
-    // tile of the kernel that runs the batch: 64 x 32 for a generated B
-    // (right-hand sides along M), 64 x 64 otherwise
-    const int em = 64, en = bmode == 2 ? 32 : 64;
+    int em = 64, en = 64;  // tile of the kernel that runs the batch
+    if (amode >= 0) {
+      gemm_tile(role, amode, bmode, &em, &en);
+      em *= 16;
+      en *= 16;
+    }
     for (size_t i = 0; i < items.size(); ++i) {
       const GemmItem& it = items[i];
       if (it.seg_end == it.seg_begin && mode != GEMM_STORE) continue;

@@ -64,6 +64,8 @@ template <class T>
 void launch_gemm(const GemmLaunch& g, hipStream_t st);
 // whether a role's kernels are built for a layout pair
 bool gemm_layout_supported(int role, int amode, int bmode);
+// output tile of the kernel that runs a role and layout pair: mb x nb blocks of 16 x 16
+void gemm_tile(int role, int amode, int bmode, int* mb, int* nb);
 
 // Compact work list of the Schur update S_ij -= Z_ki^T S_kj (offsets in
 // elements into S and into the buffer of Z_ki blocks; every operand has leading

@@ -1,9 +1,10 @@
 // HIP kernels of libh2sp for gfx950 (CDNA4, 64-wide wavefronts).
 //
 //  * gemm_kc_kernel: batched, segmented small GEMM on MFMA (v_mfma_f64_16x16x4
-//    / v_mfma_f32_16x16x4).  One wavefront per 64 x 64 output tile, operands
+//    / v_mfma_f32_16x16x4).  One wavefront per output tile (32 x 32, 64 x 32
+//    or 64 x 64 by role and operand layout), operands
 //    straight from L2 without LDS; either operand can be generated on the fly
-//    from points (kernel evaluation, so close blocks never touch HBM); the
+//    from points (kernel evaluation, so a generated block never touches HBM); the
 //    epilogue scatters the four quadrants of the tile to separate
 //    destinations (the basis / non-basis split of Section 2).
 //  * schur_kernel: the Schur updates of the block factorisation.
@@ -98,7 +99,7 @@ __device__ __forceinline__ void load4(const T* p, int k, int K, bool ok, T* v) {
   }
 }
 
-constexpr int KT = 64;  // tile edge of the K-contiguous kernels
+constexpr int KT = 64;  // tile edge of the Schur kernel
 
 // Work-groups are handed to the 8 XCDs round-robin by block index, and each
 // XCD has its own L2.  Tile lists put tiles that share operands next to each
@@ -769,9 +770,29 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
+// Output tile of each kernel instance, in 16 x 16 blocks (rows x columns).
+// Measured on the solve sweeps, the sparsification transforms and the pivot
+// GEMMs (short K, many items): 32 x 32 tiles, with more waves per SIMD, beat
+// 64 x 64 ones; a generated operand is shared by more blocks in 64 x 32 tiles.
+constexpr int tile_mb(int role, int am, int bm) {
+  return (role == ROLE_MATVEC && bm == 2) || (role == ROLE_TRANSFORM && am == 2) ? 4
+         : (role == ROLE_MATVEC)                                                 ? 4
+                                                                                 : 2;
+}
+constexpr int tile_nb(int role, int am, int bm) {
+  return (role == ROLE_MATVEC && bm == 2) || (role == ROLE_TRANSFORM && am == 2) ? 2
+         : (role == ROLE_MATVEC)                                                 ? 4
+                                                                                 : 2;
+}
+void gemm_tile(int role, int amode, int bmode, int* mb, int* nb) {
+  *mb = tile_mb(role, amode, bmode);
+  *nb = tile_nb(role, amode, bmode);
+}
+
 // Operand layouts each role plans (the host checks every batch against them).
-template <class T, int ROLE, int AM, int BM, int MB = 4, int NB = 4>
+template <class T, int ROLE, int AM, int BM>
 static void launch_kc(const GemmLaunch& g, hipStream_t st) {
+  constexpr int MB = tile_mb(ROLE, AM, BM), NB = tile_nb(ROLE, AM, BM);
   hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB>), dim3(g.ntiles), dim3(64), 0, st, g);
 }
 
@@ -790,7 +811,7 @@ void launch_gemm(const GemmLaunch& g, hipStream_t st) {
     case ROLE_MATVEC:
       if (m == 3) return launch_kc<T, ROLE_MATVEC, 1, 0>(g, st);
       if (m == 4) return launch_kc<T, ROLE_MATVEC, 1, 1>(g, st);
-      if (m == 5) return launch_kc<T, ROLE_MATVEC, 1, 2, 4, 2>(g, st);  // 64 x 32 tiles
+      if (m == 5) return launch_kc<T, ROLE_MATVEC, 1, 2>(g, st);
       break;
     default:
       if (m == 0) return launch_kc<T, ROLE_TRANSFORM, 0, 0>(g, st);
