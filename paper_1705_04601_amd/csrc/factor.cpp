@@ -105,8 +105,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       }
   }
   // Z buffer: the Z_ki blocks of the largest level, each stored with its
-  // row count rounded up to 16 (zero rows below m_k: the Schur kernel reads K
-  // in steps of 16)
+  // row count rounded up to 16 (zero rows below m_k; columns 64-byte aligned
+  // for the Schur kernel's chunks of 16 k)
   auto kpad16 = [](i64 m) { return (m + 15) & ~i64(15); };
   i64 zmax = 1;
   for (const auto& lv : by_level) {

@@ -294,9 +294,11 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
 // offset per lane and 16 x 16 block that stays fixed for the whole segment; a
 // chunk only moves the two bases on by 16 k.  Reads outside a resource return
 // zero, which covers rows past M and columns past N, and a chunk past the
-// item's last segment (a resource of size zero).  Inside a segment, k past K
-// meets the zero rows of the padded Z_ki; the S_kj operand then reads the
-// next column of the block, or zero past the block's end.
+// item's last segment (a resource of size zero).  A lane whose four k start
+// at or past K reads through an offset outside both resources (zero, and no
+// memory traffic); in the lane that holds K itself, k past K meets the zero
+// rows of the padded Z_ki, and the S_kj operand reads the next column of the
+// block, or zero past the block's end.
 // Segment descriptors are loaded 64 at a time, one per lane, and taken out
 // with readlane, so that moving to the next segment waits for no memory.
 constexpr int kRsrcFlags = 0x00020000;  // raw 32-bit buffer, no swizzle (gfx9 family)
@@ -398,15 +400,19 @@ __device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const Sc
   }
 }
 
+constexpr uint32_t kOutside = 0x80000000u;  // a buffer offset past every resource used here
+
 template <class T, int NBM, int NBN>
-__device__ __forceinline__ void schur_fetch(const SchurCursor<T, NBM, NBN>& c, T (&a)[NBM][4], T (&b)[NBN][4]) {
+__device__ __forceinline__ void schur_fetch(const SchurCursor<T, NBM, NBN>& c, int kq, T (&a)[NBM][4],
+                                            T (&b)[NBN][4]) {
   const uint32_t sh = uint32_t(c.k0) * uint32_t(sizeof(T));  // k0 < K <= K16: both sizes stay positive
   const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.pa + c.k0, c.valid ? c.na - sh : 0u);
   const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.pb + c.k0, c.valid ? c.nb - sh : 0u);
+  const bool live = c.k0 + kq < c.K;
 #pragma unroll
-  for (int q = 0; q < NBM; ++q) BufLoad4<T>::run(ra, c.oa[q], a[q]);
+  for (int q = 0; q < NBM; ++q) BufLoad4<T>::run(ra, live ? c.oa[q] : kOutside, a[q]);
 #pragma unroll
-  for (int q = 0; q < NBN; ++q) BufLoad4<T>::run(rb, c.ob[q], b[q]);
+  for (int q = 0; q < NBN; ++q) BufLoad4<T>::run(rb, live ? c.ob[q] : kOutside, b[q]);
 }
 
 template <class T, int NBM, int NBN>
@@ -440,18 +446,18 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
     schur_load_desc(c, g.segs, lane);
     schur_setup(c, S, Z, m0, n0, it.M, it.N, r, kq);
     T a[NS][NBM][4], b[NS][NBN][4];
-    schur_fetch(c, a[0], b[0]);
+    schur_fetch(c, kq, a[0], b[0]);
 #pragma unroll
     for (int i = 1; i < NS - 1; ++i) {
       schur_next(c, g.segs, S, Z, m0, n0, it.M, it.N, r, kq, lane);
-      schur_fetch(c, a[i], b[i]);
+      schur_fetch(c, kq, a[i], b[i]);
     }
     // one exit per NS chunks; chunks past the end read zeros
     while (true) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
         schur_next(c, g.segs, S, Z, m0, n0, it.M, it.N, r, kq, lane);
-        schur_fetch(c, a[(i + NS - 1) % NS], b[(i + NS - 1) % NS]);
+        schur_fetch(c, kq, a[(i + NS - 1) % NS], b[(i + NS - 1) % NS]);
         __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
         schur_mfma<T, NBM, NBN>(acc, a[i], b[i]);
         __builtin_amdgcn_sched_barrier(0);
