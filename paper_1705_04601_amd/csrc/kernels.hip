@@ -609,13 +609,15 @@ __global__ __launch_bounds__(256) void qr_kernel(const QrItem* items) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void inverse_kernel(const InvItem<T>* items, int* flag) {
+__global__ __launch_bounds__(1024) void inverse_kernel(const InvItem<T>* items, int* flag) {
   __shared__ double a[128 * 128];
   __shared__ double fcol[128];
   __shared__ int perm[128];
   const InvItem<T> it = items[blockIdx.x];
   const int m = it.m, tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  for (int e = tid; e < m * m; e += 256) a[e] = double(it.A[e]);
+  // the rank-one update: thread (row r, column group g) owns columns g, g + 16, ...
+  const int r = tid % 64, g = tid / 64;
+  for (int e = tid; e < m * m; e += 1024) a[e] = double(it.A[e]);
   __syncthreads();
   for (int j = 0; j < m; ++j) {
     if (wave == 0) {
@@ -637,35 +639,34 @@ __global__ __launch_bounds__(256) void inverse_kernel(const InvItem<T>* items, i
     }
     __syncthreads();
     const int p = perm[j];
-    if (p != j)
-      for (int c = tid; c < m; c += 256) {
-        const double t = a[j + c * m];
-        a[j + c * m] = a[p + c * m];
-        a[p + c * m] = t;
-      }
+    if (p != j && tid < m) {
+      const double t = a[j + tid * m];
+      a[j + tid * m] = a[p + tid * m];
+      a[p + tid * m] = t;
+    }
     __syncthreads();
     const double piv = a[j + j * m];
-    for (int i = tid; i < m; i += 256) fcol[i] = a[i + j * m];
+    if (tid < m) fcol[tid] = a[tid + j * m];
     __syncthreads();
-    for (int c = tid; c < m; c += 256) a[j + c * m] = (c == j ? 1.0 : a[j + c * m]) / piv;
+    if (tid < m) a[j + tid * m] = (tid == j ? 1.0 : a[j + tid * m]) / piv;
     __syncthreads();
-    for (int e = tid; e < m * m; e += 256) {
-      const int i = e % m, c = e / m;
-      if (i != j) a[e] = (c == j ? 0.0 : a[e]) - fcol[i] * a[j + c * m];
+    for (int i = r; i < m; i += 64) {
+      if (i == j) continue;
+      const double f = fcol[i];
+      for (int c = g; c < m; c += 16) a[i + c * m] = (c == j ? 0.0 : a[i + c * m]) - f * a[j + c * m];
     }
     __syncthreads();
   }
   for (int j = m - 1; j >= 0; --j) {
     const int p = perm[j];
-    if (p != j)
-      for (int i = tid; i < m; i += 256) {
-        const double t = a[i + j * m];
-        a[i + j * m] = a[i + p * m];
-        a[i + p * m] = t;
-      }
+    if (p != j && tid < m) {
+      const double t = a[tid + j * m];
+      a[tid + j * m] = a[tid + p * m];
+      a[tid + p * m] = t;
+    }
     __syncthreads();
   }
-  for (int e = tid; e < m * m; e += 256) it.Inv[e] = T(a[e]);
+  for (int e = tid; e < m * m; e += 1024) it.Inv[e] = T(a[e]);
 }
 
 __global__ void fill_kernel(double* p, int64_t n, double v) {
@@ -865,7 +866,7 @@ void launch_qr(const QrItem* items, int count, hipStream_t st) {
 template <class T>
 void launch_inverse(const InvItem<T>* items, int count, int* flag, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(inverse_kernel<T>, dim3(count), dim3(256), 0, st, items, flag);
+  hipLaunchKernelGGL(inverse_kernel<T>, dim3(count), dim3(1024), 0, st, items, flag);
 }
 template void launch_inverse<double>(const InvItem<double>*, int, int*, hipStream_t);
 template void launch_inverse<float>(const InvItem<float>*, int, int*, hipStream_t);
