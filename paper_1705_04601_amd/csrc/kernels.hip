@@ -759,13 +759,12 @@ __global__ void add_scaled_f_rm_kernel(const float* in, const double* cs, double
 }
 
 template <class T>
-__global__ void copy_segments_kernel(const CopySeg* segs, const T* src, T* dst) {
+__global__ __launch_bounds__(256) void copy_segments_kernel(const CopySeg* segs, const T* src, T* dst) {
+  // one column per wave at a time, lanes along the rows (both sides contiguous)
   const CopySeg s = segs[blockIdx.y];
-  const int len = s.rows * s.cols;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) {
-    const int c = e / s.rows, r = e - c * s.rows;
-    dst[s.dst + e] = src[s.src + int64_t(c) * s.src_ld + r];
-  }
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int c = blockIdx.x * 4 + wave; c < s.cols; c += gridDim.x * 4)
+    for (int r = lane; r < s.rows; r += 64) dst[s.dst + int64_t(c) * s.rows + r] = src[s.src + int64_t(c) * s.src_ld + r];
 }
 
 int grid_for(int64_t n) {
@@ -875,7 +874,7 @@ template <class T>
 void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st) {
   for (int c0 = 0; c0 < count; c0 += 65535) {
     const int c = (count - c0) < 65535 ? (count - c0) : 65535;
-    hipLaunchKernelGGL(copy_segments_kernel<T>, dim3(64, c), dim3(256), 0, st, segs + c0, src, dst);
+    hipLaunchKernelGGL(copy_segments_kernel<T>, dim3(8, c), dim3(256), 0, st, segs + c0, src, dst);
   }
 }
 template void launch_copy_segments<double>(const CopySeg*, int, const double*, double*, hipStream_t);
