@@ -30,10 +30,11 @@ import h2inputs  # noqa: E402
 
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense MFMA (FP32 / FP64)
 PHASES = ["qr", "close", "couplings", "strips", "factor_pivots_z", "factor_schur"]
-KERNELS = {"qr": "qr_kernel", "close": "gemm_kc_kernel<float, 0>", "couplings": "gemm_kc_kernel<float, 0>",
-           "strips": "gemm_kc_kernel<float, 0>",
-           "factor_pivots_z": "inverse_kernel<float> + gemm_kc_kernel<float, 1> + schur_reduce_kernel<float>",
-           "factor_schur": "schur_kernel<float, 0>"}
+KERNELS = {"qr": "qr_kernel", "close": "gemm_kc_kernel<float, 0, ...>", "couplings": "gemm_kc_kernel<float, 0, ...>",
+           "strips": "gemm_kc_kernel<float, 0, ...>",
+           "factor_pivots_z": "inverse_kernel<float> + gemm_kc_kernel<float, 1, ...> + copy_segments_kernel<float>"
+                              " + schur_reduce_kernel<float>",
+           "factor_schur": "schur_kernel<float>"}
 # HBM traffic of the Schur kernel measured with rocprofv3 counters; used only
 # while the kernel and its planner are the sources the counters were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_kernel_cube1m_traffic.txt")

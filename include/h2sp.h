@@ -134,9 +134,13 @@ int h2_matrix_info(const h2_matrix* h, int* depth, int64_t* ncl, int* cheb_point
 int h2_matrix_export_tree(const h2_matrix* h, int64_t* perm, int32_t* rank);
 
 /*
- * h2_matvec: y = A_H2 x in FP64 on the device (close part evaluated on the
- * fly from the points, far part by the nested bases).  x, y: DEVICE pointers,
- * column-major n x nrhs with leading dimension ld >= n, ORIGINAL point order.
+ * h2_matvec: y = A_H2 x in FP64 on the device (close part from the kernel
+ * blocks of the near leaf pairs, far part by the nested bases; Definition 4.8).
+ * The first product for a right-hand-side count builds a plan kept with the
+ * matrix; it writes the close blocks out once when they take at most a quarter
+ * of the free device memory (H2SP_CLOSE_RESIDENT=0: never), else every product
+ * evaluates them from the points.  x, y: DEVICE pointers, column-major
+ * n x nrhs with leading dimension ld >= n, ORIGINAL point order; nrhs <= 512.
  */
 int h2_matvec(const h2_matrix* h, const double* x, double* y, int64_t nrhs, int64_t ld);
 

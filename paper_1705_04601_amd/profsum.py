@@ -18,7 +18,7 @@ import hashlib
 import os
 import sys
 
-SCHUR = "schur_kernel<float, 0>"
+SCHUR = "schur_kernel<float>"
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SOURCES = [os.path.join(ROOT, "paper_1705_04601_amd", "csrc", f) for f in ("kernels.hip", "factor.cpp")]
 
