@@ -64,6 +64,7 @@ struct FactorLevel {
   double xcd_imbalance = 1;  // largest over mean work of the XCDs' tile ranges (traced)
   double col_share = 1, piv_share = 1;  // targets per distinct column, pivots per distinct pivot row (traced)
   double once_bytes = 0, stream_bytes = 0;  // Schur operands read once per level / once per tile (traced)
+  double union2 = 1, union4 = 1;  // K of the union of the pivot lists of 2 / 4 consecutive targets over their sum (traced)
 };
 
 // Output of one chunk of rows of a level (concatenated in row order).
@@ -418,6 +419,33 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       }
       L.col_share = nt / std::max(1.0, nj);
       L.piv_share = np / std::max(1.0, nk);
+      // pivot lists of consecutive targets of a row: how much would a group of
+      // G targets sharing one pass over the union of their pivots do
+      {
+        double sum_k = 0, u2 = 0, u4 = 0;
+        std::vector<int32_t> tpos(ncl, -1);
+        for (i64 pi : rows) {
+          const i64 t0 = sp.rowptr[pi], t1 = sp.rowptr[pi + 1];
+          for (i64 b = t0; b < t1; ++b) tpos[sp.colidx[b]] = int32_t(b - t0);
+          std::vector<char> g2, g4;
+          for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+            const i64 pk = ck_pos[c];
+            const double mk = double(mb[cl(pk)]);
+            g2.assign((t1 - t0) / 2 + 1, 0);
+            g4.assign((t1 - t0) / 4 + 1, 0);
+            for (i64 b = sp.rowptr[pk]; b < sp.rowptr[pk + 1]; ++b) {
+              const int32_t t = tpos[sp.colidx[b]];
+              if (t < 0) continue;
+              sum_k += mk;
+              if (!g2[t / 2]) g2[t / 2] = 1, u2 += 2 * mk;
+              if (!g4[t / 4]) g4[t / 4] = 1, u4 += 4 * mk;
+            }
+          }
+          for (i64 b = t0; b < t1; ++b) tpos[sp.colidx[b]] = -1;
+        }
+        L.union2 = u2 / std::max(1.0, sum_k);
+        L.union4 = u4 / std::max(1.0, sum_k);
+      }
       // operand bytes: every Z_ki and S_kj block once, targets read and
       // written once; against every tile reading its own operands
       std::vector<std::pair<i64, i64>> bb;
@@ -575,11 +603,13 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     if (trace_level() >= 2)
       std::fprintf(stderr,
                    "[h2sp] factor level %d: %zu rows, %d Schur tiles, %.4g GFLOP, %.3f ms (%.1f TF), XCD imbalance %.3f, "
-                   "rows per target column %.2f, rows per pivot %.2f, operands once %.3f GB, per tile %.3f GB; "
+                   "rows per target column %.2f, rows per pivot %.2f, operands once %.3f GB, per tile %.3f GB, "
+                   "grouped pivots x%.2f (2) x%.2f (4); "
                    "pivots and Z %.3f ms\n",
                    lv, by_level[lv].size(), lvls[lv].nschur_tiles, lvls[lv].schur_flops / 1e9, b,
                    lvls[lv].schur_flops / std::max(1e-6, double(b)) / 1e9, lvls[lv].xcd_imbalance, lvls[lv].col_share,
-                   lvls[lv].piv_share, lvls[lv].once_bytes / 1e9, lvls[lv].stream_bytes / 1e9, a + c);
+                   lvls[lv].piv_share, lvls[lv].once_bytes / 1e9, lvls[lv].stream_bytes / 1e9, lvls[lv].union2,
+                   lvls[lv].union4, a + c);
   }
   float tot = 0;
   HIPCHECK(hipEventElapsedTime(&tot, ev.front(), ev.back()));
