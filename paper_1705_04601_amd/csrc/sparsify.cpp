@@ -20,6 +20,7 @@
 #include <cstring>
 #include <memory>
 #include <parallel/algorithm>
+#include <string>
 
 #include "sparse.h"
 
@@ -665,27 +666,71 @@ void run_sparsify_batch(std::vector<h2_sparse*>& sps, hipStream_t st, double* ph
   int nlev = 0;
   for (h2_sparse* sp : sps) nlev = std::max(nlev, sp->H->tree.depth + 1);
   std::vector<MergedLevel> M(nlev);
+  // levels merge independently (in parallel); inside a level the instances
+  // follow in order, each batch sized once before the copies
+  int err_code = 0;
+  std::string err_msg;
+#pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k < nlev; ++k) {
-    MergedLevel& m = M[k];
-    for (h2_sparse* sp : sps) {
-      if (k > sp->H->tree.depth) continue;
-      SweepLevel& lv = sp->levels[k];
-      m.qr.insert(m.qr.end(), lv.qr.items.begin(), lv.qr.items.end());
-      std::vector<QrItem>().swap(lv.qr.items);
-      m.stack.append(lv.stack);
-      m.wproj.append(lv.wproj);
-      m.strips.append(lv.strips);
-      auto merge_chunks = [](std::vector<GemmBatch>& dst, std::vector<GemmBatch>& src) {
-        if (dst.size() < src.size()) dst.resize(src.size());
-        for (size_t c = 0; c < src.size(); ++c) dst[c].append(src[c]);
+    try {
+      MergedLevel& m = M[k];
+      size_t nq = 0, nchunk[4] = {0, 0, 0, 0};
+      for (h2_sparse* sp : sps) {
+        if (k > sp->H->tree.depth) continue;
+        const SweepLevel& lv = sp->levels[k];
+        nq += lv.qr.items.size();
+        nchunk[0] = std::max(nchunk[0], lv.close1.size());
+        nchunk[1] = std::max(nchunk[1], lv.close2.size());
+        nchunk[2] = std::max(nchunk[2], lv.coup1.size());
+        nchunk[3] = std::max(nchunk[3], lv.coup2.size());
+      }
+      m.qr.reserve(nq);
+      m.close1.resize(nchunk[0]);
+      m.close2.resize(nchunk[1]);
+      m.coup1.resize(nchunk[2]);
+      m.coup2.resize(nchunk[3]);
+      auto reserve = [&](GemmBatch& dst, auto pick) {
+        size_t ni = 0, ns = 0;
+        for (h2_sparse* sp : sps) {
+          if (k > sp->H->tree.depth) continue;
+          const GemmBatch* b = pick(sp->levels[k]);
+          if (b) ni += b->items.size(), ns += b->segs.size();
+        }
+        dst.items.reserve(ni);
+        dst.segs.reserve(ns);
       };
-      merge_chunks(m.close1, lv.close1);
-      merge_chunks(m.close2, lv.close2);
-      merge_chunks(m.coup1, lv.coup1);
-      merge_chunks(m.coup2, lv.coup2);
+      reserve(m.stack, [](SweepLevel& lv) -> const GemmBatch* { return &lv.stack; });
+      reserve(m.wproj, [](SweepLevel& lv) -> const GemmBatch* { return &lv.wproj; });
+      reserve(m.strips, [](SweepLevel& lv) -> const GemmBatch* { return &lv.strips; });
+      for (size_t c = 0; c < nchunk[0]; ++c)
+        reserve(m.close1[c], [c](SweepLevel& lv) -> const GemmBatch* { return c < lv.close1.size() ? &lv.close1[c] : nullptr; });
+      for (size_t c = 0; c < nchunk[1]; ++c)
+        reserve(m.close2[c], [c](SweepLevel& lv) -> const GemmBatch* { return c < lv.close2.size() ? &lv.close2[c] : nullptr; });
+      for (size_t c = 0; c < nchunk[2]; ++c)
+        reserve(m.coup1[c], [c](SweepLevel& lv) -> const GemmBatch* { return c < lv.coup1.size() ? &lv.coup1[c] : nullptr; });
+      for (size_t c = 0; c < nchunk[3]; ++c)
+        reserve(m.coup2[c], [c](SweepLevel& lv) -> const GemmBatch* { return c < lv.coup2.size() ? &lv.coup2[c] : nullptr; });
+      for (h2_sparse* sp : sps) {
+        if (k > sp->H->tree.depth) continue;
+        SweepLevel& lv = sp->levels[k];
+        m.qr.insert(m.qr.end(), lv.qr.items.begin(), lv.qr.items.end());
+        std::vector<QrItem>().swap(lv.qr.items);
+        m.stack.append(lv.stack);
+        m.wproj.append(lv.wproj);
+        m.strips.append(lv.strips);
+        for (size_t c = 0; c < lv.close1.size(); ++c) m.close1[c].append(lv.close1[c]);
+        for (size_t c = 0; c < lv.close2.size(); ++c) m.close2[c].append(lv.close2[c]);
+        for (size_t c = 0; c < lv.coup1.size(); ++c) m.coup1[c].append(lv.coup1[c]);
+        for (size_t c = 0; c < lv.coup2.size(); ++c) m.coup2[c].append(lv.coup2[c]);
+      }
+      m.nqr = int(m.qr.size());
+    } catch (const Error& e) {
+#pragma omp critical(h2_merge_error)
+      if (!err_code) err_code = e.code, err_msg = e.msg;
     }
-    m.nqr = int(m.qr.size());
   }
+  if (err_code) fail(err_code, err_msg);
+  tt.lap("merge");
   std::vector<GemmBatch*> all;
   std::vector<RawBlob> blobs;
   for (MergedLevel& m : M) {
@@ -700,7 +745,7 @@ void run_sparsify_batch(std::vector<h2_sparse*>& sps, hipStream_t st, double* ph
   }
   DeviceBuffer desc;
   upload_batches(all, desc, blobs);
-  tt.lap("merge+upload");
+  tt.lap("upload");
   if (sps.front()->precision == H2_MIXED) run_merged<float>(sps, M, st, phase_ms);
   else run_merged<double>(sps, M, st, phase_ms);
   tt.lap("run");
