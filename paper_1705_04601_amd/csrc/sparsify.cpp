@@ -321,20 +321,75 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
     if (epos[t] <= epos[s]) GemmBatch::set_out(it, q, blk_ptr(t, s), mb[t], false);
     else GemmBatch::set_out(it, q, blk_ptr(s, t), mb[s], true);
   };
-  // levels are independent once slots and offsets are fixed: build in parallel
+  // Levels are independent once slots and offsets are fixed, and so are the
+  // pieces of a level: its QR and stacking items, runs of its strips, and the
+  // chunks of its close and coupling pairs (chunk boundaries fixed first, by
+  // the temporary space each pair takes).  Strip runs are appended in order
+  // afterwards.
   std::string first_error;
   int first_code = 0;
-#pragma omp parallel for schedule(dynamic, 1)
+  auto guarded = [&](auto&& body) {
+    try {
+      body();
+    } catch (const Error& e) {
+#pragma omp critical(h2_plan_error)
+      if (!first_code) { first_code = e.code; first_error = e.msg; }
+    } catch (const std::exception& e) {
+#pragma omp critical(h2_plan_error)
+      if (!first_code) { first_code = H2_EINVAL; first_error = e.what(); }
+    }
+  };
+  auto chunk_starts = [](i64 count, auto&& size_of) {
+    std::vector<i64> st;
+    i64 used = kTmpChunkEntries;
+    for (i64 i = 0; i < count; ++i) {
+      const i64 sz = size_of(i);
+      if (used + sz > kTmpChunkEntries) {
+        st.push_back(i);
+        used = 0;
+      }
+      used += sz;
+    }
+    st.push_back(count);
+    return st;
+  };
+  constexpr i64 kStripRun = 32768;
+  std::vector<std::vector<GemmBatch>> strip_runs(L + 1);
+  std::vector<std::vector<i64>> close_cut(L + 1), coup_cut(L + 1);
+  std::vector<std::vector<PlanCounts>> close_pc(L + 1), coup_pc(L + 1);
   for (int k = 0; k <= L; ++k) {
-   try {
-    PlanCounts& pc = lpc[k];
+    close_cut[k] = chunk_starts(i64(closeL[k].size()),
+                                [&](i64 i) { return n_act[closeL[k][i].t] * n_act[closeL[k][i].s]; });
+    coup_cut[k] = chunk_starts(i64(coupL[k].size()), [&](i64 i) { return i64(P) * kept[coupL[k][i].s]; });
+    const size_t ncl_chunks = close_cut[k].size() - 1, ncp_chunks = coup_cut[k].size() - 1;
+    sp.levels[k].close1.resize(ncl_chunks);
+    sp.levels[k].close2.resize(ncl_chunks);
+    sp.levels[k].coup1.resize(ncp_chunks);
+    sp.levels[k].coup2.resize(ncp_chunks);
+    close_pc[k].resize(ncl_chunks);
+    coup_pc[k].resize(ncp_chunks);
+    strip_runs[k].resize((stripL[k].size() + kStripRun - 1) / kStripRun);
+  }
+  // one work unit per piece; units of every level in one worksharing loop
+  // (no OpenMP tasks: this also runs on the batched path's pool threads,
+  // where libomp's task allocator is not safe)
+  struct Unit {
+    int kind, k;  // kind 0: QR and stacking items, 1: strip run, 2: close chunk, 3: coupling chunk
+    i64 idx;
+  };
+  std::vector<Unit> units;
+  for (int k = 0; k <= L; ++k) {
     SweepLevel& lv = sp.levels[k];
-    char* Ccur = static_cast<char*>(sp.dC[k % 2].ptr);
-    char* Cnext = static_cast<char*>(sp.dC[(k + 1) % 2].ptr);
-    char* Gcur = static_cast<char*>(sp.dG[k % 2].ptr);
-    char* Gnext = static_cast<char*>(sp.dG[(k + 1) % 2].ptr);
     lv.gnext_side = (k + 1) % 2;
     lv.gnext_entries = (k < L) ? gsize[k + 1] : 0;
+    units.push_back({0, k, 0});
+    for (size_t run = 0; run < strip_runs[k].size(); ++run) units.push_back({1, k, i64(run)});
+    for (size_t ch = 0; ch + 1 < close_cut[k].size(); ++ch) units.push_back({2, k, i64(ch)});
+    for (size_t ch = 0; ch + 1 < coup_cut[k].size(); ++ch) units.push_back({3, k, i64(ch)});
+  }
+  auto qr_unit = [&](int k) {
+    PlanCounts& pc = lpc[k];
+    SweepLevel& lv = sp.levels[k];
     // 1. QR items
     std::vector<QrItem> qi;
     for (i64 c = tr.first_at_level(k); c < tr.first_at_level(k) + tr.count_at_level(k); ++c) {
@@ -379,103 +434,126 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
       }
     }
     pc.flops_misc += lv.stack.flops + lv.wproj.flops;
-    // 3. strips: G(tau, p) Q_p
-    for (const SymStrip& g : stripL[k]) {
-      const i64 tau = g.tau, p = g.p;
-      GemmItem& it = lv.strips.item(int(mb[tau]), int(n_act[p]), 0, int(kept[p]));
+  };
+  // 3. strips: G(tau, p) Q_p, in runs
+  auto strip_unit = [&](int k, size_t run) {
+    char* Gcur = static_cast<char*>(sp.dG[k % 2].ptr);
+    char* Gnext = static_cast<char*>(sp.dG[(k + 1) % 2].ptr);
+    GemmBatch& g = strip_runs[k][run];
+    const size_t b0 = run * kStripRun, b1 = std::min(stripL[k].size(), b0 + kStripRun);
+    for (size_t q = b0; q < b1; ++q) {
+      const SymStrip& gs = stripL[k][q];
+      const i64 tau = gs.tau, p = gs.p;
+      GemmItem& it = g.item(int(mb[tau]), int(n_act[p]), 0, int(kept[p]));
       if (mb[p] > 0) GemmBatch::set_out(it, 3, blk_ptr(tau, p), mb[tau], false);
       if (kept[p] > 0 && p > 0) {
         const i64 f = (p - 1) / 2;
         const i64 slot = gslot[k + 1].at(key(tau, f, ncl));
         GemmBatch::set_out(it, 2, Gnext + el * (slot + son_off(p) * mb[tau]), mb[tau], false);
       }
-      lv.strips.seg(Gcur + el * g.slot, int(mb[tau]), false, Qt + el * sp.q_off[p], int(n_act[p]), false,
-                    int(n_act[p]));
+      g.seg(Gcur + el * gs.slot, int(mb[tau]), false, Qt + el * sp.q_off[p], int(n_act[p]), false,
+            int(n_act[p]));
     }
-    pc.flops_strip += lv.strips.flops;
-    // 4. close pairs, chunked by temporary space
-    {
-      i64 used = kTmpChunkEntries;
-      for (const Pair& pr : closeL[k]) {
-        const i64 t = pr.t, s = pr.s, nt = n_act[t], ns = n_act[s];
-        if (used + nt * ns > kTmpChunkEntries) {
-          lv.close1.emplace_back();
-          lv.close2.emplace_back();
-          used = 0;
+  };
+  // 4. close pairs, one unit per chunk of temporary space
+  auto close_unit = [&](int k, size_t ch) {
+    char* Ccur = static_cast<char*>(sp.dC[k % 2].ptr);
+    char* Cnext = static_cast<char*>(sp.dC[(k + 1) % 2].ptr);
+    char* Gnext = static_cast<char*>(sp.dG[(k + 1) % 2].ptr);
+    SweepLevel& lv = sp.levels[k];
+    GemmBatch& g1 = lv.close1[ch];
+    GemmBatch& g2 = lv.close2[ch];
+    i64 used = 0;
+    for (i64 i = close_cut[k][ch]; i < close_cut[k][ch + 1]; ++i) {
+      const Pair& pr = closeL[k][i];
+      const i64 t = pr.t, s = pr.s, nt = n_act[t], ns = n_act[s];
+      char* w = tmp + el * used;
+      used += nt * ns;
+      GemmItem& a = g1.item(int(nt), int(ns), int(nt), int(ns));
+      GemmBatch::set_out(a, 0, w, nt, false);
+      if (k == 0)
+        g1.seg_gen(X + tr.start[t] * dim, X + tr.start[s] * dim, t == s, Qt + el * sp.q_off[s], int(ns), false,
+                   int(ns));
+      else
+        g1.seg(Ccur + el * cslot[k].at(key(t, s, ncl)), int(nt), false, Qt + el * sp.q_off[s], int(ns), false,
+               int(ns));
+      GemmItem& b = g2.item(int(nt), int(ns), int(kept[t]), int(kept[s]));
+      if (mb[t] > 0 && mb[s] > 0) set_s_out(b, 3, t, s);
+      if (k < L) {
+        const i64 pt = (t - 1) / 2, ps = (s - 1) / 2;
+        if (kept[t] > 0 && kept[s] > 0) {
+          char* cs = Cnext + el * cslot[k + 1].at(key(pt, ps, ncl));
+          GemmBatch::set_out(b, 0, cs + el * (son_off(t) + son_off(s) * n_act[pt]), n_act[pt], false);
+          if (pt == ps && t != s)
+            GemmBatch::set_out(b, 4, cs + el * (son_off(s) + son_off(t) * n_act[pt]), n_act[pt], true);
         }
-        GemmBatch& g1 = lv.close1.back();
-        GemmBatch& g2 = lv.close2.back();
-        char* w = tmp + el * used;
-        used += nt * ns;
-        GemmItem& a = g1.item(int(nt), int(ns), int(nt), int(ns));
-        GemmBatch::set_out(a, 0, w, nt, false);
-        if (k == 0)
-          g1.seg_gen(X + tr.start[t] * dim, X + tr.start[s] * dim, t == s, Qt + el * sp.q_off[s], int(ns), false,
-                     int(ns));
-        else
-          g1.seg(Ccur + el * cslot[k].at(key(t, s, ncl)), int(nt), false, Qt + el * sp.q_off[s], int(ns), false,
-                 int(ns));
-        GemmItem& b = g2.item(int(nt), int(ns), int(kept[t]), int(kept[s]));
-        if (mb[t] > 0 && mb[s] > 0) set_s_out(b, 3, t, s);
-        if (k < L) {
-          const i64 pt = (t - 1) / 2, ps = (s - 1) / 2;
-          if (kept[t] > 0 && kept[s] > 0) {
-            char* cs = Cnext + el * cslot[k + 1].at(key(pt, ps, ncl));
-            GemmBatch::set_out(b, 0, cs + el * (son_off(t) + son_off(s) * n_act[pt]), n_act[pt], false);
-            if (pt == ps && t != s)
-              GemmBatch::set_out(b, 4, cs + el * (son_off(s) + son_off(t) * n_act[pt]), n_act[pt], true);
-          }
-          if (mb[t] > 0 && kept[s] > 0) {
-            const i64 slot = gslot[k + 1].at(key(t, ps, ncl));
-            GemmBatch::set_out(b, 2, Gnext + el * (slot + son_off(s) * mb[t]), mb[t], false);
-          }
-          if (t != s && mb[s] > 0 && kept[t] > 0) {
-            const i64 slot = gslot[k + 1].at(key(s, pt, ncl));
-            GemmBatch::set_out(b, 1, Gnext + el * (slot + son_off(t) * mb[s]), mb[s], true);
-          }
+        if (mb[t] > 0 && kept[s] > 0) {
+          const i64 slot = gslot[k + 1].at(key(t, ps, ncl));
+          GemmBatch::set_out(b, 2, Gnext + el * (slot + son_off(s) * mb[t]), mb[t], false);
         }
-        g2.seg(Qt + el * sp.q_off[t], int(nt), true, w, int(nt), false, int(nt));
+        if (t != s && mb[s] > 0 && kept[t] > 0) {
+          const i64 slot = gslot[k + 1].at(key(s, pt, ncl));
+          GemmBatch::set_out(b, 1, Gnext + el * (slot + son_off(t) * mb[s]), mb[s], true);
+        }
       }
-      for (auto& g : lv.close1) pc.flops_close += g.flops;
-      for (auto& g : lv.close2) pc.flops_close += g.flops;
+      g2.seg(Qt + el * sp.q_off[t], int(nt), true, w, int(nt), false, int(nt));
     }
-    // 5. couplings R^_a D_ab R^_b^T into the father's close block
-    {
-      i64 used = kTmpChunkEntries;
-      for (const Pair& pr : coupL[k]) {
-        const i64 a = pr.t, b = pr.s;
-        const i64 ka = kept[a], kb = kept[b];
-        if (ka == 0 || kb == 0) fail(H2_EINVAL, "internal: coupling of a cluster without kept rows");
-        if (used + P * kb > kTmpChunkEntries) {
-          lv.coup1.emplace_back();
-          lv.coup2.emplace_back();
-          used = 0;
-        }
-        GemmBatch& g1 = lv.coup1.back();
-        GemmBatch& g2 = lv.coup2.back();
-        char* w = tmp + el * used;
-        used += P * kb;
-        GemmItem& i1 = g1.item(P, int(kb), P, int(kb));
-        GemmBatch::set_out(i1, 0, w, P, false);
-        g1.seg_gen(nodes + a * i64(P) * dim, nodes + b * i64(P) * dim, false, Wt + el * wtoff[b], int(kb), true, P);
-        const i64 pa = (a - 1) / 2, pb = (b - 1) / 2;
-        GemmItem& i2 = g2.item(int(ka), int(kb), int(ka), int(kb));
-        char* cs = Cnext + el * cslot[k + 1].at(key(pa, pb, ncl));
-        GemmBatch::set_out(i2, 0, cs + el * (son_off(a) + son_off(b) * n_act[pa]), n_act[pa], false);
-        if (pa == pb)
-          GemmBatch::set_out(i2, 4, cs + el * (son_off(b) + son_off(a) * n_act[pa]), n_act[pa], true);
-        g2.seg(Wt + el * wtoff[a], int(ka), false, w, P, false, P);
+    close_pc[k][ch].flops_close = g1.flops + g2.flops;
+  };
+  // 5. couplings R^_a D_ab R^_b^T into the father's close block, per chunk
+  auto coup_unit = [&](int k, size_t ch) {
+    char* Cnext = static_cast<char*>(sp.dC[(k + 1) % 2].ptr);
+    SweepLevel& lv = sp.levels[k];
+    GemmBatch& g1 = lv.coup1[ch];
+    GemmBatch& g2 = lv.coup2[ch];
+    i64 used = 0;
+    for (i64 i = coup_cut[k][ch]; i < coup_cut[k][ch + 1]; ++i) {
+      const Pair& pr = coupL[k][i];
+      const i64 a = pr.t, b = pr.s;
+      const i64 ka = kept[a], kb = kept[b];
+      if (ka == 0 || kb == 0) fail(H2_EINVAL, "internal: coupling of a cluster without kept rows");
+      char* w = tmp + el * used;
+      used += P * kb;
+      GemmItem& i1 = g1.item(P, int(kb), P, int(kb));
+      GemmBatch::set_out(i1, 0, w, P, false);
+      g1.seg_gen(nodes + a * i64(P) * dim, nodes + b * i64(P) * dim, false, Wt + el * wtoff[b], int(kb), true, P);
+      const i64 pa = (a - 1) / 2, pb = (b - 1) / 2;
+      GemmItem& i2 = g2.item(int(ka), int(kb), int(ka), int(kb));
+      char* cs = Cnext + el * cslot[k + 1].at(key(pa, pb, ncl));
+      GemmBatch::set_out(i2, 0, cs + el * (son_off(a) + son_off(b) * n_act[pa]), n_act[pa], false);
+      if (pa == pb)
+        GemmBatch::set_out(i2, 4, cs + el * (son_off(b) + son_off(a) * n_act[pa]), n_act[pa], true);
+      g2.seg(Wt + el * wtoff[a], int(ka), false, w, P, false, P);
+    }
+    coup_pc[k][ch].flops_coup = g1.flops + g2.flops;
+  };
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long u = 0; u < long(units.size()); ++u) {
+    const Unit un = units[u];
+    guarded([&] {
+      switch (un.kind) {
+        case 0: qr_unit(un.k); break;
+        case 1: strip_unit(un.k, size_t(un.idx)); break;
+        case 2: close_unit(un.k, size_t(un.idx)); break;
+        default: coup_unit(un.k, size_t(un.idx)); break;
       }
-      for (auto& g : lv.coup1) pc.flops_coup += g.flops;
-      for (auto& g : lv.coup2) pc.flops_coup += g.flops;
-    }
-   } catch (const Error& e) {
-#pragma omp critical
-    if (!first_code) { first_code = e.code; first_error = e.msg; }
-   } catch (const std::exception& e) {
-#pragma omp critical
-    if (!first_code) { first_code = H2_EINVAL; first_error = e.what(); }
-   }
+    });
+  }
+  // strip runs appended in order (levels in parallel), per-chunk counts summed
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int k = 0; k <= L; ++k) {
+    if (first_code) continue;
+    guarded([&, k] {
+      SweepLevel& lv = sp.levels[k];
+      size_t ni = 0, ns = 0;
+      for (const GemmBatch& g : strip_runs[k]) ni += g.items.size(), ns += g.segs.size();
+      lv.strips.items.reserve(ni);
+      lv.strips.segs.reserve(ns);
+      for (GemmBatch& g : strip_runs[k]) lv.strips.append(g);
+      lpc[k].flops_strip += lv.strips.flops;
+      for (const PlanCounts& c : close_pc[k]) lpc[k].flops_close += c.flops_close;
+      for (const PlanCounts& c : coup_pc[k]) lpc[k].flops_coup += c.flops_coup;
+    });
   }
   if (first_code) fail(first_code, first_error);
   for (const PlanCounts& c : lpc) {
