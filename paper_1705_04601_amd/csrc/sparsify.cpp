@@ -17,6 +17,8 @@
 // S keeps its upper block triangle (S symmetric, Proposition 2.1): lower-level
 // rows first, clusters left to right.
 #include <algorithm>
+#include <cstdio>
+#include <chrono>
 #include <cstring>
 #include <memory>
 #include <parallel/algorithm>
@@ -56,6 +58,19 @@ class SlotMap {
     ++size_;
     return true;
   }
+  // inserts a key known to be absent, from several threads at once; the table
+  // must have been reserved for every key inserted this way (no growth)
+  void insert_distinct_concurrent(i64 k, i64 v) {
+    const size_t mask = keys_.size() - 1;
+    size_t h = hash(k) & mask;
+    while (true) {
+      i64 expect = -1;
+      if (__atomic_compare_exchange_n(&keys_[h], &expect, k, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) break;
+      h = (h + 1) & mask;
+    }
+    vals_[h] = v;
+  }
+  void count_inserted(size_t n) { size_ += n; }
   i64 at(i64 k) const {
     if (!keys_.empty()) {
       size_t h = hash(k) & (keys_.size() - 1);
@@ -176,32 +191,82 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
   for (i64 i = 0; i < ncl; ++i) sp.epos[sp.eorder[i]] = i;
   const auto& epos = sp.epos;
 
+  tt.lap("order");
   // ---- symbolic sweep: strips, close/coupling lists, C slots, S blocks
   std::vector<std::vector<Pair>> closeL(L + 1), coupL(L + 1);
   std::vector<std::vector<SymStrip>> stripL(L + 2);
   std::vector<SlotMap> cslot(L + 2), gslot(L + 2);
   std::vector<i64> csize(L + 2, 0), gsize(L + 2, 0);
   std::vector<std::pair<i64, i64>> blocks;  // (t, s) with epos(t) <= epos(s)
+  double sym_ms[3] = {0, 0, 0};             // traced split of the sweep
+  // Per level, in parallel: every strip of the level and every close pair
+  // writes its S block and its candidate strips of the next level at fixed
+  // positions (strips first, then pairs, in order); the candidates are then
+  // made distinct keeping each key's first occurrence, and the next level's
+  // strips take their slots in that order (the layout a sequential sweep
+  // gives).
+  struct Cand {
+    i64 key;
+    int32_t tau, p;
+  };
   for (int k = 0; k <= L; ++k) {
-    auto add_strip = [&](i64 tau, i64 p) {
-      if (!gslot[k + 1].insert(key(tau, p, ncl), gsize[k + 1])) return;
-      stripL[k + 1].push_back({int32_t(tau), int32_t(p), gsize[k + 1]});
-      gsize[k + 1] += mb[tau] * n_act[p];
-    };
-    for (const SymStrip& g : stripL[k]) {
-      if (mb[g.p] > 0) blocks.push_back({g.tau, g.p});
-      if (kept[g.p] > 0 && g.p > 0) add_strip(g.tau, (g.p - 1) / 2);
-    }
-    for (const Pair& pr : H->bt.near[k]) {
-      const i64 t = pr.t, s = pr.s;
-      if (t > s || n_act[t] == 0 || n_act[s] == 0) continue;
-      closeL[k].push_back(pr);
-      if (mb[t] > 0 && mb[s] > 0) blocks.push_back(epos[t] <= epos[s] ? std::make_pair(t, s) : std::make_pair(s, t));
-      if (k < L) {
-        if (mb[t] > 0 && kept[s] > 0) add_strip(t, (s - 1) / 2);
-        if (t != s && mb[s] > 0 && kept[t] > 0) add_strip(s, (t - 1) / 2);
+    const auto c0 = std::chrono::steady_clock::now();
+    const std::vector<SymStrip>& sk = stripL[k];
+    const std::vector<Pair>& nk = H->bt.near[k];
+    const long ns = long(sk.size()), nn = long(nk.size());
+    std::vector<Cand> cand(size_t(ns + 2 * nn), Cand{-1, 0, 0});
+    std::vector<std::pair<i64, i64>> blk(size_t(ns + nn), std::make_pair(i64(-1), i64(-1)));
+    std::vector<char> is_close(size_t(nn), 0);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < ns; ++i) {
+      const SymStrip& g = sk[i];
+      if (mb[g.p] > 0) blk[i] = {g.tau, g.p};
+      if (kept[g.p] > 0 && g.p > 0) {
+        const i64 f = (g.p - 1) / 2;
+        cand[i] = {key(g.tau, f, ncl), g.tau, int32_t(f)};
       }
     }
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < nn; ++j) {
+      const i64 t = nk[j].t, s = nk[j].s;
+      if (t > s || n_act[t] == 0 || n_act[s] == 0) continue;
+      is_close[j] = 1;
+      if (mb[t] > 0 && mb[s] > 0) blk[ns + j] = epos[t] <= epos[s] ? std::make_pair(t, s) : std::make_pair(s, t);
+      if (k < L) {
+        if (mb[t] > 0 && kept[s] > 0) cand[ns + 2 * j] = {key(t, (s - 1) / 2, ncl), int32_t(t), int32_t((s - 1) / 2)};
+        if (t != s && mb[s] > 0 && kept[t] > 0)
+          cand[ns + 2 * j + 1] = {key(s, (t - 1) / 2, ncl), int32_t(s), int32_t((t - 1) / 2)};
+      }
+    }
+    for (long j = 0; j < nn; ++j)
+      if (is_close[j]) closeL[k].push_back(nk[j]);
+    for (const auto& b : blk)
+      if (b.first >= 0) blocks.push_back(b);
+    const auto c1 = std::chrono::steady_clock::now();
+    // distinct candidates, first occurrence first
+    std::vector<std::pair<i64, i64>> kv;  // (key, position)
+    kv.reserve(cand.size());
+    for (size_t q = 0; q < cand.size(); ++q)
+      if (cand[q].key >= 0) kv.push_back({cand[q].key, i64(q)});
+    __gnu_parallel::sort(kv.begin(), kv.end());
+    std::vector<i64> first;
+    first.reserve(kv.size());
+    for (size_t q = 0; q < kv.size(); ++q)
+      if (q == 0 || kv[q].first != kv[q - 1].first) first.push_back(kv[q].second);
+    __gnu_parallel::sort(first.begin(), first.end());
+    std::vector<SymStrip>& nxt = stripL[k + 1];
+    nxt.reserve(first.size());
+    for (i64 q : first) {
+      const Cand& c = cand[size_t(q)];
+      nxt.push_back({c.tau, c.p, gsize[k + 1]});
+      gsize[k + 1] += mb[c.tau] * n_act[c.p];
+    }
+    gslot[k + 1].reserve(nxt.size());
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < long(nxt.size()); ++q)
+      gslot[k + 1].insert_distinct_concurrent(key(nxt[q].tau, nxt[q].p, ncl), nxt[q].slot);
+    gslot[k + 1].count_inserted(nxt.size());
+    const auto c2 = std::chrono::steady_clock::now();
     for (const Pair& pr : H->bt.far[k])
       if (pr.t < pr.s) coupL[k].push_back(pr);
     if (k < L) {
@@ -212,7 +277,15 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
         csize[k + 1] += n_act[pr.t] * n_act[pr.s];
       }
     }
+    const auto c3 = std::chrono::steady_clock::now();
+    sym_ms[0] += std::chrono::duration<double, std::milli>(c1 - c0).count();
+    sym_ms[1] += std::chrono::duration<double, std::milli>(c2 - c1).count();
+    sym_ms[2] += std::chrono::duration<double, std::milli>(c3 - c2).count();
   }
+  if (trace_enabled())
+    std::fprintf(stderr, "[h2sp] sparsify-plan symbolic: blocks and candidates %.1f ms, distinct strips %.1f ms, far pairs and slots %.1f ms; "
+                 "%zu blocks, %zu strips\n", sym_ms[0], sym_ms[1], sym_ms[2], blocks.size(),
+                 [&] { size_t n = 0; for (auto& v : stripL) n += v.size(); return n; }());
   tt.lap("symbolic");
   // ---- upper block pattern in the elimination order: blocks as
   // (row position, column position) keys, sorted in parallel
