@@ -537,12 +537,10 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       upload_batches(all, chunk_desc.back(), blobs, cstream, st, /*parallel_pack=*/false);
       for (int lv = next; lv < end; ++lv) {
         FactorLevel<T>& L = lvls[lv];
-        // zero rows of the padded Z_ki blocks (the buffer holds the previous
-        // level's blocks in another layout)
-        if (L.zlen > 0) {
-          if constexpr (std::is_same<T, float>::value) launch_fill_f(Z, L.zlen, 0.0f, st);
-          else launch_fill(Z, L.zlen, 0.0, st);
-        }
+        // the Schur kernel reads a Z_ki block up to its K rounded up to 4
+        // (the lane holding K): rows K .. K4 - 1 must be zero; the buffer
+        // holds the previous level's blocks in another layout
+        launch_zero_pad_rows<T>(L.d_cps, int(L.cps.size()), Z, st);
         L.zb.template launch<T>(st);
         mark_ev();
         L.nschur_tiles = int32_t(L.stiles.size());

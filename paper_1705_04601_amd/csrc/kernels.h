@@ -133,6 +133,10 @@ struct CopySeg {
 };
 template <class T>
 void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st);
+// For every segment: zeroes rows rows .. (rows rounded up to 4) - 1 of the
+// block at src (cols columns, leading dimension src_ld >= that bound).
+template <class T>
+void launch_zero_pad_rows(const CopySeg* segs, int count, T* src, hipStream_t st);
 
 // Kernel blocks written out: element (k, j) of block b, at out[b.off + k + j ns],
 // is scale / |x_{t0 + j} - x_{s0 + k}| (dim coordinates per point, points

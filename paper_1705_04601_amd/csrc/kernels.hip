@@ -767,6 +767,19 @@ __global__ __launch_bounds__(256) void copy_segments_kernel(const CopySeg* segs,
     for (int r = lane; r < s.rows; r += 64) dst[s.dst + int64_t(c) * s.rows + r] = src[s.src + int64_t(c) * s.src_ld + r];
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void zero_pad_rows_kernel(const CopySeg* segs, int count, T* src) {
+  // one segment per 64 lanes: lane (column, pad row)
+  const int sid = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (sid >= count) return;
+  const CopySeg s = segs[sid];
+  const int pad = ((s.rows + 3) & ~3) - s.rows;
+  for (int e = lane; e < pad * s.cols; e += 64) {
+    const int c = e / pad, r = s.rows + e % pad;
+    src[s.src + int64_t(c) * s.src_ld + r] = T(0);
+  }
+}
+
 int grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 65536) g = 65536;
@@ -877,6 +890,12 @@ void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, 
     hipLaunchKernelGGL(copy_segments_kernel<T>, dim3(8, c), dim3(256), 0, st, segs + c0, src, dst);
   }
 }
+template <class T>
+void launch_zero_pad_rows(const CopySeg* segs, int count, T* src, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(zero_pad_rows_kernel<T>, dim3((count + 3) / 4), dim3(256), 0, st, segs, count, src);
+}
+template void launch_zero_pad_rows<double>(const CopySeg*, int, double*, hipStream_t);
+template void launch_zero_pad_rows<float>(const CopySeg*, int, float*, hipStream_t);
 template void launch_copy_segments<double>(const CopySeg*, int, const double*, double*, hipStream_t);
 template void launch_copy_segments<float>(const CopySeg*, int, const float*, float*, hipStream_t);
 
