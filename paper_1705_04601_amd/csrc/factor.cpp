@@ -389,6 +389,23 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     }
     split_targets(items, L);
     if (L.sitems.size() >= (size_t(1) << 24)) too_wide = 1;
+    // Tiles in the order of the Z_ki position where their first segment
+    // starts: rows stay together (their Z ranges are disjoint and in row
+    // order), and inside a row the tiles that run at the same time on one XCD
+    // walk the same part of the row's Z strip, which L2 then serves to all of
+    // them (measured 3% faster than target order).
+    if (L.stiles.size() < (size_t(1) << 24)) {
+      std::vector<int64_t> ord(L.stiles.size());
+#pragma omp parallel for schedule(static) num_threads(nthr)
+      for (long q = 0; q < long(ord.size()); ++q) {
+        const SchurItem& it = L.sitems[uint32_t(L.stiles[q]) >> 8];
+        ord[q] = (int64_t(L.ssegs[it.seg_begin].a_off) << 24) | int64_t(q);
+      }
+      __gnu_parallel::sort(ord.begin(), ord.end());
+      std::vector<int32_t> st(ord.size());
+      for (size_t q = 0; q < ord.size(); ++q) st[q] = L.stiles[size_t(ord[q] & 0xffffff)];
+      L.stiles.swap(st);
+    }
     if (trace_level() >= 2 && !L.stiles.empty()) {
       // the kernel gives XCD x the x-th contiguous eighth of the tile list
       const i64 n = i64(L.stiles.size()), base = n / 8, rem = n % 8;
