@@ -147,6 +147,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   double kUnits = 32768;  // H2SP_SCHUR_UNITS overrides
   if (const char* e = std::getenv("H2SP_SCHUR_UNITS")) kUnits = std::max(1.0, std::atof(e));
 
+  bool zpos_order = true;  // Schur tiles by Z position inside each XCD's share (H2SP_SCHUR_ORDER=0: by target)
+  if (const char* e = std::getenv("H2SP_SCHUR_ORDER")) zpos_order = e[0] != '0';
   i64 kMinK = 512;  // smallest K of a part; H2SP_SCHUR_SPLIT_K overrides it
   if (const char* e = std::getenv("H2SP_SCHUR_SPLIT_K")) kMinK = std::max<i64>(1, std::atoll(e));
   const i64 pcap = f.pcap;
@@ -389,21 +391,30 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     }
     split_targets(items, L);
     if (L.sitems.size() >= (size_t(1) << 24)) too_wide = 1;
-    // Tiles in the order of the Z_ki position where their first segment
-    // starts: rows stay together (their Z ranges are disjoint and in row
-    // order), and inside a row the tiles that run at the same time on one XCD
-    // walk the same part of the row's Z strip, which L2 then serves to all of
-    // them (measured 3% faster than target order).
-    if (L.stiles.size() < (size_t(1) << 24)) {
-      std::vector<int64_t> ord(L.stiles.size());
-#pragma omp parallel for schedule(static) num_threads(nthr)
-      for (long q = 0; q < long(ord.size()); ++q) {
+    // Inside each XCD's share of the tile list (the kernel gives XCD x the
+    // x-th contiguous eighth, so the shares keep the work balance of target
+    // order), tiles go in the order of the Z_ki position where their first
+    // segment starts: the tiles that run at the same time on one XCD then walk
+    // the same part of a row's Z strip, which its L2 serves to all of them.
+    // Levels of fewer than 16384 tiles keep target order: there the planning
+    // thread, not the kernel, sets the pace, and the sort would cost more than
+    // it saves.  H2SP_SCHUR_ORDER=0 keeps target order throughout.
+    if (zpos_order && L.stiles.size() >= 16384 && L.stiles.size() < (size_t(1) << 24)) {
+      const i64 n = i64(L.stiles.size()), base = n / 8, rem = n % 8;
+      std::vector<int64_t> ord(static_cast<size_t>(n));
+#pragma omp parallel for schedule(static) num_threads(nthr) if (n > 65536)
+      for (long q = 0; q < long(n); ++q) {
         const SchurItem& it = L.sitems[uint32_t(L.stiles[q]) >> 8];
         ord[q] = (int64_t(L.ssegs[it.seg_begin].a_off) << 24) | int64_t(q);
       }
-      __gnu_parallel::sort(ord.begin(), ord.end());
-      std::vector<int32_t> st(ord.size());
-      for (size_t q = 0; q < ord.size(); ++q) st[q] = L.stiles[size_t(ord[q] & 0xffffff)];
+#pragma omp parallel for schedule(static) num_threads(std::min(nthr, 8)) if (n > 4096)
+      for (int x = 0; x < 8; ++x) {
+        const i64 b0 = x * base + std::min<i64>(x, rem), b1 = (x + 1) * base + std::min<i64>(x + 1, rem);
+        std::sort(ord.begin() + b0, ord.begin() + b1);
+      }
+      std::vector<int32_t> st(static_cast<size_t>(n));
+#pragma omp parallel for schedule(static) num_threads(nthr) if (n > 65536)
+      for (long q = 0; q < long(n); ++q) st[q] = L.stiles[size_t(ord[q] & 0xffffff)];
       L.stiles.swap(st);
     }
     if (trace_level() >= 2 && !L.stiles.empty()) {
@@ -474,7 +485,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
           bb.push_back({sg.b_off, i64(sg.K) * it.N});
           stream += double(sizeof(T)) * (double(kpad16(sg.K)) * it.M + double(sg.K) * it.N);
         }
-      __gnu_parallel::sort(bb.begin(), bb.end());
+      sort_range(bb.begin(), bb.end());
       double once = double(sizeof(T)) * double(L.zlen);
       for (size_t q = 0; q < bb.size(); ++q)
         if (q == 0 || bb[q].first != bb[q - 1].first) once += double(sizeof(T)) * double(bb[q].second);
@@ -618,11 +629,12 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     if (trace_level() >= 2)
       std::fprintf(stderr,
                    "[h2sp] factor level %d: %zu rows, %d Schur tiles, %.4g GFLOP, %.3f ms (%.1f TF), XCD imbalance %.3f, "
-                   "rows per target column %.2f, rows per pivot %.2f, operands once %.3f GB, per tile %.3f GB, "
+                   "Z %.4f GB, rows per target column %.2f, rows per pivot %.2f, operands once %.3f GB, per tile %.3f GB, "
                    "grouped pivots x%.2f (2) x%.2f (4); "
                    "pivots and Z %.3f ms\n",
                    lv, by_level[lv].size(), lvls[lv].nschur_tiles, lvls[lv].schur_flops / 1e9, b,
-                   lvls[lv].schur_flops / std::max(1e-6, double(b)) / 1e9, lvls[lv].xcd_imbalance, lvls[lv].col_share,
+                   lvls[lv].schur_flops / std::max(1e-6, double(b)) / 1e9, lvls[lv].xcd_imbalance,
+                   double(lvls[lv].zlen) * sizeof(T) / 1e9, lvls[lv].col_share,
                    lvls[lv].piv_share, lvls[lv].once_bytes / 1e9, lvls[lv].stream_bytes / 1e9, lvls[lv].union2,
                    lvls[lv].union4, a + c);
   }

@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <parallel/algorithm>
+
 #include <cstdint>
 #include <functional>
 #include <string>
@@ -91,6 +94,15 @@ struct DeviceBuffer {
   void reset(size_t b, hipStream_t first_use = nullptr);
   template <class T> T* as() const { return static_cast<T*>(ptr); }
 };
+
+// Sort of a random-access range: in parallel (GNU parallel mode, OpenMP) when
+// it is long, plainly when it is short (the parallel sort's team start costs
+// more than a short sort, and plans run many of them, one per level).
+template <class It>
+void sort_range(It first, It last) {
+  if (last - first >= (1 << 17)) __gnu_parallel::sort(first, last);
+  else std::sort(first, last);
+}
 
 // Bytes held by idle cached blocks (free for the library's own allocations).
 size_t cached_device_bytes();

@@ -248,12 +248,12 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
     kv.reserve(cand.size());
     for (size_t q = 0; q < cand.size(); ++q)
       if (cand[q].key >= 0) kv.push_back({cand[q].key, i64(q)});
-    __gnu_parallel::sort(kv.begin(), kv.end());
+    sort_range(kv.begin(), kv.end());
     std::vector<i64> first;
     first.reserve(kv.size());
     for (size_t q = 0; q < kv.size(); ++q)
       if (q == 0 || kv[q].first != kv[q - 1].first) first.push_back(kv[q].second);
-    __gnu_parallel::sort(first.begin(), first.end());
+    sort_range(first.begin(), first.end());
     std::vector<SymStrip>& nxt = stripL[k + 1];
     nxt.reserve(first.size());
     for (i64 q : first) {
@@ -293,7 +293,7 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
   for (size_t b = 0; b < blocks.size(); ++b)
     bkeys[b] = (uint64_t(epos[blocks[b].first]) << 32) | uint64_t(epos[blocks[b].second]);
   std::vector<std::pair<i64, i64>>().swap(blocks);
-  __gnu_parallel::sort(bkeys.begin(), bkeys.end());
+  sort_range(bkeys.begin(), bkeys.end());
   if (std::adjacent_find(bkeys.begin(), bkeys.end()) != bkeys.end())
     fail(H2_EINVAL, "internal: duplicate S block");
   sp.rowptr.assign(ncl + 1, 0);
