@@ -252,6 +252,18 @@ int h2_last_timings(double* ms, int count);
  * the fill in exact mode).  Entries past [9] are zero; count may be up to 16. */
 int h2_last_work(double* work, int count);
 
+/* Environment variables read by the library (tuning and diagnostics only; the
+ * results do not depend on them beyond rounding order):
+ *   H2SP_TRACE=1 host phase timings and statistics on stderr; =2 adds one line
+ *     per factorisation level (tiles, flops, time, XCD spread, operand bytes);
+ *   H2SP_SCHUR_UNITS (default 32768) and H2SP_SCHUR_SPLIT_K (default 512):
+ *     split-K granularity of the Schur update (tile units per level, smallest
+ *     K of a part);
+ *   H2SP_SCHUR_ORDER=0: Schur tiles in target order instead of by Z position;
+ *   H2SP_CLOSE_RESIDENT=0: never keep the matvec's close blocks on the device;
+ *   H2SP_GRAPHS=0: run the solve and matvec sweeps eagerly instead of as
+ *     captured HIP graphs. */
+
 #ifdef __cplusplus
 }
 #endif
