@@ -792,8 +792,10 @@ int grid_for(int64_t n) {
 // Output tile of each kernel instance, in 16 x 16 blocks (rows x columns).
 // Measured on the solve sweeps, the sparsification transforms and the pivot
 // GEMMs (short K, many items): 32 x 32 tiles, with more waves per SIMD, beat
-// 64 x 64 ones; a generated operand is shared by more blocks in 64 x 32 tiles.
+// 64 x 64 ones; a generated operand is shared by more blocks in 64 x 32 tiles,
+// and the transforms whose two operands both run along K take 64 x 32 too.
 constexpr int tile_mb(int role, int am, int bm) {
+  if (role == ROLE_TRANSFORM && am == 0 && bm == 0) return 4;
   return (role == ROLE_MATVEC && bm == 2) || (role == ROLE_TRANSFORM && am == 2) ? 4
          : (role == ROLE_MATVEC)                                                 ? 4
                                                                                  : 2;
