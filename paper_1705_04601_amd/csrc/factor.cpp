@@ -147,8 +147,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   double kUnits = 32768;  // H2SP_SCHUR_UNITS overrides
   if (const char* e = std::getenv("H2SP_SCHUR_UNITS")) kUnits = std::max(1.0, std::atof(e));
 
-  bool zpos_order = true;  // Schur tiles by Z position inside each XCD's share (H2SP_SCHUR_ORDER=0: by target)
-  if (const char* e = std::getenv("H2SP_SCHUR_ORDER")) zpos_order = e[0] != '0';
+  // Levels of at least zpos_min tiles order their Schur tiles by Z position
+  // inside each XCD's share; H2SP_SCHUR_ORDER=0 never does, =2 on every level.
+  size_t zpos_min = 16384;
+  if (const char* e = std::getenv("H2SP_SCHUR_ORDER"))
+    zpos_min = e[0] == '0' ? SIZE_MAX : e[0] == '2' ? 1 : zpos_min;
   i64 kMinK = 512;  // smallest K of a part; H2SP_SCHUR_SPLIT_K overrides it
   if (const char* e = std::getenv("H2SP_SCHUR_SPLIT_K")) kMinK = std::max<i64>(1, std::atoll(e));
   const i64 pcap = f.pcap;
@@ -398,8 +401,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     // the same part of a row's Z strip, which its L2 serves to all of them.
     // Levels of fewer than 16384 tiles keep target order: there the planning
     // thread, not the kernel, sets the pace, and the sort would cost more than
-    // it saves.  H2SP_SCHUR_ORDER=0 keeps target order throughout.
-    if (zpos_order && L.stiles.size() >= 16384 && L.stiles.size() < (size_t(1) << 24)) {
+    // it saves.  The order changes no result: every tile writes its own
+    // output block, and partial sums are added by a later launch.
+    if (L.stiles.size() >= zpos_min && L.stiles.size() < (size_t(1) << 24)) {
       const i64 n = i64(L.stiles.size()), base = n / 8, rem = n % 8;
       std::vector<int64_t> ord(static_cast<size_t>(n));
 #pragma omp parallel for schedule(static) num_threads(nthr) if (n > 65536)

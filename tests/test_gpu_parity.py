@@ -228,6 +228,30 @@ def test_split_schur_targets_mixed_solve(monkeypatch):
     assert np.abs(host(xs) - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("split_k", [None, "4"], ids=["whole", "splitk"])
+@pytest.mark.parametrize("precision", [P.H2_FP64, P.H2_MIXED], ids=["fp64", "mixed"])
+def test_schur_tile_order_changes_no_bit(precision, split_k, monkeypatch):
+    """Schur tiles ordered by Z position (forced on every level) give the same
+    factor, bit for bit, as target order: each tile writes its own block."""
+    x, sc, h2, sp, a, _ = case("cube2500r48")
+    note(f"schur tile order precision={precision} split_k={split_k}")
+    if split_k:
+        monkeypatch.setenv("H2SP_SCHUR_SPLIT_K", split_k)
+    h = imported("cube2500r48")
+    b = np.random.default_rng(9).standard_normal((x.shape[0], 2))
+    outs = []
+    for order in ("0", "2"):
+        monkeypatch.setenv("H2SP_SCHUR_ORDER", order)
+        f = P.h2_factor_S(P.h2_sparsify(h, precision))
+        if split_k:
+            assert P.h2_last_work()[7] > 0
+        out = dev(np.zeros_like(b))
+        P.h2_apply_inverse(f, dev(b), out)
+        outs.append(host(out))
+    assert np.isfinite(outs[0]).all()
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_exact_factor_fill_and_inverse(name):
     """Exact mode: the filled pattern matches the oracle's graph elimination
