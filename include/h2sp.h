@@ -40,14 +40,20 @@ enum {
 };
 
 /* ---- options --------------------------------------------------------------- */
-enum { H2_KERNEL_INVDIST = 0 }; /* A_ij = scale / |x_i - x_j| (i != j), A_ii = diag */
+enum { H2_KERNEL_INVDIST = 0,   /* A_ij = scale / |x_i - x_j| (i != j), A_ii = diag */
+       H2_KERNEL_EXP = 1 };     /* A_ij = scale exp(-|x_i - x_j|^2) (i != j), A_ii =
+                                   diag: Example 2 of Section 6 (its matrix
+                                   2 delta_ij + exp(-|r_i - r_j|^2) is scale 1,
+                                   diag 3).  h2_sparsify_batch takes matrices
+                                   of one kernel kind (H2_EUNSUPPORTED
+                                   otherwise).                                 */
 enum { H2_FP64 = 0,             /* every step in FP64                                */
        H2_MIXED = 1 };          /* transforms, S and its factor in FP32 (MFMA), basis
                                    QR, pivot-block inversion and residuals in FP64   */
 
 typedef struct {
-  int kind;      /* H2_KERNEL_INVDIST                                           */
-  double scale;  /* c in c / |x - y|                                            */
+  int kind;      /* H2_KERNEL_INVDIST or H2_KERNEL_EXP                          */
+  double scale;  /* c in c / |x - y| or c exp(-|x - y|^2)                       */
   double diag;   /* value of A_ii                                               */
 } h2_kernel;
 
@@ -173,7 +179,8 @@ int h2_sparse_export_plan(const h2_sparse* sp, int64_t* n_act, int64_t* kept,
                           int64_t* rowptr, int64_t* colidx);
 /*
  * h2_sparsify_batch: sparsifies `count` independent H^2 matrices (uneven
- * sizes, ranks and depths allowed; one precision for all) in one level sweep:
+ * sizes, ranks and depths allowed; one precision and one kernel kind for
+ * all, H2_EUNSUPPORTED for matrices of different kernels) in one level sweep:
  * level k of every instance (from the leaves up) runs in the same QR,
  * transform and strip launches, their work lists concatenated.  outs[i]
  * receives the handle of hs[i], as h2_sparsify would return it; on error no

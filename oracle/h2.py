@@ -1,4 +1,4 @@
-"""Oracle: H^2 matrix of the kernel c/|x-y| by Chebyshev interpolation (FP64, CPU).
+"""Oracle: H^2 matrix of the kernel c/|x-y| (or c exp(-|x-y|^2)) by Chebyshev interpolation (FP64, CPU).
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this package.
 
@@ -36,29 +36,45 @@ from .tree import (BlockTree, ClusterTree, build_block_tree,
                    build_cluster_tree, farfield_nonempty)
 
 
+EXP = "exp"
+
+
 def kernel_block(xr: np.ndarray, xc: np.ndarray, scale: float, kernel=None) -> np.ndarray:
     """K_ij = scale / |xr_i - xc_j| for distinct points (no diagonal rule).
 
-    ``kernel`` (a function of two point arrays broadcasting to a matrix)
-    replaces the inverse distance; the tests use polynomial kernels for which
-    Chebyshev interpolation is exact.
+    ``kernel`` = EXP gives scale exp(-|xr_i - xc_j|^2), the smooth part of
+    the Gaussian matrix of Example 2 (equation of the "exp" core in Section
+    6); a function of two point arrays broadcasting to a matrix replaces the
+    inverse distance (the tests use polynomial kernels for which Chebyshev
+    interpolation is exact).
     """
+    diff = xr[:, None, :] - xc[None, :, :]
+    if isinstance(kernel, str):
+        assert kernel == EXP, kernel
+        return scale * np.exp(-(diff * diff).sum(axis=2))
     if kernel is not None:
         return kernel(xr[:, None, :], xc[None, :, :])
-    diff = xr[:, None, :] - xc[None, :, :]
     return scale / np.sqrt((diff * diff).sum(axis=2))
 
 
 def close_block(x: np.ndarray, ti: np.ndarray, si: np.ndarray, scale: float,
                 diag: float, kernel=None) -> np.ndarray:
-    """Kernel entries A[ti, si] with A_ii = diag (indices into x)."""
-    if kernel is not None:
+    """Kernel entries A[ti, si] with A_ii = diag (indices into x).
+
+    With kernel = EXP the entries are scale exp(-|x_i - x_j|^2) off the
+    diagonal; Example 2's matrix 2 delta_ij + exp(-|r_i - r_j|^2) is
+    scale = 1, diag = 3.
+    """
+    if kernel is not None and not isinstance(kernel, str):
         return kernel(x[ti][:, None, :], x[si][None, :, :])
     diff = x[ti][:, None, :] - x[si][None, :, :]
     r2 = (diff * diff).sum(axis=2)
     same = ti[:, None] == si[None, :]
-    with np.errstate(divide="ignore"):
-        out = scale / np.sqrt(r2)
+    if kernel == EXP:
+        out = scale * np.exp(-r2)
+    else:
+        with np.errstate(divide="ignore"):
+            out = scale / np.sqrt(r2)
     out[same] = diag
     return out
 
@@ -132,7 +148,7 @@ class H2Matrix:
     leaf_basis: dict          # leaf -> (|t|, r_t)
     transfer: dict            # son c -> (r_c, r_father)
     proj: dict                # t -> (r_t, P): coupling D_ts = P_t K_ts P_s^T
-    kernel: object = None     # optional replacement of the inverse distance
+    kernel: object = None     # EXP, or a replacement of the inverse distance
 
     def coupling(self, t: int, s: int) -> np.ndarray:
         k = kernel_block(self.nodes[t], self.nodes[s], self.scale, self.kernel)

@@ -52,6 +52,7 @@ struct GemmBatch {
   int mode = GEMM_STORE;
   int role = ROLE_TRANSFORM;
   int amode = -1, bmode = -1;  // operand layouts shared by every segment (build_tiles)
+  int kern = 0;                // kernel of generated operands, one per launch (build_tiles)
   double flops = 0.0;  // algorithmic flops of the batch
 
   bool empty() const { return items.empty(); }
@@ -143,6 +144,10 @@ struct GemmBatch {
     }
     if (amode >= 0 && !gemm_layout_supported(role, amode, bmode))
       fail(H2_EINVAL, "internal: no GEMM kernel for this role and operand layout");
+    kern = items.empty() ? 0 : items[0].gkern;
+    if (amode == 2 || bmode == 2)
+      for (const GemmItem& it : items)
+        if (it.gkern != kern) fail(H2_EUNSUPPORTED, "one sweep over matrices of different kernels");
     if (items.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "GEMM batch above 2^24 items");
     int em = 64, en = 64;  // tile of the kernel that runs the batch
     if (amode >= 0) {
@@ -165,9 +170,10 @@ struct GemmBatch {
     std::vector<GemmSeg>().swap(segs);
     std::vector<int32_t>().swap(tiles);
   }
-  // Parameters of generated operands (kernel c / |x - y|) for every item.
-  void set_generator(int dim, double scale, double diag) {
+  // Parameters of generated operands (kernel kind, as GemmItem::gkern) for every item.
+  void set_generator(int dim, int kern, double scale, double diag) {
     for (GemmItem& it : items) {
+      it.gkern = uint8_t(kern);
       it.gdim = dim;
       it.gscale = scale;
       it.gdiag = diag;
@@ -203,6 +209,7 @@ struct GemmBatch {
     g.ntiles = ntiles;
     g.mode = mode;
     g.role = role;
+    g.kern = kern;
     launch_gemm<T>(g, st);
   }
 };

@@ -227,7 +227,7 @@ Mat lagrange(const double* lo, const double* hi, int dim, int p, const double* p
   return out;
 }
 
-Mat kernel_at_nodes(const double* xr, const double* xc, int P, int dim, double scale) {
+Mat kernel_at_nodes(const double* xr, const double* xc, int P, int dim, int kern, double scale) {
   Mat k(P, P);
   for (int j = 0; j < P; ++j)
     for (int i = 0; i < P; ++i) {
@@ -236,7 +236,7 @@ Mat kernel_at_nodes(const double* xr, const double* xc, int P, int dim, double s
         const double d = xr[i * dim + a] - xc[j * dim + a];
         d2 += d * d;
       }
-      k(i, j) = scale / std::sqrt(d2);
+      k(i, j) = kern == H2_KERNEL_EXP ? scale * std::exp(-d2) : scale / std::sqrt(d2);
     }
   return k;
 }
@@ -252,6 +252,7 @@ void fill_structure(h2_matrix& H, const double* pts, i64 n, int dim, const h2_ke
   for (i64 i = 0; i < n; ++i)
     for (int a = 0; a < dim; ++a) H.x_tree[i * dim + a] = pts[H.tree.perm[i] * dim + a];
   H.scale = kern.scale;
+  H.kern = kern.kind;
   H.diag = kern.diag;
   H.cheb = o.cheb;
   H.P = 1;
@@ -362,7 +363,7 @@ void build_chebyshev(h2_matrix& H, double tol, int rank_cap) {
         Mat Ft(cols, q);  // F_t^T, stacked
         int off = 0;
         for (int32_t s : farOf[c]) {
-          Mat K = kernel_at_nodes(node_ptr(c), node_ptr(s), P, dim, H.scale);
+          Mat K = kernel_at_nodes(node_ptr(c), node_ptr(s), P, dim, H.kern, H.scale);
           Mat D = mul(mul(Z[c], false, K, false), false, Z[s], true);  // q x q_s
           for (int j = 0; j < q; ++j)
             for (int i = 0; i < D.n; ++i) Ft(off + i, j) = D(j, i);

@@ -11,10 +11,11 @@ namespace h2 {
 // opA = 0: A column-major M x K (element (i, k) at A[i + k lda]);
 // opA = 1: A stored K x M   (element (i, k) at A[k + i lda]).
 // opB = 0: B column-major K x N; opB = 1: B stored N x K.
-// gen = 1: A is generated, A(i, k) = scale / |pr_i - pc_k| with pr = (const
+// gen = 1: A is generated, A(i, k) = kernel(pr_i, pc_k) with pr = (const
 // double*) A and pc the points along K (dim-strided); gen = 2: B is generated
-// the same way, B(k, j) = scale / |pr_j - pc_k| with pr = (const double*) B
-// (the kernel is symmetric).  diag = 1 puts the diagonal value where the two
+// the same way, B(k, j) = kernel(pr_j, pc_k) with pr = (const double*) B
+// (the kernel is symmetric).  kernel(x, y) = scale / |x - y| (gkern 0) or
+// scale exp(-|x - y|^2) (gkern 1).  diag = 1 puts the diagonal value where the two
 // indices are equal (a cluster against itself).  scale, the diagonal value
 // and dim belong to the item (so that items of different matrices can share
 // a launch).
@@ -37,6 +38,7 @@ struct GemmItem {
   void* out[5];
   int32_t ld[5];
   uint8_t trans[5];
+  uint8_t gkern;           // generated operands: 0 inverse distance, 1 exp(-r^2)
   int32_t gdim;            // generated operands: point dimension
   double gscale, gdiag;    // generated operands: kernel scale, diagonal value
 };
@@ -58,6 +60,7 @@ struct GemmLaunch {
   int32_t ntiles;
   int mode;
   int role;
+  int kern;               // kernel of generated operands (GemmItem::gkern of every item)
 };
 
 template <class T>
@@ -139,7 +142,7 @@ template <class T>
 void launch_zero_pad_rows(const CopySeg* segs, int count, T* src, hipStream_t st);
 
 // Kernel blocks written out: element (k, j) of block b, at out[b.off + k + j ns],
-// is scale / |x_{t0 + j} - x_{s0 + k}| (dim coordinates per point, points
+// is kernel(x_{t0 + j}, x_{s0 + k}) of kind kern (as GemmItem::gkern; dim coordinates per point, points
 // consecutive in x), or diag where diag_blk is set and t0 + j == s0 + k.  The
 // values are bit for bit those the GEMM kernels generate for a B operand of
 // the same block (gen = 2).
@@ -148,8 +151,8 @@ struct KernelBlock {
   int32_t t0, s0, nt, ns;
   int32_t diag_blk, pad;
 };
-void launch_kernel_blocks(const KernelBlock* blocks, int count, const double* x, int dim, double scale,
-                          double diag, double* out, hipStream_t st);
+void launch_kernel_blocks(const KernelBlock* blocks, int count, const double* x, int dim, int kern,
+                          double scale, double diag, double* out, hipStream_t st);
 
 // Small element-wise helpers.
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);

@@ -136,12 +136,13 @@ __device__ __forceinline__ void fetch4(const T* p, int64_t ld, int row, int k, i
 }
 
 // Generated operand block for the four k of this lane: scale / |x_row - y_k|
-// (dg on the diagonal) from the row's point, held in registers for the whole
+// (KERN 0) or scale exp(-|x_row - y_k|^2) (KERN 1), dg on the diagonal, from
+// the row's point, held in registers for the whole
 // segment, and the chunk's four source points, loaded once per chunk and
 // shared by every block of the tile.  Coordinates past dim are zero on both
 // sides; the sum runs over a = 0 .. dim - 1 in order (kernel_blocks_kernel
 // forms the same values).
-template <class T>
+template <class T, int KERN>
 __device__ __forceinline__ void gen4(const double (&prow)[3], const double (&pcol)[4][3], int row, int k, int K,
                                      bool ok, int dim, double scale, double dg, bool diag, T* v) {
 #pragma unroll
@@ -158,7 +159,7 @@ __device__ __forceinline__ void gen4(const double (&prow)[3], const double (&pco
             const double d = prow[a] - pcol[s][a];
             d2 += d * d;
           }
-        val = T(scale * inv_sqrt(d2));
+        val = T(KERN == 0 ? scale * inv_sqrt(d2) : scale * exp(-d2));
       }
     }
     v[s] = val;
@@ -166,7 +167,7 @@ __device__ __forceinline__ void gen4(const double (&prow)[3], const double (&pco
 }
 
 // acc += op(A) op(B) for one segment; AM / BM select the fetch of each operand.
-template <class T, int AM, int BM, int MB, int NB>
+template <class T, int AM, int BM, int MB, int NB, int KERN>
 __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[MB][NB], int nbm, int nbn,
                                                const GemmSeg& sg, int m0, int n0, int M, int N, int lane,
                                                int dim, double scale, double dg) {
@@ -220,13 +221,13 @@ __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[MB][NB
 #pragma unroll
     for (int b = 0; b < MB; ++b)
       if (b < nbm) {
-        if constexpr (AM == 2) gen4<T>(prA[b], pcol, ra[b], k, K, oa[b], dim, scale, dg, sg.diag, a[b]);
+        if constexpr (AM == 2) gen4<T, KERN>(prA[b], pcol, ra[b], k, K, oa[b], dim, scale, dg, sg.diag, a[b]);
         else fetch4<T, AM>(pa[b], sg.lda, ra[b], k, K, oa[b], a[b]);
       }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
       if (b < nbn) {
-        if constexpr (BM == 2) gen4<T>(prB[b], pcol, cb[b], k, K, ob[b], dim, scale, dg, sg.diag, bv[b]);
+        if constexpr (BM == 2) gen4<T, KERN>(prB[b], pcol, cb[b], k, K, ob[b], dim, scale, dg, sg.diag, bv[b]);
         else fetch4<T, BM>(pb[b], sg.ldb, cb[b], k, K, ob[b], bv[b]);
       }
 #pragma unroll
@@ -240,8 +241,9 @@ __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[MB][NB
 }
 
 // AM / BM: operand layouts of every segment of the launch (see direct_segment);
-// the tile is MB x NB blocks of 16 x 16
-template <class T, int ROLE, int AM, int BM, int MB, int NB>
+// the tile is MB x NB blocks of 16 x 16; KERN: kernel of generated operands
+// (GemmItem::gkern, one for the whole launch)
+template <class T, int ROLE, int AM, int BM, int MB, int NB, int KERN>
 __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
   using V = typename Mfma<T>::V;
   const int lane = threadIdx.x;
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
     for (int b = 0; b < NB; ++b) acc[a][b] = V{0, 0, 0, 0};
   for (int si = it.seg_begin; si < it.seg_end; ++si) {
     const GemmSeg sg = g.segs[si];
-    direct_segment<T, AM, BM, MB, NB>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
+    direct_segment<T, AM, BM, MB, NB, KERN>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
   }
 #pragma unroll
   for (int bm = 0; bm < MB; ++bm)
@@ -814,7 +816,13 @@ void gemm_tile(int role, int amode, int bmode, int* mb, int* nb) {
 template <class T, int ROLE, int AM, int BM>
 static void launch_kc(const GemmLaunch& g, hipStream_t st) {
   constexpr int MB = tile_mb(ROLE, AM, BM), NB = tile_nb(ROLE, AM, BM);
-  hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB>), dim3(g.ntiles), dim3(64), 0, st, g);
+  if constexpr (AM == 2 || BM == 2) {
+    if (g.kern == 1) {
+      hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB, 1>), dim3(g.ntiles), dim3(64), 0, st, g);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB, 0>), dim3(g.ntiles), dim3(64), 0, st, g);
 }
 
 template <class T>
@@ -932,7 +940,7 @@ void launch_add_scaled_f_rm(const float* in, const double* cs, double* acc, int6
 // One work-group per block, threads along the block's elements (k fastest).
 // The value is formed exactly as gen4 forms a generated B element.
 __global__ __launch_bounds__(256) void kernel_blocks_kernel(const KernelBlock* blocks, const double* x, int dim,
-                                                          double scale, double diag, double* out) {
+                                                          int kern, double scale, double diag, double* out) {
   const KernelBlock b = blocks[blockIdx.x];
   const int64_t len = int64_t(b.nt) * b.ns;
   const double* pr = x + int64_t(b.t0) * dim;
@@ -948,16 +956,16 @@ __global__ __launch_bounds__(256) void kernel_blocks_kernel(const KernelBlock* b
         const double d = pr[j * dim + a] - pc[k * dim + a];
         d2 += d * d;
       }
-      val = double(scale * inv_sqrt(d2));
+      val = kern == 0 ? scale * inv_sqrt(d2) : scale * exp(-d2);
     }
     out[b.off + e] = val;
   }
 }
 
-void launch_kernel_blocks(const KernelBlock* blocks, int count, const double* x, int dim, double scale,
-                          double diag, double* out, hipStream_t st) {
+void launch_kernel_blocks(const KernelBlock* blocks, int count, const double* x, int dim, int kern,
+                          double scale, double diag, double* out, hipStream_t st) {
   if (count > 0)
-    hipLaunchKernelGGL(kernel_blocks_kernel, dim3(count), dim3(256), 0, st, blocks, x, dim, scale, diag, out);
+    hipLaunchKernelGGL(kernel_blocks_kernel, dim3(count), dim3(256), 0, st, blocks, x, dim, kern, scale, diag, out);
 }
 
 void launch_fill(double* p, int64_t n, double v, hipStream_t st) {

@@ -1,0 +1,177 @@
+"""GPU parity for the exp core of Example 2, A_ij = 2 delta_ij + exp(-|r_i - r_j|^2)
+(kernel H2_KERNEL_EXP with scale 1 and diagonal 3), through the C ABI.
+
+Same bars as the inverse-distance cases: the FP64 path within 1e-12 of the
+oracle's Q_t and S, the mixed path within 5e-6, the preconditioner within
+1e-10 of the oracle's block ILU(0), solves to the requested residual.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import h2inputs
+import oracle
+import paper_1705_04601_amd as P
+from h2test_util import import_arrays
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (points, n, seed, leaf, cheb, recompression tol, rank cap)
+EXP_CASES = {
+    "cube2000": ("cube", 2000, 21, 32, 4, 1e-8, 48),
+    "square1500": ("square", 1500, 22, 32, 4, 1e-8, 16),
+}
+_cache = {}
+
+
+def note(msg):
+    sys.stderr.write(f"[gpu-case] {msg}\n")
+    sys.stderr.flush()
+
+
+def case(name):
+    if name not in _cache:
+        kind, n, seed, leaf, cheb, tol, cap = EXP_CASES[name]
+        x = h2inputs.points(kind, n, seed)
+        h2 = oracle.build_h2(x, leaf, cheb, 1.0, 3.0, tol, cap, 1.0, oracle.EXP)
+        sp = oracle.sparsify(h2)
+        _cache[name] = (x, h2, sp, h2.dense(), (leaf, cheb, tol, cap))
+    return _cache[name]
+
+
+def imported(name):
+    x, h2, sp, a, (leaf, cheb, tol, cap) = case(name)
+    return P.h2_import(x, 1.0, 3.0, leaf, cheb, 1.0, *import_arrays(h2), kernel=P.H2_KERNEL_EXP)
+
+
+def dev(arr):
+    arr = np.asarray(arr, dtype=np.float64)
+    if arr.ndim == 1:
+        arr = arr[:, None]
+    return torch.from_numpy(np.ascontiguousarray(arr.T)).cuda().T
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def from_tree(v_tree, perm):
+    out = np.empty_like(v_tree)
+    out[perm] = v_tree
+    return out
+
+
+@pytest.mark.parametrize("name", list(EXP_CASES))
+def test_exp_matvec_imported(name):
+    x, h2, sp, a, _ = case(name)
+    note(f"exp matvec imported {name}")
+    v = np.random.default_rng(31).standard_normal((x.shape[0], 3))
+    y = dev(np.zeros_like(v))
+    P.h2_matvec(imported(name), dev(v), y)
+    want = from_tree(a @ v[h2.tree.perm], h2.tree.perm)
+    assert np.abs(host(y) - want).max() <= 1e-13 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("precision", [P.H2_FP64, P.H2_MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(EXP_CASES))
+def test_exp_sparsify_parity(name, precision):
+    x, h2, sp, a, _ = case(name)
+    note(f"exp sparsify {name} precision={precision}")
+    sph = P.h2_sparsify(imported(name), precision)
+    amax = np.abs(a).max()
+    if precision == P.H2_FP64:
+        for t, q in sp.q.items():
+            assert np.abs(P.h2_sparse_export_q(sph, t, q.shape[0]) - q).max() <= 1e-12, f"Q of cluster {t}"
+    worst = 0.0
+    for (t, s), blk in sp.s_blocks.items():
+        worst = max(worst, np.abs(P.h2_sparse_export_block(sph, t, s, *blk.shape) - blk).max())
+    if precision == P.H2_FP64:
+        assert worst <= 1e-12 * amax
+    else:
+        assert worst <= mixed_bar(h2, a)
+
+
+def mixed_bar(h2, a):
+    """FP32 bar for S: one transform Q_t^T C Q_s sums 2 n products per entry,
+    so its rounding is at most about 2 n u32 |C|_F (u32 = 2^-24, n the leaf
+    size), the largest close block being a diagonal leaf block.  Unlike the
+    inverse distance, whose off-diagonal entries are far below the diagonal,
+    every entry of the exp core is O(1) (at least e^-2 on the unit square),
+    so the bar is relative to that block norm, not to max |A_ij|."""
+    tr = h2.tree
+    leaves = [c for c in range(tr.ncl) if 2 * c + 1 >= tr.ncl]
+    nleaf = max(int(tr.size[c]) for c in leaves)
+    fro = max(np.linalg.norm(a[int(tr.start[c]):int(tr.start[c] + tr.size[c]),
+                               int(tr.start[c]):int(tr.start[c] + tr.size[c])]) for c in leaves)
+    return 2 * nleaf * 2.0 ** -24 * fro
+
+
+@pytest.mark.parametrize("name", list(EXP_CASES))
+def test_exp_preconditioner_matches_oracle_ilu0(name):
+    x, h2, sp, a, _ = case(name)
+    note(f"exp apply inverse {name}")
+    f = P.h2_factor_S(P.h2_sparsify(imported(name), P.H2_FP64))
+    b = np.random.default_rng(32).standard_normal((x.shape[0], 2))
+    out = dev(np.zeros_like(b))
+    P.h2_apply_inverse(f, dev(b), out)
+    ilu = oracle.BlockILU0(sp, oracle.elimination_order(sp))
+    bt = b[h2.tree.perm]
+    want = from_tree(oracle.apply_v(sp, ilu.solve(oracle.apply_ut(sp, bt))), h2.tree.perm)
+    assert np.abs(host(out) - want).max() <= 1e-10 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("name", list(EXP_CASES))
+def test_exp_own_build_mixed_solve(name):
+    """The library's own construction of the exp core, measured against the
+    exact matrix (scipy's pairwise distances) through basis-independent
+    quantities: its matvec error and the error of a mixed solve to 1e-10 are
+    within twice those of the oracle's construction with the same options."""
+    from scipy.spatial.distance import cdist
+    x, h2, sp, a, (leaf, cheb, tol, cap) = case(name)
+    note(f"exp own build solve {name}")
+    n = x.shape[0]
+    exact = np.exp(-cdist(x, x, "sqeuclidean")) + 2.0 * np.eye(n)
+    a_orig = np.empty_like(a)
+    p = h2.tree.perm
+    a_orig[np.ix_(p, p)] = a                      # the oracle's H^2, original order
+    h = P.h2_build(x, 1.0, 3.0, leaf, cheb, tol, cap, 1.0, kernel=P.H2_KERNEL_EXP)
+    v = np.random.default_rng(33).standard_normal((n, 2))
+    y = dev(np.zeros_like(v))
+    P.h2_matvec(h, dev(v), y)
+    ref = exact @ v
+    err_oracle = np.abs(a_orig @ v - ref).max() / np.abs(ref).max()
+    assert err_oracle <= 3e-4
+    assert np.abs(host(y) - ref).max() / np.abs(ref).max() <= 2 * err_oracle
+    f = P.h2_factor_S(P.h2_sparsify(h, P.H2_MIXED))
+    b = np.random.default_rng(34).standard_normal((n, 4))
+    xs = dev(np.zeros_like(b))
+    info = P.h2_solve(f, dev(b), xs, tol=1e-10, max_iter=40)
+    assert info["residual"] <= 1e-10
+    xe = np.linalg.solve(exact, b)
+    xo = np.linalg.solve(a_orig, b)
+    bound = 2 * np.abs(xo - xe).max()
+    assert np.abs(host(xs) - xe).max() <= bound + 1e-8 * np.abs(xe).max()
+
+
+def test_exp_batch_matches_single_and_rejects_mixed_kernels():
+    """A batched sweep over exp-core instances gives each its own S bit for
+    bit; a sweep mixing kernel kinds is refused."""
+    note("exp batch")
+    names = list(EXP_CASES)
+    hs = [imported(n) for n in names]
+    batch = P.h2_sparsify_batch(hs, P.H2_FP64)
+    for name, h, spb in zip(names, hs, batch):
+        single = P.h2_sparsify(h, P.H2_FP64)
+        sp = case(name)[2]
+        for (t, s), blk in list(sp.s_blocks.items())[:400]:
+            got = P.h2_sparse_export_block(spb, t, s, *blk.shape)
+            assert np.array_equal(got, P.h2_sparse_export_block(single, t, s, *blk.shape)), f"{name}: S {t},{s}"
+    x, sc = h2inputs.points("cube", 600, 23), 1.0 / (4 * np.pi * 600)
+    inv = P.h2_build(x, sc, 1.0, 32, 3, 1e-8, 27, 1.0)
+    with pytest.raises(P.H2Error):
+        P.h2_sparsify_batch([hs[0], inv], P.H2_FP64)

@@ -407,3 +407,52 @@ def test_pins_catch_a_transposed_coupling(monkeypatch):
     sp = oracle.sparsify(h2)
     u, s = oracle.dense_u(sp), oracle.dense_s(sp)
     assert np.linalg.norm(u @ s @ u.T - a_ref) > 1e-10 * np.linalg.norm(a_ref)
+
+
+# ------------------------------------------------ Example 2: exp(-|r|^2) core
+
+def test_exp_kernel_values_by_hand():
+    """Entries of 2 delta_ij + exp(-|r_i - r_j|^2) (Example 2) for three
+    points at squared distances 1, 2 and 3, written out by hand."""
+    x = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 1.0]])
+    idx = np.arange(3)
+    got = oh2.close_block(x, idx, idx, 1.0, 3.0, oracle.EXP)
+    e1, e2, e3 = 0.36787944117144233, 0.1353352832366127, 0.049787068367863944
+    want = np.array([[3.0, e1, e2], [e1, 3.0, e3], [e2, e3, 3.0]])
+    assert np.abs(got - want).max() <= 2e-16 * 3
+    far = oh2.kernel_block(x[:1], x[1:], 0.5, oracle.EXP)
+    assert np.abs(far - 0.5 * np.array([[e1, e2]])).max() <= 1e-17
+
+
+@pytest.fixture(scope="module")
+def exp_case():
+    x = h2inputs.points("cube", 1536, 11)
+    out = {}
+    for cheb in (3, 4):
+        out[cheb] = oracle.build_h2(x, 32, cheb, 1.0, 3.0, 1e-8, 64, 1.0, oracle.EXP)
+    return out
+
+
+def test_exp_h2_approximates_the_kernel(exp_case):
+    """The Chebyshev H^2 of the exp core against the dense matrix from
+    scipy's pairwise distances: small, and shrinking with the order."""
+    from scipy.spatial.distance import cdist
+    err = {}
+    for cheb, h2 in exp_case.items():
+        exact = np.exp(-cdist(h2.x_tree, h2.x_tree, "sqeuclidean")) + 2.0 * np.eye(h2.tree.n)
+        err[cheb] = np.linalg.norm(h2.dense() - exact) / np.linalg.norm(exact)
+    assert err[4] <= 1e-4
+    assert err[4] <= err[3] / 5
+
+
+def test_exp_sparsification_is_exact_and_spd(exp_case):
+    """A = U S U^T to rounding for the exp core too; S inherits the
+    positive definiteness of 2 I + (a Gaussian Gram matrix)."""
+    h2 = exp_case[4]
+    sp = oracle.sparsify(h2)
+    a = h2.dense()
+    u = oracle.dense_u(sp)
+    s = oracle.dense_s(sp)
+    assert np.linalg.norm(u @ s @ u.T - a) <= 1e-12 * np.linalg.norm(a)
+    assert np.abs(u.T @ u - np.eye(u.shape[0])).max() <= 1e-13
+    assert np.linalg.eigvalsh(0.5 * (s + s.T)).min() > 1.9
