@@ -127,8 +127,9 @@ def time_path(P, h, precision, b, x, steps, warmup, tol, max_iter, mode):
     return total / steps, recs
 
 
-def cpu_baseline(wl, budget_s=20.0):
-    """The oracle as it stands on a bounded sample of the workload (1 thread)."""
+def cpu_baseline(wl, budget_s=20.0, exact=False):
+    """The oracle as it stands on a bounded sample of the workload (1 thread);
+    exact: the block factorisation with its fill instead of block ILU(0)."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
@@ -146,10 +147,15 @@ def cpu_baseline(wl, budget_s=20.0):
         try:
             if ctx:
                 ctx.__enter__()
-            h2 = oracle.build_h2(x, leaf, cheb, sc, 1.0, tol, cap)
+            h2 = oracle.build_h2(x, leaf, cheb, sc, wl.get("diag", 1.0), tol, cap, 1.0,
+                                 oracle.EXP if wl.get("kernel") == "exp" else None)
             t0 = time.perf_counter()
             sp = oracle.sparsify(h2)
-            ilu = oracle.BlockILU0(sp)
+            if exact:
+                order = oracle.elimination_order(sp)
+                ilu = oracle.BlockILU0(oracle.filled(sp, order), order)
+            else:
+                ilu = oracle.BlockILU0(sp)
             _, hist = oracle.refine(sp, ilu.solve, b[h2.tree.perm], 1e-8)
             dt = time.perf_counter() - t0
         finally:
@@ -162,10 +168,17 @@ def cpu_baseline(wl, budget_s=20.0):
     return {"value": nrhs * best["n"] / best["seconds"], "unit": "RHS*N/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{kind} N={best['n']} (same leaf/cheb/tol, {nrhs} RHS, refine to 1e-8, "
-                      f"{best['iters']} steps): sparsify+ILU(0)+refine {best['seconds']:.2f}s on 1 thread"}
+                      f"{best['iters']} steps): sparsify+{'exact factor' if exact else 'ILU(0)'}+refine "
+                      f"{best['seconds']:.2f}s on 1 thread"}
 
 
 BATCH_WORKLOAD = "batch64"
+
+
+def kernel_label(wl):
+    if wl.get("kernel") == "exp":
+        return f"{wl['scale']} exp(-|x-y|^2), A_ii = {wl.get('diag', 1.0):g}"
+    return {"1/(4piN)": "1/(4 pi N |x-y|), A_ii = 1", "1/N": "1/(N |x-y|), A_ii = 1"}[wl["scale"]]
 
 
 def bench_batch(args, P, torch):
@@ -249,8 +262,9 @@ def main():
                     help="block ILU(0) of S (default) or the exact block factorisation with fill")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported in this build "
-              "(the sweep shards by subtree; see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(the library runs the whole sweep on one device; a multi-GPU sweep would shard by subtree)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -269,7 +283,8 @@ def main():
     x = h2inputs.points(wl["kind"], n, wl["seed"])
     sc = h2inputs.kernel_scale(wl["scale"], n)
     t0 = time.perf_counter()
-    h = P.h2_build(x, sc, 1.0, wl["leaf"], wl["cheb"], wl["tol"], wl["rank_cap"])
+    kern = P.H2_KERNEL_EXP if wl.get("kernel") == "exp" else P.H2_KERNEL_INVDIST
+    h = P.h2_build(x, sc, wl.get("diag", 1.0), wl["leaf"], wl["cheb"], wl["tol"], wl["rank_cap"], kernel=kern)
     t_build = time.perf_counter() - t0
     depth, ncl, npts = P.h2_matrix_info(h)
     _, rank = P.h2_matrix_export_tree(h, n)
@@ -320,8 +335,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "points": wl["kind"], "N": n, "nrhs": nrhs,
                    "leaf": wl["leaf"], "cheb": wl["cheb"], "recompress_tol": wl["tol"],
-                   "rank_cap": wl["rank_cap"], "kernel": "1/(4 pi N |x-y|), A_ii = 1"
-                   if wl["scale"] != "1/N" else "1/(N |x-y|), A_ii = 1",
+                   "rank_cap": wl["rank_cap"], "kernel": kernel_label(wl),
                    "factor": "block ILU(0) of S" if args.factor == "ilu0" else "exact block LDL^T of S (with fill)",
                    "precision": "mixed"},
         "mixed": {"t_sparsify": last["t_sparsify"], "t_factor_S": last["t_factor"],
@@ -345,7 +359,7 @@ def main():
         out["mixed_speedup_vs_fp64"] = sec64 / sec
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(wl, exact=args.factor == "exact")
     print(json.dumps(out))
 
 

@@ -36,7 +36,7 @@ enum {
   H2_EDEVICE = -3,      /* a HIP call failed                                        */
   H2_ESINGULAR = -4,    /* a pivot block of S is numerically singular               */
   H2_ENOCONV = -5,      /* refinement stopped above the tolerance (x still written) */
-  H2_EUNSUPPORTED = -6  /* option outside what this build supports                  */
+  H2_EUNSUPPORTED = -6  /* option outside what the library supports                */
 };
 
 /* ---- options --------------------------------------------------------------- */
