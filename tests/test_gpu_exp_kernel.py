@@ -77,6 +77,24 @@ def test_exp_matvec_imported(name):
     assert np.abs(host(y) - want).max() <= 1e-13 * np.abs(want).max()
 
 
+def test_exp_matvec_close_generated_vs_resident(monkeypatch):
+    """The exp close field written out once and generated inside the GEMM:
+    both against the oracle's dense product, and against each other to
+    rounding (the same values; the two GEMM tiles may sum in another order)."""
+    x, h2, sp, a, _ = case("cube2000")
+    note("exp matvec close resident vs generated")
+    v = np.random.default_rng(35).standard_normal((x.shape[0], 3))
+    want = from_tree(a @ v[h2.tree.perm], h2.tree.perm)
+    got = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("H2SP_CLOSE_RESIDENT", flag)
+        y = dev(np.zeros_like(v))
+        P.h2_matvec(imported("cube2000"), dev(v), y)
+        got[flag] = host(y)
+        assert np.abs(got[flag] - want).max() <= 1e-13 * np.abs(want).max()
+    assert np.abs(got["0"] - got["1"]).max() <= 1e-15 * np.abs(want).max()
+
+
 @pytest.mark.parametrize("precision", [P.H2_FP64, P.H2_MIXED], ids=["fp64", "mixed"])
 @pytest.mark.parametrize("name", list(EXP_CASES))
 def test_exp_sparsify_parity(name, precision):
