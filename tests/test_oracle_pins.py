@@ -456,3 +456,22 @@ def test_exp_sparsification_is_exact_and_spd(exp_case):
     assert np.linalg.norm(u @ s @ u.T - a) <= 1e-12 * np.linalg.norm(a)
     assert np.abs(u.T @ u - np.eye(u.shape[0])).max() <= 1e-13
     assert np.linalg.eigvalsh(0.5 * (s + s.T)).min() > 1.9
+
+
+def test_exp_pins_catch_a_dropped_square(monkeypatch):
+    """A far field of exp(-|r|) instead of exp(-|r|^2) (the close field kept
+    right) is caught by the comparison with scipy's pairwise distances."""
+    from scipy.spatial.distance import cdist
+    good = oh2.kernel_block
+
+    def bad(xr, xc, scale, kernel=None):
+        if kernel == oracle.EXP:
+            d = xr[:, None, :] - xc[None, :, :]
+            return scale * np.exp(-np.sqrt((d * d).sum(axis=2)))
+        return good(xr, xc, scale, kernel)
+
+    monkeypatch.setattr(oh2, "kernel_block", bad)
+    x = h2inputs.points("cube", 1536, 11)
+    h2 = oracle.build_h2(x, 32, 4, 1.0, 3.0, 1e-8, 64, 1.0, oracle.EXP)
+    exact = np.exp(-cdist(h2.x_tree, h2.x_tree, "sqeuclidean")) + 2.0 * np.eye(h2.tree.n)
+    assert np.linalg.norm(h2.dense() - exact) > 1e-2 * np.linalg.norm(exact)
