@@ -42,7 +42,7 @@ enum {
 /* ---- options --------------------------------------------------------------- */
 enum { H2_KERNEL_INVDIST = 0,   /* A_ij = scale / |x_i - x_j| (i != j), A_ii = diag */
        H2_KERNEL_EXP = 1 };     /* A_ij = scale exp(-|x_i - x_j|^2) (i != j), A_ii =
-                                   diag: Example 2 of Section 6 (its matrix
+                                   diag: Example 2 of Section 5.1 (its matrix
                                    2 delta_ij + exp(-|r_i - r_j|^2) is scale 1,
                                    diag 3).  h2_sparsify_batch takes matrices
                                    of one kernel kind (H2_EUNSUPPORTED

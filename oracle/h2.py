@@ -43,8 +43,8 @@ def kernel_block(xr: np.ndarray, xc: np.ndarray, scale: float, kernel=None) -> n
     """K_ij = scale / |xr_i - xc_j| for distinct points (no diagonal rule).
 
     ``kernel`` = EXP gives scale exp(-|xr_i - xc_j|^2), the smooth part of
-    the Gaussian matrix of Example 2 (equation of the "exp" core in Section
-    6); a function of two point arrays broadcasting to a matrix replaces the
+    the Gaussian matrix of Example 2 (the "exp" core, Section 5.1); a
+    function of two point arrays broadcasting to a matrix replaces the
     inverse distance (the tests use polynomial kernels for which Chebyshev
     interpolation is exact).
     """
