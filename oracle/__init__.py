@@ -21,20 +21,21 @@ basis-dependent and pinned only through the basis-independent H^2 matrix.
 
 from .tree import (ClusterTree, BlockTree, build_cluster_tree, build_block_tree,
                    farfield_nonempty, admissible, tree_depth)
-from .h2 import EXP, H2Matrix, build_h2, kernel_block, close_block
+from .h2 import EXP, IFMM, H2Matrix, build_h2, kernel_block, close_block
 from .householder import householder_qr
 from .sparsify import (Sparsified, sparsify, apply_ut, apply_v, dense_s, dense_u,
                        pattern_predicate, cluster_sizes)
 from .solve import (BlockILU0, dense_lu_solver, refine, rel_residual,
                     conjugate_gradient, elimination_order, elimination_colours,
                     block_fill, filled)
+from .precond import BlockILUT, gmres
 
 __all__ = [
     "ClusterTree", "BlockTree", "build_cluster_tree", "build_block_tree",
     "farfield_nonempty", "admissible", "tree_depth", "H2Matrix", "build_h2",
-    "EXP", "kernel_block", "close_block", "householder_qr", "Sparsified", "sparsify",
+    "EXP", "IFMM", "kernel_block", "close_block", "householder_qr", "Sparsified", "sparsify",
     "apply_ut", "apply_v", "dense_s", "dense_u", "pattern_predicate",
     "cluster_sizes", "BlockILU0", "dense_lu_solver", "refine", "rel_residual",
     "conjugate_gradient", "elimination_order", "elimination_colours",
-    "block_fill", "filled",
+    "block_fill", "filled", "BlockILUT", "gmres",
 ]

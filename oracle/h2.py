@@ -37,21 +37,41 @@ from .tree import (BlockTree, ClusterTree, build_block_tree,
 
 
 EXP = "exp"
+IFMM = "ifmm"   # used as (IFMM, d)
+
+
+def _named_kernel(kernel, r2: np.ndarray, scale: float) -> np.ndarray:
+    """Entries of a named kernel at squared distances r2 (off the diagonal).
+
+    EXP: scale exp(-r^2) (Example 2).  (IFMM, d): scale r / d for r < d and
+    scale d / r otherwise (Example 4, the test matrix of Section 5.5).
+    """
+    if kernel == EXP:
+        return scale * np.exp(-r2)
+    name, d = kernel
+    assert name == IFMM, kernel
+    r = np.sqrt(r2)
+    with np.errstate(divide="ignore"):
+        return scale * np.where(r < d, r / d, d / r)
+
+
+def _is_named(kernel) -> bool:
+    return isinstance(kernel, str) or (isinstance(kernel, tuple) and kernel[:1] == (IFMM,))
 
 
 def kernel_block(xr: np.ndarray, xc: np.ndarray, scale: float, kernel=None) -> np.ndarray:
     """K_ij = scale / |xr_i - xc_j| for distinct points (no diagonal rule).
 
     ``kernel`` = EXP gives scale exp(-|xr_i - xc_j|^2), the smooth part of
-    the Gaussian matrix of Example 2 (the "exp" core, Section 5.1); a
+    the Gaussian matrix of Example 2 (the "exp" core, Section 5.1), and
+    (IFMM, d) the matrix of Example 4 (Section 5.5); a
     function of two point arrays broadcasting to a matrix replaces the
     inverse distance (the tests use polynomial kernels for which Chebyshev
     interpolation is exact).
     """
     diff = xr[:, None, :] - xc[None, :, :]
-    if isinstance(kernel, str):
-        assert kernel == EXP, kernel
-        return scale * np.exp(-(diff * diff).sum(axis=2))
+    if _is_named(kernel):
+        return _named_kernel(kernel, (diff * diff).sum(axis=2), scale)
     if kernel is not None:
         return kernel(xr[:, None, :], xc[None, :, :])
     return scale / np.sqrt((diff * diff).sum(axis=2))
@@ -65,13 +85,13 @@ def close_block(x: np.ndarray, ti: np.ndarray, si: np.ndarray, scale: float,
     diagonal; Example 2's matrix 2 delta_ij + exp(-|r_i - r_j|^2) is
     scale = 1, diag = 3.
     """
-    if kernel is not None and not isinstance(kernel, str):
+    if kernel is not None and not _is_named(kernel):
         return kernel(x[ti][:, None, :], x[si][None, :, :])
     diff = x[ti][:, None, :] - x[si][None, :, :]
     r2 = (diff * diff).sum(axis=2)
     same = ti[:, None] == si[None, :]
-    if kernel == EXP:
-        out = scale * np.exp(-r2)
+    if kernel is not None:
+        out = _named_kernel(kernel, r2, scale)
     else:
         with np.errstate(divide="ignore"):
             out = scale / np.sqrt(r2)
