@@ -475,3 +475,27 @@ def test_exp_pins_catch_a_dropped_square(monkeypatch):
     h2 = oracle.build_h2(x, 32, 4, 1.0, 3.0, 1e-8, 64, 1.0, oracle.EXP)
     exact = np.exp(-cdist(h2.x_tree, h2.x_tree, "sqeuclidean")) + 2.0 * np.eye(h2.tree.n)
     assert np.linalg.norm(h2.dense() - exact) > 1e-2 * np.linalg.norm(exact)
+
+
+def test_s_rows_stay_sparse_as_depth_grows():
+    """Section 3 and the nnz study of Section 5.1: S stays sparse.  In a leaf
+    row, the blocks whose column cluster sits k levels up fall off
+    geometrically with k, so a row's block count is bounded whatever the
+    depth (at these N the total still rises towards that bound)."""
+    import collections
+    n = 8192
+    x = h2inputs.points("square", n, 3)
+    h2 = oracle.build_h2(x, 32, 4, 1.0 / n, 1.0, 1e-6, 0, 1.0)
+    sp = oracle.sparsify(h2)
+    tr = h2.tree
+    assert tr.depth >= 7
+    leaves = [c for c in range(tr.ncl) if 2 * c + 1 >= tr.ncl and sp.nonbasis[c] > 0]
+    per_level = collections.Counter()
+    for (t, s) in sp.s_blocks:
+        if 2 * t + 1 >= tr.ncl:
+            per_level[tr.level(s)] += 1
+    counts = [per_level[lv] / len(leaves) for lv in sorted(per_level)]
+    assert len(counts) >= 5
+    for a, b in zip(counts[1:], counts[2:]):
+        assert b <= 0.75 * a
+    assert sum(counts) <= 4 * counts[0] + counts[1]
