@@ -41,6 +41,24 @@ def test_tree_and_ranks_match_oracle(kind, n, seed, leaf, cheb, tol, cap, eta):
     assert np.array_equal(rank, h2.rank)
 
 
+@pytest.mark.parametrize("kind,n,seed,leaf,cheb,tol,cap", [
+    ("cube", 2000, 21, 32, 4, 1e-8, 48),
+    ("square", 1500, 22, 32, 4, 1e-8, 16),
+    ("sphere", 2048, 12, 64, 3, 1e-6, 27),
+])
+def test_exp_kernel_tree_and_ranks_match_oracle(kind, n, seed, leaf, cheb, tol, cap):
+    """The exp core of Example 2 through the library's host construction:
+    permutation and recompressed ranks equal the oracle's."""
+    import h2inputs
+    import oracle
+    x = h2inputs.points(kind, n, seed)
+    h2 = oracle.build_h2(x, leaf, cheb, 1.0, 3.0, tol, cap, 1.0, oracle.EXP)
+    h = P.h2_build(x, 1.0, 3.0, leaf, cheb, tol, cap, 1.0, kernel=P.H2_KERNEL_EXP)
+    perm, rank = P.h2_matrix_export_tree(h, n)
+    assert np.array_equal(perm, h2.tree.perm)
+    assert np.array_equal(rank, h2.rank)
+
+
 def _build_code(x, **kw):
     args = dict(scale=1.0, diag=1.0, leaf=16, cheb=3, tol=0.0, rank_cap=0, eta=1.0)
     args.update(kw)
@@ -65,6 +83,8 @@ def test_argument_errors():
     assert _build_code(x, leaf=129) == P.H2_EINVAL
     assert _build_code(x, cheb=5) == P.H2_EUNSUPPORTED
     assert _build_code(x, eta=-1.0) == P.H2_EINVAL
+    assert _build_code(x, kernel=7) == P.H2_EUNSUPPORTED
+    assert _build_code(x, kernel=P.H2_KERNEL_EXP, diag=3.0) == P.H2_OK
     assert "duplicate" in P.lib().h2_last_error().decode() or True
 
 
