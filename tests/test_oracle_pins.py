@@ -499,3 +499,34 @@ def test_s_rows_stay_sparse_as_depth_grows():
     for a, b in zip(counts[1:], counts[2:]):
         assert b <= 0.75 * a
     assert sum(counts) <= 4 * counts[0] + counts[1]
+
+
+def test_nonsymmetric_kernel_over_a_shared_basis():
+    """Section 2 derives A = U S V^T without symmetry.  With a non-symmetric
+    kernel over one Chebyshev basis per cluster (U = V, no recompression),
+    the sweep still reproduces A_H2 exactly, S comes out non-symmetric, and
+    the exact block factorisation of S solves A_H2 x = b like a dense LU."""
+    from scipy.spatial.distance import cdist
+
+    def kern(a, b):
+        d = a - b
+        return (1.0 + 0.5 * d[..., 0]) / np.sqrt((d * d).sum(axis=-1) + 1e-4)
+
+    n = 1200
+    x = h2inputs.points("cube", n, 31)
+    h2 = oracle.build_h2(x, 32, 4, 1.0, 1.0, 0.0, 0, 1.0, kern)
+    a = h2.dense()
+    xt = h2.x_tree
+    exact = (1.0 + 0.5 * (xt[:, None, 0] - xt[None, :, 0])) / np.sqrt(cdist(xt, xt, "sqeuclidean") + 1e-4)
+    assert np.linalg.norm(a - exact) <= 1e-4 * np.linalg.norm(exact)
+    assert np.abs(a - a.T).max() > 1e-3 * np.abs(a).max()
+    sp = oracle.sparsify(h2)
+    u, s = oracle.dense_u(sp), oracle.dense_s(sp)
+    assert np.linalg.norm(u @ s @ u.T - a) <= 1e-12 * np.linalg.norm(a)
+    assert np.abs(s - s.T).max() > 1e-3 * np.abs(s).max()
+    order = oracle.elimination_order(sp)
+    lu = oracle.BlockILU0(oracle.filled(sp, order), order)
+    b = np.random.default_rng(1).standard_normal((n, 2))
+    got = oracle.apply_v(sp, lu.solve(oracle.apply_ut(sp, b)))
+    want = np.linalg.solve(a, b)
+    assert np.abs(got - want).max() <= 1e-11 * np.abs(want).max()
