@@ -1,4 +1,4 @@
-// Construction of the H^2 matrix of c/|x - y| (the input of the method,
+// Construction of the H^2 matrix of c/|x - y| or c exp(-|x - y|^2) (the input of the method,
 // Definition 4.8; the paper takes it as given and cites H^2 compression for
 // orthogonal nested bases in Section 4.2).
 //
