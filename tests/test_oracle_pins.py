@@ -162,11 +162,88 @@ def test_matvec_matches_dense(case):
     assert np.abs(h2.matvec(v) - a @ v).max() <= 1e-13 * np.abs(a @ v).max()
 
 
+def _invdist_exact(h2):
+    """c / |x_i - x_j| off the diagonal and A_ii = diag, from scipy's pairwise
+    distances (independent of the oracle's kernel code)."""
+    from scipy.spatial.distance import cdist
+    d = cdist(h2.x_tree, h2.x_tree)
+    np.fill_diagonal(d, 1.0)
+    exact = h2.scale / d
+    np.fill_diagonal(exact, h2.diag)
+    return exact
+
+
 def test_h2_close_to_kernel(case):
     h2, sp, a, u, s = case
-    idx = np.arange(h2.tree.n)
-    exact = oh2.close_block(h2.x_tree, idx, idx, h2.scale, h2.diag)
+    exact = _invdist_exact(h2)
     assert np.linalg.norm(a - exact) <= 1e-4 * np.linalg.norm(exact)
+    # the diagonal is the prescribed value exactly (it lies in the close part)
+    assert np.array_equal(np.diag(a), np.full(h2.tree.n, h2.diag))
+
+
+# ------------------------------------------------ inverse distance c / |x - y|
+
+def test_invdist_kernel_values_by_hand():
+    """Entries of c / |x_i - x_j| with A_ii = 1 (the benchmark matrices) for
+    four points at distances 1/2, 1, 3/2, sqrt 2 and sqrt 3, written out by
+    hand, for the close blocks and the kernel blocks of the far field."""
+    x = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 1.0], [0.5, 0.0, 0.0]])
+    idx = np.arange(4)
+    c = 0.25
+    r2, r3 = 0.17677669529663688, 0.14433756729740643   # c / sqrt 2, c / sqrt 3
+    want = np.array([[1.0, 0.25, r2, 0.5],
+                     [0.25, 1.0, r3, 0.5],
+                     [r2, r3, 1.0, 0.25 / 1.5],
+                     [0.5, 0.5, 0.25 / 1.5, 1.0]])
+    got = oh2.close_block(x, idx, idx, c, 1.0)
+    assert np.abs(got - want).max() <= 2e-16
+    # a close block between different index sets has no diagonal rule
+    got = oh2.close_block(x, np.array([0, 3]), np.array([1, 2]), c, 1.0)
+    assert np.abs(got - want[np.ix_([0, 3], [1, 2])]).max() <= 2e-16
+    far = oh2.kernel_block(x[:2], x[2:], c)
+    assert np.abs(far - want[:2, 2:]).max() <= 2e-16
+
+
+@pytest.mark.parametrize("kind,n,seed,leaf", [("cube", 1536, 11, 32), ("square", 1024, 1, 32)])
+def test_invdist_h2_approximates_pairwise_distances(kind, n, seed, leaf):
+    """The Chebyshev H^2 of c / |x - y| against the dense matrix from scipy's
+    pairwise distances: the off-diagonal error is small and falls at least
+    fivefold from Chebyshev order 3 to 4 (interpolation of a smooth far
+    field), so a wrong power, sign or term in the far field fails."""
+    err = {}
+    for cheb in (3, 4):
+        h2 = _h2(kind, n, seed, leaf, cheb)
+        exact = _invdist_exact(h2)
+        off = ~np.eye(n, dtype=bool)
+        err[cheb] = np.linalg.norm((h2.dense() - exact)[off]) / np.linalg.norm(exact[off])
+    assert err[3] <= 1e-3
+    assert err[4] <= err[3] / 5
+
+
+def test_invdist_pins_catch_a_squared_distance(monkeypatch):
+    """c / |r|^2 in place of c / |r| (in the far field, then in the close
+    field) is caught by the comparison with scipy's pairwise distances."""
+    good_k, good_c = oh2.kernel_block, oh2.close_block
+
+    def bad_kernel(xr, xc, scale, kernel=None):
+        if kernel is None:
+            d = xr[:, None, :] - xc[None, :, :]
+            return scale / (d * d).sum(axis=2)
+        return good_k(xr, xc, scale, kernel)
+
+    def bad_close(x, ti, si, scale, diag, kernel=None):
+        out = good_c(x, ti, si, scale, diag, kernel)
+        if kernel is None:
+            same = ti[:, None] == si[None, :]
+            out = np.where(same, diag, out * out / scale)
+        return out
+
+    for name, fn in (("kernel_block", bad_kernel), ("close_block", bad_close)):
+        with monkeypatch.context() as m:
+            m.setattr(oh2, name, fn)
+            h2 = _h2("cube", 1536, 11, 32, 3)
+            exact = _invdist_exact(h2)
+            assert np.linalg.norm(h2.dense() - exact) > 1e-2 * np.linalg.norm(exact - np.eye(1536)), name
 
 
 def test_recompressed_bases_orthonormal():
