@@ -76,17 +76,32 @@ typedef struct {
   int mode;              /* H2_FACTOR_EXACT or H2_FACTOR_ILU0                    */
 } h2_factor_opts;
 
+enum { H2_SOLVE_AUTO = 0,       /* iterative refinement; when its contraction stalls
+                                   (residual ratio above 0.9 for 3 steps) or it
+                                   diverges (ratio above 2, or not finite), the
+                                   best x so far is kept and flexible GMRES
+                                   continues from it (GMRES-based refinement)   */
+       H2_SOLVE_REFINE = 1,     /* iterative refinement only                       */
+       H2_SOLVE_GMRES = 2 };    /* flexible GMRES from the start (Section 5.5 uses
+                                   the factor of S as a GMRES preconditioner)     */
+
 typedef struct {
   double tol;            /* stop when max_col ||b - A x||_2 / ||b||_2 <= tol     */
-  int max_iter;          /* refinement steps (>= 1)                              */
+  int max_iter;          /* preconditioner applications in all (refinement
+                            steps plus GMRES steps), >= 1                        */
+  int method;            /* H2_SOLVE_AUTO, H2_SOLVE_REFINE or H2_SOLVE_GMRES      */
+  int restart;           /* GMRES restart length, 1..64 (0: 30)                  */
 } h2_solve_opts;
 
 typedef struct {
-  int iters;                   /* refinement steps taken                         */
+  int iters;                   /* preconditioner applications (refinement steps
+                                  plus GMRES steps)                              */
   double max_rel_residual;     /* final max_col ||b - A_H2 x|| / ||b||            */
   double seconds[3];           /* device s of the preconditioner applications
                                   (U^T, triangular solves, V), of the FP64 H^2
                                   matvecs, and host s building the plans       */
+  int gmres_steps;             /* of iters, the steps taken by GMRES             */
+  int refine_steps;            /* of iters, the refinement steps                 */
 } h2_solve_info;
 
 typedef struct h2_matrix h2_matrix;   /* tree, block tree, H^2 coefficients       */
@@ -184,7 +199,8 @@ int h2_sparse_export_plan(const h2_sparse* sp, int64_t* n_act, int64_t* kept,
  * level k of every instance (from the leaves up) runs in the same QR,
  * transform and strip launches, their work lists concatenated.  outs[i]
  * receives the handle of hs[i], as h2_sparsify would return it; on error no
- * handle is returned.  h2_last_timings / h2_last_work report the whole batch.
+ * handle is returned.  A matrix may appear once (EINVAL otherwise).
+ * h2_last_timings / h2_last_work report the whole batch.
  */
 int h2_sparsify_batch(h2_matrix* const* hs, int count, const h2_sparsify_opts* opts, h2_sparse** outs);
 
@@ -217,20 +233,39 @@ int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor** out);
 int h2_factor_analyze(const h2_sparse* sp, int64_t* filled_entries, double* exact_flops);
 
 /*
- * h2_solve: x = A_H2^{-1} b by iterative refinement: x += V (L D L^T)^{-1} U^T r,
- * r = b - A_H2 x with the FP64 H^2 matvec, until max_col ||r||/||b|| <= tol.
+ * h2_solve: x = A_H2^{-1} b with M^{-1} = V (L D L^T)^{-1} U^T (eq. sp0 with the
+ * factor of S) as the approximate inverse, against the FP64 H^2 matvec
+ * (Definition 4.8), until max_col ||b - A_H2 x||_2 / ||b||_2 <= tol:
+ * iterative refinement x += M^{-1} r, r = b - A_H2 x, or right-preconditioned
+ * flexible GMRES (Saad 1993: the search directions M^{-1} v_j are kept, so an
+ * FP32 M^{-1} need not be an exactly fixed linear map; restarted, modified by
+ * classical Gram-Schmidt applied twice), chosen by opts->method.
  * b, x: DEVICE pointers, column-major n x nrhs, leading dimension ld >= n,
- * ORIGINAL point order.  ENOCONV (x written, info filled) if max_iter is hit.
+ * ORIGINAL point order; 1 <= nrhs <= 512.  opts NULL: tol 1e-10, max_iter 30,
+ * H2_SOLVE_AUTO.  ENOCONV (x written, info filled) if max_iter is hit above
+ * the tolerance.  GMRES keeps 2 restart + 1 vectors of n x nrhs FP64 on the
+ * device (ENOMEM when they do not fit).
  */
 int h2_solve(h2_factor* f, const double* b, double* x, int64_t nrhs, int64_t ld,
              const h2_solve_opts* opts, h2_solve_info* info);
+
+/*
+ * h2_solve_with: as h2_solve, for the operator `a` (its FP64 H^2 matvec), with
+ * the factor f of another H^2 matrix of the same points and cluster tree as
+ * M^{-1} (EINVAL otherwise).  Section 5.5 preconditions GMRES on an accurate
+ * H^2 matrix by the sparsification of a coarse one of the same kernel.
+ */
+int h2_solve_with(const h2_matrix* a, h2_factor* f, const double* b, double* x, int64_t nrhs,
+                  int64_t ld, const h2_solve_opts* opts, h2_solve_info* info);
 
 /*
  * Batched factorisation and solve of independent instances: each instance as
  * h2_factor_S / h2_solve, run concurrently on a pool of streams that start
  * after the work queued on the current stream and that the current stream
  * waits for on return.  b[i], x[i]: device pointers of instance i (its own
- * nrhs[i], ld[i]); infos may be NULL.  A handle may appear once per batch.
+ * nrhs[i], ld[i]); infos may be NULL.  A handle may appear once per batch,
+ * and the factors of one solve batch must belong to different matrices
+ * (EINVAL otherwise: a matrix keeps one matvec plan and its vectors).
  * Any instance failing fails the call (first error reported); ENOCONV after
  * every instance ran if one of them stopped above the tolerance.
  */

@@ -23,6 +23,7 @@ H2_KERNEL_INVDIST = 0
 H2_KERNEL_EXP = 1
 H2_FP64, H2_MIXED = 0, 1
 H2_FACTOR_EXACT, H2_FACTOR_ILU0 = 0, 1
+H2_SOLVE_AUTO, H2_SOLVE_REFINE, H2_SOLVE_GMRES = 0, 1, 2
 
 _NAMES = {0: "H2_OK", -1: "H2_EINVAL", -2: "H2_ENOMEM", -3: "H2_EDEVICE", -4: "H2_ESINGULAR",
           -5: "H2_ENOCONV", -6: "H2_EUNSUPPORTED"}
@@ -52,12 +53,14 @@ class h2_factor_opts(ctypes.Structure):
 
 
 class h2_solve_opts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("method", ctypes.c_int),
+                ("restart", ctypes.c_int)]
 
 
 class h2_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("max_rel_residual", ctypes.c_double),
-                ("seconds", ctypes.c_double * 3)]
+                ("seconds", ctypes.c_double * 3), ("gmres_steps", ctypes.c_int),
+                ("refine_steps", ctypes.c_int)]
 
 
 _lib = None
@@ -93,6 +96,8 @@ _SIGS = {
                                       _I64P, _I64P, ctypes.POINTER(h2_solve_opts), ctypes.POINTER(h2_solve_info)]),
     "h2_solve": (ctypes.c_int, [_P, _P, _P, _I64, _I64, ctypes.POINTER(h2_solve_opts),
                                 ctypes.POINTER(h2_solve_info)]),
+    "h2_solve_with": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I64, ctypes.POINTER(h2_solve_opts),
+                                     ctypes.POINTER(h2_solve_info)]),
     "h2_apply_inverse": (ctypes.c_int, [_P, _P, _P, _I64, _I64]),
     "h2_matrix_destroy": (None, [_P]),
     "h2_sparse_destroy": (None, [_P]),
@@ -315,7 +320,7 @@ def h2_solve_batch(fs, bs, xs, tol: float = 1e-10, max_iter: int = 30, check: bo
     xarr = (_P * cnt)(*[x.data_ptr() for x in xs])
     nrhs = np.array([sh[1] for sh in shapes], dtype=np.int64)
     ld = np.array([sh[2] for sh in shapes], dtype=np.int64)
-    o = h2_solve_opts(float(tol), int(max_iter))
+    o = h2_solve_opts(float(tol), int(max_iter), H2_SOLVE_AUTO, 0)
     infos = (h2_solve_info * cnt)()
     code = lib().h2_solve_batch(_handles(fs), cnt, barr, xarr, nrhs.ctypes.data_as(_I64P),
                                 ld.ctypes.data_as(_I64P), ctypes.byref(o), infos)
@@ -323,8 +328,7 @@ def h2_solve_batch(fs, bs, xs, tol: float = 1e-10, max_iter: int = 30, check: bo
         _check(code)
     elif code not in (H2_OK, H2_ENOCONV):
         _check(code)
-    return [dict(iters=i.iters, residual=i.max_rel_residual, code=code, t_precond=i.seconds[0],
-                 t_matvec=i.seconds[1], t_plan=i.seconds[2]) for i in infos]
+    return [_info_dict(i, code) for i in infos]
 
 
 def h2_factor_analyze(sp: H2SparseHandle):
@@ -335,17 +339,38 @@ def h2_factor_analyze(sp: H2SparseHandle):
     return e.value, fl.value
 
 
-def h2_solve(f: H2FactorHandle, b, x, tol: float = 1e-10, max_iter: int = 30, check: bool = True):
-    """x = A_H2^{-1} b by refinement; b, x float64 CUDA tensors (n, nrhs), column-major."""
+def _info_dict(info, code):
+    return dict(iters=info.iters, residual=info.max_rel_residual, code=code,
+                t_precond=info.seconds[0], t_matvec=info.seconds[1], t_plan=info.seconds[2],
+                gmres_steps=info.gmres_steps, refine_steps=info.refine_steps)
+
+
+def h2_solve(f: H2FactorHandle, b, x, tol: float = 1e-10, max_iter: int = 30, check: bool = True,
+             method: int = H2_SOLVE_AUTO, restart: int = 0):
+    """x = A_H2^{-1} b (refinement, GMRES fallback or GMRES); b, x float64 CUDA
+    tensors (n, nrhs), column-major."""
     _use_torch_stream()
     n, nrhs, ld = _colmajor(b)
-    o = h2_solve_opts(float(tol), int(max_iter))
+    o = h2_solve_opts(float(tol), int(max_iter), int(method), int(restart))
     info = h2_solve_info()
     code = lib().h2_solve(f.ptr, _dev(b), _dev(x), nrhs, ld, ctypes.byref(o), ctypes.byref(info))
     if check or code not in (H2_OK, H2_ENOCONV):
         _check(code)
-    return dict(iters=info.iters, residual=info.max_rel_residual, code=code,
-                t_precond=info.seconds[0], t_matvec=info.seconds[1], t_plan=info.seconds[2])
+    return _info_dict(info, code)
+
+
+def h2_solve_with(a: H2MatrixHandle, f: H2FactorHandle, b, x, tol: float = 1e-10, max_iter: int = 30,
+                  check: bool = True, method: int = H2_SOLVE_GMRES, restart: int = 0):
+    """x = A^{-1} b for the matrix `a`, with the factor `f` of another H^2
+    matrix of the same points as preconditioner."""
+    _use_torch_stream()
+    n, nrhs, ld = _colmajor(b)
+    o = h2_solve_opts(float(tol), int(max_iter), int(method), int(restart))
+    info = h2_solve_info()
+    code = lib().h2_solve_with(a.ptr, f.ptr, _dev(b), _dev(x), nrhs, ld, ctypes.byref(o), ctypes.byref(info))
+    if check or code not in (H2_OK, H2_ENOCONV):
+        _check(code)
+    return _info_dict(info, code)
 
 
 def h2_apply_inverse(f: H2FactorHandle, b, x):

@@ -48,8 +48,9 @@ def _run(cmd):
 
 
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(OBJ, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src, extra in SOURCES.items():
         obj = os.path.join(OBJ, src + ".o")
         if src.endswith(".hip"):
@@ -59,8 +60,12 @@ def build(verbose: bool = False) -> str:
         cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    # translation units are independent: compile them side by side
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"
     link = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fopenmp", "-o", tmp] + objs + \
         ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/llvm/lib"]

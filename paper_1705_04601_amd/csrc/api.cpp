@@ -26,6 +26,8 @@ static thread_local double g_work[16] = {0};
 int apply_inverse_impl(h2_factor* f, const double* b, double* x, h2::i64 nrhs, h2::i64 ld);
 int solve_impl(h2_factor* f, const double* b, double* x, h2::i64 nrhs, h2::i64 ld, const h2_solve_opts* o,
                h2_solve_info* info);
+int solve_with_impl(const h2_matrix* A, h2_factor* f, const double* b, double* x, h2::i64 nrhs, h2::i64 ld,
+                    const h2_solve_opts* o, h2_solve_info* info);
 
 using namespace h2;
 
@@ -237,6 +239,10 @@ extern "C" int h2_sparsify_batch(h2_matrix* const* hs, int count, const h2_spars
   if (!hs || !outs || count < 1) fail(H2_EINVAL, "null argument or empty batch");
   for (int i = 0; i < count; ++i) {
     if (!hs[i]) fail(H2_EINVAL, "null matrix in the batch");
+    // instances are planned on concurrent threads, and planning uploads the
+    // matrix's device copy: one matrix may appear once
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) fail(H2_EINVAL, "the same matrix twice in the batch");
     outs[i] = nullptr;
   }
   // the merged sweep generates every instance's close blocks in one launch
@@ -300,8 +306,12 @@ extern "C" int h2_solve_batch(h2_factor* const* fs, int count, const double* con
   for (int i = 0; i < count; ++i) {
     if (!fs[i] || !b[i] || !x[i]) fail(H2_EINVAL, "null factor or vector in the batch");
     if (nrhs[i] < 1 || nrhs[i] > 512 || ld[i] < fs[i]->sp->H->tree.n) fail(H2_EINVAL, "bad nrhs / ld in the batch");
-    for (int j = 0; j < i; ++j)
+    // the instances run on concurrent threads, and a matrix keeps one
+    // matvec plan (its vectors included): one matrix may appear once
+    for (int j = 0; j < i; ++j) {
       if (fs[j] == fs[i]) fail(H2_EINVAL, "the same factor twice in the batch");
+      if (fs[j]->sp->H == fs[i]->sp->H) fail(H2_EINVAL, "two factors of the same matrix in the batch");
+    }
   }
   std::vector<int> rc(count, H2_OK);
   run_pooled(count, [&](int i) {
@@ -318,7 +328,17 @@ extern "C" int h2_solve(h2_factor* f, const double* b, double* x, int64_t nrhs, 
   if (!f || !b || !x) fail(H2_EINVAL, "null argument");
   if (nrhs < 1 || nrhs > 512 || ld < f->sp->H->tree.n) fail(H2_EINVAL, "bad nrhs / ld");
   const int rc = solve_impl(f, b, x, nrhs, ld, opts, info);
-  if (rc == H2_ENOCONV) fail(H2_ENOCONV, "refinement stopped above the tolerance");
+  if (rc == H2_ENOCONV) fail(H2_ENOCONV, "solve stopped above the tolerance");
+  H2_API_END
+}
+
+extern "C" int h2_solve_with(const h2_matrix* a, h2_factor* f, const double* b, double* x, int64_t nrhs,
+                             int64_t ld, const h2_solve_opts* opts, h2_solve_info* info) {
+  H2_API_BEGIN
+  if (!a || !f || !b || !x) fail(H2_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > 512 || ld < a->tree.n) fail(H2_EINVAL, "bad nrhs / ld");
+  const int rc = solve_with_impl(a, f, b, x, nrhs, ld, opts, info);
+  if (rc == H2_ENOCONV) fail(H2_ENOCONV, "solve stopped above the tolerance");
   H2_API_END
 }
 

@@ -176,6 +176,17 @@ void launch_scatter_rm(const double* in, const int64_t* idx, double* out, int64_
 int residual_rm_blocks(int64_t n);
 void launch_residual_rm(const double* b, const double* y, double* r, int64_t n, int64_t nrhs, double* part,
                         double* nrm2, hipStream_t st);
+// Krylov helpers on RHS-fastest blocks (n x nrhs, nrhs <= 512); vector i of
+// a set starts at V + i vstride.  All sums run in a fixed order.
+// out[i nrhs + j] = sum_r V_i[r, j] w[r, j] for i < cnt; part: scratch of
+// residual_rm_blocks(n) * cnt * nrhs doubles
+void launch_multi_dot(const double* V, int64_t vstride, int cnt, const double* w, int64_t n, int64_t nrhs,
+                      double* part, double* out, hipStream_t st);
+// w[r, j] += sign * sum_{i < cnt, in order} coef[i nrhs + j] V_i[r, j]
+void launch_multi_axpy(const double* V, int64_t vstride, int cnt, const double* coef, double sign, double* w,
+                       int64_t n, int64_t nrhs, hipStream_t st);
+// v[r, j] = w[r, j] / sqrt(nrm2[j]), or 0 where nrm2[j] is 0
+void launch_scale_cols(const double* w, const double* nrm2, double* v, int64_t n, int64_t nrhs, hipStream_t st);
 // float out = in / colscale[j];  double acc += float in * colscale[j]
 void launch_scale_to_f_rm(const double* in, const double* cs, float* out, int64_t n, int64_t nrhs, hipStream_t st);
 void launch_add_scaled_f_rm(const float* in, const double* cs, double* acc, int64_t n, int64_t nrhs, hipStream_t st);

@@ -751,6 +751,47 @@ __global__ void sum_parts_kernel(const double* part, int nblk, int64_t width, do
     nrm2[c] = s;
   }
 }
+// per block of rows and vector i: partial sums of V_i[r, j] w[r, j] (lanes
+// over the columns, 4 row groups), written to part[blk][i][j]
+__global__ __launch_bounds__(256) void multi_dot_kernel(const double* V, int64_t vstride, const double* w,
+                                                        int64_t n, int64_t nrhs, int64_t rows, double* part) {
+  __shared__ double red[4][512];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i = blockIdx.y, cnt = gridDim.y;
+  const double* v = V + int64_t(i) * vstride;
+  const int64_t r0 = blockIdx.x * rows, r1 = min(n, r0 + rows);
+  double s[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s[q] = 0.0;
+  for (int64_t r = r0 + ty; r < r1; r += 4) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t j = tx + 64 * q;
+      if (j < nrhs) s[q] += v[r * nrhs + j] * w[r * nrhs + j];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) red[ty][tx + 64 * q] = s[q];
+  __syncthreads();
+  const int64_t width = int64_t(cnt) * nrhs;
+  for (int j = threadIdx.x; j < nrhs; j += 256)
+    part[blockIdx.x * width + int64_t(i) * nrhs + j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
+}
+__global__ void multi_axpy_kernel(const double* V, int64_t vstride, int cnt, const double* coef, double sign,
+                                  double* w, int64_t tot, int64_t nrhs) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = e % nrhs;
+    double acc = 0.0;
+    for (int i = 0; i < cnt; ++i) acc += coef[int64_t(i) * nrhs + j] * V[int64_t(i) * vstride + e];
+    w[e] += sign * acc;
+  }
+}
+__global__ void scale_cols_kernel(const double* w, const double* nrm2, double* v, int64_t tot, int64_t nrhs) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
+    const double q = nrm2[e % nrhs];
+    v[e] = q > 0.0 ? w[e] / sqrt(q) : 0.0;
+  }
+}
 __global__ void scale_to_f_rm_kernel(const double* in, const double* cs, float* out, int64_t tot, int64_t nrhs) {
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x)
     out[e] = float(in[e] / cs[e % nrhs]);
@@ -928,6 +969,25 @@ void launch_residual_rm(const double* b, const double* y, double* r, int64_t n, 
   const int64_t rows = (n + nblk - 1) / nblk;
   hipLaunchKernelGGL(residual_rm_kernel, dim3(nblk), dim3(256), 0, st, b, y, r, n, nrhs, rows, part);
   hipLaunchKernelGGL(sum_parts_kernel, dim3(grid_for(2 * nrhs)), dim3(256), 0, st, part, nblk, 2 * nrhs, nrm2);
+}
+void launch_multi_dot(const double* V, int64_t vstride, int cnt, const double* w, int64_t n, int64_t nrhs,
+                      double* part, double* out, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0 || cnt <= 0) return;
+  const int nblk = residual_rm_blocks(n);
+  const int64_t rows = (n + nblk - 1) / nblk;
+  hipLaunchKernelGGL(multi_dot_kernel, dim3(nblk, cnt), dim3(256), 0, st, V, vstride, w, n, nrhs, rows, part);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(grid_for(int64_t(cnt) * nrhs)), dim3(256), 0, st, part, nblk,
+                     int64_t(cnt) * nrhs, out);
+}
+void launch_multi_axpy(const double* V, int64_t vstride, int cnt, const double* coef, double sign, double* w,
+                       int64_t n, int64_t nrhs, hipStream_t st) {
+  if (n * nrhs > 0 && cnt > 0)
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, V, vstride, cnt, coef, sign, w,
+                       n * nrhs, nrhs);
+}
+void launch_scale_cols(const double* w, const double* nrm2, double* v, int64_t n, int64_t nrhs, hipStream_t st) {
+  if (n * nrhs > 0)
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, w, nrm2, v, n * nrhs, nrhs);
 }
 void launch_scale_to_f_rm(const double* in, const double* cs, float* out, int64_t n, int64_t nrhs, hipStream_t st) {
   if (n * nrhs > 0) hipLaunchKernelGGL(scale_to_f_rm_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, in, cs, out, n * nrhs, nrhs);

@@ -233,85 +233,267 @@ int apply_inverse_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 l
   return H2_OK;
 }
 
-// Iterative refinement.  x accumulates in tree order (p.rs), r = b - A_H2 x.
-int solve_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld, const h2_solve_opts* o,
-               h2_solve_info* info) {
-  h2_matrix& H = *f->sp->H;
-  const i64 n = H.tree.n;
-  hipStream_t st = current_stream();
-  const auto t_plan0 = std::chrono::steady_clock::now();
-  SolvePlan& p = solve_plan(*f, nrhs);
-  MatvecPlan& mv = matvec_plan(H, nrhs);
-  const double plan_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_plan0).count();
-  // device time of the preconditioner applications and of the matvecs
-  std::vector<hipEvent_t> ev;
-  auto mark = [&]() {
+namespace h2 {
+
+// State of a solve: right-hand side, solution and residual in tree order,
+// RHS-fastest, FP64; the matvec plan of the operator A and the solve plan of
+// the factor.
+struct SolveState {
+  h2_factor& f;
+  const h2_matrix& A;
+  SolvePlan& p;
+  MatvecPlan& mv;
+  MatvecPlanView mvb;
+  i64 n, nrhs;
+  hipStream_t st;
+  double* bt;     // b
+  double* xt;     // x
+  double* rt;     // b - A x
+  double* nrm;    // 2 nrhs: ||r_j||^2, ||b_j||^2
+  double* part;   // scratch of the reductions
+  std::vector<double> bnorm;
+  std::vector<hipEvent_t> ev;  // pairs of (start, end) events: precond, matvec
+  std::vector<int> ev_kind;    // 0: preconditioner, 1: matvec
+  void mark_begin() {
     hipEvent_t e;
     HIPCHECK(hipEventCreate(&e));
     HIPCHECK(hipEventRecord(e, st));
     ev.push_back(e);
-  };
-  MatvecPlanView mvb = matvec_buffers(mv);
-  const size_t vec = sizeof(double) * n * nrhs;
-  DeviceBuffer bt(vec), rt(vec), nrm(sizeof(double) * 2 * nrhs), cs(sizeof(double) * nrhs),
-      part(sizeof(double) * 2 * nrhs * residual_rm_blocks(n));
-  launch_gather_rm(b, ld, H.d_perm.as<i64>(), bt.as<double>(), n, nrhs, st);
-  launch_fill(p.rs.as<double>(), n * nrhs, 0.0, st);
-  std::vector<double> h_nrm(2 * nrhs), h_cs(nrhs);
-  // r = b (x = 0) and the column norms of b for the first scaling
-  launch_fill(mvb.yt, n * nrhs, 0.0, st);
-  launch_residual_rm(bt.as<double>(), mvb.yt, rt.as<double>(), n, nrhs, part.as<double>(), nrm.as<double>(), st);
-  HIPCHECK(hipMemcpyAsync(h_nrm.data(), nrm.ptr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
-  HIPCHECK(hipStreamSynchronize(st));
-  std::vector<double> bnorm(nrhs);
-  for (i64 j = 0; j < nrhs; ++j) bnorm[j] = std::sqrt(h_nrm[nrhs + j]);
+  }
+  void mark_end(int kind) {
+    mark_begin();
+    ev_kind.push_back(kind);
+  }
+  // y = A x_in (x_in in tree order, RHS-fastest) into the matvec plan's yt
+  void matvec(const double* x_in) {
+    mark_begin();
+    HIPCHECK(hipMemcpyAsync(mvb.xt, x_in, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
+    run_matvec_tree(A, mv, st);
+    mark_end(1);
+  }
+  // r = b - A x and its column norms; returns max_j ||r_j|| / ||b_j||
+  double residual(std::vector<double>& h_nrm) {
+    matvec(xt);
+    launch_residual_rm(bt, mvb.yt, rt, n, nrhs, part, nrm, st);
+    HIPCHECK(hipMemcpyAsync(h_nrm.data(), nrm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    double res = 0;
+    for (i64 j = 0; j < nrhs; ++j) {
+      const double q = bnorm[j] > 0 ? std::sqrt(h_nrm[j]) / bnorm[j] : 0.0;
+      if (!std::isfinite(q)) return q;
+      res = std::max(res, q);
+    }
+    return res;
+  }
+};
+
+// Flexible GMRES (Saad 1993), right preconditioned by M^{-1} (the factor of S
+// inside U^T and V), restarted every `m` steps, many right-hand sides at once
+// (one Krylov space per column; the columns share every launch).  Arnoldi by
+// classical Gram-Schmidt applied twice, with the Hessenberg columns on the
+// host, reduced by Givens rotations per right-hand side.  Starts from the
+// state's x and r (r = b - A x, column norms in h_nrm); stops when the true
+// residual is at or below tol or after `budget` steps.  Returns the steps
+// taken; res holds the final residual.
+static int fgmres(SolveState& S, int m, int budget, double tol, std::vector<double>& h_nrm, double& res) {
+  const i64 n = S.n, nrhs = S.nrhs, len = n * nrhs;
+  hipStream_t st = S.st;
+  DeviceBuffer vb(sizeof(double) * size_t(m + 1) * len), zb(sizeof(double) * size_t(m) * len),
+      w(sizeof(double) * len), c1(sizeof(double) * (m + 1) * nrhs), c2(sizeof(double) * (m + 1) * nrhs),
+      yd(sizeof(double) * m * nrhs), cs(sizeof(double) * nrhs), part(sizeof(double) * size_t(m + 1) * nrhs *
+                                                                      residual_rm_blocks(n));
+  double* V = vb.as<double>();
+  double* Z = zb.as<double>();
+  std::vector<double> ones(nrhs, 1.0);
+  HIPCHECK(hipMemcpyAsync(cs.ptr, ones.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+  // per column: Hessenberg (m + 1) x m column-major, rotations, right-hand side g
+  std::vector<double> H(size_t(nrhs) * (m + 1) * m), gc(size_t(nrhs) * m), gs(size_t(nrhs) * m),
+      g(size_t(nrhs) * (m + 1)), h1((m + 1) * nrhs), h2((m + 1) * nrhs), nw(nrhs), y(size_t(m) * nrhs);
+  int steps = 0;
+  while (steps < budget) {
+    // v_0 = r / ||r||, g = ||r|| e_1
+    HIPCHECK(hipMemcpyAsync(S.nrm, h_nrm.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    launch_scale_cols(S.rt, S.nrm, V, n, nrhs, st);
+    std::fill(g.begin(), g.end(), 0.0);
+    for (i64 c = 0; c < nrhs; ++c) g[c * (m + 1)] = std::sqrt(h_nrm[c]);
+    int j = 0;
+    for (; j < m && steps < budget; ++j, ++steps) {
+      double* vj = V + j * len;
+      double* zj = Z + j * len;
+      // z_j = M^{-1} v_j (columns of unit norm: no scaling), w = A z_j
+      S.mark_begin();
+      launch_fill(zj, len, 0.0, st);
+      correction(S.f, S.p, vj, zj, cs.as<double>(), st);
+      S.mark_end(0);
+      S.matvec(zj);
+      HIPCHECK(hipMemcpyAsync(w.ptr, S.mvb.yt, sizeof(double) * len, hipMemcpyDeviceToDevice, st));
+      // two passes of classical Gram-Schmidt against v_0 .. v_j, then ||w||
+      launch_multi_dot(V, len, j + 1, w.as<double>(), n, nrhs, part.as<double>(), c1.as<double>(), st);
+      launch_multi_axpy(V, len, j + 1, c1.as<double>(), -1.0, w.as<double>(), n, nrhs, st);
+      launch_multi_dot(V, len, j + 1, w.as<double>(), n, nrhs, part.as<double>(), c2.as<double>(), st);
+      launch_multi_axpy(V, len, j + 1, c2.as<double>(), -1.0, w.as<double>(), n, nrhs, st);
+      launch_multi_dot(w.as<double>(), 0, 1, w.as<double>(), n, nrhs, part.as<double>(), S.nrm, st);
+      launch_scale_cols(w.as<double>(), S.nrm, V + (j + 1) * len, n, nrhs, st);
+      HIPCHECK(hipMemcpyAsync(h1.data(), c1.ptr, sizeof(double) * (j + 1) * nrhs, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(h2.data(), c2.ptr, sizeof(double) * (j + 1) * nrhs, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(nw.data(), S.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      double est = 0;
+      for (i64 c = 0; c < nrhs; ++c) {
+        double* hc = &H[size_t(c) * (m + 1) * m + size_t(j) * (m + 1)];
+        for (int i = 0; i <= j; ++i) hc[i] = h1[i * nrhs + c] + h2[i * nrhs + c];
+        hc[j + 1] = std::sqrt(nw[c]);
+        double* gcc = &gc[size_t(c) * m];
+        double* gss = &gs[size_t(c) * m];
+        for (int i = 0; i < j; ++i) {
+          const double a = hc[i], b = hc[i + 1];
+          hc[i] = gcc[i] * a + gss[i] * b;
+          hc[i + 1] = -gss[i] * a + gcc[i] * b;
+        }
+        const double a = hc[j], b = hc[j + 1], r = std::hypot(a, b);
+        gcc[j] = r > 0 ? a / r : 1.0;
+        gss[j] = r > 0 ? b / r : 0.0;
+        hc[j] = r;
+        hc[j + 1] = 0.0;
+        double* gg = &g[size_t(c) * (m + 1)];
+        gg[j + 1] = -gss[j] * gg[j];
+        gg[j] = gcc[j] * gg[j];
+        if (S.bnorm[c] > 0) est = std::max(est, std::abs(gg[j + 1]) / S.bnorm[c]);
+      }
+      if (!std::isfinite(est)) {
+        ++steps;
+        ++j;
+        break;
+      }
+      if (est <= 0.5 * tol) {
+        ++steps;
+        ++j;
+        break;
+      }
+    }
+    // x += Z y, y from the triangular system of each column
+    for (i64 c = 0; c < nrhs; ++c) {
+      const double* hc = &H[size_t(c) * (m + 1) * m];
+      const double* gg = &g[size_t(c) * (m + 1)];
+      for (int i = j - 1; i >= 0; --i) {
+        double acc = gg[i];
+        for (int k = i + 1; k < j; ++k) acc -= hc[size_t(k) * (m + 1) + i] * y[k * nrhs + c];
+        const double d = hc[size_t(i) * (m + 1) + i];
+        y[i * nrhs + c] = d != 0.0 ? acc / d : 0.0;
+      }
+    }
+    HIPCHECK(hipMemcpyAsync(yd.ptr, y.data(), sizeof(double) * j * nrhs, hipMemcpyHostToDevice, st));
+    launch_multi_axpy(Z, len, j, yd.as<double>(), 1.0, S.xt, n, nrhs, st);
+    res = S.residual(h_nrm);
+    if (!(res > tol)) break;  // converged (or not finite)
+  }
+  return steps;
+}
+
+}  // namespace h2
+
+// Solve of A x = b with the factor f as approximate inverse (its matrix's
+// tree); x in tree order (p.rs), r = b - A x.
+static int solve_impl2(h2_factor* f, const h2_matrix& A, const double* b, double* x, i64 nrhs, i64 ld,
+                       const h2_solve_opts* o, h2_solve_info* info) {
+  const i64 n = A.tree.n;
+  hipStream_t st = current_stream();
+  const auto t_plan0 = std::chrono::steady_clock::now();
+  SolvePlan& p = solve_plan(*f, nrhs);
+  MatvecPlan& mv = matvec_plan(A, nrhs);
+  const double plan_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_plan0).count();
   const double tol = o ? o->tol : 1e-10;
   const int max_iter = o ? std::max(1, o->max_iter) : 30;
+  const int method = o ? o->method : H2_SOLVE_AUTO;
+  int restart = o && o->restart > 0 ? o->restart : 30;
+  if (method < H2_SOLVE_AUTO || method > H2_SOLVE_GMRES) fail(H2_EINVAL, "unknown solve method");
+  if (restart > 64) fail(H2_EINVAL, "GMRES restart above 64");
+  const size_t vec = sizeof(double) * n * nrhs;
+  DeviceBuffer bt(vec), rt(vec), xprev(method == H2_SOLVE_AUTO ? vec : 0), nrm(sizeof(double) * 2 * nrhs),
+      cs(sizeof(double) * nrhs), part(sizeof(double) * 2 * nrhs * residual_rm_blocks(n));
+  SolveState S{*f, A, p, mv, matvec_buffers(mv), n, nrhs, st, bt.as<double>(), p.rs.as<double>(),
+               rt.as<double>(), nrm.as<double>(), part.as<double>(), {}, {}, {}};
+  launch_gather_rm(b, ld, A.d_perm.as<i64>(), S.bt, n, nrhs, st);
+  launch_fill(S.xt, n * nrhs, 0.0, st);
+  std::vector<double> h_nrm(2 * nrhs), h_cs(nrhs);
+  // r = b (x = 0) and the column norms of b
+  launch_fill(S.mvb.yt, n * nrhs, 0.0, st);
+  launch_residual_rm(S.bt, S.mvb.yt, S.rt, n, nrhs, S.part, S.nrm, st);
+  HIPCHECK(hipMemcpyAsync(h_nrm.data(), S.nrm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  S.bnorm.resize(nrhs);
+  for (i64 j = 0; j < nrhs; ++j) S.bnorm[j] = std::sqrt(h_nrm[nrhs + j]);
   double res = 0;
-  int it = 0;
-  for (it = 1; it <= max_iter; ++it) {
+  for (i64 j = 0; j < nrhs; ++j) res = std::max(res, S.bnorm[j] > 0 ? 1.0 : 0.0);
+  int refine = 0, gm = 0, stall = 0;
+  bool to_gmres = method == H2_SOLVE_GMRES;
+  double prev = res;
+  while (!to_gmres && refine < max_iter && res > tol) {
     for (i64 j = 0; j < nrhs; ++j) {
       const double rn = std::sqrt(h_nrm[j]);
       h_cs[j] = rn > 0 ? rn : 1.0;
     }
+    if (method == H2_SOLVE_AUTO) HIPCHECK(hipMemcpyAsync(xprev.ptr, S.xt, vec, hipMemcpyDeviceToDevice, st));
     HIPCHECK(hipMemcpyAsync(cs.ptr, h_cs.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
-    mark();
-    correction(*f, p, rt.as<double>(), p.rs.as<double>(), cs.as<double>(), st);
-    mark();
-    // r = b - A x  (x = p.rs in tree order)
-    HIPCHECK(hipMemcpyAsync(mvb.xt, p.rs.ptr, vec, hipMemcpyDeviceToDevice, st));
-    run_matvec_tree(H, mv, st);
-    mark();
-    launch_residual_rm(bt.as<double>(), mvb.yt, rt.as<double>(), n, nrhs, part.as<double>(), nrm.as<double>(), st);
-    HIPCHECK(hipMemcpyAsync(h_nrm.data(), nrm.ptr, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    res = 0;
-    for (i64 j = 0; j < nrhs; ++j)
-      res = std::max(res, bnorm[j] > 0 ? std::sqrt(h_nrm[j]) / bnorm[j] : 0.0);
-    if (!std::isfinite(res)) break;
-    if (res <= tol) break;
+    S.mark_begin();
+    correction(*f, p, S.rt, S.xt, cs.as<double>(), st);
+    S.mark_end(0);
+    ++refine;
+    res = S.residual(h_nrm);
+    if (method != H2_SOLVE_AUTO) {
+      if (!std::isfinite(res)) break;
+      continue;
+    }
+    const double ratio = res / prev;
+    if (!std::isfinite(res) || ratio > 2.0) {
+      // diverging: back to the previous x (and its residual), then GMRES
+      HIPCHECK(hipMemcpyAsync(S.xt, xprev.ptr, vec, hipMemcpyDeviceToDevice, st));
+      res = S.residual(h_nrm);
+      to_gmres = true;
+      break;
+    }
+    stall = ratio > 0.9 ? stall + 1 : 0;
+    prev = res;
+    if (stall >= 3) to_gmres = true;
   }
-  if (it > max_iter) it = max_iter;
-  launch_scatter_rm(p.rs.as<double>(), H.d_perm.as<i64>(), x, ld, n, nrhs, st);
+  if (to_gmres && res > tol && refine < max_iter && std::isfinite(res))
+    gm = fgmres(S, restart, max_iter - refine, tol, h_nrm, res);
+  launch_scatter_rm(S.xt, A.d_perm.as<i64>(), x, ld, n, nrhs, st);
   HIPCHECK(hipStreamSynchronize(st));
   double t_prec = 0, t_mv = 0;
-  for (size_t e = 0; e + 2 < ev.size(); e += 3) {
-    float a = 0, c = 0;
-    HIPCHECK(hipEventElapsedTime(&a, ev[e], ev[e + 1]));
-    HIPCHECK(hipEventElapsedTime(&c, ev[e + 1], ev[e + 2]));
-    t_prec += a * 1e-3;
-    t_mv += c * 1e-3;
+  for (size_t e = 0; e < S.ev_kind.size(); ++e) {
+    float a = 0;
+    HIPCHECK(hipEventElapsedTime(&a, S.ev[2 * e], S.ev[2 * e + 1]));
+    (S.ev_kind[e] == 0 ? t_prec : t_mv) += a * 1e-3;
   }
-  for (auto e : ev) (void)hipEventDestroy(e);
+  for (auto e : S.ev) (void)hipEventDestroy(e);
   if (info) {
-    info->iters = it;
+    info->iters = refine + gm;
     info->max_rel_residual = res;
     info->seconds[0] = t_prec;
     info->seconds[1] = t_mv;
     info->seconds[2] = plan_s;
+    info->gmres_steps = gm;
+    info->refine_steps = refine;
   }
   if (!(res <= tol)) return H2_ENOCONV;
   return H2_OK;
+}
+
+int solve_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld, const h2_solve_opts* o,
+               h2_solve_info* info) {
+  return solve_impl2(f, *f->sp->H, b, x, nrhs, ld, o, info);
+}
+
+// Solve with another matrix of the same points as the operator (the factor of
+// a coarser H^2 matrix as preconditioner of a finer one, Section 5.5).
+int solve_with_impl(const h2_matrix* A, h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld,
+                    const h2_solve_opts* o, h2_solve_info* info) {
+  const h2_matrix& B = *f->sp->H;
+  if (A->tree.n != B.tree.n || A->tree.perm != B.tree.perm || A->tree.depth != B.tree.depth)
+    fail(H2_EINVAL, "the operator and the factor's matrix must share points and cluster tree");
+  const_cast<h2_matrix*>(A)->upload_all();
+  return solve_impl2(f, *A, b, x, nrhs, ld, o, info);
 }
 
 h2_factor::~h2_factor() = default;

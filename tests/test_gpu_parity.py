@@ -415,6 +415,18 @@ def test_batch_rejects_repeated_handles():
     with pytest.raises(P.H2Error) as e:
         P.h2_factor_S_batch([sp, sp])
     assert e.value.code == P.H2_EINVAL
+    # one matrix twice: its device copy and its matvec plan are per matrix
+    h = imported("torus777")
+    with pytest.raises(P.H2Error) as e:
+        P.h2_sparsify_batch([h, h], P.H2_FP64)
+    assert e.value.code == P.H2_EINVAL
+    f1 = P.h2_factor_S(P.h2_sparsify(h, P.H2_FP64))
+    f2 = P.h2_factor_S(P.h2_sparsify(h, P.H2_MIXED))
+    b = dev(np.ones((777, 1)))
+    xs = [dev(np.zeros((777, 1))), dev(np.zeros((777, 1)))]
+    with pytest.raises(P.H2Error) as e:
+        P.h2_solve_batch([f1, f2], [b, b], xs, tol=1e-10)
+    assert e.value.code == P.H2_EINVAL
 
 
 def test_graph_replays_match_eager(tmp_path):
