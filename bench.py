@@ -35,7 +35,12 @@ KERNELS = {"qr": "qr_kernel", "close": "gemm_kc_kernel<float, 0, ...>", "couplin
            "strips": "gemm_kc_kernel<float, 0, ...>",
            "factor_pivots_z": "inverse_kernel<float> + gemm_kc_kernel<float, 1, ...> + copy_segments_kernel<float>"
                               " + schur_reduce_kernel<float>",
-           "factor_schur": "schur_kernel<float>"}
+           "factor_schur": "schur_kernel<float, true> + schur_kernel<float, false>"}
+# the two Schur kernels: tiles of more than 4 x 4 blocks of 16 (whole targets
+# up to 128 x 128) and the others; h2_last_timings [8] / [9] and
+# h2_last_work [10..13] report them apart
+SCHUR_KERNELS = [("schur_big", "schur_kernel<float, true>", 8, 10, 11),
+                 ("schur_small", "schur_kernel<float, false>", 9, 12, 13)]
 # HBM traffic of the Schur kernel measured with rocprofv3 counters; used only
 # while the kernel and its planner are the sources the counters were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_kernel_cube1m_traffic.txt")
@@ -56,9 +61,10 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """Bytes per Schur launch from the committed counter summary, or None when
-    it was taken on another workload or on other kernel sources."""
+def measured_traffic(workload, kernel):
+    """Bytes per launch of one Schur kernel from the committed counter summary,
+    or None when it was taken on another workload, another kernel or other
+    kernel sources."""
     if workload != "cube1m" or not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -67,7 +73,7 @@ def measured_traffic(workload):
             k, sep, v = line.partition(":")
             if sep:
                 vals[k.strip()] = v.strip()
-    if vals.get("sources_sha256") != source_digest():
+    if vals.get("sources_sha256") != source_digest() or vals.get("kernel") != kernel:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -105,9 +111,11 @@ def run_step(P, h, precision, b, x, tol, max_iter, mode):
     del f, sp
     ms = np.concatenate([ms_sp[:4], ms_f[4:6]])
     work = np.concatenate([work_sp[:4], work_f[4:6]])
+    schur = {name: dict(ms=float(ms_f[it]), flops=float(work_f[iw]), launches=int(work_f[il]))
+             for name, _, it, iw, il in SCHUR_KERNELS}
     return dict(t_sparsify=t1 - t0, t_factor=t2 - t1, t_solve=t3 - t2, info=info,
                 phase_ms=ms, phase_flops=work, qr_bytes=work_sp[6], s_blocks=nb, s_entries=ne,
-                schur_launches=int(work_f[8]), factor_entries=int(work_f[9]))
+                schur_launches=int(work_f[8]), factor_entries=int(work_f[9]), schur=schur)
 
 
 def time_path(P, h, precision, b, x, steps, warmup, tol, max_iter, mode):
@@ -331,17 +339,31 @@ def main():
     ms = np.mean([r["phase_ms"] for r in recs], axis=0)
     fl = recs[-1]["phase_flops"]
     dom = int(np.argmax(ms))
-    achieved = fl[dom] / (ms[dom] * 1e-3) / 1e12
     peak = PEAK_TFLOPS["f64"] if PHASES[dom] == "qr" else PEAK_TFLOPS["f32"]
-    launches = last["schur_launches"] if PHASES[dom] == "factor_schur" else None
-    traffic = measured_traffic(args.workload) if PHASES[dom] == "factor_schur" else None
-    avg_s = float(ms[dom]) * 1e-3 / launches if launches else None
+    # per-kernel figures of the Schur update (event time, flops, launches, mean over the timed steps)
+    schur = {name: {"kernel": label,
+                    "ms": float(np.mean([r["schur"][name]["ms"] for r in recs])),
+                    "flops": last["schur"][name]["flops"], "launches": last["schur"][name]["launches"]}
+             for name, label, _, _, _ in SCHUR_KERNELS}
+    for v in schur.values():
+        v["tflops"] = round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] > 0 else None
+        v["avg_launch_ms"] = round(v["ms"] / v["launches"], 4) if v["launches"] else None
+    if PHASES[dom] == "factor_schur":
+        # the dominant kernel is the Schur kernel with the larger share of the phase
+        kname = max(schur, key=lambda k: schur[k]["ms"])
+        kr = schur[kname]
+        label, k_ms, k_fl, launches = kr["kernel"], kr["ms"], kr["flops"], kr["launches"]
+    else:
+        kname, label, k_ms, k_fl, launches = PHASES[dom], KERNELS[PHASES[dom]], float(ms[dom]), float(fl[dom]), None
+    achieved = k_fl / (k_ms * 1e-3) / 1e12
+    traffic = measured_traffic(args.workload, label) if launches else None
+    avg_s = k_ms * 1e-3 / launches if launches else None
     hbm = None
     if traffic and avg_s:
         # the same launch against the HBM roof: counter bytes over the launch time,
         # and the arithmetic intensity against the ridge of the two roofs
         ridge = peak * 1e12 / (HBM_PEAK_GBPS * 1e9)
-        inten = float(fl[dom]) / launches / traffic
+        inten = k_fl / launches / traffic
         hbm = {"achieved_GBps": round(traffic / avg_s / 1e9, 1), "peak_GBps": HBM_PEAK_GBPS,
                "frac": round(traffic / avg_s / 1e9 / HBM_PEAK_GBPS, 4),
                "intensity_flop_per_byte": round(inten, 2), "ridge_flop_per_byte": round(ridge, 2),
@@ -349,13 +371,14 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic, "hbm": hbm,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": f"{PHASES[dom]}: {KERNELS[PHASES[dom]]}",
+                "kernel": label,
                 "launches": launches,
-                "avg_launch_ms": round(float(ms[dom]) / launches, 4) if launches else None,
-                "flops_per_launch": float(fl[dom]) / launches if launches else None,
+                "avg_launch_ms": round(k_ms / launches, 4) if launches else None,
+                "flops_per_launch": k_fl / launches if launches else None,
                 "phase_ms": {p: round(float(v), 3) for p, v in zip(PHASES, ms)},
                 "phase_tflops": {p: round(float(f / (m * 1e-3) / 1e12), 3) if m > 0 else None
-                                 for p, f, m in zip(PHASES, fl, ms)}}
+                                 for p, f, m in zip(PHASES, fl, ms)},
+                "schur_kernels": schur}
     out = {
         "metric": "factor+solve s and RHS*N/s, mixed vs FP64 plain, 1e-8 rel. residual",
         "value": nrhs * n / sec,

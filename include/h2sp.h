@@ -282,7 +282,9 @@ void h2_factor_destroy(h2_factor* f);
 
 /* Device time (ms) of the last sparsify / factor call's kernels, by phase:
  * [0] QR, [1] close transforms, [2] couplings, [3] strips, [4] factor pivots,
- * [5] factor Schur updates, [6] total.  Measured with HIP events. */
+ * [5] factor Schur updates, [6] sparsify total, [7] factor total, [8] and [9]
+ * the Schur updates split by kernel: tiles of more than 4 x 4 blocks of 16
+ * (FP32 only) and the others.  Measured with HIP events; count up to 10. */
 int h2_last_timings(double* ms, int count);
 /* Algorithmic work of the last sparsify / factor call on this thread, same
  * phase order as h2_last_timings: flop counts of the GEMMs and QRs as planned
@@ -291,7 +293,9 @@ int h2_last_timings(double* ms, int count);
  * into parts (long K; the environment variable H2SP_SCHUR_SPLIT_K sets the
  * smallest K of a part, default 512), [8] = Schur kernel launches of the
  * factorisation, [9] = stored S entries the factorisation worked on (after
- * the fill in exact mode).  Entries past [9] are zero; count may be up to 16. */
+ * the fill in exact mode), [10] / [11] flops and launches of the Schur kernel
+ * for tiles of more than 4 x 4 blocks, [12] / [13] the same for the other
+ * Schur kernel.  Entries past [13] are zero; count may be up to 16. */
 int h2_last_work(double* work, int count);
 
 /* Environment variables read by the library (tuning and diagnostics only; the

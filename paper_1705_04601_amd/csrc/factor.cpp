@@ -49,18 +49,19 @@ struct FactorLevel {
   std::vector<CopySeg> cps;
   std::vector<SchurItem> sitems;
   PodVector<SchurSeg> ssegs;
-  std::vector<int32_t> stiles;
+  std::vector<int32_t> stiles, stiles_big;  // tiles of at most 4 x 4 blocks / larger (own launch)
   std::vector<SchurReduce> reds;
   const InvItem<T>* d_inv = nullptr;
   const CopySeg* d_cps = nullptr;
   const SchurItem* d_sitems = nullptr;
   const SchurSeg* d_ssegs = nullptr;
   const int32_t* d_stiles = nullptr;
+  const int32_t* d_stiles_big = nullptr;
   const SchurReduce* d_reds = nullptr;
   GemmBatch zb;
   i64 zlen = 0;  // extent of the level's Z_ki blocks in the Z buffer
-  int32_t nschur_tiles = 0;
-  double schur_flops = 0;
+  int32_t nschur_tiles = 0, nbig = 0, nsmall = 0;  // Schur tiles: all / big kernel / other kernel
+  double schur_flops = 0, big_flops = 0;  // all Schur tiles / tiles of the big kernel
   double xcd_imbalance = 1;  // largest over mean work of the XCDs' tile ranges (traced)
   double col_share = 1, piv_share = 1;  // targets per distinct column, pivots per distinct pivot row (traced)
   double once_bytes = 0, stream_bytes = 0;  // Schur operands read once per level / once per tile (traced)
@@ -143,7 +144,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   // the level fit the partial buffer.
   double shape_fl[4] = {0, 0, 0, 0}, pad_fl = 0, kpad = 0, ksum = 0;  // statistics (H2SP_TRACE)
   double st_pairs = 0, st_segs = 0, st_items = 0, st_rows = 0;
-  constexpr int edge = 64;  // Schur tile edge
+  constexpr int edge = schur_edge<T>;  // Schur tile edge
   double kUnits = 32768;  // H2SP_SCHUR_UNITS overrides
   if (const char* e = std::getenv("H2SP_SCHUR_UNITS")) kUnits = std::max(1.0, std::atof(e));
 
@@ -158,7 +159,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   auto split_targets = [&](const std::vector<SchurItem>& items, FactorLevel<T>& L) {
     const long ni = long(items.size());
     const bool par = ni > 16384;
-    auto tiles_of = [&](const SchurItem& it) { return i64((it.M + 63) / 64) * ((it.N + 63) / 64); };
+    auto tiles_of = [&](const SchurItem& it) { return i64((it.M + edge - 1) / edge) * ((it.N + edge - 1) / edge); };
     double work = 0;
 #pragma omp parallel for reduction(+ : work) schedule(static) num_threads(nthr) if (par)
     for (long t = 0; t < ni; ++t) work += double(items[t].ksum) * double(tiles_of(items[t]));
@@ -188,9 +189,10 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     // range order with item indices and partial offsets shifted
     struct Out {
       std::vector<SchurItem> items;
-      std::vector<int32_t> tiles;
+      std::vector<int32_t> tiles, tiles_big;
       std::vector<SchurReduce> reds;
       i64 pbase = 0, nsplit = 0;
+      double big_flops = 0;
     };
     const int nparts = par ? 4 * nthr : 1;
     std::vector<Out> outs(nparts);
@@ -199,8 +201,15 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       Out& o = outs[p];
       auto emit = [&](const SchurItem& si) {
         const uint32_t item = uint32_t(o.items.size());
+        i64 k = 0;
+        for (int32_t r = si.seg_begin; r < si.seg_end; ++r) k += L.ssegs[r].K;
         for (int a = 0; a < (si.M + edge - 1) / edge; ++a)
-          for (int b = 0; b < (si.N + edge - 1) / edge; ++b) o.tiles.push_back(int32_t((item << 8) | (a << 4) | b));
+          for (int b = 0; b < (si.N + edge - 1) / edge; ++b) {
+            const bool big = schur_big_tile<T>(si.M, si.N, a * edge, b * edge);
+            (big ? o.tiles_big : o.tiles).push_back(int32_t((item << 8) | (a << 4) | b));
+            if (big)
+              o.big_flops += 2.0 * std::min(edge, si.M - a * edge) * std::min(edge, si.N - b * edge) * double(k);
+          }
         o.items.push_back(si);
       };
       for (long t = ni * p / nparts; t < ni * (p + 1) / nparts; ++t) {
@@ -236,14 +245,16 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         }
       }
     }
-    std::vector<size_t> io(nparts + 1, 0), to(nparts + 1, 0), ro(nparts + 1, 0);
+    std::vector<size_t> io(nparts + 1, 0), to(nparts + 1, 0), tb(nparts + 1, 0), ro(nparts + 1, 0);
     std::vector<i64> po(nparts + 1, 0);
     for (int p = 0; p < nparts; ++p) {
       io[p + 1] = io[p] + outs[p].items.size();
       to[p + 1] = to[p] + outs[p].tiles.size();
+      tb[p + 1] = tb[p] + outs[p].tiles_big.size();
       ro[p + 1] = ro[p] + outs[p].reds.size();
       po[p + 1] = po[p] + outs[p].pbase;
       nsplit += outs[p].nsplit;
+      L.big_flops += outs[p].big_flops;
     }
     if (io[nparts] >= (size_t(1) << 24)) {
       too_wide = 1;
@@ -251,6 +262,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     }
     L.sitems.resize(io[nparts]);
     L.stiles.resize(to[nparts]);
+    L.stiles_big.resize(tb[nparts]);
     L.reds.resize(ro[nparts]);
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthr) if (par)
     for (int p = 0; p < nparts; ++p) {
@@ -262,6 +274,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       }
       for (size_t i = 0; i < o.tiles.size(); ++i)
         L.stiles[to[p] + i] = int32_t(uint32_t(o.tiles[i]) + (uint32_t(io[p]) << 8));
+      for (size_t i = 0; i < o.tiles_big.size(); ++i)
+        L.stiles_big[tb[p] + i] = int32_t(uint32_t(o.tiles_big[i]) + (uint32_t(io[p]) << 8));
       for (size_t i = 0; i < o.reds.size(); ++i) {
         SchurReduce r = o.reds[i];
         r.p_off += po[p];
@@ -403,12 +417,14 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     // thread, not the kernel, sets the pace, and the sort would cost more than
     // it saves.  The order changes no result: every tile writes its own
     // output block, and partial sums are added by a later launch.
-    if (L.stiles.size() >= zpos_min && L.stiles.size() < (size_t(1) << 24)) {
-      const i64 n = i64(L.stiles.size()), base = n / 8, rem = n % 8;
+    // Each of the two tile lists (big and other tiles) is ordered this way.
+    auto order_by_z = [&](std::vector<int32_t>& tl) {
+      if (tl.size() < zpos_min || tl.size() >= (size_t(1) << 24)) return;
+      const i64 n = i64(tl.size()), base = n / 8, rem = n % 8;
       std::vector<int64_t> ord(static_cast<size_t>(n));
 #pragma omp parallel for schedule(static) num_threads(nthr) if (n > 65536)
       for (long q = 0; q < long(n); ++q) {
-        const SchurItem& it = L.sitems[uint32_t(L.stiles[q]) >> 8];
+        const SchurItem& it = L.sitems[uint32_t(tl[q]) >> 8];
         ord[q] = (int64_t(L.ssegs[it.seg_begin].a_off) << 24) | int64_t(q);
       }
 #pragma omp parallel for schedule(static) num_threads(std::min(nthr, 8)) if (n > 4096)
@@ -418,22 +434,26 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       }
       std::vector<int32_t> st(static_cast<size_t>(n));
 #pragma omp parallel for schedule(static) num_threads(nthr) if (n > 65536)
-      for (long q = 0; q < long(n); ++q) st[q] = L.stiles[size_t(ord[q] & 0xffffff)];
-      L.stiles.swap(st);
-    }
-    if (trace_level() >= 2 && !L.stiles.empty()) {
-      // the kernel gives XCD x the x-th contiguous eighth of the tile list
-      const i64 n = i64(L.stiles.size()), base = n / 8, rem = n % 8;
+      for (long q = 0; q < long(n); ++q) st[q] = tl[size_t(ord[q] & 0xffffff)];
+      tl.swap(st);
+    };
+    order_by_z(L.stiles);
+    order_by_z(L.stiles_big);
+    if (trace_level() >= 2 && L.stiles.size() + L.stiles_big.size() > 0) {
+      // the kernel gives XCD x the x-th contiguous eighth of each tile list
       double w[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tot = 0;
-      for (int x = 0; x < 8; ++x)
-        for (i64 t = x * base + std::min<i64>(x, rem); t < (x + 1) * base + std::min<i64>(x + 1, rem); ++t) {
-          const uint32_t code = uint32_t(L.stiles[t]);
-          const SchurItem& it = L.sitems[code >> 8];
-          const int m0 = int((code >> 4) & 15) * edge, n0 = int(code & 15) * edge;
-          const double tm = std::min(edge, (it.M - m0 + 15) / 16 * 16), tn = std::min(edge, (it.N - n0 + 15) / 16 * 16);
-          w[x] += tm * tn * it.ksum;
-          tot += tm * tn * it.ksum;
-        }
+      for (const std::vector<int32_t>* tl : {&L.stiles, &L.stiles_big}) {
+        const i64 n = i64(tl->size()), base = n / 8, rem = n % 8;
+        for (int x = 0; x < 8; ++x)
+          for (i64 t = x * base + std::min<i64>(x, rem); t < (x + 1) * base + std::min<i64>(x + 1, rem); ++t) {
+            const uint32_t code = uint32_t((*tl)[t]);
+            const SchurItem& it = L.sitems[code >> 8];
+            const int m0 = int((code >> 4) & 15) * edge, n0 = int(code & 15) * edge;
+            const double tm = std::min(edge, (it.M - m0 + 15) / 16 * 16), tn = std::min(edge, (it.N - n0 + 15) / 16 * 16);
+            w[x] += tm * tn * it.ksum;
+            tot += tm * tn * it.ksum;
+          }
+      }
       L.xcd_imbalance = *std::max_element(w, w + 8) / std::max(1e-30, tot / 8);
     }
     if (trace_level() >= 2) {
@@ -562,6 +582,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
                          reinterpret_cast<const void**>(&L.d_ssegs)});
         blobs.push_back({L.stiles.data(), L.stiles.size() * sizeof(int32_t),
                          reinterpret_cast<const void**>(&L.d_stiles)});
+        blobs.push_back({L.stiles_big.data(), L.stiles_big.size() * sizeof(int32_t),
+                         reinterpret_cast<const void**>(&L.d_stiles_big)});
         blobs.push_back({L.reds.data(), L.reds.size() * sizeof(SchurReduce),
                          reinterpret_cast<const void**>(&L.d_reds)});
       }
@@ -575,9 +597,15 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         launch_zero_pad_rows<T>(L.d_cps, int(L.cps.size()), Z, st);
         L.zb.template launch<T>(st);
         mark_ev();
-        L.nschur_tiles = int32_t(L.stiles.size());
+        L.nschur_tiles = int32_t(L.stiles.size() + L.stiles_big.size());
+        L.nbig = int32_t(L.stiles_big.size());
+        L.nsmall = int32_t(L.stiles.size());
+        // big tiles first: they are the long ones, the others fill the tail
+        SchurLaunch sb{L.d_sitems, L.d_ssegs, L.d_stiles_big, int32_t(L.stiles_big.size()), S, Z, Pbuf};
+        launch_schur<T>(sb, true, st);
+        mark_ev();
         SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf};
-        launch_schur<T>(sl, st);
+        launch_schur<T>(sl, false, st);
         mark_ev();
         launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
         launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
@@ -586,6 +614,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         std::vector<SchurItem>().swap(L.sitems);
         PodVector<SchurSeg>().swap(L.ssegs);
         std::vector<int32_t>().swap(L.stiles);
+        std::vector<int32_t>().swap(L.stiles_big);
         std::vector<SchurReduce>().swap(L.reds);
       }
       next = end;
@@ -598,12 +627,17 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   producer.join();
   HIPCHECK(hipStreamDestroy(cstream));
   if (perr) std::rethrow_exception(perr);
-  if (int(ev.size()) != 3 * f.nflev + 1) fail(H2_EINVAL, "internal: factorisation stopped early");
+  if (int(ev.size()) != 4 * f.nflev + 1) fail(H2_EINVAL, "internal: factorisation stopped early");
   f.flops_inv += fl_inv;
   f.flops_z += fl_z;
   f.flops_schur += fl_s;
   f.split_targets += nsplit;
-  for (const auto& L : lvls) f.schur_launches += L.nschur_tiles > 0 ? 1 : 0;
+  for (const auto& L : lvls) {
+    f.schur_launches += L.nschur_tiles > 0 ? 1 : 0;
+    f.launches_big += L.nbig > 0 ? 1 : 0;
+    f.launches_small += L.nsmall > 0 ? 1 : 0;
+    f.flops_schur_big += L.big_flops;
+  }
   tt.lap("plan+upload+enqueue");
   if (trace_enabled()) {
     const double tot = std::max(1.0, shape_fl[0] + shape_fl[1] + shape_fl[2] + shape_fl[3]);
@@ -622,14 +656,18 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   mark_ev();
   HIPCHECK(hipEventSynchronize(ev.back()));
   tt.lap("device-drain");
-  double piv_ms = 0, schur_ms = 0;
+  double piv_ms = 0, schur_ms = 0, big_ms = 0, small_ms = 0;
   for (int lv = 0; lv < f.nflev; ++lv) {
-    float a = 0, b = 0, c = 0;
-    HIPCHECK(hipEventElapsedTime(&a, ev[3 * lv], ev[3 * lv + 1]));
-    HIPCHECK(hipEventElapsedTime(&b, ev[3 * lv + 1], ev[3 * lv + 2]));
-    HIPCHECK(hipEventElapsedTime(&c, ev[3 * lv + 2], ev[3 * lv + 3]));
+    float a = 0, b1 = 0, b2 = 0, c = 0;
+    HIPCHECK(hipEventElapsedTime(&a, ev[4 * lv], ev[4 * lv + 1]));
+    HIPCHECK(hipEventElapsedTime(&b1, ev[4 * lv + 1], ev[4 * lv + 2]));
+    HIPCHECK(hipEventElapsedTime(&b2, ev[4 * lv + 2], ev[4 * lv + 3]));
+    HIPCHECK(hipEventElapsedTime(&c, ev[4 * lv + 3], ev[4 * lv + 4]));
+    const float b = b1 + b2;
     piv_ms += a + c;
     schur_ms += b;
+    big_ms += b1;
+    small_ms += b2;
     if (trace_level() >= 2)
       std::fprintf(stderr,
                    "[h2sp] factor level %d: %zu rows, %d Schur tiles, %.4g GFLOP, %.3f ms (%.1f TF), XCD imbalance %.3f, "
@@ -649,6 +687,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     phase_ms[4] = piv_ms;
     phase_ms[5] = schur_ms;
     phase_ms[6] = tot;
+    phase_ms[7] = big_ms;
+    phase_ms[8] = small_ms;
   }
 }
 

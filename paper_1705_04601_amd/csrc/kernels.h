@@ -73,12 +73,17 @@ void gemm_tile(int role, int amode, int bmode, int* mb, int* nb);
 // Compact work list of the Schur update S_ij -= Z_ki^T S_kj (offsets in
 // elements into S and into the buffer of Z_ki blocks; every operand has leading
 // dimension equal to its row count).  Tiles: (item << 8) | (tile_row << 4) |
-// tile_col, 64 x 64 tiles.
+// tile_col, schur_edge<T> x schur_edge<T> tiles: 128 in FP32, so that a target
+// of up to 128 x 128 (every pivot block and S block of the library: clusters
+// have at most 128 rows) is one tile whose operands cross the memory system
+// once per chunk, and 64 in FP64, whose accumulators take twice the registers.
 // A target with a long K is split into parts: part 0 subtracts its sum from S
 // directly, every further part stores its sum (M x N, ld M) in the partial
 // buffer and a reduction item subtracts those sums, in a fixed order.
 // The kernel reads every operand through a buffer resource of the block's own
 // size, so it reads nothing outside the blocks the descriptors name.
+template <class T>
+constexpr int schur_edge = sizeof(T) == 4 ? 128 : 64;
 struct SchurItem {
   int64_t out_off;   // into S (partial == 0) or the partial buffer (partial == 1)
   int32_t M, N, seg_begin, seg_end;
@@ -101,8 +106,15 @@ struct SchurLaunch {
   const void* Z;
   void* P;               // partial buffer
 };
+// A tile is big when it has more than 4 blocks of 16 along either side (FP32
+// only); big and other tiles go to separate launches (two kernels, each with
+// the register budget of its own tile shapes).
 template <class T>
-void launch_schur(const SchurLaunch& g, hipStream_t st);
+constexpr bool schur_big_tile(int M, int N, int m0, int n0) {
+  return schur_edge<T> > 64 && (M - m0 > 64 || N - n0 > 64);
+}
+template <class T>
+void launch_schur(const SchurLaunch& g, bool big, hipStream_t st);
 template <class T>
 void launch_schur_reduce(const SchurReduce* items, int count, const T* P, T* S, hipStream_t st);
 

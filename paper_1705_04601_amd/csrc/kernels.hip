@@ -99,8 +99,6 @@ __device__ __forceinline__ void load4(const T* p, int k, int K, bool ok, T* v) {
   }
 }
 
-constexpr int KT = 64;  // tile edge of the Schur kernel
-
 // Work-groups are handed to the 8 XCDs round-robin by block index, and each
 // XCD has its own L2.  Tile lists put tiles that share operands next to each
 // other; this mapping gives XCD x the x-th contiguous eighth of the list, so
@@ -488,26 +486,53 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
       }
 }
 
-// three register sets in FP32 (the occupancy of two waves per SIMD is set by
-// the accumulators either way), two in FP64
-template <class T>
+// Depth of the register ring.  Tiles of at most 4 x 4 blocks run in their own
+// kernel at two waves per SIMD: three sets in FP32, two in FP64.  Larger FP32
+// tiles (up to a whole 128 x 128 target, 8 x 8 blocks) run in a second kernel
+// at one wave per SIMD, the accumulators (at most 256) in AGPRs and the
+// operand sets in VGPRs: as many sets (2 to 4) as fit in about 176 of them,
+// so that the smaller tiles of that kernel keep more chunks in flight.
+template <class T, int NBM, int NBN, bool BIG>
+constexpr int schur_stages() {
+  if (!BIG) return sizeof(T) == 4 ? 3 : 2;
+  constexpr int n = 176 / (4 * (NBM + NBN));
+  return n < 2 ? 2 : (n > 4 ? 4 : n);
+}
+
+// BIG = false: tiles of at most 4 x 4 blocks; BIG = true: the others (FP32).
+template <class T, bool BIG>
 __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
-  constexpr int NS = sizeof(T) == 4 ? 3 : 2;
+  constexpr int E = schur_edge<T>;
   const int lane = threadIdx.x;
   const uint32_t code = static_cast<uint32_t>(g.tiles[xcd_tile(blockIdx.x, gridDim.x)]);
   const SchurItem it = g.items[code >> 8];
-  const int m0 = int((code >> 4) & 15) * KT, n0 = int(code & 15) * KT;
-  const int nbm = min(4, (it.M - m0 + 15) / 16), nbn = min(4, (it.N - n0 + 15) / 16);
-  switch (nbm * 4 + nbn) {
+  const int m0 = int((code >> 4) & 15) * E, n0 = int(code & 15) * E;
+  constexpr int B = E / 16;
+  const int nbm = min(B, (it.M - m0 + 15) / 16), nbn = min(B, (it.N - n0 + 15) / 16);
 #define H2_SCHUR_CASE(I, J) \
-  case I * 4 + J: schur_tile<T, I, J, NS>(g, it, m0, n0, lane); break;
-    H2_SCHUR_CASE(1, 1) H2_SCHUR_CASE(1, 2) H2_SCHUR_CASE(1, 3) H2_SCHUR_CASE(1, 4)
-    H2_SCHUR_CASE(2, 1) H2_SCHUR_CASE(2, 2) H2_SCHUR_CASE(2, 3) H2_SCHUR_CASE(2, 4)
-    H2_SCHUR_CASE(3, 1) H2_SCHUR_CASE(3, 2) H2_SCHUR_CASE(3, 3) H2_SCHUR_CASE(3, 4)
-    H2_SCHUR_CASE(4, 1) H2_SCHUR_CASE(4, 2) H2_SCHUR_CASE(4, 3) H2_SCHUR_CASE(4, 4)
-#undef H2_SCHUR_CASE
-    default: break;
+  case I * 8 + J: schur_tile<T, I, J, schur_stages<T, I, J, BIG>()>(g, it, m0, n0, lane); break;
+  if constexpr (!BIG) {
+    switch (nbm * 8 + nbn) {
+#define H2_SCHUR_ROW(I) H2_SCHUR_CASE(I, 1) H2_SCHUR_CASE(I, 2) H2_SCHUR_CASE(I, 3) H2_SCHUR_CASE(I, 4)
+      H2_SCHUR_ROW(1) H2_SCHUR_ROW(2) H2_SCHUR_ROW(3) H2_SCHUR_ROW(4)
+#undef H2_SCHUR_ROW
+      default: break;
+    }
+  } else if constexpr (B == 8) {
+    switch (nbm * 8 + nbn) {
+#define H2_SCHUR_ROW(I) \
+  H2_SCHUR_CASE(I, 1) H2_SCHUR_CASE(I, 2) H2_SCHUR_CASE(I, 3) H2_SCHUR_CASE(I, 4) \
+  H2_SCHUR_CASE(I, 5) H2_SCHUR_CASE(I, 6) H2_SCHUR_CASE(I, 7) H2_SCHUR_CASE(I, 8)
+      H2_SCHUR_ROW(5) H2_SCHUR_ROW(6) H2_SCHUR_ROW(7) H2_SCHUR_ROW(8)
+#undef H2_SCHUR_ROW
+      H2_SCHUR_CASE(1, 5) H2_SCHUR_CASE(1, 6) H2_SCHUR_CASE(1, 7) H2_SCHUR_CASE(1, 8)
+      H2_SCHUR_CASE(2, 5) H2_SCHUR_CASE(2, 6) H2_SCHUR_CASE(2, 7) H2_SCHUR_CASE(2, 8)
+      H2_SCHUR_CASE(3, 5) H2_SCHUR_CASE(3, 6) H2_SCHUR_CASE(3, 7) H2_SCHUR_CASE(3, 8)
+      H2_SCHUR_CASE(4, 5) H2_SCHUR_CASE(4, 6) H2_SCHUR_CASE(4, 7) H2_SCHUR_CASE(4, 8)
+      default: break;
+    }
   }
+#undef H2_SCHUR_CASE
 }
 
 // S[target] -= sum of the target's partial sums, in part order.
@@ -904,12 +929,18 @@ template void launch_gemm<double>(const GemmLaunch&, hipStream_t);
 template void launch_gemm<float>(const GemmLaunch&, hipStream_t);
 
 template <class T>
-void launch_schur(const SchurLaunch& g, hipStream_t st) {
+void launch_schur(const SchurLaunch& g, bool big, hipStream_t st) {
   if (g.ntiles <= 0) return;
-  hipLaunchKernelGGL(schur_kernel<T>, dim3(g.ntiles), dim3(64), 0, st, g);
+  if constexpr (sizeof(T) == 4) {
+    if (big) {
+      hipLaunchKernelGGL((schur_kernel<T, true>), dim3(g.ntiles), dim3(64), 0, st, g);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((schur_kernel<T, false>), dim3(g.ntiles), dim3(64), 0, st, g);
 }
-template void launch_schur<double>(const SchurLaunch&, hipStream_t);
-template void launch_schur<float>(const SchurLaunch&, hipStream_t);
+template void launch_schur<double>(const SchurLaunch&, bool, hipStream_t);
+template void launch_schur<float>(const SchurLaunch&, bool, hipStream_t);
 
 template <class T>
 void launch_schur_reduce(const SchurReduce* items, int count, const T* P, T* S, hipStream_t st) {

@@ -1,12 +1,13 @@
 """Summaries of rocprofv3 output for the profiles kept with the sources.
 
   python -m paper_1705_04601_amd.profsum stats <out_dir> <prefix>
-      per-kernel totals from <prefix>_kernel_stats.csv and, for the Schur
+      per-kernel totals from <prefix>_kernel_stats.csv and, for each Schur
       kernel, the per-launch average from <prefix>_kernel_trace.csv
-  python -m paper_1705_04601_amd.profsum traffic <fetch_dir> <fetch_prefix> <write_dir> <write_prefix> <copy_mib>
-      HBM bytes per Schur launch from a FETCH_SIZE run and a WRITE_SIZE run
-      (KiB per dispatch), each scaled by what the counter reads for the plain
-      copy of <copy_mib> MiB that bench.py --copy-probe-mib runs first
+  python -m paper_1705_04601_amd.profsum traffic <fetch_dir> <fetch_prefix> <write_dir> <write_prefix> <copy_mib> [kernel]
+      HBM bytes per launch of one kernel (default the big-tile Schur kernel)
+      from a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch), each
+      scaled by what the counter reads for the plain copy of <copy_mib> MiB
+      that bench.py --copy-probe-mib runs first
 
 Reads CSV files only; prints text.
 """
@@ -18,7 +19,8 @@ import hashlib
 import os
 import sys
 
-SCHUR = "schur_kernel<float>"
+SCHUR = "schur_kernel<float, true>"  # the big-tile Schur kernel
+SCHUR_ANY = "schur_kernel<"
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SOURCES = [os.path.join(ROOT, "paper_1705_04601_amd", "csrc", f) for f in ("kernels.hip", "factor.cpp")]
 
@@ -39,10 +41,13 @@ def stats(out_dir: str, prefix: str) -> None:
               f"{float(r['AverageNs']) / 1e3:10.1f} {100 * t / total:6.1f}")
     trace = os.path.join(out_dir, f"{prefix}_kernel_trace.csv")
     if os.path.exists(trace):
-        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-             for r in csv.DictReader(open(trace)) if SCHUR in r["Kernel_Name"]]
-        if d:
-            print(f"\n{SCHUR}: {len(d)} launches, {sum(d) / 1e6:.1f} ms, average {sum(d) / len(d) / 1e6:.4f} ms")
+        per = {}
+        for r in csv.DictReader(open(trace)):
+            if SCHUR_ANY in r["Kernel_Name"]:
+                per.setdefault(_short(r["Kernel_Name"]), []).append(
+                    int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        for name, d in sorted(per.items()):
+            print(f"\n{name}: {len(d)} launches, {sum(d) / 1e6:.1f} ms, average {sum(d) / len(d) / 1e6:.4f} ms")
 
 
 def _counter(out_dir: str, prefix: str, counter: str):
@@ -56,25 +61,26 @@ def _counter(out_dir: str, prefix: str, counter: str):
     return per
 
 
-def traffic(fdir, fprefix, wdir, wprefix, copy_mib) -> None:
+def traffic(fdir, fprefix, wdir, wprefix, copy_mib, kernel=SCHUR) -> None:
     copy_bytes = copy_mib * (1 << 20)
     out = {}
     for what, d, p, counter in (("fetch", fdir, fprefix, "FETCH_SIZE"), ("write", wdir, wprefix, "WRITE_SIZE")):
         per = _counter(d, p, counter)
         copies = [v for n, v in per.values() if "copy" in n.lower() and v * 1024 > 0.5 * copy_bytes]
-        schur = [v for n, v in per.values() if SCHUR in n]
+        schur = [v for n, v in per.values() if kernel in n]
         if not copies or not schur:
-            raise SystemExit(f"{counter}: no copy probe or no Schur dispatch found")
+            raise SystemExit(f"{counter}: no copy probe or no {kernel} dispatch found")
         measured = sorted(copies)[len(copies) // 2] * 1024
         scale = copy_bytes / measured
         per_launch = sum(schur) * 1024 * scale / len(schur)
         out[what] = per_launch
         print(f"{counter}: copy probe reads {measured / 2**20:.1f} MiB for {copy_mib} MiB moved -> scale {scale:.4f}; "
-              f"Schur {len(schur)} launches, {per_launch / 1e9:.3f} GB per launch after scaling")
+              f"{kernel}: {len(schur)} launches, {per_launch / 1e9:.3f} GB per launch after scaling")
     h = hashlib.sha256()
     for f in SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
+    print(f"kernel: {kernel}")
     print(f"fetch_bytes_per_launch: {out['fetch']:.6g}")
     print(f"write_bytes_per_launch: {out['write']:.6g}")
     print(f"hbm_bytes_per_launch: {out['fetch'] + out['write']:.6g}")
@@ -85,7 +91,7 @@ def main(argv):
     if len(argv) >= 3 and argv[0] == "stats":
         stats(argv[1], argv[2])
     elif len(argv) >= 6 and argv[0] == "traffic":
-        traffic(argv[1], argv[2], argv[3], argv[4], int(argv[5]))
+        traffic(argv[1], argv[2], argv[3], argv[4], int(argv[5]), *argv[6:7])
     else:
         raise SystemExit(__doc__)
 

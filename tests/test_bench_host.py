@@ -27,6 +27,8 @@ def test_cpu_baseline_record(name, exact):
 
 
 def test_measured_traffic_is_bytes_or_absent():
-    t = bench.measured_traffic("cube1m")
-    assert t is None or t > 1e9
-    assert bench.measured_traffic("cube256k") is None
+    for name, label, *_ in bench.SCHUR_KERNELS:
+        t = bench.measured_traffic("cube1m", label)
+        assert t is None or t > 1e9
+        assert bench.measured_traffic("cube256k", label) is None
+    assert bench.measured_traffic("cube1m", "no such kernel") is None
