@@ -305,9 +305,12 @@ int h2_last_work(double* work, int count);
  *   H2SP_SCHUR_UNITS (default 32768) and H2SP_SCHUR_SPLIT_K (default 512):
  *     split-K granularity of the Schur update (tile units per level, smallest
  *     K of a part);
- *   H2SP_SCHUR_ORDER: levels of at least 16384 Schur tiles order them by Z
- *     position; =0 keeps target order on every level, =2 orders every level
- *     by Z position (the order changes no result bit);
+ *   H2SP_SCHUR_ORDER: levels of at least 16384 Schur tiles reorder them
+ *     inside each XCD's share; =0 keeps target order on every level, =2
+ *     reorders every level (the order changes no result bit);
+ *   H2SP_SCHUR_KEY: the key of that order, by default the target's row and
+ *     then the place of its column cluster in space; =z the Z position where
+ *     the tile's first segment starts;
  *   H2SP_CLOSE_RESIDENT=0: never keep the matvec's close blocks on the device;
  *   H2SP_GRAPHS=0: run the solve and matvec sweeps eagerly instead of as
  *     captured HIP graphs. */

@@ -47,12 +47,27 @@ def _run(cmd):
     return res
 
 
-def build(verbose: bool = False) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """An object is stale when it is missing or older than its source or any
+    header of the library."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")] + \
+        [os.path.join(HERE, "..", "include", h) for h in os.listdir(os.path.join(HERE, "..", "include"))]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compiles every source (force) or only the stale ones, then links."""
     from concurrent.futures import ThreadPoolExecutor
     os.makedirs(OBJ, exist_ok=True)
     objs, cmds = [], []
     for src, extra in SOURCES.items():
         obj = os.path.join(OBJ, src + ".o")
+        objs.append(obj)
+        if not force and not _stale(obj, os.path.join(CSRC, src)):
+            continue
         if src.endswith(".hip"):
             cmd = [HIPCC] + COMMON + extra
         else:
@@ -61,11 +76,11 @@ def build(verbose: bool = False) -> str:
         if verbose:
             print(" ".join(cmd), flush=True)
         cmds.append(cmd)
-        objs.append(obj)
     # translation units are independent: compile them side by side
     jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
-    with ThreadPoolExecutor(max_workers=jobs) as ex:
-        list(ex.map(_run, cmds))
+    if cmds:
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"
     link = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fopenmp", "-o", tmp] + objs + \
         ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/llvm/lib"]
@@ -77,4 +92,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--changed" not in sys.argv))

@@ -48,6 +48,7 @@ struct FactorLevel {
   std::vector<InvItem<T>> inv;
   std::vector<CopySeg> cps;
   std::vector<SchurItem> sitems;
+  std::vector<int64_t> skeys;  // per item: tile-order key (host only)
   PodVector<SchurSeg> ssegs;
   std::vector<int32_t> stiles, stiles_big;  // tiles of at most 4 x 4 blocks / larger (own launch)
   std::vector<SchurReduce> reds;
@@ -65,12 +66,14 @@ struct FactorLevel {
   double xcd_imbalance = 1;  // largest over mean work of the XCDs' tile ranges (traced)
   double col_share = 1, piv_share = 1;  // targets per distinct column, pivots per distinct pivot row (traced)
   double once_bytes = 0, stream_bytes = 0;  // Schur operands read once per level / once per tile (traced)
+  std::string class_stats[2];               // the same by tile class (traced)
   double union2 = 1, union4 = 1;  // K of the union of the pivot lists of 2 / 4 consecutive targets over their sum (traced)
 };
 
 // Output of one chunk of rows of a level (concatenated in row order).
 struct RowChunk {
   std::vector<SchurItem> items;
+  std::vector<int64_t> keys;  // per item: tile-order key (row, place of the target column in space)
   PodVector<SchurSeg> segs;
   double flops = 0;
   double dense_pairs = 0;  // sum over rows of (pivots above the row) x (targets of the row)
@@ -148,15 +151,23 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   double kUnits = 32768;  // H2SP_SCHUR_UNITS overrides
   if (const char* e = std::getenv("H2SP_SCHUR_UNITS")) kUnits = std::max(1.0, std::atof(e));
 
-  // Levels of at least zpos_min tiles order their Schur tiles by Z position
-  // inside each XCD's share; H2SP_SCHUR_ORDER=0 never does, =2 on every level.
+  // Levels of at least zpos_min tiles reorder their Schur tiles inside each
+  // XCD's share; H2SP_SCHUR_ORDER=0 never does, =2 on every level.  The key
+  // (H2SP_SCHUR_KEY): by default the target's row, then the first tree
+  // position of its column cluster (targets of one row whose clusters are
+  // close in space have close neighbours, so they share pivots); "z" orders
+  // by the Z position where the tile's first segment starts.
   size_t zpos_min = 16384;
   if (const char* e = std::getenv("H2SP_SCHUR_ORDER"))
     zpos_min = e[0] == '0' ? SIZE_MAX : e[0] == '2' ? 1 : zpos_min;
+  bool key_z = false;
+  if (const char* e = std::getenv("H2SP_SCHUR_KEY")) key_z = e[0] == 'z';
+  const std::vector<i64>& tstart = sp.H->tree.start;
   i64 kMinK = 512;  // smallest K of a part; H2SP_SCHUR_SPLIT_K overrides it
   if (const char* e = std::getenv("H2SP_SCHUR_SPLIT_K")) kMinK = std::max<i64>(1, std::atoll(e));
   const i64 pcap = f.pcap;
-  auto split_targets = [&](const std::vector<SchurItem>& items, FactorLevel<T>& L) {
+  auto split_targets = [&](const std::vector<SchurItem>& items, const std::vector<int64_t>& keys,
+                           FactorLevel<T>& L) {
     const long ni = long(items.size());
     const bool par = ni > 16384;
     auto tiles_of = [&](const SchurItem& it) { return i64((it.M + edge - 1) / edge) * ((it.N + edge - 1) / edge); };
@@ -189,6 +200,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     // range order with item indices and partial offsets shifted
     struct Out {
       std::vector<SchurItem> items;
+      std::vector<int64_t> keys;
       std::vector<int32_t> tiles, tiles_big;
       std::vector<SchurReduce> reds;
       i64 pbase = 0, nsplit = 0;
@@ -199,8 +211,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthr) if (par)
     for (int p = 0; p < nparts; ++p) {
       Out& o = outs[p];
-      auto emit = [&](const SchurItem& si) {
+      auto emit = [&](const SchurItem& si, int64_t key) {
         const uint32_t item = uint32_t(o.items.size());
+        o.keys.push_back(key);
         i64 k = 0;
         for (int32_t r = si.seg_begin; r < si.seg_end; ++r) k += L.ssegs[r].K;
         for (int a = 0; a < (si.M + edge - 1) / edge; ++a)
@@ -216,7 +229,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         const SchurItem& it = items[t];
         const i64 np = parts_of(t);
         if (np == 1) {
-          emit(it);
+          emit(it, keys[t]);
           continue;
         }
         const i64 len = i64(it.M) * it.N;
@@ -233,7 +246,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
               si.partial = 1;
               si.out_off = o.pbase + (part - 1) * len;  // shifted by the range's base below
             }
-            emit(si);
+            emit(si, keys[t]);
             begin = r + 1;
             ++part;
           }
@@ -261,6 +274,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       return;
     }
     L.sitems.resize(io[nparts]);
+    L.skeys.resize(io[nparts]);
     L.stiles.resize(to[nparts]);
     L.stiles_big.resize(tb[nparts]);
     L.reds.resize(ro[nparts]);
@@ -271,6 +285,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         SchurItem si = o.items[i];
         if (si.partial) si.out_off += po[p];
         L.sitems[io[p] + i] = si;
+        L.skeys[io[p] + i] = o.keys[i];
       }
       for (size_t i = 0; i < o.tiles.size(); ++i)
         L.stiles[to[p] + i] = int32_t(uint32_t(o.tiles[i]) + (uint32_t(io[p]) << 8));
@@ -366,6 +381,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
             si.ksum = int32_t(k);
             out.flops += 2.0 * mi * mj * double(k);
             out.items.push_back(si);
+            out.keys.push_back((int64_t(q) << 32) | int64_t(tstart[sp.colidx[t0 + t]]));
           }
         }
       }
@@ -391,6 +407,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       so[ch + 1] = so[ch] + chunks[ch].segs.size();
     }
     std::vector<SchurItem> items(nitems);
+    std::vector<int64_t> keys(nitems);
     L.ssegs.resize(nsegs);
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
     for (int ch = 0; ch < nchunk; ++ch) {
@@ -401,44 +418,50 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         si.seg_begin += sb;
         si.seg_end += sb;
         items[io[ch] + i] = si;
+        keys[io[ch] + i] = c.keys[i];
       }
       if (!c.segs.empty()) std::memcpy(&L.ssegs[so[ch]], c.segs.data(), c.segs.size() * sizeof(SchurSeg));
       std::vector<SchurItem>().swap(c.items);
+      std::vector<int64_t>().swap(c.keys);
       PodVector<SchurSeg>().swap(c.segs);
     }
-    split_targets(items, L);
+    split_targets(items, keys, L);
     if (L.sitems.size() >= (size_t(1) << 24)) too_wide = 1;
     // Inside each XCD's share of the tile list (the kernel gives XCD x the
     // x-th contiguous eighth, so the shares keep the work balance of target
-    // order), tiles go in the order of the Z_ki position where their first
-    // segment starts: the tiles that run at the same time on one XCD then walk
-    // the same part of a row's Z strip, which its L2 serves to all of them.
+    // order), tiles are reordered so that the tiles running at the same time
+    // on one XCD read the same Z_ki blocks, which its L2 then serves to all of
+    // them: by default by row and then by the place of the target's column
+    // cluster in space, else by the Z position where the first segment starts.
     // Levels of fewer than 16384 tiles keep target order: there the planning
     // thread, not the kernel, sets the pace, and the sort would cost more than
     // it saves.  The order changes no result: every tile writes its own
     // output block, and partial sums are added by a later launch.
     // Each of the two tile lists (big and other tiles) is ordered this way.
-    auto order_by_z = [&](std::vector<int32_t>& tl) {
+    auto order_tiles = [&](std::vector<int32_t>& tl) {
       if (tl.size() < zpos_min || tl.size() >= (size_t(1) << 24)) return;
       const i64 n = i64(tl.size()), base = n / 8, rem = n % 8;
       std::vector<int64_t> ord(static_cast<size_t>(n));
 #pragma omp parallel for schedule(static) num_threads(nthr) if (n > 65536)
       for (long q = 0; q < long(n); ++q) {
-        const SchurItem& it = L.sitems[uint32_t(tl[q]) >> 8];
-        ord[q] = (int64_t(L.ssegs[it.seg_begin].a_off) << 24) | int64_t(q);
+        const uint32_t item = uint32_t(tl[q]) >> 8;
+        ord[q] = key_z ? (int64_t(L.ssegs[L.sitems[item].seg_begin].a_off) << 24) | int64_t(q)
+                       : L.skeys[item];
       }
+      std::vector<int32_t> idx(static_cast<size_t>(n));
+      for (long q = 0; q < long(n); ++q) idx[q] = int32_t(q);
 #pragma omp parallel for schedule(static) num_threads(std::min(nthr, 8)) if (n > 4096)
       for (int x = 0; x < 8; ++x) {
         const i64 b0 = x * base + std::min<i64>(x, rem), b1 = (x + 1) * base + std::min<i64>(x + 1, rem);
-        std::sort(ord.begin() + b0, ord.begin() + b1);
+        std::stable_sort(idx.begin() + b0, idx.begin() + b1, [&](int32_t a, int32_t b) { return ord[a] < ord[b]; });
       }
       std::vector<int32_t> st(static_cast<size_t>(n));
 #pragma omp parallel for schedule(static) num_threads(nthr) if (n > 65536)
-      for (long q = 0; q < long(n); ++q) st[q] = tl[size_t(ord[q] & 0xffffff)];
+      for (long q = 0; q < long(n); ++q) st[q] = tl[size_t(idx[q])];
       tl.swap(st);
     };
-    order_by_z(L.stiles);
-    order_by_z(L.stiles_big);
+    order_tiles(L.stiles);
+    order_tiles(L.stiles_big);
     if (trace_level() >= 2 && L.stiles.size() + L.stiles_big.size() > 0) {
       // the kernel gives XCD x the x-th contiguous eighth of each tile list
       double w[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tot = 0;
@@ -517,6 +540,42 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         if (!it.partial) once += 2.0 * sizeof(T) * double(it.M) * it.N;
       L.once_bytes = once;
       L.stream_bytes = stream;
+      // the same split by tile class (big: more than 4 x 4 blocks of 16):
+      // targets, flops, Z and S bytes streamed per tile and read once
+      for (int c = 0; c < 2; ++c) {
+        double nt = 0, fl = 0, zs = 0, ss = 0, sm = 0, sn = 0, sk = 0, ns = 0;
+        std::vector<std::pair<i64, i64>> za, sb;
+        for (const SchurItem& it : L.sitems) {
+          if (int(schur_big_tile<T>(it.M, it.N, 0, 0)) != c) continue;
+          ++nt;
+          sm += it.M;
+          sn += it.N;
+          for (int32_t r = it.seg_begin; r < it.seg_end; ++r) {
+            const SchurSeg& sg = L.ssegs[r];
+            fl += 2.0 * it.M * it.N * sg.K;
+            zs += double(sizeof(T)) * double(kpad16(sg.K)) * it.M;
+            ss += double(sizeof(T)) * double(sg.K) * it.N;
+            sk += sg.K;
+            ++ns;
+            za.push_back({sg.a_off, kpad16(sg.K) * it.M});
+            sb.push_back({sg.b_off, i64(sg.K) * it.N});
+          }
+        }
+        double zo = 0, so = 0;
+        sort_range(za.begin(), za.end());
+        sort_range(sb.begin(), sb.end());
+        for (size_t q = 0; q < za.size(); ++q)
+          if (q == 0 || za[q].first != za[q - 1].first) zo += double(sizeof(T)) * double(za[q].second);
+        for (size_t q = 0; q < sb.size(); ++q)
+          if (q == 0 || sb[q].first != sb[q - 1].first) so += double(sizeof(T)) * double(sb[q].second);
+        char buf[320];
+        std::snprintf(buf, sizeof(buf),
+                      "%s: targets %.0f mean M %.1f N %.1f, segments %.0f mean K %.1f, %.4g GFLOP, "
+                      "Z per tile %.3f GB once %.3f GB, S per tile %.3f GB once %.3f GB",
+                      c ? "big" : "small", nt, sm / std::max(1.0, nt), sn / std::max(1.0, nt), ns,
+                      sk / std::max(1.0, ns), fl / 1e9, zs / 1e9, zo / 1e9, ss / 1e9, so / 1e9);
+        L.class_stats[c] = buf;
+      }
     }
   };
   // plans the levels in order, each in parallel
@@ -679,6 +738,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
                    double(lvls[lv].zlen) * sizeof(T) / 1e9, lvls[lv].col_share,
                    lvls[lv].piv_share, lvls[lv].once_bytes / 1e9, lvls[lv].stream_bytes / 1e9, lvls[lv].union2,
                    lvls[lv].union4, a + c);
+    if (trace_level() >= 2)
+      std::fprintf(stderr, "[h2sp] factor level %d small tiles %.3f ms %s; big tiles %.3f ms %s\n", lv, b2,
+                   lvls[lv].class_stats[0].c_str(), b1, lvls[lv].class_stats[1].c_str());
   }
   float tot = 0;
   HIPCHECK(hipEventElapsedTime(&tot, ev.front(), ev.back()));

@@ -402,9 +402,13 @@ __device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const Sc
 
 constexpr uint32_t kOutside = 0x80000000u;  // a buffer offset past every resource used here
 
+// Loads one chunk (the same loads for every chunk, so that the number of
+// loads in flight stays static) and returns the MFMA steps it needs: 4 for a
+// full chunk, 2 or 1 for the last chunk of a segment with 5..8 or 1..4 valid
+// k (see schur_compact), 0 past the item's end.
 template <class T, int NBM, int NBN>
-__device__ __forceinline__ void schur_fetch(const SchurCursor<T, NBM, NBN>& c, int kq, T (&a)[NBM][4],
-                                            T (&b)[NBN][4]) {
+__device__ __forceinline__ int schur_fetch(const SchurCursor<T, NBM, NBN>& c, int kq, T (&a)[NBM][4],
+                                           T (&b)[NBN][4]) {
   const uint32_t sh = uint32_t(c.k0) * uint32_t(sizeof(T));  // k0 < K <= K16: both sizes stay positive
   const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.pa + c.k0, c.valid ? c.na - sh : 0u);
   const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.pb + c.k0, c.valid ? c.nb - sh : 0u);
@@ -413,17 +417,78 @@ __device__ __forceinline__ void schur_fetch(const SchurCursor<T, NBM, NBN>& c, i
   for (int q = 0; q < NBM; ++q) BufLoad4<T>::run(ra, live ? c.oa[q] : kOutside, a[q]);
 #pragma unroll
   for (int q = 0; q < NBN; ++q) BufLoad4<T>::run(rb, live ? c.ob[q] : kOutside, b[q]);
+  const int rem = c.K - c.k0;
+  return !c.valid ? 0 : rem > 8 ? 4 : rem > 4 ? 2 : 1;
+}
+
+// Lane swaps of gfx950 on one operand register (an FP64 value is two).
+// swap32: x's lanes 32..63 trade places with y's lanes 0..31 (lane groups 2,
+// 3 of x receive groups 0, 1 of y); swap16: x's odd groups trade with y's
+// even groups (groups 1, 3 of x receive groups 0, 2 of y).
+template <class T>
+__device__ __forceinline__ void lane_swap32(T& x, T& y) {
+  static_assert(sizeof(T) % 4 == 0, "32-bit words");
+  uint32_t u[sizeof(T) / 4], v[sizeof(T) / 4];
+  __builtin_memcpy(u, &x, sizeof(T));
+  __builtin_memcpy(v, &y, sizeof(T));
+#pragma unroll
+  for (int w = 0; w < int(sizeof(T) / 4); ++w) {
+    const auto r = __builtin_amdgcn_permlane32_swap(u[w], v[w], false, false);
+    u[w] = r[0];
+    v[w] = r[1];
+  }
+  __builtin_memcpy(&x, u, sizeof(T));
+  __builtin_memcpy(&y, v, sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void lane_swap16(T& x, T& y) {
+  uint32_t u[sizeof(T) / 4], v[sizeof(T) / 4];
+  __builtin_memcpy(u, &x, sizeof(T));
+  __builtin_memcpy(v, &y, sizeof(T));
+#pragma unroll
+  for (int w = 0; w < int(sizeof(T) / 4); ++w) {
+    const auto r = __builtin_amdgcn_permlane16_swap(u[w], v[w], false, false);
+    u[w] = r[0];
+    v[w] = r[1];
+  }
+  __builtin_memcpy(&x, u, sizeof(T));
+  __builtin_memcpy(&y, v, sizeof(T));
+}
+
+// The last chunk of a segment holds rem < 16 valid k; lane group g holds
+// k = 4g + s in register s, so only groups g < ceil(rem / 4) hold data (the
+// others read zeros).  With rem <= 8 the data move into fewer registers, the
+// same moves for both operands so that every step still pairs equal k:
+//   rem 5..8: groups 2, 3 of registers 0, 1 receive registers 2, 3 of groups
+//     0, 1; steps 0 and 1 then cover all eight k;
+//   rem 1..4: after that, groups 1, 3 of register 0 receive groups 0, 2 of
+//     register 1; step 0 covers all four k.
+template <class T, int NB>
+__device__ __forceinline__ void schur_compact(T (&x)[NB][4], int nsteps) {
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    lane_swap32(x[q][0], x[q][2]);
+    lane_swap32(x[q][1], x[q][3]);
+    if (nsteps == 1) lane_swap16(x[q][0], x[q][1]);
+  }
 }
 
 template <class T, int NBM, int NBN>
-__device__ __forceinline__ void schur_mfma(typename Mfma<T>::V (&acc)[NBM][NBN], const T (&a)[NBM][4],
-                                           const T (&b)[NBN][4]) {
+__device__ __forceinline__ void schur_mfma(typename Mfma<T>::V (&acc)[NBM][NBN], T (&a)[NBM][4], T (&b)[NBN][4],
+                                           int nsteps) {
+  if (nsteps == 0) return;
+  if (nsteps < 4) {
+    schur_compact<T, NBM>(a, nsteps);
+    schur_compact<T, NBN>(b, nsteps);
+  }
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int s = 0; s < 4; ++s) {
+    if (s >= nsteps) break;
 #pragma unroll
     for (int bm = 0; bm < NBM; ++bm)
 #pragma unroll
       for (int bn = 0; bn < NBN; ++bn) acc[bm][bn] = Mfma<T>::run(b[bn][s], a[bm][s], acc[bm][bn]);
+  }
 }
 
 template <class T, int NBM, int NBN, int NS>
@@ -446,27 +511,28 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
     schur_load_desc(c, g.segs, lane);
     schur_setup(c, S, Z, m0, n0, it.M, it.N, r, kq);
     T a[NS][NBM][4], b[NS][NBN][4];
-    schur_fetch(c, kq, a[0], b[0]);
+    int steps[NS];
+    steps[0] = schur_fetch(c, kq, a[0], b[0]);
 #pragma unroll
     for (int i = 1; i < NS - 1; ++i) {
       schur_next(c, g.segs, S, Z, m0, n0, it.M, it.N, r, kq, lane);
-      schur_fetch(c, kq, a[i], b[i]);
+      steps[i] = schur_fetch(c, kq, a[i], b[i]);
     }
-    // one exit per NS chunks; chunks past the end read zeros
+    // one exit per NS chunks; chunks past the end read zeros and take no step
     while (true) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
         schur_next(c, g.segs, S, Z, m0, n0, it.M, it.N, r, kq, lane);
-        schur_fetch(c, kq, a[(i + NS - 1) % NS], b[(i + NS - 1) % NS]);
+        steps[(i + NS - 1) % NS] = schur_fetch(c, kq, a[(i + NS - 1) % NS], b[(i + NS - 1) % NS]);
         __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
-        schur_mfma<T, NBM, NBN>(acc, a[i], b[i]);
+        schur_mfma<T, NBM, NBN>(acc, a[i], b[i], steps[i]);
         __builtin_amdgcn_sched_barrier(0);
       }
       if (!c.valid) break;
     }
     // sets 0 .. NS - 2 hold chunks fetched but not yet multiplied
 #pragma unroll
-    for (int i = 0; i < NS - 1; ++i) schur_mfma<T, NBM, NBN>(acc, a[i], b[i]);
+    for (int i = 0; i < NS - 1; ++i) schur_mfma<T, NBM, NBN>(acc, a[i], b[i], steps[i]);
   }
   const bool part = it.partial != 0;
   T* out = (part ? static_cast<T*>(g.P) : S) + it.out_off;
