@@ -35,12 +35,13 @@ KERNELS = {"qr": "qr_kernel", "close": "gemm_kc_kernel<float, 0, ...>", "couplin
            "strips": "gemm_kc_kernel<float, 0, ...>",
            "factor_pivots_z": "inverse_kernel<float> + gemm_kc_kernel<float, 1, ...> + copy_segments_kernel<float>"
                               " + schur_reduce_kernel<float>",
-           "factor_schur": "schur_kernel<float, true> + schur_kernel<float, false>"}
-# the two Schur kernels: tiles of more than 4 x 4 blocks of 16 (whole targets
-# up to 128 x 128) and the others; h2_last_timings [8] / [9] and
-# h2_last_work [10..13] report them apart
-SCHUR_KERNELS = [("schur_big", "schur_kernel<float, true>", 8, 10, 11),
-                 ("schur_small", "schur_kernel<float, false>", 9, 12, 13)]
+           "factor_schur": "schur_kernel<float, 0> + schur_kernel<float, 1> + schur_kernel<float, 2>"}
+# the Schur kernels by tile class: at most 4 blocks of 16 along both sides, 5
+# along the longer side (the whole leaf targets), 6 to 8 (up to whole 128 x 128
+# targets); h2_last_timings [8..10] and h2_last_work [10..15] report them apart
+SCHUR_KERNELS = [("schur_cls0", "schur_kernel<float, 0>", 8, 10, 11),
+                 ("schur_cls1", "schur_kernel<float, 1>", 9, 12, 13),
+                 ("schur_cls2", "schur_kernel<float, 2>", 10, 14, 15)]
 # HBM traffic of the Schur kernel measured with rocprofv3 counters; used only
 # while the kernel and its planner are the sources the counters were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_kernel_cube1m_traffic.txt")

@@ -282,9 +282,10 @@ void h2_factor_destroy(h2_factor* f);
 
 /* Device time (ms) of the last sparsify / factor call's kernels, by phase:
  * [0] QR, [1] close transforms, [2] couplings, [3] strips, [4] factor pivots,
- * [5] factor Schur updates, [6] sparsify total, [7] factor total, [8] and [9]
- * the Schur updates split by kernel: tiles of more than 4 x 4 blocks of 16
- * (FP32 only) and the others.  Measured with HIP events; count up to 10. */
+ * [5] factor Schur updates, [6] sparsify total, [7] factor total, [8], [9],
+ * [10] the Schur updates split by kernel (tile class): tiles with at most 4
+ * blocks of 16 along both sides, with 5 along the longer side, with 6 to 8
+ * (FP32 only).  Measured with HIP events; count up to 12. */
 int h2_last_timings(double* ms, int count);
 /* Algorithmic work of the last sparsify / factor call on this thread, same
  * phase order as h2_last_timings: flop counts of the GEMMs and QRs as planned
@@ -293,9 +294,9 @@ int h2_last_timings(double* ms, int count);
  * into parts (long K; the environment variable H2SP_SCHUR_SPLIT_K sets the
  * smallest K of a part, default 512), [8] = Schur kernel launches of the
  * factorisation, [9] = stored S entries the factorisation worked on (after
- * the fill in exact mode), [10] / [11] flops and launches of the Schur kernel
- * for tiles of more than 4 x 4 blocks, [12] / [13] the same for the other
- * Schur kernel.  Entries past [13] are zero; count may be up to 16. */
+ * the fill in exact mode), [10] / [11], [12] / [13], [14] / [15] flops and
+ * launches of the Schur kernels of tile classes 0, 1, 2 (as in
+ * h2_last_timings [8..10]).  count may be up to 16. */
 int h2_last_work(double* work, int count);
 
 /* Environment variables read by the library (tuning and diagnostics only; the
@@ -311,6 +312,9 @@ int h2_last_work(double* work, int count);
  *   H2SP_SCHUR_KEY: the key of that order, by default the target's row and
  *     then the place of its column cluster in space; =z the Z position where
  *     the tile's first segment starts;
+ *   H2SP_SCHUR_TILED=0: the Schur update reads the S_kj operands in place
+ *     instead of from copies in 16 x 16 tiles (the copies take about 1.3 times
+ *     the memory of S and are made only when they fit);
  *   H2SP_CLOSE_RESIDENT=0: never keep the matvec's close blocks on the device;
  *   H2SP_GRAPHS=0: run the solve and matvec sweeps eagerly instead of as
  *     captured HIP graphs. */

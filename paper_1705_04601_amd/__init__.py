@@ -380,8 +380,8 @@ def h2_apply_inverse(f: H2FactorHandle, b, x):
 
 
 def h2_last_timings():
-    out = np.zeros(10)
-    _check(lib().h2_last_timings(_dptr(out), 10))
+    out = np.zeros(12)
+    _check(lib().h2_last_timings(_dptr(out), 12))
     return out
 
 

@@ -19,7 +19,7 @@ std::string& last_error() {
   static thread_local std::string msg;
   return msg;
 }
-static thread_local double g_timings[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+static thread_local double g_timings[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 static thread_local double g_work[16] = {0};
 }  // namespace h2
 
@@ -132,7 +132,7 @@ extern "C" int h2_sparsify(h2_matrix* h, const h2_sparsify_opts* opts, h2_sparse
   const int prec = opts ? opts->precision : H2_FP64;
   if (prec != H2_FP64 && prec != H2_MIXED) fail(H2_EINVAL, "unknown precision");
   std::unique_ptr<h2_sparse> sp(plan_sparsify(h, prec, true));
-  std::fill(g_timings, g_timings + 10, 0.0);
+  std::fill(g_timings, g_timings + 12, 0.0);
   std::fill(g_work, g_work + 16, 0.0);
   run_sparsify(*sp, current_stream(), g_timings);
   HIPCHECK(hipStreamSynchronize(current_stream()));
@@ -208,23 +208,22 @@ extern "C" int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor*
   const int mode = opts ? opts->mode : H2_FACTOR_ILU0;
   if (mode != H2_FACTOR_EXACT && mode != H2_FACTOR_ILU0) fail(H2_EINVAL, "unknown factorisation mode");
   if (sp->factored) fail(H2_EINVAL, "S of this sparse handle is already factored");
-  for (int i = 4; i < 10; ++i) g_timings[i] = 0;
+  for (int i = 4; i < 12; ++i) g_timings[i] = 0;
   double ph[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::unique_ptr<h2_factor> f(factor(sp, mode == H2_FACTOR_EXACT, current_stream(), ph));
   g_timings[4] = ph[4];
   g_timings[5] = ph[5];
   g_timings[7] = ph[6];
-  g_timings[8] = ph[7];
-  g_timings[9] = ph[8];
+  for (int c = 0; c < 3; ++c) g_timings[8 + c] = ph[7 + c];
   g_work[4] = f->flops_inv + f->flops_z;
   g_work[5] = f->flops_schur;
   g_work[7] = double(f->split_targets);
   g_work[8] = double(f->schur_launches);
   g_work[9] = double(sp->s_entries);
-  g_work[10] = f->flops_schur_big;
-  g_work[11] = double(f->launches_big);
-  g_work[12] = f->flops_schur - f->flops_schur_big;
-  g_work[13] = double(f->launches_small);
+  for (int c = 0; c < 3; ++c) {
+    g_work[10 + 2 * c] = f->flops_cls[c];
+    g_work[11 + 2 * c] = double(f->launches_cls[c]);
+  }
   *out = f.release();
   H2_API_END
 }
@@ -261,7 +260,7 @@ extern "C" int h2_sparsify_batch(h2_matrix* const* hs, int count, const h2_spars
   // the instances are planned concurrently (host work); their sweeps are merged below
   run_pooled(count, [&](int i) { own[i].reset(plan_sparsify(hs[i], prec, false)); });
   for (int i = 0; i < count; ++i) sps[i] = own[i].get();
-  std::fill(g_timings, g_timings + 10, 0.0);
+  std::fill(g_timings, g_timings + 12, 0.0);
   std::fill(g_work, g_work + 16, 0.0);
   run_sparsify_batch(sps, current_stream(), g_timings);
   HIPCHECK(hipStreamSynchronize(current_stream()));
@@ -289,22 +288,21 @@ extern "C" int h2_factor_S_batch(h2_sparse* const* sps, int count, const h2_fact
   run_pooled(count, [&](int i) {
     fs[i].reset(factor(sps[i], mode == H2_FACTOR_EXACT, current_stream(), &ph[size_t(i) * 10]));
   });
-  std::fill(g_timings + 4, g_timings + 10, 0.0);
+  std::fill(g_timings + 4, g_timings + 12, 0.0);
   std::fill(g_work + 4, g_work + 16, 0.0);
   for (int i = 0; i < count; ++i) {
     g_timings[4] += ph[size_t(i) * 10 + 4];
     g_timings[5] += ph[size_t(i) * 10 + 5];
-    g_timings[8] += ph[size_t(i) * 10 + 7];
-    g_timings[9] += ph[size_t(i) * 10 + 8];
+    for (int c = 0; c < 3; ++c) g_timings[8 + c] += ph[size_t(i) * 10 + 7 + c];
     g_work[4] += fs[i]->flops_inv + fs[i]->flops_z;
     g_work[5] += fs[i]->flops_schur;
     g_work[7] += double(fs[i]->split_targets);
     g_work[8] += double(fs[i]->schur_launches);
     g_work[9] += double(sps[i]->s_entries);
-    g_work[10] += fs[i]->flops_schur_big;
-    g_work[11] += double(fs[i]->launches_big);
-    g_work[12] += fs[i]->flops_schur - fs[i]->flops_schur_big;
-    g_work[13] += double(fs[i]->launches_small);
+    for (int c = 0; c < 3; ++c) {
+      g_work[10 + 2 * c] += fs[i]->flops_cls[c];
+      g_work[11 + 2 * c] += double(fs[i]->launches_cls[c]);
+    }
   }
   for (int i = 0; i < count; ++i) outs[i] = fs[i].release();
   H2_API_END
@@ -366,7 +364,7 @@ extern "C" int h2_last_timings(double* ms, int count) {
   H2_API_BEGIN
   if (!ms) fail(H2_EINVAL, "null argument");
   // [6] reports the sparsify total, [7] (internal) the factor total
-  for (int i = 0; i < count && i < 10; ++i) ms[i] = g_timings[i];
+  for (int i = 0; i < count && i < 12; ++i) ms[i] = g_timings[i];
   H2_API_END
 }
 

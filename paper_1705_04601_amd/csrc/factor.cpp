@@ -46,27 +46,29 @@ namespace {
 template <class T>
 struct FactorLevel {
   std::vector<InvItem<T>> inv;
-  std::vector<CopySeg> cps;
+  std::vector<CopySeg> cps;                 // Z_ki into the place of S_ki (end of the level)
+  std::vector<CopySeg> zts, sts;            // Z_ki into tiles; the level's rows' blocks into tiles
   std::vector<SchurItem> sitems;
   std::vector<int64_t> skeys;  // per item: tile-order key (host only)
   PodVector<SchurSeg> ssegs;
-  std::vector<int32_t> stiles, stiles_big;  // tiles of at most 4 x 4 blocks / larger (own launch)
+  std::vector<int32_t> stiles[kSchurClasses];  // Schur tiles by class (a launch each)
   std::vector<SchurReduce> reds;
   const InvItem<T>* d_inv = nullptr;
   const CopySeg* d_cps = nullptr;
+  const CopySeg* d_zts = nullptr;
+  const CopySeg* d_sts = nullptr;
   const SchurItem* d_sitems = nullptr;
   const SchurSeg* d_ssegs = nullptr;
-  const int32_t* d_stiles = nullptr;
-  const int32_t* d_stiles_big = nullptr;
+  const int32_t* d_stiles[kSchurClasses] = {nullptr, nullptr, nullptr};
   const SchurReduce* d_reds = nullptr;
   GemmBatch zb;
   i64 zlen = 0;  // extent of the level's Z_ki blocks in the Z buffer
-  int32_t nschur_tiles = 0, nbig = 0, nsmall = 0;  // Schur tiles: all / big kernel / other kernel
-  double schur_flops = 0, big_flops = 0;  // all Schur tiles / tiles of the big kernel
+  int32_t nschur_tiles = 0, ntiles_cls[kSchurClasses] = {0, 0, 0};  // Schur tiles: all / by class
+  double schur_flops = 0, cls_flops[kSchurClasses] = {0, 0, 0};      // Schur flops: all / by class
   double xcd_imbalance = 1;  // largest over mean work of the XCDs' tile ranges (traced)
   double col_share = 1, piv_share = 1;  // targets per distinct column, pivots per distinct pivot row (traced)
   double once_bytes = 0, stream_bytes = 0;  // Schur operands read once per level / once per tile (traced)
-  std::string class_stats[2];               // the same by tile class (traced)
+  std::string class_stats[kSchurClasses];   // the same by tile class (traced)
   double union2 = 1, union4 = 1;  // K of the union of the pivot lists of 2 / 4 consecutive targets over their sum (traced)
 };
 
@@ -109,20 +111,54 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         ck_blk[fillp[i]++] = b;
       }
   }
-  // Z buffer: the Z_ki blocks of the largest level, each stored with its
-  // row count rounded up to 16 (zero rows below m_k; columns 64-byte aligned
-  // for the Schur kernel's chunks of 16 k)
+  // Z buffers: the Z_ki blocks of the largest level, each with room for both
+  // sides rounded up to 16: the pivot GEMMs write them column-major (ld m_k
+  // rounded up to 16) into dZ, and the Schur kernel reads the copy in 16 x 16
+  // tiles (launch_retile) in dZt, at the same offset
   auto kpad16 = [](i64 m) { return (m + 15) & ~i64(15); };
   i64 zmax = 1;
   for (const auto& lv : by_level) {
     i64 z = 0;
     for (i64 pi : lv)
-      for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) z += kpad16(mb[cl(ck_pos[c])]) * mb[cl(pi)];
+      for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) z += kpad16(mb[cl(ck_pos[c])]) * kpad16(mb[cl(pi)]);
     zmax = std::max(zmax, z);
   }
   if (zmax >= (i64(1) << 31)) fail(H2_EUNSUPPORTED, "factor level too wide for 32-bit Z offsets");
   f.dZ.reset(sizeof(T) * zmax);
   T* Z = f.dZ.as<T>();
+  DeviceBuffer dZt(sizeof(T) * zmax);
+  T* Zt = dZt.as<T>();
+  // S_kj operands in tiles: every stored block above the diagonal gets a
+  // tiled copy (both sides rounded up to 16) once its row is final, which the
+  // Schur updates of later levels read instead of the block itself.  Used
+  // when the copies fit in device memory (H2SP_SCHUR_TILED=0: never).
+  std::vector<i64> st_off(sp.colidx.size(), -1);
+  i64 st_len = 0;
+  for (i64 pos = 0; pos < ncl; ++pos)
+    for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) {
+      st_off[b] = st_len;
+      st_len += kpad16(mb[cl(pos)]) * kpad16(mb[sp.colidx[b]]);
+    }
+  bool tiled_s = st_len > 0;
+  if (const char* e = std::getenv("H2SP_SCHUR_TILED")) tiled_s = tiled_s && e[0] != '0';
+  if (tiled_s) {
+    size_t free_b = 0, total_b = 0;
+    HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+    free_b += cached_device_bytes();
+    // leave room for the partial sums, the work lists and the solve after
+    tiled_s = double(st_len) * sizeof(T) <= 0.8 * double(free_b) - double(sizeof(T)) * (double(zmax) + (1 << 25));
+  }
+  DeviceBuffer dSt;
+  if (tiled_s) {
+    try {
+      dSt.reset(sizeof(T) * st_len, st);
+    } catch (const Error& e) {
+      if (e.code != H2_ENOMEM) throw;
+      tiled_s = false;  // another factorisation took the memory meanwhile: read S in place
+    }
+  }
+  T* St = tiled_s ? dSt.as<T>() : nullptr;
+  f.schur_tiled = tiled_s;
   // partial sums of split targets (at most pcap elements per level)
   f.pcap = std::min<i64>(i64(1) << 25, std::max<i64>(sp.s_entries, 1));
   f.dP.reset(sizeof(T) * f.pcap);
@@ -201,10 +237,10 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     struct Out {
       std::vector<SchurItem> items;
       std::vector<int64_t> keys;
-      std::vector<int32_t> tiles, tiles_big;
+      std::vector<int32_t> tiles[kSchurClasses];
       std::vector<SchurReduce> reds;
       i64 pbase = 0, nsplit = 0;
-      double big_flops = 0;
+      double cls_flops[kSchurClasses] = {0, 0, 0};
     };
     const int nparts = par ? 4 * nthr : 1;
     std::vector<Out> outs(nparts);
@@ -218,10 +254,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         for (int32_t r = si.seg_begin; r < si.seg_end; ++r) k += L.ssegs[r].K;
         for (int a = 0; a < (si.M + edge - 1) / edge; ++a)
           for (int b = 0; b < (si.N + edge - 1) / edge; ++b) {
-            const bool big = schur_big_tile<T>(si.M, si.N, a * edge, b * edge);
-            (big ? o.tiles_big : o.tiles).push_back(int32_t((item << 8) | (a << 4) | b));
-            if (big)
-              o.big_flops += 2.0 * std::min(edge, si.M - a * edge) * std::min(edge, si.N - b * edge) * double(k);
+            const int cls = schur_tile_class<T>(si.M, si.N, a * edge, b * edge);
+            o.tiles[cls].push_back(int32_t((item << 8) | (a << 4) | b));
+            o.cls_flops[cls] += 2.0 * std::min(edge, si.M - a * edge) * std::min(edge, si.N - b * edge) * double(k);
           }
         o.items.push_back(si);
       };
@@ -258,16 +293,17 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         }
       }
     }
-    std::vector<size_t> io(nparts + 1, 0), to(nparts + 1, 0), tb(nparts + 1, 0), ro(nparts + 1, 0);
+    std::vector<size_t> io(nparts + 1, 0), ro(nparts + 1, 0);
+    std::vector<size_t> to[kSchurClasses];
+    for (auto& v : to) v.assign(nparts + 1, 0);
     std::vector<i64> po(nparts + 1, 0);
     for (int p = 0; p < nparts; ++p) {
       io[p + 1] = io[p] + outs[p].items.size();
-      to[p + 1] = to[p] + outs[p].tiles.size();
-      tb[p + 1] = tb[p] + outs[p].tiles_big.size();
+      for (int c = 0; c < kSchurClasses; ++c) to[c][p + 1] = to[c][p] + outs[p].tiles[c].size();
       ro[p + 1] = ro[p] + outs[p].reds.size();
       po[p + 1] = po[p] + outs[p].pbase;
       nsplit += outs[p].nsplit;
-      L.big_flops += outs[p].big_flops;
+      for (int c = 0; c < kSchurClasses; ++c) L.cls_flops[c] += outs[p].cls_flops[c];
     }
     if (io[nparts] >= (size_t(1) << 24)) {
       too_wide = 1;
@@ -275,8 +311,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     }
     L.sitems.resize(io[nparts]);
     L.skeys.resize(io[nparts]);
-    L.stiles.resize(to[nparts]);
-    L.stiles_big.resize(tb[nparts]);
+    for (int c = 0; c < kSchurClasses; ++c) L.stiles[c].resize(to[c][nparts]);
     L.reds.resize(ro[nparts]);
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthr) if (par)
     for (int p = 0; p < nparts; ++p) {
@@ -287,10 +322,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         L.sitems[io[p] + i] = si;
         L.skeys[io[p] + i] = o.keys[i];
       }
-      for (size_t i = 0; i < o.tiles.size(); ++i)
-        L.stiles[to[p] + i] = int32_t(uint32_t(o.tiles[i]) + (uint32_t(io[p]) << 8));
-      for (size_t i = 0; i < o.tiles_big.size(); ++i)
-        L.stiles_big[tb[p] + i] = int32_t(uint32_t(o.tiles_big[i]) + (uint32_t(io[p]) << 8));
+      for (int c = 0; c < kSchurClasses; ++c)
+        for (size_t i = 0; i < o.tiles[c].size(); ++i)
+          L.stiles[c][to[c][p] + i] = int32_t(uint32_t(o.tiles[c][i]) + (uint32_t(io[p]) << 8));
       for (size_t i = 0; i < o.reds.size(); ++i) {
         SchurReduce r = o.reds[i];
         r.p_off += po[p];
@@ -318,13 +352,18 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         const i64 soff = sp.blk_off[ck_blk[c]];
         GemmItem& it = L.zb.item(int(mk), int(mi), int(mk), int(mi));
         GemmBatch::set_out(it, 0, Z + z, kpad16(mk), false);
+        L.zts.push_back({z, z, int32_t(mk), int32_t(mi), int32_t(kpad16(mk)), 0});
         // D_k^{-1} is symmetric (D_k is): read it through its transpose so that
         // both operands run along K in memory
         L.zb.seg(Inv + f.inv_off[pk], int(mk), true, S + soff, int(mk), false, int(mk));
         L.cps.push_back({soff, z, int32_t(mk), int32_t(mi), int32_t(kpad16(mk)), 0});
-        z += kpad16(mk) * mi;
+        z += kpad16(mk) * kpad16(mi);
       }
       zbase[q + 1] = z;
+      // the row's blocks above the diagonal are final after this level
+      if (tiled_s)
+        for (i64 b = sp.rowptr[pi] + 1; b < sp.rowptr[pi + 1]; ++b)
+          L.sts.push_back({st_off[b], sp.blk_off[b], int32_t(mi), int32_t(mb[sp.colidx[b]]), int32_t(mi), 0});
     }
     L.zlen = zbase[nr];
     fl_z += L.zb.flops;
@@ -365,9 +404,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
             const i64 mk = mb[cl(pk)];
             for (i64 b = sp.rowptr[pk]; b < sp.rowptr[pk + 1]; ++b) {
               const int32_t t = mark[sp.colidx[b]];
-              if (t >= 0) out.segs[sbase + fillp[t]++] = {sp.blk_off[b], int32_t(zoff), int32_t(mk)};
+              if (t >= 0) out.segs[sbase + fillp[t]++] = {tiled_s ? st_off[b] : sp.blk_off[b], int32_t(zoff), int32_t(mk)};
             }
-            zoff += kpad16(mk) * mi;
+            zoff += kpad16(mk) * kpad16(mi);
           }
           for (i64 b = t0; b < t1; ++b) mark[sp.colidx[b]] = -1;
           out.dense_pairs += double(cptr[pi + 1] - cptr[pi]) * nt_row;
@@ -460,12 +499,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       for (long q = 0; q < long(n); ++q) st[q] = tl[size_t(idx[q])];
       tl.swap(st);
     };
-    order_tiles(L.stiles);
-    order_tiles(L.stiles_big);
-    if (trace_level() >= 2 && L.stiles.size() + L.stiles_big.size() > 0) {
+    for (auto& tl : L.stiles) order_tiles(tl);
+    if (trace_level() >= 2) {
       // the kernel gives XCD x the x-th contiguous eighth of each tile list
       double w[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tot = 0;
-      for (const std::vector<int32_t>* tl : {&L.stiles, &L.stiles_big}) {
+      for (const std::vector<int32_t>* tl : {&L.stiles[0], &L.stiles[1], &L.stiles[2]}) {
         const i64 n = i64(tl->size()), base = n / 8, rem = n % 8;
         for (int x = 0; x < 8; ++x)
           for (i64 t = x * base + std::min<i64>(x, rem); t < (x + 1) * base + std::min<i64>(x + 1, rem); ++t) {
@@ -542,11 +580,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       L.stream_bytes = stream;
       // the same split by tile class (big: more than 4 x 4 blocks of 16):
       // targets, flops, Z and S bytes streamed per tile and read once
-      for (int c = 0; c < 2; ++c) {
+      for (int c = 0; c < kSchurClasses; ++c) {
         double nt = 0, fl = 0, zs = 0, ss = 0, sm = 0, sn = 0, sk = 0, ns = 0;
         std::vector<std::pair<i64, i64>> za, sb;
         for (const SchurItem& it : L.sitems) {
-          if (int(schur_big_tile<T>(it.M, it.N, 0, 0)) != c) continue;
+          if (schur_tile_class<T>(it.M, it.N, 0, 0) != c) continue;
           ++nt;
           sm += it.M;
           sn += it.N;
@@ -572,7 +610,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         std::snprintf(buf, sizeof(buf),
                       "%s: targets %.0f mean M %.1f N %.1f, segments %.0f mean K %.1f, %.4g GFLOP, "
                       "Z per tile %.3f GB once %.3f GB, S per tile %.3f GB once %.3f GB",
-                      c ? "big" : "small", nt, sm / std::max(1.0, nt), sn / std::max(1.0, nt), ns,
+                      c == 0 ? "class 0" : c == 1 ? "class 1" : "class 2", nt, sm / std::max(1.0, nt),
+                      sn / std::max(1.0, nt), ns,
                       sk / std::max(1.0, ns), fl / 1e9, zs / 1e9, zo / 1e9, ss / 1e9, so / 1e9);
         L.class_stats[c] = buf;
       }
@@ -591,13 +630,18 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     for (auto& v : marks) std::vector<int32_t>().swap(v);
     if (too_wide) fail(H2_EUNSUPPORTED, "Schur level above 2^24 targets or 2^31 segments");
   };
-  std::vector<hipEvent_t> ev;
-  auto mark_ev = [&]() {
+  // events on the main stream: the start, then per level after the Z GEMMs,
+  // after the Schur update (all classes joined) and at the level's end; per
+  // level and tile class a start and an end event on the class's stream
+  std::vector<hipEvent_t> ev, cev;
+  auto new_ev = [&](std::vector<hipEvent_t>& v, hipStream_t s_) {
     hipEvent_t e;
     HIPCHECK(hipEventCreate(&e));
-    HIPCHECK(hipEventRecord(e, st));
-    ev.push_back(e);
+    v.push_back(e);  // owned (and destroyed) from here on, even if the record fails
+    HIPCHECK(hipEventRecord(e, s_));
+    return e;
   };
+  auto mark_ev = [&]() { return new_ev(ev, st); };
   // upload in runs of planned levels: as soon as the next level is ready,
   // every ready level after it (up to kMaxRun) goes in one copy
   constexpr int kMaxRun = 32;
@@ -615,8 +659,24 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     done_planning = true;
     cv.notify_one();
   });
-  hipStream_t cstream = nullptr;
-  HIPCHECK(hipStreamCreateWithFlags(&cstream, hipStreamNonBlocking));  // no implicit sync with the null stream
+  // The tile classes of a level update disjoint targets: classes 1 and 2
+  // run on streams of their own beside class 0 on the main stream, so that
+  // the tail of one class's launch overlaps the others (all at the default
+  // priority).
+  hipStream_t cstream = nullptr, cls_st[kSchurClasses] = {st, nullptr, nullptr};
+  auto destroy_streams = [&]() {
+    if (cstream) (void)hipStreamDestroy(cstream);
+    for (int c = 1; c < kSchurClasses; ++c)
+      if (cls_st[c]) (void)hipStreamDestroy(cls_st[c]);
+  };
+  try {
+    HIPCHECK(hipStreamCreateWithFlags(&cstream, hipStreamNonBlocking));  // no implicit sync with the null stream
+    for (int c = 1; c < kSchurClasses; ++c) HIPCHECK(hipStreamCreateWithFlags(&cls_st[c], hipStreamNonBlocking));
+  } catch (...) {
+    destroy_streams();
+    producer.join();
+    throw;
+  }
   mark_ev();
   try {
     int next = 0;
@@ -635,14 +695,15 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         all.push_back(&L.zb);
         blobs.push_back({L.inv.data(), L.inv.size() * sizeof(InvItem<T>), reinterpret_cast<const void**>(&L.d_inv)});
         blobs.push_back({L.cps.data(), L.cps.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_cps)});
+        blobs.push_back({L.zts.data(), L.zts.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_zts)});
+        blobs.push_back({L.sts.data(), L.sts.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_sts)});
         blobs.push_back({L.sitems.data(), L.sitems.size() * sizeof(SchurItem),
                          reinterpret_cast<const void**>(&L.d_sitems)});
         blobs.push_back({L.ssegs.data(), L.ssegs.size() * sizeof(SchurSeg),
                          reinterpret_cast<const void**>(&L.d_ssegs)});
-        blobs.push_back({L.stiles.data(), L.stiles.size() * sizeof(int32_t),
-                         reinterpret_cast<const void**>(&L.d_stiles)});
-        blobs.push_back({L.stiles_big.data(), L.stiles_big.size() * sizeof(int32_t),
-                         reinterpret_cast<const void**>(&L.d_stiles_big)});
+        for (int c = 0; c < kSchurClasses; ++c)
+          blobs.push_back({L.stiles[c].data(), L.stiles[c].size() * sizeof(int32_t),
+                           reinterpret_cast<const void**>(&L.d_stiles[c])});
         blobs.push_back({L.reds.data(), L.reds.size() * sizeof(SchurReduce),
                          reinterpret_cast<const void**>(&L.d_reds)});
       }
@@ -650,52 +711,61 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       upload_batches(all, chunk_desc.back(), blobs, cstream, st, /*parallel_pack=*/false);
       for (int lv = next; lv < end; ++lv) {
         FactorLevel<T>& L = lvls[lv];
-        // the Schur kernel reads a Z_ki block up to its K rounded up to 4
-        // (the lane holding K): rows K .. K4 - 1 must be zero; the buffer
-        // holds the previous level's blocks in another layout
-        launch_zero_pad_rows<T>(L.d_cps, int(L.cps.size()), Z, st);
         L.zb.template launch<T>(st);
-        mark_ev();
-        L.nschur_tiles = int32_t(L.stiles.size() + L.stiles_big.size());
-        L.nbig = int32_t(L.stiles_big.size());
-        L.nsmall = int32_t(L.stiles.size());
-        // big tiles first: they are the long ones, the others fill the tail
-        SchurLaunch sb{L.d_sitems, L.d_ssegs, L.d_stiles_big, int32_t(L.stiles_big.size()), S, Z, Pbuf};
-        launch_schur<T>(sb, true, st);
-        mark_ev();
-        SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles, int32_t(L.stiles.size()), S, Z, Pbuf};
-        launch_schur<T>(sl, false, st);
+        launch_retile<T>(L.d_zts, int(L.zts.size()), Z, Zt, st);
+        const hipEvent_t fork = mark_ev();
+        for (int c = kSchurClasses - 1; c >= 0; --c) {
+          L.ntiles_cls[c] = int32_t(L.stiles[c].size());
+          L.nschur_tiles += L.ntiles_cls[c];
+          if (c > 0) HIPCHECK(hipStreamWaitEvent(cls_st[c], fork, 0));
+          new_ev(cev, cls_st[c]);
+          SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles[c], int32_t(L.stiles[c].size()), S,
+                         tiled_s ? St : S, Zt, Pbuf, tiled_s ? 1 : 0};
+          launch_schur<T>(sl, c, cls_st[c]);
+          const hipEvent_t done = new_ev(cev, cls_st[c]);
+          if (c > 0) HIPCHECK(hipStreamWaitEvent(st, done, 0));
+        }
         mark_ev();
         launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
+        if (tiled_s) launch_retile<T>(L.d_sts, int(L.sts.size()), S, St, st);
         launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
         launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
         mark_ev();
         std::vector<SchurItem>().swap(L.sitems);
         PodVector<SchurSeg>().swap(L.ssegs);
-        std::vector<int32_t>().swap(L.stiles);
-        std::vector<int32_t>().swap(L.stiles_big);
+        for (auto& tl : L.stiles) std::vector<int32_t>().swap(tl);
         std::vector<SchurReduce>().swap(L.reds);
+        std::vector<CopySeg>().swap(L.zts);
+        std::vector<CopySeg>().swap(L.sts);
       }
       next = end;
     }
   } catch (...) {
     producer.join();
-    (void)hipStreamDestroy(cstream);
+    // the buffers of this call are freed in the order of the main stream:
+    // let every queued launch finish first
+    for (int c = 0; c < kSchurClasses; ++c) (void)hipStreamSynchronize(cls_st[c]);
+    destroy_streams();
+    for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto e : cev) (void)hipEventDestroy(e);
     throw;
   }
   producer.join();
-  HIPCHECK(hipStreamDestroy(cstream));
+  destroy_streams();  // work already queued on a destroyed stream still completes
   if (perr) std::rethrow_exception(perr);
-  if (int(ev.size()) != 4 * f.nflev + 1) fail(H2_EINVAL, "internal: factorisation stopped early");
+  constexpr int kEv = 3;  // main-stream events per level
+  if (int(ev.size()) != kEv * f.nflev + 1 || int(cev.size()) != 2 * kSchurClasses * f.nflev)
+    fail(H2_EINVAL, "internal: factorisation stopped early");
   f.flops_inv += fl_inv;
   f.flops_z += fl_z;
   f.flops_schur += fl_s;
   f.split_targets += nsplit;
   for (const auto& L : lvls) {
     f.schur_launches += L.nschur_tiles > 0 ? 1 : 0;
-    f.launches_big += L.nbig > 0 ? 1 : 0;
-    f.launches_small += L.nsmall > 0 ? 1 : 0;
-    f.flops_schur_big += L.big_flops;
+    for (int c = 0; c < kSchurClasses; ++c) {
+      f.launches_cls[c] += L.ntiles_cls[c] > 0 ? 1 : 0;
+      f.flops_cls[c] += L.cls_flops[c];
+    }
   }
   tt.lap("plan+upload+enqueue");
   if (trace_enabled()) {
@@ -715,18 +785,21 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   mark_ev();
   HIPCHECK(hipEventSynchronize(ev.back()));
   tt.lap("device-drain");
-  double piv_ms = 0, schur_ms = 0, big_ms = 0, small_ms = 0;
+  double piv_ms = 0, schur_ms = 0, cls_ms[kSchurClasses] = {0, 0, 0};
   for (int lv = 0; lv < f.nflev; ++lv) {
-    float a = 0, b1 = 0, b2 = 0, c = 0;
-    HIPCHECK(hipEventElapsedTime(&a, ev[4 * lv], ev[4 * lv + 1]));
-    HIPCHECK(hipEventElapsedTime(&b1, ev[4 * lv + 1], ev[4 * lv + 2]));
-    HIPCHECK(hipEventElapsedTime(&b2, ev[4 * lv + 2], ev[4 * lv + 3]));
-    HIPCHECK(hipEventElapsedTime(&c, ev[4 * lv + 3], ev[4 * lv + 4]));
-    const float b = b1 + b2;
+    const hipEvent_t* e = &ev[size_t(kEv) * lv];
+    const hipEvent_t* ce = &cev[size_t(2 * kSchurClasses) * lv];  // classes from the last to 0
+    float a = 0, c = 0, b = 0, bc[kSchurClasses] = {0, 0, 0};
+    HIPCHECK(hipEventElapsedTime(&a, e[0], e[1]));
+    HIPCHECK(hipEventElapsedTime(&b, e[1], e[2]));
+    HIPCHECK(hipEventElapsedTime(&c, e[2], e[3]));
+    for (int k = 0; k < kSchurClasses; ++k) {
+      const int cls = kSchurClasses - 1 - k;
+      HIPCHECK(hipEventElapsedTime(&bc[cls], ce[2 * k], ce[2 * k + 1]));
+      cls_ms[cls] += bc[cls];
+    }
     piv_ms += a + c;
     schur_ms += b;
-    big_ms += b1;
-    small_ms += b2;
     if (trace_level() >= 2)
       std::fprintf(stderr,
                    "[h2sp] factor level %d: %zu rows, %d Schur tiles, %.4g GFLOP, %.3f ms (%.1f TF), XCD imbalance %.3f, "
@@ -739,18 +812,18 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
                    lvls[lv].piv_share, lvls[lv].once_bytes / 1e9, lvls[lv].stream_bytes / 1e9, lvls[lv].union2,
                    lvls[lv].union4, a + c);
     if (trace_level() >= 2)
-      std::fprintf(stderr, "[h2sp] factor level %d small tiles %.3f ms %s; big tiles %.3f ms %s\n", lv, b2,
-                   lvls[lv].class_stats[0].c_str(), b1, lvls[lv].class_stats[1].c_str());
+      for (int k = 0; k < kSchurClasses; ++k)
+        std::fprintf(stderr, "[h2sp] factor level %d tiles %.3f ms %s\n", lv, bc[k], lvls[lv].class_stats[k].c_str());
   }
   float tot = 0;
   HIPCHECK(hipEventElapsedTime(&tot, ev.front(), ev.back()));
   for (auto e : ev) (void)hipEventDestroy(e);
+  for (auto e : cev) (void)hipEventDestroy(e);
   if (phase_ms) {
     phase_ms[4] = piv_ms;
     phase_ms[5] = schur_ms;
     phase_ms[6] = tot;
-    phase_ms[7] = big_ms;
-    phase_ms[8] = small_ms;
+    for (int k = 0; k < kSchurClasses; ++k) phase_ms[7 + k] = cls_ms[k];
   }
 }
 

@@ -32,8 +32,9 @@ struct h2_factor {
   double flops_schur = 0, flops_inv = 0, flops_z = 0;
   h2::i64 split_targets = 0;                 // Schur targets summed in parts
   h2::i64 schur_launches = 0;                // factorisation levels with Schur work
-  double flops_schur_big = 0;                // of which in tiles of more than 4 x 4 blocks (FP32)
-  h2::i64 launches_big = 0, launches_small = 0;  // launches of the two Schur kernels
+  double flops_cls[3] = {0, 0, 0};           // Schur flops by tile class (kernel)
+  h2::i64 launches_cls[3] = {0, 0, 0};       // Schur kernel launches by tile class
+  bool schur_tiled = false;                  // S_kj operands read from tiled copies
   std::unique_ptr<h2::SolvePlan> solve;
   ~h2_factor();
 };

@@ -90,8 +90,8 @@ struct SchurItem {
   int32_t partial, ksum;  // ksum: K summed over the item's segments (planning)
 };
 struct SchurSeg {
-  int64_t b_off;     // S_kj in S (K x N, ld K)
-  int32_t a_off, K;  // Z_ki in the Z buffer (K x M, ld K rounded up to 16, zero rows below K)
+  int64_t b_off;     // S_kj (K x N) in the launch's S operand array: in tiles or in place (ld K)
+  int32_t a_off, K;  // Z_ki (K x M) in tiles (see launch_retile) in the Z tile buffer
 };
 struct SchurReduce {
   int64_t s_off, p_off;  // target in S; first of `parts` consecutive M x N partial sums
@@ -102,19 +102,25 @@ struct SchurLaunch {
   const SchurSeg* segs;
   const int32_t* tiles;
   int32_t ntiles;
-  void* S;
-  const void* Z;
+  void* S;               // targets (in place, column-major)
+  const void* Sb;        // S_kj operands: tiled copies (tiled_b = 1) or S itself (tiled_b = 0)
+  const void* Z;         // Z_ki operands, in tiles
   void* P;               // partial buffer
+  int32_t tiled_b;
 };
-// A tile is big when it has more than 4 blocks of 16 along either side (FP32
-// only); big and other tiles go to separate launches (two kernels, each with
-// the register budget of its own tile shapes).
+// Tile class (each class has a kernel of its own, with the register budget
+// of its shapes; see schur_kernel): 0 when the tile has at most 4 blocks of
+// 16 along both sides (every FP64 tile), 1 when the longer side has 5, 2 when
+// it has 6 to 8.
+constexpr int kSchurClasses = 3;
 template <class T>
-constexpr bool schur_big_tile(int M, int N, int m0, int n0) {
-  return schur_edge<T> > 64 && (M - m0 > 64 || N - n0 > 64);
+constexpr int schur_tile_class(int M, int N, int m0, int n0) {
+  const int e = M - m0 > N - n0 ? M - m0 : N - n0;
+  const int b = (e < schur_edge<T> ? e : schur_edge<T>) + 15;
+  return b / 16 <= 4 ? 0 : b / 16 == 5 ? 1 : 2;
 }
 template <class T>
-void launch_schur(const SchurLaunch& g, bool big, hipStream_t st);
+void launch_schur(const SchurLaunch& g, int cls, hipStream_t st);
 template <class T>
 void launch_schur_reduce(const SchurReduce* items, int count, const T* P, T* S, hipStream_t st);
 
@@ -148,10 +154,13 @@ struct CopySeg {
 };
 template <class T>
 void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st);
-// For every segment: zeroes rows rows .. (rows rounded up to 4) - 1 of the
-// block at src (cols columns, leading dimension src_ld >= that bound).
+// For every segment: the rows x cols block at src (leading dimension src_ld)
+// into 16 x 16 tiles at dst, in the order the Schur kernel's lanes read them:
+// tile (c, q) at dst + (q C + c) 256 with C = ceil(rows / 16), element
+// (16 c + 4 g + s, 16 q + r) at 4 (r + 16 g) + s inside it; the padding to
+// whole tiles is zero.  dst needs C ceil(cols / 16) 256 elements.
 template <class T>
-void launch_zero_pad_rows(const CopySeg* segs, int count, T* src, hipStream_t st);
+void launch_retile(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st);
 
 // Kernel blocks written out: element (k, j) of block b, at out[b.off + k + j ns],
 // is kernel(x_{t0 + j}, x_{s0 + k}) of kind kern (as GemmItem::gkern; dim coordinates per point, points

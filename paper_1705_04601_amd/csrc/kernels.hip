@@ -344,6 +344,7 @@ struct SchurCursor {
   const T* pa;          // Z_ki and S_kj of the current segment
   const T* pb;
   uint32_t na, nb;      // their sizes in bytes
+  int shb;              // elements the S_kj base moves per k (16 in tiles, 1 in place)
   uint32_t oa[NBM], ob[NBN];
 };
 
@@ -357,30 +358,46 @@ __device__ __forceinline__ void schur_load_desc(SchurCursor<T, NBM, NBN>& c, con
   c.d[3] = x.w;
 }
 
+// Operand addressing of one segment.  Z_ki is always in tiles (see
+// retile_kernel): chunk c of column block q at (q C + c) 256 elements with
+// C = K16 / 16, lane l's four elements at 4 l inside the tile, so that one
+// load instruction reads 1 KB (FP32) of consecutive memory.  S_kj is in tiles
+// too when the launch says so, else read in place (column-major, ld K: each
+// lane reads four consecutive k of its column).
 template <class T, int NBM, int NBN>
-__device__ __forceinline__ void schur_setup(SchurCursor<T, NBM, NBN>& c, const T* S, const T* Z, int m0, int n0,
-                                            int M, int N, int r, int kq) {
+__device__ __forceinline__ void schur_setup(SchurCursor<T, NBM, NBN>& c, const T* Sb, const T* Z, int tiled_b,
+                                            int m0, int n0, int M, int N, int r, int kq) {
   static_assert(sizeof(SchurSeg) == 16, "descriptor of four 32-bit words");
   const int idx = c.si - c.dbase;
   const uint64_t b_off = (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(c.d[1]), idx))) << 32) |
                          uint32_t(__builtin_amdgcn_readlane(int(c.d[0]), idx));
   const int a_off = __builtin_amdgcn_readlane(int(c.d[2]), idx);
   const int K = __builtin_amdgcn_readlane(int(c.d[3]), idx);
-  const int lda = (K + 15) & ~15;
+  const int ck = (K + 15) >> 4;  // chunks of 16 k
+  const int lane4 = 4 * (r + 4 * kq);
   c.K = K;
   c.pa = Z + a_off;
-  c.pb = S + int64_t(b_off);
-  c.na = uint32_t(lda * M) * uint32_t(sizeof(T));
-  c.nb = uint32_t(K * N) * uint32_t(sizeof(T));
+  c.pb = Sb + int64_t(b_off);
+  c.na = uint32_t(ck * 16 * ((M + 15) & ~15)) * uint32_t(sizeof(T));
 #pragma unroll
-  for (int q = 0; q < NBM; ++q) c.oa[q] = uint32_t((m0 + 16 * q + r) * lda + kq) * uint32_t(sizeof(T));
+  for (int q = 0; q < NBM; ++q) c.oa[q] = uint32_t((m0 / 16 + q) * ck * 256 + lane4) * uint32_t(sizeof(T));
+  if (tiled_b) {
+    c.shb = 16;
+    c.nb = uint32_t(ck * 16 * ((N + 15) & ~15)) * uint32_t(sizeof(T));
 #pragma unroll
-  for (int q = 0; q < NBN; ++q) c.ob[q] = uint32_t((n0 + 16 * q + r) * K + kq) * uint32_t(sizeof(T));
+    for (int q = 0; q < NBN; ++q) c.ob[q] = uint32_t((n0 / 16 + q) * ck * 256 + lane4) * uint32_t(sizeof(T));
+  } else {
+    c.shb = 1;
+    c.nb = uint32_t(K * N) * uint32_t(sizeof(T));
+#pragma unroll
+    for (int q = 0; q < NBN; ++q) c.ob[q] = uint32_t((n0 + 16 * q + r) * K + kq) * uint32_t(sizeof(T));
+  }
 }
 
 template <class T, int NBM, int NBN>
-__device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const SchurSeg* segs, const T* S,
-                                           const T* Z, int m0, int n0, int M, int N, int r, int kq, int lane) {
+__device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const SchurSeg* segs, const T* Sb,
+                                           const T* Z, int tiled_b, int m0, int n0, int M, int N, int r, int kq,
+                                           int lane) {
   if (!c.valid) return;
   c.k0 += 16;
   if (c.k0 < c.K) return;
@@ -394,9 +411,9 @@ __device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const Sc
   if (c.si - c.dbase >= 64) {
     c.dbase += 64;
     schur_load_desc(c, segs, lane);
-    schur_setup(c, S, Z, m0, n0, M, N, r, kq);
+    schur_setup(c, Sb, Z, tiled_b, m0, n0, M, N, r, kq);
   } else {
-    schur_setup(c, S, Z, m0, n0, M, N, r, kq);
+    schur_setup(c, Sb, Z, tiled_b, m0, n0, M, N, r, kq);
   }
 }
 
@@ -409,9 +426,12 @@ constexpr uint32_t kOutside = 0x80000000u;  // a buffer offset past every resour
 template <class T, int NBM, int NBN>
 __device__ __forceinline__ int schur_fetch(const SchurCursor<T, NBM, NBN>& c, int kq, T (&a)[NBM][4],
                                            T (&b)[NBN][4]) {
-  const uint32_t sh = uint32_t(c.k0) * uint32_t(sizeof(T));  // k0 < K <= K16: both sizes stay positive
-  const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.pa + c.k0, c.valid ? c.na - sh : 0u);
-  const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.pb + c.k0, c.valid ? c.nb - sh : 0u);
+  // k0 < K <= K16: both sizes stay positive (a chunk of tiles moves the base
+  // by 16 elements per k, an in-place column block by one)
+  const uint32_t sha = uint32_t(c.k0 * 16) * uint32_t(sizeof(T));
+  const uint32_t shb = uint32_t(c.k0 * c.shb) * uint32_t(sizeof(T));
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.pa + c.k0 * 16, c.valid ? c.na - sha : 0u);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.pb + c.k0 * c.shb, c.valid ? c.nb - shb : 0u);
   const bool live = c.k0 + kq < c.K;
 #pragma unroll
   for (int q = 0; q < NBM; ++q) BufLoad4<T>::run(ra, live ? c.oa[q] : kOutside, a[q]);
@@ -496,7 +516,9 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
   using V = typename Mfma<T>::V;
   const int r = lane % 16, kq = 4 * (lane / 16);
   T* S = static_cast<T*>(g.S);
+  const T* Sb = static_cast<const T*>(g.Sb);
   const T* Z = static_cast<const T*>(g.Z);
+  const int tb = g.tiled_b;
   V acc[NBM][NBN];
 #pragma unroll
   for (int a = 0; a < NBM; ++a)
@@ -509,20 +531,20 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
     c.k0 = 0;
     c.valid = true;
     schur_load_desc(c, g.segs, lane);
-    schur_setup(c, S, Z, m0, n0, it.M, it.N, r, kq);
+    schur_setup(c, Sb, Z, tb, m0, n0, it.M, it.N, r, kq);
     T a[NS][NBM][4], b[NS][NBN][4];
     int steps[NS];
     steps[0] = schur_fetch(c, kq, a[0], b[0]);
 #pragma unroll
     for (int i = 1; i < NS - 1; ++i) {
-      schur_next(c, g.segs, S, Z, m0, n0, it.M, it.N, r, kq, lane);
+      schur_next(c, g.segs, Sb, Z, tb, m0, n0, it.M, it.N, r, kq, lane);
       steps[i] = schur_fetch(c, kq, a[i], b[i]);
     }
     // one exit per NS chunks; chunks past the end read zeros and take no step
     while (true) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        schur_next(c, g.segs, S, Z, m0, n0, it.M, it.N, r, kq, lane);
+        schur_next(c, g.segs, Sb, Z, tb, m0, n0, it.M, it.N, r, kq, lane);
         steps[(i + NS - 1) % NS] = schur_fetch(c, kq, a[(i + NS - 1) % NS], b[(i + NS - 1) % NS]);
         __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
         schur_mfma<T, NBM, NBN>(acc, a[i], b[i], steps[i]);
@@ -552,21 +574,26 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
       }
 }
 
-// Depth of the register ring.  Tiles of at most 4 x 4 blocks run in their own
-// kernel at two waves per SIMD: three sets in FP32, two in FP64.  Larger FP32
-// tiles (up to a whole 128 x 128 target, 8 x 8 blocks) run in a second kernel
-// at one wave per SIMD, the accumulators (at most 256) in AGPRs and the
-// operand sets in VGPRs: as many sets (2 to 4) as fit in about 176 of them,
-// so that the smaller tiles of that kernel keep more chunks in flight.
-template <class T, int NBM, int NBN, bool BIG>
+// Tile classes and the depth of the register ring.  Each class runs in a
+// kernel of its own, so that each gets the register budget of its own shapes:
+//   0: at most 4 blocks of 16 along both sides (FP64: every tile); FP32
+//      three sets, FP64 two, two waves per SIMD;
+//   1: (FP32) 5 blocks along the longer side, the common whole-target shape
+//      of the leaves (65 to 80 rows); two sets, so that the accumulators
+//      (at most 100, in AGPRs) and the operands fit two waves per SIMD;
+//   2: (FP32) 6 to 8 blocks, up to a whole 128 x 128 target whose 256
+//      accumulators fill the AGPRs, one wave per SIMD; as many sets (2 to 4)
+//      as fit in about 176 VGPRs, so that the smaller of these shapes keep
+//      more chunks in flight.
+template <class T, int NBM, int NBN, int CLS>
 constexpr int schur_stages() {
-  if (!BIG) return sizeof(T) == 4 ? 3 : 2;
+  if (CLS == 0) return sizeof(T) == 4 ? 3 : 2;
+  if (CLS == 1) return 2;
   constexpr int n = 176 / (4 * (NBM + NBN));
   return n < 2 ? 2 : (n > 4 ? 4 : n);
 }
 
-// BIG = false: tiles of at most 4 x 4 blocks; BIG = true: the others (FP32).
-template <class T, bool BIG>
+template <class T, int CLS>
 __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
   constexpr int E = schur_edge<T>;
   const int lane = threadIdx.x;
@@ -576,25 +603,32 @@ __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
   constexpr int B = E / 16;
   const int nbm = min(B, (it.M - m0 + 15) / 16), nbn = min(B, (it.N - n0 + 15) / 16);
 #define H2_SCHUR_CASE(I, J) \
-  case I * 8 + J: schur_tile<T, I, J, schur_stages<T, I, J, BIG>()>(g, it, m0, n0, lane); break;
-  if constexpr (!BIG) {
+  case I * 8 + J: schur_tile<T, I, J, schur_stages<T, I, J, CLS>()>(g, it, m0, n0, lane); break;
+  if constexpr (CLS == 0) {
     switch (nbm * 8 + nbn) {
 #define H2_SCHUR_ROW(I) H2_SCHUR_CASE(I, 1) H2_SCHUR_CASE(I, 2) H2_SCHUR_CASE(I, 3) H2_SCHUR_CASE(I, 4)
       H2_SCHUR_ROW(1) H2_SCHUR_ROW(2) H2_SCHUR_ROW(3) H2_SCHUR_ROW(4)
 #undef H2_SCHUR_ROW
       default: break;
     }
-  } else if constexpr (B == 8) {
+  } else if constexpr (CLS == 1 && B == 8) {
+    switch (nbm * 8 + nbn) {
+      H2_SCHUR_CASE(5, 1) H2_SCHUR_CASE(5, 2) H2_SCHUR_CASE(5, 3) H2_SCHUR_CASE(5, 4) H2_SCHUR_CASE(5, 5)
+      H2_SCHUR_CASE(1, 5) H2_SCHUR_CASE(2, 5) H2_SCHUR_CASE(3, 5) H2_SCHUR_CASE(4, 5)
+      default: break;
+    }
+  } else if constexpr (CLS == 2 && B == 8) {
     switch (nbm * 8 + nbn) {
 #define H2_SCHUR_ROW(I) \
   H2_SCHUR_CASE(I, 1) H2_SCHUR_CASE(I, 2) H2_SCHUR_CASE(I, 3) H2_SCHUR_CASE(I, 4) \
   H2_SCHUR_CASE(I, 5) H2_SCHUR_CASE(I, 6) H2_SCHUR_CASE(I, 7) H2_SCHUR_CASE(I, 8)
-      H2_SCHUR_ROW(5) H2_SCHUR_ROW(6) H2_SCHUR_ROW(7) H2_SCHUR_ROW(8)
+      H2_SCHUR_ROW(6) H2_SCHUR_ROW(7) H2_SCHUR_ROW(8)
 #undef H2_SCHUR_ROW
-      H2_SCHUR_CASE(1, 5) H2_SCHUR_CASE(1, 6) H2_SCHUR_CASE(1, 7) H2_SCHUR_CASE(1, 8)
-      H2_SCHUR_CASE(2, 5) H2_SCHUR_CASE(2, 6) H2_SCHUR_CASE(2, 7) H2_SCHUR_CASE(2, 8)
-      H2_SCHUR_CASE(3, 5) H2_SCHUR_CASE(3, 6) H2_SCHUR_CASE(3, 7) H2_SCHUR_CASE(3, 8)
-      H2_SCHUR_CASE(4, 5) H2_SCHUR_CASE(4, 6) H2_SCHUR_CASE(4, 7) H2_SCHUR_CASE(4, 8)
+      H2_SCHUR_CASE(1, 6) H2_SCHUR_CASE(1, 7) H2_SCHUR_CASE(1, 8)
+      H2_SCHUR_CASE(2, 6) H2_SCHUR_CASE(2, 7) H2_SCHUR_CASE(2, 8)
+      H2_SCHUR_CASE(3, 6) H2_SCHUR_CASE(3, 7) H2_SCHUR_CASE(3, 8)
+      H2_SCHUR_CASE(4, 6) H2_SCHUR_CASE(4, 7) H2_SCHUR_CASE(4, 8)
+      H2_SCHUR_CASE(5, 6) H2_SCHUR_CASE(5, 7) H2_SCHUR_CASE(5, 8)
       default: break;
     }
   }
@@ -901,16 +935,23 @@ __global__ __launch_bounds__(256) void copy_segments_kernel(const CopySeg* segs,
     for (int r = lane; r < s.rows; r += 64) dst[s.dst + int64_t(c) * s.rows + r] = src[s.src + int64_t(c) * s.src_ld + r];
 }
 
+// Copies a rows x cols column-major block (ld src_ld) into 16 x 16 tiles in
+// the Schur kernel's lane order (rows = k, columns = the other index): tile
+// (c, q) of the block at (q C + c) 256 elements, C = ceil(rows / 16); inside
+// a tile, element (k = 16 c + 4 g + s, column 16 q + r) at 4 (r + 16 g) + s.
+// Places outside the block are written as zeros.  One work-group per block,
+// threads along the tiled block (writes contiguous).
 template <class T>
-__global__ __launch_bounds__(256) void zero_pad_rows_kernel(const CopySeg* segs, int count, T* src) {
-  // one segment per 64 lanes: lane (column, pad row)
-  const int sid = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
-  if (sid >= count) return;
-  const CopySeg s = segs[sid];
-  const int pad = ((s.rows + 3) & ~3) - s.rows;
-  for (int e = lane; e < pad * s.cols; e += 64) {
-    const int c = e / pad, r = s.rows + e % pad;
-    src[s.src + int64_t(c) * s.src_ld + r] = T(0);
+__global__ __launch_bounds__(256) void retile_kernel(const CopySeg* segs, const T* src, T* dst) {
+  const CopySeg sg = segs[blockIdx.y];
+  const int ck = (sg.rows + 15) >> 4, cq = (sg.cols + 15) >> 4;
+  const int64_t len = int64_t(ck) * cq * 256;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < len; e += int64_t(gridDim.x) * blockDim.x) {
+    const int t = int(e >> 8), p = int(e & 255);
+    const int q = t / ck, c = t - q * ck;
+    const int l = p >> 2, s4 = p & 3;
+    const int k = 16 * c + 4 * (l >> 4) + s4, col = 16 * q + (l & 15);
+    dst[sg.dst + e] = (k < sg.rows && col < sg.cols) ? src[sg.src + int64_t(col) * sg.src_ld + k] : T(0);
   }
 }
 
@@ -995,18 +1036,22 @@ template void launch_gemm<double>(const GemmLaunch&, hipStream_t);
 template void launch_gemm<float>(const GemmLaunch&, hipStream_t);
 
 template <class T>
-void launch_schur(const SchurLaunch& g, bool big, hipStream_t st) {
+void launch_schur(const SchurLaunch& g, int cls, hipStream_t st) {
   if (g.ntiles <= 0) return;
   if constexpr (sizeof(T) == 4) {
-    if (big) {
-      hipLaunchKernelGGL((schur_kernel<T, true>), dim3(g.ntiles), dim3(64), 0, st, g);
+    if (cls == 1) {
+      hipLaunchKernelGGL((schur_kernel<T, 1>), dim3(g.ntiles), dim3(64), 0, st, g);
+      return;
+    }
+    if (cls == 2) {
+      hipLaunchKernelGGL((schur_kernel<T, 2>), dim3(g.ntiles), dim3(64), 0, st, g);
       return;
     }
   }
-  hipLaunchKernelGGL((schur_kernel<T, false>), dim3(g.ntiles), dim3(64), 0, st, g);
+  hipLaunchKernelGGL((schur_kernel<T, 0>), dim3(g.ntiles), dim3(64), 0, st, g);
 }
-template void launch_schur<double>(const SchurLaunch&, bool, hipStream_t);
-template void launch_schur<float>(const SchurLaunch&, bool, hipStream_t);
+template void launch_schur<double>(const SchurLaunch&, int, hipStream_t);
+template void launch_schur<float>(const SchurLaunch&, int, hipStream_t);
 
 template <class T>
 void launch_schur_reduce(const SchurReduce* items, int count, const T* P, T* S, hipStream_t st) {
@@ -1039,11 +1084,14 @@ void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, 
   }
 }
 template <class T>
-void launch_zero_pad_rows(const CopySeg* segs, int count, T* src, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(zero_pad_rows_kernel<T>, dim3((count + 3) / 4), dim3(256), 0, st, segs, count, src);
+void launch_retile(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st) {
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int c = (count - c0) < 65535 ? (count - c0) : 65535;
+    hipLaunchKernelGGL(retile_kernel<T>, dim3(4, c), dim3(256), 0, st, segs + c0, src, dst);
+  }
 }
-template void launch_zero_pad_rows<double>(const CopySeg*, int, double*, hipStream_t);
-template void launch_zero_pad_rows<float>(const CopySeg*, int, float*, hipStream_t);
+template void launch_retile<double>(const CopySeg*, int, const double*, double*, hipStream_t);
+template void launch_retile<float>(const CopySeg*, int, const float*, float*, hipStream_t);
 template void launch_copy_segments<double>(const CopySeg*, int, const double*, double*, hipStream_t);
 template void launch_copy_segments<float>(const CopySeg*, int, const float*, float*, hipStream_t);
 

@@ -63,7 +63,20 @@ struct CachedBlock {
 std::mutex g_cache_mu;
 std::multimap<size_t, CachedBlock> g_cache;  // by capacity
 size_t g_cached = 0;
-constexpr size_t kCacheLimit = size_t(64) << 30;
+// idle bytes kept: half of the device's memory (the tiled operand copies of
+// the factorisation of the largest workloads take tens of GB, and a hipMalloc
+// and hipFree of that size cost a noticeable part of a factorisation)
+size_t cache_limit() {
+  static const size_t lim = [] {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || total_b == 0) {
+      (void)hipGetLastError();
+      return size_t(64) << 30;
+    }
+    return total_b / 2;
+  }();
+  return lim;
+}
 
 size_t round_cap(size_t b) {
   constexpr size_t g = size_t(2) << 20;
@@ -139,7 +152,7 @@ void device_free(void* p, size_t cap) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   g_cache.emplace(cap, CachedBlock{p, cap, ev, dev});
   g_cached += cap;
-  trim_locked(kCacheLimit);
+  trim_locked(cache_limit());
 }
 }  // namespace
 

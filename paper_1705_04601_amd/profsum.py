@@ -4,7 +4,7 @@
       per-kernel totals from <prefix>_kernel_stats.csv and, for each Schur
       kernel, the per-launch average from <prefix>_kernel_trace.csv
   python -m paper_1705_04601_amd.profsum traffic <fetch_dir> <fetch_prefix> <write_dir> <write_prefix> <copy_mib> [kernel]
-      HBM bytes per launch of one kernel (default the big-tile Schur kernel)
+      HBM bytes per launch of one kernel (default the Schur kernel of tile class 1)
       from a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch), each
       scaled by what the counter reads for the plain copy of <copy_mib> MiB
       that bench.py --copy-probe-mib runs first
@@ -19,7 +19,7 @@ import hashlib
 import os
 import sys
 
-SCHUR = "schur_kernel<float, true>"  # the big-tile Schur kernel
+SCHUR = "schur_kernel<float, 1>"  # the Schur kernel of the whole leaf targets
 SCHUR_ANY = "schur_kernel<"
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SOURCES = [os.path.join(ROOT, "paper_1705_04601_amd", "csrc", f) for f in ("kernels.hip", "factor.cpp")]
