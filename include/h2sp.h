@@ -273,8 +273,24 @@ int h2_factor_S_batch(h2_sparse* const* sps, int count, const h2_factor_opts* op
 int h2_solve_batch(h2_factor* const* fs, int count, const double* const* b, double* const* x,
                    const int64_t* nrhs, const int64_t* ld, const h2_solve_opts* opts, h2_solve_info* infos);
 
-/* One application of the preconditioner: x = V (L D L^T)^{-1} U^T b (device). */
+/* One application of the preconditioner: x = V (L D L^T)^{-1} U^T b (device),
+ * i.e. the solve S y = U^T b, x = V y of eq. sp0 (Introduction) with the
+ * block factorisation of S in place of S; b, x: device, column-major n x nrhs,
+ * leading dimension ld >= n, 1 <= nrhs <= 512; EINVAL otherwise. */
 int h2_apply_inverse(h2_factor* f, const double* b, double* x, int64_t nrhs, int64_t ld);
+
+/* h2_apply_inverse for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, with every vector and work list in
+ * one static device array of the library (64 MiB per GPU, held until the
+ * process ends) instead of memory of its own; no hipMalloc, hipFree or other
+ * allocating routine is called.  Requests whose vectors and work lists do not
+ * fit the array (about 4 n nrhs doubles plus the lists) return EINVAL with a
+ * message.  Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (other streams or threads) race; the array keeps the last call's
+ * contents, and each call writes everything it reads.  Work runs on the
+ * stream of h2_set_stream and the call returns when it is done. */
+int h2_apply_inverse_noalloc(h2_factor* f, const double* b, double* x, int64_t nrhs, int64_t ld);
 
 void h2_matrix_destroy(h2_matrix* h);
 void h2_sparse_destroy(h2_sparse* sp);

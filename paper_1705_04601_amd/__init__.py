@@ -99,6 +99,7 @@ _SIGS = {
     "h2_solve_with": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I64, ctypes.POINTER(h2_solve_opts),
                                      ctypes.POINTER(h2_solve_info)]),
     "h2_apply_inverse": (ctypes.c_int, [_P, _P, _P, _I64, _I64]),
+    "h2_apply_inverse_noalloc": (ctypes.c_int, [_P, _P, _P, _I64, _I64]),
     "h2_matrix_destroy": (None, [_P]),
     "h2_sparse_destroy": (None, [_P]),
     "h2_factor_destroy": (None, [_P]),
@@ -377,6 +378,13 @@ def h2_apply_inverse(f: H2FactorHandle, b, x):
     _use_torch_stream()
     n, nrhs, ld = _colmajor(b)
     _check(lib().h2_apply_inverse(f.ptr, _dev(b), _dev(x), nrhs, ld))
+
+
+def h2_apply_inverse_noalloc(f: H2FactorHandle, b, x):
+    """h2_apply_inverse with no device allocation (the library's static scratch)."""
+    _use_torch_stream()
+    n, nrhs, ld = _colmajor(b)
+    _check(lib().h2_apply_inverse_noalloc(f.ptr, _dev(b), _dev(x), nrhs, ld))
 
 
 def h2_last_timings():

@@ -360,6 +360,16 @@ extern "C" int h2_apply_inverse(h2_factor* f, const double* b, double* x, int64_
   H2_API_END
 }
 
+int apply_inverse_noalloc_impl(h2_factor* f, const double* b, double* x, h2::i64 nrhs, h2::i64 ld);
+
+extern "C" int h2_apply_inverse_noalloc(h2_factor* f, const double* b, double* x, int64_t nrhs, int64_t ld) {
+  H2_API_BEGIN
+  if (!f || !b || !x) fail(H2_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > 512 || ld < f->sp->H->tree.n) fail(H2_EINVAL, "bad nrhs / ld");
+  apply_inverse_noalloc_impl(f, b, x, nrhs, ld);
+  H2_API_END
+}
+
 extern "C" int h2_last_timings(double* ms, int count) {
   H2_API_BEGIN
   if (!ms) fail(H2_EINVAL, "null argument");

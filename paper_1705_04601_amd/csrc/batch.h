@@ -317,4 +317,54 @@ inline void upload_batches(const std::vector<GemmBatch*>& bs, DeviceBuffer& stor
   for (size_t i = 0; i < extra.size(); ++i) *extra[i].dev = base + xoff[i];
 }
 
+// Bump allocation inside device memory the caller owns (no allocation of
+// its own): pieces aligned to 256 bytes, H2_EINVAL once the region is used up.
+struct DeviceArena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  const char* what = "scratch";
+  void* take(size_t bytes) {
+    const size_t at = (used + 255) & ~size_t(255);
+    if (at > cap || bytes > cap - at)
+      fail(H2_EINVAL, std::string(what) + ": needs more than its " + std::to_string(cap >> 20) + " MiB");
+    used = at + bytes;
+    return base + at;
+  }
+};
+
+// As upload_batches, into a DeviceArena: staged through ordinary host memory
+// and copied on stream st, which is synchronised before the host copy is
+// released.  Allocates no device memory.
+inline void upload_batches_into(const std::vector<GemmBatch*>& bs, DeviceArena& ar, hipStream_t st) {
+  for (GemmBatch* b : bs) b->build_tiles();
+  auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t total = 0;
+  std::vector<size_t> off(bs.size() * 3);
+  for (size_t i = 0; i < bs.size(); ++i) {
+    off[3 * i] = total;
+    total = align(total + bs[i]->items.size() * sizeof(GemmItem));
+    off[3 * i + 1] = total;
+    total = align(total + bs[i]->segs.size() * sizeof(GemmSeg));
+    off[3 * i + 2] = total;
+    total = align(total + bs[i]->tiles.size() * sizeof(int32_t));
+  }
+  if (total == 0) return;
+  char* base = static_cast<char*>(ar.take(total));
+  std::vector<char> staging(total);
+  for (size_t i = 0; i < bs.size(); ++i) {
+    const GemmBatch& b = *bs[i];
+    if (!b.items.empty()) std::memcpy(&staging[off[3 * i]], b.items.data(), b.items.size() * sizeof(GemmItem));
+    if (!b.segs.empty()) std::memcpy(&staging[off[3 * i + 1]], b.segs.data(), b.segs.size() * sizeof(GemmSeg));
+    if (!b.tiles.empty()) std::memcpy(&staging[off[3 * i + 2]], b.tiles.data(), b.tiles.size() * sizeof(int32_t));
+  }
+  HIPCHECK(hipMemcpyAsync(base, staging.data(), total, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  for (size_t i = 0; i < bs.size(); ++i) {
+    bs[i]->d_items = reinterpret_cast<const GemmItem*>(base + off[3 * i]);
+    bs[i]->d_segs = reinterpret_cast<const GemmSeg*>(base + off[3 * i + 1]);
+    bs[i]->d_tiles = reinterpret_cast<const int32_t*>(base + off[3 * i + 2]);
+    bs[i]->drop_host();
+  }
+}
+
 }  // namespace h2

@@ -12,6 +12,9 @@ namespace h2 {
 struct SolvePlan {
   i64 nrhs = 0;
   DeviceBuffer zin, zbuf, y, w, rs, colscale, desc;
+  void* zin_ptr = nullptr;               // the vectors' addresses: in the buffers above, or in a
+  double* rs_ptr = nullptr;              // scratch arena (allocation-free plans)
+  bool eager = false;                    // launched one by one instead of as a captured graph
   std::vector<GemmBatch> up, down;       // U^T and V sweeps, per tree level
   std::vector<GemmBatch> fwd, bwd;       // triangular solves, per DAG level
   GemmBatch diag;                        // D^{-1}

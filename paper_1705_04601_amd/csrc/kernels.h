@@ -175,6 +175,13 @@ struct KernelBlock {
 void launch_kernel_blocks(const KernelBlock* blocks, int count, const double* x, int dim, int kern,
                           double scale, double diag, double* out, hipStream_t st);
 
+// Scratch of the entry point that allocates nothing (h2_apply_inverse_noalloc):
+// one static device array of kNoAllocScratchBytes per GPU, held until the
+// process ends.  noalloc_scratch gives its device address on the current
+// device (taken once per device with hipGetSymbolAddress).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch(void** ptr);
+
 // Small element-wise helpers.
 void launch_fill(double* p, int64_t n, double v, hipStream_t st);
 void launch_fill_f(float* p, int64_t n, float v, hipStream_t st);

@@ -28,8 +28,11 @@ struct MatvecPlanView {
 };
 MatvecPlanView matvec_buffers(MatvecPlan& p);
 
+// With an arena the vectors and the work lists are placed in it (no device
+// allocation) and the plan is launched eagerly; else they get buffers of
+// their own and the application is captured as a graph on first use.
 template <class T>
-static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
+static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs, DeviceArena* arena = nullptr) {
   TraceTimer tt("solve-plan");
   h2_sparse& sp = *f.sp;
   h2_matrix& H = *sp.H;
@@ -49,16 +52,28 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
       zoff[c] = zs;
       zs += na[c] * nrhs;
     }
-  p->zin.reset(sizeof(T) * n * nrhs);       // right-hand side in tree order (leaf z)
-  p->zbuf.reset(sizeof(T) * std::max<i64>(zs, 1));
-  p->y.reset(sizeof(T) * n * nrhs);
-  p->w.reset(sizeof(T) * n * nrhs);
-  p->rs.reset(sizeof(double) * n * nrhs);
-  p->colscale.reset(sizeof(double) * nrhs);
-  T* zin = p->zin.as<T>();
-  T* zb = p->zbuf.as<T>();
-  T* y = p->y.as<T>();
-  T* w = p->w.as<T>();
+  T *zin, *zb, *y, *w;
+  if (arena) {
+    p->eager = true;
+    zin = static_cast<T*>(arena->take(sizeof(T) * n * nrhs));
+    zb = static_cast<T*>(arena->take(sizeof(T) * std::max<i64>(zs, 1)));
+    y = static_cast<T*>(arena->take(sizeof(T) * n * nrhs));
+    w = static_cast<T*>(arena->take(sizeof(T) * n * nrhs));
+    p->rs_ptr = static_cast<double*>(arena->take(sizeof(double) * n * nrhs));
+  } else {
+    p->zin.reset(sizeof(T) * n * nrhs);       // right-hand side in tree order (leaf z)
+    p->zbuf.reset(sizeof(T) * std::max<i64>(zs, 1));
+    p->y.reset(sizeof(T) * n * nrhs);
+    p->w.reset(sizeof(T) * n * nrhs);
+    p->rs.reset(sizeof(double) * n * nrhs);
+    p->colscale.reset(sizeof(double) * nrhs);
+    zin = p->zin.as<T>();
+    zb = p->zbuf.as<T>();
+    y = p->y.as<T>();
+    w = p->w.as<T>();
+    p->rs_ptr = p->rs.as<double>();
+  }
+  p->zin_ptr = zin;
   const T* Q = (sp.precision == H2_MIXED) ? sp.dQt.as<T>() : reinterpret_cast<const T*>(sp.dQ.as<double>());
   const T* S = sp.dS.as<T>();
   (void)0;
@@ -169,7 +184,8 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
   all.push_back(&p->diag);
   for (GemmBatch* g : all) g->role = ROLE_SOLVE;
   HIPCHECK(hipStreamSynchronize(current_stream()));
-  upload_batches(all, p->desc);
+  if (arena) upload_batches_into(all, *arena, current_stream());
+  else upload_batches(all, p->desc);
   return p;
 }
 
@@ -178,13 +194,15 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs) {
 template <class T>
 static void apply_tree(h2_factor& f, SolvePlan& p, hipStream_t st) {
   const int L = f.sp->H->tree.depth;
-  p.apply.run(st, [&](hipStream_t s) {
+  auto record = [&](hipStream_t s) {
     for (int k = 0; k <= L; ++k) p.up[k].launch<T>(s);
     for (int lv = 0; lv < f.nflev; ++lv) p.fwd[lv].launch<T>(s);
     p.diag.launch<T>(s);
     for (int lv = 0; lv < f.nblev; ++lv) p.bwd[lv].launch<T>(s);
     for (int k = L; k >= 0; --k) p.down[k].launch<T>(s);
-  });
+  };
+  if (p.eager) record(st);
+  else p.apply.run(st, record);
 }
 
 SolvePlan& solve_plan(h2_factor& f, i64 nrhs) {
@@ -203,13 +221,13 @@ static void correction(h2_factor& f, SolvePlan& p, const double* r_tree, double*
                        hipStream_t st) {
   const i64 n = f.sp->H->tree.n, nrhs = p.nrhs;
   if (f.sp->precision == H2_MIXED) {
-    launch_scale_to_f_rm(r_tree, colscale_dev, p.zin.as<float>(), n, nrhs, st);
+    launch_scale_to_f_rm(r_tree, colscale_dev, static_cast<float*>(p.zin_ptr), n, nrhs, st);
     apply_tree<float>(f, p, st);
-    launch_add_scaled_f_rm(p.zin.as<float>(), colscale_dev, acc, n, nrhs, st);
+    launch_add_scaled_f_rm(static_cast<const float*>(p.zin_ptr), colscale_dev, acc, n, nrhs, st);
   } else {
-    HIPCHECK(hipMemcpyAsync(p.zin.ptr, r_tree, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
+    HIPCHECK(hipMemcpyAsync(p.zin_ptr, r_tree, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
     apply_tree<double>(f, p, st);
-    launch_add(p.zin.as<double>(), acc, n * nrhs, n * nrhs, 1, st);
+    launch_add(static_cast<const double*>(p.zin_ptr), acc, n * nrhs, n * nrhs, 1, st);
   }
 }
 
@@ -226,9 +244,33 @@ int apply_inverse_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 l
   DeviceBuffer rt(sizeof(double) * n * nrhs), ones(sizeof(double) * nrhs);
   launch_fill(ones.as<double>(), nrhs, 1.0, st);
   launch_gather_rm(b, ld, H.d_perm.as<i64>(), rt.as<double>(), n, nrhs, st);
-  launch_fill(p.rs.as<double>(), n * nrhs, 0.0, st);
-  correction(*f, p, rt.as<double>(), p.rs.as<double>(), ones.as<double>(), st);
-  launch_scatter_rm(p.rs.as<double>(), H.d_perm.as<i64>(), x, ld, n, nrhs, st);
+  launch_fill(p.rs_ptr, n * nrhs, 0.0, st);
+  correction(*f, p, rt.as<double>(), p.rs_ptr, ones.as<double>(), st);
+  launch_scatter_rm(p.rs_ptr, H.d_perm.as<i64>(), x, ld, n, nrhs, st);
+  HIPCHECK(hipStreamSynchronize(st));
+  return H2_OK;
+}
+
+// The same application without allocating device memory: every vector and
+// the work lists of a plan made for this call live in the library's static
+// scratch array (kNoAllocScratchBytes per GPU), launched eagerly.  The
+// array is shared by every call on its GPU: calls that overlap race.
+int apply_inverse_noalloc_impl(h2_factor* f, const double* b, double* x, i64 nrhs, i64 ld) {
+  h2_matrix& H = *f->sp->H;
+  const i64 n = H.tree.n;
+  hipStream_t st = current_stream();
+  void* base = nullptr;
+  HIPCHECK(noalloc_scratch(&base));
+  DeviceArena ar{static_cast<char*>(base), kNoAllocScratchBytes, 0, "h2_apply_inverse_noalloc: the scratch array"};
+  double* rt = static_cast<double*>(ar.take(sizeof(double) * n * nrhs));
+  double* ones = static_cast<double*>(ar.take(sizeof(double) * nrhs));
+  std::unique_ptr<SolvePlan> p = f->sp->precision == H2_MIXED ? make_solve_plan<float>(*f, nrhs, &ar)
+                                                               : make_solve_plan<double>(*f, nrhs, &ar);
+  launch_fill(ones, nrhs, 1.0, st);
+  launch_gather_rm(b, ld, H.d_perm.as<i64>(), rt, n, nrhs, st);
+  launch_fill(p->rs_ptr, n * nrhs, 0.0, st);
+  correction(*f, *p, rt, p->rs_ptr, ones, st);
+  launch_scatter_rm(p->rs_ptr, H.d_perm.as<i64>(), x, ld, n, nrhs, st);
   HIPCHECK(hipStreamSynchronize(st));
   return H2_OK;
 }
@@ -411,7 +453,7 @@ static int solve_impl2(h2_factor* f, const h2_matrix& A, const double* b, double
   const size_t vec = sizeof(double) * n * nrhs;
   DeviceBuffer bt(vec), rt(vec), xprev(method == H2_SOLVE_AUTO ? vec : 0), nrm(sizeof(double) * 2 * nrhs),
       cs(sizeof(double) * nrhs), part(sizeof(double) * 2 * nrhs * residual_rm_blocks(n));
-  SolveState S{*f, A, p, mv, matvec_buffers(mv), n, nrhs, st, bt.as<double>(), p.rs.as<double>(),
+  SolveState S{*f, A, p, mv, matvec_buffers(mv), n, nrhs, st, bt.as<double>(), p.rs_ptr,
                rt.as<double>(), nrm.as<double>(), part.as<double>(), {}, {}, {}};
   launch_gather_rm(b, ld, A.d_perm.as<i64>(), S.bt, n, nrhs, st);
   launch_fill(S.xt, n * nrhs, 0.0, st);
