@@ -41,20 +41,25 @@ enum {
 
 /* ---- options --------------------------------------------------------------- */
 enum { H2_KERNEL_INVDIST = 0,   /* A_ij = scale / |x_i - x_j| (i != j), A_ii = diag */
-       H2_KERNEL_EXP = 1 };     /* A_ij = scale exp(-|x_i - x_j|^2) (i != j), A_ii =
+       H2_KERNEL_EXP = 1,       /* A_ij = scale exp(-|x_i - x_j|^2) (i != j), A_ii =
                                    diag: Example 2 of Section 5.1 (its matrix
                                    2 delta_ij + exp(-|r_i - r_j|^2) is scale 1,
-                                   diag 3).  h2_sparsify_batch takes matrices
-                                   of one kernel kind (H2_EUNSUPPORTED
-                                   otherwise).                                 */
+                                   diag 3).                                    */
+       H2_KERNEL_IFMM = 2 };    /* A_ij = scale r / d for 0 < r < d and scale d / r
+                                   for r >= d, r = |x_i - x_j|, d = param > 0,
+                                   A_ii = diag: Example 4 of Section 5.5 (scale
+                                   1, diag 1).  h2_sparsify_batch takes matrices
+                                   of one kernel kind and parameter
+                                   (H2_EUNSUPPORTED otherwise).                */
 enum { H2_FP64 = 0,             /* every step in FP64                                */
        H2_MIXED = 1 };          /* transforms, S and its factor in FP32 (MFMA), basis
                                    QR, pivot-block inversion and residuals in FP64   */
 
 typedef struct {
-  int kind;      /* H2_KERNEL_INVDIST or H2_KERNEL_EXP                          */
-  double scale;  /* c in c / |x - y| or c exp(-|x - y|^2)                       */
+  int kind;      /* H2_KERNEL_INVDIST, H2_KERNEL_EXP or H2_KERNEL_IFMM          */
+  double scale;  /* c in c / |x - y|, c exp(-|x - y|^2), c r / d or c d / r     */
   double diag;   /* value of A_ii                                               */
+  double param;  /* d of H2_KERNEL_IFMM (> 0); ignored by the other kinds       */
 } h2_kernel;
 
 typedef struct {

@@ -28,7 +28,7 @@ from .sparsify import (Sparsified, sparsify, apply_ut, apply_v, dense_s, dense_u
 from .solve import (BlockILU0, dense_lu_solver, refine, rel_residual,
                     conjugate_gradient, elimination_order, elimination_colours,
                     block_fill, filled)
-from .precond import BlockILUT, gmres
+from .precond import BlockILUT, SymBlockILUT, gmres
 
 __all__ = [
     "ClusterTree", "BlockTree", "build_cluster_tree", "build_block_tree",
@@ -37,5 +37,5 @@ __all__ = [
     "apply_ut", "apply_v", "dense_s", "dense_u", "pattern_predicate",
     "cluster_sizes", "BlockILU0", "dense_lu_solver", "refine", "rel_residual",
     "conjugate_gradient", "elimination_order", "elimination_colours",
-    "block_fill", "filled", "BlockILUT", "gmres",
+    "block_fill", "filled", "BlockILUT", "SymBlockILUT", "gmres",
 ]

@@ -114,6 +114,90 @@ class BlockILUT:
         return x.reshape(r_s.shape)
 
 
+class SymBlockILUT:
+    """Symmetric block threshold incomplete factorisation S ~ U^T D^{-1} U
+    (block L D L^T with L_ik = U_ki^T D_k^{-1}, D_i = U_ii) in an
+    elimination order: the reading of ILUt for a symmetric S (Proposition
+    2.1), whose factor stays symmetric.
+
+    Row i, left-looking: its blocks at or after i in the order start as S_ij;
+    every earlier row k whose block (k, i) was kept subtracts
+    U_ki^T D_k^{-1} U_kj from block (i, j) for each kept U_kj with j at or
+    after i (a fill block where S_ij is not stored).  Once row i is finished,
+    a fill block (i, j), j after i, is dropped when its Frobenius norm is
+    below tau times that of block row i of S as given (both triangles);
+    blocks of S's own pattern are kept.  The drop decision is taken once, on
+    the upper block; the lower block L_ji mirrors it.  tau = infinity keeps
+    S's pattern (block ILU(0)), tau = 0 the whole structural fill (the exact
+    factorisation).
+    """
+
+    def __init__(self, sp: Sparsified, tau: float, order=None):
+        self.sp = sp
+        if order is None:
+            order = sp.order
+        order = [int(c) for c in order if sp.nonbasis[c] > 0]
+        self.order = order
+        self.pos = pos = {c: i for i, c in enumerate(order)}
+        upat = {c: set() for c in order}
+        ref = {c: 0.0 for c in order}
+        for (t, u), blk in sp.s_blocks.items():
+            ref[t] += float(np.sum(blk * blk))
+            if pos[u] >= pos[t]:
+                upat[t].add(u)
+        ref = {c: np.sqrt(v) for c, v in ref.items()}
+        self.upper = {}          # i -> {j: U_ij}, j at or after i
+        self.piv = {}            # i -> LU of D_i = U_ii
+        above = {c: [] for c in order}   # j -> rows k before j with U_kj kept
+        self.dropped = 0
+        self.kept_fill = 0
+        for i in order:
+            w = {j: sp.s_blocks[(i, j)].copy() for j in upat[i]}
+            for k in sorted(above[i], key=lambda u: pos[u]):
+                zki = sla.lu_solve(self.piv[k], self.upper[k][i])      # D_k^{-1} U_ki
+                for j, ukj in self.upper[k].items():
+                    if pos[j] < pos[i]:
+                        continue
+                    upd = zki.T @ ukj
+                    w[j] = w[j] - upd if j in w else -upd
+            up = {}
+            for j, blk in w.items():
+                if j != i and j not in upat[i]:
+                    if np.linalg.norm(blk) < tau * ref[i]:
+                        self.dropped += 1
+                        continue
+                    self.kept_fill += 1
+                up[j] = blk
+            self.piv[i] = sla.lu_factor(up[i])
+            self.upper[i] = up
+            for j in up:
+                if j != i:
+                    above[j].append(i)
+
+    def solve(self, r_s: np.ndarray) -> np.ndarray:
+        """(U^T D^{-1} U)^{-1} r for r in S order (n, nrhs)."""
+        sp = self.sp
+        r = r_s.reshape(sp.n, -1)
+
+        def rows_of(c):
+            return slice(sp.soff[c], sp.soff[c] + sp.nonbasis[c])
+
+        z = r.copy()
+        for k in self.order:                       # z = L^{-1} r
+            dz = sla.lu_solve(self.piv[k], z[rows_of(k)])
+            for j, ukj in self.upper[k].items():
+                if j != k:
+                    z[rows_of(j)] -= ukj.T @ dz
+        x = np.zeros_like(r)
+        for i in reversed(self.order):             # x = D^{-1} L^{-T}-part
+            acc = z[rows_of(i)].copy()
+            for j, uij in self.upper[i].items():
+                if j != i:
+                    acc -= uij @ x[rows_of(j)]
+            x[rows_of(i)] = sla.lu_solve(self.piv[i], acc)
+        return x.reshape(r_s.shape)
+
+
 def gmres(matvec, b: np.ndarray, precond=None, tol: float = 1e-10, restart: int = 50,
           max_iter: int = 500):
     """Right-preconditioned restarted GMRES, column by column.

@@ -21,6 +21,7 @@ HEADER = os.path.join(HERE, "..", "include", "h2sp.h")
 H2_OK, H2_EINVAL, H2_ENOMEM, H2_EDEVICE, H2_ESINGULAR, H2_ENOCONV, H2_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 H2_KERNEL_INVDIST = 0
 H2_KERNEL_EXP = 1
+H2_KERNEL_IFMM = 2
 H2_FP64, H2_MIXED = 0, 1
 H2_FACTOR_EXACT, H2_FACTOR_ILU0 = 0, 1
 H2_SOLVE_AUTO, H2_SOLVE_REFINE, H2_SOLVE_GMRES = 0, 1, 2
@@ -36,7 +37,8 @@ class H2Error(RuntimeError):
 
 
 class h2_kernel(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("scale", ctypes.c_double), ("diag", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int), ("scale", ctypes.c_double), ("diag", ctypes.c_double),
+                ("param", ctypes.c_double)]
 
 
 class h2_build_opts(ctypes.Structure):
@@ -179,11 +181,11 @@ def _opts(leaf, cheb, tol, rank_cap, eta):
 
 def h2_build(points: np.ndarray, scale: float, diag: float = 1.0, leaf: int = 32, cheb: int = 4,
              tol: float = 0.0, rank_cap: int = 0, eta: float = 1.0,
-             kernel: int = H2_KERNEL_INVDIST) -> H2MatrixHandle:
+             kernel: int = H2_KERNEL_INVDIST, param: float = 0.0) -> H2MatrixHandle:
     pts = np.ascontiguousarray(points, dtype=np.float64)
     _use_torch_stream()
     out = _P()
-    k = h2_kernel(int(kernel), float(scale), float(diag))
+    k = h2_kernel(int(kernel), float(scale), float(diag), float(param))
     o = _opts(leaf, cheb, tol, rank_cap, eta)
     _check(lib().h2_build(_dptr(pts), pts.shape[0], pts.shape[1], ctypes.byref(k), ctypes.byref(o),
                           ctypes.byref(out)))
@@ -192,14 +194,14 @@ def h2_build(points: np.ndarray, scale: float, diag: float = 1.0, leaf: int = 32
 
 def h2_import(points: np.ndarray, scale: float, diag: float, leaf: int, cheb: int, eta: float,
               rank: np.ndarray, nodes: np.ndarray, proj: np.ndarray, leaf_basis: np.ndarray,
-              transfer: np.ndarray, kernel: int = H2_KERNEL_INVDIST) -> H2MatrixHandle:
+              transfer: np.ndarray, kernel: int = H2_KERNEL_INVDIST, param: float = 0.0) -> H2MatrixHandle:
     pts = np.ascontiguousarray(points, dtype=np.float64)
     rank = np.ascontiguousarray(rank, dtype=np.int32)
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (nodes, proj, leaf_basis, transfer)]
     arrs = [a if a.size else np.zeros(1) for a in arrs]
     _use_torch_stream()
     out = _P()
-    k = h2_kernel(int(kernel), float(scale), float(diag))
+    k = h2_kernel(int(kernel), float(scale), float(diag), float(param))
     o = _opts(leaf, cheb, 0.0, 0, eta)
     _check(lib().h2_import(_dptr(pts), pts.shape[0], pts.shape[1], ctypes.byref(k), ctypes.byref(o),
                            rank.ctypes.data_as(_I32P), *[_dptr(a) for a in arrs], ctypes.byref(out)))

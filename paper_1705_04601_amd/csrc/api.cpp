@@ -252,7 +252,8 @@ extern "C" int h2_sparsify_batch(h2_matrix* const* hs, int count, const h2_spars
   }
   // the merged sweep generates every instance's close blocks in one launch
   for (int i = 1; i < count; ++i)
-    if (hs[i]->kern != hs[0]->kern) fail(H2_EUNSUPPORTED, "batched sparsification of matrices of different kernels");
+    if (hs[i]->kern != hs[0]->kern || hs[i]->kparam != hs[0]->kparam)
+      fail(H2_EUNSUPPORTED, "batched sparsification of matrices of different kernels");
   const int prec = opts ? opts->precision : H2_FP64;
   if (prec != H2_FP64 && prec != H2_MIXED) fail(H2_EINVAL, "unknown precision");
   std::vector<std::unique_ptr<h2_sparse>> own(count);

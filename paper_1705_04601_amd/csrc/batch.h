@@ -171,12 +171,13 @@ struct GemmBatch {
     std::vector<int32_t>().swap(tiles);
   }
   // Parameters of generated operands (kernel kind, as GemmItem::gkern) for every item.
-  void set_generator(int dim, int kern, double scale, double diag) {
+  void set_generator(int dim, int kern, double scale, double diag, double param) {
     for (GemmItem& it : items) {
       it.gkern = uint8_t(kern);
       it.gdim = dim;
       it.gscale = scale;
       it.gdiag = diag;
+      it.gparam = param;
     }
   }
   // Appends another batch's items and segments (same mode and role).

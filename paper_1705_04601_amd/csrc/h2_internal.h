@@ -158,6 +158,7 @@ struct h2_matrix {
   std::vector<double> x_tree;     // points in tree order (n * dim)
   double scale = 0, diag = 0;
   int kern = H2_KERNEL_INVDIST;   // h2_kernel::kind
+  double kparam = 0;              // h2_kernel::param (d of H2_KERNEL_IFMM)
   int cheb = 0, P = 0;            // nodes per axis, nodes per cluster
   bool identity_proj = false;     // P_t = I (no recompression)
   std::vector<int32_t> rank;      // r_t

@@ -1,4 +1,5 @@
-// Construction of the H^2 matrix of c/|x - y| or c exp(-|x - y|^2) (the input of the method,
+// Construction of the H^2 matrix of c/|x - y|, c exp(-|x - y|^2) or the kernel of Example 4
+// (c r / d below d, c d / r from d on; Section 5.5) (the input of the method,
 // Definition 4.8; the paper takes it as given and cites H^2 compression for
 // orthogonal nested bases in Section 4.2).
 //
@@ -227,7 +228,7 @@ Mat lagrange(const double* lo, const double* hi, int dim, int p, const double* p
   return out;
 }
 
-Mat kernel_at_nodes(const double* xr, const double* xc, int P, int dim, int kern, double scale) {
+Mat kernel_at_nodes(const double* xr, const double* xc, int P, int dim, int kern, double scale, double param) {
   Mat k(P, P);
   for (int j = 0; j < P; ++j)
     for (int i = 0; i < P; ++i) {
@@ -236,7 +237,14 @@ Mat kernel_at_nodes(const double* xr, const double* xc, int P, int dim, int kern
         const double d = xr[i * dim + a] - xc[j * dim + a];
         d2 += d * d;
       }
-      k(i, j) = kern == H2_KERNEL_EXP ? scale * std::exp(-d2) : scale / std::sqrt(d2);
+      if (kern == H2_KERNEL_EXP) {
+        k(i, j) = scale * std::exp(-d2);
+      } else if (kern == H2_KERNEL_IFMM) {
+        const double r = std::sqrt(d2);  // Example 4: r / d below d, d / r from d on
+        k(i, j) = r < param ? scale * (r / param) : scale * (param / r);
+      } else {
+        k(i, j) = scale / std::sqrt(d2);
+      }
     }
   return k;
 }
@@ -253,6 +261,7 @@ void fill_structure(h2_matrix& H, const double* pts, i64 n, int dim, const h2_ke
     for (int a = 0; a < dim; ++a) H.x_tree[i * dim + a] = pts[H.tree.perm[i] * dim + a];
   H.scale = kern.scale;
   H.kern = kern.kind;
+  H.kparam = kern.kind == H2_KERNEL_IFMM ? kern.param : 0.0;
   H.diag = kern.diag;
   H.cheb = o.cheb;
   H.P = 1;
@@ -363,7 +372,7 @@ void build_chebyshev(h2_matrix& H, double tol, int rank_cap) {
         Mat Ft(cols, q);  // F_t^T, stacked
         int off = 0;
         for (int32_t s : farOf[c]) {
-          Mat K = kernel_at_nodes(node_ptr(c), node_ptr(s), P, dim, H.kern, H.scale);
+          Mat K = kernel_at_nodes(node_ptr(c), node_ptr(s), P, dim, H.kern, H.scale, H.kparam);
           Mat D = mul(mul(Z[c], false, K, false), false, Z[s], true);  // q x q_s
           for (int j = 0; j < q; ++j)
             for (int i = 0; i < D.n; ++i) Ft(off + i, j) = D(j, i);

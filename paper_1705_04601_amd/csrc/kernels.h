@@ -14,8 +14,9 @@ namespace h2 {
 // gen = 1: A is generated, A(i, k) = kernel(pr_i, pc_k) with pr = (const
 // double*) A and pc the points along K (dim-strided); gen = 2: B is generated
 // the same way, B(k, j) = kernel(pr_j, pc_k) with pr = (const double*) B
-// (the kernel is symmetric).  kernel(x, y) = scale / |x - y| (gkern 0) or
-// scale exp(-|x - y|^2) (gkern 1).  diag = 1 puts the diagonal value where the two
+// (the kernel is symmetric).  kernel(x, y) = scale / |x - y| (gkern 0),
+// scale exp(-|x - y|^2) (gkern 1), or with r = |x - y| scale r / d below d and
+// scale d / r from d on (gkern 2, d = gparam).  diag = 1 puts the diagonal value where the two
 // indices are equal (a cluster against itself).  scale, the diagonal value
 // and dim belong to the item (so that items of different matrices can share
 // a launch).
@@ -38,9 +39,10 @@ struct GemmItem {
   void* out[5];
   int32_t ld[5];
   uint8_t trans[5];
-  uint8_t gkern;           // generated operands: 0 inverse distance, 1 exp(-r^2)
+  uint8_t gkern;           // generated operands: 0 inverse distance, 1 exp(-r^2), 2 r/d | d/r
   int32_t gdim;            // generated operands: point dimension
   double gscale, gdiag;    // generated operands: kernel scale, diagonal value
+  double gparam;           // generated operands: d of kernel 2
 };
 
 enum GemmMode { GEMM_STORE = 0, GEMM_ADD = 1, GEMM_SUB = 2 };
@@ -173,7 +175,7 @@ struct KernelBlock {
   int32_t diag_blk, pad;
 };
 void launch_kernel_blocks(const KernelBlock* blocks, int count, const double* x, int dim, int kern,
-                          double scale, double diag, double* out, hipStream_t st);
+                          double scale, double diag, double param, double* out, hipStream_t st);
 
 // Scratch of the entry point that allocates nothing (h2_apply_inverse_noalloc):
 // one static device array of kNoAllocScratchBytes per GPU, held until the

@@ -159,8 +159,24 @@ __device__ __forceinline__ void fetch4(const T* p, int64_t ld, int row, int k, i
   }
 }
 
-// Generated operand block for the four k of this lane: scale / |x_row - y_k|
-// (KERN 0) or scale exp(-|x_row - y_k|^2) (KERN 1), dg on the diagonal, from
+// Off-diagonal kernel value at squared distance d2: scale / r (KERN 0),
+// scale exp(-r^2) (KERN 1), scale r / d below d and scale d / r from d on
+// (KERN 2, Example 4 of Section 5.5, d = param).  Generated GEMM operands and
+// kernel_blocks_kernel both form their values here.
+template <int KERN>
+__device__ __forceinline__ double kernel_value(double d2, double scale, double param) {
+  if constexpr (KERN == 0) {
+    return scale * inv_sqrt(d2);
+  } else if constexpr (KERN == 1) {
+    return scale * exp(-d2);
+  } else {
+    const double r = sqrt(d2);
+    return r < param ? scale * (r / param) : scale * (param / r);
+  }
+}
+
+// Generated operand block for the four k of this lane: the kernel of KERN
+// (kernel_value) at x_row - y_k, dg on the diagonal, from
 // the row's point, held in registers for the whole
 // segment, and the chunk's four source points, loaded once per chunk and
 // shared by every block of the tile.  Coordinates past dim are zero on both
@@ -168,7 +184,7 @@ __device__ __forceinline__ void fetch4(const T* p, int64_t ld, int row, int k, i
 // forms the same values).
 template <class T, int KERN>
 __device__ __forceinline__ void gen4(const double (&prow)[3], const double (&pcol)[4][3], int row, int k, int K,
-                                     bool ok, int dim, double scale, double dg, bool diag, T* v) {
+                                     bool ok, int dim, double scale, double dg, double param, bool diag, T* v) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     T val = T(0);
@@ -183,7 +199,7 @@ __device__ __forceinline__ void gen4(const double (&prow)[3], const double (&pco
             const double d = prow[a] - pcol[s][a];
             d2 += d * d;
           }
-        val = T(KERN == 0 ? scale * inv_sqrt(d2) : scale * exp(-d2));
+        val = T(kernel_value<KERN>(d2, scale, param));
       }
     }
     v[s] = val;
@@ -194,7 +210,7 @@ __device__ __forceinline__ void gen4(const double (&prow)[3], const double (&pco
 template <class T, int AM, int BM, int MB, int NB, int KERN>
 __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[MB][NB], int nbm, int nbn,
                                                const GemmSeg& sg, int m0, int n0, int M, int N, int lane,
-                                               int dim, double scale, double dg) {
+                                               int dim, double scale, double dg, double param) {
   const int r = lane % 16, kq = 4 * (lane / 16);
   const T* A = static_cast<const T*>(sg.A);
   const T* B = static_cast<const T*>(sg.B);
@@ -245,13 +261,13 @@ __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[MB][NB
 #pragma unroll
     for (int b = 0; b < MB; ++b)
       if (b < nbm) {
-        if constexpr (AM == 2) gen4<T, KERN>(prA[b], pcol, ra[b], k, K, oa[b], dim, scale, dg, sg.diag, a[b]);
+        if constexpr (AM == 2) gen4<T, KERN>(prA[b], pcol, ra[b], k, K, oa[b], dim, scale, dg, param, sg.diag, a[b]);
         else fetch4<T, AM>(pa[b], sg.lda, ra[b], k, K, oa[b], a[b]);
       }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
       if (b < nbn) {
-        if constexpr (BM == 2) gen4<T, KERN>(prB[b], pcol, cb[b], k, K, ob[b], dim, scale, dg, sg.diag, bv[b]);
+        if constexpr (BM == 2) gen4<T, KERN>(prB[b], pcol, cb[b], k, K, ob[b], dim, scale, dg, param, sg.diag, bv[b]);
         else fetch4<T, BM>(pb[b], sg.ldb, cb[b], k, K, ob[b], bv[b]);
       }
 #pragma unroll
@@ -285,7 +301,8 @@ __global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
     for (int b = 0; b < NB; ++b) acc[a][b] = V{0, 0, 0, 0};
   for (int si = it.seg_begin; si < it.seg_end; ++si) {
     const GemmSeg sg = g.segs[si];
-    direct_segment<T, AM, BM, MB, NB, KERN>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag);
+    direct_segment<T, AM, BM, MB, NB, KERN>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag,
+                                            it.gparam);
   }
 #pragma unroll
   for (int bm = 0; bm < MB; ++bm)
@@ -1020,6 +1037,10 @@ static void launch_kc(const GemmLaunch& g, hipStream_t st) {
       hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB, 1>), dim3(g.ntiles), dim3(64), 0, st, g);
       return;
     }
+    if (g.kern == 2) {
+      hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB, 2>), dim3(g.ntiles), dim3(64), 0, st, g);
+      return;
+    }
   }
   hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB, 0>), dim3(g.ntiles), dim3(64), 0, st, g);
 }
@@ -1171,7 +1192,8 @@ void launch_add_scaled_f_rm(const float* in, const double* cs, double* acc, int6
 // One work-group per block, threads along the block's elements (k fastest).
 // The value is formed exactly as gen4 forms a generated B element.
 __global__ __launch_bounds__(256) void kernel_blocks_kernel(const KernelBlock* blocks, const double* x, int dim,
-                                                          int kern, double scale, double diag, double* out) {
+                                                          int kern, double scale, double diag, double param,
+                                                          double* out) {
   const KernelBlock b = blocks[blockIdx.x];
   const int64_t len = int64_t(b.nt) * b.ns;
   const double* pr = x + int64_t(b.t0) * dim;
@@ -1187,16 +1209,19 @@ __global__ __launch_bounds__(256) void kernel_blocks_kernel(const KernelBlock* b
         const double d = pr[j * dim + a] - pc[k * dim + a];
         d2 += d * d;
       }
-      val = kern == 0 ? scale * inv_sqrt(d2) : scale * exp(-d2);
+      val = kern == 0   ? kernel_value<0>(d2, scale, param)
+            : kern == 1 ? kernel_value<1>(d2, scale, param)
+                        : kernel_value<2>(d2, scale, param);
     }
     out[b.off + e] = val;
   }
 }
 
 void launch_kernel_blocks(const KernelBlock* blocks, int count, const double* x, int dim, int kern,
-                          double scale, double diag, double* out, hipStream_t st) {
+                          double scale, double diag, double param, double* out, hipStream_t st) {
   if (count > 0)
-    hipLaunchKernelGGL(kernel_blocks_kernel, dim3(count), dim3(256), 0, st, blocks, x, dim, kern, scale, diag, out);
+    hipLaunchKernelGGL(kernel_blocks_kernel, dim3(count), dim3(256), 0, st, blocks, x, dim, kern, scale, diag, param,
+                       out);
 }
 
 void launch_fill(double* p, int64_t n, double v, hipStream_t st) {

@@ -21,8 +21,11 @@ static void validate(const double* pts, i64 n, int dim, const h2_kernel* kernel,
   if (!pts || !kernel || !o) fail(H2_EINVAL, "null argument");
   if (n < 1) fail(H2_EINVAL, "n must be >= 1");
   if (dim != 2 && dim != 3) fail(H2_EINVAL, "dim must be 2 or 3");
-  if (kernel->kind != H2_KERNEL_INVDIST && kernel->kind != H2_KERNEL_EXP) fail(H2_EUNSUPPORTED, "unknown kernel kind");
+  if (kernel->kind != H2_KERNEL_INVDIST && kernel->kind != H2_KERNEL_EXP && kernel->kind != H2_KERNEL_IFMM)
+    fail(H2_EUNSUPPORTED, "unknown kernel kind");
   if (!std::isfinite(kernel->scale) || !std::isfinite(kernel->diag)) fail(H2_EINVAL, "kernel constants not finite");
+  if (kernel->kind == H2_KERNEL_IFMM && !(kernel->param > 0.0 && std::isfinite(kernel->param)))
+    fail(H2_EINVAL, "H2_KERNEL_IFMM needs a finite param d > 0");
   if (o->leaf < 2 || o->leaf > 128) fail(H2_EINVAL, "leaf must be in [2, 128]");
   if (o->cheb < 2 || o->cheb > 8) fail(H2_EINVAL, "cheb must be in [2, 8]");
   int P = 1;
@@ -152,7 +155,8 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
   if (resident) {
     p.close_blocks.reset(sizeof(double) * std::max<i64>(kb_entries, 1));
     DeviceBuffer dkb = upload(kb);
-    launch_kernel_blocks(dkb.as<KernelBlock>(), int(kb.size()), X, dim, H.kern, H.scale, H.diag, p.close_blocks.as<double>(),
+    launch_kernel_blocks(dkb.as<KernelBlock>(), int(kb.size()), X, dim, H.kern, H.scale, H.diag, H.kparam,
+                         p.close_blocks.as<double>(),
                          current_stream());
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(current_stream()));
@@ -237,7 +241,7 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
   for (auto& g : p.down) all.push_back(&g);
   for (GemmBatch* g : all) {
     g->role = ROLE_MATVEC;
-    g->set_generator(dim, H.kern, H.scale, H.diag);
+    g->set_generator(dim, H.kern, H.scale, H.diag, H.kparam);
   }
   upload_batches(all, p.desc);
   return mp;

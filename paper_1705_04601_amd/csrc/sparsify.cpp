@@ -651,7 +651,7 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
     blobs.push_back({lv.qr.items.data(), lv.qr.items.size() * sizeof(QrItem),
                      reinterpret_cast<const void**>(&lv.qr.d_items)});
   }
-  for (GemmBatch* g : all) g->set_generator(dim, H->kern, H->scale, H->diag);
+  for (GemmBatch* g : all) g->set_generator(dim, H->kern, H->scale, H->diag, H->kparam);
   tt.lap("work-lists");
   HIPCHECK(hipStreamSynchronize(current_stream()));
   if (!upload) return spp.release();  // a batched sweep merges and uploads the lists

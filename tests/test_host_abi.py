@@ -102,3 +102,24 @@ def test_null_handles_are_rejected():
     lib.h2_matrix_destroy(None)
     lib.h2_sparse_destroy(None)
     lib.h2_factor_destroy(None)
+
+
+@pytest.mark.parametrize("d", [1e-3, 1e-2])
+def test_ifmm_kernel_tree_and_ranks_match_oracle(d):
+    """The Example 4 kernel of Section 5.5 through the library's host
+    construction: permutation and recompressed ranks equal the oracle's."""
+    import h2inputs
+    import oracle
+    x = h2inputs.points("cube", 1500, 41)
+    h2 = oracle.build_h2(x, 32, 4, 1.0, 1.0, 1e-3, 64, 1.0, (oracle.IFMM, d))
+    h = P.h2_build(x, 1.0, 1.0, 32, 4, 1e-3, 64, 1.0, kernel=P.H2_KERNEL_IFMM, param=d)
+    perm, rank = P.h2_matrix_export_tree(h, 1500)
+    assert np.array_equal(perm, h2.tree.perm)
+    assert np.array_equal(rank, h2.rank)
+
+
+def test_ifmm_kernel_needs_a_positive_d():
+    x = np.random.default_rng(0).random((100, 3))
+    with pytest.raises(P.H2Error) as e:
+        P.h2_build(x, 1.0, 1.0, 32, 3, kernel=P.H2_KERNEL_IFMM, param=0.0)
+    assert e.value.code == P.H2_EINVAL
