@@ -75,10 +75,20 @@ typedef struct {
 } h2_sparsify_opts;
 
 enum { H2_FACTOR_EXACT = 0,     /* block LU of S with its fill (exact up to rounding) */
-       H2_FACTOR_ILU0 = 1 };    /* block ILU(0): S's own pattern, no fill (default)  */
+       H2_FACTOR_ILU0 = 1,      /* block ILU(0): S's own pattern, no fill (default)  */
+       H2_FACTOR_ILUT = 2 };    /* block threshold ILU with drop tolerance tau (the
+                                   ILUt of Section 5.5, read for a symmetric S):
+                                   over the fill of the exact mode, a fill block
+                                   (i, j) above the diagonal is set to zero once
+                                   row i is finished if its Frobenius norm is below
+                                   tau times that of block row i of S (both
+                                   triangles, as given); its mirror below the
+                                   diagonal goes with it.  tau = 0 is the exact
+                                   factor, tau = inf block ILU(0)                   */
 
 typedef struct {
-  int mode;              /* H2_FACTOR_EXACT or H2_FACTOR_ILU0                    */
+  int mode;              /* H2_FACTOR_EXACT, H2_FACTOR_ILU0 or H2_FACTOR_ILUT    */
+  double tau;            /* drop tolerance of H2_FACTOR_ILUT (>= 0, inf allowed)  */
 } h2_factor_opts;
 
 enum { H2_SOLVE_AUTO = 0,       /* iterative refinement; when its contraction stalls
@@ -317,7 +327,9 @@ int h2_last_timings(double* ms, int count);
  * factorisation, [9] = stored S entries the factorisation worked on (after
  * the fill in exact mode), [10] / [11], [12] / [13], [14] / [15] flops and
  * launches of the Schur kernels of tile classes 0, 1, 2 (as in
- * h2_last_timings [8..10]).  count may be up to 16. */
+ * h2_last_timings [8..10]), [16] / [17] fill blocks dropped / kept by
+ * H2_FACTOR_ILUT (fill blocks that no update reached, zero throughout, are
+ * counted in neither).  count may be up to 20. */
 int h2_last_work(double* work, int count);
 
 /* Environment variables read by the library (tuning and diagnostics only; the

@@ -23,7 +23,7 @@ H2_KERNEL_INVDIST = 0
 H2_KERNEL_EXP = 1
 H2_KERNEL_IFMM = 2
 H2_FP64, H2_MIXED = 0, 1
-H2_FACTOR_EXACT, H2_FACTOR_ILU0 = 0, 1
+H2_FACTOR_EXACT, H2_FACTOR_ILU0, H2_FACTOR_ILUT = 0, 1, 2
 H2_SOLVE_AUTO, H2_SOLVE_REFINE, H2_SOLVE_GMRES = 0, 1, 2
 
 _NAMES = {0: "H2_OK", -1: "H2_EINVAL", -2: "H2_ENOMEM", -3: "H2_EDEVICE", -4: "H2_ESINGULAR",
@@ -51,7 +51,7 @@ class h2_sparsify_opts(ctypes.Structure):
 
 
 class h2_factor_opts(ctypes.Structure):
-    _fields_ = [("mode", ctypes.c_int)]
+    _fields_ = [("mode", ctypes.c_int), ("tau", ctypes.c_double)]
 
 
 class h2_solve_opts(ctypes.Structure):
@@ -282,10 +282,10 @@ def h2_sparse_export_q(sp: H2SparseHandle, t: int, n: int) -> np.ndarray:
     return out.reshape(n, n).T
 
 
-def h2_factor_S(sp: H2SparseHandle, mode: int = H2_FACTOR_ILU0) -> H2FactorHandle:
+def h2_factor_S(sp: H2SparseHandle, mode: int = H2_FACTOR_ILU0, tau: float = 0.0) -> H2FactorHandle:
     _use_torch_stream()
     out = _P()
-    o = h2_factor_opts(int(mode))
+    o = h2_factor_opts(int(mode), float(tau))
     _check(lib().h2_factor_S(sp.ptr, ctypes.byref(o), ctypes.byref(out)))
     return H2FactorHandle(out.value, keep=sp)
 
@@ -304,10 +304,10 @@ def h2_sparsify_batch(hs, precision: int = H2_FP64):
     return [H2SparseHandle(outs[i], keep=h) for i, h in enumerate(hs)]
 
 
-def h2_factor_S_batch(sps, mode: int = H2_FACTOR_ILU0):
+def h2_factor_S_batch(sps, mode: int = H2_FACTOR_ILU0, tau: float = 0.0):
     _use_torch_stream()
     outs = (_P * len(sps))()
-    o = h2_factor_opts(int(mode))
+    o = h2_factor_opts(int(mode), float(tau))
     _check(lib().h2_factor_S_batch(_handles(sps), len(sps), ctypes.byref(o), outs))
     return [H2FactorHandle(outs[i], keep=sp) for i, sp in enumerate(sps)]
 
@@ -396,6 +396,6 @@ def h2_last_timings():
 
 
 def h2_last_work():
-    out = np.zeros(16)
-    _check(lib().h2_last_work(_dptr(out), 16))
+    out = np.zeros(20)
+    _check(lib().h2_last_work(_dptr(out), 20))
     return out

@@ -12,7 +12,7 @@
 #include "factor.h"
 
 namespace h2 {
-h2_factor* factor(h2_sparse* sp, bool exact, hipStream_t st, double* phase_ms);
+h2_factor* factor(h2_sparse* sp, int mode, double tau, hipStream_t st, double* phase_ms);
 void analyze_fill(const h2_sparse& sp, double* entries, double* flops);
 void set_stream(hipStream_t s);
 std::string& last_error() {
@@ -20,7 +20,7 @@ std::string& last_error() {
   return msg;
 }
 static thread_local double g_timings[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-static thread_local double g_work[16] = {0};
+static thread_local double g_work[20] = {0};
 }  // namespace h2
 
 int apply_inverse_impl(h2_factor* f, const double* b, double* x, h2::i64 nrhs, h2::i64 ld);
@@ -133,7 +133,7 @@ extern "C" int h2_sparsify(h2_matrix* h, const h2_sparsify_opts* opts, h2_sparse
   if (prec != H2_FP64 && prec != H2_MIXED) fail(H2_EINVAL, "unknown precision");
   std::unique_ptr<h2_sparse> sp(plan_sparsify(h, prec, true));
   std::fill(g_timings, g_timings + 12, 0.0);
-  std::fill(g_work, g_work + 16, 0.0);
+  std::fill(g_work, g_work + 20, 0.0);
   run_sparsify(*sp, current_stream(), g_timings);
   HIPCHECK(hipStreamSynchronize(current_stream()));
   finish_sparsify(*sp);
@@ -206,11 +206,14 @@ extern "C" int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor*
   if (!sp || !out) fail(H2_EINVAL, "null argument");
   *out = nullptr;
   const int mode = opts ? opts->mode : H2_FACTOR_ILU0;
-  if (mode != H2_FACTOR_EXACT && mode != H2_FACTOR_ILU0) fail(H2_EINVAL, "unknown factorisation mode");
+  const double tau = opts ? opts->tau : 0.0;
+  if (mode != H2_FACTOR_EXACT && mode != H2_FACTOR_ILU0 && mode != H2_FACTOR_ILUT)
+    fail(H2_EINVAL, "unknown factorisation mode");
+  if (mode == H2_FACTOR_ILUT && !(tau >= 0.0)) fail(H2_EINVAL, "ILUt drop tolerance must be >= 0");
   if (sp->factored) fail(H2_EINVAL, "S of this sparse handle is already factored");
   for (int i = 4; i < 12; ++i) g_timings[i] = 0;
   double ph[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  std::unique_ptr<h2_factor> f(factor(sp, mode == H2_FACTOR_EXACT, current_stream(), ph));
+  std::unique_ptr<h2_factor> f(factor(sp, mode, tau, current_stream(), ph));
   g_timings[4] = ph[4];
   g_timings[5] = ph[5];
   g_timings[7] = ph[6];
@@ -224,6 +227,8 @@ extern "C" int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor*
     g_work[10 + 2 * c] = f->flops_cls[c];
     g_work[11 + 2 * c] = double(f->launches_cls[c]);
   }
+  g_work[16] = double(f->ilut_dropped);
+  g_work[17] = double(f->ilut_kept);
   *out = f.release();
   H2_API_END
 }
@@ -262,7 +267,7 @@ extern "C" int h2_sparsify_batch(h2_matrix* const* hs, int count, const h2_spars
   run_pooled(count, [&](int i) { own[i].reset(plan_sparsify(hs[i], prec, false)); });
   for (int i = 0; i < count; ++i) sps[i] = own[i].get();
   std::fill(g_timings, g_timings + 12, 0.0);
-  std::fill(g_work, g_work + 16, 0.0);
+  std::fill(g_work, g_work + 20, 0.0);
   run_sparsify_batch(sps, current_stream(), g_timings);
   HIPCHECK(hipStreamSynchronize(current_stream()));
   for (int i = 0; i < count; ++i) {
@@ -276,7 +281,10 @@ extern "C" int h2_factor_S_batch(h2_sparse* const* sps, int count, const h2_fact
   H2_API_BEGIN
   if (!sps || !outs || count < 1) fail(H2_EINVAL, "null argument or empty batch");
   const int mode = opts ? opts->mode : H2_FACTOR_ILU0;
-  if (mode != H2_FACTOR_EXACT && mode != H2_FACTOR_ILU0) fail(H2_EINVAL, "unknown factorisation mode");
+  const double tau = opts ? opts->tau : 0.0;
+  if (mode != H2_FACTOR_EXACT && mode != H2_FACTOR_ILU0 && mode != H2_FACTOR_ILUT)
+    fail(H2_EINVAL, "unknown factorisation mode");
+  if (mode == H2_FACTOR_ILUT && !(tau >= 0.0)) fail(H2_EINVAL, "ILUt drop tolerance must be >= 0");
   for (int i = 0; i < count; ++i) {
     if (!sps[i]) fail(H2_EINVAL, "null sparse handle in the batch");
     if (sps[i]->factored) fail(H2_EINVAL, "S of a sparse handle in the batch is already factored");
@@ -287,10 +295,10 @@ extern "C" int h2_factor_S_batch(h2_sparse* const* sps, int count, const h2_fact
   std::vector<std::unique_ptr<h2_factor>> fs(count);
   std::vector<double> ph(size_t(count) * 10, 0.0);
   run_pooled(count, [&](int i) {
-    fs[i].reset(factor(sps[i], mode == H2_FACTOR_EXACT, current_stream(), &ph[size_t(i) * 10]));
+    fs[i].reset(factor(sps[i], mode, tau, current_stream(), &ph[size_t(i) * 10]));
   });
   std::fill(g_timings + 4, g_timings + 12, 0.0);
-  std::fill(g_work + 4, g_work + 16, 0.0);
+  std::fill(g_work + 4, g_work + 20, 0.0);
   for (int i = 0; i < count; ++i) {
     g_timings[4] += ph[size_t(i) * 10 + 4];
     g_timings[5] += ph[size_t(i) * 10 + 5];
@@ -304,6 +312,8 @@ extern "C" int h2_factor_S_batch(h2_sparse* const* sps, int count, const h2_fact
       g_work[10 + 2 * c] += fs[i]->flops_cls[c];
       g_work[11 + 2 * c] += double(fs[i]->launches_cls[c]);
     }
+    g_work[16] += double(fs[i]->ilut_dropped);
+    g_work[17] += double(fs[i]->ilut_kept);
   }
   for (int i = 0; i < count; ++i) outs[i] = fs[i].release();
   H2_API_END
@@ -382,7 +392,7 @@ extern "C" int h2_last_timings(double* ms, int count) {
 extern "C" int h2_last_work(double* work, int count) {
   H2_API_BEGIN
   if (!work) fail(H2_EINVAL, "null argument");
-  for (int i = 0; i < count && i < 16; ++i) work[i] = g_work[i];
+  for (int i = 0; i < count && i < 20; ++i) work[i] = g_work[i];
   H2_API_END
 }
 

@@ -48,6 +48,7 @@ struct FactorLevel {
   std::vector<InvItem<T>> inv;
   std::vector<CopySeg> cps;                 // Z_ki into the place of S_ki (end of the level)
   std::vector<CopySeg> zts, sts;            // Z_ki into tiles; the level's rows' blocks into tiles
+  std::vector<DropItem> drops;              // ILUt: the level's rows' fill blocks and their thresholds
   std::vector<SchurItem> sitems;
   std::vector<int64_t> skeys;  // per item: tile-order key (host only)
   PodVector<SchurSeg> ssegs;
@@ -57,6 +58,7 @@ struct FactorLevel {
   const CopySeg* d_cps = nullptr;
   const CopySeg* d_zts = nullptr;
   const CopySeg* d_sts = nullptr;
+  const DropItem* d_drops = nullptr;
   const SchurItem* d_sitems = nullptr;
   const SchurSeg* d_ssegs = nullptr;
   const int32_t* d_stiles[kSchurClasses] = {nullptr, nullptr, nullptr};
@@ -159,6 +161,10 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   }
   T* St = tiled_s ? dSt.as<T>() : nullptr;
   f.schur_tiled = tiled_s;
+  // ILUt: one flag per stored block (1 = dropped), written by the drop launches
+  const bool ilut = !f.drop_thr2.empty();
+  if (ilut && sp.colidx.size() >= (size_t(1) << 31)) fail(H2_EUNSUPPORTED, "ILUt pattern above 2^31 blocks");
+  DeviceBuffer dDropFlag(ilut ? sp.colidx.size() : 0);
   // partial sums of split targets (at most pcap elements per level)
   f.pcap = std::min<i64>(i64(1) << 25, std::max<i64>(sp.s_entries, 1));
   f.dP.reset(sizeof(T) * f.pcap);
@@ -360,6 +366,12 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         z += kpad16(mk) * kpad16(mi);
       }
       zbase[q + 1] = z;
+      // the row's fill blocks are tested against their threshold once the
+      // level's update is done (ILUt)
+      if (ilut)
+        for (i64 b = sp.rowptr[pi] + 1; b < sp.rowptr[pi + 1]; ++b)
+          if (f.drop_thr2[b] >= 0.0)
+            L.drops.push_back({sp.blk_off[b], f.drop_thr2[b], int32_t(mi * mb[sp.colidx[b]]), int32_t(b)});
       // the row's blocks above the diagonal are final after this level
       if (tiled_s)
         for (i64 b = sp.rowptr[pi] + 1; b < sp.rowptr[pi + 1]; ++b)
@@ -697,6 +709,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         blobs.push_back({L.cps.data(), L.cps.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_cps)});
         blobs.push_back({L.zts.data(), L.zts.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_zts)});
         blobs.push_back({L.sts.data(), L.sts.size() * sizeof(CopySeg), reinterpret_cast<const void**>(&L.d_sts)});
+        blobs.push_back({L.drops.data(), L.drops.size() * sizeof(DropItem),
+                         reinterpret_cast<const void**>(&L.d_drops)});
         blobs.push_back({L.sitems.data(), L.sitems.size() * sizeof(SchurItem),
                          reinterpret_cast<const void**>(&L.d_sitems)});
         blobs.push_back({L.ssegs.data(), L.ssegs.size() * sizeof(SchurSeg),
@@ -727,6 +741,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         }
         mark_ev();
         launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
+        // ILUt: the rows of the level are finished; small fill blocks go to zero
+        // before anything reads them (tiled copies, Z of later levels, solves)
+        if (ilut) launch_drop_small<T>(L.d_drops, int(L.drops.size()), S, dDropFlag.as<uint8_t>(), st);
         if (tiled_s) launch_retile<T>(L.d_sts, int(L.sts.size()), S, St, st);
         launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
         launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
@@ -737,6 +754,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         std::vector<SchurReduce>().swap(L.reds);
         std::vector<CopySeg>().swap(L.zts);
         std::vector<CopySeg>().swap(L.sts);
+        std::vector<DropItem>().swap(L.drops);
       }
       next = end;
     }
@@ -785,6 +803,12 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   mark_ev();
   HIPCHECK(hipEventSynchronize(ev.back()));
   tt.lap("device-drain");
+  if (ilut) {
+    std::vector<uint8_t> flag(sp.colidx.size());
+    HIPCHECK(hipMemcpy(flag.data(), dDropFlag.ptr, flag.size(), hipMemcpyDeviceToHost));
+    for (size_t b = 0; b < flag.size(); ++b)
+      if (f.drop_thr2[b] >= 0.0 && flag[b] < 2) (flag[b] ? f.ilut_dropped : f.ilut_kept) += 1;
+  }
   double piv_ms = 0, schur_ms = 0, cls_ms[kSchurClasses] = {0, 0, 0};
   for (int lv = 0; lv < f.nflev; ++lv) {
     const hipEvent_t* e = &ev[size_t(kEv) * lv];
@@ -919,9 +943,10 @@ static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
   }
   tt.lap("symbolic");
   const size_t el = sizeof(T);
-  // old blocks -> their places in the filled layout
+  // old blocks -> their places in the filled layout; every other block is fill
   std::vector<CopySeg> cps;
   cps.reserve(sp.colidx.size());
+  std::vector<char> is_fill(colidx.size(), 1);
   for (i64 pos = 0; pos < ncl; ++pos) {
     const i64 mi = mb[sp.eorder[pos]];
     i64 nb = rowptr[pos];
@@ -930,6 +955,7 @@ static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
       while (nb < rowptr[pos + 1] && colidx[nb] != cj) ++nb;
       if (nb == rowptr[pos + 1]) fail(H2_EINVAL, "internal: fill pattern misses a block of S");
       cps.push_back({blk_off[nb], sp.blk_off[b], int32_t(mi), int32_t(mb[cj]), int32_t(mi), 0});
+      is_fill[nb] = 0;
     }
   }
   DeviceBuffer nS(el * size_t(std::max<i64>(ent, 1)));
@@ -944,6 +970,7 @@ static void extend_by_fill(h2_sparse& sp, hipStream_t st) {
   sp.rowptr.swap(rowptr);
   sp.colidx.swap(colidx);
   sp.blk_off.swap(blk_off);
+  sp.is_fill.swap(is_fill);
   sp.s_entries = ent;
   tt.lap("relayout");
 }
@@ -952,8 +979,43 @@ void analyze_fill(const h2_sparse& sp, double* entries, double* flops) {
   (void)symbolic_fill(sp, 0.0, double(sp.elem), entries, flops);
 }
 
-h2_factor* factor(h2_sparse* sp, bool exact, hipStream_t st, double* phase_ms) {
-  if (exact) {
+// Square of the ILUt drop threshold of every fill block: (tau ||S_i,:||_F)^2
+// for block row i, the norm over both triangles of S as given (before any
+// update; the fill blocks are zero then).  The block norms are taken on the
+// device.
+template <class T>
+static std::vector<double> drop_thresholds(const h2_sparse& sp, double tau, hipStream_t st) {
+  const i64 nb = i64(sp.colidx.size());
+  std::vector<BlockRef> refs(nb);
+  std::vector<i64> row_of(nb);
+  for (i64 pos = 0; pos < sp.ncl; ++pos)
+    for (i64 b = sp.rowptr[pos]; b < sp.rowptr[pos + 1]; ++b) {
+      refs[b] = {sp.blk_off[b], i64(sp.nonbasis[sp.eorder[pos]]) * sp.nonbasis[sp.colidx[b]]};
+      row_of[b] = pos;
+    }
+  DeviceBuffer drefs(sizeof(BlockRef) * std::max<i64>(nb, 1)), dsq(sizeof(double) * std::max<i64>(nb, 1));
+  HIPCHECK(hipMemcpyAsync(drefs.ptr, refs.data(), sizeof(BlockRef) * nb, hipMemcpyHostToDevice, st));
+  launch_block_sumsq<T>(drefs.as<BlockRef>(), int(nb), sp.dS.as<T>(), dsq.as<double>(), st);
+  HIPCHECK(hipGetLastError());
+  std::vector<double> sq(nb);
+  HIPCHECK(hipMemcpyAsync(sq.data(), dsq.ptr, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  std::vector<double> row2(sp.ncl, 0.0);  // by elimination position, in block order
+  for (i64 b = 0; b < nb; ++b) {
+    row2[row_of[b]] += sq[b];
+    if (b != sp.rowptr[row_of[b]]) row2[sp.epos[sp.colidx[b]]] += sq[b];  // the mirror block
+  }
+  std::vector<double> thr2(nb, -1.0);
+  for (i64 b = 0; b < nb; ++b)
+    if (sp.is_fill[b]) {
+      const double t = tau * std::sqrt(row2[row_of[b]]);
+      thr2[b] = t * t;
+    }
+  return thr2;
+}
+
+h2_factor* factor(h2_sparse* sp, int mode, double tau, hipStream_t st, double* phase_ms) {
+  if (mode == H2_FACTOR_EXACT || mode == H2_FACTOR_ILUT) {
     if (sp->precision == H2_MIXED) extend_by_fill<float>(*sp, st);
     else extend_by_fill<double>(*sp, st);
   }
@@ -993,6 +1055,8 @@ h2_factor* factor(h2_sparse* sp, bool exact, hipStream_t st, double* phase_ms) {
     f.nblev = std::max(f.nblev, l + 1);
   }
   f.dInv.reset(sp->elem * std::max<i64>(io, 1));
+  if (mode == H2_FACTOR_ILUT)
+    f.drop_thr2 = sp->precision == H2_MIXED ? drop_thresholds<float>(*sp, tau, st) : drop_thresholds<double>(*sp, tau, st);
   f.dFlag.reset(sizeof(int));
   launch_fill_i(f.dFlag.as<int>(), 1, 0, st);
   if (sp->precision == H2_MIXED) factor_levels<float>(f, st, phase_ms);

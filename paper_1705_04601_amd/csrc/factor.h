@@ -38,6 +38,10 @@ struct h2_factor {
   double flops_cls[3] = {0, 0, 0};           // Schur flops by tile class (kernel)
   h2::i64 launches_cls[3] = {0, 0, 0};       // Schur kernel launches by tile class
   bool schur_tiled = false;                  // S_kj operands read from tiled copies
+  // block threshold ILU: per stored block the square of its drop threshold
+  // (fill blocks only; empty in the other modes) and the outcome
+  std::vector<double> drop_thr2;
+  h2::i64 ilut_dropped = 0, ilut_kept = 0;
   std::unique_ptr<h2::SolvePlan> solve;
   ~h2_factor();
 };

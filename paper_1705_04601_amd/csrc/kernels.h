@@ -148,6 +148,26 @@ struct InvItem {
 template <class T>
 void launch_inverse(const InvItem<T>* items, int count, int* flag, hipStream_t st);
 
+// Block threshold ILU (drop tolerance): sums of squares of blocks of S and
+// the drop of small fill blocks.  Both reduce in FP64 in a fixed order (per
+// thread strided partial sums, then a tree over the work-group).
+struct BlockRef {
+  int64_t off;  // first element in S
+  int64_t len;  // elements
+};
+template <class T>
+void launch_block_sumsq(const BlockRef* blocks, int count, const T* S, double* out, hipStream_t st);
+// For every item: if the block's sum of squares is below thr2 the block is
+// set to zero and flag[idx] to 1, or to 2 when it was zero already (a fill
+// block that no update reached); else flag[idx] = 0.
+struct DropItem {
+  int64_t off;
+  double thr2;
+  int32_t len, idx;
+};
+template <class T>
+void launch_drop_small(const DropItem* items, int count, T* S, uint8_t* flag, hipStream_t st);
+
 // Copies a rows x cols block from src (leading dimension src_ld) to a
 // contiguous block of dst (leading dimension rows), for every segment.
 struct CopySeg {

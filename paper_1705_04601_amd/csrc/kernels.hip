@@ -998,6 +998,44 @@ __global__ __launch_bounds__(256) void retile_kernel(const CopySeg* segs, const 
   }
 }
 
+// Sum of squares of a block in FP64, the same order in every kernel that
+// calls it: thread t sums elements t, t + 256, ... then a tree over the
+// work-group (256 threads).
+template <class T>
+__device__ __forceinline__ double block_sumsq(const T* p, int64_t len, double* red) {
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < len; e += 256) {
+    const double v = double(p[e]);
+    acc += v * v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void block_sumsq_kernel(const BlockRef* blocks, const T* S, double* out) {
+  __shared__ double red[256];
+  const BlockRef b = blocks[blockIdx.x];
+  const double s = block_sumsq(S + b.off, b.len, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void drop_small_kernel(const DropItem* items, T* S, uint8_t* flag) {
+  __shared__ double red[256];
+  const DropItem it = items[blockIdx.x];
+  const double sq = block_sumsq(S + it.off, it.len, red);  // the same value in every thread
+  const bool drop = sq < it.thr2;
+  if (drop)
+    for (int64_t e = threadIdx.x; e < it.len; e += 256) S[it.off + e] = T(0);
+  if (threadIdx.x == 0) flag[it.idx] = drop ? (sq > 0.0 ? 1 : 2) : 0;
+}
+
 int grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 65536) g = 65536;
@@ -1130,6 +1168,22 @@ void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, 
     hipLaunchKernelGGL(copy_segments_kernel<T>, dim3(8, c), dim3(256), 0, st, segs + c0, src, dst);
   }
 }
+template <class T>
+void launch_block_sumsq(const BlockRef* blocks, int count, const T* S, double* out, hipStream_t st) {
+  for (int c0 = 0; c0 < count; c0 += 1 << 30) {
+    const int c = count - c0 < (1 << 30) ? count - c0 : (1 << 30);
+    hipLaunchKernelGGL(block_sumsq_kernel<T>, dim3(c), dim3(256), 0, st, blocks + c0, S, out + c0);
+  }
+}
+template void launch_block_sumsq<double>(const BlockRef*, int, const double*, double*, hipStream_t);
+template void launch_block_sumsq<float>(const BlockRef*, int, const float*, double*, hipStream_t);
+template <class T>
+void launch_drop_small(const DropItem* items, int count, T* S, uint8_t* flag, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(drop_small_kernel<T>, dim3(count), dim3(256), 0, st, items, S, flag);
+}
+template void launch_drop_small<double>(const DropItem*, int, double*, uint8_t*, hipStream_t);
+template void launch_drop_small<float>(const DropItem*, int, float*, uint8_t*, hipStream_t);
+
 template <class T>
 void launch_retile(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st) {
   for (int c0 = 0; c0 < count; c0 += 65535) {

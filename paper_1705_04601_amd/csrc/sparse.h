@@ -48,6 +48,7 @@ struct h2_sparse {
   std::vector<h2::i64> colidx;     // cluster ids (sorted by elimination position)
   std::vector<h2::i64> blk_off;    // entry offset of each stored block
   h2::i64 s_entries = 0;
+  std::vector<char> is_fill;       // per stored block: fill of the exact mode (empty before)
   bool factored = false;           // S has been overwritten by its factors
   // arenas
   std::vector<h2::i64> q_off, b_off, rhat_off, w_off;
