@@ -379,7 +379,15 @@ def main():
                 "phase_ms": {p: round(float(v), 3) for p, v in zip(PHASES, ms)},
                 "phase_tflops": {p: round(float(f / (m * 1e-3) / 1e12), 3) if m > 0 else None
                                  for p, f, m in zip(PHASES, fl, ms)},
-                "schur_kernels": schur}
+                "schur_kernels": schur,
+                # the three Schur kernels of a level run concurrently on three
+                # streams: the phase as a whole, all Schur flops over its event time
+                "schur_phase": {"ms": round(float(ms[PHASES.index("factor_schur")]), 3),
+                                "tflops": round(float(fl[PHASES.index("factor_schur")])
+                                                / (float(ms[PHASES.index("factor_schur")]) * 1e-3) / 1e12, 3),
+                                "frac": round(float(fl[PHASES.index("factor_schur")])
+                                              / (float(ms[PHASES.index("factor_schur")]) * 1e-3) / 1e12
+                                              / PEAK_TFLOPS["f32"], 4)}}
     out = {
         "metric": "factor+solve s and RHS*N/s, mixed vs FP64 plain, 1e-8 rel. residual",
         "value": nrhs * n / sec,

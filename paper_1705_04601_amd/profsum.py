@@ -9,6 +9,12 @@
       scaled by what the counter reads for the plain copy of <copy_mib> MiB
       that bench.py --copy-probe-mib runs first
 
+  python -m paper_1705_04601_amd.profsum counters <out_dir> <prefix> <kernel substring>
+      per kernel matching the substring: every counter summed over its
+      dispatches; with SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE the MFMA
+      busy fraction (busy SIMD cycles over active cycles of all 1024 SIMDs;
+      GRBM_GUI_ACTIVE is summed over the 8 XCDs, so divided by 8)
+
 Reads CSV files only; prints text.
 """
 
@@ -87,9 +93,27 @@ def traffic(fdir, fprefix, wdir, wprefix, copy_mib, kernel=SCHUR) -> None:
     print(f"sources_sha256: {h.hexdigest()}")
 
 
+def counters(out_dir: str, prefix: str, sub: str) -> None:
+    tot = {}
+    for r in csv.DictReader(open(os.path.join(out_dir, f"{prefix}_counter_collection.csv"))):
+        name = _short(r["Kernel_Name"])
+        if sub not in name:
+            continue
+        d = tot.setdefault(name, {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    for name, d in sorted(tot.items()):
+        line = ", ".join(f"{c} {v:.4g}" for c, v in sorted(d.items()))
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in d and d.get("GRBM_GUI_ACTIVE"):
+            busy = d["SQ_VALU_MFMA_BUSY_CYCLES"] / (d["GRBM_GUI_ACTIVE"] / 8 * 1024)
+            line += f"; MFMA busy {busy:.3f}"
+        print(f"{name}: {line}")
+
+
 def main(argv):
     if len(argv) >= 3 and argv[0] == "stats":
         stats(argv[1], argv[2])
+    elif len(argv) >= 4 and argv[0] == "counters":
+        counters(argv[1], argv[2], argv[3])
     elif len(argv) >= 6 and argv[0] == "traffic":
         traffic(argv[1], argv[2], argv[3], argv[4], int(argv[5]), *argv[6:7])
     else:
