@@ -431,6 +431,8 @@ def main():
     out["all_steps_converged"] = not missed
     if missed:
         out["invalid"] = f"{len(missed)} timed step(s) above the residual {args.tol:g}: {missed[:4]}"
+    # the tuning entries (tile shapes, Schur knobs) the timed work planned with
+    out["tune"] = P.h2_tune_report()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, bounded sample)")
         out["cpu_baseline"] = cpu_baseline(wl, exact=args.factor == "exact")

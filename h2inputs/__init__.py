@@ -142,7 +142,7 @@ WORKLOADS = {
                      rank_cap=48, nrhs=32, scale="1/(4piN)"),
     "cube1m": dict(kind="cube", n=1048576, seed=5, leaf=128, cheb=4, tol=1e-8,
                    rank_cap=64, nrhs=128, scale="1/(4piN)"),
-    # the exp core of Example 2: 2 delta_ij + exp(-|r_i - r_j|^2) on the unit cube
+    # the exp core of Example 5.2: 2 delta_ij + exp(-|r_i - r_j|^2) on the unit cube
     "cube64k_exp": dict(kind="cube", n=65536, seed=6, leaf=64, cheb=4, tol=1e-8,
                         rank_cap=48, nrhs=16, scale="1", kernel="exp", diag=3.0),
 }

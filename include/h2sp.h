@@ -42,12 +42,12 @@ enum {
 /* ---- options --------------------------------------------------------------- */
 enum { H2_KERNEL_INVDIST = 0,   /* A_ij = scale / |x_i - x_j| (i != j), A_ii = diag */
        H2_KERNEL_EXP = 1,       /* A_ij = scale exp(-|x_i - x_j|^2) (i != j), A_ii =
-                                   diag: Example 2 of Section 5.1 (its matrix
+                                   diag: Example 5.2 of Section 5.1 (its matrix
                                    2 delta_ij + exp(-|r_i - r_j|^2) is scale 1,
                                    diag 3).                                    */
        H2_KERNEL_IFMM = 2 };    /* A_ij = scale r / d for 0 < r < d and scale d / r
                                    for r >= d, r = |x_i - x_j|, d = param > 0,
-                                   A_ii = diag: Example 4 of Section 5.5 (scale
+                                   A_ii = diag: Example 5.4 of Section 5.5 (scale
                                    1, diag 1).  h2_sparsify_batch takes matrices
                                    of one kernel kind and parameter
                                    (H2_EUNSUPPORTED otherwise).                */
@@ -242,6 +242,24 @@ int h2_sparse_export_q(const h2_sparse* sp, int64_t t, double* out);
  */
 int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor** out);
 
+/* Host-only counts of the plan of a matrix (no device work, nothing kept):
+ * the sizes the storage study of Sections 5.1-5.2 compares.  Entries, not
+ * bytes; S and U = V as the method defines them (A = U S V^T, eq. main_fact). */
+typedef struct {
+  int64_t n, clusters, depth;
+  int64_t s_blocks;          /* blocks of the upper block triangle of S             */
+  int64_t s_entries;         /* entries of S, both triangles (the nonzeros of S)     */
+  int64_t s_upper_entries;   /* entries of the upper block triangle (stored)          */
+  int64_t q_entries;         /* entries of the orthogonal blocks Q_t that form U = V  */
+  int64_t h2_entries;        /* the H^2 matrix as given: leaf bases, transfers,
+                                couplings of the admissible pairs, close blocks       */
+  int64_t h2_close_entries;  /* of which close blocks                                 */
+  int64_t filled_entries;    /* upper triangle of the exact factor's pattern, or -1   */
+  double exact_flops;        /* flops of the exact factor's Schur updates, or -1     */
+} h2_plan_counts;
+/* with_fill = 1 also runs the symbolic fill of the exact mode (may be slow). */
+int h2_plan_report(h2_matrix* h, int with_fill, h2_plan_counts* out);
+
 /* Host-only symbolic analysis of the exact mode, before factoring: entries of
  * the filled upper block triangle of S and the flops of its Schur updates
  * (2 m_i m_j m_k per update).  Either pointer may be NULL. */
@@ -332,6 +350,52 @@ int h2_last_timings(double* ms, int count);
  * counted in neither).  count may be up to 20. */
 int h2_last_work(double* work, int count);
 
+/* ---- tuning table and autotuner ---------------------------------------------- */
+/*
+ * The tile shape of every batched GEMM kind (precision, role, operand layout,
+ * bucket of item rows) and the Schur work-list knobs come from a tuning
+ * table.  Built-in defaults apply until a JSON cache replaces them: one
+ * object per GPU architecture ("gfx950": {key: integer, ...}), read once per
+ * process from H2SP_TUNE_FILE or else tune.json beside the library (a missing
+ * default file means the defaults; a malformed one, or an entry that is not
+ * built, makes every call that plans work fail with EINVAL).  Entries change
+ * speed only, never a result bit.  Keys:
+ *   "gemm.<f32|f64>.<transform|factor|solve|matvec>.a<A>b<B>.m<R>": the tile
+ *     variant (0..3, those built for the kind) of GEMM batches whose operand
+ *     layouts are A and B and whose largest item has <= 16, 32, 64 or more
+ *     rows (R = 0..3);
+ *   "schur.split_k" (16..2^30, default 512): smallest K of a split Schur part;
+ *   "schur.key_z" (0 or 1, default 0): order Schur tiles by Z position;
+ *   "schur.order_min" (default 16384): reorder levels with at least this many
+ *     tiles.
+ * The environment variables below override the Schur knobs.  Work lists
+ * already planned are planned again after any change.  h2_tune_set replaces
+ * one entry (EINVAL for unknown keys, values out of range or variants that are
+ * not built); h2_tune_get reads an entry of the table (EINVAL when it holds
+ * none: the default applies); h2_tune_clear returns to the defaults;
+ * h2_tune_load reads the object of the current device's architecture from a
+ * file (NULL: the default path); h2_tune_save writes the table there, keeping
+ * the other architectures' objects; h2_tune_report writes JSON text
+ * {"arch", "source", "used": {key: value}} naming every entry the planned
+ * work consulted since the last load (EINVAL if len is too small).
+ *
+ * h2_autotune: on the caller's matrix, in `precision`, with nrhs right-hand
+ * sides (1..512), measures every built variant of each GEMM kind that the
+ * sparsification, the ILU(0) factorisation, the preconditioner application
+ * and the FP64 product plan, and the Schur knobs (split_k in {256, 512, 1024,
+ * 2048}, key_z in {0, 1}), one key at a time with the others fixed (device
+ * time of the phase, or the time of the synchronous call), keeps the fastest
+ * of each in the table and, with a path, saves it.  Runs each phase several
+ * times: seconds to minutes.  Uses the stream of h2_set_stream.
+ */
+int h2_tune_set(const char* key, int64_t value);
+int h2_tune_get(const char* key, int64_t* value);
+int h2_tune_clear(void);
+int h2_tune_load(const char* path);
+int h2_tune_save(const char* path);
+int h2_tune_report(char* buf, int64_t len);
+int h2_autotune(h2_matrix* h, int precision, int64_t nrhs, const char* path);
+
 /* Environment variables read by the library (tuning and diagnostics only; the
  * results do not depend on them beyond rounding order):
  *   H2SP_TRACE=1 host phase timings and statistics on stderr; =2 adds one line
@@ -350,7 +414,8 @@ int h2_last_work(double* work, int count);
  *     the memory of S and are made only when they fit);
  *   H2SP_CLOSE_RESIDENT=0: never keep the matvec's close blocks on the device;
  *   H2SP_GRAPHS=0: run the solve and matvec sweeps eagerly instead of as
- *     captured HIP graphs. */
+ *     captured HIP graphs;
+ *   H2SP_TUNE_FILE: the tuning cache to read (see h2_tune_load). */
 
 #ifdef __cplusplus
 }

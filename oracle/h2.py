@@ -43,8 +43,8 @@ IFMM = "ifmm"   # used as (IFMM, d)
 def _named_kernel(kernel, r2: np.ndarray, scale: float) -> np.ndarray:
     """Entries of a named kernel at squared distances r2 (off the diagonal).
 
-    EXP: scale exp(-r^2) (Example 2).  (IFMM, d): scale r / d for r < d and
-    scale d / r otherwise (Example 4, the test matrix of Section 5.5).
+    EXP: scale exp(-r^2) (Example 5.2).  (IFMM, d): scale r / d for r < d and
+    scale d / r otherwise (Example 5.4, the test matrix of Section 5.5).
     """
     if kernel == EXP:
         return scale * np.exp(-r2)
@@ -63,8 +63,8 @@ def kernel_block(xr: np.ndarray, xc: np.ndarray, scale: float, kernel=None) -> n
     """K_ij = scale / |xr_i - xc_j| for distinct points (no diagonal rule).
 
     ``kernel`` = EXP gives scale exp(-|xr_i - xc_j|^2), the smooth part of
-    the Gaussian matrix of Example 2 (the "exp" core, Section 5.1), and
-    (IFMM, d) the matrix of Example 4 (Section 5.5); a
+    the Gaussian matrix of Example 5.2 (the "exp" core, Section 5.1), and
+    (IFMM, d) the matrix of Example 5.4 (Section 5.5); a
     function of two point arrays broadcasting to a matrix replaces the
     inverse distance (the tests use polynomial kernels for which Chebyshev
     interpolation is exact).
@@ -82,7 +82,7 @@ def close_block(x: np.ndarray, ti: np.ndarray, si: np.ndarray, scale: float,
     """Kernel entries A[ti, si] with A_ii = diag (indices into x).
 
     With kernel = EXP the entries are scale exp(-|x_i - x_j|^2) off the
-    diagonal; Example 2's matrix 2 delta_ij + exp(-|r_i - r_j|^2) is
+    diagonal; Example 5.2's matrix 2 delta_ij + exp(-|r_i - r_j|^2) is
     scale = 1, diag = 3.
     """
     if kernel is not None and not _is_named(kernel):

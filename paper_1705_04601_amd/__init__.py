@@ -65,6 +65,13 @@ class h2_solve_info(ctypes.Structure):
                 ("refine_steps", ctypes.c_int)]
 
 
+class h2_plan_counts(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("n", "clusters", "depth", "s_blocks", "s_entries",
+                                               "s_upper_entries", "q_entries", "h2_entries",
+                                               "h2_close_entries", "filled_entries")] + \
+               [("exact_flops", ctypes.c_double)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -90,6 +97,14 @@ _SIGS = {
     "h2_sparse_export_q": (ctypes.c_int, [_P, _I64, _DP]),
     "h2_factor_S": (ctypes.c_int, [_P, ctypes.POINTER(h2_factor_opts), ctypes.POINTER(_P)]),
     "h2_factor_analyze": (ctypes.c_int, [_P, _I64P, _DP]),
+    "h2_plan_report": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(h2_plan_counts)]),
+    "h2_tune_set": (ctypes.c_int, [ctypes.c_char_p, _I64]),
+    "h2_tune_get": (ctypes.c_int, [ctypes.c_char_p, _I64P]),
+    "h2_tune_clear": (ctypes.c_int, []),
+    "h2_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "h2_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "h2_tune_report": (ctypes.c_int, [ctypes.c_char_p, _I64]),
+    "h2_autotune": (ctypes.c_int, [_P, ctypes.c_int, _I64, ctypes.c_char_p]),
     "h2_sparsify_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(h2_sparsify_opts),
                                          ctypes.POINTER(_P)]),
     "h2_factor_S_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(h2_factor_opts),
@@ -340,6 +355,51 @@ def h2_factor_analyze(sp: H2SparseHandle):
     fl = ctypes.c_double()
     _check(lib().h2_factor_analyze(sp.ptr, ctypes.byref(e), ctypes.byref(fl)))
     return e.value, fl.value
+
+
+def h2_plan_report(h: H2MatrixHandle, with_fill: bool = False) -> dict:
+    """Host-only entry counts of the plan of h (S, U = V, the H^2 matrix)."""
+    c = h2_plan_counts()
+    _check(lib().h2_plan_report(h.ptr, int(with_fill), ctypes.byref(c)))
+    return {f: getattr(c, f) for f, _ in h2_plan_counts._fields_}
+
+
+def h2_tune_set(key: str, value: int) -> None:
+    _check(lib().h2_tune_set(key.encode(), int(value)))
+
+
+def h2_tune_get(key: str):
+    """The table's entry for key, or None when the default applies."""
+    v = ctypes.c_int64()
+    code = lib().h2_tune_get(key.encode(), ctypes.byref(v))
+    if code == H2_EINVAL and lib().h2_last_error().decode().startswith("no tuning entry"):
+        return None
+    _check(code)
+    return v.value
+
+
+def h2_tune_clear() -> None:
+    _check(lib().h2_tune_clear())
+
+
+def h2_tune_load(path=None) -> None:
+    _check(lib().h2_tune_load(path.encode() if path else None))
+
+
+def h2_tune_save(path=None) -> None:
+    _check(lib().h2_tune_save(path.encode() if path else None))
+
+
+def h2_tune_report() -> dict:
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().h2_tune_report(buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def h2_autotune(h: H2MatrixHandle, precision: int, nrhs: int, path=None) -> None:
+    _use_torch_stream()
+    _check(lib().h2_autotune(h.ptr, int(precision), int(nrhs), path.encode() if path else None))
 
 
 def _info_dict(info, code):

@@ -25,9 +25,19 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(HERE, "..", "include")]
 HOST = ["-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# the wide GEMM tiles (up to 32 accumulator blocks) need their epilogue fully
+# unrolled, or the accumulators move to scratch memory
+WIDE = DEVICE + ["-mllvm", "-pragma-unroll-threshold=200000"]
 
 SOURCES = {
     "kernels.hip": DEVICE,
+    "gemm_transform.hip": DEVICE,
+    "gemm_transform_gen.hip": DEVICE,
+    "gemm_factor.hip": DEVICE,
+    "gemm_solve.hip": WIDE,
+    "gemm_matvec.hip": DEVICE,
+    "tune.cpp": [],
+    "autotune.cpp": [],
     "runtime.cpp": [],
     "tree.cpp": ["-ffp-contract=off"],
     "h2build.cpp": ["-fopenmp"],

@@ -233,6 +233,45 @@ extern "C" int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor*
   H2_API_END
 }
 
+extern "C" int h2_plan_report(h2_matrix* h, int with_fill, h2_plan_counts* out) {
+  H2_API_BEGIN
+  if (!h || !out) fail(H2_EINVAL, "null argument");
+  std::unique_ptr<h2_sparse> sp(plan_symbolic(h));
+  const Tree& tr = h->tree;
+  h2_plan_counts r{};
+  r.n = tr.n;
+  r.clusters = tr.ncl();
+  r.depth = tr.depth;
+  r.s_blocks = i64(sp->colidx.size());
+  r.s_upper_entries = sp->s_entries;
+  i64 diag = 0;
+  for (i64 c = 0; c < sp->ncl; ++c) diag += sp->nonbasis[c] * sp->nonbasis[c];
+  r.s_entries = 2 * sp->s_entries - diag;
+  r.q_entries = sp->q_entries;
+  i64 h2e = 0, close = 0;
+  for (i64 c = 0; c < tr.ncl(); ++c) {
+    if (h->basis_off.size() > size_t(c) && h->basis_off[c] >= 0) h2e += tr.size[c] * i64(h->rank[c]);
+    if (h->transfer_off.size() > size_t(c) && h->transfer_off[c] >= 0 && c > 0)
+      h2e += i64(h->rank[c]) * h->rank[(c - 1) / 2];
+  }
+  for (const auto& lv : h->bt.far)
+    for (const Pair& p : lv) h2e += i64(h->rank[p.t]) * h->rank[p.s];
+  if (!h->bt.near.empty())
+    for (const Pair& p : h->bt.near[0]) close += tr.size[p.t] * tr.size[p.s];
+  r.h2_entries = h2e + close;
+  r.h2_close_entries = close;
+  r.filled_entries = -1;
+  r.exact_flops = -1;
+  if (with_fill) {
+    double e = 0, fl = 0;
+    analyze_fill(*sp, &e, &fl);
+    r.filled_entries = int64_t(e);
+    r.exact_flops = fl;
+  }
+  *out = r;
+  H2_API_END
+}
+
 extern "C" int h2_factor_analyze(const h2_sparse* sp, int64_t* filled_entries, double* exact_flops) {
   H2_API_BEGIN
   if (!sp) fail(H2_EINVAL, "null argument");

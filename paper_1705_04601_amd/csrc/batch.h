@@ -12,6 +12,7 @@
 
 #include "h2_internal.h"
 #include "kernels.h"
+#include "tune.h"
 
 namespace h2 {
 
@@ -53,6 +54,8 @@ struct GemmBatch {
   int role = ROLE_TRANSFORM;
   int amode = -1, bmode = -1;  // operand layouts shared by every segment (build_tiles)
   int kern = 0;                // kernel of generated operands, one per launch (build_tiles)
+  int prec = -1;               // 0 FP64, 1 FP32: set by the planner, selects the tile table
+  int variant = 0;             // output tile shape (gemm_shape), from the tuning table
   double flops = 0.0;  // algorithmic flops of the batch
 
   bool empty() const { return items.empty(); }
@@ -150,10 +153,15 @@ struct GemmBatch {
         if (it.gkern != kern) fail(H2_EUNSUPPORTED, "one sweep over matrices of different kernels");
     if (items.size() >= (size_t(1) << 24)) fail(H2_EUNSUPPORTED, "GEMM batch above 2^24 items");
     int em = 64, en = 64;  // tile of the kernel that runs the batch
+    variant = 0;
     if (amode >= 0) {
-      gemm_tile(role, amode, bmode, &em, &en);
-      em *= 16;
-      en *= 16;
+      if (prec < 0) fail(H2_EINVAL, "internal: GEMM batch without a precision");
+      int max_m = 0;
+      for (const GemmItem& it : items) max_m = std::max(max_m, int(it.M));
+      variant = tune_gemm_variant(prec, role, amode, bmode, gemm_row_bucket(max_m));
+      const int code = gemm_shape(prec, role, amode, bmode, variant);
+      em = 16 * (code >> 4);
+      en = 16 * (code & 15);
     }
     for (size_t i = 0; i < items.size(); ++i) {
       const GemmItem& it = items[i];
@@ -201,6 +209,8 @@ struct GemmBatch {
   template <class T>
   void launch(hipStream_t st) const {
     if (ntiles <= 0) return;
+    if (prec != (sizeof(T) == 4 ? 1 : 0) || gemm_shape(prec, role, amode, bmode, variant) == 0)
+      fail(H2_EINVAL, "internal: GEMM batch launched in another precision or with a tile shape that is not built");
     GemmLaunch g{};
     g.amode = amode;
     g.bmode = bmode;
@@ -211,6 +221,7 @@ struct GemmBatch {
     g.mode = mode;
     g.role = role;
     g.kern = kern;
+    g.variant = variant;
     launch_gemm<T>(g, st);
   }
 };

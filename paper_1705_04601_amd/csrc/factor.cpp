@@ -199,13 +199,13 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   // position of its column cluster (targets of one row whose clusters are
   // close in space have close neighbours, so they share pivots); "z" orders
   // by the Z position where the tile's first segment starts.
-  size_t zpos_min = 16384;
+  size_t zpos_min = size_t(tune_knob("schur.order_min", 16384));
   if (const char* e = std::getenv("H2SP_SCHUR_ORDER"))
     zpos_min = e[0] == '0' ? SIZE_MAX : e[0] == '2' ? 1 : zpos_min;
-  bool key_z = false;
+  bool key_z = tune_knob("schur.key_z", 0) != 0;
   if (const char* e = std::getenv("H2SP_SCHUR_KEY")) key_z = e[0] == 'z';
   const std::vector<i64>& tstart = sp.H->tree.start;
-  i64 kMinK = 512;  // smallest K of a part; H2SP_SCHUR_SPLIT_K overrides it
+  i64 kMinK = tune_knob("schur.split_k", 512);  // smallest K of a part; H2SP_SCHUR_SPLIT_K overrides it
   if (const char* e = std::getenv("H2SP_SCHUR_SPLIT_K")) kMinK = std::max<i64>(1, std::atoll(e));
   const i64 pcap = f.pcap;
   auto split_targets = [&](const std::vector<SchurItem>& items, const std::vector<int64_t>& keys,
@@ -343,6 +343,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   auto plan_level = [&](int lv) {
     FactorLevel<T>& L = lvls[lv];
     L.zb.role = ROLE_FACTOR;
+    L.zb.prec = sizeof(T) == 4 ? 1 : 0;
     const std::vector<i64>& rows = by_level[lv];
     const long nr = long(rows.size());
     std::vector<i64> zbase(nr + 1, 0);

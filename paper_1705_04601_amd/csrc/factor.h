@@ -11,6 +11,7 @@ namespace h2 {
 // right-hand sides.
 struct SolvePlan {
   i64 nrhs = 0;
+  int64_t tune_gen = 0;                  // tuning generation the lists were planned under
   DeviceBuffer zin, zbuf, y, w, rs, colscale, desc;
   void* zin_ptr = nullptr;               // the vectors' addresses: in the buffers above, or in a
   double* rs_ptr = nullptr;              // scratch arena (allocation-free plans)

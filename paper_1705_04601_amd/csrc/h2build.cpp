@@ -1,4 +1,4 @@
-// Construction of the H^2 matrix of c/|x - y|, c exp(-|x - y|^2) or the kernel of Example 4
+// Construction of the H^2 matrix of c/|x - y|, c exp(-|x - y|^2) or the kernel of Example 5.4
 // (c r / d below d, c d / r from d on; Section 5.5) (the input of the method,
 // Definition 4.8; the paper takes it as given and cites H^2 compression for
 // orthogonal nested bases in Section 4.2).
@@ -240,7 +240,7 @@ Mat kernel_at_nodes(const double* xr, const double* xc, int P, int dim, int kern
       if (kern == H2_KERNEL_EXP) {
         k(i, j) = scale * std::exp(-d2);
       } else if (kern == H2_KERNEL_IFMM) {
-        const double r = std::sqrt(d2);  // Example 4: r / d below d, d / r from d on
+        const double r = std::sqrt(d2);  // Example 5.4: r / d below d, d / r from d on
         k(i, j) = r < param ? scale * (r / param) : scale * (param / r);
       } else {
         k(i, j) = scale / std::sqrt(d2);

@@ -63,14 +63,61 @@ struct GemmLaunch {
   int mode;
   int role;
   int kern;               // kernel of generated operands (GemmItem::gkern of every item)
+  int variant;            // output tile shape (gemm_shape)
 };
+
+// Output tile shapes the GEMM kernel is built with, per role and operand
+// layout pair: variant v in precision prec (0 FP64, 1 FP32) is a tile of
+// (code >> 4) x (code & 15) blocks of 16 x 16 (rows x columns), code 0 when
+// that variant is not built.  Variant 0 is the default; the tuning table
+// selects another per precision, role, layout and row bucket.  Measured
+// defaults: on short-K work (the solve sweeps, the pivot GEMMs, the transforms
+// with M-contiguous operands) 32 x 32 tiles, with more waves per SIMD, beat
+// 64 x 64; a generated operand is shared by more blocks in 64 x 32 tiles, and
+// the transforms whose two operands both run along K take 64 x 32 too.  The
+// wider solve variants read each stored operand fewer times (a tile of
+// 128 x 64 covers 128 right-hand sides at once).  FP64 variants keep at most
+// 16 blocks (the accumulators take twice the registers).
+constexpr int kGemmVariants = 4;
+constexpr int gemm_pick(int v, int a, int b, int c, int d) {
+  return v == 0 ? a : v == 1 ? b : v == 2 ? c : v == 3 ? d : 0;
+}
+constexpr int gemm_shape(int prec, int role, int am, int bm, int v) {
+  const int m = am * 3 + bm;
+  int code = 0;
+  switch (role) {
+    case ROLE_TRANSFORM:
+      code = (m == 0 || m == 6 || m == 7) ? gemm_pick(v, 0x42, 0x22, 0x44, 0)
+             : (m == 3)                   ? gemm_pick(v, 0x22, 0x42, 0x44, 0)
+                                          : 0;
+      break;
+    case ROLE_FACTOR: code = m == 0 ? gemm_pick(v, 0x22, 0x42, 0x44, 0) : 0; break;
+    case ROLE_SOLVE: code = (m == 3 || m == 4) ? gemm_pick(v, 0x22, 0x42, 0x82, 0x84) : 0; break;
+    case ROLE_MATVEC:
+      code = (m == 3 || m == 4) ? gemm_pick(v, 0x44, 0x42, 0x22, 0) : m == 5 ? gemm_pick(v, 0x42, 0x22, 0x44, 0) : 0;
+      break;
+    default: code = 0;
+  }
+  if (prec == 0 && (code >> 4) * (code & 15) > 16) code = 0;
+  return code;
+}
+// whether a role's kernels are built for a layout pair
+constexpr bool gemm_layout_supported(int role, int amode, int bmode) {
+  return gemm_shape(1, role, amode, bmode, 0) != 0;
+}
 
 template <class T>
 void launch_gemm(const GemmLaunch& g, hipStream_t st);
-// whether a role's kernels are built for a layout pair
-bool gemm_layout_supported(int role, int amode, int bmode);
-// output tile of the kernel that runs a role and layout pair: mb x nb blocks of 16 x 16
-void gemm_tile(int role, int amode, int bmode, int* mb, int* nb);
+// the launches of one role (one translation unit each)
+template <class T>
+void launch_gemm_transform(const GemmLaunch& g, hipStream_t st);
+template <class T>
+void launch_gemm_transform_gen(const GemmLaunch& g, hipStream_t st);
+template <class T>
+void launch_gemm_factor(const GemmLaunch& g, hipStream_t st);
+template <class T>
+void launch_gemm_solve(const GemmLaunch& g, hipStream_t st);
+void launch_gemm_matvec(const GemmLaunch& g, hipStream_t st);  // FP64 only
 
 // Compact work list of the Schur update S_ij -= Z_ki^T S_kj (offsets in
 // elements into S and into the buffer of Z_ki blocks; every operand has leading

@@ -16,6 +16,7 @@
 
 #include <mutex>
 
+#include "device_common.h"
 #include "kernels.h"
 
 namespace h2 {
@@ -44,284 +45,7 @@ hipError_t noalloc_scratch(void** ptr) {
   return hipSuccess;
 }
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef double d2 __attribute__((ext_vector_type(2)));
-
-// Raw buffer loads, declared as the LLVM intrinsics they are (the clang
-// builtin of the 128-bit form returns a single dword with this compiler).
-__device__ f4 raw_buffer_load_f4(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux) __asm(
-    "llvm.amdgcn.raw.ptr.buffer.load.v4f32");
-__device__ d2 raw_buffer_load_d2(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux) __asm(
-    "llvm.amdgcn.raw.ptr.buffer.load.v2f64");
-
 namespace {
-
-template <class T> struct Mfma;
-// Output layout of the 16x16x4 instructions (lane l, accumulator element v):
-// f64 holds D[l/16 + 4v][l%16], f32 holds D[4(l/16) + v][l%16] (measured on
-// gfx950).  `row` returns that D row.
-template <> struct Mfma<double> {
-  using V = d4;
-  static __device__ __forceinline__ V run(double a, double b, V c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int v) { return lane / 16 + 4 * v; }
-};
-template <> struct Mfma<float> {
-  using V = f4;
-  static __device__ __forceinline__ V run(float a, float b, V c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
-};
-
-
-// Destination q of an item, selected with constant indices only (a dynamic
-// index into the item's arrays would move the item to scratch memory).
-template <class T>
-__device__ __forceinline__ void store_out(const GemmItem& it, int q, int lr, int lc, T v, int mode) {
-  void* b;
-  int64_t ld;
-  bool tr;
-  switch (q) {
-    case 0: b = it.out[0]; ld = it.ld[0]; tr = it.trans[0]; break;
-    case 1: b = it.out[1]; ld = it.ld[1]; tr = it.trans[1]; break;
-    case 2: b = it.out[2]; ld = it.ld[2]; tr = it.trans[2]; break;
-    case 3: b = it.out[3]; ld = it.ld[3]; tr = it.trans[3]; break;
-    default: b = it.out[4]; ld = it.ld[4]; tr = it.trans[4]; break;
-  }
-  T* base = static_cast<T*>(b);
-  if (!base) return;
-  T* p = tr ? base + lc + lr * ld : base + lr + lc * ld;
-  if (mode == GEMM_STORE) *p = v;
-  else if (mode == GEMM_ADD) *p += v;
-  else *p -= v;
-}
-
-// K-contiguous variant: A stored K x M (op(A) = A^T) and B stored K x N, so
-// both operands run along K in memory.  No LDS: lane l loads 4 consecutive k
-// (k0 + 4(l/16) .. +3) of its row of A and of its column of B and feeds them
-// to 4 consecutive MFMAs.  Inside one instruction the four lane groups then
-// carry k = k0 + 4g + s (g = 0..3) for step s: A and B agree on that
-// permutation of K, and the four steps cover all 16 values of k.  A wave owns
-// a tile of up to 4 x 4 MFMA blocks (64 x 64), sized to the item so that
-// blocks of 48 or 16 rows waste no lanes.
-template <class T> struct Vec4;
-template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4), aligned(4))); };
-template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4), aligned(8))); };
-
-template <class T>
-__device__ __forceinline__ void load4(const T* p, int k, int K, bool ok, T* v) {
-  if (ok && k + 3 < K) {
-    const typename Vec4<T>::type x = *reinterpret_cast<const typename Vec4<T>::type*>(p + k);
-    v[0] = x[0];
-    v[1] = x[1];
-    v[2] = x[2];
-    v[3] = x[3];
-  } else {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = (ok && k + s < K) ? p[k + s] : T(0);
-  }
-}
-
-// Work-groups are handed to the 8 XCDs round-robin by block index, and each
-// XCD has its own L2.  Tile lists put tiles that share operands next to each
-// other; this mapping gives XCD x the x-th contiguous eighth of the list, so
-// neighbouring tiles meet in the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int n) {
-  const int x = b % 8, q = b / 8, base = n / 8, rem = n % 8;
-  return x * base + min(x, rem) + q;
-}
-
-// 1 / sqrt(x) in FP64: the hardware reciprocal square root (relative error
-// about 5e-8) refined by two Newton steps y <- y + y (1 - x y^2) / 2, which
-// bring it below one unit in the last place (measured 1.4e-16 over
-// x in [1e-12, 1e2]).
-__device__ __forceinline__ double inv_sqrt(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = fma(y, 0.5 * fma(-(x * y), y, 1.0), y);
-  y = fma(y, 0.5 * fma(-(x * y), y, 1.0), y);
-  return y;
-}
-
-// Operand fetch of the direct kernel for one 16-row (or 16-column) block and
-// the four k of this lane: K-contiguous rows (vector load) or M-contiguous
-// columns (one load per k, coalesced across the 16 lanes of a group).
-// Generated operands go through gen4.
-template <class T, int MODE>
-__device__ __forceinline__ void fetch4(const T* p, int64_t ld, int row, int k, int K, bool ok, T* v) {
-  if (MODE == 0) {          // element (row, k) at p[k + row ld]
-    load4<T>(p, k, K, ok, v);
-  } else {                  // element (row, k) at p[row + k ld]
-#pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = (ok && k + s < K) ? p[row + int64_t(k + s) * ld] : T(0);
-  }
-}
-
-// Off-diagonal kernel value at squared distance d2: scale / r (KERN 0),
-// scale exp(-r^2) (KERN 1), scale r / d below d and scale d / r from d on
-// (KERN 2, Example 4 of Section 5.5, d = param).  Generated GEMM operands and
-// kernel_blocks_kernel both form their values here.
-template <int KERN>
-__device__ __forceinline__ double kernel_value(double d2, double scale, double param) {
-  if constexpr (KERN == 0) {
-    return scale * inv_sqrt(d2);
-  } else if constexpr (KERN == 1) {
-    return scale * exp(-d2);
-  } else {
-    const double r = sqrt(d2);
-    return r < param ? scale * (r / param) : scale * (param / r);
-  }
-}
-
-// Generated operand block for the four k of this lane: the kernel of KERN
-// (kernel_value) at x_row - y_k, dg on the diagonal, from
-// the row's point, held in registers for the whole
-// segment, and the chunk's four source points, loaded once per chunk and
-// shared by every block of the tile.  Coordinates past dim are zero on both
-// sides; the sum runs over a = 0 .. dim - 1 in order (kernel_blocks_kernel
-// forms the same values).
-template <class T, int KERN>
-__device__ __forceinline__ void gen4(const double (&prow)[3], const double (&pcol)[4][3], int row, int k, int K,
-                                     bool ok, int dim, double scale, double dg, double param, bool diag, T* v) {
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    T val = T(0);
-    if (ok && k + s < K) {
-      if (diag && row == k + s) {
-        val = T(dg);
-      } else {
-        double d2 = 0.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-          if (a < dim) {
-            const double d = prow[a] - pcol[s][a];
-            d2 += d * d;
-          }
-        val = T(kernel_value<KERN>(d2, scale, param));
-      }
-    }
-    v[s] = val;
-  }
-}
-
-// acc += op(A) op(B) for one segment; AM / BM select the fetch of each operand.
-template <class T, int AM, int BM, int MB, int NB, int KERN>
-__device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[MB][NB], int nbm, int nbn,
-                                               const GemmSeg& sg, int m0, int n0, int M, int N, int lane,
-                                               int dim, double scale, double dg, double param) {
-  const int r = lane % 16, kq = 4 * (lane / 16);
-  const T* A = static_cast<const T*>(sg.A);
-  const T* B = static_cast<const T*>(sg.B);
-  const double* pr = static_cast<const double*>(sg.A);
-  const int K = sg.K;
-  const T* pa[MB];
-  const T* pb[NB];
-  int ra[MB], cb[NB];
-  bool oa[MB], ob[NB];
-#pragma unroll
-  for (int b = 0; b < MB; ++b) {
-    ra[b] = m0 + 16 * b + r;
-    oa[b] = b < nbm && ra[b] < M;
-    pa[b] = (AM == 0) ? A + int64_t(oa[b] ? ra[b] : 0) * sg.lda : A;
-  }
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    cb[b] = n0 + 16 * b + r;
-    ob[b] = b < nbn && cb[b] < N;
-    pb[b] = (BM == 0) ? B + int64_t(ob[b] ? cb[b] : 0) * sg.ldb : B;  // BM 1, 2: addressed per element
-  }
-  // generated operands: the points of this lane's rows (A) or columns (B)
-  constexpr int GA = AM == 2 ? MB : 1, GB = BM == 2 ? NB : 1;
-  double prA[GA][3], prB[GB][3];
-  if (AM == 2) {
-#pragma unroll
-    for (int b = 0; b < GA; ++b)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) prA[b][a] = (oa[b] && a < dim) ? pr[ra[b] * dim + a] : 0.0;
-  }
-  if (BM == 2) {
-    const double* pcb = static_cast<const double*>(sg.B);
-#pragma unroll
-    for (int b = 0; b < GB; ++b)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) prB[b][a] = (ob[b] && a < dim) ? pcb[cb[b] * dim + a] : 0.0;
-  }
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const int k = k0 + kq;
-    T a[MB][4], bv[NB][4];
-    double pcol[4][3];
-    if (AM == 2 || BM == 2) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) pcol[s][a] = (k + s < K && a < dim) ? sg.pc[(k + s) * dim + a] : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < MB; ++b)
-      if (b < nbm) {
-        if constexpr (AM == 2) gen4<T, KERN>(prA[b], pcol, ra[b], k, K, oa[b], dim, scale, dg, param, sg.diag, a[b]);
-        else fetch4<T, AM>(pa[b], sg.lda, ra[b], k, K, oa[b], a[b]);
-      }
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-      if (b < nbn) {
-        if constexpr (BM == 2) gen4<T, KERN>(prB[b], pcol, cb[b], k, K, ob[b], dim, scale, dg, param, sg.diag, bv[b]);
-        else fetch4<T, BM>(pb[b], sg.ldb, cb[b], k, K, ob[b], bv[b]);
-      }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int bm = 0; bm < MB; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < NB; ++bn)
-          if (bm < nbm && bn < nbn) acc[bm][bn] = Mfma<T>::run(bv[bn][s], a[bm][s], acc[bm][bn]);
-  }
-}
-
-// AM / BM: operand layouts of every segment of the launch (see direct_segment);
-// the tile is MB x NB blocks of 16 x 16; KERN: kernel of generated operands
-// (GemmItem::gkern, one for the whole launch)
-template <class T, int ROLE, int AM, int BM, int MB, int NB, int KERN>
-__global__ __launch_bounds__(64) void gemm_kc_kernel(GemmLaunch g) {
-  using V = typename Mfma<T>::V;
-  const int lane = threadIdx.x;
-  // the solve and matvec lists interleave heavy and light items: keep their
-  // round-robin spread over the XCDs
-  const int tb = (ROLE == ROLE_TRANSFORM || ROLE == ROLE_FACTOR) ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);
-  const uint32_t code = static_cast<uint32_t>(g.tiles[tb]);
-  const GemmItem it = g.items[code >> 8];
-  const int m0 = int((code >> 4) & 15) * 16 * MB, n0 = int(code & 15) * 16 * NB;
-  const int nbm = min(MB, (it.M - m0 + 15) / 16), nbn = min(NB, (it.N - n0 + 15) / 16);
-  V acc[MB][NB];
-#pragma unroll
-  for (int a = 0; a < MB; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[a][b] = V{0, 0, 0, 0};
-  for (int si = it.seg_begin; si < it.seg_end; ++si) {
-    const GemmSeg sg = g.segs[si];
-    direct_segment<T, AM, BM, MB, NB, KERN>(acc, nbm, nbn, sg, m0, n0, it.M, it.N, lane, it.gdim, it.gscale, it.gdiag,
-                                            it.gparam);
-  }
-#pragma unroll
-  for (int bm = 0; bm < MB; ++bm)
-#pragma unroll
-    for (int bn = 0; bn < NB; ++bn) {
-      if (bm >= nbm || bn >= nbn) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + 16 * bm + lane % 16;
-        const int col = n0 + 16 * bn + Mfma<T>::row(lane, v);
-        if (row >= it.M || col >= it.N) continue;
-        const int q = (row >= it.rs ? 2 : 0) + (col >= it.cs ? 1 : 0);
-        const int lr = row - (q >= 2 ? it.rs : 0), lc = col - ((q & 1) ? it.cs : 0);
-        const T val = acc[bm][bn][v];
-        store_out<T>(it, q, lr, lc, val, g.mode);
-        if (q == 0) store_out<T>(it, 4, lr, lc, val, g.mode);
-      }
-    }
-}
 
 // Schur update of the block factorisation with compact descriptors:
 // S[out] (M x N, ld M) -= sum_seg Z[a]^T (K x M, ld K16) S[b] (K x N, ld K),
@@ -1045,76 +769,18 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-// Output tile of each kernel instance, in 16 x 16 blocks (rows x columns).
-// Measured on the solve sweeps, the sparsification transforms and the pivot
-// GEMMs (short K, many items): 32 x 32 tiles, with more waves per SIMD, beat
-// 64 x 64 ones; a generated operand is shared by more blocks in 64 x 32 tiles,
-// and the transforms whose two operands both run along K take 64 x 32 too.
-constexpr int tile_mb(int role, int am, int bm) {
-  if (role == ROLE_TRANSFORM && am == 0 && bm == 0) return 4;
-  return (role == ROLE_MATVEC && bm == 2) || (role == ROLE_TRANSFORM && am == 2) ? 4
-         : (role == ROLE_MATVEC)                                                 ? 4
-                                                                                 : 2;
-}
-constexpr int tile_nb(int role, int am, int bm) {
-  return (role == ROLE_MATVEC && bm == 2) || (role == ROLE_TRANSFORM && am == 2) ? 2
-         : (role == ROLE_MATVEC)                                                 ? 4
-                                                                                 : 2;
-}
-void gemm_tile(int role, int amode, int bmode, int* mb, int* nb) {
-  *mb = tile_mb(role, amode, bmode);
-  *nb = tile_nb(role, amode, bmode);
-}
-
-// Operand layouts each role plans (the host checks every batch against them).
-template <class T, int ROLE, int AM, int BM>
-static void launch_kc(const GemmLaunch& g, hipStream_t st) {
-  constexpr int MB = tile_mb(ROLE, AM, BM), NB = tile_nb(ROLE, AM, BM);
-  if constexpr (AM == 2 || BM == 2) {
-    if (g.kern == 1) {
-      hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB, 1>), dim3(g.ntiles), dim3(64), 0, st, g);
-      return;
-    }
-    if (g.kern == 2) {
-      hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB, 2>), dim3(g.ntiles), dim3(64), 0, st, g);
-      return;
-    }
-  }
-  hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB, 0>), dim3(g.ntiles), dim3(64), 0, st, g);
-}
-
 template <class T>
 void launch_gemm(const GemmLaunch& g, hipStream_t st) {
   if (g.ntiles <= 0) return;
-  const int m = g.amode * 3 + g.bmode;
   switch (g.role) {
-    case ROLE_FACTOR:
-      if (m == 0) return launch_kc<T, ROLE_FACTOR, 0, 0>(g, st);
-      break;
-    case ROLE_SOLVE:
-      if (m == 3) return launch_kc<T, ROLE_SOLVE, 1, 0>(g, st);
-      if (m == 4) return launch_kc<T, ROLE_SOLVE, 1, 1>(g, st);
-      break;
+    case ROLE_FACTOR: return launch_gemm_factor<T>(g, st);
+    case ROLE_SOLVE: return launch_gemm_solve<T>(g, st);
     case ROLE_MATVEC:
-      if (m == 3) return launch_kc<T, ROLE_MATVEC, 1, 0>(g, st);
-      if (m == 4) return launch_kc<T, ROLE_MATVEC, 1, 1>(g, st);
-      if (m == 5) return launch_kc<T, ROLE_MATVEC, 1, 2>(g, st);
-      break;
+      if constexpr (sizeof(T) == 8) return launch_gemm_matvec(g, st);
+      return;
     default:
-      if (m == 0) return launch_kc<T, ROLE_TRANSFORM, 0, 0>(g, st);
-      if (m == 3) return launch_kc<T, ROLE_TRANSFORM, 1, 0>(g, st);
-      if (m == 6) return launch_kc<T, ROLE_TRANSFORM, 2, 0>(g, st);
-      if (m == 7) return launch_kc<T, ROLE_TRANSFORM, 2, 1>(g, st);
-      break;
-  }
-}
-bool gemm_layout_supported(int role, int amode, int bmode) {
-  const int m = amode * 3 + bmode;
-  switch (role) {
-    case ROLE_FACTOR: return m == 0;
-    case ROLE_SOLVE: return m == 3 || m == 4;
-    case ROLE_MATVEC: return m == 3 || m == 4 || m == 5;
-    default: return m == 0 || m == 3 || m == 6 || m == 7;
+      if (g.amode == 2) return launch_gemm_transform_gen<T>(g, st);
+      return launch_gemm_transform<T>(g, st);
   }
 }
 template void launch_gemm<double>(const GemmLaunch&, hipStream_t);

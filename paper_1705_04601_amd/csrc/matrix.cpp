@@ -72,6 +72,7 @@ namespace h2 {
 
 struct MatvecPlan {
   i64 nrhs = 0;
+  int64_t tune_gen = 0;          // tuning generation the lists were planned under
   DeviceBuffer xt, yt, xhat, xtil, ytil, yhat, desc;
   DeviceBuffer close_blocks;     // kernel blocks of the close part, when resident
   GemmBatch close;
@@ -97,6 +98,7 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
   H.upload_all();
   auto mp = std::make_unique<MatvecPlan>();
   MatvecPlan& p = *mp;
+  p.tune_gen = tune_generation();
   const Tree& tr = H.tree;
   const i64 n = tr.n, ncl = tr.ncl();
   const int dim = tr.dim, P = H.P, L = tr.depth;
@@ -241,6 +243,7 @@ static std::unique_ptr<MatvecPlan> make_matvec_plan(h2_matrix& H, i64 nrhs) {
   for (auto& g : p.down) all.push_back(&g);
   for (GemmBatch* g : all) {
     g->role = ROLE_MATVEC;
+    g->prec = 0;
     g->set_generator(dim, H.kern, H.scale, H.diag, H.kparam);
   }
   upload_batches(all, p.desc);
@@ -275,7 +278,7 @@ h2::MatvecPlan& h2::matvec_plan(const h2_matrix& H, i64 nrhs) {
     std::lock_guard<std::mutex> lk(g_mv_mu);
     slot = &g_mv_plans[&H];  // node-based map: the slot stays valid
   }
-  if (!*slot || (*slot)->nrhs != nrhs) {
+  if (!*slot || (*slot)->nrhs != nrhs || (*slot)->tune_gen != tune_generation()) {
     slot->reset();
     *slot = make_matvec_plan(const_cast<h2_matrix&>(H), nrhs);
   }

@@ -41,6 +41,7 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs, Device
   const int L = tr.depth;
   auto p = std::make_unique<SolvePlan>();
   p->nrhs = nrhs;
+  p->tune_gen = tune_generation();
   const auto& na = sp.n_act;
   const auto& kp = sp.kept;
   const auto& mb = sp.nonbasis;
@@ -182,7 +183,10 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs, Device
   for (auto& g : p->fwd) all.push_back(&g);
   for (auto& g : p->bwd) all.push_back(&g);
   all.push_back(&p->diag);
-  for (GemmBatch* g : all) g->role = ROLE_SOLVE;
+  for (GemmBatch* g : all) {
+    g->role = ROLE_SOLVE;
+    g->prec = sizeof(T) == 4 ? 1 : 0;
+  }
   HIPCHECK(hipStreamSynchronize(current_stream()));
   if (arena) upload_batches_into(all, *arena, current_stream());
   else upload_batches(all, p->desc);
@@ -206,7 +210,7 @@ static void apply_tree(h2_factor& f, SolvePlan& p, hipStream_t st) {
 }
 
 SolvePlan& solve_plan(h2_factor& f, i64 nrhs) {
-  if (!f.solve || f.solve->nrhs != nrhs) {
+  if (!f.solve || f.solve->nrhs != nrhs || f.solve->tune_gen != tune_generation()) {
     f.solve.reset();
     if (f.sp->precision == H2_MIXED) f.solve = make_solve_plan<float>(f, nrhs);
     else f.solve = make_solve_plan<double>(f, nrhs);

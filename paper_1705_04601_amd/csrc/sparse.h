@@ -49,6 +49,7 @@ struct h2_sparse {
   std::vector<h2::i64> blk_off;    // entry offset of each stored block
   h2::i64 s_entries = 0;
   std::vector<char> is_fill;       // per stored block: fill of the exact mode (empty before)
+  h2::i64 q_entries = 0;           // entries of the explicit Q_t (symbolic plans)
   bool factored = false;           // S has been overwritten by its factors
   // arenas
   std::vector<h2::i64> q_off, b_off, rhat_off, w_off;
@@ -73,5 +74,6 @@ struct h2_sparse {
 namespace h2 {
 void run_sparsify(h2_sparse& sp, hipStream_t st, double* phase_ms);
 h2_sparse* plan_sparsify(h2_matrix* H, int precision, bool upload);
+h2_sparse* plan_symbolic(h2_matrix* H);
 void run_sparsify_batch(std::vector<h2_sparse*>& sps, hipStream_t st, double* phase_ms);
 }

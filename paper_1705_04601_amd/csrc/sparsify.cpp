@@ -114,9 +114,12 @@ struct SymStrip {
 
 }  // namespace
 
-static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
+// symbolic: sizes, elimination order and S pattern only, on the host (no
+// device memory, no upload of the H^2 coefficients); such a handle is not
+// sparsified and serves only to count (h2_plan_report)
+static h2_sparse* plan(h2_matrix* H, int precision, bool upload, bool symbolic = false) {
   TraceTimer tt("sparsify-plan");
-  H->upload_all();
+  if (!symbolic) H->upload_all();
   auto spp = std::make_unique<h2_sparse>();
   h2_sparse& sp = *spp;
   const Tree& tr = H->tree;
@@ -341,6 +344,10 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
     }
     qlev[k + 1] = qs;
     wlev[k + 1] = H->identity_proj ? rs : ws;
+  }
+  if (symbolic) {
+    sp.q_entries = qs;
+    return spp.release();
   }
   const bool mixed = precision == H2_MIXED;
   const size_t el = sp.elem;
@@ -651,7 +658,13 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload) {
     blobs.push_back({lv.qr.items.data(), lv.qr.items.size() * sizeof(QrItem),
                      reinterpret_cast<const void**>(&lv.qr.d_items)});
   }
-  for (GemmBatch* g : all) g->set_generator(dim, H->kern, H->scale, H->diag, H->kparam);
+  // stack and wproj (the basis QR's input) run in FP64, the transforms in the
+  // precision of S
+  for (GemmBatch* g : all) {
+    g->set_generator(dim, H->kern, H->scale, H->diag, H->kparam);
+    g->prec = sp.precision == H2_MIXED ? 1 : 0;
+  }
+  for (auto& lv : sp.levels) lv.stack.prec = lv.wproj.prec = 0;
   tt.lap("work-lists");
   HIPCHECK(hipStreamSynchronize(current_stream()));
   if (!upload) return spp.release();  // a batched sweep merges and uploads the lists
@@ -730,6 +743,7 @@ void run_sparsify(h2_sparse& sp, hipStream_t st, double* phase_ms) {
 }
 
 h2_sparse* plan_sparsify(h2_matrix* H, int precision, bool upload) { return plan(H, precision, upload); }
+h2_sparse* plan_symbolic(h2_matrix* H) { return plan(H, H2_FP64, false, true); }
 
 // Several sparsifications swept together (independent H^2 matrices of uneven
 // size): level k of every instance goes into the same launches.  Work items
@@ -894,6 +908,8 @@ void run_sparsify_batch(std::vector<h2_sparse*>& sps, hipStream_t st, double* ph
     for (auto& g : m.coup2) all.push_back(&g);
     blobs.push_back({m.qr.data(), m.qr.size() * sizeof(QrItem), reinterpret_cast<const void**>(&m.d_qr)});
   }
+  for (GemmBatch* g : all) g->prec = sps.front()->precision == H2_MIXED ? 1 : 0;
+  for (MergedLevel& m : M) m.stack.prec = m.wproj.prec = 0;
   DeviceBuffer desc;
   upload_batches(all, desc, blobs);
   tt.lap("upload");

@@ -1,4 +1,4 @@
-"""GPU parity for the exp core of Example 2, A_ij = 2 delta_ij + exp(-|r_i - r_j|^2)
+"""GPU parity for the exp core of Example 5.2, A_ij = 2 delta_ij + exp(-|r_i - r_j|^2)
 (kernel H2_KERNEL_EXP with scale 1 and diagonal 3), through the C ABI.
 
 Bars: the FP64 path within 1e-12 of the oracle's Q_t and S (relative to

@@ -1,5 +1,5 @@
 """GPU tests of the preconditioner variant of Section 5.5 (through the C ABI):
-the Example 4 kernel (H2_KERNEL_IFMM), the block threshold ILU of S
+the Example 5.4 kernel (H2_KERNEL_IFMM), the block threshold ILU of S
 (H2_FACTOR_ILUT) and GMRES on an accurate H^2 matrix preconditioned by the
 factor of a coarse one.
 

@@ -47,7 +47,7 @@ def test_tree_and_ranks_match_oracle(kind, n, seed, leaf, cheb, tol, cap, eta):
     ("sphere", 2048, 12, 64, 3, 1e-6, 27),
 ])
 def test_exp_kernel_tree_and_ranks_match_oracle(kind, n, seed, leaf, cheb, tol, cap):
-    """The exp core of Example 2 through the library's host construction:
+    """The exp core of Example 5.2 through the library's host construction:
     permutation and recompressed ranks equal the oracle's."""
     import h2inputs
     import oracle
@@ -106,7 +106,7 @@ def test_null_handles_are_rejected():
 
 @pytest.mark.parametrize("d", [1e-3, 1e-2])
 def test_ifmm_kernel_tree_and_ranks_match_oracle(d):
-    """The Example 4 kernel of Section 5.5 through the library's host
+    """The Example 5.4 kernel of Section 5.5 through the library's host
     construction: permutation and recompressed ranks equal the oracle's."""
     import h2inputs
     import oracle

@@ -486,10 +486,10 @@ def test_pins_catch_a_transposed_coupling(monkeypatch):
     assert np.linalg.norm(u @ s @ u.T - a_ref) > 1e-10 * np.linalg.norm(a_ref)
 
 
-# ------------------------------------------------ Example 2: exp(-|r|^2) core
+# ------------------------------------------------ Example 5.2: exp(-|r|^2) core
 
 def test_exp_kernel_values_by_hand():
-    """Entries of 2 delta_ij + exp(-|r_i - r_j|^2) (Example 2) for three
+    """Entries of 2 delta_ij + exp(-|r_i - r_j|^2) (Example 5.2) for three
     points at squared distances 1, 2 and 3, written out by hand."""
     x = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 1.0]])
     idx = np.arange(3)

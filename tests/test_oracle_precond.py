@@ -1,5 +1,5 @@
 """Pins of the oracle for the preconditioner variant of Section 5.5: the
-Example 4 matrix, block threshold ILU of S and right-preconditioned GMRES.
+Example 5.4 matrix, block threshold ILU of S and right-preconditioned GMRES.
 
 Checks rest on what does not depend on the oracle's own formulas: values
 written out by hand, scipy's pairwise distances, block ILU(0) and the dense
@@ -25,7 +25,7 @@ def ifmm_dense(x, d):
 
 
 def test_ifmm_kernel_values_by_hand():
-    """Example 4: 1 on the diagonal, r/d below d, d/r from d on."""
+    """Example 5.4: 1 on the diagonal, r/d below d, d/r from d on."""
     d = 0.01
     x = np.array([[0.0, 0.0, 0.0], [0.005, 0.0, 0.0], [0.0, 0.0, 0.02], [0.0, 0.01, 0.0]])
     idx = np.arange(4)
@@ -50,7 +50,7 @@ def ifmm_case():
 
 
 def test_ifmm_h2_and_conditioning(ifmm_case):
-    """The H^2 of Example 4 against the dense matrix, and the paper's
+    """The H^2 of Example 5.4 against the dense matrix, and the paper's
     observation that the condition number grows with d."""
     cond = {}
     for d, (x, fine, coarse, sp, order) in ifmm_case.items():
