@@ -361,7 +361,7 @@ int h2_last_work(double* work, int count);
  * built, makes every call that plans work fail with EINVAL).  Entries change
  * speed only, never a result bit.  Keys:
  *   "gemm.<f32|f64>.<transform|factor|solve|matvec>.a<A>b<B>.m<R>": the tile
- *     variant (0..3, those built for the kind) of GEMM batches whose operand
+ *     variant (0..5, those built for the kind) of GEMM batches whose operand
  *     layouts are A and B and whose largest item has <= 16, 32, 64 or more
  *     rows (R = 0..3);
  *   "schur.split_k" (16..2^30, default 512): smallest K of a split Schur part;

@@ -56,6 +56,7 @@ struct GemmBatch {
   int kern = 0;                // kernel of generated operands, one per launch (build_tiles)
   int prec = -1;               // 0 FP64, 1 FP32: set by the planner, selects the tile table
   int variant = 0;             // output tile shape (gemm_shape), from the tuning table
+  int wg_rows = 1;             // row tiles per work-group (build_tiles)
   double flops = 0.0;  // algorithmic flops of the batch
 
   bool empty() const { return items.empty(); }
@@ -163,12 +164,23 @@ struct GemmBatch {
       em = 16 * (code >> 4);
       en = 16 * (code & 15);
     }
+    // the solve sweeps give the row tiles of one tile column (the right-hand
+    // sides) to the waves of one work-group, so that they read each S block
+    // through one CU's cache: every item has the same rows there
+    wg_rows = 1;
+    if (role == ROLE_SOLVE && !items.empty()) {
+      const int tm0 = (items[0].M + em - 1) / em;
+      bool same = true;
+      for (const GemmItem& it : items) same = same && (it.M + em - 1) / em == tm0;
+      if (same) wg_rows = std::min(tm0, kSolveWaves);
+    }
     for (size_t i = 0; i < items.size(); ++i) {
       const GemmItem& it = items[i];
       if (it.seg_end == it.seg_begin && mode != GEMM_STORE) continue;
       const int tm = (it.M + em - 1) / em, tn = (it.N + en - 1) / en;
       if (tm > 16 || tn > 16) fail(H2_EUNSUPPORTED, "GEMM item above 16 tiles along an edge");
-      for (int a = 0; a < tm; ++a)
+      const int groups = (tm + wg_rows - 1) / wg_rows;  // tile rows of wg_rows row tiles
+      for (int a = 0; a < groups; ++a)
         for (int b = 0; b < tn; ++b) tiles.push_back(int32_t((uint32_t(i) << 8) | (a << 4) | b));
     }
     ntiles = int32_t(tiles.size());
@@ -222,6 +234,7 @@ struct GemmBatch {
     g.role = role;
     g.kern = kern;
     g.variant = variant;
+    g.wg_rows = wg_rows;
     launch_gemm<T>(g, st);
   }
 };

@@ -20,6 +20,11 @@ __device__ f4 raw_buffer_load_f4(__amdgpu_buffer_rsrc_t rsrc, int voffset, int s
 __device__ d2 raw_buffer_load_d2(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux) __asm(
     "llvm.amdgcn.raw.ptr.buffer.load.v2f64");
 
+__device__ float raw_buffer_load_f1(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux) __asm(
+    "llvm.amdgcn.raw.ptr.buffer.load.f32");
+__device__ double raw_buffer_load_d1(__amdgpu_buffer_rsrc_t rsrc, int voffset, int soffset, int aux) __asm(
+    "llvm.amdgcn.raw.ptr.buffer.load.f64");
+
 namespace {
 
 template <class T> struct Mfma;
@@ -77,5 +82,52 @@ __device__ __forceinline__ double kernel_value(double d2, double scale, double p
   }
 }
 
+// Buffer resources: reads outside [base, base + size) return zero and move no
+// memory.
+constexpr int kRsrcFlags = 0x00020000;  // raw 32-bit buffer, no swizzle (gfx9 family)
+
+// The base and the size are wave-uniform; readfirstlane keeps them in SGPRs
+// (a resource in VGPRs would make the compiler loop over the lanes).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a))));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a >> 32))));
+  const int n = __builtin_amdgcn_readfirstlane(int(bytes));
+  void* q = reinterpret_cast<void*>((uint64_t(hi) << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, 0, n, kRsrcFlags);
+}
+
+template <class T> struct BufLoad4;
+template <> struct BufLoad4<float> {
+  static __device__ __forceinline__ void run(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&v)[4]) {
+    const f4 x = raw_buffer_load_f4(rs, int(off), 0, 0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = x[s];
+  }
+};
+template <> struct BufLoad4<double> {
+  static __device__ __forceinline__ void run(__amdgpu_buffer_rsrc_t rs, uint32_t off, double (&v)[4]) {
+    const d2 x = raw_buffer_load_d2(rs, int(off), 0, 0);
+    const d2 y = raw_buffer_load_d2(rs, int(off + 16), 0, 0);
+    v[0] = x[0];
+    v[1] = x[1];
+    v[2] = y[0];
+    v[3] = y[1];
+  }
+};
+
+constexpr uint32_t kOutside = 0x80000000u;  // a buffer offset past every resource used here
+
+template <class T> struct BufLoad1;
+template <> struct BufLoad1<float> {
+  static __device__ __forceinline__ float run(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return raw_buffer_load_f1(rs, int(off), 0, 0);
+  }
+};
+template <> struct BufLoad1<double> {
+  static __device__ __forceinline__ double run(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return raw_buffer_load_d1(rs, int(off), 0, 0);
+  }
+};
 }  // namespace
 }  // namespace h2

@@ -64,6 +64,7 @@ struct GemmLaunch {
   int role;
   int kern;               // kernel of generated operands (GemmItem::gkern of every item)
   int variant;            // output tile shape (gemm_shape)
+  int wg_rows;            // waves per work-group: the row tiles of one tile column (solve sweeps), else 1
 };
 
 // Output tile shapes the GEMM kernel is built with, per role and operand
@@ -75,12 +76,16 @@ struct GemmLaunch {
 // with M-contiguous operands) 32 x 32 tiles, with more waves per SIMD, beat
 // 64 x 64; a generated operand is shared by more blocks in 64 x 32 tiles, and
 // the transforms whose two operands both run along K take 64 x 32 too.  The
-// wider solve variants read each stored operand fewer times (a tile of
-// 128 x 64 covers 128 right-hand sides at once).  FP64 variants keep at most
-// 16 blocks (the accumulators take twice the registers).
-constexpr int kGemmVariants = 4;
-constexpr int gemm_pick(int v, int a, int b, int c, int d) {
-  return v == 0 ? a : v == 1 ? b : v == 2 ? c : v == 3 ? d : 0;
+// solve sweeps also build 32 x 80 and 32 x 128 tiles, a whole target row of
+// the common non-basis sizes per wave (the work-group's waves cover the
+// right-hand sides and share the S block through the CU's cache).  FP64
+// variants keep at most 16 blocks (the accumulators take twice the
+// registers), 8 in the solve sweeps, whose kernel holds two chunks of
+// operands.
+constexpr int kGemmVariants = 6;
+constexpr int kSolveWaves = 4;  // most waves (row tiles) per work-group of the solve sweeps
+constexpr int gemm_pick(int v, int a, int b, int c, int d, int e = 0, int f = 0) {
+  return v == 0 ? a : v == 1 ? b : v == 2 ? c : v == 3 ? d : v == 4 ? e : v == 5 ? f : 0;
 }
 constexpr int gemm_shape(int prec, int role, int am, int bm, int v) {
   const int m = am * 3 + bm;
@@ -92,13 +97,13 @@ constexpr int gemm_shape(int prec, int role, int am, int bm, int v) {
                                           : 0;
       break;
     case ROLE_FACTOR: code = m == 0 ? gemm_pick(v, 0x22, 0x42, 0x44, 0) : 0; break;
-    case ROLE_SOLVE: code = (m == 3 || m == 4) ? gemm_pick(v, 0x22, 0x42, 0x82, 0x84) : 0; break;
+    case ROLE_SOLVE: code = (m == 3 || m == 4) ? gemm_pick(v, 0x22, 0x42, 0x24, 0x44, 0x25, 0x28) : 0; break;
     case ROLE_MATVEC:
       code = (m == 3 || m == 4) ? gemm_pick(v, 0x44, 0x42, 0x22, 0) : m == 5 ? gemm_pick(v, 0x42, 0x22, 0x44, 0) : 0;
       break;
     default: code = 0;
   }
-  if (prec == 0 && (code >> 4) * (code & 15) > 16) code = 0;
+  if (prec == 0 && (code >> 4) * (code & 15) > (role == ROLE_SOLVE ? 8 : 16)) code = 0;
   return code;
 }
 // whether a role's kernels are built for a layout pair

@@ -68,38 +68,6 @@ namespace {
 // block, or zero past the block's end.
 // Segment descriptors are loaded 64 at a time, one per lane, and taken out
 // with readlane, so that moving to the next segment waits for no memory.
-constexpr int kRsrcFlags = 0x00020000;  // raw 32-bit buffer, no swizzle (gfx9 family)
-
-// The base and the size are wave-uniform; readfirstlane keeps them in SGPRs
-// (a resource in VGPRs would make the compiler loop over the lanes).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-  const uint64_t a = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a))));
-  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(a >> 32))));
-  const int n = __builtin_amdgcn_readfirstlane(int(bytes));
-  void* q = reinterpret_cast<void*>((uint64_t(hi) << 32) | lo);
-  return __builtin_amdgcn_make_buffer_rsrc(q, 0, n, kRsrcFlags);
-}
-
-template <class T> struct BufLoad4;
-template <> struct BufLoad4<float> {
-  static __device__ __forceinline__ void run(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&v)[4]) {
-    const f4 x = raw_buffer_load_f4(rs, int(off), 0, 0);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = x[s];
-  }
-};
-template <> struct BufLoad4<double> {
-  static __device__ __forceinline__ void run(__amdgpu_buffer_rsrc_t rs, uint32_t off, double (&v)[4]) {
-    const d2 x = raw_buffer_load_d2(rs, int(off), 0, 0);
-    const d2 y = raw_buffer_load_d2(rs, int(off + 16), 0, 0);
-    v[0] = x[0];
-    v[1] = x[1];
-    v[2] = y[0];
-    v[3] = y[1];
-  }
-};
-
 // Chunk cursor of a tile (wave-uniform apart from the lane offsets and the
 // lane-held descriptors).
 template <class T, int NBM, int NBN>
@@ -184,7 +152,6 @@ __device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const Sc
   }
 }
 
-constexpr uint32_t kOutside = 0x80000000u;  // a buffer offset past every resource used here
 
 // Loads one chunk (the same loads for every chunk, so that the number of
 // loads in flight stays static) and returns the MFMA steps it needs: 4 for a

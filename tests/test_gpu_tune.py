@@ -50,7 +50,7 @@ def _used(role):
 
 
 def _variants(key):
-    return [v for v in range(4) if _try_set(key, v)]
+    return [v for v in range(8) if _try_set(key, v)]
 
 
 def _try_set(key, v):
