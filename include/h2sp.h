@@ -415,7 +415,10 @@ int h2_autotune(h2_matrix* h, int precision, int64_t nrhs, const char* path);
  *   H2SP_CLOSE_RESIDENT=0: never keep the matvec's close blocks on the device;
  *   H2SP_GRAPHS=0: run the solve and matvec sweeps eagerly instead of as
  *     captured HIP graphs;
- *   H2SP_TUNE_FILE: the tuning cache to read (see h2_tune_load). */
+ *   H2SP_TUNE_FILE: the tuning cache to read (see h2_tune_load);
+ *   H2SP_DEVICE_CACHE_FRACTION (default 0.9): idle device memory the library
+ *     keeps for reuse, as a fraction of the device's memory; all of it is
+ *     released when an allocation of the library fails. */
 
 #ifdef __cplusplus
 }

@@ -52,20 +52,26 @@ void check_hip(hipError_t e, const char* what) {
 // the same large buffers come back call after call.  A freed block is kept
 // with an event recorded on the freeing stream; a later request of about its
 // size takes it back after making its own stream wait for that event.  Idle
-// blocks are capped and are released first when hipMalloc runs out.
+// blocks are capped (the longest idle released first, so that the buffers of
+// the work that runs now stay) and are all released when hipMalloc runs out.
 namespace {
 struct CachedBlock {
   void* p;
   size_t cap;
   hipEvent_t done;
   int dev;
+  uint64_t seq;  // order of the frees
 };
+uint64_t g_seq = 0;
 std::mutex g_cache_mu;
 std::multimap<size_t, CachedBlock> g_cache;  // by capacity
 size_t g_cached = 0;
-// idle bytes kept: half of the device's memory (the tiled operand copies of
-// the factorisation of the largest workloads take tens of GB, and a hipMalloc
-// and hipFree of that size cost a noticeable part of a factorisation)
+// idle bytes kept: 90% of the device's memory by default
+// (H2SP_DEVICE_CACHE_FRACTION), as a caching allocator that gives memory
+// back only when an allocation fails.  A step of the largest workloads holds
+// well over half of the memory (in FP64 at N = 1M: S 120 GB and the level
+// buffers 80 GB), and a fresh hipMalloc maps pages at about 25 GB/s, so a
+// smaller cache would map them again on every call.
 size_t cache_limit() {
   static const size_t lim = [] {
     size_t free_b = 0, total_b = 0;
@@ -73,7 +79,9 @@ size_t cache_limit() {
       (void)hipGetLastError();
       return size_t(64) << 30;
     }
-    return total_b / 2;
+    double frac = 0.9;
+    if (const char* e = std::getenv("H2SP_DEVICE_CACHE_FRACTION")) frac = std::min(1.0, std::max(0.0, std::atof(e)));
+    return size_t(double(total_b) * frac);
   }();
   return lim;
 }
@@ -83,10 +91,13 @@ size_t round_cap(size_t b) {
   return b >= (size_t(1) << 20) ? (b + g - 1) & ~(g - 1) : (b + 255) & ~size_t(255);
 }
 
-// releases idle blocks (largest first) until at most `keep` bytes stay cached
+// releases idle blocks (longest idle first) until at most `keep` bytes stay
+// cached
 void trim_locked(size_t keep) {
   while (g_cached > keep && !g_cache.empty()) {
-    auto it = std::prev(g_cache.end());
+    auto it = g_cache.begin();
+    for (auto j = g_cache.begin(); j != g_cache.end(); ++j)
+      if (j->second.seq < it->second.seq) it = j;
     (void)hipEventSynchronize(it->second.done);
     (void)hipEventDestroy(it->second.done);
     int cur = 0;
@@ -124,7 +135,13 @@ void* device_alloc(size_t bytes, size_t* cap, hipStream_t first_use) {
     }
   }
   void* p = nullptr;
+  const double t0 = now_ms();
   hipError_t e = hipMalloc(&p, want);
+  if (trace_enabled() && now_ms() - t0 > 20.0) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    std::fprintf(stderr, "[h2sp] hipMalloc %.2f GB took %.1f ms (cached idle %.2f GB in %zu blocks)\n", want / 1e9,
+                 now_ms() - t0, g_cached / 1e9, g_cache.size());
+  }
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
     {
@@ -150,7 +167,7 @@ void device_free(void* p, size_t cap) {
     return;
   }
   std::lock_guard<std::mutex> lk(g_cache_mu);
-  g_cache.emplace(cap, CachedBlock{p, cap, ev, dev});
+  g_cache.emplace(cap, CachedBlock{p, cap, ev, dev, ++g_seq});
   g_cached += cap;
   trim_locked(cache_limit());
 }
