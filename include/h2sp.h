@@ -367,7 +367,9 @@ int h2_last_work(double* work, int count);
  *   "schur.split_k" (16..2^30, default 512): smallest K of a split Schur part;
  *   "schur.key_z" (0 or 1, default 0): order Schur tiles by Z position;
  *   "schur.order_min" (default 16384): reorder levels with at least this many
- *     tiles.
+ *     tiles;
+ *   "schur.split_big" (0 or 1, default 0): cut targets of 6 to 8 blocks of 16
+ *     into tiles of half the edge (more waves per SIMD, more operand reads).
  * The environment variables below override the Schur knobs.  Work lists
  * already planned are planned again after any change.  h2_tune_set replaces
  * one entry (EINVAL for unknown keys, values out of range or variants that are
@@ -383,7 +385,7 @@ int h2_last_work(double* work, int count);
  * sides (1..512), measures every built variant of each GEMM kind that the
  * sparsification, the ILU(0) factorisation, the preconditioner application
  * and the FP64 product plan, and the Schur knobs (split_k in {256, 512, 1024,
- * 2048}, key_z in {0, 1}), one key at a time with the others fixed (device
+ * 2048}, key_z and split_big in {0, 1}), one key at a time with the others fixed (device
  * time of the phase, or the time of the synchronous call), keeps the fastest
  * of each in the table and, with a path, saves it.  Runs each phase several
  * times: seconds to minutes.  Uses the stream of h2_set_stream.

@@ -141,6 +141,7 @@ extern "C" int h2_autotune(h2_matrix* h, int precision, int64_t nrhs, const char
     for (const std::string& k : used_keys("factor")) descend(k, variants_of(k), 1, factor_ms, log);
     descend("schur.split_k", {256, 512, 1024, 2048}, 1, factor_ms, log);
     descend("schur.key_z", {0, 1}, 1, factor_ms, log);
+    descend("schur.split_big", {0, 1}, 1, factor_ms, log);
     // the preconditioner application's sweeps (one warm-up call plans them)
     {
       h2_sparse* sp = nullptr;

@@ -206,6 +206,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   if (const char* e = std::getenv("H2SP_SCHUR_KEY")) key_z = e[0] == 'z';
   const std::vector<i64>& tstart = sp.H->tree.start;
   i64 kMinK = tune_knob("schur.split_k", 512);  // smallest K of a part; H2SP_SCHUR_SPLIT_K overrides it
+  // targets of class 2 (6 to 8 blocks of 16 along the longer side) as tiles of
+  // half the edge (class 0) instead of one whole-target tile
+  const bool split_big = tune_knob("schur.split_big", 0) != 0;
   if (const char* e = std::getenv("H2SP_SCHUR_SPLIT_K")) kMinK = std::max<i64>(1, std::atoll(e));
   const i64 pcap = f.pcap;
   auto split_targets = [&](const std::vector<SchurItem>& items, const std::vector<int64_t>& keys,
@@ -258,11 +261,13 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         o.keys.push_back(key);
         i64 k = 0;
         for (int32_t r = si.seg_begin; r < si.seg_end; ++r) k += L.ssegs[r].K;
-        for (int a = 0; a < (si.M + edge - 1) / edge; ++a)
-          for (int b = 0; b < (si.N + edge - 1) / edge; ++b) {
-            const int cls = schur_tile_class<T>(si.M, si.N, a * edge, b * edge);
-            o.tiles[cls].push_back(int32_t((item << 8) | (a << 4) | b));
-            o.cls_flops[cls] += 2.0 * std::min(edge, si.M - a * edge) * std::min(edge, si.N - b * edge) * double(k);
+        const bool half = split_big && schur_tile_class<T>(si.M, si.N, 0, 0) == 2;
+        const int te = half ? edge / 2 : edge;
+        for (int a = 0; a < (si.M + te - 1) / te; ++a)
+          for (int b = 0; b < (si.N + te - 1) / te; ++b) {
+            const int cls = schur_tile_class<T>(si.M, si.N, a * te, b * te, te);
+            o.tiles[cls].push_back(schur_tile_code(item, a, b, half));
+            o.cls_flops[cls] += 2.0 * std::min(te, si.M - a * te) * std::min(te, si.N - b * te) * double(k);
           }
         o.items.push_back(si);
       };

@@ -168,10 +168,17 @@ struct SchurLaunch {
 // it has 6 to 8.
 constexpr int kSchurClasses = 3;
 template <class T>
-constexpr int schur_tile_class(int M, int N, int m0, int n0) {
+constexpr int schur_tile_class(int M, int N, int m0, int n0, int edge = schur_edge<T>) {
   const int e = M - m0 > N - n0 ? M - m0 : N - n0;
-  const int b = (e < schur_edge<T> ? e : schur_edge<T>) + 15;
+  const int b = (e < edge ? e : edge) + 15;
   return b / 16 <= 4 ? 0 : b / 16 == 5 ? 1 : 2;
+}
+// Tile code of the Schur kernels: (item << 8) | (row << 4) | column in tiles
+// of the full edge, or with row and column + 8 in tiles of half the edge (a
+// target of class 2 cut into tiles of class 0, when the tuning table asks:
+// more waves per SIMD for the same work, at twice the operand reads).
+inline int32_t schur_tile_code(uint32_t item, int a, int b, bool half) {
+  return int32_t((item << 8) | ((half ? a + 8 : a) << 4) | (half ? b + 8 : b));
 }
 template <class T>
 void launch_schur(const SchurLaunch& g, int cls, hipStream_t st);

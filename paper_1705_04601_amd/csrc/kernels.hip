@@ -333,9 +333,13 @@ __global__ __launch_bounds__(64) void schur_kernel(SchurLaunch g) {
   const int lane = threadIdx.x;
   const uint32_t code = static_cast<uint32_t>(g.tiles[xcd_tile(blockIdx.x, gridDim.x)]);
   const SchurItem it = g.items[code >> 8];
-  const int m0 = int((code >> 4) & 15) * E, n0 = int(code & 15) * E;
+  // a tile row field of 8 or more marks a tile of edge E / 2 (a large target
+  // cut into quarters, see schur_tile_code)
+  const int fa = int((code >> 4) & 15), fb = int(code & 15);
+  const int te = fa >= 8 ? E / 2 : E;
+  const int m0 = (fa & 7) * te, n0 = (fb & 7) * te;
   constexpr int B = E / 16;
-  const int nbm = min(B, (it.M - m0 + 15) / 16), nbn = min(B, (it.N - n0 + 15) / 16);
+  const int nbm = min(te / 16, (it.M - m0 + 15) / 16), nbn = min(te / 16, (it.N - n0 + 15) / 16);
 #define H2_SCHUR_CASE(I, J) \
   case I * 8 + J: schur_tile<T, I, J, schur_stages<T, I, J, CLS>()>(g, it, m0, n0, lane); break;
   if constexpr (CLS == 0) {

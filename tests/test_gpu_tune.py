@@ -117,6 +117,32 @@ def test_schur_knobs():
     assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max()
 
 
+def test_split_big_targets_gives_the_same_bits():
+    """Targets of 6 to 8 blocks of 16 cut into half-edge tiles (class 0): the
+    class-2 kernel no longer runs and every sum keeps its order."""
+    torch.cuda.set_device(0)
+    n = 8192
+    x = h2inputs.points("cube", n, 43)
+    h = P.h2_build(x, 1.0 / (4.0 * np.pi * n), 1.0, 128, 4, 1e-8, 64)
+    bh = h2inputs.rhs(n, 8, 11)
+    b = torch.from_numpy(np.ascontiguousarray(bh.T)).cuda().T
+
+    def run():
+        f = P.h2_factor_S(P.h2_sparsify(h, P.H2_MIXED))
+        work = P.h2_last_work()
+        xo = torch.full_like(b, float("nan"))
+        P.h2_apply_inverse(f, b, xo)
+        torch.cuda.synchronize()
+        return xo.cpu().numpy(), work
+
+    ref, w0 = run()
+    assert w0[15] > 0  # class-2 launches at the default
+    P.h2_tune_set("schur.split_big", 1)
+    got, w1 = run()
+    assert w1[15] == 0 and w1[11] > w0[11]
+    assert np.array_equal(got, ref)
+
+
 def test_autotune_writes_a_cache_that_loads(tmp_path):
     torch.cuda.set_device(0)
     h = _matrix()
@@ -127,7 +153,7 @@ def test_autotune_writes_a_cache_that_loads(tmp_path):
     assert arch.startswith("gfx") and arch in data
     entries = data[arch]
     assert any(k.startswith("gemm.f32.solve.") for k in entries)
-    assert "schur.split_k" in entries and "schur.key_z" in entries
+    assert "schur.split_k" in entries and "schur.key_z" in entries and "schur.split_big" in entries
     P.h2_tune_clear()
     P.h2_tune_load(path)
     for k, v in entries.items():

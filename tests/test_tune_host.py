@@ -35,6 +35,7 @@ def test_set_get_and_clear():
     ("gemm.f16.solve.a1b0.m3", 0),      # unknown precision
     ("schur.split_k", 8),               # below range
     ("schur.key_z", 2),
+    ("schur.split_big", -1),
     ("no.such.key", 1),
 ])
 def test_rejects_bad_entries(key, value):
