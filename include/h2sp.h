@@ -369,7 +369,10 @@ int h2_last_work(double* work, int count);
  *   "schur.order_min" (default 16384): reorder levels with at least this many
  *     tiles;
  *   "schur.split_big" (0 or 1, default 0): cut targets of 6 to 8 blocks of 16
- *     into tiles of half the edge (more waves per SIMD, more operand reads).
+ *     into tiles of half the edge (more waves per SIMD, more operand reads);
+ *   "solve.split_k" (16..2^30, default 2048): the triangular solves cut a
+ *     target whose sources add up to more than 1.5 times this many rows into
+ *     parts of about this many (partial sums reduced in a fixed order).
  * The environment variables below override the Schur knobs.  Work lists
  * already planned are planned again after any change.  h2_tune_set replaces
  * one entry (EINVAL for unknown keys, values out of range or variants that are
@@ -385,7 +388,8 @@ int h2_last_work(double* work, int count);
  * sides (1..512), measures every built variant of each GEMM kind that the
  * sparsification, the ILU(0) factorisation, the preconditioner application
  * and the FP64 product plan, and the Schur knobs (split_k in {256, 512, 1024,
- * 2048}, key_z and split_big in {0, 1}), one key at a time with the others fixed (device
+ * 2048}, key_z and split_big in {0, 1}; the solve's split_k in {512, 1024, 2048, 4096,
+ * 2^30}), one key at a time with the others fixed (device
  * time of the phase, or the time of the synchronous call), keeps the fastest
  * of each in the table and, with a path, saves it.  Runs each phase several
  * times: seconds to minutes.  Uses the stream of h2_set_stream.

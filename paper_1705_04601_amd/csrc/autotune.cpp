@@ -160,6 +160,7 @@ extern "C" int h2_autotune(h2_matrix* h, int precision, int64_t nrhs, const char
         tune_reset_used();
         apply_ms();
         for (const std::string& k : used_keys("solve")) descend(k, variants_of(k), 3, apply_ms, log);
+        descend("solve.split_k", {512, 1024, 2048, 4096, int64_t(1) << 30}, 3, apply_ms, log);
       } catch (...) {
         h2_factor_destroy(f);
         h2_sparse_destroy(sp);

@@ -161,7 +161,7 @@ struct GemmBatch {
       for (const GemmItem& it : items) max_m = std::max(max_m, int(it.M));
       variant = tune_gemm_variant(prec, role, amode, bmode, gemm_row_bucket(max_m));
       const int code = gemm_shape(prec, role, amode, bmode, variant);
-      em = 16 * (code >> 4);
+      em = 16 * ((code >> 4) & 15);
       en = 16 * (code & 15);
     }
     // the solve sweeps give the row tiles of one tile column (the right-hand

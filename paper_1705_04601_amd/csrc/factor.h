@@ -19,6 +19,15 @@ struct SolvePlan {
   std::vector<GemmBatch> up, down;       // U^T and V sweeps, per tree level
   std::vector<GemmBatch> fwd, bwd;       // triangular solves, per DAG level
   GemmBatch diag;                        // D^{-1}
+  // long chains of the triangular solves cut into parts: parts after the
+  // first store partial sums (in `part`), which a reduction per level then
+  // subtracts from the target in part order
+  DeviceBuffer part, red;
+  void* part_ptr = nullptr;
+  void* y_ptr = nullptr;                 // the vectors the fwd and bwd levels update
+  void* w_ptr = nullptr;
+  const SchurReduce* d_red = nullptr;
+  std::vector<int> fred_off, fred_cnt, bred_off, bred_cnt;  // per level: range in d_red
   LaunchGraph apply;                     // the whole application, captured once
 };
 

@@ -384,6 +384,7 @@ __attribute__((amdgpu_waves_per_eu(MB * NB * int(sizeof(T)) >= 128 ? 2 : 1))) vo
                                               it.gparam);
     }
   }
+  const int mode = it.store ? int(GEMM_STORE) : g.mode;
 #pragma unroll
   for (int bm = 0; bm < MB; ++bm)
 #pragma unroll
@@ -397,20 +398,194 @@ __attribute__((amdgpu_waves_per_eu(MB * NB * int(sizeof(T)) >= 128 ? 2 : 1))) vo
         const int q = (row >= it.rs ? 2 : 0) + (col >= it.cs ? 1 : 0);
         const int lr = row - (q >= 2 ? it.rs : 0), lc = col - ((q & 1) ? it.cs : 0);
         const T val = acc[bm][bn][v];
-        store_out<T>(it, q, lr, lc, val, g.mode);
-        if (q == 0) store_out<T>(it, 4, lr, lc, val, g.mode);
+        store_out<T>(it, q, lr, lc, val, mode);
+        if (q == 0) store_out<T>(it, 4, lr, lc, val, mode);
       }
     }
 }
 
+
+
+// LDS-staged solve tile (FP32): the work-group's W waves cover W x 32 rows (the
+// right-hand sides) of one column tile of NB blocks of 16.  Each 16-wide k
+// step of the item's chunk stream is loaded once for the whole work-group,
+// A (the right-hand-side block, m-contiguous) into sA[k][m] and B (the S or
+// Q_t block) into sB[n][k], with the same buffer resources as pipe_fetch
+// (reads past a block return zero); the next step's loads are in flight
+// while the waves multiply the current one out of LDS, and one barrier per
+// step hands the buffers over.  Lane (r, g) reads the same k = 4 g + s of the
+// same rows and columns as the other solve kernels, so the sums run in the
+// same order.  Waves whose rows lie past the item load and wait like the
+// others but compute nothing.
+constexpr int kLdsAS = 132;  // sA row stride (words): 4 k rows apart land 16 banks apart
+constexpr int kLdsBS = 20;   // sB row stride (words): 16 k + 4, rows 16-byte aligned
+
+template <int BM, int NB, int W>
+struct LdsStage {
+  static constexpr int NA = 2;                        // float4 loads of A per thread
+  static constexpr int NBL = (64 * NB + 64 * W - 1) / (64 * W);  // float4 loads of B per thread
+  f4 a[NA];
+  f4 b[NBL];
+};
+
+template <int BM, int NB, int W>
+__device__ __forceinline__ void lds_fetch(const PipeCursor<float, BM, 2, NB>& c, int mg0, int n0, int N, int tid,
+                                          LdsStage<BM, NB, W>& r) {
+  constexpr int T = 64 * W;
+  const int K = c.K, lda = c.lda, ldb = c.ldb, k0 = c.k0;
+  const uint32_t na = c.valid ? uint32_t((K - k0) * lda) * 4u : 0u;
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.A + int64_t(k0) * lda, na);
+#pragma unroll
+  for (int j = 0; j < LdsStage<BM, NB, W>::NA; ++j) {
+    const int f = tid + j * T;  // 16 k rows of 8 W float4
+    const int k = f / (8 * W), mq = f % (8 * W);
+    r.a[j] = raw_buffer_load_f4(ra, int(uint32_t(k * lda + mg0 + 4 * mq) * 4u), 0, 0);
+  }
+  if constexpr (BM == 0) {
+    const uint32_t nb = c.valid ? uint32_t(N * ldb - k0) * 4u : 0u;
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.B + k0, nb);
+#pragma unroll
+    for (int j = 0; j < LdsStage<BM, NB, W>::NBL; ++j) {
+      const int f = tid + j * T;  // NB 16 columns of 4 float4
+      const int col = f / 4, kq4 = f % 4;
+      const uint32_t off = f < 64 * NB ? uint32_t((n0 + col) * ldb + 4 * kq4) * 4u : kOutside;
+      r.b[j] = raw_buffer_load_f4(rb, int(off), 0, 0);
+    }
+  } else {
+    const uint32_t nb = c.valid ? uint32_t((K - k0) * ldb) * 4u : 0u;
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.B + int64_t(k0) * ldb, nb);
+#pragma unroll
+    for (int j = 0; j < LdsStage<BM, NB, W>::NBL; ++j) {
+      const int f = tid + j * T;  // 16 k rows of 4 NB float4
+      const int k = f / (4 * NB), nq = f % (4 * NB);
+      const uint32_t off = f < 64 * NB ? uint32_t(k * ldb + n0 + 4 * nq) * 4u : kOutside;
+      r.b[j] = raw_buffer_load_f4(rb, int(off), 0, 0);
+    }
+  }
+}
+
+template <int BM, int NB, int W>
+__device__ __forceinline__ void lds_store(const LdsStage<BM, NB, W>& r, float* sA, float* sB, int tid) {
+  constexpr int T = 64 * W;
+#pragma unroll
+  for (int j = 0; j < LdsStage<BM, NB, W>::NA; ++j) {
+    const int f = tid + j * T;
+    const int k = f / (8 * W), mq = f % (8 * W);
+    *reinterpret_cast<f4*>(sA + k * kLdsAS + 4 * mq) = r.a[j];
+  }
+#pragma unroll
+  for (int j = 0; j < LdsStage<BM, NB, W>::NBL; ++j) {
+    const int f = tid + j * T;
+    if (f < 64 * NB) {
+      if constexpr (BM == 0) {
+        const int col = f / 4, kq4 = f % 4;
+        *reinterpret_cast<f4*>(sB + col * kLdsBS + 4 * kq4) = r.b[j];
+      } else {
+        const int k = f / (4 * NB), nq = f % (4 * NB);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sB[(4 * nq + e) * kLdsBS + k] = r.b[j][e];
+      }
+    }
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void lds_mfma(f4 (&acc)[2][NB], const float* sA, const float* sB, int wrow, int lane,
+                                         int nbn) {
+  const int r = lane % 16, g = lane / 16;
+  float a[2][4];
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[bm][s] = sA[(4 * g + s) * kLdsAS + wrow + 16 * bm + r];
+#pragma unroll
+  for (int bn = 0; bn < NB; ++bn)
+    if (bn == 0 || bn < nbn) {
+      const f4 b = *reinterpret_cast<const f4*>(sB + (16 * bn + r) * kLdsBS + 4 * g);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm) acc[bm][bn] = Mfma<float>::run(b[s], a[bm][s], acc[bm][bn]);
+    }
+}
+
+template <int BM, int NB, int W>
+__global__ __launch_bounds__(64 * W) void gemm_solve_lds_kernel(GemmLaunch g) {
+  __shared__ __attribute__((aligned(16))) float sA[2][16 * kLdsAS];
+  __shared__ __attribute__((aligned(16))) float sB[2][16 * NB * kLdsBS];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const uint32_t code = static_cast<uint32_t>(g.tiles[blockIdx.x]);
+  const GemmItem it = g.items[code >> 8];
+  const int mg0 = int((code >> 4) & 15) * W * 32;
+  const int m0 = mg0 + 32 * wave, n0 = int(code & 15) * 16 * NB;
+  const int nbm = m0 < it.M ? min(2, (it.M - m0 + 15) / 16) : 0;
+  const int nbn = min(NB, (it.N - n0 + 15) / 16);
+  f4 acc[2][NB];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = f4{0, 0, 0, 0};
+  if (it.seg_begin < it.seg_end) {
+    const int r = lane % 16, kq = 4 * (lane / 16);
+    PipeCursor<float, BM, 2, NB> c;
+    c.si = it.seg_begin;
+    c.se = it.seg_end;
+    c.k0 = 0;
+    c.valid = true;
+    c.dbase = c.si;
+    pipe_load_desc(c, g.segs, lane);
+    pipe_setup(c, m0, n0, 2, nbn, r, kq);  // the scalars; the lane offsets go unused here
+    LdsStage<BM, NB, W> st;
+    lds_fetch<BM, NB, W>(c, mg0, n0, it.N, tid, st);
+    lds_store<BM, NB, W>(st, sA[0], sB[0], tid);
+    __syncthreads();
+    for (int buf = 0;; buf ^= 1) {
+      pipe_next(c, g.segs, m0, n0, 2, nbn, r, kq, lane);
+      const bool more = c.valid;
+      lds_fetch<BM, NB, W>(c, mg0, n0, it.N, tid, st);
+      if (nbm > 0) lds_mfma<NB>(acc, sA[buf], sB[buf], 32 * wave, lane, nbn);
+      if (!more) break;
+      lds_store<BM, NB, W>(st, sA[buf ^ 1], sB[buf ^ 1], tid);
+      __syncthreads();
+    }
+  }
+  const int mode = it.store ? int(GEMM_STORE) : g.mode;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < NB; ++bn) {
+      if (bm >= nbm || bn >= nbn) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + 16 * bm + lane % 16;
+        const int col = n0 + 16 * bn + Mfma<float>::row(lane, v);
+        if (row >= it.M || col >= it.N) continue;
+        const int q = (row >= it.rs ? 2 : 0) + (col >= it.cs ? 1 : 0);
+        const int lr = row - (q >= 2 ? it.rs : 0), lc = col - ((q & 1) ? it.cs : 0);
+        const float val = acc[bm][bn][v];
+        store_out<float>(it, q, lr, lc, val, mode);
+        if (q == 0) store_out<float>(it, 4, lr, lc, val, mode);
+      }
+    }
+}
 
 // Launch of one built instance: variant V of a role and layout pair (a
 // variant that is not built launches nothing; the host plans only built ones).
 template <class T, int ROLE, int AM, int BM, int V>
 void launch_variant(const GemmLaunch& g, hipStream_t st) {
   constexpr int code = gemm_shape(sizeof(T) == 4 ? 1 : 0, ROLE, AM, BM, V);
-  if constexpr (code != 0) {
-    constexpr int MB = code >> 4, NB = code & 15;
+  if constexpr (code != 0 && (code & kGemmLds) != 0) {
+    if constexpr (ROLE == ROLE_SOLVE && AM == 1 && BM != 2 && sizeof(T) == 4 && ((code >> 4) & 15) == 2) {
+      constexpr int NB = code & 15;
+      switch (g.wg_rows) {
+        case 1: hipLaunchKernelGGL((gemm_solve_lds_kernel<BM, NB, 1>), dim3(g.ntiles), dim3(64), 0, st, g); break;
+        case 2: hipLaunchKernelGGL((gemm_solve_lds_kernel<BM, NB, 2>), dim3(g.ntiles), dim3(128), 0, st, g); break;
+        case 3: hipLaunchKernelGGL((gemm_solve_lds_kernel<BM, NB, 3>), dim3(g.ntiles), dim3(192), 0, st, g); break;
+        default: hipLaunchKernelGGL((gemm_solve_lds_kernel<BM, NB, 4>), dim3(g.ntiles), dim3(256), 0, st, g); break;
+      }
+    }
+  } else if constexpr (code != 0) {
+    constexpr int MB = (code >> 4) & 15, NB = code & 15;
     if constexpr (AM == 2 || BM == 2) {
       if (g.kern == 1) {
         hipLaunchKernelGGL((gemm_kc_kernel<T, ROLE, AM, BM, MB, NB, 1>), dim3(g.ntiles), dim3(ROLE == ROLE_SOLVE ? 64 * g.wg_rows : 64), 0, st, g);

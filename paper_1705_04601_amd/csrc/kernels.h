@@ -40,6 +40,7 @@ struct GemmItem {
   int32_t ld[5];
   uint8_t trans[5];
   uint8_t gkern;           // generated operands: 0 inverse distance, 1 exp(-r^2), 2 r/d | d/r
+  uint8_t store;           // 1: store the sum (a partial sum of a split item), whatever the launch's mode
   int32_t gdim;            // generated operands: point dimension
   double gscale, gdiag;    // generated operands: kernel scale, diagonal value
   double gparam;           // generated operands: d of kernel 2
@@ -69,21 +70,23 @@ struct GemmLaunch {
 
 // Output tile shapes the GEMM kernel is built with, per role and operand
 // layout pair: variant v in precision prec (0 FP64, 1 FP32) is a tile of
-// (code >> 4) x (code & 15) blocks of 16 x 16 (rows x columns), code 0 when
+// ((code >> 4) & 15) x (code & 15) blocks of 16 x 16 (rows x columns) per wave,
+// run by the LDS-staged kernel when code has kGemmLds, code 0 when
 // that variant is not built.  Variant 0 is the default; the tuning table
 // selects another per precision, role, layout and row bucket.  Measured
 // defaults: on short-K work (the solve sweeps, the pivot GEMMs, the transforms
 // with M-contiguous operands) 32 x 32 tiles, with more waves per SIMD, beat
 // 64 x 64; a generated operand is shared by more blocks in 64 x 32 tiles, and
 // the transforms whose two operands both run along K take 64 x 32 too.  The
-// solve sweeps also build 32 x 80 and 32 x 128 tiles, a whole target row of
-// the common non-basis sizes per wave (the work-group's waves cover the
-// right-hand sides and share the S block through the CU's cache).  FP64
+// solve sweeps also build the LDS-staged kernel, whose work-group stages each
+// 16-wide k step of the right-hand sides and of the S block once for all its
+// waves.  FP64
 // variants keep at most 16 blocks (the accumulators take twice the
 // registers), 8 in the solve sweeps, whose kernel holds two chunks of
 // operands.
 constexpr int kGemmVariants = 6;
 constexpr int kSolveWaves = 4;  // most waves (row tiles) per work-group of the solve sweeps
+constexpr int kGemmLds = 0x100; // shape flag: the solve kernel that stages operand chunks in LDS
 constexpr int gemm_pick(int v, int a, int b, int c, int d, int e = 0, int f = 0) {
   return v == 0 ? a : v == 1 ? b : v == 2 ? c : v == 3 ? d : v == 4 ? e : v == 5 ? f : 0;
 }
@@ -97,13 +100,16 @@ constexpr int gemm_shape(int prec, int role, int am, int bm, int v) {
                                           : 0;
       break;
     case ROLE_FACTOR: code = m == 0 ? gemm_pick(v, 0x22, 0x42, 0x44, 0) : 0; break;
-    case ROLE_SOLVE: code = (m == 3 || m == 4) ? gemm_pick(v, 0x22, 0x42, 0x24, 0x44, 0x25, 0x28) : 0; break;
+    case ROLE_SOLVE:
+      code = (m == 3 || m == 4) ? gemm_pick(v, 0x22, 0x42, 0x24, 0x44, kGemmLds | 0x22, kGemmLds | 0x24) : 0;
+      if (prec == 0 && (code & kGemmLds)) code = 0;  // the LDS-staged kernel is FP32 only
+      break;
     case ROLE_MATVEC:
       code = (m == 3 || m == 4) ? gemm_pick(v, 0x44, 0x42, 0x22, 0) : m == 5 ? gemm_pick(v, 0x42, 0x22, 0x44, 0) : 0;
       break;
     default: code = 0;
   }
-  if (prec == 0 && (code >> 4) * (code & 15) > (role == ROLE_SOLVE ? 8 : 16)) code = 0;
+  if (prec == 0 && ((code >> 4) & 15) * (code & 15) > (role == ROLE_SOLVE ? 8 : 16)) code = 0;
   return code;
 }
 // whether a role's kernels are built for a layout pair

@@ -117,43 +117,138 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs, Device
   };
   p->fwd.resize(f.nflev);
   p->bwd.resize(f.nblev);
+  // A target whose sources add up to more than 1.5 kt rows of K is cut at
+  // segment boundaries into parts of about kt: the target's chain is the
+  // level's critical path.  Part 0 subtracts its sum from the target; the
+  // others store theirs in the partial buffer, and a reduction subtracts
+  // them in part order (deterministic).
+  const i64 kt = tune_knob("solve.split_k", 2048);
+  std::vector<std::vector<Rec>> frec(f.nflev), brec(f.nblev);
+  std::vector<i64> fneed(f.nflev, 0), bneed(f.nblev, 0);
+  auto parts_of = [&](i64 ksum) -> i64 { return ksum * 2 > 3 * kt ? (ksum + kt - 1) / kt : 1; };
+  auto need_of = [&](const std::vector<Rec>& recs) {
+    i64 need = 0;
+    for (size_t r = 0; r < recs.size();) {
+      const i64 ct = sp.eorder[recs[r].target];
+      i64 ksum = 0;
+      for (; r < recs.size() && sp.eorder[recs[r].target] == ct; ++r)
+        ksum += mb[sp.eorder[recs[r].src]];
+      need += (parts_of(ksum) - 1) * nrhs * mb[ct];
+    }
+    return need;
+  };
 #pragma omp parallel for schedule(dynamic, 1)
   for (int lv = 0; lv < f.nflev; ++lv) {
-    std::vector<Rec> recs;
+    std::vector<Rec>& recs = frec[lv];
     for (i64 pk : fl[lv])
       for (i64 b = sp.rowptr[pk] + 1; b < sp.rowptr[pk + 1]; ++b) recs.push_back({sp.epos[sp.colidx[b]], pk, b});
     std::sort(recs.begin(), recs.end(), by_target);
-    GemmBatch& g = p->fwd[lv];
-    g.mode = GEMM_SUB;
-    for (size_t r = 0; r < recs.size();) {
-      const i64 ci = sp.eorder[recs[r].target];
-      // u_i^T -= u_k^T Z_ki  (Z_ki: m_k x m_i, ld m_k)
-      GemmItem& it = g.item(N, int(mb[ci]), N, int(mb[ci]));
-      GemmBatch::set_out(it, 0, y + sp.soff[ci] * nrhs, nrhs, false);
-      for (; r < recs.size() && sp.eorder[recs[r].target] == ci; ++r) {
-        const i64 ck = sp.eorder[recs[r].src];
-        g.seg(y + sp.soff[ck] * nrhs, N, false, S + sp.blk_off[recs[r].blk], int(mb[ck]), false, int(mb[ck]));
-      }
-    }
+    fneed[lv] = need_of(recs);
   }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int lv = 0; lv < f.nblev; ++lv) {
-    std::vector<Rec> recs;
+    std::vector<Rec>& recs = brec[lv];
     for (i64 pj : bl[lv])
       for (i64 b : colblk[pj]) recs.push_back({row_of[b], pj, b});
     std::sort(recs.begin(), recs.end(), by_target);
-    GemmBatch& g = p->bwd[lv];
+    bneed[lv] = need_of(recs);
+  }
+  i64 pcap = 1;
+  for (i64 v : fneed) pcap = std::max(pcap, v);
+  for (i64 v : bneed) pcap = std::max(pcap, v);
+  T* part;
+  if (arena) {
+    part = static_cast<T*>(arena->take(sizeof(T) * pcap));
+  } else {
+    p->part.reset(sizeof(T) * pcap);
+    part = p->part.as<T>();
+  }
+  p->part_ptr = part;
+  p->y_ptr = y;
+  p->w_ptr = w;
+  std::vector<std::vector<SchurReduce>> fred(f.nflev), bred(f.nblev);
+  // one level's items: sources of each target in elimination order, cut into parts
+  auto build_level = [&](const std::vector<Rec>& recs, GemmBatch& g, std::vector<SchurReduce>& reds, T* vec,
+                         bool fwd_side) {
     g.mode = GEMM_SUB;
+    i64 poff = 0;
     for (size_t r = 0; r < recs.size();) {
-      const i64 ck = sp.eorder[recs[r].target];
-      // x_k^T -= x_j^T Z_kj^T  (Z_kj: m_k x m_j, ld m_k)
-      GemmItem& it = g.item(N, int(mb[ck]), N, int(mb[ck]));
-      GemmBatch::set_out(it, 0, w + sp.soff[ck] * nrhs, nrhs, false);
-      for (; r < recs.size() && sp.eorder[recs[r].target] == ck; ++r) {
-        const i64 cj = sp.eorder[recs[r].src];
-        g.seg(w + sp.soff[cj] * nrhs, N, false, S + sp.blk_off[recs[r].blk], int(mb[ck]), true, int(mb[cj]));
+      const i64 ct = sp.eorder[recs[r].target];
+      size_t e = r;
+      i64 ksum = 0;
+      for (; e < recs.size() && sp.eorder[recs[e].target] == ct; ++e) ksum += mb[sp.eorder[recs[e].src]];
+      const i64 np = parts_of(ksum);
+      const i64 len = nrhs * mb[ct];
+      i64 acc = 0, part_no = 0;
+      GemmItem* it = nullptr;
+      for (size_t q = r; q < e; ++q) {
+        if (!it) {
+          it = &g.item(N, int(mb[ct]), N, int(mb[ct]));
+          if (part_no == 0) {
+            GemmBatch::set_out(*it, 0, vec + sp.soff[ct] * nrhs, nrhs, false);
+          } else {
+            GemmBatch::set_out(*it, 0, part + poff + (part_no - 1) * len, nrhs, false);
+            it->store = 1;
+          }
+        }
+        const i64 cs = sp.eorder[recs[q].src];
+        if (fwd_side) {
+          // u_i^T -= u_k^T Z_ki  (Z_ki: m_k x m_i, ld m_k)
+          g.seg(y + sp.soff[cs] * nrhs, N, false, S + sp.blk_off[recs[q].blk], int(mb[cs]), false, int(mb[cs]));
+        } else {
+          // x_k^T -= x_j^T Z_kj^T  (Z_kj: m_k x m_j, ld m_k)
+          g.seg(w + sp.soff[cs] * nrhs, N, false, S + sp.blk_off[recs[q].blk], int(mb[ct]), true, int(mb[cs]));
+        }
+        acc += mb[cs];
+        if (part_no < np - 1 && acc * np >= (part_no + 1) * ksum) {
+          ++part_no;
+          it = nullptr;
+        }
       }
+      if (np > 1) {
+        reds.push_back({sp.soff[ct] * nrhs, poff, int32_t(len), int32_t(np - 1)});
+        poff += (np - 1) * len;
+      }
+      r = e;
     }
+  };
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int lv = 0; lv < f.nflev; ++lv) {
+    build_level(frec[lv], p->fwd[lv], fred[lv], y, true);
+    std::vector<Rec>().swap(frec[lv]);
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int lv = 0; lv < f.nblev; ++lv) {
+    build_level(brec[lv], p->bwd[lv], bred[lv], w, false);
+    std::vector<Rec>().swap(brec[lv]);
+  }
+  std::vector<SchurReduce> reds;
+  p->fred_off.assign(f.nflev, 0);
+  p->fred_cnt.assign(f.nflev, 0);
+  p->bred_off.assign(f.nblev, 0);
+  p->bred_cnt.assign(f.nblev, 0);
+  for (int lv = 0; lv < f.nflev; ++lv) {
+    p->fred_off[lv] = int(reds.size());
+    p->fred_cnt[lv] = int(fred[lv].size());
+    reds.insert(reds.end(), fred[lv].begin(), fred[lv].end());
+  }
+  for (int lv = 0; lv < f.nblev; ++lv) {
+    p->bred_off[lv] = int(reds.size());
+    p->bred_cnt[lv] = int(bred[lv].size());
+    reds.insert(reds.end(), bred[lv].begin(), bred[lv].end());
+  }
+  if (!reds.empty()) {
+    const size_t bytes = reds.size() * sizeof(SchurReduce);
+    void* dst;
+    if (arena) {
+      dst = arena->take(bytes);
+    } else {
+      p->red.reset(bytes);
+      dst = p->red.ptr;
+    }
+    HIPCHECK(hipMemcpyAsync(dst, reds.data(), bytes, hipMemcpyHostToDevice, current_stream()));
+    HIPCHECK(hipStreamSynchronize(current_stream()));
+    p->d_red = static_cast<const SchurReduce*>(dst);
   }
   // v_i^T = u_i^T D_i^{-1}: D_i^{-1} is symmetric (D_i is), read as stored
   for (i64 pos : f.rows) {
@@ -200,9 +295,19 @@ static void apply_tree(h2_factor& f, SolvePlan& p, hipStream_t st) {
   const int L = f.sp->H->tree.depth;
   auto record = [&](hipStream_t s) {
     for (int k = 0; k <= L; ++k) p.up[k].launch<T>(s);
-    for (int lv = 0; lv < f.nflev; ++lv) p.fwd[lv].launch<T>(s);
+    for (int lv = 0; lv < f.nflev; ++lv) {
+      p.fwd[lv].launch<T>(s);
+      if (p.fred_cnt[lv] > 0)
+        launch_schur_reduce<T>(p.d_red + p.fred_off[lv], p.fred_cnt[lv], static_cast<const T*>(p.part_ptr),
+                               static_cast<T*>(p.y_ptr), s);
+    }
     p.diag.launch<T>(s);
-    for (int lv = 0; lv < f.nblev; ++lv) p.bwd[lv].launch<T>(s);
+    for (int lv = 0; lv < f.nblev; ++lv) {
+      p.bwd[lv].launch<T>(s);
+      if (p.bred_cnt[lv] > 0)
+        launch_schur_reduce<T>(p.d_red + p.bred_off[lv], p.bred_cnt[lv], static_cast<const T*>(p.part_ptr),
+                               static_cast<T*>(p.w_ptr), s);
+    }
     for (int k = L; k >= 0; --k) p.down[k].launch<T>(s);
   };
   if (p.eager) record(st);
