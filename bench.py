@@ -45,7 +45,8 @@ SCHUR_KERNELS = [("schur_cls0", "schur_kernel<float, 0>", 8, 10, 11),
 # HBM traffic of the Schur kernel measured with rocprofv3 counters; used only
 # while the kernel and its planner are the sources the counters were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_kernel_cube1m_traffic.txt")
-TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1705_04601_amd", "csrc", f) for f in ("kernels.hip", "factor.cpp")]
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1705_04601_amd", "csrc", f)
+                   for f in ("kernels.hip", "device_common.h", "factor.cpp")]
 
 
 def log(msg):

@@ -406,6 +406,8 @@ int h2_autotune(h2_matrix* h, int precision, int64_t nrhs, const char* path);
  * results do not depend on them beyond rounding order):
  *   H2SP_TRACE=1 host phase timings and statistics on stderr; =2 adds one line
  *     per factorisation level (tiles, flops, time, XCD spread, operand bytes);
+ *     =3 also times every launch of a preconditioner application (run eagerly)
+ *     and sums them by launch size;
  *   H2SP_SCHUR_UNITS (default 32768) and H2SP_SCHUR_SPLIT_K (default 512):
  *     split-K granularity of the Schur update (tile units per level, smallest
  *     K of a part);

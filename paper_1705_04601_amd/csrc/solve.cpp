@@ -310,6 +310,59 @@ static void apply_tree(h2_factor& f, SolvePlan& p, hipStream_t st) {
     }
     for (int k = L; k >= 0; --k) p.down[k].launch<T>(s);
   };
+  if (trace_level() >= 3) {
+    // every sweep launch timed on its own (eager), summed by launch size
+    struct Rec {
+      const GemmBatch* b;
+      hipEvent_t e0, e1;
+    };
+    std::vector<Rec> recs;
+    auto timed = [&](const GemmBatch& b) {
+      Rec r{&b, nullptr, nullptr};
+      HIPCHECK(hipEventCreate(&r.e0));
+      HIPCHECK(hipEventCreate(&r.e1));
+      HIPCHECK(hipEventRecord(r.e0, st));
+      b.launch<T>(st);
+      HIPCHECK(hipEventRecord(r.e1, st));
+      recs.push_back(r);
+    };
+    for (int k = 0; k <= L; ++k) timed(p.up[k]);
+    for (int lv = 0; lv < f.nflev; ++lv) {
+      timed(p.fwd[lv]);
+      if (p.fred_cnt[lv] > 0)
+        launch_schur_reduce<T>(p.d_red + p.fred_off[lv], p.fred_cnt[lv], static_cast<const T*>(p.part_ptr),
+                               static_cast<T*>(p.y_ptr), st);
+    }
+    timed(p.diag);
+    for (int lv = 0; lv < f.nblev; ++lv) {
+      timed(p.bwd[lv]);
+      if (p.bred_cnt[lv] > 0)
+        launch_schur_reduce<T>(p.d_red + p.bred_off[lv], p.bred_cnt[lv], static_cast<const T*>(p.part_ptr),
+                               static_cast<T*>(p.w_ptr), st);
+    }
+    for (int k = L; k >= 0; --k) timed(p.down[k]);
+    HIPCHECK(hipStreamSynchronize(st));
+    const int64_t edges[] = {0, 256, 1024, 4096, 16384, 65536, int64_t(1) << 40};
+    double ms[6] = {0}, fl[6] = {0};
+    int cnt[6] = {0};
+    for (const Rec& r : recs) {
+      float t = 0;
+      HIPCHECK(hipEventElapsedTime(&t, r.e0, r.e1));
+      int bkt = 0;
+      while (bkt < 5 && r.b->ntiles >= edges[bkt + 1]) ++bkt;
+      ms[bkt] += t;
+      fl[bkt] += r.b->flops;
+      ++cnt[bkt];
+      (void)hipEventDestroy(r.e0);
+      (void)hipEventDestroy(r.e1);
+    }
+    for (int bkt = 0; bkt < 6; ++bkt)
+      if (cnt[bkt])
+        std::fprintf(stderr, "[h2sp] solve sweep launches of %lld..%lld work-groups: %d launches, %.1f ms, %.2f TFLOP/s\n",
+                     (long long)edges[bkt], (long long)edges[bkt + 1] - 1, cnt[bkt], ms[bkt],
+                     fl[bkt] / (ms[bkt] * 1e-3) / 1e12);
+    return;
+  }
   if (p.eager) record(st);
   else p.apply.run(st, record);
 }

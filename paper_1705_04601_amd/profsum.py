@@ -28,7 +28,7 @@ import sys
 SCHUR = "schur_kernel<float, 1>"  # the Schur kernel of the whole leaf targets
 SCHUR_ANY = "schur_kernel<"
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SOURCES = [os.path.join(ROOT, "paper_1705_04601_amd", "csrc", f) for f in ("kernels.hip", "factor.cpp")]
+SOURCES = [os.path.join(ROOT, "paper_1705_04601_amd", "csrc", f) for f in ("kernels.hip", "device_common.h", "factor.cpp")]
 
 
 def _short(name: str) -> str:
