@@ -300,7 +300,10 @@ int h2_solve_with(const h2_matrix* a, h2_factor* f, const double* b, double* x, 
  * and the factors of one solve batch must belong to different matrices
  * (EINVAL otherwise: a matrix keeps one matvec plan and its vectors).
  * Any instance failing fails the call (first error reported); ENOCONV after
- * every instance ran if one of them stopped above the tolerance.
+ * every instance ran if one of them stopped above the tolerance.  A batched
+ * factorisation times each instance as a whole only: h2_last_timings gives
+ * the sum of the instances' totals in [7] and zero for the per-level phases
+ * [4], [5] and [8..10].
  */
 int h2_factor_S_batch(h2_sparse* const* sps, int count, const h2_factor_opts* opts, h2_factor** outs);
 int h2_solve_batch(h2_factor* const* fs, int count, const double* const* b, double* const* x,

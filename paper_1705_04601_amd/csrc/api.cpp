@@ -12,7 +12,7 @@
 #include "factor.h"
 
 namespace h2 {
-h2_factor* factor(h2_sparse* sp, int mode, double tau, hipStream_t st, double* phase_ms);
+h2_factor* factor(h2_sparse* sp, int mode, double tau, hipStream_t st, double* phase_ms, bool level_events);
 void analyze_fill(const h2_sparse& sp, double* entries, double* flops);
 void set_stream(hipStream_t s);
 std::string& last_error() {
@@ -213,7 +213,7 @@ extern "C" int h2_factor_S(h2_sparse* sp, const h2_factor_opts* opts, h2_factor*
   if (sp->factored) fail(H2_EINVAL, "S of this sparse handle is already factored");
   for (int i = 4; i < 12; ++i) g_timings[i] = 0;
   double ph[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  std::unique_ptr<h2_factor> f(factor(sp, mode, tau, current_stream(), ph));
+  std::unique_ptr<h2_factor> f(factor(sp, mode, tau, current_stream(), ph, true));
   g_timings[4] = ph[4];
   g_timings[5] = ph[5];
   g_timings[7] = ph[6];
@@ -334,7 +334,7 @@ extern "C" int h2_factor_S_batch(h2_sparse* const* sps, int count, const h2_fact
   std::vector<std::unique_ptr<h2_factor>> fs(count);
   std::vector<double> ph(size_t(count) * 10, 0.0);
   run_pooled(count, [&](int i) {
-    fs[i].reset(factor(sps[i], mode, tau, current_stream(), &ph[size_t(i) * 10]));
+    fs[i].reset(factor(sps[i], mode, tau, current_stream(), &ph[size_t(i) * 10], false));
   });
   std::fill(g_timings + 4, g_timings + 12, 0.0);
   std::fill(g_work + 4, g_work + 20, 0.0);

@@ -23,6 +23,7 @@
 // on a copy stream and queues their launches, so host planning overlaps the
 // device work of the levels before it.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cstdio>
 #include <cstdlib>
@@ -85,8 +86,11 @@ struct RowChunk {
 
 }  // namespace
 
+// level_events: time every level (pivots and Z, Schur update by tile class)
+// with events; else only the whole factorisation (many small instances of a
+// batch, where a few events per level cost more host time than their work).
 template <class T>
-static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
+static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool level_events) {
   TraceTimer tt("factor");
   h2_sparse& sp = *f.sp;
   const i64 ncl = sp.ncl;
@@ -660,6 +664,18 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     return e;
   };
   auto mark_ev = [&]() { return new_ev(ev, st); };
+  // events that only order the class streams after the level's Z (no timing)
+  std::vector<hipEvent_t> sync_ev;
+  auto sync_event = [&](hipStream_t s_) {
+    hipEvent_t e;
+    HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    sync_ev.push_back(e);
+    HIPCHECK(hipEventRecord(e, s_));
+    return e;
+  };
+  // per level and tile class: the index of its start event in cev, or -1
+  // when the class has no tiles there (nothing launched, nothing timed)
+  std::vector<std::array<int, kSchurClasses>> cls_at(f.nflev);
   // upload in runs of planned levels: as soon as the next level is ready,
   // every ready level after it (up to kMaxRun) goes in one copy
   constexpr int kMaxRun = 32;
@@ -733,19 +749,29 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         FactorLevel<T>& L = lvls[lv];
         L.zb.template launch<T>(st);
         launch_retile<T>(L.d_zts, int(L.zts.size()), Z, Zt, st);
-        const hipEvent_t fork = mark_ev();
-        for (int c = kSchurClasses - 1; c >= 0; --c) {
+        for (int c = 0; c < kSchurClasses; ++c) {
           L.ntiles_cls[c] = int32_t(L.stiles[c].size());
           L.nschur_tiles += L.ntiles_cls[c];
+        }
+        const bool fork_any = L.ntiles_cls[1] > 0 || L.ntiles_cls[2] > 0;
+        hipEvent_t fork = nullptr;
+        if (level_events) fork = mark_ev();
+        else if (fork_any) fork = sync_event(st);
+        cls_at[lv].fill(-1);
+        for (int c = kSchurClasses - 1; c >= 0; --c) {
+          if (L.ntiles_cls[c] == 0) continue;
           if (c > 0) HIPCHECK(hipStreamWaitEvent(cls_st[c], fork, 0));
-          new_ev(cev, cls_st[c]);
+          if (level_events) {
+            cls_at[lv][c] = int(cev.size());
+            new_ev(cev, cls_st[c]);
+          }
           SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles[c], int32_t(L.stiles[c].size()), S,
                          tiled_s ? St : S, Zt, Pbuf, tiled_s ? 1 : 0};
           launch_schur<T>(sl, c, cls_st[c]);
-          const hipEvent_t done = new_ev(cev, cls_st[c]);
+          const hipEvent_t done = level_events ? new_ev(cev, cls_st[c]) : (c > 0 ? sync_event(cls_st[c]) : nullptr);
           if (c > 0) HIPCHECK(hipStreamWaitEvent(st, done, 0));
         }
-        mark_ev();
+        if (level_events) mark_ev();
         launch_schur_reduce<T>(L.d_reds, int(L.reds.size()), Pbuf, S, st);
         // ILUt: the rows of the level are finished; small fill blocks go to zero
         // before anything reads them (tiled copies, Z of later levels, solves)
@@ -753,7 +779,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
         if (tiled_s) launch_retile<T>(L.d_sts, int(L.sts.size()), S, St, st);
         launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
         launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
-        mark_ev();
+        if (level_events) mark_ev();
         std::vector<SchurItem>().swap(L.sitems);
         PodVector<SchurSeg>().swap(L.ssegs);
         for (auto& tl : L.stiles) std::vector<int32_t>().swap(tl);
@@ -772,14 +798,14 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
     destroy_streams();
     for (auto e : ev) (void)hipEventDestroy(e);
     for (auto e : cev) (void)hipEventDestroy(e);
+    for (auto e : sync_ev) (void)hipEventDestroy(e);
     throw;
   }
   producer.join();
   destroy_streams();  // work already queued on a destroyed stream still completes
   if (perr) std::rethrow_exception(perr);
-  constexpr int kEv = 3;  // main-stream events per level
-  if (int(ev.size()) != kEv * f.nflev + 1 || int(cev.size()) != 2 * kSchurClasses * f.nflev)
-    fail(H2_EINVAL, "internal: factorisation stopped early");
+  constexpr int kEv = 3;  // main-stream events per level (level_events)
+  if (int(ev.size()) != (level_events ? kEv * f.nflev : 0) + 1) fail(H2_EINVAL, "internal: factorisation stopped early");
   f.flops_inv += fl_inv;
   f.flops_z += fl_z;
   f.flops_schur += fl_s;
@@ -816,16 +842,16 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
       if (f.drop_thr2[b] >= 0.0 && flag[b] < 2) (flag[b] ? f.ilut_dropped : f.ilut_kept) += 1;
   }
   double piv_ms = 0, schur_ms = 0, cls_ms[kSchurClasses] = {0, 0, 0};
-  for (int lv = 0; lv < f.nflev; ++lv) {
+  for (int lv = 0; level_events && lv < f.nflev; ++lv) {
     const hipEvent_t* e = &ev[size_t(kEv) * lv];
-    const hipEvent_t* ce = &cev[size_t(2 * kSchurClasses) * lv];  // classes from the last to 0
     float a = 0, c = 0, b = 0, bc[kSchurClasses] = {0, 0, 0};
     HIPCHECK(hipEventElapsedTime(&a, e[0], e[1]));
     HIPCHECK(hipEventElapsedTime(&b, e[1], e[2]));
     HIPCHECK(hipEventElapsedTime(&c, e[2], e[3]));
-    for (int k = 0; k < kSchurClasses; ++k) {
-      const int cls = kSchurClasses - 1 - k;
-      HIPCHECK(hipEventElapsedTime(&bc[cls], ce[2 * k], ce[2 * k + 1]));
+    for (int cls = 0; cls < kSchurClasses; ++cls) {
+      const int k = cls_at[lv][cls];
+      if (k < 0) continue;
+      HIPCHECK(hipEventElapsedTime(&bc[cls], cev[k], cev[k + 1]));
       cls_ms[cls] += bc[cls];
     }
     piv_ms += a + c;
@@ -849,6 +875,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms) {
   HIPCHECK(hipEventElapsedTime(&tot, ev.front(), ev.back()));
   for (auto e : ev) (void)hipEventDestroy(e);
   for (auto e : cev) (void)hipEventDestroy(e);
+  for (auto e : sync_ev) (void)hipEventDestroy(e);
   if (phase_ms) {
     phase_ms[4] = piv_ms;
     phase_ms[5] = schur_ms;
@@ -1020,7 +1047,7 @@ static std::vector<double> drop_thresholds(const h2_sparse& sp, double tau, hipS
   return thr2;
 }
 
-h2_factor* factor(h2_sparse* sp, int mode, double tau, hipStream_t st, double* phase_ms) {
+h2_factor* factor(h2_sparse* sp, int mode, double tau, hipStream_t st, double* phase_ms, bool level_events) {
   if (mode == H2_FACTOR_EXACT || mode == H2_FACTOR_ILUT) {
     if (sp->precision == H2_MIXED) extend_by_fill<float>(*sp, st);
     else extend_by_fill<double>(*sp, st);
@@ -1065,8 +1092,8 @@ h2_factor* factor(h2_sparse* sp, int mode, double tau, hipStream_t st, double* p
     f.drop_thr2 = sp->precision == H2_MIXED ? drop_thresholds<float>(*sp, tau, st) : drop_thresholds<double>(*sp, tau, st);
   f.dFlag.reset(sizeof(int));
   launch_fill_i(f.dFlag.as<int>(), 1, 0, st);
-  if (sp->precision == H2_MIXED) factor_levels<float>(f, st, phase_ms);
-  else factor_levels<double>(f, st, phase_ms);
+  if (sp->precision == H2_MIXED) factor_levels<float>(f, st, phase_ms, level_events);
+  else factor_levels<double>(f, st, phase_ms, level_events);
   int flag = 0;
   HIPCHECK(hipMemcpy(&flag, f.dFlag.ptr, sizeof(int), hipMemcpyDeviceToHost));
   if (flag) fail(H2_ESINGULAR, "singular pivot block in the factorisation of S");
