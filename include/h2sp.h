@@ -375,7 +375,10 @@ int h2_last_work(double* work, int count);
  *     into tiles of half the edge (more waves per SIMD, more operand reads);
  *   "solve.split_k" (16..2^30, default 2048): the triangular solves cut a
  *     target whose sources add up to more than 1.5 times this many rows into
- *     parts of about this many (partial sums reduced in a fixed order).
+ *     parts of about this many (partial sums reduced in a fixed order);
+ *   "solve.transpose" (0 or 1, default 0): the backward sweep reads a
+ *     transposed copy of the factored S (made once per factor, when it fits
+ *     in a third of the memory the device can give) instead of S itself.
  * The environment variables below override the Schur knobs.  Work lists
  * already planned are planned again after any change.  h2_tune_set replaces
  * one entry (EINVAL for unknown keys, values out of range or variants that are

@@ -52,6 +52,10 @@ struct h2_factor {
   // (fill blocks only; empty in the other modes) and the outcome
   std::vector<double> drop_thr2;
   h2::i64 ilut_dropped = 0, ilut_kept = 0;
+  // the factored S with every block transposed (same offsets), made for the
+  // backward sweep when it fits beside S; empty otherwise
+  h2::DeviceBuffer dST;
+  bool st_tried = false;
   std::unique_ptr<h2::SolvePlan> solve;
   ~h2_factor();
 };

@@ -241,6 +241,11 @@ struct CopySeg {
 };
 template <class T>
 void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st);
+// For every segment: dst + dst_off receives the transpose (cols x rows,
+// column-major) of the rows x cols column-major block at src + src_off
+// (src_ld = rows).  LDS tiles of 32 x 32, reads and writes both contiguous.
+template <class T>
+void launch_transpose_blocks(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st);
 // For every segment: the rows x cols block at src (leading dimension src_ld)
 // into 16 x 16 tiles at dst, in the order the Schur kernel's lanes read them:
 // tile (c, q) at dst + (q C + c) 256 with C = ceil(rows / 16), element

@@ -77,6 +77,39 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs, Device
   p->zin_ptr = zin;
   const T* Q = (sp.precision == H2_MIXED) ? sp.dQt.as<T>() : reinterpret_cast<const T*>(sp.dQ.as<double>());
   const T* S = sp.dS.as<T>();
+  // Operands of the backward sweep, when the tuning table asks: every block
+  // of S transposed (made once per factor, when it fits in a third of the
+  // memory the device can give), so that the backward sweep reads
+  // K-contiguous blocks like the forward one instead of strided ones.  Off by
+  // default: on the 1M-point cube it takes 7 ms off an application (239 vs
+  // 246 ms) and costs a pass over S per factor.
+  const T* ST = nullptr;
+  if (!arena && tune_knob("solve.transpose", 0) != 0) {
+    if (!f.st_tried) {
+      f.st_tried = true;
+      const size_t bytes = sizeof(T) * size_t(std::max<i64>(sp.s_entries, 1));
+      size_t free_b = 0, total_b = 0;
+      HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+      if (bytes <= (free_b + cached_device_bytes()) / 3) {
+        std::vector<CopySeg> segs;
+        for (i64 pos = 0; pos < ncl; ++pos) {
+          const int rows = int(mb[sp.eorder[pos]]);
+          for (i64 b = sp.rowptr[pos]; b < sp.rowptr[pos + 1]; ++b) {
+            const int cols = int(mb[sp.colidx[b]]);
+            if (rows > 0 && cols > 0) segs.push_back({sp.blk_off[b], sp.blk_off[b], rows, cols, rows, 0});
+          }
+        }
+        f.dST.reset(bytes);
+        DeviceBuffer dsegs(sizeof(CopySeg) * std::max<size_t>(segs.size(), 1));
+        HIPCHECK(hipMemcpyAsync(dsegs.ptr, segs.data(), sizeof(CopySeg) * segs.size(), hipMemcpyHostToDevice,
+                                current_stream()));
+        launch_transpose_blocks<T>(dsegs.as<CopySeg>(), int(segs.size()), S, f.dST.as<T>(), current_stream());
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(current_stream()));
+      }
+    }
+    if (f.dST.ptr) ST = f.dST.as<T>();
+  }
   (void)0;
   const T* Inv = f.dInv.as<T>();
   auto son_off = [&](i64 c) -> i64 { return (c % 2 == 1) ? 0 : kp[c - 1]; };
@@ -196,8 +229,11 @@ static std::unique_ptr<SolvePlan> make_solve_plan(h2_factor& f, i64 nrhs, Device
           // u_i^T -= u_k^T Z_ki  (Z_ki: m_k x m_i, ld m_k)
           g.seg(y + sp.soff[cs] * nrhs, N, false, S + sp.blk_off[recs[q].blk], int(mb[cs]), false, int(mb[cs]));
         } else {
-          // x_k^T -= x_j^T Z_kj^T  (Z_kj: m_k x m_j, ld m_k)
-          g.seg(w + sp.soff[cs] * nrhs, N, false, S + sp.blk_off[recs[q].blk], int(mb[ct]), true, int(mb[cs]));
+          // x_k^T -= x_j^T Z_kj^T  (Z_kj: m_k x m_j, ld m_k; its transpose m_j x m_k, ld m_j)
+          if (ST)
+            g.seg(w + sp.soff[cs] * nrhs, N, false, ST + sp.blk_off[recs[q].blk], int(mb[cs]), false, int(mb[cs]));
+          else
+            g.seg(w + sp.soff[cs] * nrhs, N, false, S + sp.blk_off[recs[q].blk], int(mb[ct]), true, int(mb[cs]));
         }
         acc += mb[cs];
         if (part_no < np - 1 && acc * np >= (part_no + 1) * ksum) {

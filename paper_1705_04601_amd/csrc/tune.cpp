@@ -49,6 +49,7 @@ constexpr Knob kKnobs[] = {
     {"schur.order_min", 1, int64_t(1) << 40},
     {"schur.split_big", 0, 1},
     {"solve.split_k", 16, int64_t(1) << 30},
+    {"solve.transpose", 0, 1},
 };
 
 // Parses "gemm.<f32|f64>.<role>.a<am>b<bm>.m<bucket>"; false if malformed.

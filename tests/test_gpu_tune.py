@@ -117,6 +117,21 @@ def test_schur_knobs():
     assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("precision", [P.H2_MIXED, P.H2_FP64])
+def test_transposed_backward_operands_give_the_same_bits(precision):
+    """The backward sweep on the transposed copy of S (K-contiguous blocks)
+    against the sweep that reads S's blocks strided: the same sums in the same
+    order."""
+    torch.cuda.set_device(0)
+    h = _matrix()
+    b = _rhs(40, 12)
+    P.h2_tune_set("solve.transpose", 0)
+    ref = _apply(h, precision, b)
+    P.h2_tune_set("solve.transpose", 1)
+    got = _apply(h, precision, b)
+    assert np.array_equal(got, ref)
+
+
 def test_split_big_targets_gives_the_same_bits():
     """Targets of 6 to 8 blocks of 16 cut into half-edge tiles (class 0): the
     class-2 kernel no longer runs and every sum keeps its order."""

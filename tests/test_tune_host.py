@@ -36,6 +36,7 @@ def test_set_get_and_clear():
     ("schur.split_k", 8),               # below range
     ("schur.key_z", 2),
     ("schur.split_big", -1),
+    ("solve.transpose", 2),
     ("no.such.key", 1),
 ])
 def test_rejects_bad_entries(key, value):
