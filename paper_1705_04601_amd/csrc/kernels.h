@@ -105,7 +105,9 @@ constexpr int gemm_shape(int prec, int role, int am, int bm, int v) {
       if (prec == 0 && (code & kGemmLds)) code = 0;  // the LDS-staged kernel is FP32 only
       break;
     case ROLE_MATVEC:
-      code = (m == 3 || m == 4) ? gemm_pick(v, 0x44, 0x42, 0x22, 0) : m == 5 ? gemm_pick(v, 0x42, 0x22, 0x44, 0) : 0;
+      code = (m == 3 || m == 4) ? gemm_pick(v, 0x44, 0x42, 0x22, 0)
+             : m == 5           ? gemm_pick(v, 0x42, 0x22, 0x44, 0x81)
+                                : 0;
       break;
     default: code = 0;
   }

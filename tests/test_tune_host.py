@@ -28,7 +28,7 @@ def test_set_get_and_clear():
 @pytest.mark.parametrize("key,value", [
     ("gemm.f32.solve.a1b0.m3", 6),      # no seventh variant
     ("gemm.f64.solve.a1b0.m3", 3),      # 64 x 64 is not built for the FP64 solve
-    ("gemm.f64.matvec.a1b2.m3", 3),     # no fourth matvec variant
+    ("gemm.f64.matvec.a1b2.m3", 4),     # no fifth matvec variant
     ("gemm.f32.solve.a0b0.m3", 0),      # no solve kernel for this layout
     ("gemm.f32.solver.a1b0.m3", 0),     # unknown role
     ("gemm.f32.solve.a1b0.m4", 0),      # unknown bucket
