@@ -175,10 +175,11 @@ __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[MB][NB
   }
 }
 
-// Pipelined path of the stored layouts with A M-contiguous (the solve sweeps:
-// A is a block of right-hand sides, element (m, k) at A[m + k lda]; B is a
-// block of S or Q_t, K-contiguous (BM 0: (k, n) at B[k + n ldb]) or
-// N-contiguous (BM 1: (k, n) at B[n + k ldb])).  The item's (segment, 16-wide
+// Pipelined path of the stored layouts with A M-contiguous (the solve sweeps,
+// where A is a block of right-hand sides and B a block of S or Q_t, and the
+// transforms of that layout): element (m, k) of A at A[m + k lda]; B
+// K-contiguous (BM 0: (k, n) at B[k + n ldb]) or N-contiguous (BM 1: (k, n) at
+// B[n + k ldb]).  The item's (segment, 16-wide
 // k step) pairs form one chunk stream read through two register sets: the
 // loads of the next chunk are in flight while the MFMAs of the current one
 // issue.  Every chunk issues the same loads, through buffer resources that
@@ -277,7 +278,7 @@ __device__ __forceinline__ void pipe_next(PipeCursor<T, BM, MB, NB>& c, const Ge
 // The same loads for every chunk: resources start at the chunk (A: k0 rows
 // on, B: k0 on along K) and end with the segment's block.
 template <class T, int BM, int MB, int NB>
-__device__ __forceinline__ void pipe_fetch(const PipeCursor<T, BM, MB, NB>& c, int N, T (&a)[MB][4],
+__device__ __forceinline__ void pipe_fetch(const PipeCursor<T, BM, MB, NB>& c, int N, int kq, T (&a)[MB][4],
                                            T (&b)[NB][4]) {
   const int K = c.K, lda = c.lda, ldb = c.ldb, k0 = c.k0;
   const uint32_t na = c.valid ? uint32_t((K - k0) * lda) * uint32_t(sizeof(T)) : 0u;
@@ -289,8 +290,15 @@ __device__ __forceinline__ void pipe_fetch(const PipeCursor<T, BM, MB, NB>& c, i
   if constexpr (BM == 0) {
     const uint32_t nb = c.valid ? uint32_t(N * ldb - k0) * uint32_t(sizeof(T)) : 0u;
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.B + k0, nb);
+    // k past K inside a column (when ldb > K) is storage outside the block,
+    // whatever it holds: read as zero
+    const int kr = K - k0 - kq;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) BufLoad4<T>::run(rb, c.ob[q][0], b[q]);
+    for (int q = 0; q < NB; ++q) {
+      BufLoad4<T>::run(rb, c.ob[q][0], b[q]);
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) b[q][s2] = s2 < kr ? b[q][s2] : T(0);
+    }
   } else {
     const uint32_t nb = c.valid ? uint32_t((K - k0) * ldb) * uint32_t(sizeof(T)) : 0u;
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.B + int64_t(k0) * ldb, nb);
@@ -334,12 +342,12 @@ __device__ __forceinline__ void pipe_item(typename Mfma<T>::V (&acc)[MB][NB], co
   pipe_load_desc(c, g.segs, lane);
   pipe_setup(c, m0, n0, nbm, nbn, r, kq);
   T a[2][MB][4], b[2][NB][4];
-  pipe_fetch(c, it.N, a[0], b[0]);
+  pipe_fetch(c, it.N, kq, a[0], b[0]);
   while (true) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       pipe_next(c, g.segs, m0, n0, nbm, nbn, r, kq, lane);
-      pipe_fetch(c, it.N, a[1 - i], b[1 - i]);
+      pipe_fetch(c, it.N, kq, a[1 - i], b[1 - i]);
       __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
       pipe_mfma<T, MB, NB>(acc, a[i], b[i], nbn);
       __builtin_amdgcn_sched_barrier(0);
@@ -375,7 +383,7 @@ __attribute__((amdgpu_waves_per_eu(MB * NB * int(sizeof(T)) >= 128 ? 2 : 1))) vo
   for (int a = 0; a < MB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = V{0, 0, 0, 0};
-  if constexpr (ROLE == ROLE_SOLVE && AM == 1 && BM != 2) {
+  if constexpr ((ROLE == ROLE_SOLVE || ROLE == ROLE_TRANSFORM) && AM == 1 && BM != 2) {
     pipe_item<T, BM, MB, NB>(acc, g, it, m0, n0, nbm, nbn, lane);
   } else {
     for (int si = it.seg_begin; si < it.seg_end; ++si) {
