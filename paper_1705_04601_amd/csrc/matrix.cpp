@@ -56,15 +56,18 @@ static void check_duplicates(const h2_matrix& H) {
 
 using namespace h2;
 
+// One thread at a time per matrix (the batched entry points reject a matrix
+// that appears twice); marked done only once every copy is in place, so that
+// a failed upload is retried rather than leaving null device pointers.
 void h2_matrix::upload_all() {
   if (on_device) return;
-  on_device = true;
   d_x = upload(x_tree);
   d_nodes = upload(nodes);
   d_proj = upload(proj);
   d_basis = upload(basis);
   d_transfer = upload(transfer);
   d_perm = upload(tree.perm);
+  on_device = true;
 }
 
 // ---------------------------------------------------------------- matvec plan
