@@ -191,8 +191,9 @@ __device__ __forceinline__ void direct_segment(typename Mfma<T>::V (&acc)[MB][NB
 // both give the same bits.  Segment descriptors are loaded 64 at a time, one
 // per lane, and taken out with readlane, so that moving to the next segment
 // waits for no memory.
-template <class T, int BM, int MB, int NB>
+template <class T, int BM, int MB, int NB, int AM = 1>
 struct PipeCursor {
+  static constexpr int AL = AM == 0 ? 1 : 4;  // A loads per block and chunk
   static constexpr int BL = BM == 0 ? 1 : 4;  // B loads per block and chunk
   int si, se, k0;
   bool valid;
@@ -201,13 +202,13 @@ struct PipeCursor {
   const T* A;                      // the current segment (wave-uniform)
   const T* B;
   int K, lda, ldb;
-  uint32_t oa[MB][4], ob[NB][BL];  // lane offsets inside a chunk (bytes), fixed per segment
+  uint32_t oa[MB][AL], ob[NB][BL];  // lane offsets inside a chunk (bytes), fixed per segment
 };
 
 // Descriptors of segments dbase .. dbase + 63, one per lane (vector loads, so
 // that a segment switch reads registers only).
-template <class T, int BM, int MB, int NB>
-__device__ __forceinline__ void pipe_load_desc(PipeCursor<T, BM, MB, NB>& c, const GemmSeg* segs, int lane) {
+template <class T, int BM, int MB, int NB, int AM>
+__device__ __forceinline__ void pipe_load_desc(PipeCursor<T, BM, MB, NB, AM>& c, const GemmSeg* segs, int lane) {
   static_assert(sizeof(GemmSeg) == 40, "descriptor layout: A, B, pc, K, lda, ldb, flags");
   const int i = c.dbase + lane < c.se ? c.dbase + lane : c.se - 1;
   const uint32_t* w = reinterpret_cast<const uint32_t*>(segs + i);
@@ -225,8 +226,8 @@ __device__ __forceinline__ void pipe_load_desc(PipeCursor<T, BM, MB, NB>& c, con
 
 // The current segment's fields and lane offsets (blocks outside the item:
 // kOutside).
-template <class T, int BM, int MB, int NB>
-__device__ __forceinline__ void pipe_setup(PipeCursor<T, BM, MB, NB>& c, int m0, int n0, int nbm, int nbn, int r,
+template <class T, int BM, int MB, int NB, int AM>
+__device__ __forceinline__ void pipe_setup(PipeCursor<T, BM, MB, NB, AM>& c, int m0, int n0, int nbm, int nbn, int r,
                                            int kq) {
   const int idx = c.si - c.dbase;
   auto rd = [&](int k) { return uint32_t(__builtin_amdgcn_readlane(int(c.d[k]), idx)); };
@@ -237,10 +238,15 @@ __device__ __forceinline__ void pipe_setup(PipeCursor<T, BM, MB, NB>& c, int m0,
   c.ldb = int(rd(6));
   const int lda = c.lda, ldb = c.ldb;
 #pragma unroll
-  for (int q = 0; q < MB; ++q)
+  for (int q = 0; q < MB; ++q) {
+    if constexpr (AM == 0) {
+      c.oa[q][0] = q < nbm ? uint32_t((m0 + 16 * q + r) * lda + kq) * uint32_t(sizeof(T)) : kOutside;
+    } else {
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-      c.oa[q][s] = q < nbm ? uint32_t((kq + s) * lda + m0 + 16 * q + r) * uint32_t(sizeof(T)) : kOutside;
+      for (int s = 0; s < 4; ++s)
+        c.oa[q][s] = q < nbm ? uint32_t((kq + s) * lda + m0 + 16 * q + r) * uint32_t(sizeof(T)) : kOutside;
+    }
+  }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     if constexpr (BM == 0) {
@@ -253,8 +259,8 @@ __device__ __forceinline__ void pipe_setup(PipeCursor<T, BM, MB, NB>& c, int m0,
   }
 }
 
-template <class T, int BM, int MB, int NB>
-__device__ __forceinline__ void pipe_next(PipeCursor<T, BM, MB, NB>& c, const GemmSeg* segs, int m0, int n0,
+template <class T, int BM, int MB, int NB, int AM>
+__device__ __forceinline__ void pipe_next(PipeCursor<T, BM, MB, NB, AM>& c, const GemmSeg* segs, int m0, int n0,
                                           int nbm, int nbn, int r, int kq, int lane) {
   if (!c.valid) return;
   c.k0 += 16;
@@ -277,16 +283,30 @@ __device__ __forceinline__ void pipe_next(PipeCursor<T, BM, MB, NB>& c, const Ge
 
 // The same loads for every chunk: resources start at the chunk (A: k0 rows
 // on, B: k0 on along K) and end with the segment's block.
-template <class T, int BM, int MB, int NB>
-__device__ __forceinline__ void pipe_fetch(const PipeCursor<T, BM, MB, NB>& c, int N, int kq, T (&a)[MB][4],
-                                           T (&b)[NB][4]) {
+template <class T, int BM, int MB, int NB, int AM>
+__device__ __forceinline__ void pipe_fetch(const PipeCursor<T, BM, MB, NB, AM>& c, int M, int N, int kq,
+                                           T (&a)[MB][4], T (&b)[NB][4]) {
   const int K = c.K, lda = c.lda, ldb = c.ldb, k0 = c.k0;
-  const uint32_t na = c.valid ? uint32_t((K - k0) * lda) * uint32_t(sizeof(T)) : 0u;
-  const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.A + int64_t(k0) * lda, na);
+  if constexpr (AM == 0) {
+    // A K-contiguous ((m, k) at A[k + m lda]): four k of a row per load, k
+    // past K inside a row read as zero
+    const uint32_t na = c.valid ? uint32_t(M * lda - k0) * uint32_t(sizeof(T)) : 0u;
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.A + k0, na);
+    const int kr = K - k0 - kq;
 #pragma unroll
-  for (int q = 0; q < MB; ++q)
+    for (int q = 0; q < MB; ++q) {
+      BufLoad4<T>::run(ra, c.oa[q][0], a[q]);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) a[q][s] = BufLoad1<T>::run(ra, c.oa[q][s]);
+      for (int s2 = 0; s2 < 4; ++s2) a[q][s2] = s2 < kr ? a[q][s2] : T(0);
+    }
+  } else {
+    const uint32_t na = c.valid ? uint32_t((K - k0) * lda) * uint32_t(sizeof(T)) : 0u;
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.A + int64_t(k0) * lda, na);
+#pragma unroll
+    for (int q = 0; q < MB; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[q][s] = BufLoad1<T>::run(ra, c.oa[q][s]);
+  }
   if constexpr (BM == 0) {
     const uint32_t nb = c.valid ? uint32_t(N * ldb - k0) * uint32_t(sizeof(T)) : 0u;
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.B + k0, nb);
@@ -328,12 +348,12 @@ __device__ __forceinline__ void pipe_mfma(typename Mfma<T>::V (&acc)[MB][NB], co
 // Two register sets: the loop multiplies one chunk while the next one's
 // loads are in flight, and leaves once per two chunks; a chunk past the
 // item's end reads zeros, so multiplying it adds nothing.
-template <class T, int BM, int MB, int NB>
+template <class T, int AM, int BM, int MB, int NB>
 __device__ __forceinline__ void pipe_item(typename Mfma<T>::V (&acc)[MB][NB], const GemmLaunch& g,
                                           const GemmItem& it, int m0, int n0, int nbm, int nbn, int lane) {
   if (it.seg_begin >= it.seg_end) return;
   const int r = lane % 16, kq = 4 * (lane / 16);
-  PipeCursor<T, BM, MB, NB> c;
+  PipeCursor<T, BM, MB, NB, AM> c;
   c.si = it.seg_begin;
   c.se = it.seg_end;
   c.k0 = 0;
@@ -342,12 +362,12 @@ __device__ __forceinline__ void pipe_item(typename Mfma<T>::V (&acc)[MB][NB], co
   pipe_load_desc(c, g.segs, lane);
   pipe_setup(c, m0, n0, nbm, nbn, r, kq);
   T a[2][MB][4], b[2][NB][4];
-  pipe_fetch(c, it.N, kq, a[0], b[0]);
+  pipe_fetch(c, it.M, it.N, kq, a[0], b[0]);
   while (true) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       pipe_next(c, g.segs, m0, n0, nbm, nbn, r, kq, lane);
-      pipe_fetch(c, it.N, kq, a[1 - i], b[1 - i]);
+      pipe_fetch(c, it.M, it.N, kq, a[1 - i], b[1 - i]);
       __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
       pipe_mfma<T, MB, NB>(acc, a[i], b[i], nbn);
       __builtin_amdgcn_sched_barrier(0);
@@ -383,8 +403,9 @@ __attribute__((amdgpu_waves_per_eu(MB * NB * int(sizeof(T)) >= 128 ? 2 : 1))) vo
   for (int a = 0; a < MB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = V{0, 0, 0, 0};
-  if constexpr ((ROLE == ROLE_SOLVE || ROLE == ROLE_TRANSFORM) && AM == 1 && BM != 2) {
-    pipe_item<T, BM, MB, NB>(acc, g, it, m0, n0, nbm, nbn, lane);
+  if constexpr (((ROLE == ROLE_SOLVE || ROLE == ROLE_TRANSFORM) && AM == 1 && BM != 2) ||
+                ((ROLE == ROLE_TRANSFORM || ROLE == ROLE_FACTOR) && AM == 0 && BM == 0)) {
+    pipe_item<T, AM, BM, MB, NB>(acc, g, it, m0, n0, nbm, nbn, lane);
   } else {
     for (int si = it.seg_begin; si < it.seg_end; ++si) {
       const GemmSeg sg = g.segs[si];
