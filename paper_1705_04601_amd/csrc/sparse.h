@@ -25,6 +25,7 @@ struct SweepLevel {
   std::vector<GemmBatch> coup1, coup2;    // chunks: K W_b^T, then W_a (.)
   i64 gnext_entries = 0;           // entries of the next level's strip arena to clear
   int gnext_side = 0;              // which of the two strip arenas is "next"
+  int nbatches = 0;                // GEMM batches of this level and the ones below (plan)
 };
 
 struct PlanCounts {
@@ -54,6 +55,10 @@ struct h2_sparse {
   // arenas
   std::vector<h2::i64> q_off, b_off, rhat_off, w_off;
   h2::DeviceBuffer dQ, dQt, dB, dRhat, dW, dWt, dS, dC[2], dG[2], dTmp, dDesc;
+  // work lists of the levels above the leaves, uploaded by the sweep while the
+  // leaf level runs (plan() uploads the leaf level's only)
+  h2::DeviceBuffer dDesc2;
+  bool upload_rest = false;
   std::vector<h2::SweepLevel> levels;
   h2::PlanCounts counts;
   size_t elem = 8;                 // bytes per S / transform element

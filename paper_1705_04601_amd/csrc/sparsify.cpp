@@ -648,6 +648,7 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload, bool symbolic =
   std::vector<GemmBatch*> all;
   std::vector<RawBlob> blobs;
   for (auto& lv : sp.levels) {
+    lv.nbatches = 0;
     all.push_back(&lv.stack);
     all.push_back(&lv.wproj);
     all.push_back(&lv.strips);
@@ -657,6 +658,7 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload, bool symbolic =
     for (auto& g : lv.coup2) all.push_back(&g);
     blobs.push_back({lv.qr.items.data(), lv.qr.items.size() * sizeof(QrItem),
                      reinterpret_cast<const void**>(&lv.qr.d_items)});
+    lv.nbatches = int(all.size());  // batches of this level and the ones below
   }
   // stack and wproj (the basis QR's input) run in FP64, the transforms in the
   // precision of S
@@ -668,10 +670,49 @@ static h2_sparse* plan(h2_matrix* H, int precision, bool upload, bool symbolic =
   tt.lap("work-lists");
   HIPCHECK(hipStreamSynchronize(current_stream()));
   if (!upload) return spp.release();  // a batched sweep merges and uploads the lists
-  upload_batches(all, sp.dDesc, blobs);
+  // the leaf level's lists now; the others during the leaf level's kernels
+  // (run_levels), so that their copy overlaps device work
+  {
+    const size_t n0 = size_t(sp.levels[0].nbatches);
+    std::vector<GemmBatch*> first(all.begin(), all.begin() + n0);
+    std::vector<RawBlob> firstb(blobs.begin(), blobs.begin() + 1);
+    upload_batches(first, sp.dDesc, firstb);
+    std::vector<QrItem>().swap(sp.levels[0].qr.items);
+    sp.upload_rest = all.size() > n0;
+  }
   tt.lap("upload");
-  for (auto& lv : sp.levels) std::vector<QrItem>().swap(lv.qr.items);
   return spp.release();
+}
+
+// Uploads the work lists of levels 1..L on a copy stream; `st` waits for the
+// copy, after the leaf level's kernels already queued on it.
+static void upload_rest(h2_sparse& sp, hipStream_t st) {
+  std::vector<GemmBatch*> all;
+  std::vector<RawBlob> blobs;
+  for (size_t k = 1; k < sp.levels.size(); ++k) {
+    SweepLevel& lv = sp.levels[k];
+    all.push_back(&lv.stack);
+    all.push_back(&lv.wproj);
+    all.push_back(&lv.strips);
+    for (auto& g : lv.close1) all.push_back(&g);
+    for (auto& g : lv.close2) all.push_back(&g);
+    for (auto& g : lv.coup1) all.push_back(&g);
+    for (auto& g : lv.coup2) all.push_back(&g);
+    blobs.push_back({lv.qr.items.data(), lv.qr.items.size() * sizeof(QrItem),
+                     reinterpret_cast<const void**>(&lv.qr.d_items)});
+  }
+  hipStream_t copy = nullptr;
+  HIPCHECK(hipStreamCreateWithFlags(&copy, hipStreamNonBlocking));
+  try {
+    upload_batches(all, sp.dDesc2, blobs, copy, st);
+  } catch (...) {
+    (void)hipStreamSynchronize(copy);
+    (void)hipStreamDestroy(copy);
+    throw;
+  }
+  (void)hipStreamDestroy(copy);  // upload_batches made st wait for the copy
+  for (size_t k = 1; k < sp.levels.size(); ++k) std::vector<QrItem>().swap(sp.levels[k].qr.items);
+  sp.upload_rest = false;
 }
 
 template <class T>
@@ -715,6 +756,7 @@ static void run_levels(h2_sparse& sp, hipStream_t st, double* phase_ms) {
       lv.coup2[c].launch<T>(st);
     }
     mark();  // couplings end
+    if (k == 0 && sp.upload_rest) upload_rest(sp, st);
   }
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipEventSynchronize(ev.back()));
