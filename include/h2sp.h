@@ -10,7 +10,7 @@
  *
  * Method (Sushnikova & Oseledets, "Simple non-extensive sparsification of the
  * hierarchical matrices"):
- *   - the H^2 matrix is Definition 4.8: close part + sum over the interaction
+ *   - the H^2 matrix is Definition 4.9: close part + sum over the interaction
  *     lists of R_t D_ts E_s^T with nested cluster bases (Section 4.1);
  *   - Section 2 (eqs. usv, fin, main_fact) and Section 4 (4.2, 4.3) turn it into
  *     A = U S V^T, S sparse of the same size, U and V orthogonal products of
@@ -143,7 +143,9 @@ int h2_build(const double* pts, int64_t n, int dim, const h2_kernel* kernel,
 
 /*
  * h2_import: same tree and block tree as h2_build (derived from the points),
- * but the cluster-basis coefficients come from the caller (HOST arrays):
+ * but the coefficients of the H^2 format (cluster bases R_t with their
+ * transfer matrices, couplings D_b; Definitions 4.7 and 4.9) come from the
+ * caller (HOST arrays):
  *   rank[ncl]            r_t per cluster in heap order (0 for clusters without
  *                        a basis, i.e. without farfield of their own or of an
  *                        ancestor; must match that set exactly)
@@ -171,7 +173,7 @@ int h2_matrix_export_tree(const h2_matrix* h, int64_t* perm, int32_t* rank);
 
 /*
  * h2_matvec: y = A_H2 x in FP64 on the device (close part from the kernel
- * blocks of the near leaf pairs, far part by the nested bases; Definition 4.8).
+ * blocks of the near leaf pairs, far part by the nested bases; Definition 4.9).
  * The first product for a right-hand-side count builds a plan kept with the
  * matrix; it writes the close blocks out once when they take at most a quarter
  * of the free device memory (H2SP_CLOSE_RESIDENT=0: never), else every product
@@ -268,7 +270,7 @@ int h2_factor_analyze(const h2_sparse* sp, int64_t* filled_entries, double* exac
 /*
  * h2_solve: x = A_H2^{-1} b with M^{-1} = V (L D L^T)^{-1} U^T (eq. sp0 with the
  * factor of S) as the approximate inverse, against the FP64 H^2 matvec
- * (Definition 4.8), until max_col ||b - A_H2 x||_2 / ||b||_2 <= tol:
+ * (Definition 4.9), until max_col ||b - A_H2 x||_2 / ||b||_2 <= tol:
  * iterative refinement x += M^{-1} r, r = b - A_H2 x, or right-preconditioned
  * flexible GMRES (Saad 1993: the search directions M^{-1} v_j are kept, so an
  * FP32 M^{-1} need not be an exactly fixed linear map; restarted, modified by

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this package.
 
-The H^2 format is Definition 4.8 (with Definitions 4.5-4.7): the matrix is
+The H^2 format is Definition 4.9 (with Definitions 4.5-4.8): the matrix is
 the close part (kernel entries of the nearfield leaf pairs) plus, for every
 farfield pair (t, s), R_t D_ts E_s^T with nested cluster bases.  The kernel
 is symmetric and one cluster tree serves rows and columns, so E = R.
@@ -186,7 +186,7 @@ class H2Matrix:
         return np.vstack(parts)
 
     def dense(self) -> np.ndarray:
-        """Dense A_H2 in tree order (small n only): Definition 4.8."""
+        """Dense A_H2 in tree order (small n only): Definition 4.9."""
         n = self.tree.n
         a = np.zeros((n, n))
         idx = np.arange(n)

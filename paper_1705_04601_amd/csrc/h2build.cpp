@@ -1,6 +1,6 @@
 // Construction of the H^2 matrix of c/|x - y|, c exp(-|x - y|^2) or the kernel of Example 5.4
 // (c r / d below d, c d / r from d on; Section 5.5) (the input of the method,
-// Definition 4.8; the paper takes it as given and cites H^2 compression for
+// Definition 4.9 (the H^2 matrix); the paper takes it as given and cites H^2 compression for
 // orthogonal nested bases in Section 4.2).
 //
 // * Tensor Chebyshev nodes of the first kind (p per axis) on each cluster's

@@ -1,5 +1,5 @@
 // h2_matrix: construction, import, export and the FP64 H^2 matrix-vector
-// product (Definition 4.8): close part from kernel blocks kept on the device
+// product (Definition 4.9, the H^2 matrix): close part from kernel blocks kept on the device
 // (or evaluated on the fly from the points when they do not fit), far part by
 // the nested bases (upward pass, couplings, downward pass).
 #include <cmath>
