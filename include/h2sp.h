@@ -428,6 +428,12 @@ int h2_autotune(h2_matrix* h, int precision, int64_t nrhs, const char* path);
  *   H2SP_SCHUR_TILED=0: the Schur update reads the S_kj operands in place
  *     instead of from copies in 16 x 16 tiles (the copies take about 1.3 times
  *     the memory of S and are made only when they fit);
+ *   H2SP_SCHUR_MERGE: on a pattern extended by fill (H2_FACTOR_EXACT,
+ *     H2_FACTOR_ILUT) a run of pivots whose Z_ki and tiled S_kj blocks follow
+ *     each other in memory (the supernodal runs of the filled pattern) is one
+ *     Schur segment, with the S_kj copies in column order; on S's own pattern
+ *     one segment per pivot and the copies in row order.  =0 / =1 forces
+ *     either (the same sums, grouped differently inside the MFMA steps);
  *   H2SP_CLOSE_RESIDENT=0: never keep the matvec's close blocks on the device;
  *   H2SP_GRAPHS=0: run the solve and matvec sweeps eagerly instead of as
  *     captured HIP graphs;

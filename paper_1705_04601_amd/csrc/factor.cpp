@@ -53,6 +53,7 @@ struct FactorLevel {
   std::vector<SchurItem> sitems;
   std::vector<int64_t> skeys;  // per item: tile-order key (host only)
   PodVector<SchurSeg> ssegs;
+  PodVector<int32_t> sk;  // per segment: K without the padding of merged pivots (host only)
   std::vector<int32_t> stiles[kSchurClasses];  // Schur tiles by class (a launch each)
   std::vector<SchurReduce> reds;
   const InvItem<T>* d_inv = nullptr;
@@ -80,6 +81,7 @@ struct RowChunk {
   std::vector<SchurItem> items;
   std::vector<int64_t> keys;  // per item: tile-order key (row, place of the target column in space)
   PodVector<SchurSeg> segs;
+  PodVector<int32_t> tk;  // per segment: K without the padding of merged pivots
   double flops = 0;
   double dense_pairs = 0;  // sum over rows of (pivots above the row) x (targets of the row)
 };
@@ -137,14 +139,35 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
   // S_kj operands in tiles: every stored block above the diagonal gets a
   // tiled copy (both sides rounded up to 16) once its row is final, which the
   // Schur updates of later levels read instead of the block itself.  Used
-  // when the copies fit in device memory (H2SP_SCHUR_TILED=0: never).
+  // when the copies fit in device memory (H2SP_SCHUR_TILED=0: never).  The
+  // copies go in column order (for each S position j, its blocks S_kj in the
+  // order of k), so that the blocks of consecutive pivots k of a column follow
+  // each other along k, as the Z_ki of a row do in the Z buffer.
+  // On a pattern extended by fill (exact mode, ILUt), a run of pivots whose
+  // Z_ki and tiled S_kj blocks follow each other in memory is one segment
+  // (the supernodal runs of the filled pattern): the tiles then go k-outer
+  // and the S_kj copies in column order.  Otherwise one segment per pivot,
+  // column-outer tiles and the copies in row order, which keeps the S_kj of
+  // the tiles that run together (one pivot row, many targets) close in memory.
+  // H2SP_SCHUR_MERGE=0 / =1 forces either.
+  bool merge_runs = !sp.is_fill.empty();
+  if (const char* e = std::getenv("H2SP_SCHUR_MERGE")) merge_runs = e[0] != '0';
+  const bool kouter = merge_runs;
   std::vector<i64> st_off(sp.colidx.size(), -1);
   i64 st_len = 0;
-  for (i64 pos = 0; pos < ncl; ++pos)
-    for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) {
-      st_off[b] = st_len;
-      st_len += kpad16(mb[cl(pos)]) * kpad16(mb[sp.colidx[b]]);
-    }
+  if (merge_runs) {
+    for (i64 j = 0; j < ncl; ++j)
+      for (i64 c = cptr[j]; c < cptr[j + 1]; ++c) {
+        st_off[ck_blk[c]] = st_len;
+        st_len += kpad16(mb[cl(ck_pos[c])]) * kpad16(mb[cl(j)]);
+      }
+  } else {
+    for (i64 pos = 0; pos < ncl; ++pos)
+      for (i64 b = sp.rowptr[pos] + 1; b < sp.rowptr[pos + 1]; ++b) {
+        st_off[b] = st_len;
+        st_len += kpad16(mb[cl(pos)]) * kpad16(mb[sp.colidx[b]]);
+      }
+  }
   bool tiled_s = st_len > 0;
   if (const char* e = std::getenv("H2SP_SCHUR_TILED")) tiled_s = tiled_s && e[0] != '0';
   if (tiled_s) {
@@ -165,6 +188,16 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
   }
   T* St = tiled_s ? dSt.as<T>() : nullptr;
   f.schur_tiled = tiled_s;
+  merge_runs = merge_runs && tiled_s;  // S_kj read in place: blocks of a column are not adjacent
+  // per place in a column list: how many entries from there on hold
+  // consecutive elimination positions (runs of pivots)
+  std::vector<int32_t> crun(merge_runs ? ck_pos.size() : 0);
+  if (merge_runs)
+    for (i64 j = 0; j < ncl; ++j)
+      for (i64 c = cptr[j + 1] - 1; c >= cptr[j]; --c)
+        crun[c] = (c + 1 < cptr[j + 1] && ck_pos[c + 1] == ck_pos[c] + 1) ? crun[c + 1] + 1 : 1;
+  // K of segment r without the padding rows of merged pivots
+  auto seg_k = [&](const FactorLevel<T>& L, int32_t r) -> i64 { return merge_runs ? L.sk[r] : L.ssegs[r].K; };
   // ILUt: one flag per stored block (1 = dropped), written by the drop launches
   const bool ilut = !f.drop_thr2.empty();
   if (ilut && sp.colidx.size() >= (size_t(1) << 31)) fail(H2_EUNSUPPORTED, "ILUt pattern above 2^31 blocks");
@@ -263,8 +296,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
       auto emit = [&](const SchurItem& si, int64_t key) {
         const uint32_t item = uint32_t(o.items.size());
         o.keys.push_back(key);
-        i64 k = 0;
-        for (int32_t r = si.seg_begin; r < si.seg_end; ++r) k += L.ssegs[r].K;
+        i64 k = 0;  // flops without the padding rows of merged pivots
+        for (int32_t r = si.seg_begin; r < si.seg_end; ++r) k += seg_k(L, r);
         const bool half = split_big && schur_tile_class<T>(si.M, si.N, 0, 0) == 2;
         const int te = half ? edge / 2 : edge;
         for (int a = 0; a < (si.M + te - 1) / te; ++a)
@@ -347,6 +380,114 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
       }
     }
   };
+  // Schur work of a level on a filled pattern: for a target (i, j) the pivots
+  // k with S_ki and S_kj stored are the intersection of the column lists of i
+  // and j (both in elimination order), walked by runs of consecutive
+  // positions with a binary search over the gaps.  A run is one segment (its
+  // Z_ki follow each other in the Z buffer, its S_kj in the column-ordered
+  // copies), and a segment whose blocks continue the previous one joins it.
+  // A segment holds at most kcap padded rows (half the smallest split-K
+  // part), so that long targets can still be split into parts that run in
+  // parallel.  The rows are cut into pieces of targets, planned in parallel
+  // and concatenated in row and target order: the same segments as one per
+  // pivot joined afterwards, without visiting every pivot of every target.
+  const i64 kcap = std::max<i64>(16, kMinK / 2);
+  auto plan_runs = [&](const std::vector<i64>& rows, const std::vector<i64>& zbase, std::vector<RowChunk>& chunks) {
+    const long nr = long(rows.size());
+    i64 ntar = 0;
+    for (long q = 0; q < nr; ++q) ntar += sp.rowptr[rows[q] + 1] - sp.rowptr[rows[q]];
+    const i64 per = std::max<i64>(16, ntar / (16 * i64(nthr)) + 1);
+    struct Piece {
+      long q;
+      i64 b0, b1;  // targets: stored blocks b0 .. b1 - 1 of row q
+    };
+    std::vector<Piece> pieces;
+    for (long q = 0; q < nr; ++q) {
+      const i64 t0 = sp.rowptr[rows[q]], t1 = sp.rowptr[rows[q] + 1];
+      for (i64 b = t0; b < t1; b += per) pieces.push_back({q, b, std::min(t1, b + per)});
+    }
+    chunks.assign(pieces.size(), RowChunk());
+#pragma omp parallel num_threads(nthr)
+    {
+      std::vector<i64> zo, kp, tp;  // per pivot of the row: Z offset, padded and true K before it
+      long zrow = -1;
+#pragma omp for schedule(dynamic, 1)
+      for (long pc = 0; pc < long(pieces.size()); ++pc) {
+        const Piece& P = pieces[pc];
+        RowChunk& out = chunks[pc];
+        const i64 pi = rows[P.q];
+        const i64 mi = mb[cl(pi)], mi16 = kpad16(mi);
+        const i64 c0 = cptr[pi], nci = cptr[pi + 1] - c0;
+        const i64* ci = ck_pos.data() + c0;
+        if (zrow != P.q) {
+          zrow = P.q;
+          zo.resize(nci + 1);
+          kp.resize(nci + 1);
+          tp.resize(nci + 1);
+          zo[0] = zbase[P.q];
+          kp[0] = tp[0] = 0;
+          for (i64 p = 0; p < nci; ++p) {
+            const i64 mk = mb[cl(ci[p])];
+            zo[p + 1] = zo[p] + kpad16(mk) * mi16;
+            kp[p + 1] = kp[p] + kpad16(mk);
+            tp[p + 1] = tp[p] + mk;
+          }
+        }
+        out.dense_pairs += double(nci) * double(P.b1 - P.b0);
+        for (i64 b = P.b0; b < P.b1; ++b) {
+          const i64 mj = mb[sp.colidx[b]], mj16 = kpad16(mj);
+          const i64 cj0 = cptr[sp.epos[sp.colidx[b]]], ncj = cptr[sp.epos[sp.colidx[b]] + 1] - cj0;
+          const i64* cj = ck_pos.data() + cj0;
+          const size_t sb = out.segs.size();
+          i64 p = 0, q = 0;
+          while (p < nci && q < ncj) {
+            if (ci[p] < cj[q]) {
+              p = std::lower_bound(ci + p + 1, ci + nci, cj[q]) - ci;
+              continue;
+            }
+            if (ci[p] > cj[q]) {
+              q = std::lower_bound(cj + q + 1, cj + ncj, ci[p]) - cj;
+              continue;
+            }
+            // the run, in pieces of at most kcap padded rows (at least one
+            // pivot each)
+            const i64 e = p + std::min<i64>(crun[c0 + p], crun[cj0 + q]);
+            while (p < e) {
+              i64 u = std::upper_bound(kp.begin() + p + 1, kp.begin() + e + 1, kp[p] + kcap) - kp.begin() - 1;
+              u = std::max(u, p + 1);
+              const i64 K = kp[u - 1] - kp[p] + (tp[u] - tp[u - 1]);
+              const i64 aoff = zo[p], boff = st_off[ck_blk[cj0 + q]];
+              const int32_t tk = int32_t(tp[u] - tp[p]);
+              q += u - p;
+              p = u;
+              if (out.segs.size() > sb) {
+                SchurSeg& pv = out.segs.back();
+                const i64 kpv = kpad16(pv.K);
+                if (i64(pv.a_off) + kpv * mi16 == aoff && pv.b_off + kpv * mj16 == boff && kpv + K <= kcap) {
+                  pv.K = int32_t(kpv + K);
+                  out.tk.back() += tk;
+                  continue;
+                }
+              }
+              out.segs.push_back({boff, int32_t(aoff), int32_t(K)});
+              out.tk.push_back(tk);
+            }
+          }
+          if (out.segs.size() == sb) continue;
+          SchurItem si{sp.blk_off[b], int32_t(mi), int32_t(mj), int32_t(sb), int32_t(out.segs.size()), 0, 0};
+          i64 k = 0, kt = 0;
+          for (size_t r = sb; r < out.segs.size(); ++r) {
+            k += out.segs[r].K;
+            kt += out.tk[r];
+          }
+          si.ksum = int32_t(k);
+          out.flops += 2.0 * mi * mj * double(kt);
+          out.items.push_back(si);
+          out.keys.push_back((int64_t(P.q) << 32) | int64_t(tstart[sp.colidx[b]]));
+        }
+      }
+    }
+  };
   // Plans one level: Z GEMMs, copies and inverses row by row (cheap), Schur
   // targets in parallel over chunks of rows, concatenated in row order.
   auto plan_level = [&](int lv) {
@@ -368,7 +509,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
         const i64 soff = sp.blk_off[ck_blk[c]];
         GemmItem& it = L.zb.item(int(mk), int(mi), int(mk), int(mi));
         GemmBatch::set_out(it, 0, Z + z, kpad16(mk), false);
-        L.zts.push_back({z, z, int32_t(mk), int32_t(mi), int32_t(kpad16(mk)), 0});
+        L.zts.push_back({z, z, int32_t(mk), int32_t(mi), int32_t(kpad16(mk)), kouter ? 1 : 0});
         // D_k^{-1} is symmetric (D_k is): read it through its transpose so that
         // both operands run along K in memory
         L.zb.seg(Inv + f.inv_off[pk], int(mk), true, S + soff, int(mk), false, int(mk));
@@ -385,14 +526,20 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
       // the row's blocks above the diagonal are final after this level
       if (tiled_s)
         for (i64 b = sp.rowptr[pi] + 1; b < sp.rowptr[pi + 1]; ++b)
-          L.sts.push_back({st_off[b], sp.blk_off[b], int32_t(mi), int32_t(mb[sp.colidx[b]]), int32_t(mi), 0});
+          L.sts.push_back({st_off[b], sp.blk_off[b], int32_t(mi), int32_t(mb[sp.colidx[b]]), int32_t(mi), kouter ? 1 : 0});
     }
     L.zlen = zbase[nr];
     fl_z += L.zb.flops;
     // Schur targets: every stored (i, j), j at or after i, of a row i of the level
-    const int nchunk = int(std::min<long>(nr, 8L * nthr));
-    std::vector<RowChunk> chunks(nchunk);
-    const int nt = int(std::min<long>(nthr, std::max<long>(1, nr / 2)));
+    int nchunk = int(std::min<long>(nr, 8L * nthr));
+    int nt = int(std::min<long>(nthr, std::max<long>(1, nr / 2)));
+    std::vector<RowChunk> chunks;
+    if (merge_runs) {
+      plan_runs(rows, zbase, chunks);
+      nchunk = int(chunks.size());
+      nt = nthr;
+    } else {
+      chunks.resize(nchunk);
 #pragma omp parallel num_threads(nt)
     {
       std::vector<int32_t>& mark = marks[omp_get_thread_num()];
@@ -447,6 +594,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
         }
       }
     }
+    }
     size_t nitems = 0, nsegs = 0;
     for (const RowChunk& c : chunks) {
       nitems += c.items.size();
@@ -470,6 +618,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
     std::vector<SchurItem> items(nitems);
     std::vector<int64_t> keys(nitems);
     L.ssegs.resize(nsegs);
+    L.sk.resize(merge_runs ? nsegs : 0);
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
     for (int ch = 0; ch < nchunk; ++ch) {
       RowChunk& c = chunks[ch];
@@ -481,10 +630,14 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
         items[io[ch] + i] = si;
         keys[io[ch] + i] = c.keys[i];
       }
-      if (!c.segs.empty()) std::memcpy(&L.ssegs[so[ch]], c.segs.data(), c.segs.size() * sizeof(SchurSeg));
+      if (!c.segs.empty()) {
+        std::memcpy(&L.ssegs[so[ch]], c.segs.data(), c.segs.size() * sizeof(SchurSeg));
+        if (merge_runs) std::memcpy(&L.sk[so[ch]], c.tk.data(), c.tk.size() * sizeof(int32_t));
+      }
       std::vector<SchurItem>().swap(c.items);
       std::vector<int64_t>().swap(c.keys);
       PodVector<SchurSeg>().swap(c.segs);
+      PodVector<int32_t>().swap(c.tk);
     }
     split_targets(items, keys, L);
     if (L.sitems.size() >= (size_t(1) << 24)) too_wide = 1;
@@ -612,7 +765,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
           sn += it.N;
           for (int32_t r = it.seg_begin; r < it.seg_end; ++r) {
             const SchurSeg& sg = L.ssegs[r];
-            fl += 2.0 * it.M * it.N * sg.K;
+            fl += 2.0 * it.M * it.N * seg_k(L, r);
             zs += double(sizeof(T)) * double(kpad16(sg.K)) * it.M;
             ss += double(sizeof(T)) * double(sg.K) * it.N;
             sk += sg.K;
@@ -766,7 +919,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
             new_ev(cev, cls_st[c]);
           }
           SchurLaunch sl{L.d_sitems, L.d_ssegs, L.d_stiles[c], int32_t(L.stiles[c].size()), S,
-                         tiled_s ? St : S, Zt, Pbuf, tiled_s ? 1 : 0};
+                         tiled_s ? St : S, Zt, Pbuf, tiled_s ? 1 : 0, kouter ? 1 : 0};
           launch_schur<T>(sl, c, cls_st[c]);
           const hipEvent_t done = level_events ? new_ev(cev, cls_st[c]) : (c > 0 ? sync_event(cls_st[c]) : nullptr);
           if (c > 0) HIPCHECK(hipStreamWaitEvent(st, done, 0));

@@ -169,6 +169,7 @@ struct SchurLaunch {
   const void* Z;         // Z_ki operands, in tiles
   void* P;               // partial buffer
   int32_t tiled_b;
+  int32_t kouter;        // tile layout of Z and the tiled S_kj (see launch_retile): 1 k-outer, 0 column-outer
 };
 // Tile class (each class has a kernel of its own, with the register budget
 // of its shapes; see schur_kernel): 0 when the tile has at most 4 blocks of
@@ -239,7 +240,7 @@ void launch_drop_small(const DropItem* items, int count, T* S, uint8_t* flag, hi
 // contiguous block of dst (leading dimension rows), for every segment.
 struct CopySeg {
   int64_t dst, src;          // dst: rows x cols, ld rows; src: ld src_ld
-  int32_t rows, cols, src_ld, pad;
+  int32_t rows, cols, src_ld, pad;  // pad: launch_retile's layout (1 k-outer, 0 column-outer)
 };
 template <class T>
 void launch_copy_segments(const CopySeg* segs, int count, const T* src, T* dst, hipStream_t st);

@@ -59,9 +59,10 @@ namespace {
 // Operands are read with buffer loads: per segment, one resource (base and
 // size in bytes) for the Z_ki block and one for the S_kj block, and one 32-bit
 // offset per lane and 16 x 16 block that stays fixed for the whole segment; a
-// chunk only moves the two bases on by 16 k.  Reads outside a resource return
-// zero, which covers rows past M and columns past N, and a chunk past the
-// item's last segment (a resource of size zero).  A lane whose four k start
+// chunk only moves the two bases on by one row of tiles (16 k).  Reads outside
+// a resource return zero, which covers a chunk past the item's last segment (a
+// resource of size zero); rows past M and columns past N are the zero padding
+// of the tiles.  A lane whose four k start
 // at or past K reads through an offset outside both resources (zero, and no
 // memory traffic); in the lane that holds K itself, k past K meets the zero
 // rows of the padded Z_ki, and the S_kj operand reads the next column of the
@@ -79,7 +80,8 @@ struct SchurCursor {
   const T* pa;          // Z_ki and S_kj of the current segment
   const T* pb;
   uint32_t na, nb;      // their sizes in bytes
-  int shb;              // elements the S_kj base moves per k (16 in tiles, 1 in place)
+  int sha;              // elements the Z_ki base moves per k (16 per 16-column block)
+  int shb;              // elements the S_kj base moves per k (as for Z_ki in tiles, 1 in place)
   uint32_t oa[NBM], ob[NBN];
 };
 
@@ -94,14 +96,17 @@ __device__ __forceinline__ void schur_load_desc(SchurCursor<T, NBM, NBN>& c, con
 }
 
 // Operand addressing of one segment.  Z_ki is always in tiles (see
-// retile_kernel): chunk c of column block q at (q C + c) 256 elements with
-// C = K16 / 16, lane l's four elements at 4 l inside the tile, so that one
-// load instruction reads 1 KB (FP32) of consecutive memory.  S_kj is in tiles
-// too when the launch says so, else read in place (column-major, ld K: each
-// lane reads four consecutive k of its column).
+// retile_kernel), lane l's four elements at 4 l inside the tile, so that one
+// load instruction reads 1 KB (FP32) of consecutive memory; chunk c of column
+// block q lies at (q C + c) 256 elements, C = K16 / 16 (column-outer), or at
+// (c Q + q) 256, Q = M16 / 16 (k-outer).  In the k-outer layout blocks of
+// consecutive pivots laid out one after the other read as one segment whose
+// K is the sum of their padded K (the padding rows are zero).  S_kj is in
+// tiles too (the same layout) when the launch says so, else read in place
+// (column-major, ld K: each lane reads four consecutive k of its column).
 template <class T, int NBM, int NBN>
 __device__ __forceinline__ void schur_setup(SchurCursor<T, NBM, NBN>& c, const T* Sb, const T* Z, int tiled_b,
-                                            int m0, int n0, int M, int N, int r, int kq) {
+                                            int kouter, int m0, int n0, int M, int N, int r, int kq) {
   static_assert(sizeof(SchurSeg) == 16, "descriptor of four 32-bit words");
   const int idx = c.si - c.dbase;
   const uint64_t b_off = (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(c.d[1]), idx))) << 32) |
@@ -114,13 +119,16 @@ __device__ __forceinline__ void schur_setup(SchurCursor<T, NBM, NBN>& c, const T
   c.pa = Z + a_off;
   c.pb = Sb + int64_t(b_off);
   c.na = uint32_t(ck * 16 * ((M + 15) & ~15)) * uint32_t(sizeof(T));
+  // per 16 k the base moves by one row of tiles (k-outer) or one tile
+  c.sha = kouter ? 16 * ((M + 15) >> 4) : 16;
+  const int qa = kouter ? 256 : ck * 256;  // elements between column blocks
 #pragma unroll
-  for (int q = 0; q < NBM; ++q) c.oa[q] = uint32_t((m0 / 16 + q) * ck * 256 + lane4) * uint32_t(sizeof(T));
+  for (int q = 0; q < NBM; ++q) c.oa[q] = uint32_t((m0 / 16 + q) * qa + lane4) * uint32_t(sizeof(T));
   if (tiled_b) {
-    c.shb = 16;
+    c.shb = kouter ? 16 * ((N + 15) >> 4) : 16;
     c.nb = uint32_t(ck * 16 * ((N + 15) & ~15)) * uint32_t(sizeof(T));
 #pragma unroll
-    for (int q = 0; q < NBN; ++q) c.ob[q] = uint32_t((n0 / 16 + q) * ck * 256 + lane4) * uint32_t(sizeof(T));
+    for (int q = 0; q < NBN; ++q) c.ob[q] = uint32_t((n0 / 16 + q) * qa + lane4) * uint32_t(sizeof(T));
   } else {
     c.shb = 1;
     c.nb = uint32_t(K * N) * uint32_t(sizeof(T));
@@ -131,8 +139,8 @@ __device__ __forceinline__ void schur_setup(SchurCursor<T, NBM, NBN>& c, const T
 
 template <class T, int NBM, int NBN>
 __device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const SchurSeg* segs, const T* Sb,
-                                           const T* Z, int tiled_b, int m0, int n0, int M, int N, int r, int kq,
-                                           int lane) {
+                                           const T* Z, int tiled_b, int kouter, int m0, int n0, int M, int N, int r,
+                                           int kq, int lane) {
   if (!c.valid) return;
   c.k0 += 16;
   if (c.k0 < c.K) return;
@@ -146,9 +154,9 @@ __device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const Sc
   if (c.si - c.dbase >= 64) {
     c.dbase += 64;
     schur_load_desc(c, segs, lane);
-    schur_setup(c, Sb, Z, tiled_b, m0, n0, M, N, r, kq);
+    schur_setup(c, Sb, Z, tiled_b, kouter, m0, n0, M, N, r, kq);
   } else {
-    schur_setup(c, Sb, Z, tiled_b, m0, n0, M, N, r, kq);
+    schur_setup(c, Sb, Z, tiled_b, kouter, m0, n0, M, N, r, kq);
   }
 }
 
@@ -160,11 +168,11 @@ __device__ __forceinline__ void schur_next(SchurCursor<T, NBM, NBN>& c, const Sc
 template <class T, int NBM, int NBN>
 __device__ __forceinline__ int schur_fetch(const SchurCursor<T, NBM, NBN>& c, int kq, T (&a)[NBM][4],
                                            T (&b)[NBN][4]) {
-  // k0 < K <= K16: both sizes stay positive (a chunk of tiles moves the base
-  // by 16 elements per k, an in-place column block by one)
-  const uint32_t sha = uint32_t(c.k0 * 16) * uint32_t(sizeof(T));
+  // k0 < K <= K16: both sizes stay positive (a row of tiles moves the base by
+  // 16 elements per k and 16-column block, an in-place column block by one)
+  const uint32_t sha = uint32_t(c.k0 * c.sha) * uint32_t(sizeof(T));
   const uint32_t shb = uint32_t(c.k0 * c.shb) * uint32_t(sizeof(T));
-  const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.pa + c.k0 * 16, c.valid ? c.na - sha : 0u);
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(c.pa + c.k0 * c.sha, c.valid ? c.na - sha : 0u);
   const __amdgpu_buffer_rsrc_t rb = make_rsrc(c.pb + c.k0 * c.shb, c.valid ? c.nb - shb : 0u);
   const bool live = c.k0 + kq < c.K;
 #pragma unroll
@@ -252,7 +260,7 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
   T* S = static_cast<T*>(g.S);
   const T* Sb = static_cast<const T*>(g.Sb);
   const T* Z = static_cast<const T*>(g.Z);
-  const int tb = g.tiled_b;
+  const int tb = g.tiled_b, ko = g.kouter;
   V acc[NBM][NBN];
 #pragma unroll
   for (int a = 0; a < NBM; ++a)
@@ -265,20 +273,20 @@ __device__ __forceinline__ void schur_tile(const SchurLaunch& g, const SchurItem
     c.k0 = 0;
     c.valid = true;
     schur_load_desc(c, g.segs, lane);
-    schur_setup(c, Sb, Z, tb, m0, n0, it.M, it.N, r, kq);
+    schur_setup(c, Sb, Z, tb, ko, m0, n0, it.M, it.N, r, kq);
     T a[NS][NBM][4], b[NS][NBN][4];
     int steps[NS];
     steps[0] = schur_fetch(c, kq, a[0], b[0]);
 #pragma unroll
     for (int i = 1; i < NS - 1; ++i) {
-      schur_next(c, g.segs, Sb, Z, tb, m0, n0, it.M, it.N, r, kq, lane);
+      schur_next(c, g.segs, Sb, Z, tb, ko, m0, n0, it.M, it.N, r, kq, lane);
       steps[i] = schur_fetch(c, kq, a[i], b[i]);
     }
     // one exit per NS chunks; chunks past the end read zeros and take no step
     while (true) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        schur_next(c, g.segs, Sb, Z, tb, m0, n0, it.M, it.N, r, kq, lane);
+        schur_next(c, g.segs, Sb, Z, tb, ko, m0, n0, it.M, it.N, r, kq, lane);
         steps[(i + NS - 1) % NS] = schur_fetch(c, kq, a[(i + NS - 1) % NS], b[(i + NS - 1) % NS]);
         __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
         schur_mfma<T, NBM, NBN>(acc, a[i], b[i], steps[i]);
@@ -675,8 +683,10 @@ __global__ __launch_bounds__(256) void copy_segments_kernel(const CopySeg* segs,
 
 // Copies a rows x cols column-major block (ld src_ld) into 16 x 16 tiles in
 // the Schur kernel's lane order (rows = k, columns = the other index): tile
-// (c, q) of the block at (q C + c) 256 elements, C = ceil(rows / 16); inside
-// a tile, element (k = 16 c + 4 g + s, column 16 q + r) at 4 (r + 16 g) + s.
+// (c, q) of the block at (q C + c) 256 elements, C = ceil(rows / 16)
+// (column-outer, segment field pad = 0), or at (c Q + q) 256 elements,
+// Q = ceil(cols / 16) (k-outer, pad = 1: rows of tiles follow k); inside a
+// tile, element (k = 16 c + 4 g + s, column 16 q + r) at 4 (r + 16 g) + s.
 // Places outside the block are written as zeros.  One work-group per block,
 // threads along the tiled block (writes contiguous).
 template <class T>
@@ -686,7 +696,7 @@ __global__ __launch_bounds__(256) void retile_kernel(const CopySeg* segs, const 
   const int64_t len = int64_t(ck) * cq * 256;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < len; e += int64_t(gridDim.x) * blockDim.x) {
     const int t = int(e >> 8), p = int(e & 255);
-    const int q = t / ck, c = t - q * ck;
+    const int c = sg.pad ? t / cq : t % ck, q = sg.pad ? t % cq : t / ck;
     const int l = p >> 2, s4 = p & 3;
     const int k = 16 * c + 4 * (l >> 4) + s4, col = 16 * q + (l & 15);
     dst[sg.dst + e] = (k < sg.rows && col < sg.cols) ? src[sg.src + int64_t(col) * sg.src_ld + k] : T(0);

@@ -295,6 +295,36 @@ def test_exact_factor_mixed_solve(name):
     assert np.abs(host(xs) - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("mode", ["exact", "ilu0"])
+@pytest.mark.parametrize("precision", [P.H2_FP64, P.H2_MIXED], ids=["fp64", "mixed"])
+def test_schur_merged_runs_match_per_pivot(precision, mode, monkeypatch):
+    """Runs of pivots merged into one Schur segment (k-outer tiles, S copies in
+    column order) and one segment per pivot give the same factor up to the
+    grouping of the sums inside the MFMA steps, and the same Schur flops (the
+    padding rows between merged pivots are not counted)."""
+    name = "cube2500r48"
+    x, sc, h2, sp, a, _ = case(name)
+    note(f"schur merged runs {mode} precision={precision}")
+    h = imported(name)
+    fm = P.H2_FACTOR_EXACT if mode == "exact" else P.H2_FACTOR_ILU0
+    b = np.random.default_rng(12).standard_normal((x.shape[0], 3))
+    outs, flops = [], []
+    for merge in ("0", "1"):
+        monkeypatch.setenv("H2SP_SCHUR_MERGE", merge)
+        f = P.h2_factor_S(P.h2_sparsify(h, precision), fm)
+        flops.append(P.h2_last_work()[5])
+        out = dev(np.zeros_like(b))
+        P.h2_apply_inverse(f, dev(b), out)
+        outs.append(host(out))
+    assert np.isfinite(outs[0]).all() and np.isfinite(outs[1]).all()
+    assert abs(flops[0] - flops[1]) <= 1e-12 * flops[0]
+    bar = 1e-12 if precision == P.H2_FP64 else 1e-4
+    assert np.abs(outs[0] - outs[1]).max() <= bar * np.abs(outs[0]).max()
+    if mode == "exact" and precision == P.H2_FP64:
+        ref = from_tree(np.linalg.solve(a, to_tree(b, h2.tree.perm)), h2.tree.perm)
+        assert np.abs(outs[1] - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
 def test_factor_twice_is_rejected():
     x, sc, h2, sp, a, _ = case("torus777")
     note("factor twice")
