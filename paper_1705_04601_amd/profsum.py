@@ -15,6 +15,13 @@
       busy fraction (busy SIMD cycles over active cycles of all 1024 SIMDs;
       GRBM_GUI_ACTIVE is summed over the 8 XCDs, so divided by 8)
 
+  python -m paper_1705_04601_amd.profsum busy <out_dir> <prefix> <first_regex> <last_regex> [after_regex]
+      device occupancy of one phase from <prefix>_kernel_trace.csv: the window
+      from the first start of a kernel matching first_regex (after the last
+      kernel matching after_regex, when given) to the last end of a kernel
+      matching last_regex, the union of all kernel intervals inside it (busy,
+      whatever stream they ran on), and the idle time with its gaps
+
 Reads CSV files only; prints text.
 """
 
@@ -109,11 +116,40 @@ def counters(out_dir: str, prefix: str, sub: str) -> None:
         print(f"{name}: {line}")
 
 
+def busy(out_dir: str, prefix: str, first: str, last: str, after: str | None = None) -> None:
+    import re
+    rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+            for r in csv.DictReader(open(os.path.join(out_dir, f"{prefix}_kernel_trace.csv")))]
+    rf, rl = re.compile(first), re.compile(last)
+    ta = max((a for a, _, k in rows if re.search(after, k)), default=0) if after else 0
+    t0 = min(a for a, _, k in rows if rf.search(k) and a > ta)
+    t1 = max(b for _, b, k in rows if rl.search(k))
+    iv = sorted((max(a, t0), min(b, t1)) for a, b, _ in rows if b > t0 and a < t1)
+    busy_ns, gaps, cur_a, cur_b = 0, [], iv[0][0], iv[0][1]
+    if cur_a > t0:
+        gaps.append(cur_a - t0)
+    for a, b in iv[1:]:
+        if a > cur_b:
+            busy_ns += cur_b - cur_a
+            gaps.append(a - cur_b)
+            cur_a, cur_b = a, b
+        else:
+            cur_b = max(cur_b, b)
+    busy_ns += cur_b - cur_a
+    gaps.sort()
+    med = gaps[len(gaps) // 2] if gaps else 0
+    print(f"window {first!r} .. {last!r}: {len(iv)} kernels over {(t1 - t0) / 1e6:.1f} ms, "
+          f"busy {busy_ns / 1e6:.1f} ms ({busy_ns / max(1, t1 - t0):.3f}), idle {sum(gaps) / 1e6:.1f} ms "
+          f"in {len(gaps)} gaps (median {med / 1e3:.1f} us, largest {(gaps[-1] if gaps else 0) / 1e6:.2f} ms)")
+
+
 def main(argv):
     if len(argv) >= 3 and argv[0] == "stats":
         stats(argv[1], argv[2])
     elif len(argv) >= 4 and argv[0] == "counters":
         counters(argv[1], argv[2], argv[3])
+    elif len(argv) >= 5 and argv[0] == "busy":
+        busy(argv[1], argv[2], argv[3], argv[4], *argv[5:6])
     elif len(argv) >= 6 and argv[0] == "traffic":
         traffic(argv[1], argv[2], argv[3], argv[4], int(argv[5]), *argv[6:7])
     else:
