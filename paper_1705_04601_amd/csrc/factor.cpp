@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <condition_variable>
@@ -189,19 +190,75 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
   T* St = tiled_s ? dSt.as<T>() : nullptr;
   f.schur_tiled = tiled_s;
   merge_runs = merge_runs && tiled_s;  // S_kj read in place: blocks of a column are not adjacent
-  // per place in a column list: how many entries from there on hold
-  // consecutive elimination positions (runs of pivots)
+  // end of each column list: the entries cptr[j] .. cend[j] - 1
+  std::vector<i64> cend(cptr.begin() + 1, cptr.end());
+  // per place in a column list: how many live entries from there on hold
+  // consecutive elimination positions (runs of pivots); 0 marks an entry
+  // whose block ILUt dropped (see prune_level)
   std::vector<int32_t> crun(merge_runs ? ck_pos.size() : 0);
+  auto run_at = [&](i64 j, i64 c) -> int32_t {
+    return (c + 1 < cend[j] && crun[c + 1] > 0 && ck_pos[c + 1] == ck_pos[c] + 1) ? crun[c + 1] + 1 : 1;
+  };
   if (merge_runs)
     for (i64 j = 0; j < ncl; ++j)
-      for (i64 c = cptr[j + 1] - 1; c >= cptr[j]; --c)
-        crun[c] = (c + 1 < cptr[j + 1] && ck_pos[c + 1] == ck_pos[c] + 1) ? crun[c + 1] + 1 : 1;
+      for (i64 c = cend[j] - 1; c >= cptr[j]; --c) crun[c] = run_at(j, c);
+  // a dead entry is skipped by the plans (`live`)
+  auto live = [&](i64 c) { return !merge_runs || crun[c] > 0; };
   // K of segment r without the padding rows of merged pivots
   auto seg_k = [&](const FactorLevel<T>& L, int32_t r) -> i64 { return merge_runs ? L.sk[r] : L.ssegs[r].K; };
   // ILUt: one flag per stored block (1 = dropped), written by the drop launches
   const bool ilut = !f.drop_thr2.empty();
   if (ilut && sp.colidx.size() >= (size_t(1) << 31)) fail(H2_EUNSUPPORTED, "ILUt pattern above 2^31 blocks");
   DeviceBuffer dDropFlag(ilut ? sp.colidx.size() : 0);
+  // ILUt with planned runs: each level is planned after the previous level's
+  // drop decisions are back on the host, and the dropped blocks (zero from
+  // then on) leave the column lists, so that no later level multiplies them.
+  // Planning then waits for the device level by level.  H2SP_ILUT_PRUNE=0
+  // keeps the full structural fill in every plan.
+  bool prune = ilut && merge_runs;
+  if (const char* e = std::getenv("H2SP_ILUT_PRUNE")) prune = prune && e[0] != '0';
+  std::vector<uint8_t> hdrop(prune ? sp.colidx.size() : 0, 0);  // drop flags of finished levels
+  int flags_done = -1;                                           // last level whose flags are in hdrop
+  bool prod_abort = false;                                       // the enqueuing side failed
+  auto is_dropped = [&](i64 b) { return f.drop_thr2[b] >= 0.0 && hdrop[b] != 0; };
+  double prune_ms = 0, plan_ms = 0, flag_ms = 0;  // host time of the pruned planning (traced)
+  // place of every stored block above the diagonal in its column list
+  std::vector<i64> cidx(prune ? sp.colidx.size() : 0, -1);
+  if (prune)
+    for (i64 c = 0; c < i64(ck_blk.size()); ++c) cidx[ck_blk[c]] = c;
+  // from a dead entry, a later entry on the way to the next live one (path
+  // compressed by every lookup; the planning threads share it, so relaxed
+  // atomics: any value written is a valid step)
+  const i64 nent = i64(ck_pos.size());
+  std::unique_ptr<std::atomic<i64>[]> nxt(new std::atomic<i64>[prune ? nent : 0]);
+  for (i64 c = 0; c < (prune ? nent : 0); ++c) nxt[c].store(c + 1, std::memory_order_relaxed);
+  // first live entry at or after c (nent past the last)
+  auto next_live = [&](i64 c) {
+    i64 r = c;
+    while (r < nent && crun[r] == 0) r = nxt[r].load(std::memory_order_relaxed);
+    for (i64 x = c; x < r && crun[x] == 0;) {
+      const i64 y = nxt[x].load(std::memory_order_relaxed);
+      nxt[x].store(r, std::memory_order_relaxed);
+      x = y;
+    }
+    return r;
+  };
+  // marks the entries of the blocks that level l dropped as dead (a pivot row
+  // k whose S_kj is zero from then on leaves the column list of j); only the
+  // run lengths just before a dead entry change
+  auto prune_level = [&](int l) {
+    for (i64 pk : by_level[l])
+      for (i64 b = sp.rowptr[pk] + 1; b < sp.rowptr[pk + 1]; ++b) {
+        if (!is_dropped(b)) continue;
+        const i64 j = sp.epos[sp.colidx[b]], c = cidx[b];
+        crun[c] = 0;
+        for (i64 q = c - 1; q >= cptr[j] && crun[q] > 0; --q) {
+          const int32_t r = run_at(j, q);
+          if (r == crun[q]) break;
+          crun[q] = r;
+        }
+      }
+  };
   // partial sums of split targets (at most pcap elements per level)
   f.pcap = std::min<i64>(i64(1) << 25, std::max<i64>(sp.s_entries, 1));
   f.dP.reset(sizeof(T) * f.pcap);
@@ -417,7 +474,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
         RowChunk& out = chunks[pc];
         const i64 pi = rows[P.q];
         const i64 mi = mb[cl(pi)], mi16 = kpad16(mi);
-        const i64 c0 = cptr[pi], nci = cptr[pi + 1] - c0;
+        const i64 c0 = cptr[pi], nci = cend[pi] - c0;
         const i64* ci = ck_pos.data() + c0;
         if (zrow != P.q) {
           zrow = P.q;
@@ -427,7 +484,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
           zo[0] = zbase[P.q];
           kp[0] = tp[0] = 0;
           for (i64 p = 0; p < nci; ++p) {
-            const i64 mk = mb[cl(ci[p])];
+            const i64 mk = live(c0 + p) ? mb[cl(ci[p])] : 0;  // dead entries take no room in Z
             zo[p + 1] = zo[p] + kpad16(mk) * mi16;
             kp[p + 1] = kp[p] + kpad16(mk);
             tp[p + 1] = tp[p] + mk;
@@ -436,11 +493,19 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
         out.dense_pairs += double(nci) * double(P.b1 - P.b0);
         for (i64 b = P.b0; b < P.b1; ++b) {
           const i64 mj = mb[sp.colidx[b]], mj16 = kpad16(mj);
-          const i64 cj0 = cptr[sp.epos[sp.colidx[b]]], ncj = cptr[sp.epos[sp.colidx[b]] + 1] - cj0;
+          const i64 cj0 = cptr[sp.epos[sp.colidx[b]]], ncj = cend[sp.epos[sp.colidx[b]]] - cj0;
           const i64* cj = ck_pos.data() + cj0;
           const size_t sb = out.segs.size();
           i64 p = 0, q = 0;
           while (p < nci && q < ncj) {
+            if (crun[c0 + p] == 0) {  // S_ki dropped
+              p = std::min(next_live(c0 + p), c0 + nci) - c0;
+              continue;
+            }
+            if (crun[cj0 + q] == 0) {  // S_kj dropped
+              q = std::min(next_live(cj0 + q), cj0 + ncj) - cj0;
+              continue;
+            }
             if (ci[p] < cj[q]) {
               p = std::lower_bound(ci + p + 1, ci + nci, cj[q]) - ci;
               continue;
@@ -503,7 +568,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
       L.inv.push_back({S + sp.blk_off[sp.rowptr[pi]], Inv + f.inv_off[pi], int32_t(mi), 0});
       fl_inv += 2.0 * mi * mi * mi;
       i64 z = zbase[q];
-      for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+      for (i64 c = cptr[pi]; c < cend[pi]; ++c) {
+        if (!live(c)) continue;  // S_ki dropped: Z_ki is zero and no plan reads it
         const i64 pk = ck_pos[c];
         const i64 mk = mb[cl(pk)];
         const i64 soff = sp.blk_off[ck_blk[c]];
@@ -556,7 +622,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
           const int nt_row = int(t1 - t0);
           for (i64 b = t0; b < t1; ++b) mark[sp.colidx[b]] = int32_t(b - t0);
           cnt.assign(nt_row + 1, 0);
-          for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+          for (i64 c = cptr[pi]; c < cend[pi]; ++c) {
             const i64 pk = ck_pos[c];
             for (i64 b = sp.rowptr[pk]; b < sp.rowptr[pk + 1]; ++b) {
               const int32_t t = mark[sp.colidx[b]];
@@ -568,7 +634,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
           out.segs.resize(sbase + cnt[nt_row]);
           fillp.assign(cnt.begin(), cnt.end() - 1);
           i64 zoff = zbase[q];
-          for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+          for (i64 c = cptr[pi]; c < cend[pi]; ++c) {
             const i64 pk = ck_pos[c];
             const i64 mk = mb[cl(pk)];
             for (i64 b = sp.rowptr[pk]; b < sp.rowptr[pk + 1]; ++b) {
@@ -578,7 +644,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
             zoff += kpad16(mk) * kpad16(mi);
           }
           for (i64 b = t0; b < t1; ++b) mark[sp.colidx[b]] = -1;
-          out.dense_pairs += double(cptr[pi + 1] - cptr[pi]) * nt_row;
+          out.dense_pairs += double(cend[pi] - cptr[pi]) * nt_row;
           for (int t = 0; t < nt_row; ++t) {
             if (cnt[t + 1] == cnt[t]) continue;
             const i64 mj = mb[sp.colidx[t0 + t]];
@@ -700,7 +766,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
           ++nt;
           if (!seen_j[sp.colidx[b]]) seen_j[sp.colidx[b]] = 1, ++nj;
         }
-        for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+        for (i64 c = cptr[pi]; c < cend[pi]; ++c) {
           ++np;
           if (!seen_k[ck_pos[c]]) seen_k[ck_pos[c]] = 1, ++nk;
         }
@@ -716,7 +782,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
           const i64 t0 = sp.rowptr[pi], t1 = sp.rowptr[pi + 1];
           for (i64 b = t0; b < t1; ++b) tpos[sp.colidx[b]] = int32_t(b - t0);
           std::vector<char> g2, g4;
-          for (i64 c = cptr[pi]; c < cptr[pi + 1]; ++c) {
+          for (i64 c = cptr[pi]; c < cend[pi]; ++c) {
             const i64 pk = ck_pos[c];
             const double mk = double(mb[cl(pk)]);
             g2.assign((t1 - t0) / 2 + 1, 0);
@@ -795,12 +861,24 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
   // plans the levels in order, each in parallel
   auto plan_all = [&]() {
     for (int lv = 0; lv < f.nflev && !too_wide; ++lv) {
+      if (prune && lv > 0) {
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&] { return flags_done >= lv - 1 || prod_abort; });
+          if (prod_abort) break;
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        prune_level(lv - 1);
+        prune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      }
+      const auto t1 = std::chrono::steady_clock::now();
       plan_level(lv);
+      if (prune) plan_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
       {
         std::lock_guard<std::mutex> lk(mu);
         ready[lv] = 1;
       }
-      cv.notify_one();
+      cv.notify_all();
     }
     for (auto& v : marks) std::vector<int32_t>().swap(v);
     if (too_wide) fail(H2_EUNSUPPORTED, "Schur level above 2^24 targets or 2^31 segments");
@@ -844,7 +922,7 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
     }
     std::lock_guard<std::mutex> lk(mu);
     done_planning = true;
-    cv.notify_one();
+    cv.notify_all();
   });
   // The tile classes of a level update disjoint targets: classes 1 and 2
   // run on streams of their own beside class 0 on the main stream, so that
@@ -861,6 +939,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
     for (int c = 1; c < kSchurClasses; ++c) HIPCHECK(hipStreamCreateWithFlags(&cls_st[c], hipStreamNonBlocking));
   } catch (...) {
     destroy_streams();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      prod_abort = true;
+    }
+    cv.notify_all();
     producer.join();
     throw;
   }
@@ -933,6 +1016,28 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
         launch_inverse<T>(L.d_inv, int(L.inv.size()), f.dFlag.as<int>(), st);
         launch_copy_segments<T>(L.d_cps, int(L.cps.size()), Z, S, st);
         if (level_events) mark_ev();
+        if (prune && lv + 1 < f.nflev) {
+          // the level's drop flags, for the planning of the next level
+          i64 b0 = i64(sp.colidx.size()), b1 = 0;
+          for (i64 pk : by_level[lv]) {
+            b0 = std::min(b0, sp.rowptr[pk] + 1);
+            b1 = std::max(b1, sp.rowptr[pk + 1]);
+          }
+          const auto t0 = std::chrono::steady_clock::now();
+          if (b1 > b0) {
+            HIPCHECK(hipMemcpyAsync(hdrop.data() + b0, dDropFlag.as<uint8_t>() + b0, size_t(b1 - b0),
+                                    hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+          }
+          // the level is done: its work lists can go back to the cache
+          chunk_desc.back() = DeviceBuffer();
+          flag_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+          {
+            std::lock_guard<std::mutex> lk(mu);
+            flags_done = lv;
+          }
+          cv.notify_all();
+        }
         std::vector<SchurItem>().swap(L.sitems);
         PodVector<SchurSeg>().swap(L.ssegs);
         for (auto& tl : L.stiles) std::vector<int32_t>().swap(tl);
@@ -944,6 +1049,11 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
       next = end;
     }
   } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      prod_abort = true;
+    }
+    cv.notify_all();
     producer.join();
     // the buffers of this call are freed in the order of the main stream:
     // let every queued launch finish first
@@ -971,6 +1081,9 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
     }
   }
   tt.lap("plan+upload+enqueue");
+  if (trace_enabled() && prune)
+    std::fprintf(stderr, "[h2sp] ILUt pruned planning: prune %.1f ms, plan %.1f ms, wait for flags %.1f ms\n", prune_ms,
+                 plan_ms, flag_ms);
   if (trace_enabled()) {
     const double tot = std::max(1.0, shape_fl[0] + shape_fl[1] + shape_fl[2] + shape_fl[3]);
     std::fprintf(stderr,

@@ -131,6 +131,35 @@ def test_ilut_application_matches_oracle(d, tau):
         assert np.abs(got - ex).max() <= 1e-10 * np.abs(ex).max()
 
 
+@pytest.mark.parametrize("tau", [3e-5, 1e-3, np.inf])
+@pytest.mark.parametrize("precision", [P.H2_FP64, P.H2_MIXED], ids=["fp64", "mixed"])
+def test_ilut_pruned_plans_match_full_fill(precision, tau, monkeypatch):
+    """Planning each level without the blocks dropped so far (they hold zeros)
+    gives the same drop decisions and the same factor, up to the grouping of
+    the sums, as planning on the full structural fill, and less Schur work."""
+    note(f"ilut pruned plans precision={precision} tau={tau}")
+    c = case(1e-2)
+    b = np.random.default_rng(6).standard_normal((N, 2))
+    outs, counts, flops = [], [], []
+    for prune in ("0", "1"):
+        monkeypatch.setenv("H2SP_ILUT_PRUNE", prune)
+        f = P.h2_factor_S(P.h2_sparsify(c["hc"], precision), P.H2_FACTOR_ILUT, tau)
+        work = P.h2_last_work()
+        counts.append((int(work[16]), int(work[17])))
+        flops.append(work[5])
+        out = dev(np.zeros_like(b))
+        P.h2_apply_inverse(f, dev(b), out)
+        outs.append(host(out))
+    assert counts[0] == counts[1]
+    if counts[0][0] > 0:
+        assert flops[1] < flops[0]
+    else:
+        assert flops[1] == flops[0]
+    bar = 1e-12 if precision == P.H2_FP64 else 1e-4
+    assert np.isfinite(outs[1]).all()
+    assert np.abs(outs[0] - outs[1]).max() <= bar * np.abs(outs[0]).max()
+
+
 @pytest.mark.parametrize("d", D)
 @pytest.mark.parametrize("precision", [P.H2_FP64, P.H2_MIXED], ids=["fp64", "mixed"])
 def test_gmres_with_ilut_reaches_1e10(d, precision):
