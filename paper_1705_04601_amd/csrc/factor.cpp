@@ -1029,8 +1029,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
                                     hipMemcpyDeviceToHost, st));
             HIPCHECK(hipStreamSynchronize(st));
           }
-          // the level is done: its work lists can go back to the cache
-          chunk_desc.back() = DeviceBuffer();
+          // the run's levels are done: their work lists can go back to the cache
+          if (lv + 1 == end) chunk_desc.back() = DeviceBuffer();
           flag_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
           {
             std::lock_guard<std::mutex> lk(mu);
