@@ -437,7 +437,8 @@ int h2_autotune(h2_matrix* h, int precision, int64_t nrhs, const char* path);
  *   H2SP_ILUT_PRUNE=0: H2_FACTOR_ILUT plans every level on the full structural
  *     fill; by default (with merged runs) each level is planned after the
  *     previous level's drop decisions, without the blocks dropped so far
- *     (zero from then on), which the device waits for level by level;
+ *     (zero from then on); the planning then waits for the device level by
+ *     level instead of running ahead of it;
  *   H2SP_CLOSE_RESIDENT=0: never keep the matvec's close blocks on the device;
  *   H2SP_GRAPHS=0: run the solve and matvec sweeps eagerly instead of as
  *     captured HIP graphs;
