@@ -299,7 +299,7 @@ def bench_precond(args, P, torch):
     """One step = h2_sparsify of the coarse matrix + h2_factor_S (ILUt) +
     h2_solve_with (GMRES on the fine matrix to 1e-10), one right-hand side."""
     wl = PRECOND_WORKLOADS[args.workload]
-    n, d, tau = wl["n"], wl["d"], wl["tau"]
+    n, d, tau = wl["n"], wl["d"], wl["tau"] if args.tau is None else args.tau
     x = h2inputs.points("cube", n, wl["seed"])
     t0 = time.perf_counter()
     common = dict(leaf=64, cheb=4, rank_cap=64, kernel=P.H2_KERNEL_IFMM, param=d)
@@ -381,6 +381,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=40)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tau", type=float, default=None,
+                    help="drop tolerance of the block ILUt (the Section 5.5 workloads; default theirs)")
     ap.add_argument("--factor", default="ilu0", choices=["ilu0", "exact"],
                     help="block ILU(0) of S (default) or the exact block factorisation with fill")
     args = ap.parse_args()

@@ -215,7 +215,8 @@ static void factor_levels(h2_factor& f, hipStream_t st, double* phase_ms, bool l
   // then on) leave the column lists, so that no later level multiplies them.
   // Planning then waits for the device level by level.  H2SP_ILUT_PRUNE=0
   // keeps the full structural fill in every plan.
-  bool prune = ilut && merge_runs;
+  // (tau = 0 drops nothing: the plans then run ahead of the device as usual)
+  bool prune = ilut && merge_runs && std::any_of(f.drop_thr2.begin(), f.drop_thr2.end(), [](double t) { return t > 0.0; });
   if (const char* e = std::getenv("H2SP_ILUT_PRUNE")) prune = prune && e[0] != '0';
   std::vector<uint8_t> hdrop(prune ? sp.colidx.size() : 0, 0);  // drop flags of finished levels
   int flags_done = -1;                                           // last level whose flags are in hdrop
